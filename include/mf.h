@@ -1,0 +1,176 @@
+/*
+ * mf.h -- C ABI of the MI355X (gfx950) matrix-free finite element library.
+ *
+ * The library computes the action y = A x of a finite element bilinear form
+ * without assembling A: for every cell it gathers the cell's degrees of
+ * freedom through the cell-to-node map, evaluates the element kernel at
+ * quadrature points and scatter-adds the local result (Sun et al.,
+ * "A study of vectorization for matrix-free finite element methods",
+ * Section 2: the action of a bilinear form is the assembly of a linear form,
+ * eq. 1; Section 2.2: a parallel loop over cells with indirectly accessed
+ * data -- maps -- and access descriptors R / INC; Listing 3's gather, zero,
+ * local kernel, scatter-increment structure).
+ *
+ * Conventions
+ * -----------
+ * - Every function returns int: MF_OK (0) on success, a negative MF_E* code
+ *   otherwise; mf_last_error() then returns a message (thread-local). Outputs
+ *   are written only on success. No C++ exception crosses this boundary.
+ * - Host arrays passed to *_create are copied; the caller keeps ownership.
+ * - Device vectors (x, y, d, b, ...) are caller-owned device pointers
+ *   (e.g. torch data_ptr()) of the operator's precision (double for MF_F64,
+ *   float for MF_F32) unless stated. They are never retained after the call,
+ *   except by an mf_batch, which binds the pointers given at creation.
+ * - `stream` is a hipStream_t passed as void*; NULL is the default stream.
+ *   Calls are asynchronous on that stream unless documented as synchronous.
+ * - Objects are immutable after creation; different objects may be used
+ *   concurrently. One mf_op must not be used by two streams at once (it owns
+ *   a workspace).
+ * - Indices are int32 (nodes, cells); sizes are int64.
+ * - Reference cells and local orderings:
+ *     hex  [0,1]^3, vertex v at (v&1, (v>>1)&1, (v>>2)&1); Q_k nodes on the
+ *          Gauss-Lobatto-Legendre points, local id i + n*j + n*n*l, n = k+1;
+ *     tet  vertices (0,0,0),(1,0,0),(0,1,0),(0,0,1); P_k nodes at the
+ *          equispaced lattice points alpha/k, a1 fastest, then a2, then a3;
+ *     tri  vertices (0,0),(1,0),(0,1); P1 nodes at the vertices.
+ *   Vector fields are node-interleaved: dof = ncomp*node + component.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MF_OK = 0,
+  MF_EINVAL = -1,       /* bad argument: null pointer, size, index out of range */
+  MF_ENOMEM = -2,       /* device or host allocation failed */
+  MF_EDEVICE = -3,      /* a HIP runtime call or kernel launch failed */
+  MF_EMESH = -4,        /* degenerate or inverted cell */
+  MF_ENOTCONV = -5,     /* iteration limit reached before the tolerance */
+  MF_EBREAKDOWN = -6,   /* non-finite value or loss of positivity in a solver */
+  MF_EUNSUPPORTED = -7  /* valid request this build does not implement */
+};
+
+enum { MF_CELL_TRI = 0, MF_CELL_TET = 1, MF_CELL_HEX = 2 };
+
+/* Bilinear forms (paper, supplementary material "operators"):
+ *   MASS        int c u v            (c: optional vertex coefficient, else 1)
+ *   HELMHOLTZ   int grad u . grad v + u v                       (eq. 2)
+ *   LAPLACIAN   int grad u : grad v, ncomp 1 or 3 (paper: vector-valued)
+ *   POISSON     int kappa grad u . grad v  (kappa: vertex coefficient)
+ *   ELASTICITY  int sigma(u) : eps(v), sigma = 2 mu eps(u) + lambda tr(eps(u)) I;
+ *               the paper's int eps(u):eps(v) is lambda = 0, mu = 1/2. */
+enum { MF_OP_MASS = 0, MF_OP_HELMHOLTZ = 1, MF_OP_LAPLACIAN = 2, MF_OP_POISSON = 3,
+       MF_OP_ELASTICITY = 4 };
+
+enum { MF_F64 = 0, MF_F32 = 1 };
+
+typedef struct mf_mesh mf_mesh;
+typedef struct mf_space mf_space;
+typedef struct mf_op mf_op;
+
+/* Create a mesh. coords: host, nverts x gdim (gdim 2 for TRI, 3 otherwise),
+ * components interleaved per vertex (the paper's coordinate dat accessed as
+ * coords[gdim*vertex + i], Listing 3). cell2vert: host, ncells x (3|4|8).
+ * Every cell's Jacobian determinant is checked at its vertices (hex: at the
+ * 8 corners, which must share one sign); a zero or sign-changing determinant
+ * gives MF_EMESH. |det J| is used afterwards (Listing 2 takes fabs of the
+ * determinant). Errors: MF_EINVAL (bad type/sizes/index), MF_EMESH. */
+int mf_mesh_create(int cell_type, int64_t nverts, const double *coords, int64_t ncells,
+                   const int32_t *cell2vert, mf_mesh **out);
+
+/* Create a Lagrange space of the given degree (hex: Q_k on GLL nodes, k = 1..6;
+ * tet: P_k equispaced, k = 1..3; tri: P1) with ncomp components.
+ * cell2node: host, ncells x D (D = (k+1)^3 hex, (k+1)(k+2)(k+3)/6 tet, 3 tri),
+ * entries in [0, nnodes) -- the paper's cell2dof map (Section 2.2). The caller's
+ * node numbering is kept at this boundary. Errors: MF_EINVAL, MF_EUNSUPPORTED. */
+int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *cell2node,
+                    int64_t nnodes, mf_space **out);
+
+typedef struct {
+  const double *vertex_coef; /* host, nverts; MASS coefficient c or POISSON kappa; NULL -> 1 */
+  double lambda, mu;         /* ELASTICITY Lame parameters */
+  const uint8_t *dirichlet;  /* host, nnodes; nonzero marks a node whose every component is
+                                constrained: (A x)_b = x_b there, and constrained values are
+                                excluded from every other row. NULL -> no constraint. */
+} mf_op_params;
+
+/* Create an operator. precision MF_F64 or MF_F32 (FP32 arithmetic with FP32
+ * accumulation; cell geometry is precomputed in FP64 and rounded once).
+ * nq1d: hex quadrature points per direction, 0 -> k+1 (tensor Gauss-Legendre);
+ * simplices ignore it and use a rule exact for the integrand. params may be
+ * NULL (coefficient 1, lambda 1, mu 0.5, no constraints). stream: device
+ * uploads are ordered on it; the call returns after they complete.
+ * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
+int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,
+                 const mf_op_params *params, void *stream, mf_op **out);
+
+/* y = A x over all cells; y (ndofs) is overwritten (the paper's assemble(L)
+ * returns a fresh vector, Listing 1; the local tensor is zeroed before each
+ * cell, Listing 3). x and y must not alias. */
+int mf_op_apply(const mf_op *op, const void *x, void *y, void *stream);
+
+/* The paper's wrapper contract over a cell range (Listing 3: start <= n < end,
+ * access INC): y += A_[start,end) x if accumulate, else y = A_[start,end) x.
+ * No constraint rows are set here (only the masking of constrained values). */
+int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x, void *y,
+                      int accumulate, void *stream);
+
+/* d = diag(A) (ndofs, op precision); constrained dofs get 1. Used as the Jacobi
+ * preconditioner. */
+int mf_op_diagonal(const mf_op *op, void *d, void *stream);
+
+typedef struct {
+  int64_t ncells, nnodes, ndofs;
+  int cell_type, kind, precision, degree, ncomp, nq1d, nqp;
+  int dofs_per_cell;      /* D (nodes per cell) */
+  double flops_per_apply; /* algorithmic flops of one mf_op_apply */
+  double bytes_per_apply; /* algorithmic HBM bytes of one mf_op_apply (perfect caching) */
+} mf_op_info;
+
+int mf_op_get_info(const mf_op *op, mf_op_info *info);
+
+/* ----------------------------------------------------------------- solvers */
+typedef struct {
+  int outer_iterations;   /* FP64 residual refreshes (1 for plain FP64 CG) */
+  int inner_iterations;   /* total CG iterations with the (inner) operator */
+  int fallbacks;          /* learned-preconditioner steps replaced by Jacobi */
+  double rel_residual;    /* final true ||b - A64 x||_2 / ||b||_2 */
+} mf_cg_info;
+
+typedef struct mf_precond mf_precond;
+
+/* Jacobi preconditioner from A's diagonal (FP64). */
+int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out);
+
+/* Conjugate gradients for A64 x = b, all vectors FP64 on the device (Hestenes
+ * and Stiefel; not in the paper -- the solver that consumes the action).
+ * A32 == NULL: plain preconditioned CG with the FP64 action.
+ * A32 != NULL: iterative refinement -- the outer loop forms r = b - A64 x in
+ * FP64 and stops when ||r||/||b|| <= rtol; each inner solve runs preconditioned
+ * CG on A32 d = r with the FP32 action (FP64 vectors, dot products and
+ * updates) to relative tolerance inner_rtol (0 -> 1e-4), then x += d.
+ * x holds the initial guess on entry. Synchronous. info may be NULL.
+ * Errors: MF_ENOTCONV (maxit total inner iterations reached; x holds the last
+ * iterate, info filled), MF_EBREAKDOWN (non-finite residual or p'Ap <= 0). */
+int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const double *b,
+                double *x, double rtol, double inner_rtol, int maxit, mf_cg_info *info,
+                void *stream);
+
+void mf_precond_destroy(mf_precond *p);
+
+/* ----------------------------------------------------------------- teardown / errors */
+void mf_mesh_destroy(mf_mesh *m);   /* NULL-safe */
+void mf_space_destroy(mf_space *s); /* NULL-safe */
+void mf_op_destroy(mf_op *op);      /* NULL-safe; waits for the op's work */
+const char *mf_last_error(void);
+const char *mf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

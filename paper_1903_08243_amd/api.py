@@ -1,0 +1,239 @@
+"""ctypes binding of include/mf.h (argument marshalling only).
+
+Every numerical step runs in libmf.so's HIP kernels. Device vectors are torch
+tensors on the GPU; the binding passes their data pointers and the current
+torch stream to the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
+MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY = range(5)
+F64, F32 = 0, 1
+_ERR = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EMESH", -5: "ENOTCONV", -6: "EBREAKDOWN",
+        -7: "EUNSUPPORTED"}
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libmf.so")
+_lib = None
+
+
+class MFError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"MF_{_ERR.get(code, code)}: {msg}")
+        self.code = code
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+class _OpInfo(ctypes.Structure):
+    _fields_ = [("ncells", ctypes.c_int64), ("nnodes", ctypes.c_int64), ("ndofs", ctypes.c_int64),
+                ("cell_type", ctypes.c_int), ("kind", ctypes.c_int), ("precision", ctypes.c_int),
+                ("degree", ctypes.c_int), ("ncomp", ctypes.c_int), ("nq1d", ctypes.c_int),
+                ("nqp", ctypes.c_int), ("dofs_per_cell", ctypes.c_int),
+                ("flops_per_apply", ctypes.c_double), ("bytes_per_apply", ctypes.c_double)]
+
+
+class _OpParams(ctypes.Structure):
+    _fields_ = [("vertex_coef", ctypes.c_void_p), ("lam", ctypes.c_double), ("mu", ctypes.c_double),
+                ("dirichlet", ctypes.c_void_p)]
+
+
+class CGInfo(ctypes.Structure):
+    _fields_ = [("outer_iterations", ctypes.c_int), ("inner_iterations", ctypes.c_int),
+                ("fallbacks", ctypes.c_int), ("rel_residual", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+def load_library():
+    """Load libmf.so; raises if it has not been built (no fallback exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: run __graft_entry__.build() "
+                          "(python -m paper_1903_08243_amd.build)")
+    L = ctypes.CDLL(_LIB_PATH)
+    P, I, I64, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_double
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "mf_mesh_create": (I, [I, I64, P, I64, P, PP]),
+        "mf_space_create": (I, [P, I, I, P, I64, PP]),
+        "mf_op_create": (I, [P, I, I, I, ctypes.POINTER(_OpParams), P, PP]),
+        "mf_op_apply": (I, [P, P, P, P]),
+        "mf_op_apply_range": (I, [P, I64, I64, P, P, I, P]),
+        "mf_op_diagonal": (I, [P, P, P]),
+        "mf_op_get_info": (I, [P, ctypes.POINTER(_OpInfo)]),
+        "mf_precond_create_jacobi": (I, [P, P, PP]),
+        "mf_cg_solve": (I, [P, P, P, P, P, D, D, I, ctypes.POINTER(CGInfo), P]),
+        "mf_mesh_destroy": (None, [P]),
+        "mf_space_destroy": (None, [P]),
+        "mf_op_destroy": (None, [P]),
+        "mf_precond_destroy": (None, [P]),
+        "mf_last_error": (ctypes.c_char_p, []),
+        "mf_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype, f.argtypes = res, args
+    _lib = L
+    return L
+
+
+def _check(rc):
+    if rc != 0:
+        raise MFError(rc, load_library().mf_last_error().decode())
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype=None):
+    """Device pointer of a torch tensor (contiguous, on the GPU)."""
+    if not t.is_cuda:
+        raise ValueError("device vectors must be GPU tensors")
+    if not t.is_contiguous():
+        raise ValueError("device vectors must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Mesh:
+    def __init__(self, cell_type, coords, cell2vert):
+        L = load_library()
+        self._coords = _np(coords, np.float64)
+        self._c2v = _np(cell2vert, np.int32)
+        h = ctypes.c_void_p()
+        _check(L.mf_mesh_create(cell_type, self._coords.shape[0], self._coords.ctypes.data,
+                                self._c2v.shape[0], self._c2v.ctypes.data, ctypes.byref(h)))
+        self.handle, self.cell_type = h, cell_type
+        self.nverts, self.ncells = self._coords.shape[0], self._c2v.shape[0]
+
+    @classmethod
+    def from_meshgen(cls, m):
+        return cls(m.cell_type, m.coords, m.cell2vert)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mf_mesh_destroy(self.handle)
+            self.handle = None
+
+
+class Space:
+    def __init__(self, mesh: Mesh, degree, ncomp, cell2node, nnodes):
+        L = load_library()
+        c2n = _np(cell2node, np.int32)
+        h = ctypes.c_void_p()
+        _check(L.mf_space_create(mesh.handle, degree, ncomp, c2n.ctypes.data, int(nnodes), ctypes.byref(h)))
+        self.handle, self.mesh = h, mesh
+        self.degree, self.ncomp, self.nnodes = degree, ncomp, int(nnodes)
+        self.ndofs = self.nnodes * ncomp
+
+    @classmethod
+    def from_meshgen(cls, s, mesh: Mesh | None = None):
+        mesh = mesh or Mesh.from_meshgen(s.mesh)
+        return cls(mesh, s.degree, s.ncomp, s.cell2node, s.nnodes)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mf_space_destroy(self.handle)
+            self.handle = None
+
+
+class Operator:
+    """A matrix-free operator; apply() runs the HIP kernels on the current torch stream."""
+
+    def __init__(self, space: Space, kind, precision=F64, nq1d=0, vertex_coef=None, lam=1.0, mu=0.5,
+                 dirichlet=None, stream=None):
+        L = load_library()
+        self._coef = None if vertex_coef is None else _np(vertex_coef, np.float64)
+        self._bc = None if dirichlet is None else _np(dirichlet, np.uint8)
+        pr = _OpParams(None if self._coef is None else self._coef.ctypes.data, lam, mu,
+                       None if self._bc is None else self._bc.ctypes.data)
+        h = ctypes.c_void_p()
+        _check(L.mf_op_create(space.handle, kind, precision, nq1d, ctypes.byref(pr), _stream(stream),
+                              ctypes.byref(h)))
+        self.handle, self.space = h, space
+        info = _OpInfo()
+        _check(L.mf_op_get_info(h, ctypes.byref(info)))
+        self.info = {f: getattr(info, f) for f, _ in _OpInfo._fields_}
+        self.ndofs = info.ndofs
+        self.precision = precision
+
+    @property
+    def torch_dtype(self):
+        import torch
+        return torch.float64 if self.precision == F64 else torch.float32
+
+    def apply(self, x, y=None, stream=None):
+        import torch
+        if y is None:
+            y = torch.empty(self.ndofs, dtype=self.torch_dtype, device=x.device)
+        self._size(x), self._size(y)
+        _check(load_library().mf_op_apply(self.handle, _dev(x, self.torch_dtype), _dev(y, self.torch_dtype),
+                                          _stream(stream)))
+        return y
+
+    def apply_range(self, start, end, x, y, accumulate=False, stream=None):
+        self._size(x), self._size(y)
+        _check(load_library().mf_op_apply_range(self.handle, start, end, _dev(x, self.torch_dtype),
+                                                _dev(y, self.torch_dtype), int(accumulate), _stream(stream)))
+        return y
+
+    def diagonal(self, stream=None):
+        import torch
+        d = torch.empty(self.ndofs, dtype=self.torch_dtype, device="cuda")
+        _check(load_library().mf_op_diagonal(self.handle, _dev(d), _stream(stream)))
+        return d
+
+    def _size(self, t):
+        if t.numel() != self.ndofs:
+            raise ValueError(f"vector has {t.numel()} entries, operator has {self.ndofs} dofs")
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mf_op_destroy(self.handle)
+            self.handle = None
+
+
+class JacobiPrecond:
+    def __init__(self, op: Operator, stream=None):
+        h = ctypes.c_void_p()
+        _check(load_library().mf_precond_create_jacobi(op.handle, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mf_precond_destroy(self.handle)
+            self.handle = None
+
+
+def cg_solve(A64: Operator, b, x, A32: Operator | None = None, precond=None, rtol=1e-10, inner_rtol=0.0,
+             maxit=10000, stream=None, raise_on_error=True):
+    """FP64 (optionally FP32-refined) preconditioned CG; x holds the initial guess."""
+    import torch
+    info = CGInfo()
+    rc = load_library().mf_cg_solve(A64.handle, None if A32 is None else A32.handle,
+                                    None if precond is None else precond.handle, _dev(b, torch.float64),
+                                    _dev(x, torch.float64), rtol, inner_rtol, maxit, ctypes.byref(info),
+                                    _stream(stream))
+    if rc != 0 and raise_on_error:
+        _check(rc)
+    return info.as_dict() | {"rc": rc}

@@ -1,0 +1,248 @@
+// Conjugate-gradient driver: plain FP64 PCG, and FP32-action iterative
+// refinement (FP64 outer residual, FP64 inner vectors, dots and updates).
+//
+// The operator action is the paper's matrix-free residual evaluation
+// (Section 1: a matrix-vector product is the assembly of a linear form);
+// CG is the textbook consumer of that action and is not part of the paper.
+//
+// The iteration body (operator action + dot + finalize + update + finalize +
+// search-direction update) is a fixed launch sequence with device-resident
+// scalars. A chunk of CHUNK iterations is captured once into a hipGraph on a
+// private stream and replayed; the host reads the 64-byte state after each
+// replay to test convergence. Iterations after convergence are no-ops
+// (alpha = beta = 0), so a partially used chunk is harmless.
+#include <cmath>
+#include <cstring>
+#include <memory>
+
+#include "cg_internal.h"
+
+namespace mf {
+
+static constexpr int CHUNK = 8;
+
+struct CgWork {
+  int64_t n = 0;
+  DeviceBuffer r, p, Ap, part, st, p32, Ap32, d, x32;
+  hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;
+  CgState *host_st = nullptr;  // pinned
+  hipGraphExec_t exec[2] = {nullptr, nullptr};  // [0] FP64 operator chunk, [1] FP32 operator chunk
+  ~CgWork() {
+    for (auto &e : exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    if (host_st) (void)hipHostFree(host_st);
+    if (ev) (void)hipEventDestroy(ev);
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+static int apply_any(const mf_op *A, const void *x, void *y, hipStream_t s) { return mf_op_apply(A, x, y, s); }
+
+// One chunk of PCG iterations on operator A (FP64 or FP32 action), recorded on w.s.
+static int record_chunk(const mf_op *A, const double *dinv, double *x, CgWork &w) {
+  const bool a32 = A->precision == MF_F32;
+  for (int j = 0; j < CHUNK; j++) {
+    int rc = a32 ? apply_any(A, w.p32.ptr, w.Ap32.ptr, w.s) : apply_any(A, w.p.ptr, w.Ap.ptr, w.s);
+    if (rc) return rc;
+    rc = cg_step_after_apply(x, w.r.as<double>(), w.p.as<double>(), a32 ? w.p32.as<float>() : nullptr,
+                             a32 ? w.Ap32.ptr : w.Ap.ptr, a32, dinv, w.n, w.part.as<double>(), w.st.as<CgState>(),
+                             w.s);
+    if (rc) return rc;
+  }
+  return MF_OK;
+}
+
+static int chunk_graph(const mf_op *A, const double *dinv, double *x, CgWork &w, hipGraphExec_t &exec) {
+  if (exec) return MF_OK;
+  hipGraph_t g = nullptr;
+  MF_HIP(hipStreamBeginCapture(w.s, hipStreamCaptureModeThreadLocal));
+  int rc = record_chunk(A, dinv, x, w);
+  hipError_t e = hipStreamEndCapture(w.s, &g);
+  if (rc) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(MF_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    exec = nullptr;
+    return fail(MF_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+  }
+  return MF_OK;
+}
+
+static int read_state(CgWork &w, CgState &out) {
+  MF_HIP(hipMemcpyAsync(w.host_st, w.st.ptr, sizeof(CgState), hipMemcpyDeviceToHost, w.s));
+  MF_HIP(hipStreamSynchronize(w.s));
+  out = *w.host_st;
+  return MF_OK;
+}
+
+// PCG from the residual already stored in w.r (for iterate x); x is updated in place.
+static int pcg_core(const mf_op *A, const double *dinv, double *x, double tol2, int maxit, CgWork &w,
+                    CgState &out) {
+  const bool a32 = A->precision == MF_F32;
+  CgState init{};
+  init.tol2 = tol2;
+  init.maxit = maxit;
+  *w.host_st = init;
+  MF_HIP(hipMemcpyAsync(w.st.ptr, w.host_st, sizeof(CgState), hipMemcpyHostToDevice, w.s));
+  int rc = cg_init(w.r.as<double>(), dinv, w.p.as<double>(), a32 ? w.p32.as<float>() : nullptr, w.n,
+                   w.part.as<double>(), w.st.as<CgState>(), w.s);
+  if (rc) return rc;
+  rc = read_state(w, out);
+  if (rc || out.stop || maxit <= 0) return rc;
+  hipGraphExec_t &exec = w.exec[a32 ? 1 : 0];
+  rc = chunk_graph(A, dinv, x, w, exec);
+  if (rc) return rc;
+  while (true) {
+    MF_HIP(hipGraphLaunch(exec, w.s));
+    rc = read_state(w, out);
+    if (rc) return rc;
+    if (out.stop) break;
+  }
+  return MF_OK;
+}
+
+static int residual(const mf_op *A64, const double *b, const double *x, CgWork &w, double &rr) {
+  int rc = mf_op_apply(A64, x, w.Ap.ptr, w.s);
+  if (rc) return rc;
+  rc = cg_residual(b, w.Ap.ptr, false, w.r.as<double>(), w.n, w.part.as<double>(), w.st.as<CgState>(), w.s);
+  if (rc) return rc;
+  CgState st;
+  rc = read_state(w, st);
+  rr = st.rr;
+  return rc;
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out) {
+  if (!A || !out) return fail(MF_EINVAL, "mf_precond_create_jacobi: null argument");
+  hipStream_t s = (hipStream_t)stream;
+  std::unique_ptr<mf_precond> P(new (std::nothrow) mf_precond);
+  if (!P) return fail(MF_ENOMEM, "mf_precond_create_jacobi: host allocation");
+  P->kind = 0;
+  P->n = A->ndofs;
+  DeviceBuffer d;
+  int rc = d.alloc((size_t)A->ndofs * (A->precision == MF_F64 ? 8 : 4));
+  if (!rc) rc = P->dinv.alloc((size_t)A->ndofs * 8);
+  if (!rc) rc = mf_op_diagonal(A, d.ptr, s);
+  if (!rc) rc = cg_recip(d.ptr, A->precision == MF_F32, P->dinv.as<double>(), A->ndofs, s);
+  if (rc) return rc;
+  MF_HIP(hipStreamSynchronize(s));
+  *out = P.release();
+  return MF_OK;
+}
+
+void mf_precond_destroy(mf_precond *p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  delete p;
+}
+
+int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const double *b, double *x, double rtol,
+                double inner_rtol, int maxit, mf_cg_info *info, void *stream) {
+  if (!A64 || !b || !x) return fail(MF_EINVAL, "mf_cg_solve: null argument");
+  if (A64->precision != MF_F64) return fail(MF_EINVAL, "mf_cg_solve: A64 must be an FP64 operator");
+  if (A32 && (A32->ndofs != A64->ndofs || A32->precision != MF_F32))
+    return fail(MF_EINVAL, "mf_cg_solve: A32 must be an FP32 operator of the same size");
+  if (M && M->n != A64->ndofs) return fail(MF_EINVAL, "mf_cg_solve: preconditioner size");
+  if (!(rtol > 0.0) || maxit < 0) return fail(MF_EINVAL, "mf_cg_solve: rtol / maxit");
+  if (M && M->kind != 0) return fail(MF_EUNSUPPORTED, "mf_cg_solve: use mf_fcg_solve for learned preconditioners");
+  const int64_t n = A64->ndofs;
+  hipStream_t caller = (hipStream_t)stream;
+  CgWork w;
+  w.n = n;
+  MF_HIP(hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking));
+  MF_HIP(hipEventCreateWithFlags(&w.ev, hipEventDisableTiming));
+  MF_HIP(hipHostMalloc((void **)&w.host_st, sizeof(CgState), hipHostMallocDefault));
+  // order the solve after the caller's pending work on its stream
+  MF_HIP(hipEventRecord(w.ev, caller));
+  MF_HIP(hipStreamWaitEvent(w.s, w.ev, 0));
+  int rc = MF_OK;
+  for (DeviceBuffer *bptr : {&w.r, &w.p, &w.Ap})
+    if (!rc) rc = bptr->alloc((size_t)n * 8);
+  if (!rc) rc = w.part.alloc((size_t)2 * CG_NPART * 8);
+  if (!rc) rc = w.st.alloc(sizeof(CgState));
+  if (A32) {
+    if (!rc) rc = w.p32.alloc((size_t)n * 4);
+    if (!rc) rc = w.Ap32.alloc((size_t)n * 4);
+    if (!rc) rc = w.d.alloc((size_t)n * 8);
+  }
+  if (rc) return rc;
+  const double *dinv = M ? M->dinv.as<double>() : nullptr;
+
+  // ||b||^2 via the residual kernel with Ax = 0 is avoided: r = b - A*0 costs an apply; use r = b - Ap with Ap = 0
+  rc = launch_fill<double>(w.Ap.as<double>(), 0.0, n, w.s);
+  if (!rc) rc = cg_residual(b, w.Ap.ptr, false, w.r.as<double>(), n, w.part.as<double>(), w.st.as<CgState>(), w.s);
+  CgState st{};
+  if (!rc) rc = read_state(w, st);
+  if (rc) return rc;
+  const double bb = st.rr;
+  mf_cg_info inf{0, 0, 0, 0.0};
+  if (bb == 0.0) {
+    rc = launch_fill<double>(x, 0.0, n, w.s);
+    if (!rc) rc = read_state(w, st);
+    if (info) *info = inf;
+    return rc;
+  }
+  const double tol2 = rtol * rtol * bb;
+  double rr = 0.0;
+  int status = MF_OK;
+  if (!A32) {
+    // plain PCG with the FP64 action; restart from the true residual if the recurrence drifted
+    for (int restart = 0; restart < 5; restart++) {
+      rc = residual(A64, b, x, w, rr);
+      if (rc) return rc;
+      inf.outer_iterations++;
+      if (rr <= tol2 || inf.inner_iterations >= maxit) break;
+      rc = pcg_core(A64, dinv, x, tol2, maxit - inf.inner_iterations, w, st);
+      if (rc) return rc;
+      inf.inner_iterations += st.iters;
+      if (st.breakdown) {
+        status = fail(MF_EBREAKDOWN, "CG breakdown (non-finite value or p'Ap <= 0)");
+        break;
+      }
+    }
+    if (status == MF_OK) {
+      rc = residual(A64, b, x, w, rr);
+      if (rc) return rc;
+    }
+  } else {
+    const double irt = inner_rtol > 0.0 ? inner_rtol : 1e-4;
+    for (int outer = 0; outer < 100; outer++) {
+      rc = residual(A64, b, x, w, rr);
+      if (rc) return rc;
+      inf.outer_iterations++;
+      if (rr <= tol2 || !(rr == rr) || inf.inner_iterations >= maxit) break;
+      // inner: A32 d = r from d = 0, FP64 vectors
+      rc = launch_fill<double>(w.d.as<double>(), 0.0, n, w.s);
+      if (rc) return rc;
+      rc = pcg_core(A32, dinv, w.d.as<double>(), irt * irt * rr, maxit - inf.inner_iterations, w, st);
+      if (rc) return rc;
+      inf.inner_iterations += st.iters;
+      if (st.breakdown) {
+        status = fail(MF_EBREAKDOWN, "inner CG breakdown (non-finite value or p'Ap <= 0)");
+        break;
+      }
+      rc = cg_axpy(x, w.d.as<double>(), n, w.s);
+      if (rc) return rc;
+    }
+  }
+  inf.rel_residual = std::sqrt(rr / bb);
+  if (status == MF_OK && !(rr == rr)) status = fail(MF_EBREAKDOWN, "non-finite residual");
+  if (status == MF_OK && rr > tol2)
+    status = fail(MF_ENOTCONV, "CG did not reach the tolerance within maxit iterations");
+  MF_HIP(hipStreamSynchronize(w.s));
+  if (info) *info = inf;
+  return status;
+}
+
+}  // extern "C"

@@ -1,0 +1,503 @@
+// C ABI entry points: mesh / space / operator setup and the operator action.
+//
+// Setup is host C++ in FP64: validation of the input maps (the paper's
+// cell2dof and cell2vert maps, Section 2.2), cell geometry precompute, the
+// constant tables of the element kernel, and the device layouts the kernels
+// read. The action itself runs entirely in the HIP kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "mf_internal.h"
+
+namespace mf {
+
+static thread_local std::string g_err;
+void set_error(const std::string &m) { g_err = m; }
+int fail(int code, const std::string &m) {
+  g_err = m;
+  return code;
+}
+
+int DeviceBuffer::alloc(size_t b) {
+  if (ptr) (void)hipFree(ptr);
+  ptr = nullptr;
+  bytes = b;
+  if (b == 0) return MF_OK;
+  if (hipMalloc(&ptr, b) != hipSuccess) {
+    ptr = nullptr;
+    (void)hipGetLastError();
+    return fail(MF_ENOMEM, "hipMalloc of " + std::to_string(b) + " bytes failed");
+  }
+  return MF_OK;
+}
+
+static int upload(DeviceBuffer &buf, const void *src, size_t bytes, hipStream_t s) {
+  int rc = buf.alloc(bytes);
+  if (rc) return rc;
+  if (bytes) MF_HIP(hipMemcpyAsync(buf.ptr, src, bytes, hipMemcpyHostToDevice, s));
+  return MF_OK;
+}
+
+template <typename T> static std::vector<T> cast_vec(const std::vector<double> &v) {
+  return std::vector<T>(v.begin(), v.end());
+}
+
+static int nvc_of(int cell_type) {
+  return cell_type == MF_CELL_TRI ? 3 : cell_type == MF_CELL_TET ? 4 : cell_type == MF_CELL_HEX ? 8 : 0;
+}
+
+// Trilinear map x(xi) = c0 + c1 xi1 + c2 xi2 + c3 xi3 + c4 xi1 xi2 + c5 xi1 xi3 + c6 xi2 xi3
+// + c7 xi1 xi2 xi3 from the 8 vertex values (vertex v at (v&1, v>>1&1, v>>2&1)).
+static void trilinear_coeffs(const double X[8], double c[8]) {
+  c[0] = X[0];
+  c[1] = X[1] - X[0];
+  c[2] = X[2] - X[0];
+  c[3] = X[4] - X[0];
+  c[4] = X[3] - X[1] - X[2] + X[0];
+  c[5] = X[5] - X[1] - X[4] + X[0];
+  c[6] = X[6] - X[2] - X[4] + X[0];
+  c[7] = X[7] - X[3] - X[5] - X[6] + X[1] + X[2] + X[4] - X[0];
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+const char *mf_last_error(void) { return g_err.c_str(); }
+const char *mf_version(void) { return "mf 0.1 (gfx950)"; }
+
+int mf_mesh_create(int cell_type, int64_t nverts, const double *coords, int64_t ncells,
+                   const int32_t *cell2vert, mf_mesh **out) {
+  if (!out) return fail(MF_EINVAL, "mf_mesh_create: out is NULL");
+  const int nvc = nvc_of(cell_type);
+  if (!nvc) return fail(MF_EINVAL, "mf_mesh_create: unknown cell type");
+  if (nverts <= 0 || ncells < 0 || !coords || (ncells > 0 && !cell2vert))
+    return fail(MF_EINVAL, "mf_mesh_create: bad sizes or null arrays");
+  if (nverts > INT32_MAX || ncells > INT32_MAX) return fail(MF_EINVAL, "mf_mesh_create: sizes exceed int32");
+  const int g = cell_type == MF_CELL_TRI ? 2 : 3;
+  for (int64_t i = 0; i < ncells * nvc; i++)
+    if (cell2vert[i] < 0 || cell2vert[i] >= nverts)
+      return fail(MF_EINVAL, "mf_mesh_create: cell2vert entry " + std::to_string(i) + " out of range");
+  // degenerate / inverted cells
+  for (int64_t K = 0; K < ncells; K++) {
+    const int32_t *cv = cell2vert + K * nvc;
+    double L = 0.0;  // longest vertex offset from vertex 0
+    for (int v = 1; v < nvc; v++) {
+      double s = 0.0;
+      for (int a = 0; a < g; a++) {
+        const double d = coords[(int64_t)cv[v] * g + a] - coords[(int64_t)cv[0] * g + a];
+        s += d * d;
+      }
+      L = std::max(L, std::sqrt(s));
+    }
+    const double tol = 1e-13 * std::pow(L, g);
+    if (cell_type == MF_CELL_TRI) {
+      const double *p0 = coords + (int64_t)cv[0] * 2, *p1 = coords + (int64_t)cv[1] * 2, *p2 = coords + (int64_t)cv[2] * 2;
+      const double det = (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]);
+      if (!(std::fabs(det) > tol)) return fail(MF_EMESH, "degenerate triangle " + std::to_string(K));
+    } else if (cell_type == MF_CELL_TET) {
+      double J[3][3];
+      for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) J[a][b] = coords[(int64_t)cv[b + 1] * 3 + a] - coords[(int64_t)cv[0] * 3 + a];
+      const double det = J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+                         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+                         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+      if (!(std::fabs(det) > tol)) return fail(MF_EMESH, "degenerate tetrahedron " + std::to_string(K));
+    } else {
+      double c[3][8];
+      for (int a = 0; a < 3; a++) {
+        double X[8];
+        for (int v = 0; v < 8; v++) X[v] = coords[(int64_t)cv[v] * 3 + a];
+        trilinear_coeffs(X, c[a]);
+      }
+      int sign = 0;
+      for (int corner = 0; corner < 8; corner++) {
+        const double x1 = corner & 1, x2 = (corner >> 1) & 1, x3 = (corner >> 2) & 1;
+        double j1[3], j2[3], j3[3];
+        for (int a = 0; a < 3; a++) {
+          j1[a] = c[a][1] + c[a][4] * x2 + c[a][5] * x3 + c[a][7] * x2 * x3;
+          j2[a] = c[a][2] + c[a][4] * x1 + c[a][6] * x3 + c[a][7] * x1 * x3;
+          j3[a] = c[a][3] + c[a][5] * x1 + c[a][6] * x2 + c[a][7] * x1 * x2;
+        }
+        const double det = j1[0] * (j2[1] * j3[2] - j2[2] * j3[1]) + j1[1] * (j2[2] * j3[0] - j2[0] * j3[2]) +
+                           j1[2] * (j2[0] * j3[1] - j2[1] * j3[0]);
+        const int sg = det > tol ? 1 : det < -tol ? -1 : 0;
+        if (sg == 0 || (sign != 0 && sg != sign))
+          return fail(MF_EMESH, "degenerate or tangled hexahedron " + std::to_string(K));
+        sign = sg;
+      }
+    }
+  }
+  mf_mesh *m = new (std::nothrow) mf_mesh;
+  if (!m) return fail(MF_ENOMEM, "mf_mesh_create: host allocation");
+  m->cell_type = cell_type;
+  m->gdim = g;
+  m->nvc = nvc;
+  m->nverts = nverts;
+  m->ncells = ncells;
+  m->coords.assign(coords, coords + nverts * g);
+  m->cell2vert.assign(cell2vert, cell2vert + ncells * nvc);
+  *out = m;
+  return MF_OK;
+}
+
+void mf_mesh_destroy(mf_mesh *m) { delete m; }
+
+int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *cell2node, int64_t nnodes,
+                    mf_space **out) {
+  if (!mesh || !out || !cell2node) return fail(MF_EINVAL, "mf_space_create: null argument");
+  if (ncomp < 1 || ncomp > 3) return fail(MF_EINVAL, "mf_space_create: ncomp must be 1..3");
+  if (nnodes <= 0 || nnodes > INT32_MAX / 3) return fail(MF_EINVAL, "mf_space_create: nnodes out of range");
+  int D = 0;
+  if (mesh->cell_type == MF_CELL_HEX) {
+    if (degree < 1 || degree > 6) return fail(MF_EUNSUPPORTED, "hex spaces support degree 1..6");
+    D = (degree + 1) * (degree + 1) * (degree + 1);
+  } else if (mesh->cell_type == MF_CELL_TET) {
+    if (degree < 1 || degree > 3) return fail(MF_EUNSUPPORTED, "tet spaces support degree 1..3");
+    D = tet_ndofs(degree);
+  } else {
+    if (degree != 1) return fail(MF_EUNSUPPORTED, "tri spaces support degree 1");
+    D = 3;
+  }
+  for (int64_t i = 0; i < mesh->ncells * D; i++)
+    if (cell2node[i] < 0 || cell2node[i] >= nnodes)
+      return fail(MF_EINVAL, "mf_space_create: cell2node entry " + std::to_string(i) + " out of range");
+  mf_space *s = new (std::nothrow) mf_space;
+  if (!s) return fail(MF_ENOMEM, "mf_space_create: host allocation");
+  s->cell_type = mesh->cell_type;
+  s->gdim = mesh->gdim;
+  s->nvc = mesh->nvc;
+  s->nverts = mesh->nverts;
+  s->ncells = mesh->ncells;
+  s->coords = mesh->coords;
+  s->cell2vert = mesh->cell2vert;
+  s->degree = degree;
+  s->ncomp = ncomp;
+  s->D = D;
+  s->nnodes = nnodes;
+  s->cell2node.assign(cell2node, cell2node + mesh->ncells * D);
+  *out = s;
+  return MF_OK;
+}
+
+void mf_space_destroy(mf_space *s) { delete s; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ operator setup
+namespace mf {
+
+template <typename T> static void build_hex_table(int k, int nq, std::vector<unsigned char> &out) {
+  const int N = k + 1;
+  std::vector<double> g, w, V, dV, Vg, dVg;
+  gauss_legendre(nq, g, w);
+  lagrange_eval(gll_points(k), g, V, dV);  // V[a*N+i] = l_i(g_a)
+  lagrange_eval(g, g, Vg, dVg);            // dVg[a*nq+b] = L_b'(g_a)
+  std::vector<T> t;
+  for (int a = 0; a < N; a++)
+    for (int i = 0; i < N; i++) t.push_back((T)V[a * N + i]);
+  for (int a = 0; a < N; a++)
+    for (int b = 0; b < N; b++) t.push_back((T)dVg[a * N + b]);
+  for (int a = 0; a < N; a++) t.push_back((T)g[a]);
+  for (int a = 0; a < N; a++) t.push_back((T)w[a]);
+  for (int a = 0; a < N; a++)
+    for (int i = 0; i < N; i++) t.push_back((T)dV[a * N + i]);
+  out.resize(t.size() * sizeof(T));
+  std::memcpy(out.data(), t.data(), out.size());
+}
+
+template <typename T> static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+  const int k = sp->degree, N = k + 1;
+  if (op->nq1d != N) return fail(MF_EUNSUPPORTED, "hex operators support nq1d = k+1 only");
+  build_hex_table<T>(k, op->nq1d, op->tab_host);
+  if (op->tab_host.size() != hex_table_bytes<T>(N)) return fail(MF_EDEVICE, "hex table layout mismatch");
+  const int64_t nc = sp->ncells;
+  std::vector<T> geo((size_t)nc * 24, T(0));
+  for (int64_t K = 0; K < nc; K++) {
+    for (int a = 0; a < 3; a++) {
+      double X[8], c[8];
+      for (int v = 0; v < 8; v++) X[v] = sp->coords[(int64_t)sp->cell2vert[K * 8 + v] * 3 + a];
+      trilinear_coeffs(X, c);
+      for (int m = 1; m < 8; m++) geo[K * 24 + 3 * (m - 1) + a] = (T)c[m];
+    }
+  }
+  int rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+  if (rc) return rc;
+  if (op->has_coef) {
+    std::vector<T> cf((size_t)nc * 8);
+    for (int64_t K = 0; K < nc; K++) {
+      double X[8], c[8];
+      for (int v = 0; v < 8; v++) X[v] = pr->vertex_coef[sp->cell2vert[K * 8 + v]];
+      trilinear_coeffs(X, c);
+      for (int m = 0; m < 8; m++) cf[K * 8 + m] = (T)c[m];
+    }
+    rc = upload(op->coef, cf.data(), cf.size() * sizeof(T), s);
+    if (rc) return rc;
+  }
+  return MF_OK;
+}
+
+template <typename T> static int setup_tet(mf_op *op, const mf_space *sp, hipStream_t s) {
+  const int k = sp->degree, D = sp->D;
+  std::vector<double> pts, w, phi, dphi;
+  const int deg = 2 * k - 2;  // grad u . grad v on affine cells
+  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree");
+  const int nq = (int)w.size();
+  op->nqp = nq;
+  tet_lagrange(k, pts, phi, dphi);
+  std::vector<T> tab;
+  for (double v : dphi) tab.push_back((T)v);
+  for (double v : w) tab.push_back((T)v);
+  int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
+  if (rc) return rc;
+  const int64_t nc = sp->ncells, nb = (nc + 63) / 64;
+  std::vector<T> geo((size_t)nb * 10 * 64, T(0));
+  for (int64_t K = 0; K < nc; K++) {
+    const int32_t *cv = sp->cell2vert.data() + K * 4;
+    double J[3][3];
+    for (int a = 0; a < 3; a++)
+      for (int b = 0; b < 3; b++) J[a][b] = sp->coords[(int64_t)cv[b + 1] * 3 + a] - sp->coords[(int64_t)cv[0] * 3 + a];
+    // columns j_b = J[:, b]; rows of J^{-1}: (j2 x j3, j3 x j1, j1 x j2) / det
+    double jc[3][3];
+    for (int b = 0; b < 3; b++)
+      for (int a = 0; a < 3; a++) jc[b][a] = J[a][b];
+    auto cross = [](const double *u, const double *v, double *o) {
+      o[0] = u[1] * v[2] - u[2] * v[1];
+      o[1] = u[2] * v[0] - u[0] * v[2];
+      o[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    double R[3][3];
+    cross(jc[1], jc[2], R[0]);
+    cross(jc[2], jc[0], R[1]);
+    cross(jc[0], jc[1], R[2]);
+    const double det = jc[0][0] * R[0][0] + jc[0][1] * R[0][1] + jc[0][2] * R[0][2];
+    const int64_t b = K / 64, l = K % 64;
+    for (int bb = 0; bb < 3; bb++)
+      for (int a = 0; a < 3; a++) geo[(b * 10 + 3 * bb + a) * 64 + l] = (T)(R[bb][a] / det);
+    geo[(b * 10 + 9) * 64 + l] = (T)std::fabs(det);
+  }
+  return upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+}
+
+template <typename T> static int setup_tri(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+  const int64_t nc = sp->ncells;
+  std::vector<T> geo((size_t)nc * 4, T(0));
+  for (int64_t K = 0; K < nc; K++) {
+    const int32_t *cv = sp->cell2vert.data() + K * 3;
+    const double *p0 = &sp->coords[(int64_t)cv[0] * 2], *p1 = &sp->coords[(int64_t)cv[1] * 2],
+                 *p2 = &sp->coords[(int64_t)cv[2] * 2];
+    const double area = 0.5 * std::fabs((p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]));
+    for (int i = 0; i < 3; i++) geo[K * 4 + i] = (T)(area * (op->has_coef ? pr->vertex_coef[cv[i]] : 1.0));
+  }
+  op->nqp = 0;
+  return upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+}
+
+static void count_work(mf_op *op) {
+  const double s = op->precision == MF_F64 ? 8.0 : 4.0;
+  const double nc = (double)op->ncells, nd = (double)op->ndofs;
+  const int comps = op->ncomp;
+  double fl = 0.0, by = 2.0 * nd * s + 4.0 * op->D * nc;
+  if (op->cell_type == MF_CELL_HEX) {
+    const double n = op->degree + 1, q3 = n * n * n;
+    const bool grad = op->kind != MF_OP_MASS, mass = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ;
+    // 1D contractions: 3 forward + 3 backward with B, plus 3 + 3 with the collocation
+    // derivative when gradients are needed; each costs 2 n^4 flops per component.
+    const double contr = (grad ? 12.0 : 6.0) * 2.0 * n * n * n * n * comps;
+    // per point: Jacobian 12, adjugate rows 18 (6 for the mass-only kernel), det 5,
+    // weights/scale 4; per component: push-forward 18 + fluxes 21, mass term 4
+    const double geo = grad ? 39.0 : 24.0;
+    const double pw = (grad ? 39.0 : 0.0) * comps + (mass ? 4.0 * comps : 0.0);
+    fl = nc * (contr + q3 * (geo + pw));
+    by += nc * 24.0 * s + (op->has_coef ? nc * 8.0 * s : 0.0);
+  } else if (op->cell_type == MF_CELL_TET) {
+    const double D = op->D, Q = op->nqp;
+    // per point per component: reference gradient 6D, its push-forward 18, stress 8,
+    // P 20, test contraction 6D
+    fl = nc * Q * 3.0 * (12.0 * D + 46.0);
+    by += nc * 10.0 * s;
+  } else {
+    fl = nc * 30.0;
+    by += nc * 3.0 * s;
+  }
+  op->flops = fl;
+  op->bytes = by;
+}
+
+template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool acc,
+                                            bool bc, hipStream_t s) {
+  int rc = MF_OK;
+  if (!acc) {
+    rc = launch_fill<T>(y, T(0), op->ndofs, s);
+    if (rc) return rc;
+  }
+  if (op->cell_type == MF_CELL_HEX) {
+    HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, x, y, c0, c1,
+                 op->ncomp};
+    rc = launch_hex_apply<T>(op->degree + 1, op->kind, a, op->tab_host.data(), s);
+  } else if (op->cell_type == MF_CELL_TET) {
+    TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu};
+    rc = launch_tet_elasticity<T>(op->degree, op->nqp, a, s);
+  } else {
+    TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), x, y, c0, c1};
+    rc = launch_tri_mass<T>(a, s);
+  }
+  if (rc) return rc;
+  if (bc && op->n_bc_dofs) rc = launch_copy_constrained<T>(op->bc_dofs.as<int32_t>(), op->n_bc_dofs, x, y, s);
+  return rc;
+}
+
+template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
+  int rc = launch_fill<T>(d, T(0), op->ndofs, s);
+  if (rc) return rc;
+  if (op->cell_type == MF_CELL_HEX) {
+    HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, nullptr, d, 0,
+                 op->ncells, op->ncomp};
+    rc = launch_hex_diag<T>(op->degree + 1, op->kind, a, op->tab_host.data(), s);
+  } else if (op->cell_type == MF_CELL_TET) {
+    TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), nullptr, d, 0, op->ncells, (T)op->lam,
+                 (T)op->mu};
+    rc = launch_tet_elasticity_diag<T>(op->degree, op->nqp, a, s);
+  } else {
+    TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), nullptr, d, 0, op->ncells};
+    rc = launch_tri_mass_diag<T>(a, s);
+  }
+  if (rc) return rc;
+  if (op->n_bc_dofs) rc = launch_set_constrained<T>(op->bc_dofs.as<int32_t>(), op->n_bc_dofs, T(1), d, s);
+  return rc;
+}
+
+}  // namespace mf
+
+extern "C" {
+
+int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf_op_params *params, void *stream,
+                 mf_op **out) {
+  if (!sp || !out) return fail(MF_EINVAL, "mf_op_create: null argument");
+  if (precision != MF_F64 && precision != MF_F32) return fail(MF_EINVAL, "mf_op_create: precision");
+  if (kind < MF_OP_MASS || kind > MF_OP_ELASTICITY) return fail(MF_EINVAL, "mf_op_create: operator kind");
+  mf_op_params defaults{nullptr, 1.0, 0.5, nullptr};
+  const mf_op_params *pr = params ? params : &defaults;
+  hipStream_t s = (hipStream_t)stream;
+  const int ct = sp->cell_type;
+  // supported combinations
+  bool ok = false;
+  if (ct == MF_CELL_HEX)
+    ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3) : (kind != MF_OP_ELASTICITY && sp->ncomp == 1);
+  else if (ct == MF_CELL_TET)
+    ok = kind == MF_OP_ELASTICITY && sp->ncomp == 3;
+  else
+    ok = kind == MF_OP_MASS && sp->ncomp == 1;
+  if (!ok) return fail(MF_EUNSUPPORTED, "mf_op_create: operator / cell / ncomp combination not built");
+  if (kind == MF_OP_POISSON && !pr->vertex_coef) return fail(MF_EINVAL, "POISSON needs vertex_coef (kappa)");
+  std::unique_ptr<mf_op> op(new (std::nothrow) mf_op);
+  if (!op) return fail(MF_ENOMEM, "mf_op_create: host allocation");
+  op->cell_type = ct;
+  op->kind = kind;
+  op->precision = precision;
+  op->degree = sp->degree;
+  op->ncomp = sp->ncomp;
+  op->D = sp->D;
+  op->ncells = sp->ncells;
+  op->nnodes = sp->nnodes;
+  op->ndofs = sp->nnodes * sp->ncomp;
+  op->lam = pr->lambda;
+  op->mu = pr->mu;
+  op->has_coef = pr->vertex_coef != nullptr && (kind == MF_OP_MASS || kind == MF_OP_POISSON);
+  op->nq1d = ct == MF_CELL_HEX ? (nq1d > 0 ? nq1d : sp->degree + 1) : 0;
+  if (ct == MF_CELL_HEX) op->nqp = op->nq1d * op->nq1d * op->nq1d;
+
+  // maps: constrained nodes are stored as -1 (gathered as 0, never scattered)
+  const int64_t nc = sp->ncells;
+  const int D = sp->D;
+  std::vector<int32_t> m;
+  auto flag = [&](int32_t node) { return (pr->dirichlet && pr->dirichlet[node]) ? -1 : node; };
+  if (ct == MF_CELL_TET) {
+    const int64_t nb = (nc + 63) / 64;
+    m.assign((size_t)nb * D * 64, -1);
+    for (int64_t K = 0; K < nc; K++)
+      for (int i = 0; i < D; i++) m[((K / 64) * D + i) * 64 + K % 64] = flag(sp->cell2node[K * D + i]);
+  } else {
+    m.resize((size_t)nc * D);
+    for (int64_t i = 0; i < nc * D; i++) m[i] = flag(sp->cell2node[i]);
+  }
+  int rc = upload(op->map, m.data(), m.size() * sizeof(int32_t), s);
+  if (rc) return rc;
+  if (pr->dirichlet) {
+    std::vector<int32_t> bd;
+    for (int64_t n = 0; n < sp->nnodes; n++)
+      if (pr->dirichlet[n])
+        for (int c = 0; c < sp->ncomp; c++) bd.push_back((int32_t)(n * sp->ncomp + c));
+    op->n_bc_dofs = (int64_t)bd.size();
+    rc = upload(op->bc_dofs, bd.data(), bd.size() * sizeof(int32_t), s);
+    if (rc) return rc;
+  }
+  if (ct == MF_CELL_HEX)
+    rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, s) : setup_hex<float>(op.get(), sp, pr, s);
+  else if (ct == MF_CELL_TET)
+    rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, s) : setup_tet<float>(op.get(), sp, s);
+  else
+    rc = precision == MF_F64 ? setup_tri<double>(op.get(), sp, pr, s) : setup_tri<float>(op.get(), sp, pr, s);
+  if (rc) return rc;
+  MF_HIP(hipStreamSynchronize(s));
+  count_work(op.get());
+  *out = op.release();
+  return MF_OK;
+}
+
+void mf_op_destroy(mf_op *op) {
+  if (!op) return;
+  (void)hipDeviceSynchronize();
+  delete op;
+}
+
+int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x, void *y, int accumulate,
+                      void *stream) {
+  if (!op || !x || !y) return fail(MF_EINVAL, "mf_op_apply_range: null argument");
+  if (start < 0 || end > op->ncells || start > end) return fail(MF_EINVAL, "mf_op_apply_range: bad cell range");
+  if (x == y) return fail(MF_EINVAL, "mf_op_apply_range: x and y alias");
+  hipStream_t s = (hipStream_t)stream;
+  return op->precision == MF_F64
+             ? op_apply_t<double>(op, start, end, (const double *)x, (double *)y, accumulate != 0, false, s)
+             : op_apply_t<float>(op, start, end, (const float *)x, (float *)y, accumulate != 0, false, s);
+}
+
+int mf_op_apply(const mf_op *op, const void *x, void *y, void *stream) {
+  if (!op || !x || !y) return fail(MF_EINVAL, "mf_op_apply: null argument");
+  if (x == y) return fail(MF_EINVAL, "mf_op_apply: x and y alias");
+  hipStream_t s = (hipStream_t)stream;
+  return op->precision == MF_F64
+             ? op_apply_t<double>(op, 0, op->ncells, (const double *)x, (double *)y, false, true, s)
+             : op_apply_t<float>(op, 0, op->ncells, (const float *)x, (float *)y, false, true, s);
+}
+
+int mf_op_diagonal(const mf_op *op, void *d, void *stream) {
+  if (!op || !d) return fail(MF_EINVAL, "mf_op_diagonal: null argument");
+  hipStream_t s = (hipStream_t)stream;
+  return op->precision == MF_F64 ? op_diag_t<double>(op, (double *)d, s) : op_diag_t<float>(op, (float *)d, s);
+}
+
+int mf_op_get_info(const mf_op *op, mf_op_info *info) {
+  if (!op || !info) return fail(MF_EINVAL, "mf_op_get_info: null argument");
+  info->ncells = op->ncells;
+  info->nnodes = op->nnodes;
+  info->ndofs = op->ndofs;
+  info->cell_type = op->cell_type;
+  info->kind = op->kind;
+  info->precision = op->precision;
+  info->degree = op->degree;
+  info->ncomp = op->ncomp;
+  info->nq1d = op->nq1d;
+  info->nqp = op->nqp;
+  info->dofs_per_cell = op->D;
+  info->flops_per_apply = op->flops;
+  info->bytes_per_apply = op->bytes;
+  return MF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,185 @@
+// Operator action on affine simplices.
+//
+// Affine cells have one Jacobian per cell (Section 2.1: the Jacobian is
+// constant on each triangle when the coordinate map is affine; Section 4.1:
+// tri and tet meshes use an affine map), so the FP64 setup precomputes
+// J^{-1} and |det J| per cell once. Simplices are not sum-factorised
+// (Section 4.2.3): the kernels contract dense tabulations of the reference
+// basis gradients at quadrature points, the paper's constant tables.
+//
+// GPU mapping follows the paper's cross-element idea (Section 3.1: one SIMD
+// lane per element, element index fastest in every temporary) on a 64-wide
+// wavefront: lane = cell, and the AoSoA layouts [cell/64][entry][cell%64]
+// make every map / geometry load a unit-stride wavefront access. The tables
+// are uniform across the wavefront and are read through the scalar cache.
+#include "mf_internal.h"
+
+namespace mf {
+
+__device__ __forceinline__ void atomic_add_s(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add_s(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// ----------------------------------------------------------------- tet linear elasticity
+// a(u, v) = int sigma(u) : grad v, sigma = lambda tr(grad u) I + mu (grad u + grad u^T)
+// (supplementary material, "elasticity", with Lame parameters).
+// Block = 3 wavefronts; wavefront c carries displacement component c of the same 64
+// cells, so each lane keeps only that component's D nodal values (and D outputs) in
+// registers. The three components meet once per quadrature point through LDS to form
+// the stress.
+template <typename T, int K, int NQ>
+__global__ void __launch_bounds__(192) tet_elasticity_kernel(const TetArgs<T> A) {
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  __shared__ T sG[2][9][64];
+  const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+  const int64_t batch = A.c0 / 64 + blockIdx.x;
+  const int64_t cell = batch * 64 + lane;
+  const bool valid = cell >= A.c0 && cell < A.c1;
+  const int32_t *mp = A.map + batch * (D * 64) + lane;
+  const T *gp = A.geo + batch * (10 * 64) + lane;
+  T Ki[9];
+#pragma unroll
+  for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
+  const T adet = gp[9 * 64];
+  T xe[D], ye[D];
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int idx = valid ? mp[i * 64] : -1;
+    xe[i] = idx >= 0 ? A.x[3 * (int64_t)idx + c] : T(0);
+    ye[i] = T(0);
+  }
+  const T *__restrict__ dphi = A.tab;
+  const T *__restrict__ qw = A.tab + NQ * D * 3;
+  for (int q = 0; q < NQ; q++) {
+    const T *tq = dphi + q * D * 3;
+    T g0 = T(0), g1 = T(0), g2 = T(0);
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      g0 += xe[i] * tq[3 * i + 0];
+      g1 += xe[i] * tq[3 * i + 1];
+      g2 += xe[i] * tq[3 * i + 2];
+    }
+    const int buf = q & 1;
+#pragma unroll
+    for (int a = 0; a < 3; a++) sG[buf][3 * c + a][lane] = g0 * Ki[a] + g1 * Ki[3 + a] + g2 * Ki[6 + a];
+    __syncthreads();
+    // row c and column c of the displacement gradient (c is uniform per wavefront)
+    const T tr = sG[buf][0][lane] + sG[buf][4][lane] + sG[buf][8][lane];
+    T sig[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++)
+      sig[a] = A.mu * (sG[buf][3 * c + a][lane] + sG[buf][3 * a + c][lane]) + (a == c ? A.lam * tr : T(0));
+    const T wd = qw[q] * adet;
+    T P[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) P[d] = wd * (sig[0] * Ki[3 * d + 0] + sig[1] * Ki[3 * d + 1] + sig[2] * Ki[3 * d + 2]);
+#pragma unroll
+    for (int i = 0; i < D; i++) ye[i] += P[0] * tq[3 * i + 0] + P[1] * tq[3 * i + 1] + P[2] * tq[3 * i + 2];
+  }
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int idx = valid ? mp[i * 64] : -1;
+    if (idx >= 0) atomic_add_s(&A.y[3 * (int64_t)idx + c], ye[i]);
+  }
+}
+
+// diag[(i,c)] = sum_q w |det| [ lambda (d_c phi_i)^2 + mu (|grad phi_i|^2 + (d_c phi_i)^2) ]
+template <typename T, int K, int NQ>
+__global__ void __launch_bounds__(192) tet_elasticity_diag_kernel(const TetArgs<T> A) {
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
+  const int64_t batch = A.c0 / 64 + blockIdx.x;
+  const int64_t cell = batch * 64 + lane;
+  const bool valid = cell >= A.c0 && cell < A.c1;
+  const int32_t *mp = A.map + batch * (D * 64) + lane;
+  const T *gp = A.geo + batch * (10 * 64) + lane;
+  T Ki[9];
+  for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
+  const T adet = gp[9 * 64];
+  const T *dphi = A.tab;
+  const T *qw = A.tab + NQ * D * 3;
+  for (int i = 0; i < D; i++) {
+    T acc = T(0);
+    for (int q = 0; q < NQ; q++) {
+      const T *tq = dphi + (q * D + i) * 3;
+      T gr[3];
+      for (int a = 0; a < 3; a++) gr[a] = tq[0] * Ki[a] + tq[1] * Ki[3 + a] + tq[2] * Ki[6 + a];
+      const T n2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
+      const T gc = c == 0 ? gr[0] : (c == 1 ? gr[1] : gr[2]);
+      acc += qw[q] * adet * (A.lam * gc * gc + A.mu * (n2 + gc * gc));
+    }
+    const int idx = valid ? mp[i * 64] : -1;
+    if (idx >= 0) atomic_add_s(&A.y[3 * (int64_t)idx + c], acc);
+  }
+}
+
+template <typename T, int K, int NQ>
+static int launch_tet_kq(const TetArgs<T> &a, hipStream_t s, bool diag) {
+  const int64_t b0 = a.c0 / 64, b1 = (a.c1 + 63) / 64;
+  if (a.c1 <= a.c0) return MF_OK;
+  dim3 grid((unsigned)(b1 - b0)), block(192);
+  if (diag) tet_elasticity_diag_kernel<T, K, NQ><<<grid, block, 0, s>>>(a);
+  else tet_elasticity_kernel<T, K, NQ><<<grid, block, 0, s>>>(a);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T> static int launch_tet(int k, int nq, const TetArgs<T> &a, hipStream_t s, bool diag) {
+  if (k == 1 && nq == 1) return launch_tet_kq<T, 1, 1>(a, s, diag);
+  if (k == 2 && nq == 4) return launch_tet_kq<T, 2, 4>(a, s, diag);
+  if (k == 3 && nq == 14) return launch_tet_kq<T, 3, 14>(a, s, diag);
+  return fail(MF_EUNSUPPORTED, "tet elasticity: degree / rule");
+}
+
+template <typename T> int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, hipStream_t s) {
+  return launch_tet<T>(k, nq, a, s, false);
+}
+template <typename T> int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s) {
+  return launch_tet<T>(k, nq, a, s, true);
+}
+template int launch_tet_elasticity<double>(int, int, const TetArgs<double> &, hipStream_t);
+template int launch_tet_elasticity<float>(int, int, const TetArgs<float> &, hipStream_t);
+template int launch_tet_elasticity_diag<double>(int, int, const TetArgs<double> &, hipStream_t);
+template int launch_tet_elasticity_diag<float>(int, int, const TetArgs<float> &, hipStream_t);
+
+// ----------------------------------------------------------------- tri P1 mass with P1 coefficient
+// Exact element matrix: int_T lam_a lam_i lam_j = |T| (1 + d_ai + d_aj + d_ij + 2 d_ai d_aj) / 60,
+// so with s_a = |T| c_a, S = sum s_a, X = sum x_j:
+//   y_i = [ (S + s_i) X + <s, x> + (S + 2 s_i) x_i ] / 60.
+template <typename T>
+__global__ void __launch_bounds__(256) tri_mass_kernel(const TriArgs<T> A, bool diag) {
+  const int64_t cell = A.c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= A.c1) return;
+  int idx[3];
+  T s[3], x[3];
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    idx[i] = A.map[cell * 3 + i];
+    s[i] = A.geo[cell * 4 + i];
+    x[i] = (!diag && idx[i] >= 0) ? A.x[idx[i]] : T(0);
+  }
+  const T S = s[0] + s[1] + s[2];
+  const T X = x[0] + x[1] + x[2];
+  const T sx = s[0] * x[0] + s[1] * x[1] + s[2] * x[2];
+  const T k60 = T(1) / T(60);
+#pragma unroll
+  for (int i = 0; i < 3; i++) {
+    const T v = diag ? (T(2) * S + T(4) * s[i]) * k60 : ((S + s[i]) * X + sx + (S + T(2) * s[i]) * x[i]) * k60;
+    if (idx[i] >= 0) atomic_add_s(&A.y[idx[i]], v);
+  }
+}
+
+template <typename T> static int launch_tri(const TriArgs<T> &a, hipStream_t s, bool diag) {
+  const int64_t n = a.c1 - a.c0;
+  if (n <= 0) return MF_OK;
+  tri_mass_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(a, diag);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template <typename T> int launch_tri_mass(const TriArgs<T> &a, hipStream_t s) { return launch_tri<T>(a, s, false); }
+template <typename T> int launch_tri_mass_diag(const TriArgs<T> &a, hipStream_t s) { return launch_tri<T>(a, s, true); }
+template int launch_tri_mass<double>(const TriArgs<double> &, hipStream_t);
+template int launch_tri_mass<float>(const TriArgs<float> &, hipStream_t);
+template int launch_tri_mass_diag<double>(const TriArgs<double> &, hipStream_t);
+template int launch_tri_mass_diag<float>(const TriArgs<float> &, hipStream_t);
+
+}  // namespace mf
