@@ -91,12 +91,24 @@ int mf_mesh_create(int cell_type, int64_t nverts, const double *coords, int64_t 
 int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *cell2node,
                     int64_t nnodes, mf_space **out);
 
+/* Scatter-add strategies for the race of shared nodes (the paper serialises
+ * the write-back, Section 3.1, and proposes conflict detection, Section 5):
+ *   COLOURED  cells are coloured at space creation so that cells of one colour
+ *             share no node; a full apply is one launch per colour with plain
+ *             read-modify-write stores -- deterministic, bit-reproducible.
+ *   ATOMIC    one launch, device-scope floating-point atomics.
+ *   AUTO      COLOURED for 3-component hex operators of degree >= 3 on meshes
+ *             of at least 4096 cells (where it measured faster), else ATOMIC.
+ * Range applies (mf_op_apply_range*) always use ATOMIC. */
+enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2 };
+
 typedef struct {
   const double *vertex_coef; /* host, nverts; MASS coefficient c or POISSON kappa; NULL -> 1 */
   double lambda, mu;         /* ELASTICITY Lame parameters */
   const uint8_t *dirichlet;  /* host, nnodes; nonzero marks a node whose every component is
                                 constrained: (A x)_b = x_b there, and constrained values are
                                 excluded from every other row. NULL -> no constraint. */
+  int scatter;               /* MF_SCATTER_* */
 } mf_op_params;
 
 /* Create an operator. precision MF_F64 or MF_F32 (FP32 arithmetic with FP32
@@ -123,6 +135,29 @@ int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x
 /* d = diag(A) (ndofs, op precision); constrained dofs get 1. Used as the Jacobi
  * preconditioner. */
 int mf_op_diagonal(const mf_op *op, void *d, void *stream);
+
+/* Internal cell order and numbering. Every space colours its cells greedily
+ * (first fit, user cell order, two cells conflict when they share a vertex --
+ * for these conforming spaces exactly when they share a node) and orders them
+ * by colour, user order within a colour. mf_space_get_colouring writes the
+ * user cell of each internal cell (ncells entries, may be NULL), the colour
+ * offsets (ncolours + 1 entries, may be NULL) and the number of colours.
+ * Nodes are numbered internally in order of first appearance when the cells
+ * are traversed in that internal order; the kernels gather
+ * and scatter only in that numbering, so the nodes of neighbouring cells are
+ * neighbours in memory whatever numbering the caller uses. mf_op_apply and
+ * mf_op_apply_range take user-numbered vectors and pay one permutation in and
+ * one out; the _internal variants take internally numbered vectors (dof =
+ * ncomp*internal_node + component) and run only the operator kernels.
+ * mf_space_get_permutation writes internal_to_user[i] = the user node of
+ * internal node i (nnodes entries, host). All operators built on one space
+ * share its numbering. */
+int mf_space_get_colouring(const mf_space *space, int32_t *internal_to_user_cell, int64_t *colour_ptr,
+                           int *ncolours);
+int mf_space_get_permutation(const mf_space *space, int32_t *internal_to_user);
+int mf_op_apply_internal(const mf_op *op, const void *x, void *y, void *stream);
+int mf_op_apply_range_internal(const mf_op *op, int64_t start, int64_t end, const void *x, void *y,
+                               int accumulate, void *stream);
 
 typedef struct {
   int64_t ncells, nnodes, ndofs;

@@ -6,6 +6,6 @@ used for device memory and streams. If the library has not been built the
 first call raises -- there is no CPU fallback.
 """
 from .api import (  # noqa: F401
-    CELL_HEX, CELL_TET, CELL_TRI, F32, F64, MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY,
+    CELL_HEX, CELL_TET, CELL_TRI, F32, F64, SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED, MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY,
     MFError, Mesh, Space, Operator, JacobiPrecond, cg_solve, library_path, load_library,
 )

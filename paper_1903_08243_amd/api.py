@@ -14,6 +14,7 @@ import numpy as np
 CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
 MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY = range(5)
 F64, F32 = 0, 1
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED = 0, 1, 2
 _ERR = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EMESH", -5: "ENOTCONV", -6: "EBREAKDOWN",
         -7: "EUNSUPPORTED"}
 
@@ -42,7 +43,7 @@ class _OpInfo(ctypes.Structure):
 
 class _OpParams(ctypes.Structure):
     _fields_ = [("vertex_coef", ctypes.c_void_p), ("lam", ctypes.c_double), ("mu", ctypes.c_double),
-                ("dirichlet", ctypes.c_void_p)]
+                ("dirichlet", ctypes.c_void_p), ("scatter", ctypes.c_int)]
 
 
 class CGInfo(ctypes.Structure):
@@ -71,6 +72,10 @@ def load_library():
         "mf_op_apply": (I, [P, P, P, P]),
         "mf_op_apply_range": (I, [P, I64, I64, P, P, I, P]),
         "mf_op_diagonal": (I, [P, P, P]),
+        "mf_op_apply_internal": (I, [P, P, P, P]),
+        "mf_op_apply_range_internal": (I, [P, I64, I64, P, P, I, P]),
+        "mf_space_get_permutation": (I, [P, P]),
+        "mf_space_get_colouring": (I, [P, P, P, ctypes.POINTER(ctypes.c_int)]),
         "mf_op_get_info": (I, [P, ctypes.POINTER(_OpInfo)]),
         "mf_precond_create_jacobi": (I, [P, P, PP]),
         "mf_cg_solve": (I, [P, P, P, P, P, D, D, I, ctypes.POINTER(CGInfo), P]),
@@ -146,6 +151,22 @@ class Space:
         self.degree, self.ncomp, self.nnodes = degree, ncomp, int(nnodes)
         self.ndofs = self.nnodes * ncomp
 
+    def internal_to_user(self):
+        """Host array: user node of each internal node (the library's cell-order numbering)."""
+        out = np.empty(self.nnodes, dtype=np.int32)
+        _check(load_library().mf_space_get_permutation(self.handle, out.ctypes.data))
+        return out
+
+    def colouring(self):
+        """(internal -> user cell order, colour offsets) of the library's cell colouring."""
+        L = load_library()
+        n = ctypes.c_int()
+        _check(L.mf_space_get_colouring(self.handle, None, None, ctypes.byref(n)))
+        order = np.empty(self.mesh.ncells, dtype=np.int32)
+        ptr = np.empty(n.value + 1, dtype=np.int64)
+        _check(L.mf_space_get_colouring(self.handle, order.ctypes.data, ptr.ctypes.data, ctypes.byref(n)))
+        return order, ptr
+
     @classmethod
     def from_meshgen(cls, s, mesh: Mesh | None = None):
         mesh = mesh or Mesh.from_meshgen(s.mesh)
@@ -161,12 +182,12 @@ class Operator:
     """A matrix-free operator; apply() runs the HIP kernels on the current torch stream."""
 
     def __init__(self, space: Space, kind, precision=F64, nq1d=0, vertex_coef=None, lam=1.0, mu=0.5,
-                 dirichlet=None, stream=None):
+                 dirichlet=None, scatter=SCATTER_AUTO, stream=None):
         L = load_library()
         self._coef = None if vertex_coef is None else _np(vertex_coef, np.float64)
         self._bc = None if dirichlet is None else _np(dirichlet, np.uint8)
         pr = _OpParams(None if self._coef is None else self._coef.ctypes.data, lam, mu,
-                       None if self._bc is None else self._bc.ctypes.data)
+                       None if self._bc is None else self._bc.ctypes.data, scatter)
         h = ctypes.c_void_p()
         _check(L.mf_op_create(space.handle, kind, precision, nq1d, ctypes.byref(pr), _stream(stream),
                               ctypes.byref(h)))
@@ -189,6 +210,23 @@ class Operator:
         self._size(x), self._size(y)
         _check(load_library().mf_op_apply(self.handle, _dev(x, self.torch_dtype), _dev(y, self.torch_dtype),
                                           _stream(stream)))
+        return y
+
+    def apply_internal(self, x, y=None, stream=None):
+        """y = A x with x, y in the space's internal numbering (no boundary permutation)."""
+        import torch
+        if y is None:
+            y = torch.empty(self.ndofs, dtype=self.torch_dtype, device=x.device)
+        self._size(x), self._size(y)
+        _check(load_library().mf_op_apply_internal(self.handle, _dev(x, self.torch_dtype),
+                                                   _dev(y, self.torch_dtype), _stream(stream)))
+        return y
+
+    def apply_range_internal(self, start, end, x, y, accumulate=False, stream=None):
+        self._size(x), self._size(y)
+        _check(load_library().mf_op_apply_range_internal(self.handle, start, end, _dev(x, self.torch_dtype),
+                                                         _dev(y, self.torch_dtype), int(accumulate),
+                                                         _stream(stream)))
         return y
 
     def apply_range(self, start, end, x, y, accumulate=False, stream=None):

@@ -23,7 +23,7 @@ static constexpr int CHUNK = 8;
 
 struct CgWork {
   int64_t n = 0;
-  DeviceBuffer r, p, Ap, part, st, p32, Ap32, d, x32;
+  DeviceBuffer r, p, Ap, part, st, p32, Ap32, d, bi, xi;
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   CgState *host_st = nullptr;  // pinned
@@ -37,7 +37,8 @@ struct CgWork {
   }
 };
 
-static int apply_any(const mf_op *A, const void *x, void *y, hipStream_t s) { return mf_op_apply(A, x, y, s); }
+// all solver vectors live in the operators' internal numbering
+static int apply_any(const mf_op *A, const void *x, void *y, hipStream_t s) { return op_apply_internal(A, x, y, s); }
 
 // One chunk of PCG iterations on operator A (FP64 or FP32 action), recorded on w.s.
 static int record_chunk(const mf_op *A, const double *dinv, double *x, CgWork &w) {
@@ -107,7 +108,7 @@ static int pcg_core(const mf_op *A, const double *dinv, double *x, double tol2, 
 }
 
 static int residual(const mf_op *A64, const double *b, const double *x, CgWork &w, double &rr) {
-  int rc = mf_op_apply(A64, x, w.Ap.ptr, w.s);
+  int rc = op_apply_internal(A64, x, w.Ap.ptr, w.s);
   if (rc) return rc;
   rc = cg_residual(b, w.Ap.ptr, false, w.r.as<double>(), w.n, w.part.as<double>(), w.st.as<CgState>(), w.s);
   if (rc) return rc;
@@ -130,10 +131,11 @@ int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out) {
   if (!P) return fail(MF_ENOMEM, "mf_precond_create_jacobi: host allocation");
   P->kind = 0;
   P->n = A->ndofs;
+  P->numbering_id = A->numbering_id;
   DeviceBuffer d;
   int rc = d.alloc((size_t)A->ndofs * (A->precision == MF_F64 ? 8 : 4));
   if (!rc) rc = P->dinv.alloc((size_t)A->ndofs * 8);
-  if (!rc) rc = mf_op_diagonal(A, d.ptr, s);
+  if (!rc) rc = op_diagonal_internal(A, d.ptr, s);
   if (!rc) rc = cg_recip(d.ptr, A->precision == MF_F32, P->dinv.as<double>(), A->ndofs, s);
   if (rc) return rc;
   MF_HIP(hipStreamSynchronize(s));
@@ -153,7 +155,10 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
   if (A64->precision != MF_F64) return fail(MF_EINVAL, "mf_cg_solve: A64 must be an FP64 operator");
   if (A32 && (A32->ndofs != A64->ndofs || A32->precision != MF_F32))
     return fail(MF_EINVAL, "mf_cg_solve: A32 must be an FP32 operator of the same size");
-  if (M && M->n != A64->ndofs) return fail(MF_EINVAL, "mf_cg_solve: preconditioner size");
+  if (A32 && A32->numbering_id != A64->numbering_id)
+    return fail(MF_EINVAL, "mf_cg_solve: A32 and A64 must be built on the same space");
+  if (M && (M->n != A64->ndofs || M->numbering_id != A64->numbering_id))
+    return fail(MF_EINVAL, "mf_cg_solve: preconditioner built for another space");
   if (!(rtol > 0.0) || maxit < 0) return fail(MF_EINVAL, "mf_cg_solve: rtol / maxit");
   if (M && M->kind != 0) return fail(MF_EUNSUPPORTED, "mf_cg_solve: use mf_fcg_solve for learned preconditioners");
   const int64_t n = A64->ndofs;
@@ -178,6 +183,18 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
   }
   if (rc) return rc;
   const double *dinv = M ? M->dinv.as<double>() : nullptr;
+  // move b and x into the internal numbering (once per solve)
+  double *x_user = x;
+  if (!A64->identity) {
+    rc = w.bi.alloc((size_t)n * 8);
+    if (!rc) rc = w.xi.alloc((size_t)n * 8);
+    const int32_t *uoi = A64->perm.as<int32_t>();
+    if (!rc) rc = launch_to_internal<double>(uoi, A64->nnodes, A64->ncomp, b, w.bi.as<double>(), w.s);
+    if (!rc) rc = launch_to_internal<double>(uoi, A64->nnodes, A64->ncomp, x, w.xi.as<double>(), w.s);
+    if (rc) return rc;
+    b = w.bi.as<double>();
+    x = w.xi.as<double>();
+  }
 
   // ||b||^2 via the residual kernel with Ax = 0 is avoided: r = b - A*0 costs an apply; use r = b - Ap with Ap = 0
   rc = launch_fill<double>(w.Ap.as<double>(), 0.0, n, w.s);
@@ -188,7 +205,7 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
   const double bb = st.rr;
   mf_cg_info inf{0, 0, 0, 0.0};
   if (bb == 0.0) {
-    rc = launch_fill<double>(x, 0.0, n, w.s);
+    rc = launch_fill<double>(x_user, 0.0, n, w.s);
     if (!rc) rc = read_state(w, st);
     if (info) *info = inf;
     return rc;
@@ -235,6 +252,10 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
       rc = cg_axpy(x, w.d.as<double>(), n, w.s);
       if (rc) return rc;
     }
+  }
+  if (x != x_user) {
+    rc = launch_from_internal<double>(A64->perm.as<int32_t>(), A64->nnodes, A64->ncomp, x, x_user, false, w.s);
+    if (rc) return rc;
   }
   inf.rel_residual = std::sqrt(rr / bb);
   if (status == MF_OK && !(rr == rr)) status = fail(MF_EBREAKDOWN, "non-finite residual");

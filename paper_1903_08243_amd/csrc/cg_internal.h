@@ -31,5 +31,6 @@ int cg_cast(const double *a, float *b, int64_t n, hipStream_t s);
 struct mf_precond {
   int kind = 0;  // 0 Jacobi, 1 learned
   int64_t n = 0;
-  mf::DeviceBuffer dinv;  // FP64 inverse diagonal
+  uint64_t numbering_id = 0;  // internal numbering of the operator it was built from
+  mf::DeviceBuffer dinv;      // FP64 inverse diagonal, internal numbering
 };

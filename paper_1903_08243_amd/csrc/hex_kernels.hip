@@ -9,11 +9,16 @@
 // tensor-product cell (Section 3 and Section 4.2.4: per-direction 1D loops
 // instead of dense tabulation).
 //
-// GPU mapping (gfx950): a workgroup holds EPB = floor(256 / n^2) cells; each
-// cell owns n^2 threads and three n^3 LDS buffers. A thread always holds one
-// "pencil" (a 1D line of n values) in registers, so each 1D contraction is a
-// register-only product with the uniform table (kernel-argument / scalar
-// loads) and LDS is only used to switch the pencil direction between stages.
+// GPU mapping (gfx950): a workgroup is one 64-wide wavefront holding
+// EPB = floor(64 / n^2) cells; each cell owns n^2 lanes and three n^3 LDS
+// buffers. Because a wavefront owns its cells outright, the LDS exchanges
+// between stages need no cross-wavefront barrier, and wavefronts on a SIMD
+// run independently (no barrier convoys). Lanes left over (64 - EPB n^2)
+// mirror an active lane: they compute the same pencil and store the same
+// values, but never scatter.
+// A thread always holds one "pencil" (a 1D line of n values) in registers, so
+// each 1D contraction is a register-only product with compile-time tables
+// and LDS is only used to switch the pencil direction between stages.
 // Forward:  z-contraction (B) -> y (B) -> x (B), x-derivative (collocation D)
 //           -> y-derivative (D) -> z-derivative (D, in registers)
 // Pointwise: Jacobian from the cell's trilinear coefficients (two FMAs per
@@ -21,266 +26,360 @@
 //           fluxes F = coef G grad_ref u and mass term w |det| coef u.
 // Backward: transposes in the reverse order, then atomic scatter-add.
 #include "mf_internal.h"
+#include "hex_tables.inc"
+
+#include <map>
+#include <mutex>
 
 namespace mf {
 
 enum { K_MASS = MF_OP_MASS, K_HELM = MF_OP_HELMHOLTZ, K_LAP = MF_OP_LAPLACIAN, K_POIS = MF_OP_POISSON };
 
-template <typename T, int N> struct HexTabD {
-  T B[N][N];
-  T D[N][N];
-  T g[N];
-  T w[N];
-  T dB[N][N];
+// Compile-time 1D tables (generated from the host table code at build time, see
+// gen_hex_tables.cpp): constants are materialised with scalar moves where used.
+template <typename T, int N> struct TabT {
+  static __device__ __forceinline__ constexpr T B(int a, int i) { return T(HexC<N>::B[a][i]); }
+  static __device__ __forceinline__ constexpr T D(int a, int b) { return T(HexC<N>::D[a][b]); }
+  static __device__ __forceinline__ constexpr T dB(int a, int i) { return T(HexC<N>::dB[a][i]); }
+  static __device__ __forceinline__ constexpr T g(int a) { return T(HexC<N>::g[a]); }
+  static __device__ __forceinline__ constexpr T w(int a) { return T(HexC<N>::w[a]); }
 };
 
 __device__ __forceinline__ void atomic_add_f(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f(float *p, float v) { unsafeAtomicAdd(p, v); }
 
-template <int N> constexpr int hex_epb() { return 256 / (N * N); }
+template <int N> constexpr int hex_epb() { return 64 / (N * N); }
+
+// Padded LDS layout of one cell's n^3 buffer: entry (x, y, z) at z*SZ + y*SY + x,
+// cells SE apart. The strides are chosen (by an offline search over the three
+// pencil access patterns of a wavefront) to spread 8-byte accesses over the LDS
+// banks; the natural strides n, n^2, n^3 put the y- and x-pencil accesses of a
+// quarter-wavefront on a few banks.
+template <int N> struct HexLds;
+template <> struct HexLds<2> { static constexpr int SY = 2, SZ = 5, SE = 12; };
+template <> struct HexLds<3> { static constexpr int SY = 3, SZ = 9, SE = 27; };
+template <> struct HexLds<4> { static constexpr int SY = 4, SZ = 19, SE = 80; };
+template <> struct HexLds<5> { static constexpr int SY = 5, SZ = 25, SE = 135; };
+template <> struct HexLds<6> { static constexpr int SY = 9, SZ = 54, SE = 324; };
+template <> struct HexLds<7> { static constexpr int SY = 7, SZ = 52, SE = 364; };
 
 // ---------------------------------------------------------------------------------- apply
-template <typename T, int N, int KIND>
-__global__ void __launch_bounds__(256) hex_apply_kernel(const HexArgs<T> A, const HexTabD<T, N> tb) {
+template <typename T, int N, int KIND, bool ATOMIC>
+__global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
+  using TB = TabT<T, N>;
   constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N>();
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
-  __shared__ T s0[EPB * N3];
-  __shared__ T s1[GRAD ? EPB * N3 : 1];
-  __shared__ T s2[GRAD ? EPB * N3 : 1];
+  constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ, SE = HexLds<N>::SE;
+  __shared__ T s0[EPB * SE];
+  __shared__ T s1[GRAD ? EPB * SE : 1];
+  __shared__ T s2[GRAD ? EPB * SE : 1];
+#define IX(x, y, z) ((z) * SZ + (y) * SY + (x))
   __shared__ T sg[EPB * 32];
 
   const int t = threadIdx.x;
-  const int le = t / NN, p = t - le * NN;
+  const bool mirror = t >= EPB * NN;
+  const int tt = mirror ? t - EPB * NN : t;
+  const int le = tt / NN, p = tt - le * NN;
   const int pa = p % N, pb = p / N;
-  const int64_t cell0 = A.c0 + (int64_t)blockIdx.x * EPB;
-  const int64_t cell = cell0 + le;
-  const bool valid = cell < A.c1;
+  const int nc = A.ncomp;
+  const int64_t nb = (A.c1 - A.c0 + EPB - 1) / EPB;  // cell batches (EPB cells each)
+  const int64_t G = gridDim.x;
+  int64_t b = blockIdx.x;
+  if (b >= nb) return;  // whole workgroup (= one wavefront)
 
-  for (int i = t; i < EPB * 32; i += EPB * NN) {
-    const int e = i >> 5, j = i & 31;
-    const int64_t c = cell0 + e;
-    T v = T(0);
-    if (c < A.c1) {
-      if (j < 24) v = A.geo[c * 24 + j];
-      else if (COEF && A.coef) v = A.coef[c * 8 + (j - 24)];
-      else if (j == 24) v = T(1);  // coefficient 1 when absent
+  // Work items are (batch, component) pairs, batches b, b+G, b+2G, ... for this
+  // wavefront. The gathers of the next item, the map of the batch after next and
+  // the geometry of the next batch are issued before the current item's
+  // arithmetic, so their memory latency overlaps it.
+  constexpr int GL = (EPB * 32 + 63) / 64;  // geometry values staged per lane
+  auto load_idx = [&](int64_t bb, int *idx) {
+    const int64_t c = A.c0 + bb * EPB + le;
+    bool ok = bb < nb && c < A.c1;
+    if (ok && A.cell_user) {
+      const int64_t u = A.cell_user[c];
+      ok = u >= A.ulo && u < A.uhi;
     }
-    sg[i] = v;
+    const int32_t *cm = A.map + (ok ? c : A.c0) * N3;
+#pragma unroll
+    for (int l = 0; l < N; l++) idx[l] = ok ? cm[pa + N * pb + NN * l] : -1;
+  };
+  auto gather = [&](const int *idx, int comp, T *r) {
+#pragma unroll
+    for (int l = 0; l < N; l++) r[l] = idx[l] >= 0 ? A.x[(int64_t)idx[l] * nc + comp] : T(0);
+  };
+  auto load_geo = [&](int64_t bb, T *g) {
+#pragma unroll
+    for (int q = 0; q < GL; q++) {
+      const int i = t + 64 * q;
+      const int e = i >> 5, j = i & 31;
+      const int64_t c = A.c0 + bb * EPB + e;
+      T v = T(0);
+      if (i < EPB * 32 && bb < nb && c < A.c1) {
+        if (j < 24) v = A.geo[c * 24 + j];
+        else if (COEF && A.coef) v = A.coef[c * 8 + (j - 24)];
+        else if (j == 24) v = T(1);  // coefficient 1 when absent
+      } else if (j == 0 || j == 4 || j == 8) {
+        v = T(1);  // cells past the end: unit-cube geometry keeps the arithmetic finite
+      }
+      g[q] = v;
+    }
+  };
+  auto store_geo = [&](const T *g) {
+#pragma unroll
+    for (int q = 0; q < GL; q++)
+      if (t + 64 * q < EPB * 32) sg[t + 64 * q] = g[q];
+  };
+
+  int idx_cur[N], idx_n1[N];
+  T r_cur[N];
+  load_idx(b, idx_cur);
+  load_idx(b + G, idx_n1);
+  gather(idx_cur, 0, r_cur);
+  {
+    T g[GL];
+    load_geo(b, g);
+    store_geo(g);
   }
   __syncthreads();
 
-  T *u0 = s0 + le * N3;
-  T *u1 = s1 + (GRAD ? le * N3 : 0);
-  T *u2 = s2 + (GRAD ? le * N3 : 0);
-  const T *G = sg + le * 32;
+  T *u0 = s0 + le * SE;
+  T *u1 = s1 + (GRAD ? le * SE : 0);
+  T *u2 = s2 + (GRAD ? le * SE : 0);
+  const T *Gc = sg + le * 32;
+  const T x1 = TB::g(pa), x2 = TB::g(pb);
+  const T wab = TB::w(pa) * TB::w(pb);
 
-  // Per-thread geometry for the pointwise stage: this thread owns points (pa, pb, *).
-  const T x1 = tb.g[pa], x2 = tb.g[pb];
-  T A1[3], B1[3], A2[3], B2[3], A3[3];
-#pragma unroll
-  for (int d = 0; d < 3; d++) {
-    const T c1 = G[0 + d], c2 = G[3 + d], c3 = G[6 + d], c4 = G[9 + d], c5 = G[12 + d],
-            c6 = G[15 + d], c7 = G[18 + d];
-    A1[d] = c1 + c4 * x2;
-    B1[d] = c5 + c7 * x2;
-    A2[d] = c2 + c4 * x1;
-    B2[d] = c6 + c7 * x1;
-    A3[d] = c3 + c5 * x1 + c6 * x2 + c7 * x1 * x2;
-  }
-  T ka = T(1), kb = T(0);
-  if (COEF) {
-    const T *K = G + 24;
-    ka = K[0] + K[1] * x1 + K[2] * x2 + K[4] * x1 * x2;
-    kb = K[3] + K[5] * x1 + K[6] * x2 + K[7] * x1 * x2;
-  }
-  const T wab = tb.w[pa] * tb.w[pb];
-  const int32_t *cmap = A.map + (valid ? cell : 0) * N3;
-  const int nc = A.ncomp;
+  for (; b < nb; b += G) {
+    int idx_n2[N];
+    load_idx(b + 2 * G, idx_n2);
+    T g_nx[GL];
+    load_geo(b + G, g_nx);
 
-  for (int comp = 0; comp < nc; comp++) {
-    T r[N], v[N];
-    // ---- gather z-pencil (i, j) = (pa, pb), contract z with B
+    // Per-thread geometry for the pointwise stage: this thread owns points (pa, pb, *).
+    T A1[3], B1[3], A2[3], B2[3], A3[3];
 #pragma unroll
-    for (int l = 0; l < N; l++) {
-      const int idx = valid ? cmap[pa + N * pb + NN * l] : -1;
-      r[l] = idx >= 0 ? A.x[(int64_t)idx * nc + comp] : T(0);
+    for (int d = 0; d < 3; d++) {
+      const T c1 = Gc[0 + d], c2 = Gc[3 + d], c3 = Gc[6 + d], c4 = Gc[9 + d], c5 = Gc[12 + d],
+              c6 = Gc[15 + d], c7 = Gc[18 + d];
+      A1[d] = c1 + c4 * x2;
+      B1[d] = c5 + c7 * x2;
+      A2[d] = c2 + c4 * x1;
+      B2[d] = c6 + c7 * x1;
+      A3[d] = c3 + c5 * x1 + c6 * x2 + c7 * x1 * x2;
     }
-#pragma unroll
-    for (int c = 0; c < N; c++) {
-      T s = T(0);
-#pragma unroll
-      for (int l = 0; l < N; l++) s += tb.B[c][l] * r[l];
-      u0[c * NN + pb * N + pa] = s;
+    T ka = T(1), kb = T(0);
+    if (COEF) {
+      const T *K = Gc + 24;
+      ka = K[0] + K[1] * x1 + K[2] * x2 + K[4] * x1 * x2;
+      kb = K[3] + K[5] * x1 + K[6] * x2 + K[7] * x1 * x2;
     }
-    __syncthreads();
-    // ---- y-pencil (x = pa, z = pb): contract y with B
+
+    for (int comp = 0; comp < nc; comp++) {
+      T r_nx[N], yv[N];
+      if (comp + 1 < nc) gather(idx_cur, comp + 1, r_nx);
+      else gather(idx_n1, 0, r_nx);
+      if constexpr (!ATOMIC) {
+        // no other cell of this launch touches these nodes: read y now, write it at the end
 #pragma unroll
-    for (int yy = 0; yy < N; yy++) r[yy] = u0[pb * NN + yy * N + pa];
-#pragma unroll
-    for (int b = 0; b < N; b++) {
-      T s = T(0);
-#pragma unroll
-      for (int yy = 0; yy < N; yy++) s += tb.B[b][yy] * r[yy];
-      u0[pb * NN + b * N + pa] = s;
-    }
-    __syncthreads();
-    // ---- x-pencil (y = pa, z = pb): contract x with B -> u at points; x-derivative
-#pragma unroll
-    for (int xx = 0; xx < N; xx++) r[xx] = u0[pb * NN + pa * N + xx];
-#pragma unroll
-    for (int a = 0; a < N; a++) {
-      T s = T(0);
-#pragma unroll
-      for (int xx = 0; xx < N; xx++) s += tb.B[a][xx] * r[xx];
-      v[a] = s;
-    }
-#pragma unroll
-    for (int a = 0; a < N; a++) u0[pb * NN + pa * N + a] = v[a];
-    if constexpr (GRAD) {
-#pragma unroll
-      for (int a = 0; a < N; a++) {
-        T s = T(0);
-#pragma unroll
-        for (int b = 0; b < N; b++) s += tb.D[a][b] * v[b];
-        u1[pb * NN + pa * N + a] = s;
+        for (int l = 0; l < N; l++)
+          yv[l] = (!mirror && idx_cur[l] >= 0) ? A.y[(int64_t)idx_cur[l] * nc + comp] : T(0);
       }
-      __syncthreads();
-      // ---- y-pencil (x = pa, z = pb): y-derivative of u
-#pragma unroll
-      for (int yy = 0; yy < N; yy++) r[yy] = u0[pb * NN + yy * N + pa];
-#pragma unroll
-      for (int b = 0; b < N; b++) {
-        T s = T(0);
-#pragma unroll
-        for (int yy = 0; yy < N; yy++) s += tb.D[b][yy] * r[yy];
-        u2[pb * NN + b * N + pa] = s;
-      }
-    }
-    __syncthreads();
-    // ---- pointwise on z-pencil (a, b) = (pa, pb)
-    {
-      T uz[N], f2[N];
-#pragma unroll
-      for (int c = 0; c < N; c++) uz[c] = u0[c * NN + pb * N + pa];
-#pragma unroll
+      T r[N], v[N];
+      // ---- z-pencil (i, j) = (pa, pb) gathered one item earlier; contract z with B
+  #pragma unroll
+      for (int l = 0; l < N; l++) r[l] = r_cur[l];
+  #pragma unroll
       for (int c = 0; c < N; c++) {
-        const T x3 = tb.g[c];
-        T j1[3], j2[3];
-#pragma unroll
-        for (int d = 0; d < 3; d++) {
-          j1[d] = A1[d] + x3 * B1[d];
-          j2[d] = A2[d] + x3 * B2[d];
-        }
-        const T *j3 = A3;
-        // adjugate rows: r0 = j2 x j3, r1 = j3 x j1, r2 = j1 x j2  (J^{-1} = rows / det)
-        const T r0[3] = {j2[1] * j3[2] - j2[2] * j3[1], j2[2] * j3[0] - j2[0] * j3[2],
-                         j2[0] * j3[1] - j2[1] * j3[0]};
-        const T det = j1[0] * r0[0] + j1[1] * r0[1] + j1[2] * r0[2];
-        const T adet = det < T(0) ? -det : det;
-        const T wq = wab * tb.w[c];
-        const T kq = COEF ? ka + kb * x3 : T(1);
-        T mterm = T(0);
-        if constexpr (MASS) mterm = wq * adet * kq * uz[c];
-        if constexpr (GRAD) {
-          const T r1[3] = {j3[1] * j1[2] - j3[2] * j1[1], j3[2] * j1[0] - j3[0] * j1[2],
-                           j3[0] * j1[1] - j3[1] * j1[0]};
-          const T r2[3] = {j1[1] * j2[2] - j1[2] * j2[1], j1[2] * j2[0] - j1[0] * j2[2],
-                           j1[0] * j2[1] - j1[1] * j2[0]};
-          const T sc = wq * kq / adet;
-          // d(u)/d(ref x), d/d(ref y) from LDS, d/d(ref z) from the register pencil
-          T dz = T(0);
-#pragma unroll
-          for (int cc = 0; cc < N; cc++) dz += tb.D[c][cc] * uz[cc];
-          const T dx = u1[c * NN + pb * N + pa];
-          const T dy = u2[c * NN + pb * N + pa];
-          // physical gradient times |det| pieces: e_b = r_b . (adj^T d) ; F = sc * adj adj^T d
-          const T gx = r0[0] * dx + r1[0] * dy + r2[0] * dz;
-          const T gy = r0[1] * dx + r1[1] * dy + r2[1] * dz;
-          const T gz = r0[2] * dx + r1[2] * dy + r2[2] * dz;
-          const T f0 = sc * (r0[0] * gx + r0[1] * gy + r0[2] * gz);
-          const T f1 = sc * (r1[0] * gx + r1[1] * gy + r1[2] * gz);
-          f2[c] = sc * (r2[0] * gx + r2[1] * gy + r2[2] * gz);
-          u1[c * NN + pb * N + pa] = f0;
-          u2[c * NN + pb * N + pa] = f1;
-        }
-        v[c] = mterm;
-      }
-      if constexpr (GRAD) {
-        // z-transpose of the derivative: v[c] += sum_c' D[c'][c] f2[c']
-#pragma unroll
-        for (int c = 0; c < N; c++) {
-          T s = v[c];
-#pragma unroll
-          for (int cc = 0; cc < N; cc++) s += tb.D[cc][c] * f2[cc];
-          v[c] = s;
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < N; c++) u0[c * NN + pb * N + pa] = v[c];
-    }
-    __syncthreads();
-    if constexpr (GRAD) {
-      // ---- y-pencil (x = pa, z = pb): add D^T along y of f1
-#pragma unroll
-      for (int yy = 0; yy < N; yy++) r[yy] = u2[pb * NN + yy * N + pa];
-#pragma unroll
-      for (int b = 0; b < N; b++) {
-        T s = u0[pb * NN + b * N + pa];
-#pragma unroll
-        for (int yy = 0; yy < N; yy++) s += tb.D[yy][b] * r[yy];
-        u0[pb * NN + b * N + pa] = s;
+        T s = T(0);
+  #pragma unroll
+        for (int l = 0; l < N; l++) s += TB::B(c, l) * r[l];
+        u0[IX(pa, pb, c)] = s;
       }
       __syncthreads();
-    }
-    // ---- x-pencil (y = pa, z = pb): add D^T along x of f0, then B^T along x
-#pragma unroll
-    for (int a = 0; a < N; a++) v[a] = u0[pb * NN + pa * N + a];
-    if constexpr (GRAD) {
-#pragma unroll
-      for (int a = 0; a < N; a++) r[a] = u1[pb * NN + pa * N + a];
-#pragma unroll
+      // ---- y-pencil (x = pa, z = pb): contract y with B
+  #pragma unroll
+      for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
+  #pragma unroll
+      for (int b = 0; b < N; b++) {
+        T s = T(0);
+  #pragma unroll
+        for (int yy = 0; yy < N; yy++) s += TB::B(b, yy) * r[yy];
+        u0[IX(pa, b, pb)] = s;
+      }
+      __syncthreads();
+      // ---- x-pencil (y = pa, z = pb): contract x with B -> u at points; x-derivative
+  #pragma unroll
+      for (int xx = 0; xx < N; xx++) r[xx] = u0[IX(xx, pa, pb)];
+  #pragma unroll
       for (int a = 0; a < N; a++) {
-        T s = v[a];
-#pragma unroll
-        for (int aa = 0; aa < N; aa++) s += tb.D[aa][a] * r[aa];
+        T s = T(0);
+  #pragma unroll
+        for (int xx = 0; xx < N; xx++) s += TB::B(a, xx) * r[xx];
         v[a] = s;
       }
+  #pragma unroll
+      for (int a = 0; a < N; a++) u0[IX(a, pa, pb)] = v[a];
+      if constexpr (GRAD) {
+  #pragma unroll
+        for (int a = 0; a < N; a++) {
+          T s = T(0);
+  #pragma unroll
+          for (int b = 0; b < N; b++) s += TB::D(a, b) * v[b];
+          u1[IX(a, pa, pb)] = s;
+        }
+        __syncthreads();
+        // ---- y-pencil (x = pa, z = pb): y-derivative of u
+  #pragma unroll
+        for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
+  #pragma unroll
+        for (int b = 0; b < N; b++) {
+          T s = T(0);
+  #pragma unroll
+          for (int yy = 0; yy < N; yy++) s += TB::D(b, yy) * r[yy];
+          u2[IX(pa, b, pb)] = s;
+        }
+      }
+      __syncthreads();
+      // ---- pointwise on z-pencil (a, b) = (pa, pb)
+      {
+        T uz[N], f2[N];
+  #pragma unroll
+        for (int c = 0; c < N; c++) uz[c] = u0[IX(pa, pb, c)];
+  #pragma unroll
+        for (int c = 0; c < N; c++) {
+          const T x3 = TB::g(c);
+          T j1[3], j2[3];
+  #pragma unroll
+          for (int d = 0; d < 3; d++) {
+            j1[d] = A1[d] + x3 * B1[d];
+            j2[d] = A2[d] + x3 * B2[d];
+          }
+          const T *j3 = A3;
+          // adjugate rows: r0 = j2 x j3, r1 = j3 x j1, r2 = j1 x j2  (J^{-1} = rows / det)
+          const T r0[3] = {j2[1] * j3[2] - j2[2] * j3[1], j2[2] * j3[0] - j2[0] * j3[2],
+                           j2[0] * j3[1] - j2[1] * j3[0]};
+          const T det = j1[0] * r0[0] + j1[1] * r0[1] + j1[2] * r0[2];
+          const T adet = det < T(0) ? -det : det;
+          const T wq = wab * TB::w(c);
+          const T kq = COEF ? ka + kb * x3 : T(1);
+          T mterm = T(0);
+          if constexpr (MASS) mterm = wq * adet * kq * uz[c];
+          if constexpr (GRAD) {
+            const T r1[3] = {j3[1] * j1[2] - j3[2] * j1[1], j3[2] * j1[0] - j3[0] * j1[2],
+                             j3[0] * j1[1] - j3[1] * j1[0]};
+            const T r2[3] = {j1[1] * j2[2] - j1[2] * j2[1], j1[2] * j2[0] - j1[0] * j2[2],
+                             j1[0] * j2[1] - j1[1] * j2[0]};
+            const T sc = wq * kq / adet;
+            // d(u)/d(ref x), d/d(ref y) from LDS, d/d(ref z) from the register pencil
+            T dz = T(0);
+  #pragma unroll
+            for (int cc = 0; cc < N; cc++) dz += TB::D(c, cc) * uz[cc];
+            const T dx = u1[IX(pa, pb, c)];
+            const T dy = u2[IX(pa, pb, c)];
+            // physical gradient times |det| pieces: e_b = r_b . (adj^T d) ; F = sc * adj adj^T d
+            const T gx = r0[0] * dx + r1[0] * dy + r2[0] * dz;
+            const T gy = r0[1] * dx + r1[1] * dy + r2[1] * dz;
+            const T gz = r0[2] * dx + r1[2] * dy + r2[2] * dz;
+            const T f0 = sc * (r0[0] * gx + r0[1] * gy + r0[2] * gz);
+            const T f1 = sc * (r1[0] * gx + r1[1] * gy + r1[2] * gz);
+            f2[c] = sc * (r2[0] * gx + r2[1] * gy + r2[2] * gz);
+            u1[IX(pa, pb, c)] = f0;
+            u2[IX(pa, pb, c)] = f1;
+          }
+          v[c] = mterm;
+        }
+        if constexpr (GRAD) {
+          // z-transpose of the derivative: v[c] += sum_c' D[c'][c] f2[c']
+  #pragma unroll
+          for (int c = 0; c < N; c++) {
+            T s = v[c];
+  #pragma unroll
+            for (int cc = 0; cc < N; cc++) s += TB::D(cc, c) * f2[cc];
+            v[c] = s;
+          }
+        }
+  #pragma unroll
+        for (int c = 0; c < N; c++) u0[IX(pa, pb, c)] = v[c];
+      }
+      __syncthreads();
+      if constexpr (GRAD) {
+        // ---- y-pencil (x = pa, z = pb): add D^T along y of f1
+  #pragma unroll
+        for (int yy = 0; yy < N; yy++) r[yy] = u2[IX(pa, yy, pb)];
+  #pragma unroll
+        for (int b = 0; b < N; b++) {
+          T s = u0[IX(pa, b, pb)];
+  #pragma unroll
+          for (int yy = 0; yy < N; yy++) s += TB::D(yy, b) * r[yy];
+          u0[IX(pa, b, pb)] = s;
+        }
+        __syncthreads();
+      }
+      // ---- x-pencil (y = pa, z = pb): add D^T along x of f0, then B^T along x
+  #pragma unroll
+      for (int a = 0; a < N; a++) v[a] = u0[IX(a, pa, pb)];
+      if constexpr (GRAD) {
+  #pragma unroll
+        for (int a = 0; a < N; a++) r[a] = u1[IX(a, pa, pb)];
+  #pragma unroll
+        for (int a = 0; a < N; a++) {
+          T s = v[a];
+  #pragma unroll
+          for (int aa = 0; aa < N; aa++) s += TB::D(aa, a) * r[aa];
+          v[a] = s;
+        }
+      }
+  #pragma unroll
+      for (int i = 0; i < N; i++) {
+        T s = T(0);
+  #pragma unroll
+        for (int a = 0; a < N; a++) s += TB::B(a, i) * v[a];
+        u0[IX(i, pa, pb)] = s;
+      }
+      __syncthreads();
+      // ---- y-pencil (x = pa, z = pb): B^T along y
+  #pragma unroll
+      for (int b = 0; b < N; b++) r[b] = u0[IX(pa, b, pb)];
+  #pragma unroll
+      for (int j = 0; j < N; j++) {
+        T s = T(0);
+  #pragma unroll
+        for (int b = 0; b < N; b++) s += TB::B(b, j) * r[b];
+        u0[IX(pa, j, pb)] = s;
+      }
+      __syncthreads();
+      // ---- z-pencil (i, j) = (pa, pb): B^T along z, scatter-add
+  #pragma unroll
+      for (int c = 0; c < N; c++) r[c] = u0[IX(pa, pb, c)];
+  #pragma unroll
+      for (int l = 0; l < N; l++) {
+        T s = T(0);
+  #pragma unroll
+        for (int c = 0; c < N; c++) s += TB::B(c, l) * r[c];
+        const int idx = mirror ? -1 : idx_cur[l];
+        if (idx >= 0) {
+          if constexpr (ATOMIC) atomic_add_f(&A.y[(int64_t)idx * nc + comp], s);
+          else A.y[(int64_t)idx * nc + comp] = yv[l] + s;
+        }
+      }
+
+#pragma unroll
+      for (int l = 0; l < N; l++) r_cur[l] = r_nx[l];
+      __syncthreads();
     }
-#pragma unroll
-    for (int i = 0; i < N; i++) {
-      T s = T(0);
-#pragma unroll
-      for (int a = 0; a < N; a++) s += tb.B[a][i] * v[a];
-      u0[pb * NN + pa * N + i] = s;
-    }
-    __syncthreads();
-    // ---- y-pencil (x = pa, z = pb): B^T along y
-#pragma unroll
-    for (int b = 0; b < N; b++) r[b] = u0[pb * NN + b * N + pa];
-#pragma unroll
-    for (int j = 0; j < N; j++) {
-      T s = T(0);
-#pragma unroll
-      for (int b = 0; b < N; b++) s += tb.B[b][j] * r[b];
-      u0[pb * NN + j * N + pa] = s;
-    }
-    __syncthreads();
-    // ---- z-pencil (i, j) = (pa, pb): B^T along z, scatter-add
-#pragma unroll
-    for (int c = 0; c < N; c++) r[c] = u0[c * NN + pb * N + pa];
 #pragma unroll
     for (int l = 0; l < N; l++) {
-      T s = T(0);
-#pragma unroll
-      for (int c = 0; c < N; c++) s += tb.B[c][l] * r[c];
-      const int idx = valid ? cmap[pa + N * pb + NN * l] : -1;
-      if (idx >= 0) atomic_add_f(&A.y[(int64_t)idx * nc + comp], s);
+      idx_cur[l] = idx_n1[l];
+      idx_n1[l] = idx_n2[l];
     }
-    if (comp + 1 < nc) __syncthreads();
+    store_geo(g_nx);
+    __syncthreads();
   }
 }
+
+#undef IX
 
 // ---------------------------------------------------------------------------------- diagonal
 // diag_i = sum_q [ grad_ref phi_i^T G grad_ref phi_i + m phi_i^2 ], one thread per cell node;
@@ -288,7 +387,8 @@ __global__ void __launch_bounds__(256) hex_apply_kernel(const HexArgs<T> A, cons
 template <int N> constexpr int hexd_epb() { return (N * N * N >= 256) ? 1 : 256 / (N * N * N); }
 
 template <typename T, int N, int KIND>
-__global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A, const HexTabD<T, N> tb) {
+__global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A) {
+  using TB = TabT<T, N>;
   constexpr int N3 = N * N * N, EPB = hexd_epb<N>();
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
@@ -302,7 +402,7 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A, const
   {
     const int a = p % N, b = (p / N) % N, c = p / (N * N);
     const T *G = A.geo + cg * 24;
-    const T x1 = tb.g[a], x2 = tb.g[b], x3 = tb.g[c];
+    const T x1 = TB::g(a), x2 = TB::g(b), x3 = TB::g(c);
     T j1[3], j2[3], j3[3];
     for (int d = 0; d < 3; d++) {
       const T c1 = G[0 + d], c2 = G[3 + d], c3 = G[6 + d], c4 = G[9 + d], c5 = G[12 + d],
@@ -316,7 +416,7 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A, const
     const T r2[3] = {j1[1] * j2[2] - j1[2] * j2[1], j1[2] * j2[0] - j1[0] * j2[2], j1[0] * j2[1] - j1[1] * j2[0]};
     const T det = j1[0] * r0[0] + j1[1] * r0[1] + j1[2] * r0[2];
     const T adet = det < T(0) ? -det : det;
-    const T wq = tb.w[a] * tb.w[b] * tb.w[c];
+    const T wq = TB::w(a) * TB::w(b) * TB::w(c);
     T kq = T(1);
     if (COEF && A.coef) {
       const T *K = A.coef + cg * 8;
@@ -340,11 +440,11 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A, const
     for (int b = 0; b < N; b++)
       for (int a = 0; a < N; a++) {
         const int q = a + N * (b + N * c);
-        const T bi = tb.B[a][i], bj = tb.B[b][j], bl = tb.B[c][l];
+        const T bi = TB::B(a, i), bj = TB::B(b, j), bl = TB::B(c, l);
         const T vv = bi * bj * bl;
         T s = sG[le][6][q] * vv * vv;
         if (GRAD) {
-          const T d0 = tb.dB[a][i] * bj * bl, d1 = bi * tb.dB[b][j] * bl, d2 = bi * bj * tb.dB[c][l];
+          const T d0 = TB::dB(a, i) * bj * bl, d1 = bi * TB::dB(b, j) * bl, d2 = bi * bj * TB::dB(c, l);
           s += sG[le][0][q] * d0 * d0 + sG[le][3][q] * d1 * d1 + sG[le][5][q] * d2 * d2 +
                T(2) * (sG[le][1][q] * d0 * d1 + sG[le][2][q] * d0 * d2 + sG[le][4][q] * d1 * d2);
         }
@@ -358,36 +458,68 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A, const
 }
 
 // ---------------------------------------------------------------------------------- launchers
-template <typename T, int N>
-static int launch_apply_n(int kind, const HexArgs<T> &a, const void *tab, hipStream_t s) {
-  const HexTabD<T, N> &tb = *static_cast<const HexTabD<T, N> *>(tab);
+// Number of 64-thread workgroups of `fn` that fit on the device at once.
+static int64_t resident_waves(const void *fn) {
+  static std::mutex mu;
+  static std::map<const void *, int64_t> cache;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(fn);
+  if (it != cache.end()) return it->second;
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu <= 0) {
+    (void)hipGetLastError();
+    cus = 256;
+    per_cu = 8;
+  }
+  const int64_t r = (int64_t)cus * per_cu;
+  cache[fn] = r;
+  return r;
+}
+
+template <typename T, int N, bool AT>
+static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
   constexpr int EPB = hex_epb<N>();
   const int64_t nc = a.c1 - a.c0;
   if (nc <= 0) return MF_OK;
-  dim3 grid((unsigned)((nc + EPB - 1) / EPB)), block(EPB * N * N);
+  const int64_t nb = (nc + EPB - 1) / EPB;
+  void *fn = nullptr;
   switch (kind) {
-    case K_MASS: hex_apply_kernel<T, N, K_MASS><<<grid, block, 0, s>>>(a, tb); break;
-    case K_HELM: hex_apply_kernel<T, N, K_HELM><<<grid, block, 0, s>>>(a, tb); break;
-    case K_LAP: hex_apply_kernel<T, N, K_LAP><<<grid, block, 0, s>>>(a, tb); break;
-    case K_POIS: hex_apply_kernel<T, N, K_POIS><<<grid, block, 0, s>>>(a, tb); break;
+    case K_MASS: fn = (void *)hex_apply_kernel<T, N, K_MASS, AT>; break;
+    case K_HELM: fn = (void *)hex_apply_kernel<T, N, K_HELM, AT>; break;
+    case K_LAP: fn = (void *)hex_apply_kernel<T, N, K_LAP, AT>; break;
+    case K_POIS: fn = (void *)hex_apply_kernel<T, N, K_POIS, AT>; break;
     default: return fail(MF_EUNSUPPORTED, "hex kernel: operator kind");
+  }
+  // persistent grid: as many wavefronts as can be resident at once (cached per kernel)
+  const int64_t resident = resident_waves(fn);
+  dim3 grid((unsigned)(nb < resident ? nb : resident)), block(64);
+  switch (kind) {
+    case K_MASS: hex_apply_kernel<T, N, K_MASS, AT><<<grid, block, 0, s>>>(a); break;
+    case K_HELM: hex_apply_kernel<T, N, K_HELM, AT><<<grid, block, 0, s>>>(a); break;
+    case K_LAP: hex_apply_kernel<T, N, K_LAP, AT><<<grid, block, 0, s>>>(a); break;
+    case K_POIS: hex_apply_kernel<T, N, K_POIS, AT><<<grid, block, 0, s>>>(a); break;
   }
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
 
 template <typename T, int N>
-static int launch_diag_n(int kind, const HexArgs<T> &a, const void *tab, hipStream_t s) {
-  const HexTabD<T, N> &tb = *static_cast<const HexTabD<T, N> *>(tab);
+static int launch_apply_n(int kind, const HexArgs<T> &a, bool atomic, hipStream_t s) {
+  return atomic ? launch_apply_na<T, N, true>(kind, a, s) : launch_apply_na<T, N, false>(kind, a, s);
+}
+
+template <typename T, int N>
+static int launch_diag_n(int kind, const HexArgs<T> &a, hipStream_t s) {
   constexpr int EPB = hexd_epb<N>();
   const int64_t nc = a.c1 - a.c0;
   if (nc <= 0) return MF_OK;
   dim3 grid((unsigned)((nc + EPB - 1) / EPB)), block(EPB * N * N * N);
   switch (kind) {
-    case K_MASS: hex_diag_kernel<T, N, K_MASS><<<grid, block, 0, s>>>(a, tb); break;
-    case K_HELM: hex_diag_kernel<T, N, K_HELM><<<grid, block, 0, s>>>(a, tb); break;
-    case K_LAP: hex_diag_kernel<T, N, K_LAP><<<grid, block, 0, s>>>(a, tb); break;
-    case K_POIS: hex_diag_kernel<T, N, K_POIS><<<grid, block, 0, s>>>(a, tb); break;
+    case K_MASS: hex_diag_kernel<T, N, K_MASS><<<grid, block, 0, s>>>(a); break;
+    case K_HELM: hex_diag_kernel<T, N, K_HELM><<<grid, block, 0, s>>>(a); break;
+    case K_LAP: hex_diag_kernel<T, N, K_LAP><<<grid, block, 0, s>>>(a); break;
+    case K_POIS: hex_diag_kernel<T, N, K_POIS><<<grid, block, 0, s>>>(a); break;
     default: return fail(MF_EUNSUPPORTED, "hex diagonal: operator kind");
   }
   MF_HIP(hipGetLastError());
@@ -395,49 +527,36 @@ static int launch_diag_n(int kind, const HexArgs<T> &a, const void *tab, hipStre
 }
 
 template <typename T>
-int launch_hex_apply(int N, int kind, const HexArgs<T> &a, const void *tab, hipStream_t s) {
+int launch_hex_apply(int N, int kind, const HexArgs<T> &a, bool atomic, hipStream_t s) {
   switch (N) {
-    case 2: return launch_apply_n<T, 2>(kind, a, tab, s);
-    case 3: return launch_apply_n<T, 3>(kind, a, tab, s);
-    case 4: return launch_apply_n<T, 4>(kind, a, tab, s);
-    case 5: return launch_apply_n<T, 5>(kind, a, tab, s);
-    case 6: return launch_apply_n<T, 6>(kind, a, tab, s);
-    case 7: return launch_apply_n<T, 7>(kind, a, tab, s);
+    case 2: return launch_apply_n<T, 2>(kind, a, atomic, s);
+    case 3: return launch_apply_n<T, 3>(kind, a, atomic, s);
+    case 4: return launch_apply_n<T, 4>(kind, a, atomic, s);
+    case 5: return launch_apply_n<T, 5>(kind, a, atomic, s);
+    case 6: return launch_apply_n<T, 6>(kind, a, atomic, s);
+    case 7: return launch_apply_n<T, 7>(kind, a, atomic, s);
   }
   return fail(MF_EUNSUPPORTED, "hex kernel: degree");
 }
 
 template <typename T>
-int launch_hex_diag(int N, int kind, const HexArgs<T> &a, const void *tab, hipStream_t s) {
+int launch_hex_diag(int N, int kind, const HexArgs<T> &a, hipStream_t s) {
   switch (N) {
-    case 2: return launch_diag_n<T, 2>(kind, a, tab, s);
-    case 3: return launch_diag_n<T, 3>(kind, a, tab, s);
-    case 4: return launch_diag_n<T, 4>(kind, a, tab, s);
-    case 5: return launch_diag_n<T, 5>(kind, a, tab, s);
-    case 6: return launch_diag_n<T, 6>(kind, a, tab, s);
-    case 7: return launch_diag_n<T, 7>(kind, a, tab, s);
+    case 2: return launch_diag_n<T, 2>(kind, a, s);
+    case 3: return launch_diag_n<T, 3>(kind, a, s);
+    case 4: return launch_diag_n<T, 4>(kind, a, s);
+    case 5: return launch_diag_n<T, 5>(kind, a, s);
+    case 6: return launch_diag_n<T, 6>(kind, a, s);
+    case 7: return launch_diag_n<T, 7>(kind, a, s);
   }
   return fail(MF_EUNSUPPORTED, "hex diagonal: degree");
 }
 
-template int launch_hex_apply<double>(int, int, const HexArgs<double> &, const void *, hipStream_t);
-template int launch_hex_apply<float>(int, int, const HexArgs<float> &, const void *, hipStream_t);
-template int launch_hex_diag<double>(int, int, const HexArgs<double> &, const void *, hipStream_t);
-template int launch_hex_diag<float>(int, int, const HexArgs<float> &, const void *, hipStream_t);
+template int launch_hex_apply<double>(int, int, const HexArgs<double> &, bool, hipStream_t);
+template int launch_hex_apply<float>(int, int, const HexArgs<float> &, bool, hipStream_t);
+template int launch_hex_diag<double>(int, int, const HexArgs<double> &, hipStream_t);
+template int launch_hex_diag<float>(int, int, const HexArgs<float> &, hipStream_t);
 
-// Size of the table struct the launchers expect for (T, N); used by the host setup.
-template <typename T> size_t hex_table_bytes(int N) {
-  switch (N) {
-    case 2: return sizeof(HexTabD<T, 2>);
-    case 3: return sizeof(HexTabD<T, 3>);
-    case 4: return sizeof(HexTabD<T, 4>);
-    case 5: return sizeof(HexTabD<T, 5>);
-    case 6: return sizeof(HexTabD<T, 6>);
-    case 7: return sizeof(HexTabD<T, 7>);
-  }
-  return 0;
-}
-template size_t hex_table_bytes<double>(int);
-template size_t hex_table_bytes<float>(int);
+
 
 }  // namespace mf

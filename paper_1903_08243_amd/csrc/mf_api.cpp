@@ -5,6 +5,7 @@
 // constant tables of the element kernel, and the device layouts the kernels
 // read. The action itself runs entirely in the HIP kernels.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -181,7 +182,91 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
   s->D = D;
   s->nnodes = nnodes;
   s->cell2node.assign(cell2node, cell2node + mesh->ncells * D);
+  // colouring: greedy first-fit in user cell order over the cell-vertex graph
+  // (for conforming Lagrange spaces two cells share a node iff they share a vertex)
+  const int nvc = mesh->nvc;
+  const int64_t nc = mesh->ncells;
+  std::vector<int64_t> vptr(mesh->nverts + 1, 0);
+  for (int64_t i = 0; i < nc * nvc; i++) vptr[mesh->cell2vert[i] + 1]++;
+  for (int64_t v = 0; v < mesh->nverts; v++) vptr[v + 1] += vptr[v];
+  std::vector<int32_t> vcells(nc * nvc);
+  {
+    std::vector<int64_t> fillp(vptr.begin(), vptr.end() - 1);
+    for (int64_t K = 0; K < nc; K++)
+      for (int v = 0; v < nvc; v++) vcells[fillp[mesh->cell2vert[K * nvc + v]]++] = (int32_t)K;
+  }
+  std::vector<int32_t> colour(nc, -1);
+  std::vector<int64_t> stamp;  // stamp[c] == K + 1 marks colour c as used by a neighbour of K
+  int ncol = 0;
+  for (int64_t K = 0; K < nc; K++) {
+    for (int v = 0; v < nvc; v++) {
+      const int32_t vid = mesh->cell2vert[K * nvc + v];
+      for (int64_t q = vptr[vid]; q < vptr[vid + 1]; q++) {
+        const int32_t c = colour[vcells[q]];
+        if (c >= 0) stamp[c] = K + 1;
+      }
+    }
+    int c = 0;
+    while (c < ncol && stamp[c] == K + 1) c++;
+    if (c == ncol) {
+      ncol++;
+      stamp.push_back(0);
+    }
+    colour[K] = c;
+  }
+  s->colour_ptr.assign(ncol + 1, 0);
+  for (int64_t K = 0; K < nc; K++) s->colour_ptr[colour[K] + 1]++;
+  for (int c = 0; c < ncol; c++) s->colour_ptr[c + 1] += s->colour_ptr[c];
+  s->cell_user_of_int.resize(nc);
+  {
+    std::vector<int64_t> fillp(s->colour_ptr.begin(), s->colour_ptr.end() - 1);
+    for (int64_t K = 0; K < nc; K++) s->cell_user_of_int[fillp[colour[K]]++] = (int32_t)K;
+  }
+  s->cell2vert_int.resize(nc * nvc);
+  for (int64_t ic = 0; ic < nc; ic++)
+    for (int v = 0; v < nvc; v++) s->cell2vert_int[ic * nvc + v] = mesh->cell2vert[(int64_t)s->cell_user_of_int[ic] * nvc + v];
+  // internal node numbering: first appearance in the internal cell order
+  s->int_of_user.assign((size_t)nnodes, -1);
+  s->user_of_int.clear();
+  s->user_of_int.reserve((size_t)nnodes);
+  s->cell2node_int.resize(s->cell2node.size());
+  for (int64_t ic = 0; ic < nc; ic++) {
+    const int32_t *row = cell2node + (int64_t)s->cell_user_of_int[ic] * D;
+    for (int i = 0; i < D; i++) {
+      const int32_t u = row[i];
+      if (s->int_of_user[u] < 0) {
+        s->int_of_user[u] = (int32_t)s->user_of_int.size();
+        s->user_of_int.push_back(u);
+      }
+      s->cell2node_int[ic * D + i] = s->int_of_user[u];
+    }
+  }
+  for (int64_t u = 0; u < nnodes; u++)  // nodes in no cell keep their relative order at the end
+    if (s->int_of_user[u] < 0) {
+      s->int_of_user[u] = (int32_t)s->user_of_int.size();
+      s->user_of_int.push_back((int32_t)u);
+    }
+  s->identity = true;
+  for (int64_t i = 0; i < nnodes && s->identity; i++) s->identity = s->user_of_int[i] == i;
+  static std::atomic<uint64_t> next_id{1};
+  s->numbering_id = next_id++;
   *out = s;
+  return MF_OK;
+}
+
+int mf_space_get_colouring(const mf_space *s, int32_t *internal_to_user_cell, int64_t *colour_ptr,
+                           int *ncolours) {
+  if (!s || !ncolours) return fail(MF_EINVAL, "mf_space_get_colouring: null argument");
+  *ncolours = (int)s->colour_ptr.size() - 1;
+  if (internal_to_user_cell)
+    std::memcpy(internal_to_user_cell, s->cell_user_of_int.data(), s->cell_user_of_int.size() * sizeof(int32_t));
+  if (colour_ptr) std::memcpy(colour_ptr, s->colour_ptr.data(), s->colour_ptr.size() * sizeof(int64_t));
+  return MF_OK;
+}
+
+int mf_space_get_permutation(const mf_space *s, int32_t *internal_to_user) {
+  if (!s || !internal_to_user) return fail(MF_EINVAL, "mf_space_get_permutation: null argument");
+  std::memcpy(internal_to_user, s->user_of_int.data(), s->user_of_int.size() * sizeof(int32_t));
   return MF_OK;
 }
 
@@ -192,36 +277,15 @@ void mf_space_destroy(mf_space *s) { delete s; }
 // ------------------------------------------------------------------ operator setup
 namespace mf {
 
-template <typename T> static void build_hex_table(int k, int nq, std::vector<unsigned char> &out) {
-  const int N = k + 1;
-  std::vector<double> g, w, V, dV, Vg, dVg;
-  gauss_legendre(nq, g, w);
-  lagrange_eval(gll_points(k), g, V, dV);  // V[a*N+i] = l_i(g_a)
-  lagrange_eval(g, g, Vg, dVg);            // dVg[a*nq+b] = L_b'(g_a)
-  std::vector<T> t;
-  for (int a = 0; a < N; a++)
-    for (int i = 0; i < N; i++) t.push_back((T)V[a * N + i]);
-  for (int a = 0; a < N; a++)
-    for (int b = 0; b < N; b++) t.push_back((T)dVg[a * N + b]);
-  for (int a = 0; a < N; a++) t.push_back((T)g[a]);
-  for (int a = 0; a < N; a++) t.push_back((T)w[a]);
-  for (int a = 0; a < N; a++)
-    for (int i = 0; i < N; i++) t.push_back((T)dV[a * N + i]);
-  out.resize(t.size() * sizeof(T));
-  std::memcpy(out.data(), t.data(), out.size());
-}
-
 template <typename T> static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
   const int k = sp->degree, N = k + 1;
   if (op->nq1d != N) return fail(MF_EUNSUPPORTED, "hex operators support nq1d = k+1 only");
-  build_hex_table<T>(k, op->nq1d, op->tab_host);
-  if (op->tab_host.size() != hex_table_bytes<T>(N)) return fail(MF_EDEVICE, "hex table layout mismatch");
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 24, T(0));
   for (int64_t K = 0; K < nc; K++) {
     for (int a = 0; a < 3; a++) {
       double X[8], c[8];
-      for (int v = 0; v < 8; v++) X[v] = sp->coords[(int64_t)sp->cell2vert[K * 8 + v] * 3 + a];
+      for (int v = 0; v < 8; v++) X[v] = sp->coords[(int64_t)sp->cell2vert_int[K * 8 + v] * 3 + a];
       trilinear_coeffs(X, c);
       for (int m = 1; m < 8; m++) geo[K * 24 + 3 * (m - 1) + a] = (T)c[m];
     }
@@ -232,7 +296,7 @@ template <typename T> static int setup_hex(mf_op *op, const mf_space *sp, const 
     std::vector<T> cf((size_t)nc * 8);
     for (int64_t K = 0; K < nc; K++) {
       double X[8], c[8];
-      for (int v = 0; v < 8; v++) X[v] = pr->vertex_coef[sp->cell2vert[K * 8 + v]];
+      for (int v = 0; v < 8; v++) X[v] = pr->vertex_coef[sp->cell2vert_int[K * 8 + v]];
       trilinear_coeffs(X, c);
       for (int m = 0; m < 8; m++) cf[K * 8 + m] = (T)c[m];
     }
@@ -258,7 +322,7 @@ template <typename T> static int setup_tet(mf_op *op, const mf_space *sp, hipStr
   const int64_t nc = sp->ncells, nb = (nc + 63) / 64;
   std::vector<T> geo((size_t)nb * 10 * 64, T(0));
   for (int64_t K = 0; K < nc; K++) {
-    const int32_t *cv = sp->cell2vert.data() + K * 4;
+    const int32_t *cv = sp->cell2vert_int.data() + K * 4;
     double J[3][3];
     for (int a = 0; a < 3; a++)
       for (int b = 0; b < 3; b++) J[a][b] = sp->coords[(int64_t)cv[b + 1] * 3 + a] - sp->coords[(int64_t)cv[0] * 3 + a];
@@ -288,7 +352,7 @@ template <typename T> static int setup_tri(mf_op *op, const mf_space *sp, const 
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 4, T(0));
   for (int64_t K = 0; K < nc; K++) {
-    const int32_t *cv = sp->cell2vert.data() + K * 3;
+    const int32_t *cv = sp->cell2vert_int.data() + K * 3;
     const double *p0 = &sp->coords[(int64_t)cv[0] * 2], *p1 = &sp->coords[(int64_t)cv[1] * 2],
                  *p2 = &sp->coords[(int64_t)cv[2] * 2];
     const double area = 0.5 * std::fabs((p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]));
@@ -329,6 +393,26 @@ static void count_work(mf_op *op) {
   op->bytes = by;
 }
 
+// One launch of the cell kernel over internal cells [c0, c1). atomic: scatter with
+// atomics (optionally only cells whose user index is in [ulo, uhi)); otherwise
+// plain read-modify-write, which requires [c0, c1) to lie inside one colour.
+template <typename T>
+static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool atomic, const int32_t *filt,
+                       int64_t ulo, int64_t uhi, hipStream_t s) {
+  if (op->cell_type == MF_CELL_HEX) {
+    HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, x, y, c0, c1,
+                 op->ncomp, filt, ulo, uhi};
+    return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
+  } else if (op->cell_type == MF_CELL_TET) {
+    TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
+                 filt, ulo, uhi};
+    return launch_tet_elasticity<T>(op->degree, op->nqp, a, atomic, s);
+  }
+  TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), x, y, c0, c1, filt, ulo, uhi};
+  return launch_tri_mass<T>(a, atomic, s);
+}
+
+// y (+)= A_[c0,c1) x in internal numbering; [c0, c1) is a range of user cells.
 template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool acc,
                                             bool bc, hipStream_t s) {
   int rc = MF_OK;
@@ -336,20 +420,28 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
     rc = launch_fill<T>(y, T(0), op->ndofs, s);
     if (rc) return rc;
   }
-  if (op->cell_type == MF_CELL_HEX) {
-    HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, x, y, c0, c1,
-                 op->ncomp};
-    rc = launch_hex_apply<T>(op->degree + 1, op->kind, a, op->tab_host.data(), s);
-  } else if (op->cell_type == MF_CELL_TET) {
-    TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu};
-    rc = launch_tet_elasticity<T>(op->degree, op->nqp, a, s);
-  } else {
-    TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), x, y, c0, c1};
-    rc = launch_tri_mass<T>(a, s);
+  if (c0 == 0 && c1 == op->ncells) {
+    if (op->coloured) {
+      // one launch per colour: cells of a colour share no node, so no atomics
+      for (size_t c = 0; c + 1 < op->colour_ptr.size() && !rc; c++)
+        rc = cell_launch<T>(op, op->colour_ptr[c], op->colour_ptr[c + 1], x, y, false, nullptr, 0, 0, s);
+    } else {
+      rc = cell_launch<T>(op, 0, op->ncells, x, y, true, nullptr, 0, 0, s);
+    }
+  } else if (c1 > c0) {
+    rc = cell_launch<T>(op, 0, op->ncells, x, y, true, op->cell_user.as<int32_t>(), c0, c1, s);
   }
   if (rc) return rc;
   if (bc && op->n_bc_dofs) rc = launch_copy_constrained<T>(op->bc_dofs.as<int32_t>(), op->n_bc_dofs, x, y, s);
   return rc;
+}
+
+// Coloured launches avoid device-scope float atomics but cost one launch per
+// colour with 1/ncolours of the cells each. Measured on MI355X (32^3 hex), the
+// single atomic launch is faster for scalar operators; the coloured launches win
+// for 3-component operators from Q3 up (three atomics per node otherwise).
+static bool default_coloured(const mf_op *op) {
+  return op->cell_type == MF_CELL_HEX && op->ncomp == 3 && op->degree >= 3 && op->ncells >= 4096;
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
@@ -357,14 +449,14 @@ template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s)
   if (rc) return rc;
   if (op->cell_type == MF_CELL_HEX) {
     HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, nullptr, d, 0,
-                 op->ncells, op->ncomp};
-    rc = launch_hex_diag<T>(op->degree + 1, op->kind, a, op->tab_host.data(), s);
+                 op->ncells, op->ncomp, nullptr, 0, 0};
+    rc = launch_hex_diag<T>(op->degree + 1, op->kind, a, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), nullptr, d, 0, op->ncells, (T)op->lam,
-                 (T)op->mu};
+                 (T)op->mu, nullptr, 0, 0};
     rc = launch_tet_elasticity_diag<T>(op->degree, op->nqp, a, s);
   } else {
-    TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), nullptr, d, 0, op->ncells};
+    TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), nullptr, d, 0, op->ncells, nullptr, 0, 0};
     rc = launch_tri_mass_diag<T>(a, s);
   }
   if (rc) return rc;
@@ -381,7 +473,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (!sp || !out) return fail(MF_EINVAL, "mf_op_create: null argument");
   if (precision != MF_F64 && precision != MF_F32) return fail(MF_EINVAL, "mf_op_create: precision");
   if (kind < MF_OP_MASS || kind > MF_OP_ELASTICITY) return fail(MF_EINVAL, "mf_op_create: operator kind");
-  mf_op_params defaults{nullptr, 1.0, 0.5, nullptr};
+  mf_op_params defaults{nullptr, 1.0, 0.5, nullptr, MF_SCATTER_AUTO};
   const mf_op_params *pr = params ? params : &defaults;
   hipStream_t s = (hipStream_t)stream;
   const int ct = sp->cell_type;
@@ -416,25 +508,40 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   const int64_t nc = sp->ncells;
   const int D = sp->D;
   std::vector<int32_t> m;
-  auto flag = [&](int32_t node) { return (pr->dirichlet && pr->dirichlet[node]) ? -1 : node; };
+  // (internal node ids; the Dirichlet mask is given per user node)
+  auto flag = [&](int32_t inode) { return (pr->dirichlet && pr->dirichlet[sp->user_of_int[inode]]) ? -1 : inode; };
+  const std::vector<int32_t> &c2n = sp->cell2node_int;
   if (ct == MF_CELL_TET) {
     const int64_t nb = (nc + 63) / 64;
     m.assign((size_t)nb * D * 64, -1);
     for (int64_t K = 0; K < nc; K++)
-      for (int i = 0; i < D; i++) m[((K / 64) * D + i) * 64 + K % 64] = flag(sp->cell2node[K * D + i]);
+      for (int i = 0; i < D; i++) m[((K / 64) * D + i) * 64 + K % 64] = flag(c2n[K * D + i]);
   } else {
     m.resize((size_t)nc * D);
-    for (int64_t i = 0; i < nc * D; i++) m[i] = flag(sp->cell2node[i]);
+    for (int64_t i = 0; i < nc * D; i++) m[i] = flag(c2n[i]);
   }
   int rc = upload(op->map, m.data(), m.size() * sizeof(int32_t), s);
   if (rc) return rc;
   if (pr->dirichlet) {
     std::vector<int32_t> bd;
     for (int64_t n = 0; n < sp->nnodes; n++)
-      if (pr->dirichlet[n])
+      if (pr->dirichlet[sp->user_of_int[n]])
         for (int c = 0; c < sp->ncomp; c++) bd.push_back((int32_t)(n * sp->ncomp + c));
     op->n_bc_dofs = (int64_t)bd.size();
     rc = upload(op->bc_dofs, bd.data(), bd.size() * sizeof(int32_t), s);
+    if (rc) return rc;
+  }
+  op->identity = sp->identity;
+  op->numbering_id = sp->numbering_id;
+  op->colour_ptr = sp->colour_ptr;
+  rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
+  if (rc) return rc;
+  op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
+  if (!op->identity) {
+    rc = upload(op->perm, sp->user_of_int.data(), sp->user_of_int.size() * sizeof(int32_t), s);
+    const size_t vb = (size_t)op->ndofs * (precision == MF_F64 ? 8 : 4);
+    if (!rc) rc = op->wx.alloc(vb);
+    if (!rc) rc = op->wy.alloc(vb);
     if (rc) return rc;
   }
   if (ct == MF_CELL_HEX)
@@ -456,6 +563,44 @@ void mf_op_destroy(mf_op *op) {
   delete op;
 }
 
+}  // extern "C"
+
+namespace mf {
+
+// User-numbering wrappers: permute x into the internal numbering, run the
+// internal-numbering kernels on the workspaces, permute the result back.
+template <typename T>
+static int user_apply(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool acc, bool bc, hipStream_t s) {
+  if (op->identity) return op_apply_t<T>(op, c0, c1, x, y, acc, bc, s);
+  T *wx = op->wx.as<T>(), *wy = op->wy.as<T>();
+  const int32_t *uoi = op->perm.as<int32_t>();
+  int rc = launch_to_internal<T>(uoi, op->nnodes, op->ncomp, x, wx, s);
+  if (!rc) rc = op_apply_t<T>(op, c0, c1, wx, wy, false, bc, s);
+  if (!rc) rc = launch_from_internal<T>(uoi, op->nnodes, op->ncomp, wy, y, acc, s);
+  return rc;
+}
+
+template <typename T> static int user_diag(const mf_op *op, T *d, hipStream_t s) {
+  if (op->identity) return op_diag_t<T>(op, d, s);
+  int rc = op_diag_t<T>(op, op->wy.as<T>(), s);
+  if (!rc) rc = launch_from_internal<T>(op->perm.as<int32_t>(), op->nnodes, op->ncomp, op->wy.as<T>(), d, false, s);
+  return rc;
+}
+
+int op_apply_internal(const mf_op *op, const void *x, void *y, hipStream_t s) {
+  return op->precision == MF_F64
+             ? op_apply_t<double>(op, 0, op->ncells, (const double *)x, (double *)y, false, true, s)
+             : op_apply_t<float>(op, 0, op->ncells, (const float *)x, (float *)y, false, true, s);
+}
+
+int op_diagonal_internal(const mf_op *op, void *d, hipStream_t s) {
+  return op->precision == MF_F64 ? op_diag_t<double>(op, (double *)d, s) : op_diag_t<float>(op, (float *)d, s);
+}
+
+}  // namespace mf
+
+extern "C" {
+
 int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x, void *y, int accumulate,
                       void *stream) {
   if (!op || !x || !y) return fail(MF_EINVAL, "mf_op_apply_range: null argument");
@@ -463,8 +608,8 @@ int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x
   if (x == y) return fail(MF_EINVAL, "mf_op_apply_range: x and y alias");
   hipStream_t s = (hipStream_t)stream;
   return op->precision == MF_F64
-             ? op_apply_t<double>(op, start, end, (const double *)x, (double *)y, accumulate != 0, false, s)
-             : op_apply_t<float>(op, start, end, (const float *)x, (float *)y, accumulate != 0, false, s);
+             ? user_apply<double>(op, start, end, (const double *)x, (double *)y, accumulate != 0, false, s)
+             : user_apply<float>(op, start, end, (const float *)x, (float *)y, accumulate != 0, false, s);
 }
 
 int mf_op_apply(const mf_op *op, const void *x, void *y, void *stream) {
@@ -472,14 +617,31 @@ int mf_op_apply(const mf_op *op, const void *x, void *y, void *stream) {
   if (x == y) return fail(MF_EINVAL, "mf_op_apply: x and y alias");
   hipStream_t s = (hipStream_t)stream;
   return op->precision == MF_F64
-             ? op_apply_t<double>(op, 0, op->ncells, (const double *)x, (double *)y, false, true, s)
-             : op_apply_t<float>(op, 0, op->ncells, (const float *)x, (float *)y, false, true, s);
+             ? user_apply<double>(op, 0, op->ncells, (const double *)x, (double *)y, false, true, s)
+             : user_apply<float>(op, 0, op->ncells, (const float *)x, (float *)y, false, true, s);
+}
+
+int mf_op_apply_internal(const mf_op *op, const void *x, void *y, void *stream) {
+  if (!op || !x || !y) return fail(MF_EINVAL, "mf_op_apply_internal: null argument");
+  if (x == y) return fail(MF_EINVAL, "mf_op_apply_internal: x and y alias");
+  return op_apply_internal(op, x, y, (hipStream_t)stream);
+}
+
+int mf_op_apply_range_internal(const mf_op *op, int64_t start, int64_t end, const void *x, void *y, int accumulate,
+                               void *stream) {
+  if (!op || !x || !y) return fail(MF_EINVAL, "mf_op_apply_range_internal: null argument");
+  if (start < 0 || end > op->ncells || start > end) return fail(MF_EINVAL, "mf_op_apply_range_internal: bad range");
+  if (x == y) return fail(MF_EINVAL, "mf_op_apply_range_internal: x and y alias");
+  hipStream_t s = (hipStream_t)stream;
+  return op->precision == MF_F64
+             ? op_apply_t<double>(op, start, end, (const double *)x, (double *)y, accumulate != 0, false, s)
+             : op_apply_t<float>(op, start, end, (const float *)x, (float *)y, accumulate != 0, false, s);
 }
 
 int mf_op_diagonal(const mf_op *op, void *d, void *stream) {
   if (!op || !d) return fail(MF_EINVAL, "mf_op_diagonal: null argument");
   hipStream_t s = (hipStream_t)stream;
-  return op->precision == MF_F64 ? op_diag_t<double>(op, (double *)d, s) : op_diag_t<float>(op, (float *)d, s);
+  return op->precision == MF_F64 ? user_diag<double>(op, (double *)d, s) : user_diag<float>(op, (float *)d, s);
 }
 
 int mf_op_get_info(const mf_op *op, mf_op_info *info) {

@@ -21,20 +21,9 @@ int fail(int code, const std::string &msg);
   } while (0)
 
 // ------------------------------------------------------------------ tables (host, FP64)
-// 1D Gauss-Legendre rule on [0,1].
-void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
-// k+1 Gauss-Lobatto-Legendre points on [0,1].
-std::vector<double> gll_points(int k);
-// Lagrange basis on `nodes` evaluated at `pts`: V[q*n+i], dV[q*n+i].
-void lagrange_eval(const std::vector<double> &nodes, const std::vector<double> &pts,
-                   std::vector<double> &V, std::vector<double> &dV);
-// Simplex quadrature of the given exact degree on the reference tet: points (x,y,z) and weights
-// (summing to 1/6). Returns false if no rule of that degree is built in.
-bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w);
-// P_k Lagrange basis on the reference tet at pts: phi[q*D+i], dphi[(q*D+i)*3+d].
-void tet_lagrange(int k, const std::vector<double> &pts, std::vector<double> &phi,
-                  std::vector<double> &dphi);
-int tet_ndofs(int k);
+}  // namespace mf
+#include "tables.h"
+namespace mf {
 
 // ------------------------------------------------------------------ objects
 struct DeviceBuffer {
@@ -62,7 +51,21 @@ struct mf_space {
   std::vector<int32_t> cell2vert;
   int degree = 0, ncomp = 0, D = 0;
   int64_t nnodes = 0;
-  std::vector<int32_t> cell2node;
+  std::vector<int32_t> cell2node;      // user numbering, as given
+  // Internal node numbering: nodes numbered in order of first appearance when the
+  // cells are traversed in order, so the nodes of consecutive cells are close in
+  // memory. The kernels use only the internal numbering.
+  std::vector<int32_t> user_of_int;    // internal node -> user node
+  std::vector<int32_t> int_of_user;    // user node -> internal node
+  // Internal cell order: cells sorted by colour (a greedy first-fit colouring in
+  // which no two cells of one colour share a vertex, hence no node), original
+  // order within a colour. colour_ptr[c] .. colour_ptr[c+1] are colour c's cells.
+  std::vector<int32_t> cell_user_of_int;  // internal cell -> user cell
+  std::vector<int64_t> colour_ptr;
+  std::vector<int32_t> cell2node_int;  // internal cell order, internal node numbering
+  std::vector<int32_t> cell2vert_int;  // internal cell order
+  uint64_t numbering_id = 0;           // equal ids <=> identical internal numbering
+  bool identity = false;               // internal numbering equals the user numbering
 };
 
 namespace mf {
@@ -74,21 +77,19 @@ template <typename T> struct HexArgs {
   const T *coef;       // ncells x 8 monomial coefficients of the vertex coefficient, or null
   const T *x;
   T *y;
-  int64_t c0, c1;      // cell range
+  int64_t c0, c1;      // internal cell range
   int ncomp;
+  const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
+  int64_t ulo, uhi;
 };
 
-// Hex tables for (T, N) are laid out contiguously as T B[N][N] (B[a][i] = l_i(g_a), GLL
-// Lagrange basis at Gauss point a), T D[N][N] (D[a][b] = derivative of the Lagrange
-// polynomial through the Gauss points, index b, at g_a), T g[N] (Gauss points on [0,1]),
-// T w[N] (weights), T dB[N][N] (dB[a][i] = l_i'(g_a)); hex_table_bytes gives the size.
-template <typename T> size_t hex_table_bytes(int N);
-
 // Kernel launchers (hex_kernels.hip)
+// atomic: scatter with device-scope atomics (any cell set); otherwise plain
+// read-modify-write, valid only when no two cells of [c0, c1) share a node.
 template <typename T>
-int launch_hex_apply(int N, int kind, const HexArgs<T> &a, const void *tab, hipStream_t s);
+int launch_hex_apply(int N, int kind, const HexArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
-int launch_hex_diag(int N, int kind, const HexArgs<T> &a, const void *tab, hipStream_t s);
+int launch_hex_diag(int N, int kind, const HexArgs<T> &a, hipStream_t s);
 
 // Tet elasticity (simplex_kernels.hip)
 template <typename T> struct TetArgs {
@@ -99,9 +100,11 @@ template <typename T> struct TetArgs {
   T *y;
   int64_t c0, c1;
   T lam, mu;
+  const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
+  int64_t ulo, uhi;
 };
 template <typename T>
-int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, hipStream_t s);
+int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s);
 
@@ -112,8 +115,10 @@ template <typename T> struct TriArgs {
   const T *x;
   T *y;
   int64_t c0, c1;
+  const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
+  int64_t ulo, uhi;
 };
-template <typename T> int launch_tri_mass(const TriArgs<T> &a, hipStream_t s);
+template <typename T> int launch_tri_mass(const TriArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T> int launch_tri_mass_diag(const TriArgs<T> &a, hipStream_t s);
 
 // Vector kernels (vec_kernels.hip)
@@ -122,7 +127,19 @@ template <typename T>
 int launch_copy_constrained(const int32_t *dofs, int64_t n, const T *x, T *y, hipStream_t s);
 template <typename T>
 int launch_set_constrained(const int32_t *dofs, int64_t n, T v, T *y, hipStream_t s);
+// x_int[i*nc + c] = x_user[uoi[i]*nc + c]
+template <typename T>
+int launch_to_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *xu, T *xi, hipStream_t s);
+// y_user[uoi[i]*nc + c] (+)= y_int[i*nc + c]
+template <typename T>
+int launch_from_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *yi, T *yu, bool acc, hipStream_t s);
 
+}  // namespace mf
+
+namespace mf {
+// Internal-numbering entry points used by the solvers.
+int op_apply_internal(const mf_op *op, const void *x, void *y, hipStream_t s);
+int op_diagonal_internal(const mf_op *op, void *d, hipStream_t s);
 }  // namespace mf
 
 struct mf_op {
@@ -130,8 +147,14 @@ struct mf_op {
   int64_t ncells = 0, nnodes = 0, ndofs = 0;
   double lam = 1.0, mu = 0.5;
   bool has_coef = false;
-  mf::DeviceBuffer map, geo, coef, tab, bc_dofs;
+  mf::DeviceBuffer map, geo, coef, tab, bc_dofs;  // map and bc_dofs in internal numbering
+  mf::DeviceBuffer perm;                          // internal node -> user node (int32)
+  mf::DeviceBuffer cell_user;                     // internal cell -> user cell (int32)
+  std::vector<int64_t> colour_ptr;                // colour ranges of the internal cell order
+  mf::DeviceBuffer wx, wy;                        // user-numbering workspaces (ndofs, op precision)
+  uint64_t numbering_id = 0;
+  bool identity = false;
+  bool coloured = true;  // full applies: one launch per colour with plain stores
   int64_t n_bc_dofs = 0;
-  std::vector<unsigned char> tab_host;  // hex tables passed by value to kernels
   double flops = 0.0, bytes = 0.0;
 };

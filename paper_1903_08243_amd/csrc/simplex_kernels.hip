@@ -26,14 +26,18 @@ __device__ __forceinline__ void atomic_add_s(float *p, float v) { unsafeAtomicAd
 // cells, so each lane keeps only that component's D nodal values (and D outputs) in
 // registers. The three components meet once per quadrature point through LDS to form
 // the stress.
-template <typename T, int K, int NQ>
+template <typename T, int K, int NQ, bool ATOMIC>
 __global__ void __launch_bounds__(192) tet_elasticity_kernel(const TetArgs<T> A) {
   constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
   __shared__ T sG[2][9][64];
   const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
   const int64_t batch = A.c0 / 64 + blockIdx.x;
   const int64_t cell = batch * 64 + lane;
-  const bool valid = cell >= A.c0 && cell < A.c1;
+  bool valid = cell >= A.c0 && cell < A.c1;
+  if (valid && A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    valid = u >= A.ulo && u < A.uhi;
+  }
   const int32_t *mp = A.map + batch * (D * 64) + lane;
   const T *gp = A.geo + batch * (10 * 64) + lane;
   T Ki[9];
@@ -78,7 +82,10 @@ __global__ void __launch_bounds__(192) tet_elasticity_kernel(const TetArgs<T> A)
 #pragma unroll
   for (int i = 0; i < D; i++) {
     const int idx = valid ? mp[i * 64] : -1;
-    if (idx >= 0) atomic_add_s(&A.y[3 * (int64_t)idx + c], ye[i]);
+    if (idx >= 0) {
+      if constexpr (ATOMIC) atomic_add_s(&A.y[3 * (int64_t)idx + c], ye[i]);
+      else A.y[3 * (int64_t)idx + c] += ye[i];  // cells of one launch share no node
+    }
   }
 }
 
@@ -113,31 +120,33 @@ __global__ void __launch_bounds__(192) tet_elasticity_diag_kernel(const TetArgs<
 }
 
 template <typename T, int K, int NQ>
-static int launch_tet_kq(const TetArgs<T> &a, hipStream_t s, bool diag) {
+static int launch_tet_kq(const TetArgs<T> &a, hipStream_t s, bool diag, bool atomic) {
   const int64_t b0 = a.c0 / 64, b1 = (a.c1 + 63) / 64;
   if (a.c1 <= a.c0) return MF_OK;
   dim3 grid((unsigned)(b1 - b0)), block(192);
   if (diag) tet_elasticity_diag_kernel<T, K, NQ><<<grid, block, 0, s>>>(a);
-  else tet_elasticity_kernel<T, K, NQ><<<grid, block, 0, s>>>(a);
+  else if (atomic) tet_elasticity_kernel<T, K, NQ, true><<<grid, block, 0, s>>>(a);
+  else tet_elasticity_kernel<T, K, NQ, false><<<grid, block, 0, s>>>(a);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
 
-template <typename T> static int launch_tet(int k, int nq, const TetArgs<T> &a, hipStream_t s, bool diag) {
-  if (k == 1 && nq == 1) return launch_tet_kq<T, 1, 1>(a, s, diag);
-  if (k == 2 && nq == 4) return launch_tet_kq<T, 2, 4>(a, s, diag);
-  if (k == 3 && nq == 14) return launch_tet_kq<T, 3, 14>(a, s, diag);
+template <typename T>
+static int launch_tet(int k, int nq, const TetArgs<T> &a, hipStream_t s, bool diag, bool atomic) {
+  if (k == 1 && nq == 1) return launch_tet_kq<T, 1, 1>(a, s, diag, atomic);
+  if (k == 2 && nq == 4) return launch_tet_kq<T, 2, 4>(a, s, diag, atomic);
+  if (k == 3 && nq == 14) return launch_tet_kq<T, 3, 14>(a, s, diag, atomic);
   return fail(MF_EUNSUPPORTED, "tet elasticity: degree / rule");
 }
 
-template <typename T> int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, hipStream_t s) {
-  return launch_tet<T>(k, nq, a, s, false);
+template <typename T> int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  return launch_tet<T>(k, nq, a, s, false, atomic);
 }
 template <typename T> int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s) {
-  return launch_tet<T>(k, nq, a, s, true);
+  return launch_tet<T>(k, nq, a, s, true, true);
 }
-template int launch_tet_elasticity<double>(int, int, const TetArgs<double> &, hipStream_t);
-template int launch_tet_elasticity<float>(int, int, const TetArgs<float> &, hipStream_t);
+template int launch_tet_elasticity<double>(int, int, const TetArgs<double> &, bool, hipStream_t);
+template int launch_tet_elasticity<float>(int, int, const TetArgs<float> &, bool, hipStream_t);
 template int launch_tet_elasticity_diag<double>(int, int, const TetArgs<double> &, hipStream_t);
 template int launch_tet_elasticity_diag<float>(int, int, const TetArgs<float> &, hipStream_t);
 
@@ -146,9 +155,13 @@ template int launch_tet_elasticity_diag<float>(int, int, const TetArgs<float> &,
 // so with s_a = |T| c_a, S = sum s_a, X = sum x_j:
 //   y_i = [ (S + s_i) X + <s, x> + (S + 2 s_i) x_i ] / 60.
 template <typename T>
-__global__ void __launch_bounds__(256) tri_mass_kernel(const TriArgs<T> A, bool diag) {
+__global__ void __launch_bounds__(256) tri_mass_kernel(const TriArgs<T> A, bool diag, bool atomic) {
   const int64_t cell = A.c0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= A.c1) return;
+  if (A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    if (u < A.ulo || u >= A.uhi) return;
+  }
   int idx[3];
   T s[3], x[3];
 #pragma unroll
@@ -164,21 +177,26 @@ __global__ void __launch_bounds__(256) tri_mass_kernel(const TriArgs<T> A, bool 
 #pragma unroll
   for (int i = 0; i < 3; i++) {
     const T v = diag ? (T(2) * S + T(4) * s[i]) * k60 : ((S + s[i]) * X + sx + (S + T(2) * s[i]) * x[i]) * k60;
-    if (idx[i] >= 0) atomic_add_s(&A.y[idx[i]], v);
+    if (idx[i] >= 0) {
+      if (atomic) atomic_add_s(&A.y[idx[i]], v);
+      else A.y[idx[i]] += v;  // cells of one launch share no node
+    }
   }
 }
 
-template <typename T> static int launch_tri(const TriArgs<T> &a, hipStream_t s, bool diag) {
+template <typename T> static int launch_tri(const TriArgs<T> &a, hipStream_t s, bool diag, bool atomic) {
   const int64_t n = a.c1 - a.c0;
   if (n <= 0) return MF_OK;
-  tri_mass_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(a, diag);
+  tri_mass_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(a, diag, atomic);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
-template <typename T> int launch_tri_mass(const TriArgs<T> &a, hipStream_t s) { return launch_tri<T>(a, s, false); }
-template <typename T> int launch_tri_mass_diag(const TriArgs<T> &a, hipStream_t s) { return launch_tri<T>(a, s, true); }
-template int launch_tri_mass<double>(const TriArgs<double> &, hipStream_t);
-template int launch_tri_mass<float>(const TriArgs<float> &, hipStream_t);
+template <typename T> int launch_tri_mass(const TriArgs<T> &a, bool atomic, hipStream_t s) {
+  return launch_tri<T>(a, s, false, atomic);
+}
+template <typename T> int launch_tri_mass_diag(const TriArgs<T> &a, hipStream_t s) { return launch_tri<T>(a, s, true, true); }
+template int launch_tri_mass<double>(const TriArgs<double> &, bool, hipStream_t);
+template int launch_tri_mass<float>(const TriArgs<float> &, bool, hipStream_t);
 template int launch_tri_mass_diag<double>(const TriArgs<double> &, hipStream_t);
 template int launch_tri_mass_diag<float>(const TriArgs<float> &, hipStream_t);
 

@@ -12,7 +12,9 @@
 #include <algorithm>
 #include <cmath>
 
-#include "mf_internal.h"
+#include <cmath>
+
+#include "tables.h"
 
 namespace mf {
 

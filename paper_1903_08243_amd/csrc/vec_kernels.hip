@@ -23,6 +23,27 @@ __global__ void set_constrained_kernel(const int32_t *__restrict__ dofs, int64_t
   if (i < n) y[dofs[i]] = v;
 }
 
+template <typename T>
+__global__ void to_internal_kernel(const int32_t *__restrict__ uoi, int64_t nnodes, int nc, const T *__restrict__ xu,
+                                   T *__restrict__ xi) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes) return;
+  const int64_t u = uoi[i];
+  for (int c = 0; c < nc; c++) xi[i * nc + c] = xu[u * nc + c];
+}
+
+template <typename T>
+__global__ void from_internal_kernel(const int32_t *__restrict__ uoi, int64_t nnodes, int nc, const T *__restrict__ yi,
+                                     T *__restrict__ yu, bool acc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nnodes) return;
+  const int64_t u = uoi[i];
+  for (int c = 0; c < nc; c++) {
+    const T v = yi[i * nc + c];
+    yu[u * nc + c] = acc ? yu[u * nc + c] + v : v;
+  }
+}
+
 static unsigned grid_for(int64_t n, int block, int64_t cap) {
   int64_t g = (n + block - 1) / block;
   if (g > cap) g = cap;
@@ -47,6 +68,25 @@ template <typename T> int launch_set_constrained(const int32_t *dofs, int64_t n,
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
+
+template <typename T>
+int launch_to_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *xu, T *xi, hipStream_t s) {
+  if (nnodes <= 0) return MF_OK;
+  to_internal_kernel<T><<<grid_for(nnodes, 256, 1ll << 30), 256, 0, s>>>(uoi, nnodes, nc, xu, xi);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template <typename T>
+int launch_from_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *yi, T *yu, bool acc, hipStream_t s) {
+  if (nnodes <= 0) return MF_OK;
+  from_internal_kernel<T><<<grid_for(nnodes, 256, 1ll << 30), 256, 0, s>>>(uoi, nnodes, nc, yi, yu, acc);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_to_internal<double>(const int32_t *, int64_t, int, const double *, double *, hipStream_t);
+template int launch_to_internal<float>(const int32_t *, int64_t, int, const float *, float *, hipStream_t);
+template int launch_from_internal<double>(const int32_t *, int64_t, int, const double *, double *, bool, hipStream_t);
+template int launch_from_internal<float>(const int32_t *, int64_t, int, const float *, float *, bool, hipStream_t);
 
 template int launch_fill<double>(double *, double, int64_t, hipStream_t);
 template int launch_fill<float>(float *, float, int64_t, hipStream_t);

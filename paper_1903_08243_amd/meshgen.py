@@ -122,11 +122,10 @@ def hex_space(mesh: Mesh, k: int, ncomp: int = 1, renumber: bool = True,
     c = np.arange(m)
     cz, cy, cx = np.meshgrid(c, c, c, indexing="ij")
     cx, cy, cz = cx.ravel(), cy.ravel(), cz.ravel()
-    c2n = np.empty((m ** 3, n ** 3), dtype=np.int64)
-    for l in range(n):
-        for j in range(n):
-            for i in range(n):
-                c2n[:, i + n * j + n * n * l] = (cx * k + i) + G * ((cy * k + j) + G * (cz * k + l))
+    base = (cx * k) + G * ((cy * k) + G * (cz * k))
+    loc = _lattice(k, 3)  # local node (i, j, l), i fastest
+    off = loc[:, 0] + G * (loc[:, 1] + G * loc[:, 2])
+    c2n = base[:, None] + off[None, :]
     nn = G ** 3
     perm = _permutation(nn, renumber, config, k if seed_k is None else seed_k)
     c2n = perm[c2n]

@@ -235,3 +235,84 @@ def test_run_to_run_reproducible_within_rounding(mf):
     xt = torch.tensor(x, device="cuda")
     y2 = op.apply(xt).cpu().numpy()
     assert _relerr(y2, y1) <= 1e-14
+
+
+def _greedy_colouring(c2v, nverts):
+    """Definition: first-fit colouring in cell order; cells conflict when they share a vertex."""
+    vcells = [[] for _ in range(nverts)]
+    for K, row in enumerate(c2v):
+        for v in row:
+            vcells[v].append(K)
+    colour = np.full(len(c2v), -1, np.int64)
+    for K, row in enumerate(c2v):
+        used = {colour[J] for v in row for J in vcells[v] if colour[J] >= 0}
+        c = 0
+        while c in used:
+            c += 1
+        colour[K] = c
+    return colour
+
+
+def _first_touch(c2n, nnodes):
+    """Definition: order of first appearance in the cell-major map."""
+    seen = np.full(nnodes, -1, np.int64)
+    order = []
+    for u in c2n.ravel():
+        if seen[u] < 0:
+            seen[u] = len(order)
+            order.append(u)
+    rest = [u for u in range(nnodes) if seen[u] < 0]
+    return np.array(order + rest, dtype=np.int32)
+
+
+@pytest.mark.parametrize("case", ["hex", "tet", "tri"])
+def test_colouring_and_internal_numbering_bit_exact(mf, case):
+    import torch
+    if case == "hex":
+        mesh = mg.hex_mesh(4, 0.15)
+        space, kind = mg.hex_space(mesh, 3, ncomp=3), 2
+    elif case == "tet":
+        mesh = mg.tet_mesh(3, 0.2)
+        space, kind = mg.tet_space(mesh, 2), 4
+    else:
+        mesh = mg.tri_mesh(6, 0.1)
+        space, kind = mg.tri_p1_space(mesh, True), 0
+    sp = mf.Space.from_meshgen(space)
+    colour = _greedy_colouring(mesh.cell2vert, mesh.nverts)
+    order, ptr = sp.colouring()
+    assert np.array_equal(order, np.argsort(colour, kind="stable").astype(np.int32))
+    assert np.array_equal(ptr, np.concatenate([[0], np.cumsum(np.bincount(colour))]))
+    # validity: no two cells of one colour share a node
+    for c in range(len(ptr) - 1):
+        cells = order[ptr[c]:ptr[c + 1]]
+        nodes = space.cell2node[cells].ravel()
+        assert len(np.unique(nodes)) == nodes.size
+    i2u = sp.internal_to_user()
+    assert np.array_equal(i2u, _first_touch(space.cell2node[order], space.nnodes))
+    coef = np.ones(mesh.nverts) if kind == 0 else None
+    op = mf.Operator(sp, kind, 0, vertex_coef=coef)
+    nc = space.ncomp
+    x = np.random.default_rng(9).uniform(-1, 1, space.ndofs)
+    y_user = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    dof_i2u = (i2u[:, None].astype(np.int64) * nc + np.arange(nc)).ravel()
+    y_int = op.apply_internal(torch.tensor(x[dof_i2u], device="cuda")).cpu().numpy()
+    assert np.abs(y_int - y_user[dof_i2u]).max() <= 1e-14 * np.abs(y_user).max()
+    ref = oracle.OracleOp(space, kind, coef=coef).apply(x)
+    assert _relerr(y_user, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_coloured_scatter_is_bit_reproducible_and_matches_atomic(mf, prec):
+    import torch
+    mesh = mg.hex_mesh(17, 0.15)  # 4913 cells: coloured by default
+    space = mg.hex_space(mesh, 3)
+    sp = mf.Space.from_meshgen(space)
+    x = torch.tensor(np.random.default_rng(0).uniform(-1, 1, space.ndofs), device="cuda",
+                     dtype=torch.float64 if prec == 0 else torch.float32)
+    opc = mf.Operator(sp, 1, prec, scatter=mf.SCATTER_COLOURED)
+    opa = mf.Operator(sp, 1, prec, scatter=mf.SCATTER_ATOMIC)
+    y1 = opc.apply(x).cpu().numpy()
+    y2 = opc.apply(x).cpu().numpy()
+    assert np.array_equal(y1, y2)
+    ya = opa.apply(x).cpu().numpy()
+    assert _relerr(ya, y1) <= (1e-14 if prec == 0 else 1e-6)
