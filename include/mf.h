@@ -198,6 +198,39 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
 
 void mf_precond_destroy(mf_precond *p);
 
+/* ----------------------------------------------------------------- batched solves
+ * Many independent systems A64[i] x[i] = b[i] on uneven hex meshes and degrees,
+ * solved together (not in the paper -- the batched form of the CG consumer of
+ * the action). Every iteration applies all operators in ONE persistent launch
+ * over a device work list of (operator, cell-batch range) items; vector stages
+ * run over the concatenated vectors of all systems; chunks of iterations are
+ * captured into a hipGraph and replayed. Requirements: FP64 hex operators of
+ * one kind, degree <= 5, without constraints; A32 (nullable) holds the FP32
+ * operators on the same spaces (iterative refinement as in mf_cg_solve); M
+ * (nullable, entries nullable) Jacobi preconditioners of the A64[i].
+ * The batch binds the device pointers b[i] (input) and x[i] (initial guess in,
+ * solution out, user numbering); they must stay valid while the batch exists. */
+typedef struct mf_batch mf_batch;
+int mf_batch_create(int nsys, const mf_op *const *A64, const mf_op *const *A32, const mf_precond *const *M,
+                    const double *const *b, double *const *x, void *stream, mf_batch **out);
+/* Solve all systems to ||b_i - A64_i x_i|| <= rtol ||b_i|| (true FP64 residual).
+ * infos (nullable) receives nsys entries. maxit bounds the inner iterations of
+ * the slowest system summed over refinements. Synchronous. Errors as
+ * mf_cg_solve (MF_ENOTCONV if any system misses the tolerance). */
+int mf_batch_solve(mf_batch *batch, double rtol, double inner_rtol, int maxit, mf_cg_info *infos, void *stream);
+/* One batched operator launch (inner = 1: the inner operators on the internal
+ * search directions; 0: the FP64 operators on the iterates), for timing. */
+int mf_batch_apply(mf_batch *batch, int inner, void *stream);
+/* Autotuner: times the batched launch for work-list granularities (cell batches
+ * per item) 1..32 and persistent grids of 1, 2, 4 x (CUs x 4) workgroups and
+ * keeps the fastest. With cache_path, a result for the same (kind, inner
+ * precision, CU count, set of (degree, cells)) is read from / appended to that
+ * text file. */
+int mf_batch_autotune(mf_batch *batch, const char *cache_path, void *stream);
+int mf_batch_get_tuning(const mf_batch *batch, int *items_per, int *grid);
+int mf_batch_set_tuning(mf_batch *batch, int items_per, int grid);
+void mf_batch_destroy(mf_batch *batch);
+
 /* ----------------------------------------------------------------- teardown / errors */
 void mf_mesh_destroy(mf_mesh *m);   /* NULL-safe */
 void mf_space_destroy(mf_space *s); /* NULL-safe */

@@ -79,6 +79,13 @@ def load_library():
         "mf_op_get_info": (I, [P, ctypes.POINTER(_OpInfo)]),
         "mf_precond_create_jacobi": (I, [P, P, PP]),
         "mf_cg_solve": (I, [P, P, P, P, P, D, D, I, ctypes.POINTER(CGInfo), P]),
+        "mf_batch_create": (I, [I, P, P, P, P, P, P, PP]),
+        "mf_batch_solve": (I, [P, D, D, I, P, P]),
+        "mf_batch_apply": (I, [P, I, P]),
+        "mf_batch_autotune": (I, [P, ctypes.c_char_p, P]),
+        "mf_batch_get_tuning": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "mf_batch_set_tuning": (I, [P, I, I]),
+        "mf_batch_destroy": (None, [P]),
         "mf_mesh_destroy": (None, [P]),
         "mf_space_destroy": (None, [P]),
         "mf_op_destroy": (None, [P]),
@@ -275,3 +282,59 @@ def cg_solve(A64: Operator, b, x, A32: Operator | None = None, precond=None, rto
     if rc != 0 and raise_on_error:
         _check(rc)
     return info.as_dict() | {"rc": rc}
+
+
+class Batch:
+    """Many systems solved together: one persistent launch applies every operator
+    per CG iteration; iterations are replayed from a captured hipGraph.
+
+    The device vectors b[i] (rhs) and x[i] (initial guess / solution, user
+    numbering, FP64) are bound at creation and must outlive the batch."""
+
+    def __init__(self, A64, b, x, A32=None, M=None, stream=None):
+        import torch
+        L = load_library()
+        n = len(A64)
+        if len(b) != n or len(x) != n or (A32 is not None and len(A32) != n) or (M is not None and len(M) != n):
+            raise ValueError("A64, b, x (and A32, M) must have the same length")
+        for t in list(b) + list(x):
+            _dev(t, torch.float64)
+        P = ctypes.c_void_p
+        self._keep = (list(A64), list(A32 or []), list(M or []), list(b), list(x))
+        a64 = (P * n)(*[a.handle.value for a in A64])
+        a32 = None if A32 is None else (P * n)(*[a.handle.value for a in A32])
+        mm = None if M is None else (P * n)(*[(m.handle.value if m is not None else None) for m in M])
+        bb = (P * n)(*[t.data_ptr() for t in b])
+        xx = (P * n)(*[t.data_ptr() for t in x])
+        h = ctypes.c_void_p()
+        _check(L.mf_batch_create(n, a64, a32, mm, bb, xx, _stream(stream), ctypes.byref(h)))
+        self.handle, self.n = h, n
+
+    def solve(self, rtol=1e-10, inner_rtol=0.0, maxit=100000, stream=None, raise_on_error=True):
+        infos = (CGInfo * self.n)()
+        rc = load_library().mf_batch_solve(self.handle, rtol, inner_rtol, maxit, infos, _stream(stream))
+        if rc != 0 and raise_on_error:
+            _check(rc)
+        return [i.as_dict() for i in infos], rc
+
+    def apply(self, inner=True, stream=None):
+        _check(load_library().mf_batch_apply(self.handle, int(inner), _stream(stream)))
+
+    def autotune(self, cache_path=None, stream=None):
+        _check(load_library().mf_batch_autotune(self.handle, None if cache_path is None else cache_path.encode(),
+                                                _stream(stream)))
+        return self.tuning
+
+    @property
+    def tuning(self):
+        per, grid = ctypes.c_int(), ctypes.c_int()
+        _check(load_library().mf_batch_get_tuning(self.handle, ctypes.byref(per), ctypes.byref(grid)))
+        return per.value, grid.value
+
+    def set_tuning(self, items_per, grid):
+        _check(load_library().mf_batch_set_tuning(self.handle, items_per, grid))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mf_batch_destroy(self.handle)
+            self.handle = None

@@ -64,19 +64,28 @@ template <> struct HexLds<6> { static constexpr int SY = 9, SZ = 54, SE = 324; }
 template <> struct HexLds<7> { static constexpr int SY = 7, SZ = 52, SE = 364; };
 
 // ---------------------------------------------------------------------------------- apply
+// LDS (in units of T) one wavefront needs for degree n-1: three padded n^3 buffers
+// per cell (one without gradients) and 32 geometry values per cell.
+template <int N, bool GRAD> constexpr int hex_lds_size() {
+  return hex_epb<N>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32);
+}
+
+// Processes cell batches b, b+G, b+2G, ... < nb (EPB cells each) of one operator on
+// the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
 template <typename T, int N, int KIND, bool ATOMIC>
-__global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
+__device__ __forceinline__ void hex_cells(const HexArgs<T> &A, int64_t b, const int64_t G, const int64_t nb,
+                                          T *lds) {
   using TB = TabT<T, N>;
   constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N>();
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
   constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ, SE = HexLds<N>::SE;
-  __shared__ T s0[EPB * SE];
-  __shared__ T s1[GRAD ? EPB * SE : 1];
-  __shared__ T s2[GRAD ? EPB * SE : 1];
+  T *s0 = lds;
+  T *s1 = lds + (GRAD ? EPB * SE : 0);
+  T *s2 = lds + (GRAD ? 2 * EPB * SE : 0);
+  T *sg = lds + (GRAD ? 3 : 1) * EPB * SE;
 #define IX(x, y, z) ((z) * SZ + (y) * SY + (x))
-  __shared__ T sg[EPB * 32];
 
   const int t = threadIdx.x;
   const bool mirror = t >= EPB * NN;
@@ -84,9 +93,6 @@ __global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
   const int le = tt / NN, p = tt - le * NN;
   const int pa = p % N, pb = p / N;
   const int nc = A.ncomp;
-  const int64_t nb = (A.c1 - A.c0 + EPB - 1) / EPB;  // cell batches (EPB cells each)
-  const int64_t G = gridDim.x;
-  int64_t b = blockIdx.x;
   if (b >= nb) return;  // whole workgroup (= one wavefront)
 
   // Work items are (batch, component) pairs, batches b, b+G, b+2G, ... for this
@@ -380,6 +386,80 @@ __global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
 }
 
 #undef IX
+
+template <typename T, int N, int KIND, bool ATOMIC>
+__global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
+  __shared__ T lds[hex_lds_size<N, KIND != K_MASS>()];
+  const int64_t nb = (A.c1 - A.c0 + hex_epb<N>() - 1) / hex_epb<N>();  // cell batches
+  hex_cells<T, N, KIND, ATOMIC>(A, blockIdx.x, gridDim.x, nb, lds);
+}
+
+// ---------------------------------------------------------------------------------- batched apply
+// One persistent launch applies many operators (uneven sizes and degrees): each
+// wavefront walks a device work list of (operator, batch range) items and runs the
+// degree's code path. Items of operators whose solve has stopped are skipped.
+template <typename T> struct HexBatchOp {
+  HexArgs<T> a;
+  int N;
+  int pad;
+};
+struct HexBatchItem {
+  int32_t op;
+  int32_t pad;
+  int64_t b0, b1;  // cell batches [b0, b1) of the operator (EPB(N) cells each)
+};
+
+template <typename T, int KIND>
+__global__ void __launch_bounds__(64) hex_batch_kernel(const HexBatchOp<T> *__restrict__ ops,
+                                                       const HexBatchItem *__restrict__ items, int nitems,
+                                                       const int *__restrict__ stop, int stop_stride) {
+  constexpr bool GRAD = KIND != K_MASS;
+  constexpr int L2 = hex_lds_size<2, GRAD>(), L3 = hex_lds_size<3, GRAD>(), L4 = hex_lds_size<4, GRAD>(),
+                L5 = hex_lds_size<5, GRAD>(), L6 = hex_lds_size<6, GRAD>();
+  constexpr int LM = L2 > L3 ? (L2 > L4 ? (L2 > L5 ? (L2 > L6 ? L2 : L6) : (L5 > L6 ? L5 : L6))
+                                        : (L4 > L5 ? (L4 > L6 ? L4 : L6) : (L5 > L6 ? L5 : L6)))
+                             : (L3 > L4 ? (L3 > L5 ? (L3 > L6 ? L3 : L6) : (L5 > L6 ? L5 : L6))
+                                        : (L4 > L5 ? (L4 > L6 ? L4 : L6) : (L5 > L6 ? L5 : L6)));
+  __shared__ T lds[LM];
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const HexBatchItem w = items[it];
+    if (stop && stop[(int64_t)w.op * stop_stride]) continue;
+    const HexArgs<T> A = ops[w.op].a;
+    switch (ops[w.op].N) {
+      case 2: hex_cells<T, 2, KIND, true>(A, w.b0, 1, w.b1, lds); break;
+      case 3: hex_cells<T, 3, KIND, true>(A, w.b0, 1, w.b1, lds); break;
+      case 4: hex_cells<T, 4, KIND, true>(A, w.b0, 1, w.b1, lds); break;
+      case 5: hex_cells<T, 5, KIND, true>(A, w.b0, 1, w.b1, lds); break;
+      case 6: hex_cells<T, 6, KIND, true>(A, w.b0, 1, w.b1, lds); break;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+int launch_hex_batch(int kind, const void *ops, const void *items, int nitems, int grid, const int *stop,
+                     int stop_stride, hipStream_t s) {
+  if (nitems <= 0) return MF_OK;
+  const HexBatchOp<T> *o = (const HexBatchOp<T> *)ops;
+  const HexBatchItem *w = (const HexBatchItem *)items;
+  switch (kind) {
+    case K_MASS: hex_batch_kernel<T, K_MASS><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
+    case K_HELM: hex_batch_kernel<T, K_HELM><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
+    case K_LAP: hex_batch_kernel<T, K_LAP><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
+    case K_POIS: hex_batch_kernel<T, K_POIS><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
+    default: return fail(MF_EUNSUPPORTED, "batched kernel: operator kind");
+  }
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_hex_batch<double>(int, const void *, const void *, int, int, const int *, int, hipStream_t);
+template int launch_hex_batch<float>(int, const void *, const void *, int, int, const int *, int, hipStream_t);
+
+size_t hex_batch_op_bytes(int precision) {
+  return precision == MF_F64 ? sizeof(HexBatchOp<double>) : sizeof(HexBatchOp<float>);
+}
+size_t hex_batch_item_bytes() { return sizeof(HexBatchItem); }
+int hex_cells_per_batch(int N) { return 64 / (N * N); }
 
 // ---------------------------------------------------------------------------------- diagonal
 // diag_i = sum_q [ grad_ref phi_i^T G grad_ref phi_i + m phi_i^2 ], one thread per cell node;

@@ -90,6 +90,15 @@ template <typename T>
 int launch_hex_apply(int N, int kind, const HexArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_hex_diag(int N, int kind, const HexArgs<T> &a, hipStream_t s);
+// Batched persistent launch over a device work list (see hex_kernels.hip for the
+// layouts of the op and item records; degrees 1..5). stop (optional) is read at
+// stop[op * stop_stride]; items of stopped operators are skipped.
+template <typename T>
+int launch_hex_batch(int kind, const void *ops, const void *items, int nitems, int grid, const int *stop,
+                     int stop_stride, hipStream_t s);
+size_t hex_batch_op_bytes(int precision);
+size_t hex_batch_item_bytes();
+int hex_cells_per_batch(int N);
 
 // Tet elasticity (simplex_kernels.hip)
 template <typename T> struct TetArgs {
