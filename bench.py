@@ -140,6 +140,63 @@ def bench_cg(mf, mg, k=3, m=32):
     return out
 
 
+def bench_c4(mf, mg, nsys=64, seed=0):
+    """64 Helmholtz systems on hex meshes m ~ U{8..40}^3, Q_k with k ~ U{2..5}, b ~ U[-1,1]:
+    FP32-action batched CG with FP64 refinement to 1e-10 (autotuned persistent launch)
+    vs the same batch in FP64 vs one FP64 Jacobi-CG solve after another."""
+    import tempfile
+
+    import torch
+    r = np.random.default_rng([4, 9, seed])
+    ms, ks = r.integers(8, 41, size=nsys), r.integers(2, 6, size=nsys)
+    sy = []
+    for i in range(nsys):
+        mesh = mg.hex_mesh(int(ms[i]), 0.15, config=3, seed_k=100 + i)
+        space = mg.hex_space(mesh, int(ks[i]), config=3, seed_k=100 + i)
+        sp = mf.Space.from_meshgen(space)
+        A64 = mf.Operator(sp, mf.HELMHOLTZ, mf.F64)
+        A32 = mf.Operator(sp, mf.HELMHOLTZ, mf.F32)
+        M = mf.JacobiPrecond(A64)
+        b = torch.tensor(mg.uniform(space.ndofs, -1, 1, 3, mg.PURPOSE_RHS, 100 + i), device="cuda")
+        sy.append((A64, A32, M, b))
+    ndofs = sum(int(s[3].numel()) for s in sy)
+    out = {"systems": nsys, "total_dofs": ndofs, "mesh_m": [int(v) for v in ms], "degree": [int(v) for v in ks]}
+    cache = os.path.join(tempfile.gettempdir(), "mf_batch_tuning.txt")
+    for name, refined in (("batched_fp32_refined", True), ("batched_fp64", False)):
+        xs = [torch.zeros_like(s[3]) for s in sy]
+        B = mf.Batch([s[0] for s in sy], [s[3] for s in sy], xs, A32=[s[1] for s in sy] if refined else None,
+                     M=[s[2] for s in sy])
+        t0 = time.perf_counter()
+        tune = B.autotune(cache)
+        t_tune = time.perf_counter() - t0
+        B.solve(rtol=1e-10)  # warm-up (graph capture)
+        for x in xs:
+            x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos, rc = B.solve(rtol=1e-10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"seconds": dt, "rc": rc, "max_rel_residual": max(i["rel_residual"] for i in infos),
+                     "max_inner_iterations": max(i["inner_iterations"] for i in infos),
+                     "max_outer": max(i["outer_iterations"] for i in infos),
+                     "tuning_items_per_grid": list(tune), "autotune_seconds": t_tune}
+        del B
+    xs = [torch.zeros_like(s[3]) for s in sy]
+    for (A64, A32, M, b), x in zip(sy, xs):  # warm
+        mf.cg_solve(A64, b, x, precond=M, rtol=1e-10)
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [mf.cg_solve(A64, b, x, precond=M, rtol=1e-10) for (A64, A32, M, b), x in zip(sy, xs)]
+    torch.cuda.synchronize()
+    out["sequential_fp64"] = {"seconds": time.perf_counter() - t0,
+                              "max_rel_residual": max(i["rel_residual"] for i in res),
+                              "max_iterations": max(i["inner_iterations"] for i in res)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -240,6 +297,16 @@ def main():
         log("timing the CPU oracle on a bounded sample ...")
         cpu = cpu_baseline(mg, cases)
         log(f"  cpu oracle: {cpu['value']:.4f} GDoF/s on {cpu['cores']} threads")
+    n_ops = len(cases)
+    if not args.quick:
+        del cases  # free the headline operators before the batched workload
+        torch.cuda.empty_cache()
+        try:
+            log("batched solves (64 Helmholtz systems) ...")
+            extra["c4_batched"] = bench_c4(mf, mg)
+            log(f"  c4: {json.dumps({k: v for k, v in extra['c4_batched'].items() if k not in ('mesh_m', 'degree')})}")
+        except Exception as ex:
+            extra["c4_batched"] = {"error": repr(ex)}
 
     out = {
         "metric": METRIC, "value": value, "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
@@ -247,7 +314,7 @@ def main():
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "FP64 Helmholtz + Laplacian (ncomp 3 and 1) actions, Q1..Q6 GLL, (k+1)^3 Gauss, "
                                "32^3 hex of the unit cube perturbed +-0.15h, random node renumbering",
-                   "cells": 32768, "degrees": degrees, "operators_per_step": len(cases),
+                   "cells": 32768, "degrees": degrees, "operators_per_step": n_ops,
                    "dofs_per_step": dofs_per_step},
         "roofline": roofline, "cpu_baseline": cpu,
         "internal_numbering": {"value": value_int, "unit": "GDoF/s", "ms_per_step": t_int * 1e3,

@@ -221,9 +221,9 @@ int mf_batch_solve(mf_batch *batch, double rtol, double inner_rtol, int maxit, m
 /* One batched operator launch (inner = 1: the inner operators on the internal
  * search directions; 0: the FP64 operators on the iterates), for timing. */
 int mf_batch_apply(mf_batch *batch, int inner, void *stream);
-/* Autotuner: times the batched launch for work-list granularities (cell batches
- * per item) 1..32 and persistent grids of 1, 2, 4 x (CUs x 4) workgroups and
- * keeps the fastest. With cache_path, a result for the same (kind, inner
+/* Autotuner: times the batched launch with one wavefront per single-batch work
+ * item (grid 0), and persistent grids of 1, 2, 4 x (CUs x 4) wavefronts with
+ * work-list granularities of 1..32 cell batches per item, and keeps the fastest. With cache_path, a result for the same (kind, inner
  * precision, CU count, set of (degree, cells)) is read from / appended to that
  * text file. */
 int mf_batch_autotune(mf_batch *batch, const char *cache_path, void *stream);

@@ -51,7 +51,7 @@ struct mf_batch {
   std::vector<double *> b_user, x_user;
   mf::DeviceBuffer b, x, r, p, Ap, p32, Ap32, d, dinv, part, st, chunks, cptr;
   mf::DeviceBuffer ops64x, ops_in, items;  // op tables: FP64 residual (x -> Ap), inner (p -> Ap / p32 -> Ap32)
-  int nch = 0, nitems = 0, grid = 0, items_per = 4;
+  int nch = 0, nitems = 0, grid = 0, items_per = 1;  // grid 0: one wavefront per item
   int64_t resident = 0;
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
@@ -117,12 +117,13 @@ static int build_items(mf_batch *B, int per) {
 static int batch_apply(mf_batch *B, const mf::DeviceBuffer &ops, int precision, void *y, const CgState *st) {
   const int *stop = st ? (const int *)((const char *)st + offsetof(CgState, stop)) : nullptr;
   const int stride = (int)(sizeof(CgState) / sizeof(int));
+  const BatchVec v = vec_desc(B);
   int rc;
   if (precision == MF_F64) {
-    rc = launch_fill<double>((double *)y, 0.0, B->ntot, B->s);
+    rc = st ? batch_fill(v, (double *)y, st, B->s) : launch_fill<double>((double *)y, 0.0, B->ntot, B->s);
     if (!rc) rc = launch_hex_batch<double>(B->kind, ops.ptr, B->items.ptr, B->nitems, B->grid, stop, stride, B->s);
   } else {
-    rc = launch_fill<float>((float *)y, 0.0f, B->ntot, B->s);
+    rc = st ? batch_fill(v, (float *)y, st, B->s) : launch_fill<float>((float *)y, 0.0f, B->ntot, B->s);
     if (!rc) rc = launch_hex_batch<float>(B->kind, ops.ptr, B->items.ptr, B->nitems, B->grid, stop, stride, B->s);
   }
   return rc;
@@ -274,8 +275,8 @@ int mf_batch_create(int nsys, const mf_op *const *A64, const mf_op *const *A32, 
   rc = B->refine ? upload_ops(B->ops_in, t32p, B->s) : upload_ops(B->ops_in, t64p, B->s);
   if (rc) return rc;
   B->resident = batch_resident(B.get());
-  B->grid = (int)B->resident;
-  if ((rc = build_items(B.get(), 4))) return rc;
+  B->grid = 0;
+  if ((rc = build_items(B.get(), 1))) return rc;
   MF_HIP(hipStreamSynchronize(B->s));
   *out = B.release();
   return MF_OK;
@@ -295,7 +296,8 @@ int mf_batch_get_tuning(const mf_batch *B, int *items_per, int *grid) {
 }
 
 int mf_batch_set_tuning(mf_batch *B, int items_per, int grid) {
-  if (!B || items_per < 1 || grid < 1) return fail(MF_EINVAL, "mf_batch_set_tuning: bad arguments");
+  if (!B || items_per < 1 || grid < 0 || (grid == 0 && items_per != 1))
+    return fail(MF_EINVAL, "mf_batch_set_tuning: items_per >= 1, grid >= 0 (grid 0 needs items_per 1)");
   if (B->exec) {
     (void)hipGraphExecDestroy(B->exec);
     B->exec = nullptr;
@@ -340,23 +342,24 @@ int mf_batch_autotune(mf_batch *B, const char *cache_path, void *stream) {
       if (line.rfind(key, 0) == 0) {
         std::istringstream is(line.substr(std::strlen(key)));
         int per = 0, grid = 0;
-        if (is >> per >> grid && per > 0 && grid > 0) return mf_batch_set_tuning(B, per, grid);
+        if (is >> per >> grid && per > 0 && grid >= 0) return mf_batch_set_tuning(B, per, grid);
       }
     }
   }
   (void)stream;
   const int pers[] = {1, 2, 4, 8, 16, 32};
-  const int64_t grids[] = {B->resident, 2 * B->resident, 4 * B->resident};
+  const int64_t grids[] = {0, B->resident, 2 * B->resident, 4 * B->resident};
   hipEvent_t e0, e1;
   MF_HIP(hipEventCreate(&e0));
   MF_HIP(hipEventCreate(&e1));
   float best = 1e30f;
-  int best_per = 4, best_grid = (int)B->resident;
+  int best_per = 1, best_grid = 0;
   const bool a32 = B->refine;
   for (int per : pers) {
     int rc = build_items(B, per);
     if (rc) return rc;
     for (int64_t g : grids) {
+      if (g == 0 && per != 1) continue;
       B->grid = (int)g;
       for (int w = 0; w < 2; w++)
         if ((rc = batch_apply(B, B->ops_in, a32 ? MF_F32 : MF_F64, a32 ? B->Ap32.ptr : B->Ap.ptr, nullptr))) return rc;

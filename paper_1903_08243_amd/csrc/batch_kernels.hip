@@ -176,7 +176,23 @@ __global__ void bfinalize_kernel(const double *__restrict__ part, int nch, const
   st[s] = S;
 }
 
+template <typename T>
+__global__ void __launch_bounds__(BR) bfill_kernel(T *__restrict__ y, const VChunk *__restrict__ ch,
+                                                   const CgState *__restrict__ st) {
+  const VChunk c = ch[blockIdx.x];
+  if (st[c.sys].stop) return;
+  for (int64_t i = c.start + threadIdx.x; i < c.start + c.len; i += BR) y[i] = T(0);
+}
+
 // ------------------------------------------------------------------ launchers
+template <typename T> int batch_fill(const BatchVec &v, T *y, const CgState *st, hipStream_t s) {
+  bfill_kernel<T><<<v.nch, BR, 0, s>>>(y, v.chunks, st);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int batch_fill<double>(const BatchVec &, double *, const CgState *, hipStream_t);
+template int batch_fill<float>(const BatchVec &, float *, const CgState *, hipStream_t);
+
 static int fin(const BatchVec &v, CgState *st, int stage, hipStream_t s) {
   bfinalize_kernel<<<(v.nsys + 63) / 64, 64, 0, s>>>(v.part, v.nch, v.cptr, st, v.nsys, stage);
   MF_HIP(hipGetLastError());

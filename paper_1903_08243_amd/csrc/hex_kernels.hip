@@ -28,8 +28,6 @@
 #include "mf_internal.h"
 #include "hex_tables.inc"
 
-#include <map>
-#include <mutex>
 
 namespace mf {
 
@@ -70,11 +68,10 @@ template <int N, bool GRAD> constexpr int hex_lds_size() {
   return hex_epb<N>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32);
 }
 
-// Processes cell batches b, b+G, b+2G, ... < nb (EPB cells each) of one operator on
-// the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
+// Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
+// on the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
 template <typename T, int N, int KIND, bool ATOMIC>
-__device__ __forceinline__ void hex_cells(const HexArgs<T> &A, int64_t b, const int64_t G, const int64_t nb,
-                                          T *lds) {
+__device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, T *lds) {
   using TB = TabT<T, N>;
   constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N>();
   constexpr bool GRAD = KIND != K_MASS;
@@ -93,60 +90,33 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, int64_t b, const 
   const int le = tt / NN, p = tt - le * NN;
   const int pa = p % N, pb = p / N;
   const int nc = A.ncomp;
-  if (b >= nb) return;  // whole workgroup (= one wavefront)
 
-  // Work items are (batch, component) pairs, batches b, b+G, b+2G, ... for this
-  // wavefront. The gathers of the next item, the map of the batch after next and
-  // the geometry of the next batch are issued before the current item's
-  // arithmetic, so their memory latency overlaps it.
-  constexpr int GL = (EPB * 32 + 63) / 64;  // geometry values staged per lane
-  auto load_idx = [&](int64_t bb, int *idx) {
-    const int64_t c = A.c0 + bb * EPB + le;
-    bool ok = bb < nb && c < A.c1;
+  // One batch of EPB cells per call: map, geometry and the first component's
+  // gathers are issued together, then each component is processed in turn.
+  int idx_cur[N];
+  {
+    const int64_t c = A.c0 + b * EPB + le;
+    bool ok = c < A.c1;
     if (ok && A.cell_user) {
       const int64_t u = A.cell_user[c];
       ok = u >= A.ulo && u < A.uhi;
     }
     const int32_t *cm = A.map + (ok ? c : A.c0) * N3;
 #pragma unroll
-    for (int l = 0; l < N; l++) idx[l] = ok ? cm[pa + N * pb + NN * l] : -1;
-  };
-  auto gather = [&](const int *idx, int comp, T *r) {
-#pragma unroll
-    for (int l = 0; l < N; l++) r[l] = idx[l] >= 0 ? A.x[(int64_t)idx[l] * nc + comp] : T(0);
-  };
-  auto load_geo = [&](int64_t bb, T *g) {
-#pragma unroll
-    for (int q = 0; q < GL; q++) {
-      const int i = t + 64 * q;
-      const int e = i >> 5, j = i & 31;
-      const int64_t c = A.c0 + bb * EPB + e;
-      T v = T(0);
-      if (i < EPB * 32 && bb < nb && c < A.c1) {
-        if (j < 24) v = A.geo[c * 24 + j];
-        else if (COEF && A.coef) v = A.coef[c * 8 + (j - 24)];
-        else if (j == 24) v = T(1);  // coefficient 1 when absent
-      } else if (j == 0 || j == 4 || j == 8) {
-        v = T(1);  // cells past the end: unit-cube geometry keeps the arithmetic finite
-      }
-      g[q] = v;
+    for (int l = 0; l < N; l++) idx_cur[l] = ok ? cm[pa + N * pb + NN * l] : -1;
+  }
+  for (int i = t; i < EPB * 32; i += 64) {
+    const int e = i >> 5, j = i & 31;
+    const int64_t c = A.c0 + b * EPB + e;
+    T v = T(0);
+    if (c < A.c1) {
+      if (j < 24) v = A.geo[c * 24 + j];
+      else if (COEF && A.coef) v = A.coef[c * 8 + (j - 24)];
+      else if (j == 24) v = T(1);  // coefficient 1 when absent
+    } else if (j == 0 || j == 4 || j == 8) {
+      v = T(1);  // cells past the end: unit-cube geometry keeps the arithmetic finite
     }
-  };
-  auto store_geo = [&](const T *g) {
-#pragma unroll
-    for (int q = 0; q < GL; q++)
-      if (t + 64 * q < EPB * 32) sg[t + 64 * q] = g[q];
-  };
-
-  int idx_cur[N], idx_n1[N];
-  T r_cur[N];
-  load_idx(b, idx_cur);
-  load_idx(b + G, idx_n1);
-  gather(idx_cur, 0, r_cur);
-  {
-    T g[GL];
-    load_geo(b, g);
-    store_geo(g);
+    sg[i] = v;
   }
   __syncthreads();
 
@@ -156,13 +126,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, int64_t b, const 
   const T *Gc = sg + le * 32;
   const T x1 = TB::g(pa), x2 = TB::g(pb);
   const T wab = TB::w(pa) * TB::w(pb);
-
-  for (; b < nb; b += G) {
-    int idx_n2[N];
-    load_idx(b + 2 * G, idx_n2);
-    T g_nx[GL];
-    load_geo(b + G, g_nx);
-
+  {
     // Per-thread geometry for the pointwise stage: this thread owns points (pa, pb, *).
     T A1[3], B1[3], A2[3], B2[3], A3[3];
 #pragma unroll
@@ -183,9 +147,9 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, int64_t b, const 
     }
 
     for (int comp = 0; comp < nc; comp++) {
-      T r_nx[N], yv[N];
-      if (comp + 1 < nc) gather(idx_cur, comp + 1, r_nx);
-      else gather(idx_n1, 0, r_nx);
+      T yv[N], r_cur[N];
+#pragma unroll
+      for (int l = 0; l < N; l++) r_cur[l] = idx_cur[l] >= 0 ? A.x[(int64_t)idx_cur[l] * nc + comp] : T(0);
       if constexpr (!ATOMIC) {
         // no other cell of this launch touches these nodes: read y now, write it at the end
 #pragma unroll
@@ -371,17 +335,8 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, int64_t b, const 
         }
       }
 
-#pragma unroll
-      for (int l = 0; l < N; l++) r_cur[l] = r_nx[l];
       __syncthreads();
     }
-#pragma unroll
-    for (int l = 0; l < N; l++) {
-      idx_cur[l] = idx_n1[l];
-      idx_n1[l] = idx_n2[l];
-    }
-    store_geo(g_nx);
-    __syncthreads();
   }
 }
 
@@ -391,7 +346,7 @@ template <typename T, int N, int KIND, bool ATOMIC>
 __global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
   __shared__ T lds[hex_lds_size<N, KIND != K_MASS>()];
   const int64_t nb = (A.c1 - A.c0 + hex_epb<N>() - 1) / hex_epb<N>();  // cell batches
-  hex_cells<T, N, KIND, ATOMIC>(A, blockIdx.x, gridDim.x, nb, lds);
+  if ((int64_t)blockIdx.x < nb) hex_cells<T, N, KIND, ATOMIC>(A, blockIdx.x, lds);
 }
 
 // ---------------------------------------------------------------------------------- batched apply
@@ -409,46 +364,71 @@ struct HexBatchItem {
   int64_t b0, b1;  // cell batches [b0, b1) of the operator (EPB(N) cells each)
 };
 
-template <typename T, int KIND>
+template <typename T, int KIND, bool PERSIST>
 __global__ void __launch_bounds__(64) hex_batch_kernel(const HexBatchOp<T> *__restrict__ ops,
                                                        const HexBatchItem *__restrict__ items, int nitems,
                                                        const int *__restrict__ stop, int stop_stride) {
   constexpr bool GRAD = KIND != K_MASS;
   constexpr int L2 = hex_lds_size<2, GRAD>(), L3 = hex_lds_size<3, GRAD>(), L4 = hex_lds_size<4, GRAD>(),
                 L5 = hex_lds_size<5, GRAD>(), L6 = hex_lds_size<6, GRAD>();
-  constexpr int LM = L2 > L3 ? (L2 > L4 ? (L2 > L5 ? (L2 > L6 ? L2 : L6) : (L5 > L6 ? L5 : L6))
-                                        : (L4 > L5 ? (L4 > L6 ? L4 : L6) : (L5 > L6 ? L5 : L6)))
-                             : (L3 > L4 ? (L3 > L5 ? (L3 > L6 ? L3 : L6) : (L5 > L6 ? L5 : L6))
-                                        : (L4 > L5 ? (L4 > L6 ? L4 : L6) : (L5 > L6 ? L5 : L6)));
+  constexpr int LA = L2 > L3 ? L2 : L3, LB = L4 > L5 ? L4 : L5, LC = LA > LB ? LA : LB;
+  constexpr int LM = LC > L6 ? LC : L6;
   __shared__ T lds[LM];
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-    const HexBatchItem w = items[it];
-    if (stop && stop[(int64_t)w.op * stop_stride]) continue;
+  if constexpr (PERSIST) {
+    // wavefronts stride over the work list and the batch ranges of their items
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+      const HexBatchItem w = items[it];
+      if (stop && stop[(int64_t)w.op * stop_stride]) continue;
+      const HexArgs<T> A = ops[w.op].a;
+      for (int64_t b = w.b0; b < w.b1; b++) {
+        switch (ops[w.op].N) {
+          case 2: hex_cells<T, 2, KIND, true>(A, b, lds); break;
+          case 3: hex_cells<T, 3, KIND, true>(A, b, lds); break;
+          case 4: hex_cells<T, 4, KIND, true>(A, b, lds); break;
+          case 5: hex_cells<T, 5, KIND, true>(A, b, lds); break;
+          case 6: hex_cells<T, 6, KIND, true>(A, b, lds); break;
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    // one wavefront per single-batch item: no loop, so the compiler keeps the
+    // tables as rematerialised constants instead of loop-invariant registers
+    if ((int)blockIdx.x >= nitems) return;
+    const HexBatchItem w = items[blockIdx.x];
+    if (stop && stop[(int64_t)w.op * stop_stride]) return;
     const HexArgs<T> A = ops[w.op].a;
     switch (ops[w.op].N) {
-      case 2: hex_cells<T, 2, KIND, true>(A, w.b0, 1, w.b1, lds); break;
-      case 3: hex_cells<T, 3, KIND, true>(A, w.b0, 1, w.b1, lds); break;
-      case 4: hex_cells<T, 4, KIND, true>(A, w.b0, 1, w.b1, lds); break;
-      case 5: hex_cells<T, 5, KIND, true>(A, w.b0, 1, w.b1, lds); break;
-      case 6: hex_cells<T, 6, KIND, true>(A, w.b0, 1, w.b1, lds); break;
+      case 2: hex_cells<T, 2, KIND, true>(A, w.b0, lds); break;
+      case 3: hex_cells<T, 3, KIND, true>(A, w.b0, lds); break;
+      case 4: hex_cells<T, 4, KIND, true>(A, w.b0, lds); break;
+      case 5: hex_cells<T, 5, KIND, true>(A, w.b0, lds); break;
+      case 6: hex_cells<T, 6, KIND, true>(A, w.b0, lds); break;
     }
-    __syncthreads();
   }
 }
 
+// grid <= 0: one wavefront per work item (items must then hold one batch each);
+// grid > 0: a persistent grid of that many wavefronts.
 template <typename T>
 int launch_hex_batch(int kind, const void *ops, const void *items, int nitems, int grid, const int *stop,
                      int stop_stride, hipStream_t s) {
   if (nitems <= 0) return MF_OK;
   const HexBatchOp<T> *o = (const HexBatchOp<T> *)ops;
   const HexBatchItem *w = (const HexBatchItem *)items;
+  const bool persist = grid > 0;
+  const unsigned g = persist ? (unsigned)grid : (unsigned)nitems;
+#define MF_BATCH_LAUNCH(K)                                                                    \
+  if (persist) hex_batch_kernel<T, K, true><<<g, 64, 0, s>>>(o, w, nitems, stop, stop_stride); \
+  else hex_batch_kernel<T, K, false><<<g, 64, 0, s>>>(o, w, nitems, stop, stop_stride);
   switch (kind) {
-    case K_MASS: hex_batch_kernel<T, K_MASS><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
-    case K_HELM: hex_batch_kernel<T, K_HELM><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
-    case K_LAP: hex_batch_kernel<T, K_LAP><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
-    case K_POIS: hex_batch_kernel<T, K_POIS><<<grid, 64, 0, s>>>(o, w, nitems, stop, stop_stride); break;
+    case K_MASS: MF_BATCH_LAUNCH(K_MASS) break;
+    case K_HELM: MF_BATCH_LAUNCH(K_HELM) break;
+    case K_LAP: MF_BATCH_LAUNCH(K_LAP) break;
+    case K_POIS: MF_BATCH_LAUNCH(K_POIS) break;
     default: return fail(MF_EUNSUPPORTED, "batched kernel: operator kind");
   }
+#undef MF_BATCH_LAUNCH
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
@@ -538,25 +518,6 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------------- launchers
-// Number of 64-thread workgroups of `fn` that fit on the device at once.
-static int64_t resident_waves(const void *fn) {
-  static std::mutex mu;
-  static std::map<const void *, int64_t> cache;
-  std::lock_guard<std::mutex> lock(mu);
-  auto it = cache.find(fn);
-  if (it != cache.end()) return it->second;
-  int dev = 0, cus = 0, per_cu = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64, 0) != hipSuccess || per_cu <= 0) {
-    (void)hipGetLastError();
-    cus = 256;
-    per_cu = 8;
-  }
-  const int64_t r = (int64_t)cus * per_cu;
-  cache[fn] = r;
-  return r;
-}
-
 template <typename T, int N, bool AT>
 static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
   constexpr int EPB = hex_epb<N>();
@@ -571,9 +532,8 @@ static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
     case K_POIS: fn = (void *)hex_apply_kernel<T, N, K_POIS, AT>; break;
     default: return fail(MF_EUNSUPPORTED, "hex kernel: operator kind");
   }
-  // persistent grid: as many wavefronts as can be resident at once (cached per kernel)
-  const int64_t resident = resident_waves(fn);
-  dim3 grid((unsigned)(nb < resident ? nb : resident)), block(64);
+  (void)fn;
+  dim3 grid((unsigned)nb), block(64);  // one cell batch per wavefront
   switch (kind) {
     case K_MASS: hex_apply_kernel<T, N, K_MASS, AT><<<grid, block, 0, s>>>(a); break;
     case K_HELM: hex_apply_kernel<T, N, K_HELM, AT><<<grid, block, 0, s>>>(a); break;
