@@ -197,6 +197,28 @@ def bench_c4(mf, mg, nsys=64, seed=0):
     return out
 
 
+def profile_kernel(mf, mg):
+    """The dominant kernel of the headline step (FP64 3-component Laplacian, Q6, 32^3)
+    launched 10 times on internally numbered vectors, then a plain 256 MiB device copy
+    10 times: the copy's counter reading per byte calibrates the HBM traffic counters."""
+    import torch
+    mesh = mg.hex_mesh(32, 0.15, config=1, seed_k=6)
+    space = mg.hex_space(mesh, 6, ncomp=3, config=1)
+    op = mf.Operator(mf.Space.from_meshgen(space), mf.LAPLACIAN, mf.F64)
+    x = torch.tensor(mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, 6), device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(10):
+        op.apply_internal(x, y)
+    a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profiled": "laplacian3-Q6 fp64 x10, copy 256MiB x10", "flops_per_apply": op.info["flops_per_apply"],
+                      "bytes_per_apply": op.info["bytes_per_apply"],
+                      "cell_launches_per_apply": op.info["cell_launches"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -204,6 +226,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="degrees 1..3 only (debugging)")
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched 64-system solves")
+    ap.add_argument("--profile-kernel", action="store_true",
+                    help="only run the dominant action kernel 10 times and a 256 MiB reference copy "
+                         "(for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design "
@@ -216,6 +242,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     mf.load_library()
+    if args.profile_kernel:
+        profile_kernel(mf, mg)
+        return
     degrees = [1, 2, 3] if args.quick else [1, 2, 3, 4, 5, 6]
     kinds = [("helmholtz", mf.HELMHOLTZ, 1), ("laplacian3", mf.LAPLACIAN, 3), ("laplacian1", mf.LAPLACIAN, 1)]
     log("building headline operators ...")
@@ -274,17 +303,20 @@ def main():
     dom = cases[dom_i]
     op, x, y = dom["ops"][mf.F64]
     t_dom = per[dom_i]["fp64"]["us"] * 1e-6
+    nl = op.info["cell_launches"]  # equal-size colour launches share the action's work evenly
     r = roof(op, t_dom, 0)
     if r["bound"] == "alu":
         roofline = {"bound": "alu", "achieved": r["flops"] / t_dom / 1e12, "peak": PEAK_FP64 / 1e12,
                     "unit": "TFLOP/s", "frac": r["flops"] / t_dom / PEAK_FP64, "traffic": None,
                     "kernel": f"hex_apply_kernel<double,{dom['k'] + 1},{dom['kind']}> ({dom['name']})",
-                    "flops_per_launch": r["flops"], "bytes_per_launch": r["bytes"], "launch_us": t_dom * 1e6}
+                    "flops_per_launch": r["flops"] / nl, "bytes_per_launch": r["bytes"] / nl,
+                    "launch_us": t_dom * 1e6 / nl, "launches_per_apply": nl}
     else:
         roofline = {"bound": "hbm", "achieved": r["bytes"] / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                     "frac": r["bytes"] / t_dom / PEAK_HBM, "traffic": None,
                     "kernel": f"hex_apply_kernel<double,{dom['k'] + 1},{dom['kind']}> ({dom['name']})",
-                    "flops_per_launch": r["flops"], "bytes_per_launch": r["bytes"], "launch_us": t_dom * 1e6}
+                    "flops_per_launch": r["flops"] / nl, "bytes_per_launch": r["bytes"] / nl,
+                    "launch_us": t_dom * 1e6 / nl, "launches_per_apply": nl}
 
     extra = {}
     try:
@@ -298,7 +330,7 @@ def main():
         cpu = cpu_baseline(mg, cases)
         log(f"  cpu oracle: {cpu['value']:.4f} GDoF/s on {cpu['cores']} threads")
     n_ops = len(cases)
-    if not args.quick:
+    if not args.quick and not args.no_c4:
         del cases  # free the headline operators before the batched workload
         torch.cuda.empty_cache()
         try:

@@ -97,7 +97,7 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             share no node; a full apply is one launch per colour with plain
  *             read-modify-write stores -- deterministic, bit-reproducible.
  *   ATOMIC    one launch, device-scope floating-point atomics.
- *   AUTO      COLOURED for 3-component hex operators of degree >= 3 on meshes
+ *   AUTO      COLOURED for 3-component hex operators of degree >= 2 on meshes
  *             of at least 4096 cells (where it measured faster), else ATOMIC.
  * Range applies (mf_op_apply_range*) always use ATOMIC. */
 enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2 };
@@ -163,8 +163,10 @@ typedef struct {
   int64_t ncells, nnodes, ndofs;
   int cell_type, kind, precision, degree, ncomp, nq1d, nqp;
   int dofs_per_cell;      /* D (nodes per cell) */
-  double flops_per_apply; /* algorithmic flops of one mf_op_apply */
-  double bytes_per_apply; /* algorithmic HBM bytes of one mf_op_apply (perfect caching) */
+  double flops_per_apply; /* algorithmic flops of one operator action */
+  double bytes_per_apply; /* algorithmic HBM bytes of one action (perfect caching) */
+  int cell_launches;      /* cell-kernel launches per full action (colours, or 1) */
+  int ncolours;           /* colours of the space's cell colouring */
 } mf_op_info;
 
 int mf_op_get_info(const mf_op *op, mf_op_info *info);
@@ -188,7 +190,9 @@ int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out);
  * A32 != NULL: iterative refinement -- the outer loop forms r = b - A64 x in
  * FP64 and stops when ||r||/||b|| <= rtol; each inner solve runs preconditioned
  * CG on A32 d = r with the FP32 action (FP64 vectors, dot products and
- * updates) to relative tolerance inner_rtol (0 -> 1e-4), then x += d.
+ * updates) to relative tolerance max(inner_rtol, rtol ||b|| / ||r||) -- the
+ * final target, floored at inner_rtol (0 -> 1e-6, the FP32 action's accuracy)
+ * -- then x += d.
  * x holds the initial guess on entry. Synchronous. info may be NULL.
  * Errors: MF_ENOTCONV (maxit total inner iterations reached; x holds the last
  * iterate, info filled), MF_EBREAKDOWN (non-finite residual or p'Ap <= 0). */

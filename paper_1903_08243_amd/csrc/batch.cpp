@@ -88,8 +88,11 @@ static int upload_ops(mf::DeviceBuffer &buf, const std::vector<HostBatchOp<T>> &
   return MF_OK;
 }
 
-// Work list: every system's cell batches split into items of `per` batches,
-// interleaved across systems so that concurrent wavefronts work on different operators.
+// Work list: every system's cell batches split into items of `per` batches. System
+// after system for the one-wavefront-per-item launch (which hands each XCD a
+// contiguous range, so an operator's neighbouring cells share one L2); interleaved
+// across systems for the persistent launch, so concurrent wavefronts spread over
+// the operators.
 static int build_items(mf_batch *B, int per) {
   std::vector<std::vector<HostBatchItem>> lists(B->nsys);
   size_t longest = 0;
@@ -101,9 +104,13 @@ static int build_items(mf_batch *B, int per) {
     longest = std::max(longest, lists[i].size());
   }
   std::vector<HostBatchItem> items;
-  for (size_t j = 0; j < longest; j++)
-    for (int i = 0; i < B->nsys; i++)
-      if (j < lists[i].size()) items.push_back(lists[i][j]);
+  if (B->grid == 0) {
+    for (int i = 0; i < B->nsys; i++) items.insert(items.end(), lists[i].begin(), lists[i].end());
+  } else {
+    for (size_t j = 0; j < longest; j++)
+      for (int i = 0; i < B->nsys; i++)
+        if (j < lists[i].size()) items.push_back(lists[i][j]);
+  }
   int rc = B->items.alloc(items.size() * sizeof(HostBatchItem));
   if (rc) return rc;
   MF_HIP(hipMemcpyAsync(B->items.ptr, items.data(), items.size() * sizeof(HostBatchItem), hipMemcpyHostToDevice, B->s));
@@ -356,11 +363,11 @@ int mf_batch_autotune(mf_batch *B, const char *cache_path, void *stream) {
   int best_per = 1, best_grid = 0;
   const bool a32 = B->refine;
   for (int per : pers) {
-    int rc = build_items(B, per);
-    if (rc) return rc;
     for (int64_t g : grids) {
       if (g == 0 && per != 1) continue;
       B->grid = (int)g;
+      int rc = build_items(B, per);
+      if (rc) return rc;
       for (int w = 0; w < 2; w++)
         if ((rc = batch_apply(B, B->ops_in, a32 ? MF_F32 : MF_F64, a32 ? B->Ap32.ptr : B->Ap.ptr, nullptr))) return rc;
       MF_HIP(hipEventRecord(e0, B->s));
@@ -417,7 +424,7 @@ int mf_batch_solve(mf_batch *B, double rtol, double inner_rtol, int maxit, mf_cg
   std::vector<double> bb(ns), rr(ns);
   std::vector<int> outer(ns, 0), inner(ns, 0), done(ns, 0);
   for (int i = 0; i < ns; i++) bb[i] = B->host_st[i].rr;
-  const double irt = inner_rtol > 0.0 ? inner_rtol : 1e-4;
+  const double floor_rt = inner_rtol > 0.0 ? inner_rtol : 1e-6;  // see mf_cg_solve
   int status = MF_OK;
   int total_inner = 0;
   for (int it = 0; it < 100; it++) {
@@ -436,6 +443,7 @@ int mf_batch_solve(mf_batch *B, double rtol, double inner_rtol, int maxit, mf_cg
     // inner solves A d = r from d = 0 (all systems together); converged systems stop at once
     for (int i = 0; i < ns; i++) {
       CgState S{};
+      const double irt = std::max(floor_rt, std::sqrt(rtol * rtol * bb[i] / std::max(rr[i], 1e-300)));
       S.tol2 = done[i] ? DBL_MAX : (B->refine ? irt * irt * rr[i] : rtol * rtol * bb[i]);
       S.maxit = maxit - total_inner;
       B->host_st[i] = S;

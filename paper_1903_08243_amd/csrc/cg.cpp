@@ -11,6 +11,7 @@
 // private stream and replayed; the host reads the 64-byte state after each
 // replay to test convergence. Iterations after convergence are no-ops
 // (alpha = beta = 0), so a partially used chunk is harmless.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -37,8 +38,9 @@ struct CgWork {
   }
 };
 
-// all solver vectors live in the operators' internal numbering
-static int apply_any(const mf_op *A, const void *x, void *y, hipStream_t s) { return op_apply_internal(A, x, y, s); }
+// all solver vectors live in the operators' internal numbering; the output was
+// cleared by the preceding vector kernel, so the action accumulates
+static int apply_any(const mf_op *A, const void *x, void *y, hipStream_t s) { return op_apply_internal_acc(A, x, y, s); }
 
 // One chunk of PCG iterations on operator A (FP64 or FP32 action), recorded on w.s.
 static int record_chunk(const mf_op *A, const double *dinv, double *x, CgWork &w) {
@@ -91,7 +93,7 @@ static int pcg_core(const mf_op *A, const double *dinv, double *x, double tol2, 
   *w.host_st = init;
   MF_HIP(hipMemcpyAsync(w.st.ptr, w.host_st, sizeof(CgState), hipMemcpyHostToDevice, w.s));
   int rc = cg_init(w.r.as<double>(), dinv, w.p.as<double>(), a32 ? w.p32.as<float>() : nullptr, w.n,
-                   w.part.as<double>(), w.st.as<CgState>(), w.s);
+                   w.part.as<double>(), w.st.as<CgState>(), w.s, a32 ? w.Ap32.ptr : w.Ap.ptr);
   if (rc) return rc;
   rc = read_state(w, out);
   if (rc || out.stop || maxit <= 0) return rc;
@@ -233,12 +235,17 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
       if (rc) return rc;
     }
   } else {
-    const double irt = inner_rtol > 0.0 ? inner_rtol : 1e-4;
+    // Inner tolerance: aim straight at the final target, but not below the FP32
+    // action's accuracy floor (inner_rtol, default 1e-6): the first inner solve
+    // then removes six orders of magnitude and the next one the rest, so little
+    // Krylov information is lost to restarts.
+    const double floor_rt = inner_rtol > 0.0 ? inner_rtol : 1e-6;
     for (int outer = 0; outer < 100; outer++) {
       rc = residual(A64, b, x, w, rr);
       if (rc) return rc;
       inf.outer_iterations++;
       if (rr <= tol2 || !(rr == rr) || inf.inner_iterations >= maxit) break;
+      const double irt = std::max(floor_rt, std::sqrt(tol2 / rr));
       // inner: A32 d = r from d = 0, FP64 vectors
       rc = launch_fill<double>(w.d.as<double>(), 0.0, n, w.s);
       if (rc) return rc;

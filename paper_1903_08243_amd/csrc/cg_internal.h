@@ -18,9 +18,13 @@ struct CgState {
 
 int cg_residual(const double *b, const void *Ax, bool ax32, double *r, int64_t n, double *part, CgState *st,
                 hipStream_t s);
+// z = M^-1 r, p = z (+ FP32 copy), r'z and r'r; ap_zero (nullable, FP32 when p32 is set)
+// is cleared for the next accumulating action
 int cg_init(const double *r, const double *dinv, double *p, float *p32, int64_t n, double *part, CgState *st,
-            hipStream_t s);
-int cg_step_after_apply(double *x, double *r, double *p, float *p32, const void *Ap, bool ap32, const double *dinv,
+            hipStream_t s, void *ap_zero);
+// after Ap = A p: alpha, x += alpha p, r -= alpha Ap, beta, p = z + beta p; Ap is cleared
+// for the next accumulating action
+int cg_step_after_apply(double *x, double *r, double *p, float *p32, void *Ap, bool ap32, const double *dinv,
                         int64_t n, double *part, CgState *st, hipStream_t s);
 int cg_axpy(double *x, const double *d, int64_t n, hipStream_t s);
 int cg_recip(const void *d, bool d32, double *dinv, int64_t n, hipStream_t s);

@@ -43,14 +43,19 @@ __global__ void __launch_bounds__(RB) residual_kernel(const double *__restrict__
 // z = M^{-1} r (dinv == null: identity), p = z (and its FP32 copy), partials r'z and r'r.
 __global__ void __launch_bounds__(RB) init_p_kernel(const double *__restrict__ r, const double *__restrict__ dinv,
                                                     double *__restrict__ p, float *__restrict__ p32, int64_t n,
-                                                    double *__restrict__ part) {
+                                                    double *__restrict__ part, void *__restrict__ ap_zero) {
   __shared__ double sh[RB / 64];
   double s1 = 0.0, s2 = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
     const double ri = r[i];
     const double z = dinv ? dinv[i] * ri : ri;
     p[i] = z;
-    if (p32) p32[i] = (float)z;
+    if (p32) {
+      p32[i] = (float)z;
+      if (ap_zero) ((float *)ap_zero)[i] = 0.0f;
+    } else if (ap_zero) {
+      ((double *)ap_zero)[i] = 0.0;
+    }
     s1 += ri * z;
     s2 += ri * ri;
   }
@@ -98,16 +103,23 @@ __global__ void __launch_bounds__(RB) update_kernel(double *__restrict__ x, doub
   }
 }
 
-// p = M^{-1} r + beta p (and the FP32 copy for the next FP32 action)
+// p = M^{-1} r + beta p (and the FP32 copy for the next FP32 action); the output of
+// the next (accumulating) action is cleared in the same pass
 __global__ void __launch_bounds__(RB) p_update_kernel(double *__restrict__ p, float *__restrict__ p32,
                                                       const double *__restrict__ r, const double *__restrict__ dinv,
-                                                      const CgState *__restrict__ st, int64_t n) {
+                                                      const CgState *__restrict__ st, int64_t n,
+                                                      void *__restrict__ ap_zero) {
   const double beta = st->beta;
   for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
     const double z = dinv ? dinv[i] * r[i] : r[i];
     const double v = z + beta * p[i];
     p[i] = v;
-    if (p32) p32[i] = (float)v;
+    if (p32) {
+      p32[i] = (float)v;
+      ((float *)ap_zero)[i] = 0.0f;
+    } else {
+      ((double *)ap_zero)[i] = 0.0;
+    }
   }
 }
 
@@ -130,6 +142,8 @@ __global__ void __launch_bounds__(RB) finalize_kernel(const double *__restrict__
                                                       int stage) {
   __shared__ double sh[RB / 64];
   const int nsum = (stage == CG_STAGE_UPDATE || stage == CG_STAGE_INIT) ? 2 : 1;
+  CgState S;
+  if (threadIdx.x == 0) S = *st;  // issued together with the partial loads below
   double tot[2] = {0.0, 0.0};
   for (int k = 0; k < nsum; k++) {
     double s = 0.0;
@@ -137,7 +151,6 @@ __global__ void __launch_bounds__(RB) finalize_kernel(const double *__restrict__
     tot[k] = block_sum(s, sh);
   }
   if (threadIdx.x != 0) return;
-  CgState S = *st;
   switch (stage) {
     case CG_STAGE_RESIDUAL:  // tot0 = r'r
       S.rr = tot[0];
@@ -201,15 +214,15 @@ int cg_residual(const double *b, const void *Ax, bool ax32, double *r, int64_t n
 }
 
 int cg_init(const double *r, const double *dinv, double *p, float *p32, int64_t n, double *part, CgState *st,
-            hipStream_t s) {
+            hipStream_t s, void *ap_zero) {
   const unsigned g = grid_n(n);
-  init_p_kernel<<<g, RB, 0, s>>>(r, dinv, p, p32, n, part);
+  init_p_kernel<<<g, RB, 0, s>>>(r, dinv, p, p32, n, part, ap_zero);
   finalize_kernel<<<1, RB, 0, s>>>(part, (int)g, st, CG_STAGE_INIT);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
 
-int cg_step_after_apply(double *x, double *r, double *p, float *p32, const void *Ap, bool ap32, const double *dinv,
+int cg_step_after_apply(double *x, double *r, double *p, float *p32, void *Ap, bool ap32, const double *dinv,
                         int64_t n, double *part, CgState *st, hipStream_t s) {
   const unsigned g = grid_n(n);
   if (ap32) dot_kernel<float><<<g, RB, 0, s>>>(p, (const float *)Ap, n, part);
@@ -218,7 +231,7 @@ int cg_step_after_apply(double *x, double *r, double *p, float *p32, const void 
   if (ap32) update_kernel<float><<<g, RB, 0, s>>>(x, r, p, (const float *)Ap, dinv, st, n, part);
   else update_kernel<double><<<g, RB, 0, s>>>(x, r, p, (const double *)Ap, dinv, st, n, part);
   finalize_kernel<<<1, RB, 0, s>>>(part, (int)g, st, CG_STAGE_UPDATE);
-  p_update_kernel<<<g, RB, 0, s>>>(p, p32, r, dinv, st, n);
+  p_update_kernel<<<g, RB, 0, s>>>(p, p32, r, dinv, st, n, Ap);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }

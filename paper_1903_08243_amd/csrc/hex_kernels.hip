@@ -62,6 +62,18 @@ template <> struct HexLds<6> { static constexpr int SY = 9, SZ = 54, SE = 324; }
 template <> struct HexLds<7> { static constexpr int SY = 7, SZ = 52, SE = 364; };
 
 // ---------------------------------------------------------------------------------- apply
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each with its
+// own L2. Mapping workgroup w to batch (w % 8) * ceil(nb / 8) + w / 8 gives every
+// XCD one contiguous range of cell batches, so the nodes neighbouring cells share
+// (and the cache lines around them) are fetched into one L2 instead of several.
+// The grid must hold 8 * ceil(nb / 8) workgroups; results >= nb are idle.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_batch(int64_t w, int64_t nb) {
+  const int64_t per = (nb + kXcds - 1) / kXcds;
+  return (w % kXcds) * per + w / kXcds;
+}
+inline int64_t xcd_grid(int64_t nb) { return ((nb + kXcds - 1) / kXcds) * kXcds; }
+
 // LDS (in units of T) one wavefront needs for degree n-1: three padded n^3 buffers
 // per cell (one without gradients) and 32 geometry values per cell.
 template <int N, bool GRAD> constexpr int hex_lds_size() {
@@ -346,7 +358,8 @@ template <typename T, int N, int KIND, bool ATOMIC>
 __global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
   __shared__ T lds[hex_lds_size<N, KIND != K_MASS>()];
   const int64_t nb = (A.c1 - A.c0 + hex_epb<N>() - 1) / hex_epb<N>();  // cell batches
-  if ((int64_t)blockIdx.x < nb) hex_cells<T, N, KIND, ATOMIC>(A, blockIdx.x, lds);
+  const int64_t b = xcd_batch(blockIdx.x, nb);
+  if (b < nb) hex_cells<T, N, KIND, ATOMIC>(A, b, lds);
 }
 
 // ---------------------------------------------------------------------------------- batched apply
@@ -394,8 +407,9 @@ __global__ void __launch_bounds__(64) hex_batch_kernel(const HexBatchOp<T> *__re
   } else {
     // one wavefront per single-batch item: no loop, so the compiler keeps the
     // tables as rematerialised constants instead of loop-invariant registers
-    if ((int)blockIdx.x >= nitems) return;
-    const HexBatchItem w = items[blockIdx.x];
+    const int64_t wi = xcd_batch(blockIdx.x, nitems);  // contiguous item ranges per XCD
+    if (wi >= nitems) return;
+    const HexBatchItem w = items[wi];
     if (stop && stop[(int64_t)w.op * stop_stride]) return;
     const HexArgs<T> A = ops[w.op].a;
     switch (ops[w.op].N) {
@@ -417,7 +431,7 @@ int launch_hex_batch(int kind, const void *ops, const void *items, int nitems, i
   const HexBatchOp<T> *o = (const HexBatchOp<T> *)ops;
   const HexBatchItem *w = (const HexBatchItem *)items;
   const bool persist = grid > 0;
-  const unsigned g = persist ? (unsigned)grid : (unsigned)nitems;
+  const unsigned g = persist ? (unsigned)grid : (unsigned)xcd_grid(nitems);
 #define MF_BATCH_LAUNCH(K)                                                                    \
   if (persist) hex_batch_kernel<T, K, true><<<g, 64, 0, s>>>(o, w, nitems, stop, stop_stride); \
   else hex_batch_kernel<T, K, false><<<g, 64, 0, s>>>(o, w, nitems, stop, stop_stride);
@@ -533,7 +547,7 @@ static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
     default: return fail(MF_EUNSUPPORTED, "hex kernel: operator kind");
   }
   (void)fn;
-  dim3 grid((unsigned)nb), block(64);  // one cell batch per wavefront
+  dim3 grid((unsigned)xcd_grid(nb)), block(64);  // one cell batch per wavefront
   switch (kind) {
     case K_MASS: hex_apply_kernel<T, N, K_MASS, AT><<<grid, block, 0, s>>>(a); break;
     case K_HELM: hex_apply_kernel<T, N, K_HELM, AT><<<grid, block, 0, s>>>(a); break;

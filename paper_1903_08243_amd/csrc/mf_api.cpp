@@ -439,9 +439,9 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
 // Coloured launches avoid device-scope float atomics but cost one launch per
 // colour with 1/ncolours of the cells each. Measured on MI355X (32^3 hex), the
 // single atomic launch is faster for scalar operators; the coloured launches win
-// for 3-component operators from Q3 up (three atomics per node otherwise).
+// for 3-component operators from Q2 up (three atomics per node otherwise).
 static bool default_coloured(const mf_op *op) {
-  return op->cell_type == MF_CELL_HEX && op->ncomp == 3 && op->degree >= 3 && op->ncells >= 4096;
+  return op->cell_type == MF_CELL_HEX && op->ncomp == 3 && op->degree >= 2 && op->ncells >= 4096;
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
@@ -593,6 +593,12 @@ int op_apply_internal(const mf_op *op, const void *x, void *y, hipStream_t s) {
              : op_apply_t<float>(op, 0, op->ncells, (const float *)x, (float *)y, false, true, s);
 }
 
+int op_apply_internal_acc(const mf_op *op, const void *x, void *y, hipStream_t s) {
+  return op->precision == MF_F64
+             ? op_apply_t<double>(op, 0, op->ncells, (const double *)x, (double *)y, true, true, s)
+             : op_apply_t<float>(op, 0, op->ncells, (const float *)x, (float *)y, true, true, s);
+}
+
 int op_diagonal_internal(const mf_op *op, void *d, hipStream_t s) {
   return op->precision == MF_F64 ? op_diag_t<double>(op, (double *)d, s) : op_diag_t<float>(op, (float *)d, s);
 }
@@ -659,6 +665,8 @@ int mf_op_get_info(const mf_op *op, mf_op_info *info) {
   info->dofs_per_cell = op->D;
   info->flops_per_apply = op->flops;
   info->bytes_per_apply = op->bytes;
+  info->ncolours = (int)op->colour_ptr.size() - 1;
+  info->cell_launches = op->coloured ? info->ncolours : 1;
   return MF_OK;
 }
 

@@ -148,6 +148,8 @@ int launch_from_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *yi
 namespace mf {
 // Internal-numbering entry points used by the solvers.
 int op_apply_internal(const mf_op *op, const void *x, void *y, hipStream_t s);
+// y += A x (internal numbering, y not cleared), then the constraint rows y_b = x_b
+int op_apply_internal_acc(const mf_op *op, const void *x, void *y, hipStream_t s);
 int op_diagonal_internal(const mf_op *op, void *d, hipStream_t s);
 }  // namespace mf
 

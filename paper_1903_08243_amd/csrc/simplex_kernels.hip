@@ -31,7 +31,11 @@ __global__ void __launch_bounds__(192) tet_elasticity_kernel(const TetArgs<T> A)
   constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
   __shared__ T sG[2][9][64];
   const int lane = threadIdx.x & 63, c = threadIdx.x >> 6;
-  const int64_t batch = A.c0 / 64 + blockIdx.x;
+  // XCD-aware: workgroup w runs on XCD w % 8; each XCD takes a contiguous range of batches
+  const int64_t nbt = (A.c1 + 63) / 64 - A.c0 / 64, per = (nbt + 7) / 8;
+  const int64_t bl = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (bl >= nbt) return;
+  const int64_t batch = A.c0 / 64 + bl;
   const int64_t cell = batch * 64 + lane;
   bool valid = cell >= A.c0 && cell < A.c1;
   if (valid && A.cell_user) {
@@ -123,7 +127,7 @@ template <typename T, int K, int NQ>
 static int launch_tet_kq(const TetArgs<T> &a, hipStream_t s, bool diag, bool atomic) {
   const int64_t b0 = a.c0 / 64, b1 = (a.c1 + 63) / 64;
   if (a.c1 <= a.c0) return MF_OK;
-  dim3 grid((unsigned)(b1 - b0)), block(192);
+  dim3 grid((unsigned)(diag ? b1 - b0 : ((b1 - b0 + 7) / 8) * 8)), block(192);
   if (diag) tet_elasticity_diag_kernel<T, K, NQ><<<grid, block, 0, s>>>(a);
   else if (atomic) tet_elasticity_kernel<T, K, NQ, true><<<grid, block, 0, s>>>(a);
   else tet_elasticity_kernel<T, K, NQ, false><<<grid, block, 0, s>>>(a);
