@@ -87,6 +87,27 @@ def roof(op, t, prec):
             "tflops": F / t / 1e12, "gbs": B / t / 1e9}
 
 
+PROFILE = os.path.join(ROOT, "profiles", "hex_apply_laplacian3_q6_fp64_32cube.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    try:
+        kv = {}
+        for line in open(PROFILE):
+            parts = line.strip().split(": ", 1)
+            if len(parts) == 2:
+                kv[parts[0]] = parts[1]
+        src = os.path.join(ROOT, kv["kernel_source"])
+        if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["kernel_source_sha256"]:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(mg, cases, budget_s=20.0):
     """The oracle (dense, FP64, all host cores) on a bounded sample: a contiguous
     slice of cells of every headline operator, scaled to GDoF/s by the slice fraction."""
@@ -305,15 +326,18 @@ def main():
     t_dom = per[dom_i]["fp64"]["us"] * 1e-6
     nl = op.info["cell_launches"]  # equal-size colour launches share the action's work evenly
     r = roof(op, t_dom, 0)
+    traffic = measured_traffic() if (dom["k"], dom["kind"], dom["ncomp"]) == (6, mf.LAPLACIAN, 3) else None
     if r["bound"] == "alu":
         roofline = {"bound": "alu", "achieved": r["flops"] / t_dom / 1e12, "peak": PEAK_FP64 / 1e12,
-                    "unit": "TFLOP/s", "frac": r["flops"] / t_dom / PEAK_FP64, "traffic": None,
+                    "unit": "TFLOP/s", "frac": r["flops"] / t_dom / PEAK_FP64, "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     "kernel": f"hex_apply_kernel<double,{dom['k'] + 1},{dom['kind']}> ({dom['name']})",
                     "flops_per_launch": r["flops"] / nl, "bytes_per_launch": r["bytes"] / nl,
                     "launch_us": t_dom * 1e6 / nl, "launches_per_apply": nl}
     else:
         roofline = {"bound": "hbm", "achieved": r["bytes"] / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                    "frac": r["bytes"] / t_dom / PEAK_HBM, "traffic": None,
+                    "frac": r["bytes"] / t_dom / PEAK_HBM, "traffic": traffic,
+                    "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
                     "kernel": f"hex_apply_kernel<double,{dom['k'] + 1},{dom['kind']}> ({dom['name']})",
                     "flops_per_launch": r["flops"] / nl, "bytes_per_launch": r["bytes"] / nl,
                     "launch_us": t_dom * 1e6 / nl, "launches_per_apply": nl}
