@@ -193,6 +193,11 @@ int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out);
  * updates) to relative tolerance max(inner_rtol, rtol ||b|| / ||r||) -- the
  * final target, floored at inner_rtol (0 -> 1e-6, the FP32 action's accuracy)
  * -- then x += d.
+ * M == NULL: no preconditioner; a Jacobi M: preconditioned CG; a learned M
+ * (mf_precond_create_cnn): flexible CG with the Polak-Ribiere beta
+ * -alpha <z_k+1, A p_k> / <z_k, r_k>, where any iteration whose network output z
+ * is non-finite or has <z, r> <= 0 uses the Jacobi z instead (counted in
+ * info->fallbacks).
  * x holds the initial guess on entry. Synchronous. info may be NULL.
  * Errors: MF_ENOTCONV (maxit total inner iterations reached; x holds the last
  * iterate, info filled), MF_EBREAKDOWN (non-finite residual or p'Ap <= 0). */
@@ -201,6 +206,66 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
                 void *stream);
 
 void mf_precond_destroy(mf_precond *p);
+
+/* z = M r for FP64 device vectors of the operator's space in user numbering
+ * (Jacobi: z = D^-1 r; learned: as below). Asynchronous on stream. */
+int mf_precond_apply(const mf_precond *M, const double *r, double *z, void *stream);
+
+/* ----------------------------------------------------------------- learned preconditioner
+ * Not in the paper: a convolutional approximate inverse for the matrix-free
+ * operator on the DoF lattice of a structured hex mesh (Q_k on m^3 cells:
+ * (k m + 1)^3 nodes). The network N is a three-level U-Net on FP32
+ * channel-last lattices of n = 4 j + 1 points per direction:
+ *   h0 = relu(A x); c1 = R h0; h1 = relu(B c1); c2 = R h1; h2 = relu(C c2);
+ *   g2 = relu(D h2); u1 = P g2 + h1; g1 = relu(E u1); u0 = P g1 + h0; y = F u0,
+ * with 3x3x3 convolutions (zero padding, no bias; A: 1 -> C channels, B..E:
+ * C -> C, F: C -> 1), full-weighting restriction R (1/4, 1/2, 1/4 per direction)
+ * and trilinear prolongation P. Parameters: one FP32 vector holding A..F in that
+ * order, each as W[tap][cin][cout] with tap = (dx+1) + 3 (dy+1) + 9 (dz+1) and
+ * out[v] = sum_d in[v + d] W[tap(d)]; mf_cnn_nparams(C) = 27 (2 C + 4 C^2).
+ * Channels C: 4, 8 or 16. A network object holds the parameters, Adam moments
+ * and training workspaces; one object must not be used by two streams at once. */
+typedef struct mf_cnn mf_cnn;
+int64_t mf_cnn_nparams(int channels); /* -1 for an unsupported channel count */
+/* theta: host, mf_cnn_nparams(channels) floats (the initial weights; copied). */
+int mf_cnn_create(int channels, const float *theta, mf_cnn **out);
+int mf_cnn_get_params(const mf_cnn *net, float *theta);   /* host out; synchronises the device */
+int mf_cnn_set_params(mf_cnn *net, const float *theta);   /* host in; resets the Adam state */
+/* Binary file: 8-byte magic "MFCNN01", int32 channels, int32 pad, int64 nparams,
+ * then the FP32 parameters (little-endian). */
+int mf_cnn_save(const mf_cnn *net, const char *path);
+int mf_cnn_load(const char *path, mf_cnn **out);
+void mf_cnn_destroy(mf_cnn *net); /* NULL-safe */
+/* y = N(x) for a batch of lattices: x, y device FP32 [batch][nz][ny][nx];
+ * every size 4 j + 1 with j >= 1 (else MF_EINVAL). Asynchronous on stream. */
+int mf_cnn_forward(mf_cnn *net, int batch, int nz, int ny, int nx, const float *x, float *y, void *stream);
+/* Loss of a batch, mean over samples of |N(x_b) - t_b|^2 / |t_b|^2 (a sample
+ * with t_b = 0 contributes 0), and its gradient with respect to the parameters.
+ * loss: host (nullable, then asynchronous), grad: device nparams floats (nullable). */
+int mf_cnn_loss_grad(mf_cnn *net, int batch, int nz, int ny, int nx, const float *x, const float *t,
+                     double *loss, float *grad, void *stream);
+/* nsteps Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * batches of training pairs: r, e device FP32 [npairs][n][n][n]; step s uses the
+ * pairs order[s*batch .. s*batch+batch-1] (host int32, each in [0, npairs)).
+ * losses: host, nsteps doubles (the loss before each step; nullable). Synchronous. */
+int mf_cnn_train(mf_cnn *net, int npairs, int n, const float *r, const float *e, int nsteps, int batch,
+                 const int32_t *order, float lr, double *losses, void *stream);
+/* Learned preconditioner for a scalar operator A on a lattice of nz x ny x nx
+ * nodes: node_grid (host, A's nnodes entries, user numbering) gives each node's
+ * lattice index (z ny + y) nx + x and must be a bijection. The preconditioner is
+ * z = D^-1/2 N(D^-1/2 r) with D = diag(A), and z = r on Dirichlet nodes. The
+ * network is borrowed: it must outlive the preconditioner, and training it
+ * later changes the preconditioner. Errors: MF_EUNSUPPORTED (vector space),
+ * MF_EINVAL (sizes, not a bijection). */
+int mf_precond_create_cnn(const mf_op *A, const mf_cnn *net, int nz, int ny, int nx,
+                          const int32_t *node_grid, void *stream, mf_precond **out);
+/* Training pairs from a residual / error pair of A (r = A e; FP64 device vectors,
+ * user numbering): both are diagonally scaled (r~ = D^-1/2 r, e~ = D^1/2 e, the
+ * pair of the unit-diagonal operator), and crop c is the n^3 sub-lattice starting
+ * at (z, y, x) = corners[3c .. 3c+2] (host int32), scaled by 1 / rms of its r~
+ * values. r_out, e_out: device FP32 [ncrops][n][n][n]. Synchronous. */
+int mf_precond_harvest(const mf_precond *M, const double *r, const double *e, int ncrops, int n,
+                       const int32_t *corners, float *r_out, float *e_out, void *stream);
 
 /* ----------------------------------------------------------------- batched solves
  * Many independent systems A64[i] x[i] = b[i] on uneven hex meshes and degrees,

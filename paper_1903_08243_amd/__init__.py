@@ -7,5 +7,6 @@ first call raises -- there is no CPU fallback.
 """
 from .api import (  # noqa: F401
     CELL_HEX, CELL_TET, CELL_TRI, F32, F64, SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED, MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY,
-    MFError, Mesh, Space, Operator, JacobiPrecond, Batch, cg_solve, library_path, load_library,
+    MFError, Mesh, Space, Operator, JacobiPrecond, LearnedPrecond, CNN, Batch, cg_solve, cnn_nparams,
+    cnn_initial_weights, library_path, load_library,
 )

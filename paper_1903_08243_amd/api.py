@@ -91,6 +91,19 @@ def load_library():
         "mf_space_destroy": (None, [P]),
         "mf_op_destroy": (None, [P]),
         "mf_precond_destroy": (None, [P]),
+        "mf_precond_apply": (I, [P, P, P, P]),
+        "mf_cnn_nparams": (I64, [I]),
+        "mf_cnn_create": (I, [I, P, PP]),
+        "mf_cnn_get_params": (I, [P, P]),
+        "mf_cnn_set_params": (I, [P, P]),
+        "mf_cnn_save": (I, [P, ctypes.c_char_p]),
+        "mf_cnn_load": (I, [ctypes.c_char_p, PP]),
+        "mf_cnn_destroy": (None, [P]),
+        "mf_cnn_forward": (I, [P, I, I, I, I, P, P, P]),
+        "mf_cnn_loss_grad": (I, [P, I, I, I, I, P, P, ctypes.POINTER(D), P, P]),
+        "mf_cnn_train": (I, [P, I, I, P, P, I, I, P, ctypes.c_float, P, P]),
+        "mf_precond_create_cnn": (I, [P, P, I, I, I, P, P, PP]),
+        "mf_precond_harvest": (I, [P, P, P, I, I, P, P, P, P]),
         "mf_last_error": (ctypes.c_char_p, []),
         "mf_version": (ctypes.c_char_p, []),
     }
@@ -259,16 +272,155 @@ class Operator:
             self.handle = None
 
 
-class JacobiPrecond:
-    def __init__(self, op: Operator, stream=None):
-        h = ctypes.c_void_p()
-        _check(load_library().mf_precond_create_jacobi(op.handle, _stream(stream), ctypes.byref(h)))
-        self.handle = h
+class _Precond:
+    def apply(self, r, z=None, stream=None):
+        """z = M r (FP64 device vectors, user numbering)."""
+        import torch
+        if z is None:
+            z = torch.empty_like(r)
+        _check(load_library().mf_precond_apply(self.handle, _dev(r, torch.float64), _dev(z, torch.float64),
+                                               _stream(stream)))
+        return z
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:
             _lib.mf_precond_destroy(self.handle)
             self.handle = None
+
+
+class JacobiPrecond(_Precond):
+    def __init__(self, op: Operator, stream=None):
+        h = ctypes.c_void_p()
+        _check(load_library().mf_precond_create_jacobi(op.handle, _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+
+def cnn_nparams(channels):
+    n = load_library().mf_cnn_nparams(channels)
+    if n < 0:
+        raise ValueError("channels must be 4, 8 or 16")
+    return n
+
+
+def cnn_initial_weights(channels, seed=0, scale=0.05):
+    """Initial parameters: the network starts as the identity map (channel 0 of A
+    and F carries r through relu(r) - relu(-r) via channels 0 and 1), plus small
+    seeded Gaussian weights on every tap. Host float32 array."""
+    C = channels
+    sizes = [27 * C, 27 * C * C, 27 * C * C, 27 * C * C, 27 * C * C, 27 * C]
+    g = np.random.default_rng([1903, 8243, seed])
+    th = (g.standard_normal(sum(sizes)) * scale).astype(np.float32)
+    offs = np.cumsum([0] + sizes)
+    A = th[offs[0]:offs[1]].reshape(27, 1, C)
+    F = th[offs[5]:offs[6]].reshape(27, C, 1)
+    A[13, 0, 0] += 1.0
+    A[13, 0, 1] -= 1.0
+    F[13, 0, 0] += 1.0
+    F[13, 1, 0] -= 1.0
+    return th
+
+
+class CNN:
+    """The learned preconditioner's network (see include/mf.h). Lattices are
+    float32 device tensors shaped [batch, nz, ny, nx]."""
+
+    def __init__(self, channels, theta=None, _handle=None):
+        L = load_library()
+        self.channels = channels
+        self.nparams = cnn_nparams(channels)
+        if _handle is not None:
+            self.handle = _handle
+            return
+        th = _np(cnn_initial_weights(channels) if theta is None else theta, np.float32)
+        if th.size != self.nparams:
+            raise ValueError(f"theta must have {self.nparams} entries")
+        h = ctypes.c_void_p()
+        _check(L.mf_cnn_create(channels, th.ctypes.data, ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def load(cls, path):
+        h = ctypes.c_void_p()
+        _check(load_library().mf_cnn_load(path.encode(), ctypes.byref(h)))
+        with open(path, "rb") as f:  # the library validated the header
+            channels = int(np.frombuffer(f.read(12)[8:12], dtype="<i4")[0])
+        return cls(channels, _handle=h)
+
+    def params(self):
+        th = np.empty(self.nparams, np.float32)
+        _check(load_library().mf_cnn_get_params(self.handle, th.ctypes.data))
+        return th
+
+    def set_params(self, theta):
+        th = _np(theta, np.float32)
+        if th.size != self.nparams:
+            raise ValueError(f"theta must have {self.nparams} entries")
+        _check(load_library().mf_cnn_set_params(self.handle, th.ctypes.data))
+
+    def save(self, path):
+        _check(load_library().mf_cnn_save(self.handle, path.encode()))
+
+    def forward(self, x, y=None, stream=None):
+        import torch
+        if x.dim() != 4:
+            raise ValueError("x must be [batch, nz, ny, nx]")
+        if y is None:
+            y = torch.empty_like(x)
+        B, nz, ny, nx = x.shape
+        _check(load_library().mf_cnn_forward(self.handle, B, nz, ny, nx, _dev(x, torch.float32),
+                                             _dev(y, torch.float32), _stream(stream)))
+        return y
+
+    def loss_grad(self, x, t, stream=None):
+        import torch
+        B, nz, ny, nx = x.shape
+        g = torch.empty(self.nparams, dtype=torch.float32, device=x.device)
+        loss = ctypes.c_double()
+        _check(load_library().mf_cnn_loss_grad(self.handle, B, nz, ny, nx, _dev(x, torch.float32),
+                                               _dev(t, torch.float32), ctypes.byref(loss), _dev(g),
+                                               _stream(stream)))
+        return loss.value, g
+
+    def train(self, r, e, order, batch, lr=1e-3, stream=None):
+        """Adam steps over pairs r, e ([npairs, n, n, n] float32); order: int array of
+        nsteps * batch pair indices. Returns the per-step losses (before each step)."""
+        import torch
+        npairs, n = r.shape[0], r.shape[1]
+        order = _np(order, np.int32)
+        nsteps = order.size // batch
+        losses = np.zeros(max(nsteps, 1), np.float64)
+        _check(load_library().mf_cnn_train(self.handle, npairs, n, _dev(r, torch.float32), _dev(e, torch.float32),
+                                           nsteps, batch, order.ctypes.data, lr, losses.ctypes.data,
+                                           _stream(stream)))
+        return losses[:nsteps]
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.mf_cnn_destroy(self.handle)
+            self.handle = None
+
+
+class LearnedPrecond(_Precond):
+    """z = D^-1/2 N(D^-1/2 r) on the DoF lattice of a structured hex mesh
+    (shape = (nz, ny, nx); node_grid[u] = lattice index of user node u)."""
+
+    def __init__(self, op: Operator, net: CNN, shape, node_grid, stream=None):
+        ng = _np(node_grid, np.int32)
+        h = ctypes.c_void_p()
+        nz, ny, nx = shape
+        _check(load_library().mf_precond_create_cnn(op.handle, net.handle, nz, ny, nx, ng.ctypes.data,
+                                                    _stream(stream), ctypes.byref(h)))
+        self.handle, self.net, self.shape = h, net, tuple(shape)
+
+    def harvest(self, r, e, corners, n, stream=None):
+        """Diagonally scaled n^3 crops of the pair (r, e) at the given corners (z, y, x)."""
+        import torch
+        c = _np(corners, np.int32).reshape(-1, 3)
+        ro = torch.empty((c.shape[0], n, n, n), dtype=torch.float32, device=r.device)
+        eo = torch.empty_like(ro)
+        _check(load_library().mf_precond_harvest(self.handle, _dev(r, torch.float64), _dev(e, torch.float64),
+                                                 c.shape[0], n, c.ctypes.data, _dev(ro), _dev(eo), _stream(stream)))
+        return ro, eo
 
 
 def cg_solve(A64: Operator, b, x, A32: Operator | None = None, precond=None, rtol=1e-10, inner_rtol=0.0,

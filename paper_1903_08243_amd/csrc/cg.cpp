@@ -24,7 +24,8 @@ static constexpr int CHUNK = 8;
 
 struct CgWork {
   int64_t n = 0;
-  DeviceBuffer r, p, Ap, part, st, p32, Ap32, d, bi, xi;
+  DeviceBuffer r, p, Ap, part, st, p32, Ap32, d, bi, xi, z;
+  const mf_precond *M = nullptr;  // learned preconditioner (flexible CG), or null
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
   CgState *host_st = nullptr;  // pinned
@@ -45,6 +46,21 @@ static int apply_any(const mf_op *A, const void *x, void *y, hipStream_t s) { re
 // One chunk of PCG iterations on operator A (FP64 or FP32 action), recorded on w.s.
 static int record_chunk(const mf_op *A, const double *dinv, double *x, CgWork &w) {
   const bool a32 = A->precision == MF_F32;
+  if (w.M) {
+    // flexible CG: z = M r from the learned preconditioner, Polak-Ribiere beta
+    for (int j = 0; j < CHUNK; j++) {
+      void *Ap = a32 ? w.Ap32.ptr : w.Ap.ptr;
+      int rc = a32 ? apply_any(A, w.p32.ptr, Ap, w.s) : apply_any(A, w.p.ptr, Ap, w.s);
+      if (!rc) rc = fcg_update(x, w.r.as<double>(), w.p.as<double>(), Ap, a32, w.n, w.part.as<double>(),
+                               w.st.as<CgState>(), w.s);
+      if (!rc) rc = precond_cnn_apply_internal(w.M, w.r.as<double>(), w.z.as<double>(), w.s);
+      if (!rc) rc = fcg_direction(w.r.as<double>(), w.z.as<double>(), dinv, w.p.as<double>(),
+                                  a32 ? w.p32.as<float>() : nullptr, Ap, a32, w.n, w.part.as<double>(),
+                                  w.st.as<CgState>(), w.s);
+      if (rc) return rc;
+    }
+    return MF_OK;
+  }
   for (int j = 0; j < CHUNK; j++) {
     int rc = a32 ? apply_any(A, w.p32.ptr, w.Ap32.ptr, w.s) : apply_any(A, w.p.ptr, w.Ap.ptr, w.s);
     if (rc) return rc;
@@ -92,8 +108,16 @@ static int pcg_core(const mf_op *A, const double *dinv, double *x, double tol2, 
   init.maxit = maxit;
   *w.host_st = init;
   MF_HIP(hipMemcpyAsync(w.st.ptr, w.host_st, sizeof(CgState), hipMemcpyHostToDevice, w.s));
-  int rc = cg_init(w.r.as<double>(), dinv, w.p.as<double>(), a32 ? w.p32.as<float>() : nullptr, w.n,
-                   w.part.as<double>(), w.st.as<CgState>(), w.s, a32 ? w.Ap32.ptr : w.Ap.ptr);
+  int rc;
+  if (w.M) {
+    rc = precond_cnn_apply_internal(w.M, w.r.as<double>(), w.z.as<double>(), w.s);
+    if (!rc) rc = fcg_init(w.r.as<double>(), w.z.as<double>(), dinv, w.p.as<double>(),
+                           a32 ? w.p32.as<float>() : nullptr, w.n, w.part.as<double>(), w.st.as<CgState>(), w.s,
+                           a32 ? w.Ap32.ptr : w.Ap.ptr);
+  } else {
+    rc = cg_init(w.r.as<double>(), dinv, w.p.as<double>(), a32 ? w.p32.as<float>() : nullptr, w.n,
+                 w.part.as<double>(), w.st.as<CgState>(), w.s, a32 ? w.Ap32.ptr : w.Ap.ptr);
+  }
   if (rc) return rc;
   rc = read_state(w, out);
   if (rc || out.stop || maxit <= 0) return rc;
@@ -134,8 +158,15 @@ int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out) {
   P->kind = 0;
   P->n = A->ndofs;
   P->numbering_id = A->numbering_id;
+  P->nnodes = A->nnodes;
+  P->ncomp = A->ncomp;
+  P->identity = A->identity;
   DeviceBuffer d;
   int rc = d.alloc((size_t)A->ndofs * (A->precision == MF_F64 ? 8 : 4));
+  if (!rc && !A->identity) {
+    rc = P->perm.alloc((size_t)A->nnodes * 4);
+    if (!rc) MF_HIP(hipMemcpyAsync(P->perm.ptr, A->perm.ptr, (size_t)A->nnodes * 4, hipMemcpyDeviceToDevice, s));
+  }
   if (!rc) rc = P->dinv.alloc((size_t)A->ndofs * 8);
   if (!rc) rc = op_diagonal_internal(A, d.ptr, s);
   if (!rc) rc = cg_recip(d.ptr, A->precision == MF_F32, P->dinv.as<double>(), A->ndofs, s);
@@ -162,7 +193,6 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
   if (M && (M->n != A64->ndofs || M->numbering_id != A64->numbering_id))
     return fail(MF_EINVAL, "mf_cg_solve: preconditioner built for another space");
   if (!(rtol > 0.0) || maxit < 0) return fail(MF_EINVAL, "mf_cg_solve: rtol / maxit");
-  if (M && M->kind != 0) return fail(MF_EUNSUPPORTED, "mf_cg_solve: use mf_fcg_solve for learned preconditioners");
   const int64_t n = A64->ndofs;
   hipStream_t caller = (hipStream_t)stream;
   CgWork w;
@@ -176,7 +206,11 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
   int rc = MF_OK;
   for (DeviceBuffer *bptr : {&w.r, &w.p, &w.Ap})
     if (!rc) rc = bptr->alloc((size_t)n * 8);
-  if (!rc) rc = w.part.alloc((size_t)2 * CG_NPART * 8);
+  if (!rc) rc = w.part.alloc((size_t)4 * CG_NPART * 8);
+  if (M && M->kind == 1) {
+    w.M = M;
+    if (!rc) rc = w.z.alloc((size_t)n * 8);
+  }
   if (!rc) rc = w.st.alloc(sizeof(CgState));
   if (A32) {
     if (!rc) rc = w.p32.alloc((size_t)n * 4);
@@ -225,6 +259,7 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
       rc = pcg_core(A64, dinv, x, tol2, maxit - inf.inner_iterations, w, st);
       if (rc) return rc;
       inf.inner_iterations += st.iters;
+      inf.fallbacks += st.nfallback;
       if (st.breakdown) {
         status = fail(MF_EBREAKDOWN, "CG breakdown (non-finite value or p'Ap <= 0)");
         break;
@@ -252,6 +287,7 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
       rc = pcg_core(A32, dinv, w.d.as<double>(), irt * irt * rr, maxit - inf.inner_iterations, w, st);
       if (rc) return rc;
       inf.inner_iterations += st.iters;
+      inf.fallbacks += st.nfallback;
       if (st.breakdown) {
         status = fail(MF_EBREAKDOWN, "inner CG breakdown (non-finite value or p'Ap <= 0)");
         break;

@@ -70,3 +70,21 @@ def test_host_errors_without_device_work():
     assert L.mf_space_create(h, 1, 1, c2n.ctypes.data, 8, ctypes.byref(s)) == 0
     L.mf_space_destroy(s)
     L.mf_mesh_destroy(h)
+
+
+def test_learned_precond_host_validation():
+    """Channel counts, parameter counts and unreadable network files are rejected
+    on the host."""
+    import numpy as np
+    from paper_1903_08243_amd import api
+    if not os.path.exists(api.library_path()):
+        pytest.skip("libmf.so not built")
+    lib = api.load_library()
+    for c in (4, 8, 16):
+        assert lib.mf_cnn_nparams(c) == 27 * (2 * c + 4 * c * c)
+    assert lib.mf_cnn_nparams(5) == -1
+    th = np.zeros(10, np.float32)
+    h = ctypes.c_void_p()
+    assert lib.mf_cnn_create(5, th.ctypes.data, ctypes.byref(h)) == -7
+    assert lib.mf_cnn_load(b"/nonexistent/net.bin", ctypes.byref(h)) == -1
+    assert lib.mf_cnn_forward(None, 1, 5, 5, 5, None, None, None) == -1
