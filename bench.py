@@ -218,6 +218,89 @@ def bench_c4(mf, mg, nsys=64, seed=0):
     return out
 
 
+def bench_c5(mf, mg, m=64, k=3, channels=8, npairs=2000, crop=33, steps=1500, batch=8, lr=1e-3,
+             train_rhs=2, seed=0):
+    """Variable-coefficient Poisson, Q3 on 64^3 hex (193^3 = 7,189,057 dofs), kappa =
+    exp(GRF), homogeneous Dirichlet, b = M f: time to 1e-10 with Jacobi-CG (FP64, and
+    FP32-action refinement) against flexible CG with the learned preconditioner
+    (FP32-action refinement). The network is trained on (r, e) crops harvested from
+    Jacobi-CG iterates of other right-hand sides; harvest and training are timed
+    separately."""
+    import torch
+    t_setup = time.perf_counter()
+    mesh = mg.hex_mesh(m, 0.15, config=5, seed_k=seed)
+    space = mg.hex_space(mesh, k, config=5, seed_k=seed)
+    kappa = np.exp(mg.gaussian_random_field(mesh.vert_ijk, m, config=5))
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    G = m * k + 1
+    ijk = space.node_ijk
+    node_grid = (ijk[:, 0] + G * (ijk[:, 1] + G * ijk[:, 2])).astype(np.int32)
+    sp = mf.Space.from_meshgen(space)
+    A64 = mf.Operator(sp, mf.POISSON, mf.F64, vertex_coef=kappa, dirichlet=mask)
+    A32 = mf.Operator(sp, mf.POISSON, mf.F32, vertex_coef=kappa, dirichlet=mask)
+    Mass = mf.Operator(sp, mf.MASS, mf.F64, dirichlet=mask)
+    J = mf.JacobiPrecond(A64)
+
+    def rhs(i):
+        f = mg.uniform(space.ndofs, -1, 1, 5, mg.PURPOSE_RHS, i)
+        f[bnd] = 0.0
+        return Mass.apply(torch.tensor(f, device="cuda"))
+
+    out = {"problem": f"variable-kappa Poisson Q{k}, {m}^3 perturbed renumbered hex, {space.ndofs} dofs, "
+                      "Dirichlet, kappa = exp(GRF, l=0.1)", "setup_seconds": time.perf_counter() - t_setup}
+    # training pairs: Jacobi-CG iterates x_j of other right-hand sides, e = x* - x_j, r = A e
+    net = mf.CNN(channels, mf.cnn_initial_weights(channels, seed=seed))
+    M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
+    g = np.random.default_rng([5, 7, seed])
+    snaps = [int(round(1.25 ** i)) for i in range(0, 40)]
+    snaps = sorted(set(j for j in snaps if j <= 2000))
+    per = -(-npairs // (train_rhs * len(snaps)))
+    t0 = time.perf_counter()
+    R, E = [], []
+    for i in range(train_rhs):
+        b = rhs(1000 + i)
+        xs = torch.zeros_like(b)
+        mf.cg_solve(A64, b, xs, precond=J, rtol=1e-12, maxit=200000)
+        for j in snaps:
+            xj = torch.zeros_like(b)
+            mf.cg_solve(A64, b, xj, precond=J, rtol=1e-14, maxit=j, raise_on_error=False)
+            e = xs - xj
+            r = A64.apply(e)
+            corners = g.integers(0, G - crop + 1, size=(per, 3)).astype(np.int32)
+            ro, eo = M.harvest(r, e, corners, crop)
+            R.append(ro)
+            E.append(eo)
+    R, E = torch.cat(R)[:npairs], torch.cat(E)[:npairs]
+    torch.cuda.synchronize()
+    out["harvest_seconds"] = time.perf_counter() - t0
+    out["pairs"] = int(R.shape[0])
+    t0 = time.perf_counter()
+    order = g.integers(0, R.shape[0], size=steps * batch).astype(np.int32)
+    losses = net.train(R, E, order, batch, lr=lr)
+    out["train_seconds"] = time.perf_counter() - t0
+    out["train"] = {"steps": steps, "batch": batch, "lr": lr, "channels": channels, "crop": crop,
+                    "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-50:]))}
+    del R, E
+    torch.cuda.empty_cache()
+    b = rhs(0)
+    for name, a32, prec in (("jacobi_fp64", None, J), ("jacobi_fp32_refined", A32, J),
+                            ("learned_fp32_refined", A32, M), ("learned_fp64", None, M)):
+        x = torch.zeros_like(b)
+        mf.cg_solve(A64, b, x, A32=a32, precond=prec, rtol=1e-10, maxit=200000)  # warm (graph capture)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = mf.cg_solve(A64, b, x, A32=a32, precond=prec, rtol=1e-10, maxit=200000)
+        torch.cuda.synchronize()
+        out[name] = {"seconds": time.perf_counter() - t0, "iterations": info["inner_iterations"],
+                     "outer": info["outer_iterations"], "fallbacks": info["fallbacks"],
+                     "rel_residual": info["rel_residual"]}
+        log(f"  c5 {name}: {json.dumps(out[name])}")
+    return out
+
+
 def profile_kernel(mf, mg):
     """The dominant kernel of the headline step (FP64 3-component Laplacian, Q6, 32^3)
     launched 10 times on internally numbered vectors, then a plain 256 MiB device copy
@@ -248,6 +331,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quick", action="store_true", help="degrees 1..3 only (debugging)")
     ap.add_argument("--no-c4", action="store_true", help="skip the batched 64-system solves")
+    ap.add_argument("--no-c5", action="store_true", help="skip the learned-preconditioner comparison")
+    ap.add_argument("--c5-only", action="store_true", help="only the learned-preconditioner comparison")
+    ap.add_argument("--c5-m", type=int, default=64, help="cells per direction of that problem")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only run the dominant action kernel 10 times and a 256 MiB reference copy "
                          "(for hardware-counter runs)")
@@ -265,6 +351,9 @@ def main():
     mf.load_library()
     if args.profile_kernel:
         profile_kernel(mf, mg)
+        return
+    if args.c5_only:
+        print(json.dumps(bench_c5(mf, mg, m=args.c5_m)))
         return
     degrees = [1, 2, 3] if args.quick else [1, 2, 3, 4, 5, 6]
     kinds = [("helmholtz", mf.HELMHOLTZ, 1), ("laplacian3", mf.LAPLACIAN, 3), ("laplacian1", mf.LAPLACIAN, 1)]
@@ -363,6 +452,13 @@ def main():
             log(f"  c4: {json.dumps({k: v for k, v in extra['c4_batched'].items() if k not in ('mesh_m', 'degree')})}")
         except Exception as ex:
             extra["c4_batched"] = {"error": repr(ex)}
+    if not args.quick and not args.no_c5:
+        torch.cuda.empty_cache()
+        try:
+            log("learned preconditioner (variable-kappa Poisson Q3 64^3) ...")
+            extra["c5_learned_precond"] = bench_c5(mf, mg)
+        except Exception as ex:
+            extra["c5_learned_precond"] = {"error": repr(ex)}
 
     out = {
         "metric": METRIC, "value": value, "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
