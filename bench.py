@@ -136,6 +136,48 @@ def cpu_baseline(mg, cases, budget_s=20.0):
                       f"{tot_t:.1f} s of CPU work"}
 
 
+def bench_simplex(mf, mg, reps=20):
+    """P1 triangle mass with a nodal coefficient (64x64x2 triangles, and a weak-scaled
+    2048x2048x2 mesh for the bandwidth figure) and vector P2/P3 tet elasticity
+    (48^3 x 6 Kuhn tets perturbed +-0.2h, renumbered, lambda 1, mu 0.5) in FP64 and
+    FP32 (MFMA contractions). Per operator: kernel time, GDoF/s, roofline fraction."""
+    import torch
+    out = {}
+    for m, tag in ((64, "tri_p1_mass_64"), (2048, "tri_p1_mass_2048_weak_scaled")):
+        mesh = mg.tri_mesh(m)
+        space = mg.tri_p1_space(mesh)
+        c = mg.uniform(mesh.nverts, 0.5, 1.5, 0, mg.PURPOSE_COEF)
+        sp = mf.Space.from_meshgen(space)
+        op = mf.Operator(sp, mf.MASS, mf.F64, vertex_coef=c)
+        x = torch.tensor(mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X), device="cuda")
+        y = torch.empty_like(x)
+        t = time_kernel(op, x, y, reps)
+        r = roof(op, t, 0)
+        out[tag] = {"cells": mesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
+                    "bound": r["bound"], "frac": r["frac"], "gbs": r["gbs"]}
+        log(f"  {tag}: {json.dumps(out[tag])}")
+    mesh = mg.tet_mesh(48, 0.2, config=2)
+    for k in (2, 3):
+        space = mg.tet_space(mesh, k, config=2)
+        sp = mf.Space.from_meshgen(space)
+        x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32_mfma")):
+            op = mf.Operator(sp, mf.ELASTICITY, prec, lam=1.0, mu=0.5)
+            xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+            yt = torch.empty_like(xt)
+            t = time_kernel(op, xt, yt, reps)
+            F, B = op.info["flops_per_apply"], op.info["bytes_per_apply"]
+            P = PEAK_FP64 if prec == mf.F64 else PEAK_FP32
+            tag = f"tet_elasticity_p{k}_{ptag}"
+            out[tag] = {"cells": mesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
+                        "bound": "alu" if prec == mf.F64 else "mfma", "tflops": F / t / 1e12,
+                        "frac": max(F / P, B / PEAK_HBM) / t, "gbs": B / t / 1e9}
+            log(f"  {tag}: {json.dumps(out[tag])}")
+            del op, xt, yt
+        del sp, space
+    return out
+
+
 def bench_cg(mf, mg, k=3, m=32):
     """Time to 1e-10 relative residual: FP64 Jacobi-CG vs FP32-action refinement (Helmholtz)."""
     import torch
@@ -262,7 +304,8 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, npairs=2000, crop=33, steps=1500, ba
     for i in range(train_rhs):
         b = rhs(1000 + i)
         xs = torch.zeros_like(b)
-        mf.cg_solve(A64, b, xs, precond=J, rtol=1e-12, maxit=200000)
+        ref = mf.cg_solve(A64, b, xs, precond=J, rtol=1e-12, maxit=200000)
+        log(f"  c5 training rhs {i}: reference solve {ref['inner_iterations']} iterations")
         for j in snaps:
             xj = torch.zeros_like(b)
             mf.cg_solve(A64, b, xj, precond=J, rtol=1e-14, maxit=j, raise_on_error=False)
@@ -280,6 +323,7 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, npairs=2000, crop=33, steps=1500, ba
     order = g.integers(0, R.shape[0], size=steps * batch).astype(np.int32)
     losses = net.train(R, E, order, batch, lr=lr)
     out["train_seconds"] = time.perf_counter() - t0
+    log(f"  c5 trained {steps} steps: loss {np.mean(losses[:10]):.4f} -> {np.mean(losses[-50:]):.4f}")
     out["train"] = {"steps": steps, "batch": batch, "lr": lr, "channels": channels, "crop": crop,
                     "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-50:]))}
     del R, E
@@ -334,6 +378,7 @@ def main():
     ap.add_argument("--no-c5", action="store_true", help="skip the learned-preconditioner comparison")
     ap.add_argument("--c5-only", action="store_true", help="only the learned-preconditioner comparison")
     ap.add_argument("--c5-m", type=int, default=64, help="cells per direction of that problem")
+    ap.add_argument("--simplex-only", action="store_true", help="only the triangle mass and tet elasticity actions")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only run the dominant action kernel 10 times and a 256 MiB reference copy "
                          "(for hardware-counter runs)")
@@ -354,6 +399,9 @@ def main():
         return
     if args.c5_only:
         print(json.dumps(bench_c5(mf, mg, m=args.c5_m)))
+        return
+    if args.simplex_only:
+        print(json.dumps(bench_simplex(mf, mg)))
         return
     degrees = [1, 2, 3] if args.quick else [1, 2, 3, 4, 5, 6]
     kinds = [("helmholtz", mf.HELMHOLTZ, 1), ("laplacian3", mf.LAPLACIAN, 3), ("laplacian1", mf.LAPLACIAN, 1)]
@@ -432,6 +480,10 @@ def main():
                     "launch_us": t_dom * 1e6 / nl, "launches_per_apply": nl}
 
     extra = {}
+    try:
+        extra["simplex"] = bench_simplex(mf, mg)
+    except Exception as ex:  # reported, never silently replaced
+        extra["simplex"] = {"error": repr(ex)}
     try:
         extra["cg"] = bench_cg(mf, mg)
         log(f"  cg: {json.dumps(extra['cg'])}")

@@ -5,6 +5,7 @@
 // constant tables of the element kernel, and the device layouts the kernels
 // read. The action itself runs entirely in the HIP kernels.
 #include <algorithm>
+#include <type_traits>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -317,6 +318,12 @@ template <typename T> static int setup_tet(mf_op *op, const mf_space *sp, hipStr
   std::vector<T> tab;
   for (double v : dphi) tab.push_back((T)v);
   for (double v : w) tab.push_back((T)v);
+  if (std::is_same<T, float>::value && k >= 2) {
+    // per-lane operands of the MFMA contractions, appended after the weights
+    std::vector<float> mt((size_t)tet_mfma_table_floats(k, nq));
+    tet_mfma_tables(k, nq, dphi.data(), mt.data());
+    for (float v : mt) tab.push_back((T)v);
+  }
   int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
   if (rc) return rc;
   const int64_t nc = sp->ncells, nb = (nc + 63) / 64;
