@@ -260,7 +260,7 @@ def bench_c4(mf, mg, nsys=64, seed=0):
     return out
 
 
-def bench_c5(mf, mg, m=64, k=3, channels=8, npairs=2000, crop=33, steps=1500, batch=8, lr=1e-3,
+def bench_c5(mf, mg, m=64, k=3, channels=8, levels=6, npairs=500, crop=65, steps=1000, batch=4, lr=1e-3,
              train_rhs=2, seed=0):
     """Variable-coefficient Poisson, Q3 on 64^3 hex (193^3 = 7,189,057 dofs), kappa =
     exp(GRF), homogeneous Dirichlet, b = M f: time to 1e-10 with Jacobi-CG (FP64, and
@@ -293,7 +293,7 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, npairs=2000, crop=33, steps=1500, ba
     out = {"problem": f"variable-kappa Poisson Q{k}, {m}^3 perturbed renumbered hex, {space.ndofs} dofs, "
                       "Dirichlet, kappa = exp(GRF, l=0.1)", "setup_seconds": time.perf_counter() - t_setup}
     # training pairs: Jacobi-CG iterates x_j of other right-hand sides, e = x* - x_j, r = A e
-    net = mf.CNN(channels, mf.cnn_initial_weights(channels, seed=seed))
+    net = mf.CNN(channels, levels, mf.cnn_initial_weights(channels, levels, seed=seed))
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
     g = np.random.default_rng([5, 7, seed])
     snaps = [int(round(1.25 ** i)) for i in range(0, 40)]
@@ -324,7 +324,7 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, npairs=2000, crop=33, steps=1500, ba
     losses = net.train(R, E, order, batch, lr=lr)
     out["train_seconds"] = time.perf_counter() - t0
     log(f"  c5 trained {steps} steps: loss {np.mean(losses[:10]):.4f} -> {np.mean(losses[-50:]):.4f}")
-    out["train"] = {"steps": steps, "batch": batch, "lr": lr, "channels": channels, "crop": crop,
+    out["train"] = {"steps": steps, "batch": batch, "lr": lr, "channels": channels, "levels": levels, "crop": crop,
                     "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-50:]))}
     del R, E
     torch.cuda.empty_cache()

@@ -214,30 +214,33 @@ int mf_precond_apply(const mf_precond *M, const double *r, double *z, void *stre
 /* ----------------------------------------------------------------- learned preconditioner
  * Not in the paper: a convolutional approximate inverse for the matrix-free
  * operator on the DoF lattice of a structured hex mesh (Q_k on m^3 cells:
- * (k m + 1)^3 nodes). The network N is a three-level U-Net on FP32
- * channel-last lattices of n = 4 j + 1 points per direction:
- *   h0 = relu(A x); c1 = R h0; h1 = relu(B c1); c2 = R h1; h2 = relu(C c2);
- *   g2 = relu(D h2); u1 = P g2 + h1; g1 = relu(E u1); u0 = P g1 + h0; y = F u0,
- * with 3x3x3 convolutions (zero padding, no bias; A: 1 -> C channels, B..E:
- * C -> C, F: C -> 1), full-weighting restriction R (1/4, 1/2, 1/4 per direction)
- * and trilinear prolongation P. Parameters: one FP32 vector holding A..F in that
- * order, each as W[tap][cin][cout] with tap = (dx+1) + 3 (dy+1) + 9 (dz+1) and
- * out[v] = sum_d in[v + d] W[tap(d)]; mf_cnn_nparams(C) = 27 (2 C + 4 C^2).
- * Channels C: 4, 8 or 16. A network object holds the parameters, Adam moments
- * and training workspaces; one object must not be used by two streams at once. */
+ * (k m + 1)^3 nodes). The network N is an L-level U-Net (2 <= L <= 8) on FP32
+ * channel-last lattices whose sizes n satisfy n = j 2^(L-1) + 1, j >= 1:
+ *   h_0 = relu(A x);  c_l = R h_(l-1), h_l = relu(B_l c_l)          (l = 1 .. L-1)
+ *   g_(L-1) = relu(D h_(L-1));  u_l = P g_(l+1) + h_l               (l = L-2 .. 0)
+ *   g_l = relu(E_l u_l)  (l = L-2 .. 1);   y = x + F u_0,
+ * with 3x3x3 convolutions (zero padding, no bias; A: 1 -> C channels, F: C -> 1,
+ * the others C -> C), full-weighting restriction R (1/4, 1/2, 1/4 per direction)
+ * and trilinear prolongation P. With zero weights N is the identity (so the
+ * preconditioner below is Jacobi). Parameters: one FP32 vector holding
+ * A, B_1 .. B_(L-1), D, E_(L-2) .. E_1, F in that order, each as W[tap][cin][cout]
+ * with tap = (dx+1) + 3 (dy+1) + 9 (dz+1) and out[v] = sum_d in[v + d] W[tap(d)];
+ * mf_cnn_nparams(C, L) = 27 (2 C + (2 L - 2) C^2). Channels C: 4, 8 or 16.
+ * A network object holds the parameters, Adam moments and training workspaces;
+ * one object must not be used by two streams at once. */
 typedef struct mf_cnn mf_cnn;
-int64_t mf_cnn_nparams(int channels); /* -1 for an unsupported channel count */
-/* theta: host, mf_cnn_nparams(channels) floats (the initial weights; copied). */
-int mf_cnn_create(int channels, const float *theta, mf_cnn **out);
+int64_t mf_cnn_nparams(int channels, int levels); /* -1 for unsupported values */
+/* theta: host, mf_cnn_nparams(channels, levels) floats (initial weights; copied). */
+int mf_cnn_create(int channels, int levels, const float *theta, mf_cnn **out);
 int mf_cnn_get_params(const mf_cnn *net, float *theta);   /* host out; synchronises the device */
 int mf_cnn_set_params(mf_cnn *net, const float *theta);   /* host in; resets the Adam state */
-/* Binary file: 8-byte magic "MFCNN01", int32 channels, int32 pad, int64 nparams,
+/* Binary file: 8-byte magic "MFCNN02", int32 channels, int32 levels, int64 nparams,
  * then the FP32 parameters (little-endian). */
 int mf_cnn_save(const mf_cnn *net, const char *path);
 int mf_cnn_load(const char *path, mf_cnn **out);
 void mf_cnn_destroy(mf_cnn *net); /* NULL-safe */
 /* y = N(x) for a batch of lattices: x, y device FP32 [batch][nz][ny][nx];
- * every size 4 j + 1 with j >= 1 (else MF_EINVAL). Asynchronous on stream. */
+ * every size j 2^(L-1) + 1 with j >= 1 (else MF_EINVAL). Asynchronous on stream. */
 int mf_cnn_forward(mf_cnn *net, int batch, int nz, int ny, int nx, const float *x, float *y, void *stream);
 /* Loss of a batch, mean over samples of |N(x_b) - t_b|^2 / |t_b|^2 (a sample
  * with t_b = 0 contributes 0), and its gradient with respect to the parameters.

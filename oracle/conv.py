@@ -1,45 +1,47 @@
 """CPU oracle of the learned preconditioner's network (forward, loss, backward).
 
-TEST INFRASTRUCTURE: only tests, the smoke check and the benchmark's CPU baseline use it. Plain numpy in float64,
-direct sliding-window convolutions, backward written out by the chain rule.
-The network is not from the paper; it is the small convolutional
-approximate inverse used as a preconditioner for CG on the tensor-product
-DoF lattice. Definition (node lattices of n = 4m + 1 points per direction,
-channel-last arrays [z, y, x, c]):
+TEST INFRASTRUCTURE: only tests, the smoke check and the benchmark's CPU
+baseline use it. Plain numpy in float64, direct sliding-window convolutions,
+backward written out by the chain rule. The network is not from the paper; it
+is the convolutional approximate inverse used as a preconditioner for CG on the
+tensor-product DoF lattice. Definition (L >= 2 levels, C channels, lattices of
+n points per direction with (n - 1) divisible by 2^(L-1), channel-last arrays
+[batch, z, y, x, c]):
 
-  h0 = relu(conv_A(x))          n^3, 1 -> C
-  c1 = R(h0)                    m1 = (n+1)/2
-  h1 = relu(conv_B(c1))         C -> C
-  c2 = R(h1)                    m2 = (m1+1)/2
-  h2 = relu(conv_C(c2))         C -> C
-  g2 = relu(conv_D(h2))         C -> C
-  u1 = P(g2) + h1
-  g1 = relu(conv_E(u1))         C -> C
-  u0 = P(g1) + h0
-  y  = conv_F(u0)               C -> 1
+  h_0 = relu(conv_A(x))                              1 -> C
+  c_l = R h_(l-1),  h_l = relu(conv_B_l(c_l))        l = 1 .. L-1, C -> C
+  g_(L-1) = relu(conv_D(h_(L-1)))                    C -> C
+  u_l = P g_(l+1) + h_l                              l = L-2 .. 0
+  g_l = relu(conv_E_l(u_l))                          l = L-2 .. 1, C -> C
+  y = x + conv_F(u_0)                                C -> 1
 
 conv: 3x3x3 taps, zero padding, no bias; weight W[tap, cin, cout] with
-tap = (dx+1) + 3 (dy+1) + 9 (dz+1) and out[v] = sum in[v + d] W[tap(d)].
+tap = (dx+1) + 3 (dy+1) + 9 (dz+1) and out[v] = sum_d in[v + d] W[tap(d)].
 R (full weighting): c[I] = sum_d prod_k w(d_k) f[2I + d], w(0)=1/2, w(+-1)=1/4,
 values outside the fine lattice are 0. P (trilinear prolongation):
 f[i] = sum_I prod_k l(i_k - 2 I_k) c[I], l(0)=1, l(+-1)=1/2, so P^T = 8 R.
+Parameters in the order A, B_1 .. B_(L-1), D, E_(L-2) .. E_1, F.
 Loss of a sample: |y - t|^2 / |t|^2; a batch averages the samples.
 """
 from __future__ import annotations
 
 import numpy as np
 
-LAYERS = ("A", "B", "C", "D", "E", "F")
+
+def layer_names(L: int):
+    return ["A"] + [f"B{l}" for l in range(1, L)] + ["D"] + [f"E{l}" for l in range(L - 2, 0, -1)] + ["F"]
 
 
-def layer_shapes(C: int):
-    return {"A": (27, 1, C), "B": (27, C, C), "C": (27, C, C), "D": (27, C, C), "E": (27, C, C), "F": (27, C, 1)}
+def layer_shapes(C: int, L: int):
+    sh = {}
+    for name in layer_names(L):
+        sh[name] = (27, 1, C) if name == "A" else (27, C, 1) if name == "F" else (27, C, C)
+    return sh
 
 
-def unpack(theta: np.ndarray, C: int):
+def unpack(theta: np.ndarray, C: int, L: int):
     out, o = {}, 0
-    for name in LAYERS:
-        sh = layer_shapes(C)[name]
+    for name, sh in layer_shapes(C, L).items():
         n = int(np.prod(sh))
         out[name] = theta[o:o + n].reshape(sh)
         o += n
@@ -47,8 +49,8 @@ def unpack(theta: np.ndarray, C: int):
     return out
 
 
-def nparams(C: int) -> int:
-    return sum(int(np.prod(s)) for s in layer_shapes(C).values())
+def nparams(C: int, L: int) -> int:
+    return sum(int(np.prod(s)) for s in layer_shapes(C, L).values())
 
 
 def _taps():
@@ -116,7 +118,6 @@ def prolong(c: np.ndarray, shape) -> np.ndarray:
         idx_odd[ax] = slice(1, n - 1, 2)
         idx_lo[ax] = slice(0, n - 2, 2)
         idx_hi[ax] = slice(2, n, 2)
-        # only rows already filled along the earlier axes are interpolated here
         out[tuple(idx_odd)] = 0.5 * (out[tuple(idx_lo)] + out[tuple(idx_hi)])
     return out
 
@@ -125,54 +126,57 @@ def relu(a):
     return np.maximum(a, 0.0)
 
 
-def forward(theta: np.ndarray, C: int, x: np.ndarray, keep: bool = False):
-    """x: [B, n, n, n, 1] -> y: [B, n, n, n, 1]."""
-    W = unpack(theta, C)
-    n = x.shape[1:4]
-    h0 = relu(conv(x, W["A"]))
-    c1 = restrict(h0)
-    h1 = relu(conv(c1, W["B"]))
-    c2 = restrict(h1)
-    h2 = relu(conv(c2, W["C"]))
-    g2 = relu(conv(h2, W["D"]))
-    u1 = prolong(g2, h1.shape[1:4]) + h1
-    g1 = relu(conv(u1, W["E"]))
-    u0 = prolong(g1, n) + h0
-    y = conv(u0, W["F"])
+def forward(theta: np.ndarray, C: int, L: int, x: np.ndarray, keep: bool = False):
+    """x: [B, nz, ny, nx, 1] -> y: [B, nz, ny, nx, 1]."""
+    W = unpack(theta, C, L)
+    h = [relu(conv(x, W["A"]))]
+    c = [None]
+    for l in range(1, L):
+        c.append(restrict(h[l - 1]))
+        h.append(relu(conv(c[l], W[f"B{l}"])))
+    g = [None] * L
+    u = [None] * (L - 1)
+    g[L - 1] = relu(conv(h[L - 1], W["D"]))
+    for l in range(L - 2, -1, -1):
+        u[l] = prolong(g[l + 1], h[l].shape[1:4]) + h[l]
+        if l >= 1:
+            g[l] = relu(conv(u[l], W[f"E{l}"]))
+    y = x + conv(u[0], W["F"])
     if keep:
-        return y, dict(x=x, h0=h0, c1=c1, h1=h1, c2=c2, h2=h2, g2=g2, u1=u1, g1=g1, u0=u0)
+        return y, dict(x=x, h=h, c=c, g=g, u=u)
     return y
 
 
-def loss_and_grad(theta: np.ndarray, C: int, x: np.ndarray, t: np.ndarray):
+def loss_and_grad(theta: np.ndarray, C: int, L: int, x: np.ndarray, t: np.ndarray):
     """Batch-mean relative squared error and its gradient with respect to theta."""
-    W = unpack(theta, C)
-    y, a = forward(theta, C, x, keep=True)
+    W = unpack(theta, C, L)
+    y, a = forward(theta, C, L, x, keep=True)
+    h, c, g, u = a["h"], a["c"], a["g"], a["u"]
     B = x.shape[0]
     tt = np.sum(t.reshape(B, -1) ** 2, axis=1)
     diff = (y - t).reshape(B, -1)
     loss = float(np.mean(np.sum(diff ** 2, axis=1) / tt))
     gy = (2.0 / B) * (diff / tt[:, None]).reshape(y.shape)
     grads = {}
-    gu0, grads["F"] = conv_backward(a["u0"], W["F"], gy)
-    gh0 = gu0.copy()
-    gg1 = restrict(gu0) * 8.0  # P^T = 8 R
-    gg1 = gg1 * (a["g1"] > 0)
-    gu1, grads["E"] = conv_backward(a["u1"], W["E"], gg1)
-    gh1 = gu1.copy()
-    gg2 = restrict(gu1) * 8.0
-    gg2 = gg2 * (a["g2"] > 0)
-    gh2, grads["D"] = conv_backward(a["h2"], W["D"], gg2)
-    gh2 = gh2 * (a["h2"] > 0)
-    gc2, grads["C"] = conv_backward(a["c2"], W["C"], gh2)
-    gh1 = gh1 + prolong(gc2, a["h1"].shape[1:4]) / 8.0  # R^T = P / 8
-    gh1 = gh1 * (a["h1"] > 0)
-    gc1, grads["B"] = conv_backward(a["c1"], W["B"], gh1)
-    gh0 = gh0 + prolong(gc1, a["h0"].shape[1:4]) / 8.0
-    gh0 = gh0 * (a["h0"] > 0)
-    _, grads["A"] = conv_backward(a["x"], W["A"], gh0)
-    g = np.concatenate([grads[k].ravel() for k in LAYERS])
-    return loss, g
+    # decoder, fine to coarse: y = x + F u_0 (the skip from x carries no weight)
+    gu = [None] * (L - 1)
+    gu[0], grads["F"] = conv_backward(u[0], W["F"], gy)
+    gh = [None] * L
+    for l in range(0, L - 1):
+        gh[l] = gu[l].copy()  # u_l = P g_(l+1) + h_l
+        gg = restrict(gu[l]) * 8.0 * (g[l + 1] > 0)  # P^T = 8 R, then the relu of g_(l+1)
+        if l + 1 <= L - 2:
+            gu[l + 1], grads[f"E{l + 1}"] = conv_backward(u[l + 1], W[f"E{l + 1}"], gg)
+        else:
+            gh[L - 1], grads["D"] = conv_backward(h[L - 1], W["D"], gg)
+    # encoder, coarse to fine
+    for l in range(L - 1, 0, -1):
+        gpre = gh[l] * (h[l] > 0)
+        gc, grads[f"B{l}"] = conv_backward(c[l], W[f"B{l}"], gpre)
+        gh[l - 1] = gh[l - 1] + prolong(gc, h[l - 1].shape[1:4]) / 8.0  # R^T = P / 8
+    _, grads["A"] = conv_backward(x, W["A"], gh[0] * (h[0] > 0))
+    gvec = np.concatenate([grads[k].ravel() for k in layer_names(L)])
+    return loss, gvec
 
 
 def adam_step(theta, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
@@ -184,13 +188,13 @@ def adam_step(theta, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def precond_apply(theta, C, r, diag, grid_of_dof, shape, dirichlet=None):
+def precond_apply(theta, C, L, r, diag, grid_of_dof, shape, dirichlet=None):
     """z = D^{-1/2} N(D^{-1/2} r) on the lattice: dof i sits at linear index
     grid_of_dof[i] of a (z, y, x) lattice of `shape`; constrained dofs pass through."""
     s = 1.0 / np.sqrt(diag)
     g = np.zeros(int(np.prod(shape)))
     g[grid_of_dof] = s * r
-    y = forward(theta, C, g.reshape((1,) + tuple(shape) + (1,)))
+    y = forward(theta, C, L, g.reshape((1,) + tuple(shape) + (1,)))
     z = s * y.reshape(-1)[grid_of_dof]
     if dirichlet is not None:
         z = np.where(dirichlet, r, z)

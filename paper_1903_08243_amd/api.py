@@ -92,8 +92,8 @@ def load_library():
         "mf_op_destroy": (None, [P]),
         "mf_precond_destroy": (None, [P]),
         "mf_precond_apply": (I, [P, P, P, P]),
-        "mf_cnn_nparams": (I64, [I]),
-        "mf_cnn_create": (I, [I, P, PP]),
+        "mf_cnn_nparams": (I64, [I, I]),
+        "mf_cnn_create": (I, [I, I, P, PP]),
         "mf_cnn_get_params": (I, [P, P]),
         "mf_cnn_set_params": (I, [P, P]),
         "mf_cnn_save": (I, [P, ctypes.c_char_p]),
@@ -295,47 +295,36 @@ class JacobiPrecond(_Precond):
         self.handle = h
 
 
-def cnn_nparams(channels):
-    n = load_library().mf_cnn_nparams(channels)
+def cnn_nparams(channels, levels):
+    n = load_library().mf_cnn_nparams(channels, levels)
     if n < 0:
-        raise ValueError("channels must be 4, 8 or 16")
+        raise ValueError("channels must be 4, 8 or 16 and levels 2..8")
     return n
 
 
-def cnn_initial_weights(channels, seed=0, scale=0.05):
-    """Initial parameters: the network starts as the identity map (channel 0 of A
-    and F carries r through relu(r) - relu(-r) via channels 0 and 1), plus small
-    seeded Gaussian weights on every tap. Host float32 array."""
-    C = channels
-    sizes = [27 * C, 27 * C * C, 27 * C * C, 27 * C * C, 27 * C * C, 27 * C]
+def cnn_initial_weights(channels, levels, seed=0, scale=0.02):
+    """Initial parameters: small seeded Gaussian weights, so that the network starts
+    close to the identity (and the preconditioner close to Jacobi). Host float32."""
     g = np.random.default_rng([1903, 8243, seed])
-    th = (g.standard_normal(sum(sizes)) * scale).astype(np.float32)
-    offs = np.cumsum([0] + sizes)
-    A = th[offs[0]:offs[1]].reshape(27, 1, C)
-    F = th[offs[5]:offs[6]].reshape(27, C, 1)
-    A[13, 0, 0] += 1.0
-    A[13, 0, 1] -= 1.0
-    F[13, 0, 0] += 1.0
-    F[13, 1, 0] -= 1.0
-    return th
+    return (g.standard_normal(cnn_nparams(channels, levels)) * scale).astype(np.float32)
 
 
 class CNN:
     """The learned preconditioner's network (see include/mf.h). Lattices are
     float32 device tensors shaped [batch, nz, ny, nx]."""
 
-    def __init__(self, channels, theta=None, _handle=None):
+    def __init__(self, channels, levels, theta=None, _handle=None):
         L = load_library()
-        self.channels = channels
-        self.nparams = cnn_nparams(channels)
+        self.channels, self.levels = channels, levels
+        self.nparams = cnn_nparams(channels, levels)
         if _handle is not None:
             self.handle = _handle
             return
-        th = _np(cnn_initial_weights(channels) if theta is None else theta, np.float32)
+        th = _np(cnn_initial_weights(channels, levels) if theta is None else theta, np.float32)
         if th.size != self.nparams:
             raise ValueError(f"theta must have {self.nparams} entries")
         h = ctypes.c_void_p()
-        _check(L.mf_cnn_create(channels, th.ctypes.data, ctypes.byref(h)))
+        _check(L.mf_cnn_create(channels, levels, th.ctypes.data, ctypes.byref(h)))
         self.handle = h
 
     @classmethod
@@ -343,8 +332,8 @@ class CNN:
         h = ctypes.c_void_p()
         _check(load_library().mf_cnn_load(path.encode(), ctypes.byref(h)))
         with open(path, "rb") as f:  # the library validated the header
-            channels = int(np.frombuffer(f.read(12)[8:12], dtype="<i4")[0])
-        return cls(channels, _handle=h)
+            channels, levels = (int(v) for v in np.frombuffer(f.read(16)[8:16], dtype="<i4"))
+        return cls(channels, levels, _handle=h)
 
     def params(self):
         th = np.empty(self.nparams, np.float32)

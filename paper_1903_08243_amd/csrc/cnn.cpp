@@ -16,46 +16,10 @@
 
 namespace mf {
 
-static bool lattice_ok(int n) { return n >= 5 && (n - 1) % 4 == 0; }
-
-int CnnActs::ensure(const Grid3 &g, int c) {
-  if (g.B == g0.B && g.Z == g0.Z && g.Y == g0.Y && g.X == g0.X && c == C && h0.ptr) return MF_OK;
-  g0 = g;
-  g1 = coarser(g0);
-  g2 = coarser(g1);
-  C = 0;  // set once every buffer is allocated
-  const size_t f0 = (size_t)g0.points() * c * 4, f1 = (size_t)g1.points() * c * 4, f2 = (size_t)g2.points() * c * 4;
-  int rc = MF_OK;
-  for (auto pr : {std::make_pair(&h0, f0), std::make_pair(&u0, f0), std::make_pair(&c1, f1), std::make_pair(&h1, f1),
-                  std::make_pair(&u1, f1), std::make_pair(&g1b, f1), std::make_pair(&c2, f2), std::make_pair(&h2, f2),
-                  std::make_pair(&g2b, f2), std::make_pair(&y, (size_t)g0.points() * 4)}) {
-    DeviceBuffer &b = *pr.first;
-    if (b.ptr) {
-      (void)hipFree(b.ptr);
-      b.ptr = nullptr;
-      b.bytes = 0;
-    }
-    if (!rc) rc = b.alloc(pr.second);
-  }
-  if (!rc) C = c;
-  return rc;
-}
-
-static const float *layer(const float *theta, const CnnLayout &L, int l) { return theta + L.off[l]; }
-
-int cnn_forward(const float *theta, const CnnLayout &L, const float *x, CnnActs &a, hipStream_t s) {
-  const int C = L.C;
-  int rc = cnn_conv(x, layer(theta, L, 0), a.h0.as<float>(), nullptr, a.g0, 1, C, true, false, s);
-  if (!rc) rc = cnn_restrict(a.h0.as<float>(), a.c1.as<float>(), nullptr, 1.0f, a.g0, C, s);
-  if (!rc) rc = cnn_conv(a.c1.as<float>(), layer(theta, L, 1), a.h1.as<float>(), nullptr, a.g1, C, C, true, false, s);
-  if (!rc) rc = cnn_restrict(a.h1.as<float>(), a.c2.as<float>(), nullptr, 1.0f, a.g1, C, s);
-  if (!rc) rc = cnn_conv(a.c2.as<float>(), layer(theta, L, 2), a.h2.as<float>(), nullptr, a.g2, C, C, true, false, s);
-  if (!rc) rc = cnn_conv(a.h2.as<float>(), layer(theta, L, 3), a.g2b.as<float>(), nullptr, a.g2, C, C, true, false, s);
-  if (!rc) rc = cnn_prolong_add(a.g2b.as<float>(), a.h1.as<float>(), a.u1.as<float>(), nullptr, 1.0f, a.g1, C, s);
-  if (!rc) rc = cnn_conv(a.u1.as<float>(), layer(theta, L, 4), a.g1b.as<float>(), nullptr, a.g1, C, C, true, false, s);
-  if (!rc) rc = cnn_prolong_add(a.g1b.as<float>(), a.h0.as<float>(), a.u0.as<float>(), nullptr, 1.0f, a.g0, C, s);
-  if (!rc) rc = cnn_conv(a.u0.as<float>(), layer(theta, L, 5), a.y.as<float>(), nullptr, a.g0, C, 1, false, false, s);
-  return rc;
+// every direction: (n - 1) divisible by 2^(L-1) with a coarsest lattice of at least 2 points
+static bool lattice_ok(int n, int L) {
+  const int q = 1 << (L - 1);
+  return n >= q + 1 && (n - 1) % q == 0;
 }
 
 // Grows a buffer to at least `bytes`.
@@ -69,63 +33,99 @@ static int grow(DeviceBuffer &b, size_t bytes) {
   return b.alloc(bytes);
 }
 
+int CnnActs::ensure(const Grid3 &g0, int c, int levels) {
+  const Grid3 &o = grid[0];
+  if (g0.B == o.B && g0.Z == o.Z && g0.Y == o.Y && g0.X == o.X && c == C && levels == L && h[0].ptr) return MF_OK;
+  C = 0;  // set once every buffer is allocated
+  L = levels;
+  grid[0] = g0;
+  for (int l = 1; l < L; l++) grid[l] = coarser(grid[l - 1]);
+  int rc = MF_OK;
+  for (int l = 0; l < L && !rc; l++) {
+    const size_t f = (size_t)grid[l].points() * c * 4;
+    rc = grow(h[l], f);
+    if (!rc && l >= 1) rc = grow(this->c[l], f);
+    if (!rc && l >= 1) rc = grow(g[l], f);
+    if (!rc && l <= L - 2) rc = grow(u[l], f);
+  }
+  if (!rc) rc = grow(y, (size_t)g0.points() * 4);
+  if (!rc) C = c;
+  return rc;
+}
+
+int cnn_forward(const float *theta, const CnnLayout &Ly, const float *x, CnnActs &a, hipStream_t s) {
+  const int C = Ly.C, L = Ly.L;
+  auto F = [&](DeviceBuffer &b) { return b.as<float>(); };
+  int rc = cnn_conv(x, theta + Ly.A(), F(a.h[0]), nullptr, a.grid[0], 1, C, true, false, s);
+  for (int l = 1; l < L && !rc; l++) {
+    rc = cnn_restrict(F(a.h[l - 1]), F(a.c[l]), nullptr, 1.0f, a.grid[l - 1], C, s);
+    if (!rc) rc = cnn_conv(F(a.c[l]), theta + Ly.B(l), F(a.h[l]), nullptr, a.grid[l], C, C, true, false, s);
+  }
+  if (!rc) rc = cnn_conv(F(a.h[L - 1]), theta + Ly.Dl(), F(a.g[L - 1]), nullptr, a.grid[L - 1], C, C, true, false, s);
+  for (int l = L - 2; l >= 0 && !rc; l--) {
+    rc = cnn_prolong_add(F(a.g[l + 1]), F(a.h[l]), F(a.u[l]), nullptr, 1.0f, a.grid[l], C, s);
+    if (!rc && l >= 1) rc = cnn_conv(F(a.u[l]), theta + Ly.E(l), F(a.g[l]), nullptr, a.grid[l], C, C, true, false, s);
+  }
+  // y = x + F u_0
+  if (!rc) rc = cnn_conv(F(a.u[0]), theta + Ly.F(), F(a.y), nullptr, a.grid[0], C, 1, false, false, s, x);
+  return rc;
+}
+
 // Loss of the batch (x, t) and the gradient of every weight into net->grad.
 // x, t: [B][Z][Y][X]; the loss (FP64) is left in net->loss on the device.
-static int loss_grad(mf_cnn *net, const Grid3 &g, const float *x, const float *t, hipStream_t s) {
-  const int C = net->C;
-  const CnnLayout &L = net->L;
+static int loss_grad(mf_cnn *net, const Grid3 &g0, const float *x, const float *t, hipStream_t s) {
+  const int C = net->C, L = net->levels;
+  const CnnLayout &Ly = net->L;
   CnnActs &a = net->acts;
-  int rc = a.ensure(g, C);
+  int rc = a.ensure(g0, C, L);
   if (rc) return rc;
-  const size_t f0 = (size_t)a.g0.points() * C * 4, f1 = (size_t)a.g1.points() * C * 4;
   int64_t pf = 0;
-  for (const Grid3 *gg : {&a.g0, &a.g1, &a.g2}) {
-    const int64_t v = cnn_wgrad_part_floats(*gg, C, C);
+  for (int l = 0; l < L; l++) {
+    const int64_t v = cnn_wgrad_part_floats(a.grid[l], C, C);
     pf = v > pf ? v : pf;
+    rc = grow(net->gh[l], (size_t)a.grid[l].points() * C * 4);
+    if (rc) return rc;
   }
-  if (!rc) rc = grow(net->gy, (size_t)a.g0.points() * 4);
-  if (!rc) rc = grow(net->gA, f0);
-  if (!rc) rc = grow(net->gB, f1);
-  if (!rc) rc = grow(net->gC, f1);
+  const size_t f1 = (size_t)a.grid[1].points() * C * 4;
+  if (!rc) rc = grow(net->gy, (size_t)g0.points() * 4);
+  if (!rc) rc = grow(net->s1, f1);
+  if (!rc) rc = grow(net->s2, f1);
   if (!rc) rc = grow(net->part, (size_t)pf * 4);
-  if (!rc) rc = grow(net->lpart, (size_t)cnn_loss_part_doubles(g.B) * 8);
+  if (!rc) rc = grow(net->lpart, (size_t)cnn_loss_part_doubles(g0.B) * 8);
   if (!rc) rc = grow(net->loss, 8);
   if (rc) return rc;
+  auto F = [&](DeviceBuffer &b) { return b.as<float>(); };
   const float *th = net->theta.as<float>();
   float *gr = net->grad.as<float>();
   float *part = net->part.as<float>();
-  rc = cnn_forward(th, L, x, a, s);
-  if (!rc) rc = cnn_loss(a.y.as<float>(), t, net->gy.as<float>(), net->loss.as<double>(), net->lpart.as<double>(),
-                         g.B, (int64_t)g.Z * g.Y * g.X, s);
-  // y = F u0
-  float *gu0 = net->gA.as<float>();  // becomes g(h0) after the skip contribution
-  if (!rc) rc = cnn_wgrad(a.u0.as<float>(), net->gy.as<float>(), gr + L.off[5], part, a.g0, C, 1, s);
-  if (!rc) rc = cnn_conv(net->gy.as<float>(), layer(th, L, 5), gu0, nullptr, a.g0, 1, C, false, true, s);
-  // u0 = P g1 + h0, g1 = relu(E u1): g(g1) = 8 R g(u0) masked by g1 > 0
-  float *gg1 = net->gB.as<float>();
-  if (!rc) rc = cnn_restrict(gu0, gg1, a.g1b.as<float>(), 8.0f, a.g0, C, s);
-  float *gu1 = net->gC.as<float>();  // becomes g(h1)
-  if (!rc) rc = cnn_wgrad(a.u1.as<float>(), gg1, gr + L.off[4], part, a.g1, C, C, s);
-  if (!rc) rc = cnn_conv(gg1, layer(th, L, 4), gu1, nullptr, a.g1, C, C, false, true, s);
-  // u1 = P g2 + h1, g2 = relu(D h2): g(g2) = 8 R g(u1) masked by g2 > 0 (coarsest grid; reuse gB's head)
-  float *gg2 = net->gB.as<float>();
-  if (!rc) rc = cnn_restrict(gu1, gg2, a.g2b.as<float>(), 8.0f, a.g1, C, s);
-  // h2 = relu(C c2): g(h2) = D^T g(g2) masked by h2 > 0
-  float *gh2 = net->gB.as<float>() + (size_t)a.g2.points() * C;
-  if (!rc) rc = cnn_wgrad(a.h2.as<float>(), gg2, gr + L.off[3], part, a.g2, C, C, s);
-  if (!rc) rc = cnn_conv(gg2, layer(th, L, 3), gh2, a.h2.as<float>(), a.g2, C, C, false, true, s);
-  float *gc2 = net->gB.as<float>();  // g(g2) no longer needed
-  if (!rc) rc = cnn_wgrad(a.c2.as<float>(), gh2, gr + L.off[2], part, a.g2, C, C, s);
-  if (!rc) rc = cnn_conv(gh2, layer(th, L, 2), gc2, nullptr, a.g2, C, C, false, true, s);
-  // c2 = R h1: g(h1) += R^T g(c2) = P g(c2) / 8, then masked by h1 > 0
-  if (!rc) rc = cnn_prolong_add(gc2, gu1, gu1, a.h1.as<float>(), 0.125f, a.g1, C, s);
-  float *gc1 = net->gB.as<float>();
-  if (!rc) rc = cnn_wgrad(a.c1.as<float>(), gu1, gr + L.off[1], part, a.g1, C, C, s);
-  if (!rc) rc = cnn_conv(gu1, layer(th, L, 1), gc1, nullptr, a.g1, C, C, false, true, s);
-  // c1 = R h0: g(h0) = g(u0) + P g(c1) / 8, masked by h0 > 0
-  if (!rc) rc = cnn_prolong_add(gc1, gu0, gu0, a.h0.as<float>(), 0.125f, a.g0, C, s);
-  if (!rc) rc = cnn_wgrad(x, gu0, gr + L.off[0], part, a.g0, 1, C, s);
-  (void)f1;
+  float *S1 = F(net->s1), *S2 = F(net->s2);
+  rc = cnn_forward(th, Ly, x, a, s);
+  if (!rc) rc = cnn_loss(F(a.y), t, F(net->gy), net->loss.as<double>(), net->lpart.as<double>(), g0.B,
+                         (int64_t)g0.Z * g0.Y * g0.X, s);
+  // decoder, fine to coarse. y = x + F u_0: gh[0] starts as g(u_0) (the skip u_0 = P g_1 + h_0)
+  if (!rc) rc = cnn_wgrad(F(a.u[0]), F(net->gy), gr + Ly.F(), part, a.grid[0], C, 1, s);
+  if (!rc) rc = cnn_conv(F(net->gy), th + Ly.F(), F(net->gh[0]), nullptr, a.grid[0], 1, C, false, true, s);
+  for (int l = 0; l < L - 1 && !rc; l++) {
+    // g(g_(l+1)) = 8 R g(u_l) masked by g_(l+1) > 0
+    rc = cnn_restrict(F(net->gh[l]), S1, F(a.g[l + 1]), 8.0f, a.grid[l], C, s);
+    if (rc) break;
+    if (l + 1 <= L - 2) {  // g_(l+1) = relu(E_(l+1) u_(l+1)): g(u_(l+1)) starts gh[l+1]
+      rc = cnn_wgrad(F(a.u[l + 1]), S1, gr + Ly.E(l + 1), part, a.grid[l + 1], C, C, s);
+      if (!rc) rc = cnn_conv(S1, th + Ly.E(l + 1), F(net->gh[l + 1]), nullptr, a.grid[l + 1], C, C, false, true, s);
+    } else {  // g_(L-1) = relu(D h_(L-1)): g(h_(L-1)), masked by h_(L-1) > 0
+      rc = cnn_wgrad(F(a.h[L - 1]), S1, gr + Ly.Dl(), part, a.grid[L - 1], C, C, s);
+      if (!rc)
+        rc = cnn_conv(S1, th + Ly.Dl(), F(net->gh[L - 1]), F(a.h[L - 1]), a.grid[L - 1], C, C, false, true, s);
+    }
+  }
+  // encoder, coarse to fine: gh[l] holds the pre-activation gradient of h_l
+  for (int l = L - 1; l >= 1 && !rc; l--) {
+    rc = cnn_wgrad(F(a.c[l]), F(net->gh[l]), gr + Ly.B(l), part, a.grid[l], C, C, s);
+    if (!rc) rc = cnn_conv(F(net->gh[l]), th + Ly.B(l), S2, nullptr, a.grid[l], C, C, false, true, s);
+    // c_l = R h_(l-1): g(h_(l-1)) += P g(c_l) / 8, then masked by h_(l-1) > 0
+    if (!rc) rc = cnn_prolong_add(S2, F(net->gh[l - 1]), F(net->gh[l - 1]), F(a.h[l - 1]), 0.125f, a.grid[l - 1], C, s);
+  }
+  if (!rc) rc = cnn_wgrad(x, F(net->gh[0]), gr + Ly.A(), part, a.grid[0], 1, C, s);
   return rc;
 }
 
@@ -137,11 +137,14 @@ static int adam(mf_cnn *net, float lr, hipStream_t s) {
                   net->L.nparams(), lr, (float)b1, (float)b2, 1e-8f, (float)bc1, (float)bc2, s);
 }
 
-static int check_grid(int B, int nz, int ny, int nx, const char *who) {
-  if (B < 1 || !lattice_ok(nz) || !lattice_ok(ny) || !lattice_ok(nx))
-    return fail(MF_EINVAL, std::string(who) + ": lattice sizes must be 4m+1 (m >= 1) and batch >= 1");
+static int check_grid(int B, int nz, int ny, int nx, int L, const char *who) {
+  if (B < 1 || !lattice_ok(nz, L) || !lattice_ok(ny, L) || !lattice_ok(nx, L))
+    return fail(MF_EINVAL, std::string(who) + ": every lattice size must be j 2^(L-1) + 1 (j >= 1), batch >= 1");
   return MF_OK;
 }
+
+static bool channels_ok(int c) { return c == 4 || c == 8 || c == 16; }
+static bool levels_ok(int l) { return l >= 2 && l <= CNN_MAX_LEVELS; }
 
 }  // namespace mf
 
@@ -149,25 +152,26 @@ using namespace mf;
 
 struct CnnFileHeader {
   char magic[8];
-  int32_t channels, pad;
+  int32_t channels, levels;
   int64_t nparams;
 };
 
 extern "C" {
 
-int64_t mf_cnn_nparams(int channels) {
-  if (channels != 4 && channels != 8 && channels != 16) return -1;
-  return CnnLayout(channels).nparams();
+int64_t mf_cnn_nparams(int channels, int levels) {
+  if (!channels_ok(channels) || !levels_ok(levels)) return -1;
+  return CnnLayout(channels, levels).nparams();
 }
 
-int mf_cnn_create(int channels, const float *theta, mf_cnn **out) {
+int mf_cnn_create(int channels, int levels, const float *theta, mf_cnn **out) {
   if (!out || !theta) return fail(MF_EINVAL, "mf_cnn_create: null argument");
-  if (channels != 4 && channels != 8 && channels != 16)
-    return fail(MF_EUNSUPPORTED, "mf_cnn_create: channels must be 4, 8 or 16");
+  if (!channels_ok(channels) || !levels_ok(levels))
+    return fail(MF_EUNSUPPORTED, "mf_cnn_create: channels must be 4, 8 or 16 and levels 2..8");
   std::unique_ptr<mf_cnn> net(new (std::nothrow) mf_cnn);
   if (!net) return fail(MF_ENOMEM, "mf_cnn_create: host allocation");
   net->C = channels;
-  net->L = CnnLayout(channels);
+  net->levels = levels;
+  net->L = CnnLayout(channels, levels);
   const size_t nb = (size_t)net->L.nparams() * 4;
   int rc = net->theta.alloc(nb);
   if (!rc) rc = net->grad.alloc(nb);
@@ -208,8 +212,9 @@ int mf_cnn_save(const mf_cnn *net, const char *path) {
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(MF_EINVAL, std::string("mf_cnn_save: cannot open ") + path);
   CnnFileHeader h{};
-  std::memcpy(h.magic, "MFCNN01", 8);
+  std::memcpy(h.magic, "MFCNN02", 8);
   h.channels = net->C;
+  h.levels = net->levels;
   h.nparams = net->L.nparams();
   const bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 && std::fwrite(th.data(), 4, th.size(), f) == th.size();
   if (std::fclose(f) != 0 || !ok) return fail(MF_EINVAL, std::string("mf_cnn_save: write failed: ") + path);
@@ -221,8 +226,9 @@ int mf_cnn_load(const char *path, mf_cnn **out) {
   FILE *f = std::fopen(path, "rb");
   if (!f) return fail(MF_EINVAL, std::string("mf_cnn_load: cannot open ") + path);
   CnnFileHeader h{};
-  bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "MFCNN01", 8) == 0 &&
-            (h.channels == 4 || h.channels == 8 || h.channels == 16) && h.nparams == CnnLayout(h.channels).nparams();
+  bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "MFCNN02", 8) == 0 &&
+            channels_ok(h.channels) && levels_ok(h.levels) &&
+            h.nparams == CnnLayout(h.channels, h.levels).nparams();
   std::vector<float> th;
   if (ok) {
     th.resize((size_t)h.nparams);
@@ -230,7 +236,7 @@ int mf_cnn_load(const char *path, mf_cnn **out) {
   }
   std::fclose(f);
   if (!ok) return fail(MF_EINVAL, std::string("mf_cnn_load: not a network file: ") + path);
-  return mf_cnn_create(h.channels, th.data(), out);
+  return mf_cnn_create(h.channels, h.levels, th.data(), out);
 }
 
 void mf_cnn_destroy(mf_cnn *net) {
@@ -241,11 +247,11 @@ void mf_cnn_destroy(mf_cnn *net) {
 
 int mf_cnn_forward(mf_cnn *net, int batch, int nz, int ny, int nx, const float *x, float *y, void *stream) {
   if (!net || !x || !y) return fail(MF_EINVAL, "mf_cnn_forward: null argument");
-  int rc = check_grid(batch, nz, ny, nx, "mf_cnn_forward");
+  int rc = check_grid(batch, nz, ny, nx, net->levels, "mf_cnn_forward");
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   const Grid3 g{batch, nz, ny, nx};
-  rc = net->acts.ensure(g, net->C);
+  rc = net->acts.ensure(g, net->C, net->levels);
   if (!rc) rc = cnn_forward(net->theta.as<float>(), net->L, x, net->acts, s);
   if (rc) return rc;
   MF_HIP(hipMemcpyAsync(y, net->acts.y.ptr, (size_t)g.points() * 4, hipMemcpyDeviceToDevice, s));
@@ -255,7 +261,7 @@ int mf_cnn_forward(mf_cnn *net, int batch, int nz, int ny, int nx, const float *
 int mf_cnn_loss_grad(mf_cnn *net, int batch, int nz, int ny, int nx, const float *x, const float *t, double *loss,
                      float *grad, void *stream) {
   if (!net || !x || !t) return fail(MF_EINVAL, "mf_cnn_loss_grad: null argument");
-  int rc = check_grid(batch, nz, ny, nx, "mf_cnn_loss_grad");
+  int rc = check_grid(batch, nz, ny, nx, net->levels, "mf_cnn_loss_grad");
   if (rc) return rc;
   hipStream_t s = (hipStream_t)stream;
   rc = loss_grad(net, Grid3{batch, nz, ny, nx}, x, t, s);
@@ -273,7 +279,7 @@ int mf_cnn_train(mf_cnn *net, int npairs, int n, const float *r, const float *e,
                  const int32_t *order, float lr, double *losses, void *stream) {
   if (!net || !r || !e || !order) return fail(MF_EINVAL, "mf_cnn_train: null argument");
   if (npairs < 1 || nsteps < 0 || !(lr > 0.0f)) return fail(MF_EINVAL, "mf_cnn_train: npairs / nsteps / lr");
-  int rc = check_grid(batch, n, n, n, "mf_cnn_train");
+  int rc = check_grid(batch, n, n, n, net->levels, "mf_cnn_train");
   if (rc) return rc;
   for (int64_t i = 0; i < (int64_t)nsteps * batch; i++)
     if (order[i] < 0 || order[i] >= npairs) return fail(MF_EINVAL, "mf_cnn_train: order index out of range");
@@ -309,7 +315,7 @@ int mf_precond_create_cnn(const mf_op *A, const mf_cnn *net, int nz, int ny, int
                           void *stream, mf_precond **out) {
   if (!A || !net || !node_grid || !out) return fail(MF_EINVAL, "mf_precond_create_cnn: null argument");
   if (A->ncomp != 1) return fail(MF_EUNSUPPORTED, "mf_precond_create_cnn: scalar spaces only");
-  int rc = check_grid(1, nz, ny, nx, "mf_precond_create_cnn");
+  int rc = check_grid(1, nz, ny, nx, net->levels, "mf_precond_create_cnn");
   if (rc) return rc;
   const int64_t n = A->ndofs;
   if ((int64_t)nz * ny * nx != n) return fail(MF_EINVAL, "mf_precond_create_cnn: lattice size != number of nodes");
@@ -343,7 +349,7 @@ int mf_precond_create_cnn(const mf_op *A, const mf_cnn *net, int nz, int ny, int
   if (!rc) rc = P->bc.alloc((size_t)n);
   if (!rc) rc = P->gin.alloc((size_t)n * 4);
   if (!rc) rc = P->gaux.alloc((size_t)n * 4);
-  if (!rc) rc = P->acts.ensure(Grid3{1, nz, ny, nx}, net->C);
+  if (!rc) rc = P->acts.ensure(Grid3{1, nz, ny, nx}, net->C, net->levels);
   if (rc) return rc;
   MF_HIP(hipMemcpyAsync(P->gidx.ptr, gi.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
   MF_HIP(hipMemsetAsync(P->bc.ptr, 0, (size_t)n, s));

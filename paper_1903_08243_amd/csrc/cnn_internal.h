@@ -1,30 +1,37 @@
 // Learned convolutional preconditioner: network object, kernels and launchers.
 //
-// The network is a three-level U-Net on channel-last FP32 lattices
-// ([batch][z][y][x][channel]) with n = 4 m + 1 points per direction:
-//   h0 = relu(A x); c1 = R h0; h1 = relu(B c1); c2 = R h1; h2 = relu(C c2);
-//   g2 = relu(D h2); u1 = P g2 + h1; g1 = relu(E u1); u0 = P g1 + h0; y = F u0.
+// The network is an L-level U-Net on channel-last FP32 lattices
+// ([batch][z][y][x][channel]) with (n - 1) divisible by 2^(L-1) per direction:
+//   h_0 = relu(A x);  c_l = R h_(l-1), h_l = relu(B_l c_l)     (l = 1 .. L-1)
+//   g_(L-1) = relu(D h_(L-1));  u_l = P g_(l+1) + h_l         (l = L-2 .. 0)
+//   g_l = relu(E_l u_l) (l = L-2 .. 1);  y = x + F u_0.
 // Convolutions have 3x3x3 taps, zero padding and no bias; weights W[tap][cin][cout]
 // with tap = (dx+1) + 3 (dy+1) + 9 (dz+1) and out[v] = sum_d in[v + d] W[tap(d)].
 // R is full weighting (1/4, 1/2, 1/4 per direction), P trilinear interpolation
-// (P^T = 8 R). Without biases the network is positively homogeneous of degree one.
+// (P^T = 8 R). Without biases the network is positively homogeneous of degree one,
+// and with zero weights it is the identity.
 #pragma once
 #include "mf_internal.h"
 
 namespace mf {
 
-constexpr int CNN_LAYERS = 6;
+constexpr int CNN_MAX_LEVELS = 8;
 
-// Offsets of the six weight tensors in the flat parameter vector.
+// Offsets of the 2L weight tensors in the flat parameter vector, stored in the
+// order A, B_1 .. B_(L-1), D, E_(L-2) .. E_1, F.
 struct CnnLayout {
-  int C = 0;
-  int64_t off[CNN_LAYERS + 1] = {};
-  explicit CnnLayout(int c = 0) : C(c) {
-    const int64_t sz[CNN_LAYERS] = {27LL * c, 27LL * c * c, 27LL * c * c, 27LL * c * c, 27LL * c * c, 27LL * c};
+  int C = 0, L = 0;
+  int64_t off[2 * CNN_MAX_LEVELS + 1] = {};
+  CnnLayout(int c = 0, int levels = 0) : C(c), L(levels) {
     off[0] = 0;
-    for (int l = 0; l < CNN_LAYERS; l++) off[l + 1] = off[l] + sz[l];
+    for (int t = 0; t < 2 * L; t++) off[t + 1] = off[t] + ((t == 0 || t == 2 * L - 1) ? 27LL * c : 27LL * c * c);
   }
-  int64_t nparams() const { return off[CNN_LAYERS]; }
+  int64_t nparams() const { return off[2 * L]; }
+  int64_t A() const { return off[0]; }
+  int64_t B(int l) const { return off[l]; }                  // l = 1 .. L-1
+  int64_t Dl() const { return off[L]; }
+  int64_t E(int l) const { return off[L + (L - 1 - l)]; }    // l = L-2 .. 1
+  int64_t F() const { return off[2 * L - 1]; }
 };
 
 struct Grid3 {
@@ -33,12 +40,12 @@ struct Grid3 {
 };
 inline Grid3 coarser(const Grid3 &g) { return {g.B, (g.Z + 1) / 2, (g.Y + 1) / 2, (g.X + 1) / 2}; }
 
-// out = conv(in) (channels ci -> co), optional ReLU; FLIP: the transposed
+// out = conv(in) (channels ci -> co) [+ add], optional ReLU; FLIP: the transposed
 // convolution of the backward pass (taps mirrored, weight W[t][co][ci] of the
 // forward layer with ci/co swapped), its result multiplied by (mask > 0) if mask
 // is set.
 int cnn_conv(const float *in, const float *W, float *out, const float *mask, const Grid3 &g, int ci, int co,
-             bool relu, bool flip, hipStream_t s);
+             bool relu, bool flip, hipStream_t s, const float *add = nullptr);
 // dW[t][ci][co] = sum over points of a[v + d_t][ci] g[v][co]; partials per chunk,
 // then an ordered FP64 sum over chunks (deterministic). part: workspace of
 // cnn_wgrad_part_floats(g, ci, co) floats.
@@ -73,25 +80,26 @@ int cnn_crops(const float *gr, const float *ge, int Z, int Y, int X, const int32
               float *r_out, float *e_out, hipStream_t s);
 int cnn_mark(const int32_t *idx, int64_t n, uint8_t *mask, hipStream_t s);
 
-// Activations of one forward pass (kept for the backward pass when training).
+// Activations of one forward pass (kept for the backward pass when training):
+// per level l the lattice grid[l], h[l], c[l] (l >= 1), g[l] (l >= 1), u[l] (l <= L-2).
 struct CnnActs {
-  Grid3 g0{}, g1{}, g2{};
-  int C = 0;
-  DeviceBuffer h0, c1, h1, c2, h2, g2b, u1, g1b, u0, y;
-  int ensure(const Grid3 &g, int C);
+  Grid3 grid[CNN_MAX_LEVELS] = {};
+  int C = 0, L = 0;
+  DeviceBuffer h[CNN_MAX_LEVELS], c[CNN_MAX_LEVELS], g[CNN_MAX_LEVELS], u[CNN_MAX_LEVELS], y;
+  int ensure(const Grid3 &g0, int C, int L);
 };
 
-// Forward pass over g0 (x: [B][Z][Y][X], one channel); result in a.y.
+// Forward pass over a.grid[0] (x: [B][Z][Y][X], one channel); result in a.y.
 int cnn_forward(const float *theta, const CnnLayout &L, const float *x, CnnActs &a, hipStream_t s);
 
 }  // namespace mf
 
 struct mf_cnn {
-  int C = 0;
+  int C = 0, levels = 0;
   mf::CnnLayout L;
   mf::DeviceBuffer theta, grad, m, v;
   int64_t step = 0;  // Adam steps taken
   // training workspaces (grown on demand)
   mf::CnnActs acts;
-  mf::DeviceBuffer xb, tb, gy, gA, gB, gC, part, lpart, loss;
+  mf::DeviceBuffer xb, tb, gy, gh[mf::CNN_MAX_LEVELS], s1, s2, part, lpart, loss;
 };

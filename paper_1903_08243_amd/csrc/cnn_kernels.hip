@@ -23,8 +23,8 @@ __device__ __forceinline__ void decode(int64_t p, int X, int Y, int Z, int &b, i
 // ------------------------------------------------------------------ convolution
 template <int CI, int CO, bool FLIP, bool RELU>
 __global__ void __launch_bounds__(CB) conv_kernel(const float *__restrict__ in, const float *__restrict__ W,
-                                                  float *__restrict__ out, const float *__restrict__ mask, int B,
-                                                  int Z, int Y, int X) {
+                                                  float *__restrict__ out, const float *__restrict__ mask,
+                                                  const float *__restrict__ add, int B, int Z, int Y, int X) {
   const int64_t np = (int64_t)B * Z * Y * X;
   const int64_t p = (int64_t)blockIdx.x * CB + threadIdx.x;
   if (p >= np) return;
@@ -61,43 +61,44 @@ __global__ void __launch_bounds__(CB) conv_kernel(const float *__restrict__ in, 
   for (int o = 0; o < CO; o++) {
     float r = RELU ? fmaxf(acc[o], 0.0f) : acc[o];
     if (mask) r = mask[p * CO + o] > 0.0f ? r : 0.0f;
+    if (add) r += add[p * CO + o];
     dst[o] = r;
   }
 }
 
 template <int CI, int CO>
-static int conv_launch(const float *in, const float *W, float *out, const float *mask, const Grid3 &g, bool relu,
-                       bool flip, hipStream_t s) {
+static int conv_launch(const float *in, const float *W, float *out, const float *mask, const float *add,
+                       const Grid3 &g, bool relu, bool flip, hipStream_t s) {
   const int64_t np = g.points();
   const unsigned nb = (unsigned)((np + CB - 1) / CB);
   if (flip) {
-    if (relu) conv_kernel<CI, CO, true, true><<<nb, CB, 0, s>>>(in, W, out, mask, g.B, g.Z, g.Y, g.X);
-    else conv_kernel<CI, CO, true, false><<<nb, CB, 0, s>>>(in, W, out, mask, g.B, g.Z, g.Y, g.X);
+    if (relu) conv_kernel<CI, CO, true, true><<<nb, CB, 0, s>>>(in, W, out, mask, add, g.B, g.Z, g.Y, g.X);
+    else conv_kernel<CI, CO, true, false><<<nb, CB, 0, s>>>(in, W, out, mask, add, g.B, g.Z, g.Y, g.X);
   } else {
-    if (relu) conv_kernel<CI, CO, false, true><<<nb, CB, 0, s>>>(in, W, out, mask, g.B, g.Z, g.Y, g.X);
-    else conv_kernel<CI, CO, false, false><<<nb, CB, 0, s>>>(in, W, out, mask, g.B, g.Z, g.Y, g.X);
+    if (relu) conv_kernel<CI, CO, false, true><<<nb, CB, 0, s>>>(in, W, out, mask, add, g.B, g.Z, g.Y, g.X);
+    else conv_kernel<CI, CO, false, false><<<nb, CB, 0, s>>>(in, W, out, mask, add, g.B, g.Z, g.Y, g.X);
   }
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
 
 template <int C>
-static int conv_dispatch(const float *in, const float *W, float *out, const float *mask, const Grid3 &g, int ci,
-                         int co, bool relu, bool flip, hipStream_t s) {
-  if (ci == 1 && co == C) return conv_launch<1, C>(in, W, out, mask, g, relu, flip, s);
-  if (ci == C && co == C) return conv_launch<C, C>(in, W, out, mask, g, relu, flip, s);
-  if (ci == C && co == 1) return conv_launch<C, 1>(in, W, out, mask, g, relu, flip, s);
+static int conv_dispatch(const float *in, const float *W, float *out, const float *mask, const float *add,
+                         const Grid3 &g, int ci, int co, bool relu, bool flip, hipStream_t s) {
+  if (ci == 1 && co == C) return conv_launch<1, C>(in, W, out, mask, add, g, relu, flip, s);
+  if (ci == C && co == C) return conv_launch<C, C>(in, W, out, mask, add, g, relu, flip, s);
+  if (ci == C && co == 1) return conv_launch<C, 1>(in, W, out, mask, add, g, relu, flip, s);
   return fail(MF_EUNSUPPORTED, "cnn_conv: channel pair");
 }
 
 int cnn_conv(const float *in, const float *W, float *out, const float *mask, const Grid3 &g, int ci, int co,
-             bool relu, bool flip, hipStream_t s) {
+             bool relu, bool flip, hipStream_t s, const float *add) {
   if (g.points() == 0) return MF_OK;
   const int C = ci > co ? ci : co;
   switch (C) {
-    case 4: return conv_dispatch<4>(in, W, out, mask, g, ci, co, relu, flip, s);
-    case 8: return conv_dispatch<8>(in, W, out, mask, g, ci, co, relu, flip, s);
-    case 16: return conv_dispatch<16>(in, W, out, mask, g, ci, co, relu, flip, s);
+    case 4: return conv_dispatch<4>(in, W, out, mask, add, g, ci, co, relu, flip, s);
+    case 8: return conv_dispatch<8>(in, W, out, mask, add, g, ci, co, relu, flip, s);
+    case 16: return conv_dispatch<16>(in, W, out, mask, add, g, ci, co, relu, flip, s);
   }
   return fail(MF_EUNSUPPORTED, "cnn_conv: channels must be 4, 8 or 16");
 }

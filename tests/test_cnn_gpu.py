@@ -33,33 +33,34 @@ def _rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-def _theta(C, seed, scale=0.3):
-    return (np.random.default_rng(seed).standard_normal(conv.nparams(C)) * scale).astype(np.float32)
+def _theta(C, L, seed, scale=0.3):
+    return (np.random.default_rng(seed).standard_normal(conv.nparams(C, L)) * scale).astype(np.float32)
 
 
-@pytest.mark.parametrize("C,shape,B", [(4, (9, 9, 9), 2), (8, (13, 5, 9), 1), (16, (5, 9, 5), 2)])
-def test_forward_matches_oracle(mf, C, shape, B):
+@pytest.mark.parametrize("C,L,shape,B", [(4, 3, (9, 9, 9), 2), (8, 2, (13, 5, 9), 1), (16, 3, (5, 9, 5), 2),
+                                         (4, 4, (9, 17, 9), 1)])
+def test_forward_matches_oracle(mf, C, L, shape, B):
     import torch
-    print(f"cnn forward C={C} shape={shape} B={B}", flush=True)
-    th = _theta(C, C)
+    print(f"cnn forward C={C} L={L} shape={shape} B={B}", flush=True)
+    th = _theta(C, L, C + L)
     x = np.random.default_rng(1).standard_normal((B,) + shape).astype(np.float32)
-    net = mf.CNN(C, th)
+    net = mf.CNN(C, L, th)
     y = net.forward(torch.tensor(x, device="cuda")).cpu().numpy()
-    ref = conv.forward(th.astype(np.float64), C, x.astype(np.float64)[..., None])[..., 0]
+    ref = conv.forward(th.astype(np.float64), C, L, x.astype(np.float64)[..., None])[..., 0]
     assert _rel(y, ref) <= TOL32
 
 
-@pytest.mark.parametrize("C,n,B", [(4, 9, 2), (8, 13, 3)])
-def test_loss_and_gradient_match_oracle(mf, C, n, B):
+@pytest.mark.parametrize("C,L,n,B", [(4, 3, 9, 2), (8, 4, 17, 2), (4, 2, 13, 3)])
+def test_loss_and_gradient_match_oracle(mf, C, L, n, B):
     import torch
-    print(f"cnn loss/grad C={C} n={n} B={B}", flush=True)
-    th = _theta(C, 10 + C)
+    print(f"cnn loss/grad C={C} L={L} n={n} B={B}", flush=True)
+    th = _theta(C, L, 10 + C + L)
     g = np.random.default_rng(2)
     x = g.standard_normal((B, n, n, n)).astype(np.float32)
     t = g.standard_normal((B, n, n, n)).astype(np.float32)
-    net = mf.CNN(C, th)
+    net = mf.CNN(C, L, th)
     loss, grad = net.loss_grad(torch.tensor(x, device="cuda"), torch.tensor(t, device="cuda"))
-    rl, rg = conv.loss_and_grad(th.astype(np.float64), C, x.astype(np.float64)[..., None],
+    rl, rg = conv.loss_and_grad(th.astype(np.float64), C, L, x.astype(np.float64)[..., None],
                                 t.astype(np.float64)[..., None])
     assert abs(loss - rl) <= 1e-5 * rl
     assert _rel(grad.cpu().numpy(), rg) <= 1e-4
@@ -67,22 +68,23 @@ def test_loss_and_gradient_match_oracle(mf, C, n, B):
 
 def test_adam_steps_match_oracle(mf):
     import torch
-    C, n, B, lr = 4, 9, 2, 1e-3
+    C, L, n, B, lr = 4, 3, 9, 2, 1e-3
     print("cnn adam steps", flush=True)
-    th = _theta(C, 5)
+    th = _theta(C, L, 5)
     g = np.random.default_rng(3)
     r = g.standard_normal((4, n, n, n)).astype(np.float32)
     e = g.standard_normal((4, n, n, n)).astype(np.float32)
     order = np.array([0, 1, 2, 3, 1, 3], np.int32)  # three steps of two pairs
-    net = mf.CNN(C, th)
+    net = mf.CNN(C, L, th)
     losses = net.train(torch.tensor(r, device="cuda"), torch.tensor(e, device="cuda"), order, B, lr=lr)
     # oracle: same three steps in FP64
     t64, m, v = th.astype(np.float64), np.zeros(th.size), np.zeros(th.size)
     ref_losses, grads = [], []
     for s in range(3):
         idx = order[2 * s:2 * s + 2]
-        L, gr = conv.loss_and_grad(t64, C, r[idx].astype(np.float64)[..., None], e[idx].astype(np.float64)[..., None])
-        ref_losses.append(L)
+        lo, gr = conv.loss_and_grad(t64, C, L, r[idx].astype(np.float64)[..., None],
+                                    e[idx].astype(np.float64)[..., None])
+        ref_losses.append(lo)
         grads.append(gr)
         t64, m, v = conv.adam_step(t64, gr, m, v, s + 1, lr)
     np.testing.assert_allclose(losses, ref_losses, rtol=1e-5)
@@ -95,12 +97,12 @@ def test_adam_steps_match_oracle(mf):
 
 
 def test_save_load_roundtrip(mf, tmp_path):
-    th = _theta(8, 7)
-    net = mf.CNN(8, th)
+    th = _theta(8, 5, 7)
+    net = mf.CNN(8, 5, th)
     p = str(tmp_path / "net.bin")
     net.save(p)
     net2 = mf.CNN.load(p)
-    assert net2.channels == 8
+    assert (net2.channels, net2.levels) == (8, 5)
     np.testing.assert_array_equal(net2.params(), th)
 
 
@@ -123,10 +125,10 @@ def _poisson_problem(mf, m, k, seed):
 def test_precond_apply_matches_oracle(mf):
     import torch
     print("learned precond apply", flush=True)
-    C = 4
+    C, L = 4, 3
     space, kappa, bnd, node_grid, G, A64, _ = _poisson_problem(mf, 4, 2, 1)
-    th = _theta(C, 9, 0.2)
-    net = mf.CNN(C, th)
+    th = _theta(C, L, 9, 0.2)
+    net = mf.CNN(C, L, th)
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
     r = np.random.default_rng(4).uniform(-1, 1, space.ndofs)
     r[bnd] = np.random.default_rng(5).uniform(-1, 1, bnd.size)  # pass-through must keep these
@@ -135,7 +137,7 @@ def test_precond_apply_matches_oracle(mf):
     d[bnd] = 1.0
     dmask = np.zeros(space.nnodes, bool)
     dmask[bnd] = True
-    ref = conv.precond_apply(th.astype(np.float64), C, r, d, node_grid, (G, G, G), dmask)
+    ref = conv.precond_apply(th.astype(np.float64), C, L, r, d, node_grid, (G, G, G), dmask)
     assert _rel(z, ref) <= TOL32
     np.testing.assert_array_equal(z[bnd], r[bnd])
 
@@ -143,7 +145,7 @@ def test_precond_apply_matches_oracle(mf):
 def test_harvest_matches_definition(mf):
     import torch
     space, kappa, bnd, node_grid, G, A64, _ = _poisson_problem(mf, 4, 3, 2)  # 13^3 lattice
-    net = mf.CNN(4)
+    net = mf.CNN(4, 2)
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
     g = np.random.default_rng(6)
     r, e = g.standard_normal(space.ndofs), g.standard_normal(space.ndofs)
@@ -176,7 +178,7 @@ def test_fcg_solves_against_dense(mf, refine):
     import torch
     print(f"fcg dense refine={refine}", flush=True)
     space, kappa, bnd, node_grid, G, A64, A32 = _poisson_problem(mf, 2, 2, 3)  # 5^3 lattice, 125 dofs
-    net = mf.CNN(4, _theta(4, 11, 0.2))
+    net = mf.CNN(4, 3, _theta(4, 3, 11, 0.2))
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
     b = _rhs(space, bnd, 3)
     x = torch.zeros(space.ndofs, dtype=torch.float64, device="cuda")
@@ -194,7 +196,7 @@ def test_fcg_identity_network_is_jacobi_cg(mf):
     import torch
     print("fcg identity network", flush=True)
     space, kappa, bnd, node_grid, G, A64, _ = _poisson_problem(mf, 6, 2, 4)  # 13^3 lattice
-    net = mf.CNN(4, mf.cnn_initial_weights(4, scale=0.0))
+    net = mf.CNN(4, 3, np.zeros(mf.cnn_nparams(4, 3), np.float32))  # the identity network
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
     J = mf.JacobiPrecond(A64)
     bt = torch.tensor(_rhs(space, bnd, 4), device="cuda")
@@ -214,15 +216,15 @@ def test_fcg_falls_back_to_jacobi(mf, how):
     import torch
     print(f"fcg fallback {how}", flush=True)
     space, kappa, bnd, node_grid, G, A64, _ = _poisson_problem(mf, 4, 2, 5)
-    th = mf.cnn_initial_weights(4, scale=0.0)
-    off_F = th.size - 27 * 4  # layer F: W[tap][cin][0]
-    if how == "negative":
-        th[off_F + 13 * 4 + 0] = -1.0
-        th[off_F + 13 * 4 + 1] = 1.0
-    else:
+    th = np.zeros(mf.cnn_nparams(4, 3), np.float32)
+    off_F = th.size - 27 * 4  # layer F: W[tap][cin][0]; layer A first: W[tap][0][cout]
+    th[13 * 4 + 0], th[13 * 4 + 1] = 1.0, -1.0  # h_0 = (relu(x), relu(-x), 0, 0) at the centre tap
+    if how == "negative":  # F u_0 = -2 x, so y = x + F u_0 = -x
+        th[off_F + 13 * 4 + 0], th[off_F + 13 * 4 + 1] = -2.0, 2.0
+    else:  # 1e30 * 1e30 overflows FP32
         th[13 * 4 + 0] = 1e30
         th[off_F + 13 * 4 + 0] = 1e30
-    net = mf.CNN(4, th)
+    net = mf.CNN(4, 3, th)
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
     J = mf.JacobiPrecond(A64)
     bt = torch.tensor(_rhs(space, bnd, 5), device="cuda")
@@ -244,7 +246,7 @@ def test_training_reduces_loss_and_iterations(mf):
     import torch
     print("cnn train end-to-end", flush=True)
     space, kappa, bnd, node_grid, G, A64, A32 = _poisson_problem(mf, 8, 2, 6)  # 17^3 lattice
-    net = mf.CNN(4, mf.cnn_initial_weights(4, seed=1))
+    net = mf.CNN(4, 3, mf.cnn_initial_weights(4, 3, seed=1))
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
     J = mf.JacobiPrecond(A64)
     bt = torch.tensor(_rhs(space, bnd, 6), device="cuda")

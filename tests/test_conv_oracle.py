@@ -110,62 +110,77 @@ def test_restrict_of_constant_interior():
     assert abs(c[0, 0, 0, 0, 0] - 0.75 ** 3) < 1e-15
 
 
-def test_network_positively_homogeneous():
+def test_parameter_count_and_order():
+    for C, L in ((4, 2), (8, 3), (16, 6)):
+        assert conv.nparams(C, L) == 27 * (2 * C + (2 * L - 2) * C * C)
+    assert conv.layer_names(4) == ["A", "B1", "B2", "B3", "D", "E2", "E1", "F"]
+
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_network_positively_homogeneous(L):
     C = 4
     r = np.random.default_rng(3)
-    th = r.standard_normal(conv.nparams(C)) * 0.3
+    th = r.standard_normal(conv.nparams(C, L)) * 0.3
     x = r.standard_normal((1, 9, 9, 9, 1))
-    y1 = conv.forward(th, C, x)
-    y2 = conv.forward(th, C, 2.5 * x)
+    y1 = conv.forward(th, C, L, x)
+    y2 = conv.forward(th, C, L, 2.5 * x)
     np.testing.assert_allclose(y2, 2.5 * y1, rtol=1e-12, atol=1e-14)
 
 
-def test_network_linear_part_matches_explicit_composition():
-    # with every ReLU inactive-free (all pre-activations positive) the network is linear;
-    # check against composing brute-force convolutions and the explicit 1D matrices
+def test_zero_weights_give_the_identity():
+    x = np.random.default_rng(8).standard_normal((2, 9, 5, 9, 1))
+    np.testing.assert_array_equal(conv.forward(np.zeros(conv.nparams(4, 3)), 4, 3, x), x)
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_network_linear_part_matches_explicit_composition(L):
+    # with every pre-activation positive the network is linear; check it against
+    # composing brute-force convolutions and the explicit 1D transfer matrices
     C = 2
     r = np.random.default_rng(4)
-    th = np.abs(r.standard_normal(conv.nparams(C))) * 0.2
+    th = np.abs(r.standard_normal(conv.nparams(C, L))) * 0.2
     x = np.abs(r.standard_normal((1, 5, 5, 5, 1)))
-    W = conv.unpack(th, C)
-    R, P = _R1(5), _P1(5)
-    R2, P2 = _R1(3), _P1(3)
+    W = conv.unpack(th, C, L)
     rs = lambda f, M: np.einsum("Zz,Yy,Xx,bzyxc->bZYXc", M, M, M, f)
-    h0 = _brute_conv(x, W["A"])
-    h1 = _brute_conv(rs(h0, R), W["B"])
-    h2 = _brute_conv(rs(h1, R2), W["C"])
-    g2 = _brute_conv(h2, W["D"])
-    g1 = _brute_conv(rs(g2, P2) + h1, W["E"])
-    y = _brute_conv(rs(g1, P) + h0, W["F"])
-    np.testing.assert_allclose(conv.forward(th, C, x), y, rtol=1e-12)
+    sizes = [5, 3, 2][:L]
+    h = [_brute_conv(x, W["A"])]
+    for l in range(1, L):
+        h.append(_brute_conv(rs(h[l - 1], _R1(sizes[l - 1])), W[f"B{l}"]))
+    g = _brute_conv(h[L - 1], W["D"])
+    for l in range(L - 2, -1, -1):
+        u = rs(g, _P1(sizes[l])) + h[l]
+        if l >= 1:
+            g = _brute_conv(u, W[f"E{l}"])
+    y = x + _brute_conv(u, W["F"])
+    np.testing.assert_allclose(conv.forward(th, C, L, x), y, rtol=1e-12)
 
 
-@pytest.mark.parametrize("C,n", [(2, 5), (3, 9)])
-def test_gradient_matches_central_differences(C, n):
-    r = np.random.default_rng(10 + C)
-    th = r.standard_normal(conv.nparams(C)) * 0.4
+@pytest.mark.parametrize("C,L,n", [(2, 2, 5), (3, 3, 9), (2, 4, 9)])
+def test_gradient_matches_central_differences(C, L, n):
+    r = np.random.default_rng(10 + C + L)
+    th = r.standard_normal(conv.nparams(C, L)) * 0.4
     x = r.standard_normal((2, n, n, n, 1))
     t = r.standard_normal((2, n, n, n, 1))
-    loss, g = conv.loss_and_grad(th, C, x, t)
+    loss, g = conv.loss_and_grad(th, C, L, x, t)
     idx = r.choice(th.size, size=40, replace=False)
     h = 1e-6
     for i in idx:
         tp, tm = th.copy(), th.copy()
         tp[i] += h
         tm[i] -= h
-        fd = (conv.loss_and_grad(tp, C, x, t)[0] - conv.loss_and_grad(tm, C, x, t)[0]) / (2 * h)
+        fd = (conv.loss_and_grad(tp, C, L, x, t)[0] - conv.loss_and_grad(tm, C, L, x, t)[0]) / (2 * h)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (i, fd, g[i])
 
 
 def test_loss_definition():
-    C = 2
+    C, L = 2, 2
     r = np.random.default_rng(5)
-    th = r.standard_normal(conv.nparams(C))
+    th = r.standard_normal(conv.nparams(C, L))
     x = r.standard_normal((3, 5, 5, 5, 1))
     t = r.standard_normal((3, 5, 5, 5, 1))
-    y = conv.forward(th, C, x)
+    y = conv.forward(th, C, L, x)
     want = np.mean([np.sum((y[b] - t[b]) ** 2) / np.sum(t[b] ** 2) for b in range(3)])
-    assert abs(conv.loss_and_grad(th, C, x, t)[0] - want) <= 1e-13 * want
+    assert abs(conv.loss_and_grad(th, C, L, x, t)[0] - want) <= 1e-13 * want
 
 
 def test_adam_first_step_closed_form():
@@ -180,22 +195,16 @@ def test_adam_first_step_closed_form():
 
 
 def test_precond_apply_diagonal_scaling_and_passthrough():
-    # with the network equal to the identity (only the centre taps of A and F, and skip paths
-    # cancelled by zero middle layers) z = D^{-1/2} D^{-1/2} r = r / d
-    C = 1
-    th = np.zeros(conv.nparams(C))
-    W = conv.unpack(th, C)
-    W["A"][13, 0, 0] = 1.0
-    W["F"][13, 0, 0] = 1.0
+    # with zero weights the network is the identity, so z = D^{-1/2} D^{-1/2} r = r / d
+    C, L = 4, 2
+    th = np.zeros(conv.nparams(C, L))
     n = 5
     r = np.random.default_rng(7)
     perm = r.permutation(n ** 3)
     res = r.standard_normal(n ** 3)
-    # positive r so that the ReLU of the first layer is the identity
-    res = np.abs(res)
     d = r.uniform(0.5, 2.0, n ** 3)
     bc = np.zeros(n ** 3, bool)
     bc[:7] = True
-    z = conv.precond_apply(th, C, res, d, perm, (n, n, n), bc)
+    z = conv.precond_apply(th, C, L, res, d, perm, (n, n, n), bc)
     np.testing.assert_allclose(z[~bc], res[~bc] / d[~bc], rtol=1e-14)
     np.testing.assert_array_equal(z[bc], res[bc])

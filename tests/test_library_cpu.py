@@ -81,10 +81,13 @@ def test_learned_precond_host_validation():
         pytest.skip("libmf.so not built")
     lib = api.load_library()
     for c in (4, 8, 16):
-        assert lib.mf_cnn_nparams(c) == 27 * (2 * c + 4 * c * c)
-    assert lib.mf_cnn_nparams(5) == -1
+        for L in (2, 3, 6):
+            assert lib.mf_cnn_nparams(c, L) == 27 * (2 * c + (2 * L - 2) * c * c)
+    assert lib.mf_cnn_nparams(5, 3) == -1
+    assert lib.mf_cnn_nparams(8, 1) == -1
     th = np.zeros(10, np.float32)
     h = ctypes.c_void_p()
-    assert lib.mf_cnn_create(5, th.ctypes.data, ctypes.byref(h)) == -7
+    assert lib.mf_cnn_create(5, 3, th.ctypes.data, ctypes.byref(h)) == -7
+    assert lib.mf_cnn_create(8, 9, th.ctypes.data, ctypes.byref(h)) == -7
     assert lib.mf_cnn_load(b"/nonexistent/net.bin", ctypes.byref(h)) == -1
     assert lib.mf_cnn_forward(None, 1, 5, 5, 5, None, None, None) == -1

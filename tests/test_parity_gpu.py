@@ -72,6 +72,26 @@ def test_tet_elasticity_action(mf, k, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [2, 3])
+def test_tet_elasticity_dirichlet_rows(mf, k, prec):
+    """Constrained nodes (boundary of the cube) through the FP64 kernel and the FP32
+    MFMA kernel: identity rows, and the other rows see x with the constrained values 0."""
+    print(f"tet dirichlet k={k} prec={prec}", flush=True)
+    mesh = mg.tet_mesh(3, 0.2, config=2)
+    space = mg.tet_space(mesh, k, ncomp=3, config=2)
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+    xm = x.reshape(-1, 3).copy()
+    xm[bnd] = 0.0
+    ref = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=1.0, mu=0.5).apply(xm.ravel()).reshape(-1, 3)
+    ref[bnd] = x.reshape(-1, 3)[bnd]
+    y, _ = _gpu_apply(mf, space, 4, prec, x, lam=1.0, mu=0.5, dirichlet=mask)
+    assert _relerr(y, ref.ravel()) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 def test_tri_mass_action(mf, prec):
     mesh = mg.tri_mesh(20, 0.2, config=0)  # 800 cells
     space = mg.tri_p1_space(mesh, renumber=True)
