@@ -140,7 +140,8 @@ def bench_simplex(mf, mg, reps=20):
     """P1 triangle mass with a nodal coefficient (64x64x2 triangles, and a weak-scaled
     2048x2048x2 mesh for the bandwidth figure) and vector P2/P3 tet elasticity
     (48^3 x 6 Kuhn tets perturbed +-0.2h, renumbered, lambda 1, mu 0.5) in FP64 and
-    FP32 (MFMA contractions). Per operator: kernel time, GDoF/s, roofline fraction."""
+    FP32 (MFMA contractions; coloured scatter by default, atomic scatter for
+    comparison). Per operator: kernel time, GDoF/s, roofline fraction."""
     import torch
     out = {}
     for m, tag in ((64, "tri_p1_mass_64"), (2048, "tri_p1_mass_2048_weak_scaled")):
@@ -161,8 +162,10 @@ def bench_simplex(mf, mg, reps=20):
         space = mg.tet_space(mesh, k, config=2)
         sp = mf.Space.from_meshgen(space)
         x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
-        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32_mfma")):
-            op = mf.Operator(sp, mf.ELASTICITY, prec, lam=1.0, mu=0.5)
+        for prec, ptag, sc in ((mf.F64, "fp64", mf.SCATTER_AUTO), (mf.F32, "fp32", mf.SCATTER_AUTO),
+                               (mf.F64, "fp64_atomic_scatter", mf.SCATTER_ATOMIC),
+                               (mf.F32, "fp32_atomic_scatter", mf.SCATTER_ATOMIC)):
+            op = mf.Operator(sp, mf.ELASTICITY, prec, lam=1.0, mu=0.5, scatter=sc)
             xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
             yt = torch.empty_like(xt)
             t = time_kernel(op, xt, yt, reps)
@@ -170,7 +173,8 @@ def bench_simplex(mf, mg, reps=20):
             P = PEAK_FP64 if prec == mf.F64 else PEAK_FP32
             tag = f"tet_elasticity_p{k}_{ptag}"
             out[tag] = {"cells": mesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
-                        "bound": "alu" if prec == mf.F64 else "mfma", "tflops": F / t / 1e12,
+                        "launches": op.info["cell_launches"],
+                        "bound": "mfma", "tflops": F / t / 1e12,
                         "frac": max(F / P, B / PEAK_HBM) / t, "gbs": B / t / 1e9}
             log(f"  {tag}: {json.dumps(out[tag])}")
             del op, xt, yt

@@ -276,8 +276,8 @@ int mf_precond_harvest(const mf_precond *M, const double *r, const double *e, in
  * the action). Every iteration applies all operators in ONE persistent launch
  * over a device work list of (operator, cell-batch range) items; vector stages
  * run over the concatenated vectors of all systems; chunks of iterations are
- * captured into a hipGraph and replayed. Requirements: FP64 hex operators of
- * one kind, degree <= 5, without constraints; A32 (nullable) holds the FP32
+ * captured into a hipGraph and replayed. Requirements: scalar FP64 hex operators
+ * of one kind, degree <= 5, without constraints; A32 (nullable) holds the FP32
  * operators on the same spaces (iterative refinement as in mf_cg_solve); M
  * (nullable, entries nullable) Jacobi preconditioners of the A64[i].
  * The batch binds the device pointers b[i] (input) and x[i] (initial guess in,

@@ -209,9 +209,9 @@ int mf_batch_create(int nsys, const mf_op *const *A64, const mf_op *const *A32, 
   for (int i = 0; i < nsys; i++) {
     const mf_op *a = A64[i];
     if (!a || a->cell_type != MF_CELL_HEX || a->precision != MF_F64 || a->kind != B->kind || a->degree > 5 ||
-        a->n_bc_dofs != 0)
-      return fail(MF_EUNSUPPORTED, "mf_batch_create: operators must be FP64 hex operators of one kind, degree <= 5, "
-                                   "without constraints");
+        a->n_bc_dofs != 0 || a->ncomp != 1)
+      return fail(MF_EUNSUPPORTED, "mf_batch_create: operators must be scalar FP64 hex operators of one kind, "
+                                   "degree <= 5, without constraints");
     if (A32) {
       const mf_op *f = A32[i];
       if (!f || f->precision != MF_F32 || f->numbering_id != a->numbering_id || f->kind != a->kind)

@@ -83,7 +83,7 @@ template <int N, bool GRAD> constexpr int hex_lds_size() {
 // Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
 // on the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
 template <typename T, int N, int KIND, bool ATOMIC>
-__device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, T *lds) {
+__device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, const int comp, T *lds) {
   using TB = TabT<T, N>;
   constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N>();
   constexpr bool GRAD = KIND != K_MASS;
@@ -158,7 +158,10 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       kb = K[3] + K[5] * x1 + K[6] * x2 + K[7] * x1 * x2;
     }
 
-    for (int comp = 0; comp < nc; comp++) {
+    {
+      // One component per call: the body has no loop over components, so the
+      // compiler materialises the table constants at their uses instead of keeping
+      // them live across iterations (which doubled the register count).
       T yv[N], r_cur[N];
 #pragma unroll
       for (int l = 0; l < N; l++) r_cur[l] = idx_cur[l] >= 0 ? A.x[(int64_t)idx_cur[l] * nc + comp] : T(0);
@@ -354,12 +357,15 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 
 #undef IX
 
+// Work item = (cell batch, component): the ncomp components of a batch are
+// consecutive items, so they run on the same XCD at about the same time and share
+// the cache lines of their interleaved values.
 template <typename T, int N, int KIND, bool ATOMIC>
 __global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
   __shared__ T lds[hex_lds_size<N, KIND != K_MASS>()];
   const int64_t nb = (A.c1 - A.c0 + hex_epb<N>() - 1) / hex_epb<N>();  // cell batches
-  const int64_t b = xcd_batch(blockIdx.x, nb);
-  if (b < nb) hex_cells<T, N, KIND, ATOMIC>(A, b, lds);
+  const int64_t vb = xcd_batch(blockIdx.x, nb * A.ncomp);
+  if (vb < nb * A.ncomp) hex_cells<T, N, KIND, ATOMIC>(A, vb / A.ncomp, (int)(vb % A.ncomp), lds);
 }
 
 // ---------------------------------------------------------------------------------- batched apply
@@ -395,11 +401,11 @@ __global__ void __launch_bounds__(64) hex_batch_kernel(const HexBatchOp<T> *__re
       const HexArgs<T> A = ops[w.op].a;
       for (int64_t b = w.b0; b < w.b1; b++) {
         switch (ops[w.op].N) {
-          case 2: hex_cells<T, 2, KIND, true>(A, b, lds); break;
-          case 3: hex_cells<T, 3, KIND, true>(A, b, lds); break;
-          case 4: hex_cells<T, 4, KIND, true>(A, b, lds); break;
-          case 5: hex_cells<T, 5, KIND, true>(A, b, lds); break;
-          case 6: hex_cells<T, 6, KIND, true>(A, b, lds); break;
+          case 2: hex_cells<T, 2, KIND, true>(A, b, 0, lds); break;
+          case 3: hex_cells<T, 3, KIND, true>(A, b, 0, lds); break;
+          case 4: hex_cells<T, 4, KIND, true>(A, b, 0, lds); break;
+          case 5: hex_cells<T, 5, KIND, true>(A, b, 0, lds); break;
+          case 6: hex_cells<T, 6, KIND, true>(A, b, 0, lds); break;
         }
         __syncthreads();
       }
@@ -413,11 +419,11 @@ __global__ void __launch_bounds__(64) hex_batch_kernel(const HexBatchOp<T> *__re
     if (stop && stop[(int64_t)w.op * stop_stride]) return;
     const HexArgs<T> A = ops[w.op].a;
     switch (ops[w.op].N) {
-      case 2: hex_cells<T, 2, KIND, true>(A, w.b0, lds); break;
-      case 3: hex_cells<T, 3, KIND, true>(A, w.b0, lds); break;
-      case 4: hex_cells<T, 4, KIND, true>(A, w.b0, lds); break;
-      case 5: hex_cells<T, 5, KIND, true>(A, w.b0, lds); break;
-      case 6: hex_cells<T, 6, KIND, true>(A, w.b0, lds); break;
+      case 2: hex_cells<T, 2, KIND, true>(A, w.b0, 0, lds); break;
+      case 3: hex_cells<T, 3, KIND, true>(A, w.b0, 0, lds); break;
+      case 4: hex_cells<T, 4, KIND, true>(A, w.b0, 0, lds); break;
+      case 5: hex_cells<T, 5, KIND, true>(A, w.b0, 0, lds); break;
+      case 6: hex_cells<T, 6, KIND, true>(A, w.b0, 0, lds); break;
     }
   }
 }
@@ -547,7 +553,7 @@ static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
     default: return fail(MF_EUNSUPPORTED, "hex kernel: operator kind");
   }
   (void)fn;
-  dim3 grid((unsigned)xcd_grid(nb)), block(64);  // one cell batch per wavefront
+  dim3 grid((unsigned)xcd_grid(nb * a.ncomp)), block(64);  // one (cell batch, component) per wavefront
   switch (kind) {
     case K_MASS: hex_apply_kernel<T, N, K_MASS, AT><<<grid, block, 0, s>>>(a); break;
     case K_HELM: hex_apply_kernel<T, N, K_HELM, AT><<<grid, block, 0, s>>>(a); break;

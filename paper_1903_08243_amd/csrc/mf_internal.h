@@ -116,10 +116,10 @@ template <typename T>
 int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s);
-// FP32 degree >= 2: the action runs on MFMA and needs these per-lane operands of
-// the tabulation appended to TetArgs::tab after the weights (host-built)
+// Degree >= 2: the action runs on MFMA and needs these per-lane operands of the
+// tabulation appended to TetArgs::tab after the weights (host-built)
 int tet_mfma_table_floats(int k, int nq);
-void tet_mfma_tables(int k, int nq, const double *dphi, float *out);
+void tet_mfma_tables(int k, int nq, const double *dphi, double *out, bool f64);
 
 // Tri P1 mass with vertex coefficient (simplex_kernels.hip)
 template <typename T> struct TriArgs {

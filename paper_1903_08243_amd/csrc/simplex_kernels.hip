@@ -95,25 +95,43 @@ __global__ void __launch_bounds__(192) tet_elasticity_kernel(const TetArgs<T> A)
   }
 }
 
-// ----------------------------------------------------------------- FP32 tet elasticity on MFMA
-// Both contractions of the FP32 action are GEMMs over a batch of cells (the
+// ----------------------------------------------------------------- tet elasticity on MFMA
+// Both contractions of the action are GEMMs over a batch of cells (the
 // tabulation of the reference gradients is shared by all cells):
 //   forward  G[(q,a)][(cell,c)] = sum_i dphi[q][i][a] x[i][(cell,c)]
 //   backward y[i][(cell,c)]     = sum_(q,a) dphi[q][i][a] P[(q,a)][(cell,c)]
-// computed with v_mfma_f32_16x16x4f32 (operands: A[m][k] from lane m + 16 k,
-// B[k][n] from lane n + 16 k; result C[m][n] in lane n + 16 (m / 4), element m % 4).
+// computed with v_mfma_f32_16x16x4f32 / v_mfma_f64_16x16x4f64 (degree >= 2;
+// operands: A[m][k] from lane m + 16 k, B[k][n] from lane n + 16 k; result
+// C[m][n] in lane n + 16 (m / 4), element m % 4 for FP32, and in lane
+// n + 16 (m % 4), element m / 4 for FP64 -- measured on gfx950).
 // A wavefront owns 16 cells (n = cell) and one accumulator per displacement
-// component. The forward rows are ordered m = 4 g + a for the 4 quadrature
-// points q = 4 r + g of row tile r (a = 3 is padding), so lane (cell, g) ends up
+// component. The forward rows are ordered so that the row of (q = 4 r + g, a)
+// lands in lane group g, element a (a = 3 is padding), so lane (cell, g) ends up
 // with the full reference gradient of all three components at one point, forms
 // the stress there, and its P values are exactly the B operand of the backward
 // K-steps (r, a) whose 4 entries are the points q = 4 r + 0..3. The per-lane
 // operands of the tabulation are precomputed on the host (mfma_tab layout:
 // fwd[r][s][64], bwd[t][r][a][64]).
 typedef float mf_floatx4 __attribute__((ext_vector_type(4)));
+typedef double mf_doublex4 __attribute__((ext_vector_type(4)));
+template <typename T> struct Mfma16;
+template <> struct Mfma16<float> {
+  typedef mf_floatx4 V;
+  static __device__ __forceinline__ V fma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<double> {
+  typedef mf_doublex4 V;
+  static __device__ __forceinline__ V fma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
 
-template <int K, int NQ, bool ATOMIC>
-__global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<float> A) {
+template <typename T, int K, int NQ, bool ATOMIC>
+__global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<T> A) {
+  using MF = Mfma16<T>;
+  using V4 = typename MF::V;
   constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
   constexpr int NR = (NQ + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -130,54 +148,54 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
     valid = u >= A.ulo && u < A.uhi;
   }
   const int32_t *mp = A.map + batch * (D * 64) + cl;
-  const float *gp = A.geo + batch * (10 * 64) + cl;
-  float Ki[9];
+  const T *gp = A.geo + batch * (10 * 64) + cl;
+  T Ki[9];
 #pragma unroll
   for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
-  const float adet = gp[9 * 64];
-  const float *qw = A.tab + NQ * D * 3;
-  const float *fwd = qw + NQ;
-  const float *bwd = fwd + NR * NS * 64;
+  const T adet = gp[9 * 64];
+  const T *qw = A.tab + NQ * D * 3;
+  const T *fwd = qw + NQ;
+  const T *bwd = fwd + NR * NS * 64;
   // nodal values: lane (cell, g) holds the nodes i = 4 s + g, all three components
-  float xv[NS][3];
+  T xv[NS][3];
 #pragma unroll
   for (int s = 0; s < NS; s++) {
     const int i = 4 * s + g;
     const int idx = (valid && i < D) ? mp[i * 64] : -1;
 #pragma unroll
-    for (int c = 0; c < 3; c++) xv[s][c] = idx >= 0 ? A.x[3 * (int64_t)idx + c] : 0.0f;
+    for (int c = 0; c < 3; c++) xv[s][c] = idx >= 0 ? A.x[3 * (int64_t)idx + c] : T(0);
   }
-  mf_floatx4 yacc[NT][3];
+  V4 yacc[NT][3];
 #pragma unroll
   for (int t = 0; t < NT; t++)
 #pragma unroll
-    for (int c = 0; c < 3; c++) yacc[t][c] = mf_floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < 3; c++) yacc[t][c] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int r = 0; r < NR; r++) {
-    mf_floatx4 gacc[3];
+    V4 gacc[3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) gacc[c] = mf_floatx4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int c = 0; c < 3; c++) gacc[c] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int s = 0; s < NS; s++) {
-      const float av = fwd[(r * NS + s) * 64 + lane];
+      const T av = fwd[(r * NS + s) * 64 + lane];
 #pragma unroll
-      for (int c = 0; c < 3; c++) gacc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, xv[s][c], gacc[c], 0, 0, 0);
+      for (int c = 0; c < 3; c++) gacc[c] = MF::fma(av, xv[s][c], gacc[c]);
     }
     // point q = 4 r + g of this lane's cell: reference gradients gacc[c][a]
     const int q = 4 * r + g;
-    const float wd = q < NQ ? qw[q] * adet : 0.0f;
-    float gr[3][3];
+    const T wd = q < NQ ? qw[q] * adet : T(0);
+    T gr[3][3];
 #pragma unroll
     for (int c = 0; c < 3; c++)
 #pragma unroll
       for (int a = 0; a < 3; a++) gr[c][a] = gacc[c][0] * Ki[a] + gacc[c][1] * Ki[3 + a] + gacc[c][2] * Ki[6 + a];
-    const float tr = gr[0][0] + gr[1][1] + gr[2][2];
-    float P[3][3];
+    const T tr = gr[0][0] + gr[1][1] + gr[2][2];
+    T P[3][3];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
-      float sig[3];
+      T sig[3];
 #pragma unroll
-      for (int a = 0; a < 3; a++) sig[a] = A.mu * (gr[c][a] + gr[a][c]) + (a == c ? A.lam * tr : 0.0f);
+      for (int a = 0; a < 3; a++) sig[a] = A.mu * (gr[c][a] + gr[a][c]) + (a == c ? A.lam * tr : T(0));
 #pragma unroll
       for (int d = 0; d < 3; d++) P[c][d] = wd * (sig[0] * Ki[3 * d + 0] + sig[1] * Ki[3 * d + 1] + sig[2] * Ki[3 * d + 2]);
     }
@@ -185,17 +203,18 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
     for (int t = 0; t < NT; t++)
 #pragma unroll
       for (int d = 0; d < 3; d++) {
-        const float av = bwd[((t * NR + r) * 3 + d) * 64 + lane];
+        const T av = bwd[((t * NR + r) * 3 + d) * 64 + lane];
 #pragma unroll
-        for (int c = 0; c < 3; c++) yacc[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, P[c][d], yacc[t][c], 0, 0, 0);
+        for (int c = 0; c < 3; c++) yacc[t][c] = MF::fma(av, P[c][d], yacc[t][c]);
       }
   }
-  // lane (cell, g) holds y for the nodes i = 16 t + 4 g + v
+  // lane (cell, g) holds y for the nodes i = 16 t + 4 g + v (FP32), 16 t + g + 4 v (FP64)
+  constexpr bool F64 = sizeof(T) == 8;
 #pragma unroll
   for (int t = 0; t < NT; t++)
 #pragma unroll
     for (int v = 0; v < 4; v++) {
-      const int i = 16 * t + 4 * g + v;
+      const int i = F64 ? 16 * t + g + 4 * v : 16 * t + 4 * g + v;
       const int idx = (valid && i < D) ? mp[i * 64] : -1;
       if (idx >= 0) {
 #pragma unroll
@@ -214,22 +233,23 @@ int tet_mfma_table_floats(int k, int nq) {
   return NR * NS * 64 + NT * NR * 3 * 64;
 }
 
-void tet_mfma_tables(int k, int nq, const double *dphi, float *out) {
+void tet_mfma_tables(int k, int nq, const double *dphi, double *out, bool f64) {
   const int D = (k + 1) * (k + 2) * (k + 3) / 6;
   const int NR = (nq + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
-  float *fwd = out, *bwd = out + NR * NS * 64;
+  double *fwd = out, *bwd = out + NR * NS * 64;
   for (int r = 0; r < NR; r++)
     for (int s = 0; s < NS; s++)
       for (int l = 0; l < 64; l++) {
-        const int m = l % 16, kk = l / 16, q = 4 * r + m / 4, a = m % 4, i = 4 * s + kk;
-        fwd[(r * NS + s) * 64 + l] = (a < 3 && q < nq && i < D) ? (float)dphi[(q * D + i) * 3 + a] : 0.0f;
+        const int m = l % 16, kk = l / 16, i = 4 * s + kk;
+        const int q = 4 * r + (f64 ? m % 4 : m / 4), a = f64 ? m / 4 : m % 4;
+        fwd[(r * NS + s) * 64 + l] = (a < 3 && q < nq && i < D) ? dphi[(q * D + i) * 3 + a] : 0.0;
       }
   for (int t = 0; t < NT; t++)
     for (int r = 0; r < NR; r++)
       for (int d = 0; d < 3; d++)
         for (int l = 0; l < 64; l++) {
           const int i = 16 * t + l % 16, q = 4 * r + l / 16;
-          bwd[((t * NR + r) * 3 + d) * 64 + l] = (i < D && q < nq) ? (float)dphi[(q * D + i) * 3 + d] : 0.0f;
+          bwd[((t * NR + r) * 3 + d) * 64 + l] = (i < D && q < nq) ? dphi[(q * D + i) * 3 + d] : 0.0;
         }
 }
 
@@ -268,11 +288,10 @@ static int launch_tet_kq(const TetArgs<T> &a, hipStream_t s, bool diag, bool ato
   const int64_t b0 = a.c0 / 64, b1 = (a.c1 + 63) / 64;
   if (a.c1 <= a.c0) return MF_OK;
   dim3 grid((unsigned)(diag ? b1 - b0 : ((b1 - b0 + 7) / 8) * 8)), block(192);
-  if constexpr (std::is_same<T, float>::value && K >= 2) {
+  if constexpr (K >= 2) {
     if (!diag) {
-      const TetArgs<float> &af = a;
-      if (atomic) tet_elasticity_mfma_kernel<K, NQ, true><<<grid, dim3(256), 0, s>>>(af);
-      else tet_elasticity_mfma_kernel<K, NQ, false><<<grid, dim3(256), 0, s>>>(af);
+      if (atomic) tet_elasticity_mfma_kernel<T, K, NQ, true><<<grid, dim3(256), 0, s>>>(a);
+      else tet_elasticity_mfma_kernel<T, K, NQ, false><<<grid, dim3(256), 0, s>>>(a);
       MF_HIP(hipGetLastError());
       return MF_OK;
     }
