@@ -147,16 +147,10 @@ def forward(theta: np.ndarray, C: int, L: int, x: np.ndarray, keep: bool = False
     return y
 
 
-def loss_and_grad(theta: np.ndarray, C: int, L: int, x: np.ndarray, t: np.ndarray):
-    """Batch-mean relative squared error and its gradient with respect to theta."""
+def backward(theta: np.ndarray, C: int, L: int, acts: dict, gy: np.ndarray) -> np.ndarray:
+    """Gradient with respect to theta given gy = dLoss/dy and the kept activations."""
     W = unpack(theta, C, L)
-    y, a = forward(theta, C, L, x, keep=True)
-    h, c, g, u = a["h"], a["c"], a["g"], a["u"]
-    B = x.shape[0]
-    tt = np.sum(t.reshape(B, -1) ** 2, axis=1)
-    diff = (y - t).reshape(B, -1)
-    loss = float(np.mean(np.sum(diff ** 2, axis=1) / tt))
-    gy = (2.0 / B) * (diff / tt[:, None]).reshape(y.shape)
+    x, h, c, g, u = acts["x"], acts["h"], acts["c"], acts["g"], acts["u"]
     grads = {}
     # decoder, fine to coarse: y = x + F u_0 (the skip from x carries no weight)
     gu = [None] * (L - 1)
@@ -175,8 +169,38 @@ def loss_and_grad(theta: np.ndarray, C: int, L: int, x: np.ndarray, t: np.ndarra
         gc, grads[f"B{l}"] = conv_backward(c[l], W[f"B{l}"], gpre)
         gh[l - 1] = gh[l - 1] + prolong(gc, h[l - 1].shape[1:4]) / 8.0  # R^T = P / 8
     _, grads["A"] = conv_backward(x, W["A"], gh[0] * (h[0] > 0))
-    gvec = np.concatenate([grads[k].ravel() for k in layer_names(L)])
-    return loss, gvec
+    return np.concatenate([grads[k].ravel() for k in layer_names(L)])
+
+
+def loss_and_grad(theta: np.ndarray, C: int, L: int, x: np.ndarray, t: np.ndarray):
+    """Batch-mean relative squared error and its gradient with respect to theta."""
+    y, acts = forward(theta, C, L, x, keep=True)
+    B = x.shape[0]
+    tt = np.sum(t.reshape(B, -1) ** 2, axis=1)
+    diff = (y - t).reshape(B, -1)
+    loss = float(np.mean(np.sum(diff ** 2, axis=1) / tt))
+    gy = (2.0 / B) * (diff / tt[:, None]).reshape(y.shape)
+    return loss, backward(theta, C, L, acts, gy)
+
+
+def energy_loss_and_grad(theta, C, L, r, A, diag, grid_of_dof, shape, dirichlet):
+    """Energy (Ritz) loss of the preconditioned residual z = M r for one residual r:
+    (z^T A z - 2 z^T r) / (r^T D^{-1} r), i.e. the A-norm error of z against A^{-1} r
+    up to the constant r^T A^{-1} r, and its gradient with respect to theta. A is a
+    dense symmetric matrix; constrained dofs pass r through (z_B = r_B)."""
+    s = 1.0 / np.sqrt(diag)
+    g = np.zeros(int(np.prod(shape)))
+    g[grid_of_dof] = s * r
+    x = g.reshape((1,) + tuple(shape) + (1,))
+    y, acts = forward(theta, C, L, x, keep=True)
+    z = np.where(dirichlet, r, s * y.reshape(-1)[grid_of_dof])
+    Az = A @ z
+    ns = float(np.sum(r * r / diag))
+    loss = float((z @ Az - 2.0 * z @ r) / ns)
+    gz = np.where(dirichlet, 0.0, 2.0 * (Az - r) / ns)
+    gyv = np.zeros(int(np.prod(shape)))
+    gyv[grid_of_dof] = s * gz
+    return loss, backward(theta, C, L, acts, gyv.reshape(y.shape))
 
 
 def adam_step(theta, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

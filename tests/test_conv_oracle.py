@@ -208,3 +208,45 @@ def test_precond_apply_diagonal_scaling_and_passthrough():
     z = conv.precond_apply(th, C, L, res, d, perm, (n, n, n), bc)
     np.testing.assert_allclose(z[~bc], res[~bc] / d[~bc], rtol=1e-14)
     np.testing.assert_array_equal(z[bc], res[bc])
+
+
+def test_energy_loss_gradient_matches_central_differences():
+    # a random SPD matrix on a 5^3 lattice with a few pass-through dofs
+    C, L, n = 2, 2, 5
+    N = n ** 3
+    r = np.random.default_rng(21)
+    Q = r.standard_normal((N, N))
+    A = Q @ Q.T / N + np.eye(N)
+    diag = np.diag(A).copy()
+    perm = r.permutation(N)
+    bc = np.zeros(N, bool)
+    bc[perm[:9]] = True
+    res = r.standard_normal(N)
+    th = r.standard_normal(conv.nparams(C, L)) * 0.3
+    loss, g = conv.energy_loss_and_grad(th, C, L, res, A, diag, perm, (n, n, n), bc)
+    for i in r.choice(th.size, size=30, replace=False):
+        tp, tm = th.copy(), th.copy()
+        tp[i] += 1e-6
+        tm[i] -= 1e-6
+        fd = (conv.energy_loss_and_grad(tp, C, L, res, A, diag, perm, (n, n, n), bc)[0]
+              - conv.energy_loss_and_grad(tm, C, L, res, A, diag, perm, (n, n, n), bc)[0]) / 2e-6
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (i, fd, g[i])
+
+
+def test_energy_loss_of_the_exact_inverse_is_minus_one_in_the_scaled_units():
+    # z = A^{-1} r gives z^T A z - 2 z^T r = -r^T A^{-1} r, and any other z is larger:
+    # check the definition with zero weights (z = D^{-1} r) against the closed form
+    n = 5
+    N = n ** 3
+    r = np.random.default_rng(22)
+    Q = r.standard_normal((N, N))
+    A = Q @ Q.T / N + np.eye(N)
+    d = np.diag(A).copy()
+    res = r.standard_normal(N)
+    bc = np.zeros(N, bool)
+    loss, _ = conv.energy_loss_and_grad(np.zeros(conv.nparams(4, 2)), 4, 2, res, A, d, np.arange(N), (n, n, n), bc)
+    z = res / d
+    want = (z @ A @ z - 2 * z @ res) / np.sum(res * res / d)
+    assert abs(loss - want) <= 1e-12 * abs(want)
+    best = -(res @ np.linalg.solve(A, res)) / np.sum(res * res / d)
+    assert loss >= best
