@@ -262,6 +262,22 @@ int mf_cnn_train(mf_cnn *net, int npairs, int n, const float *r, const float *e,
  * MF_EINVAL (sizes, not a bijection). */
 int mf_precond_create_cnn(const mf_op *A, const mf_cnn *net, int nz, int ny, int nx,
                           const int32_t *node_grid, void *stream, mf_precond **out);
+/* Energy (Ritz) loss of the learned preconditioner for one residual r of A
+ * (FP64 device vector, user numbering): with z = P r,
+ *   loss = (z^T A z - 2 z^T r) / (r^T D^-1 r),
+ * which is the A-norm error |z - A^-1 r|_A^2 up to the constant r^T A^-1 r, so
+ * minimising it over the weights improves the preconditioner for every mode in
+ * proportion to its energy. P must be a learned preconditioner built on net and A
+ * the FP64 operator P was built from. loss: host (nullable); grad: device nparams
+ * floats (nullable). Synchronous. */
+int mf_cnn_energy_loss_grad(mf_cnn *net, const mf_precond *P, const mf_op *A, const double *r, double *loss,
+                            float *grad, void *stream);
+/* nsteps Adam steps (as mf_cnn_train) on that loss, one residual per step:
+ * r: device FP64 [nsamples][ndofs] (user numbering), step s uses r[order[s]]
+ * (host int32). losses: host, nsteps doubles (the loss before each step;
+ * nullable). Synchronous. */
+int mf_cnn_train_energy(mf_cnn *net, const mf_precond *P, const mf_op *A, int nsamples, const double *r,
+                        int nsteps, const int32_t *order, float lr, double *losses, void *stream);
 /* Training pairs from a residual / error pair of A (r = A e; FP64 device vectors,
  * user numbering): both are diagonally scaled (r~ = D^-1/2 r, e~ = D^1/2 e, the
  * pair of the unit-diagonal operator), and crop c is the n^3 sub-lattice starting

@@ -104,6 +104,8 @@ def load_library():
         "mf_cnn_train": (I, [P, I, I, P, P, I, I, P, ctypes.c_float, P, P]),
         "mf_precond_create_cnn": (I, [P, P, I, I, I, P, P, PP]),
         "mf_precond_harvest": (I, [P, P, P, I, I, P, P, P, P]),
+        "mf_cnn_energy_loss_grad": (I, [P, P, P, P, ctypes.POINTER(D), P, P]),
+        "mf_cnn_train_energy": (I, [P, P, P, I, P, I, P, ctypes.c_float, P, P]),
         "mf_last_error": (ctypes.c_char_p, []),
         "mf_version": (ctypes.c_char_p, []),
     }
@@ -382,6 +384,29 @@ class CNN:
                                            nsteps, batch, order.ctypes.data, lr, losses.ctypes.data,
                                            _stream(stream)))
         return losses[:nsteps]
+
+    def energy_loss_grad(self, precond, op, r, stream=None):
+        """Energy loss (z'Az - 2 z'r) / (r'D^-1 r) of z = precond(r) and its gradient."""
+        import torch
+        g = torch.empty(self.nparams, dtype=torch.float32, device=r.device)
+        loss = ctypes.c_double()
+        _check(load_library().mf_cnn_energy_loss_grad(self.handle, precond.handle, op.handle,
+                                                      _dev(r, torch.float64), ctypes.byref(loss), _dev(g),
+                                                      _stream(stream)))
+        return loss.value, g
+
+    def train_energy(self, precond, op, R, order, lr=1e-3, stream=None):
+        """Adam steps on the energy loss; R: [nsamples, ndofs] float64 residuals (user
+        numbering), order: sample index per step. Returns the per-step losses."""
+        import torch
+        if R.dim() != 2 or not R.is_contiguous():
+            raise ValueError("R must be a contiguous [nsamples, ndofs] tensor")
+        order = _np(order, np.int32)
+        losses = np.zeros(max(order.size, 1), np.float64)
+        _check(load_library().mf_cnn_train_energy(self.handle, precond.handle, op.handle, R.shape[0],
+                                                  _dev(R, torch.float64), order.size, order.ctypes.data, lr,
+                                                  losses.ctypes.data, _stream(stream)))
+        return losses[:order.size]
 
     def __del__(self):
         if getattr(self, "handle", None) and _lib is not None:

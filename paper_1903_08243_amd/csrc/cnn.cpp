@@ -71,40 +71,31 @@ int cnn_forward(const float *theta, const CnnLayout &Ly, const float *x, CnnActs
   return rc;
 }
 
-// Loss of the batch (x, t) and the gradient of every weight into net->grad.
-// x, t: [B][Z][Y][X]; the loss (FP64) is left in net->loss on the device.
-static int loss_grad(mf_cnn *net, const Grid3 &g0, const float *x, const float *t, hipStream_t s) {
+// Gradient of every weight into net->grad from gy = dLoss/dy, for the forward pass
+// kept in `a` (its input x).
+static int cnn_backward(mf_cnn *net, CnnActs &a, const float *x, const float *gyp, hipStream_t s) {
   const int C = net->C, L = net->levels;
   const CnnLayout &Ly = net->L;
-  CnnActs &a = net->acts;
-  int rc = a.ensure(g0, C, L);
-  if (rc) return rc;
   int64_t pf = 0;
-  for (int l = 0; l < L; l++) {
+  int rc = MF_OK;
+  for (int l = 0; l < L && !rc; l++) {
     const int64_t v = cnn_wgrad_part_floats(a.grid[l], C, C);
     pf = v > pf ? v : pf;
     rc = grow(net->gh[l], (size_t)a.grid[l].points() * C * 4);
-    if (rc) return rc;
   }
   const size_t f1 = (size_t)a.grid[1].points() * C * 4;
-  if (!rc) rc = grow(net->gy, (size_t)g0.points() * 4);
   if (!rc) rc = grow(net->s1, f1);
   if (!rc) rc = grow(net->s2, f1);
   if (!rc) rc = grow(net->part, (size_t)pf * 4);
-  if (!rc) rc = grow(net->lpart, (size_t)cnn_loss_part_doubles(g0.B) * 8);
-  if (!rc) rc = grow(net->loss, 8);
   if (rc) return rc;
   auto F = [&](DeviceBuffer &b) { return b.as<float>(); };
   const float *th = net->theta.as<float>();
   float *gr = net->grad.as<float>();
   float *part = net->part.as<float>();
   float *S1 = F(net->s1), *S2 = F(net->s2);
-  rc = cnn_forward(th, Ly, x, a, s);
-  if (!rc) rc = cnn_loss(F(a.y), t, F(net->gy), net->loss.as<double>(), net->lpart.as<double>(), g0.B,
-                         (int64_t)g0.Z * g0.Y * g0.X, s);
   // decoder, fine to coarse. y = x + F u_0: gh[0] starts as g(u_0) (the skip u_0 = P g_1 + h_0)
-  if (!rc) rc = cnn_wgrad(F(a.u[0]), F(net->gy), gr + Ly.F(), part, a.grid[0], C, 1, s);
-  if (!rc) rc = cnn_conv(F(net->gy), th + Ly.F(), F(net->gh[0]), nullptr, a.grid[0], 1, C, false, true, s);
+  rc = cnn_wgrad(F(a.u[0]), gyp, gr + Ly.F(), part, a.grid[0], C, 1, s);
+  if (!rc) rc = cnn_conv(gyp, th + Ly.F(), F(net->gh[0]), nullptr, a.grid[0], 1, C, false, true, s);
   for (int l = 0; l < L - 1 && !rc; l++) {
     // g(g_(l+1)) = 8 R g(u_l) masked by g_(l+1) > 0
     rc = cnn_restrict(F(net->gh[l]), S1, F(a.g[l + 1]), 8.0f, a.grid[l], C, s);
@@ -126,6 +117,21 @@ static int loss_grad(mf_cnn *net, const Grid3 &g0, const float *x, const float *
     if (!rc) rc = cnn_prolong_add(S2, F(net->gh[l - 1]), F(net->gh[l - 1]), F(a.h[l - 1]), 0.125f, a.grid[l - 1], C, s);
   }
   if (!rc) rc = cnn_wgrad(x, F(net->gh[0]), gr + Ly.A(), part, a.grid[0], 1, C, s);
+  return rc;
+}
+
+// Loss of the batch (x, t) and the gradient of every weight into net->grad.
+// x, t: [B][Z][Y][X]; the loss (FP64) is left in net->loss on the device.
+static int loss_grad(mf_cnn *net, const Grid3 &g0, const float *x, const float *t, hipStream_t s) {
+  CnnActs &a = net->acts;
+  int rc = a.ensure(g0, net->C, net->levels);
+  if (!rc) rc = grow(net->gy, (size_t)g0.points() * 4);
+  if (!rc) rc = grow(net->lpart, (size_t)cnn_loss_part_doubles(g0.B) * 8);
+  if (!rc) rc = grow(net->loss, 8);
+  if (!rc) rc = cnn_forward(net->theta.as<float>(), net->L, x, a, s);
+  if (!rc) rc = cnn_loss(a.y.as<float>(), t, net->gy.as<float>(), net->loss.as<double>(), net->lpart.as<double>(),
+                         g0.B, (int64_t)g0.Z * g0.Y * g0.X, s);
+  if (!rc) rc = cnn_backward(net, a, x, net->gy.as<float>(), s);
   return rc;
 }
 
@@ -433,6 +439,107 @@ int mf_precond_harvest(const mf_precond *P, const double *r, const double *e, in
                    e_out, s);
   if (rc) return rc;
   MF_HIP(hipStreamSynchronize(s));  // the corner buffer is freed on return
+  return MF_OK;
+}
+
+}  // extern "C"
+
+namespace mf {
+
+// Workspaces of energy-loss training on a lattice preconditioner.
+struct EnergyWork {
+  DeviceBuffer z, Az, part, scal;
+};
+
+// One sample: r (FP64, internal numbering) -> loss into *loss_dev, gradient into net->grad.
+static int energy_step(mf_cnn *net, const mf_precond *P, const mf_op *A, const double *ri, double *loss_dev,
+                       EnergyWork &w, hipStream_t s) {
+  const int64_t n = P->n;
+  int rc = cnn_to_grid(ri, P->sd.as<double>(), +1, P->gidx.as<int32_t>(), P->gin.as<float>(), n, s);
+  if (!rc) rc = cnn_forward(net->theta.as<float>(), net->L, P->gin.as<float>(), P->acts, s);
+  if (!rc)
+    rc = cnn_from_grid(P->acts.y.as<float>(), P->sd.as<double>(), P->gidx.as<int32_t>(), P->bc.as<uint8_t>(), ri,
+                       w.z.as<double>(), n, s);
+  if (!rc) rc = op_apply_internal(A, w.z.ptr, w.Az.ptr, s);
+  if (!rc) rc = grow(net->gy, (size_t)n * 4);
+  if (!rc)
+    rc = cnn_energy(w.z.as<double>(), w.Az.as<double>(), ri, P->dinv.as<double>(), P->sd.as<double>(),
+                    P->gidx.as<int32_t>(), P->bc.as<uint8_t>(), n, w.part.as<double>(), loss_dev,
+                    w.scal.as<double>(), net->gy.as<float>(), s);
+  if (!rc) rc = cnn_backward(net, P->acts, P->gin.as<float>(), net->gy.as<float>(), s);
+  return rc;
+}
+
+static int energy_setup(mf_cnn *net, const mf_precond *P, const mf_op *A, EnergyWork &w, const char *who) {
+  if (!net || !P || !A) return fail(MF_EINVAL, std::string(who) + ": null argument");
+  if (P->kind != 1 || P->net != net)
+    return fail(MF_EINVAL, std::string(who) + ": P must be a learned preconditioner built on this network");
+  if (A->precision != MF_F64 || A->ndofs != P->n || A->numbering_id != P->numbering_id)
+    return fail(MF_EINVAL, std::string(who) + ": A must be the FP64 operator P was built from");
+  int rc = w.z.alloc((size_t)P->n * 8);
+  if (!rc) rc = w.Az.alloc((size_t)P->n * 8);
+  if (!rc) rc = w.part.alloc((size_t)cnn_energy_part_doubles() * 8);
+  if (!rc) rc = w.scal.alloc(8);
+  return rc;
+}
+
+// r (user numbering) -> internal numbering in P's workspace (or r itself)
+static int to_internal_of(const mf_precond *P, const double *r, const double *&ri, hipStream_t s) {
+  ri = r;
+  if (P->identity) return MF_OK;
+  int rc = grow(P->wr, (size_t)P->n * 8);
+  if (!rc) rc = launch_to_internal<double>(P->perm.as<int32_t>(), P->nnodes, P->ncomp, r, P->wr.as<double>(), s);
+  ri = P->wr.as<double>();
+  return rc;
+}
+
+}  // namespace mf
+
+extern "C" {
+
+int mf_cnn_energy_loss_grad(mf_cnn *net, const mf_precond *P, const mf_op *A, const double *r, double *loss,
+                            float *grad, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  EnergyWork w;
+  int rc = energy_setup(net, P, A, w, "mf_cnn_energy_loss_grad");
+  if (rc) return rc;
+  if (!r) return fail(MF_EINVAL, "mf_cnn_energy_loss_grad: null r");
+  DeviceBuffer ld;
+  rc = ld.alloc(8);
+  const double *ri = nullptr;
+  if (!rc) rc = to_internal_of(P, r, ri, s);
+  if (!rc) rc = energy_step(net, P, A, ri, ld.as<double>(), w, s);
+  if (rc) return rc;
+  if (grad) MF_HIP(hipMemcpyAsync(grad, net->grad.ptr, (size_t)net->L.nparams() * 4, hipMemcpyDeviceToDevice, s));
+  if (loss) MF_HIP(hipMemcpyAsync(loss, ld.ptr, 8, hipMemcpyDeviceToHost, s));
+  MF_HIP(hipStreamSynchronize(s));
+  return MF_OK;
+}
+
+int mf_cnn_train_energy(mf_cnn *net, const mf_precond *P, const mf_op *A, int nsamples, const double *r,
+                        int nsteps, const int32_t *order, float lr, double *losses, void *stream) {
+  hipStream_t s = (hipStream_t)stream;
+  EnergyWork w;
+  int rc = energy_setup(net, P, A, w, "mf_cnn_train_energy");
+  if (rc) return rc;
+  if (!r || !order || nsamples < 1 || nsteps < 0 || !(lr > 0.0f))
+    return fail(MF_EINVAL, "mf_cnn_train_energy: r / order / nsamples / nsteps / lr");
+  for (int i = 0; i < nsteps; i++)
+    if (order[i] < 0 || order[i] >= nsamples) return fail(MF_EINVAL, "mf_cnn_train_energy: order index out of range");
+  DeviceBuffer lhist;
+  if (nsteps > 0) {
+    rc = lhist.alloc((size_t)nsteps * 8);
+    if (rc) return rc;
+  }
+  for (int st = 0; st < nsteps; st++) {
+    const double *ri = nullptr;
+    rc = to_internal_of(P, r + (int64_t)order[st] * P->n, ri, s);
+    if (!rc) rc = energy_step(net, P, A, ri, lhist.as<double>() + st, w, s);
+    if (!rc) rc = adam(net, lr, s);
+    if (rc) return rc;
+  }
+  if (losses && nsteps > 0) MF_HIP(hipMemcpyAsync(losses, lhist.ptr, (size_t)nsteps * 8, hipMemcpyDeviceToHost, s));
+  MF_HIP(hipStreamSynchronize(s));
   return MF_OK;
 }
 

@@ -79,6 +79,13 @@ int cnn_from_grid(const float *grid, const double *sd, const int32_t *gidx, cons
 int cnn_crops(const float *gr, const float *ge, int Z, int Y, int X, const int32_t *corners, int ncrops, int n,
               float *r_out, float *e_out, hipStream_t s);
 int cnn_mark(const int32_t *idx, int64_t n, uint8_t *mask, hipStream_t s);
+// Energy (Ritz) loss of z = M r: loss = (z'Az - 2 z'r) / (r'D^{-1}r) into *loss (device),
+// and its gradient with respect to the network output on the lattice into gy
+// (constrained dofs: 0). part: cnn_energy_part_doubles() doubles; scale: 1 double.
+int64_t cnn_energy_part_doubles();
+int cnn_energy(const double *z, const double *Az, const double *r, const double *dinv, const double *sd,
+               const int32_t *gidx, const uint8_t *bc, int64_t n, double *part, double *loss, double *scale, float *gy,
+               hipStream_t s);
 
 // Activations of one forward pass (kept for the backward pass when training):
 // per level l the lattice grid[l], h[l], c[l] (l >= 1), g[l] (l >= 1), u[l] (l <= L-2).

@@ -472,6 +472,82 @@ int cnn_crops(const float *gr, const float *ge, int Z, int Y, int X, const int32
   return MF_OK;
 }
 
+// ------------------------------------------------------------------ energy (Ritz) loss
+constexpr int EN_BLK = 1024;
+
+// partials of z'Az, z'r and r'D^{-1}r (FP64)
+__global__ void __launch_bounds__(CB) energy_part_kernel(const double *__restrict__ z, const double *__restrict__ Az,
+                                                         const double *__restrict__ r, const double *__restrict__ dinv,
+                                                         int64_t n, double *__restrict__ part) {
+  __shared__ double sh[3][CB / 64];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x; i < n; i += (int64_t)gridDim.x * CB) {
+    const double zi = z[i], ri = r[i];
+    a += zi * Az[i];
+    b += zi * ri;
+    c += ri * ri * dinv[i];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+    c += __shfl_down(c, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][w] = a;
+    sh[1][w] = b;
+    sh[2][w] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    double t = 0.0;
+    for (int q = 0; q < CB / 64; q++) t += sh[threadIdx.x][q];
+    part[threadIdx.x * EN_BLK + blockIdx.x] = t;
+  }
+}
+
+// one thread: loss = (z'Az - 2 z'r) / (r'D^{-1}r) into *loss, gradient scale 2 / (r'D^{-1}r) into *scale
+__global__ void energy_final_kernel(const double *__restrict__ part, int nblk, double *__restrict__ loss,
+                                    double *__restrict__ scale) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int q = 0; q < nblk; q++) {
+    a += part[q];
+    b += part[EN_BLK + q];
+    c += part[2 * EN_BLK + q];
+  }
+  const bool ok = c > 0.0;
+  *loss = ok ? (a - 2.0 * b) / c : 0.0;
+  *scale = ok ? 2.0 / c : 0.0;
+}
+
+// dLoss/dy on the lattice: y enters z = D^{-1/2} y on free dofs, so g_y = D^{-1/2} g_z
+__global__ void energy_grad_kernel(const double *__restrict__ Az, const double *__restrict__ r,
+                                   const double *__restrict__ sd, const int32_t *__restrict__ gidx,
+                                   const uint8_t *__restrict__ bc, const double *__restrict__ scale, int64_t n,
+                                   float *__restrict__ gy) {
+  const int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x;
+  if (i >= n) return;
+  gy[gidx[i]] = (bc && bc[i]) ? 0.0f : (float)(sd[i] * (*scale) * (Az[i] - r[i]));
+}
+
+int64_t cnn_energy_part_doubles() { return 3 * EN_BLK; }
+
+int cnn_energy(const double *z, const double *Az, const double *r, const double *dinv, const double *sd,
+               const int32_t *gidx, const uint8_t *bc, int64_t n, double *part, double *loss, double *scale, float *gy,
+               hipStream_t s) {
+  if (n <= 0) return fail(MF_EINVAL, "cnn_energy: empty vector");
+  int64_t g = (n + CB - 1) / CB;
+  const int nblk = (int)(g < EN_BLK ? g : EN_BLK);
+  energy_part_kernel<<<nblk, CB, 0, s>>>(z, Az, r, dinv, n, part);
+  MF_HIP(hipGetLastError());
+  energy_final_kernel<<<1, 64, 0, s>>>(part, nblk, loss, scale);
+  MF_HIP(hipGetLastError());
+  energy_grad_kernel<<<(unsigned)((n + CB - 1) / CB), CB, 0, s>>>(Az, r, sd, gidx, bc, scale, n, gy);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
 __global__ void mark_kernel(const int32_t *__restrict__ idx, int64_t n, uint8_t *__restrict__ mask) {
   const int64_t i = (int64_t)blockIdx.x * CB + threadIdx.x;
   if (i < n) mask[idx[i]] = 1;

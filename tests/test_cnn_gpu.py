@@ -272,3 +272,47 @@ def test_training_reduces_loss_and_iterations(mf):
     info = mf.cg_solve(A64, bt, x, A32=A32, precond=M, rtol=1e-10)
     assert info["rel_residual"] <= 1e-10
     assert _rel(x.cpu().numpy(), xs.cpu().numpy()) <= 1e-8
+
+
+def _dense_dirichlet(space, kappa, bnd):
+    K = oracle.OracleOp(space, oracle.OP_POISSON, coef=kappa).assemble_dense()
+    K[bnd, :] = 0.0
+    K[:, bnd] = 0.0
+    K[bnd, bnd] = 1.0
+    d = oracle.OracleOp(space, oracle.OP_POISSON, coef=kappa).diagonal()
+    d[bnd] = 1.0
+    return K, d
+
+
+def test_energy_loss_and_gradient_match_oracle(mf):
+    import torch
+    print("cnn energy loss/grad", flush=True)
+    C, L = 4, 3
+    space, kappa, bnd, node_grid, G, A64, _ = _poisson_problem(mf, 4, 2, 8)  # 9^3 lattice
+    th = _theta(C, L, 31, 0.2)
+    net = mf.CNN(C, L, th)
+    M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
+    r = np.random.default_rng(9).uniform(-1, 1, space.ndofs)
+    r[bnd] = 0.0
+    loss, grad = net.energy_loss_grad(M, A64, torch.tensor(r, device="cuda"))
+    K, d = _dense_dirichlet(space, kappa, bnd)
+    dmask = np.zeros(space.nnodes, bool)
+    dmask[bnd] = True
+    rl, rg = conv.energy_loss_and_grad(th.astype(np.float64), C, L, r, K, d, node_grid, (G, G, G), dmask)
+    assert abs(loss - rl) <= 1e-5 * abs(rl)
+    assert _rel(grad.cpu().numpy(), rg) <= 1e-4
+
+
+def test_energy_training_lowers_the_loss(mf):
+    import torch
+    print("cnn energy training", flush=True)
+    space, kappa, bnd, node_grid, G, A64, _ = _poisson_problem(mf, 8, 2, 9)  # 17^3 lattice
+    net = mf.CNN(4, 4, mf.cnn_initial_weights(4, 4, seed=2))
+    M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
+    g = np.random.default_rng(10)
+    R = g.uniform(-1, 1, (6, space.ndofs))
+    R[:, bnd] = 0.0
+    Rt = torch.tensor(R, device="cuda")
+    losses = net.train_energy(M, A64, Rt, g.integers(0, 6, size=200), lr=2e-3)
+    assert np.all(np.isfinite(losses))
+    assert losses[-20:].mean() < losses[:5].mean()
