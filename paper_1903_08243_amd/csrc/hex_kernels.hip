@@ -9,13 +9,13 @@
 // tensor-product cell (Section 3 and Section 4.2.4: per-direction 1D loops
 // instead of dense tabulation).
 //
-// GPU mapping (gfx950): a workgroup is one 64-wide wavefront holding
-// EPB = floor(64 / n^2) cells; each cell owns n^2 lanes and three n^3 LDS
-// buffers. Because a wavefront owns its cells outright, the LDS exchanges
-// between stages need no cross-wavefront barrier, and wavefronts on a SIMD
-// run independently (no barrier convoys). Lanes left over (64 - EPB n^2)
-// mirror an active lane: they compute the same pencil and store the same
-// values, but never scatter.
+// GPU mapping (gfx950): a workgroup of WPB 64-wide wavefronts (one for n <= 5)
+// holds EPB = floor(64 WPB / n^2) cells; each cell owns n^2 lanes and three n^3
+// LDS buffers. With one wavefront, the LDS exchanges between stages need no
+// cross-wavefront barrier and wavefronts on a SIMD run independently; n = 6 and 7
+// use 2 and 4 wavefronts to keep more lanes busy. Lanes left over
+// (64 WPB - EPB n^2) mirror an active lane: they compute the same pencil and store
+// the same values, but never scatter.
 // A thread always holds one "pencil" (a 1D line of n values) in registers, so
 // each 1D contraction is a register-only product with compile-time tables
 // and LDS is only used to switch the pencil direction between stages.
@@ -46,7 +46,12 @@ template <typename T, int N> struct TabT {
 __device__ __forceinline__ void atomic_add_f(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f(float *p, float v) { unsafeAtomicAdd(p, v); }
 
-template <int N> constexpr int hex_epb() { return 64 / (N * N); }
+// Wavefronts per workgroup of the apply kernel: a workgroup holds floor(64 WPB / n^2)
+// cells, so n = 6 (36 lanes per cell) and n = 7 (49) keep 84% and 96% of their lanes
+// busy with 2 and 4 wavefronts instead of 56% and 77% with one. The batched kernel
+// always uses one wavefront.
+template <int N> constexpr int hex_wpb() { return N == 6 ? 2 : N == 7 ? 4 : 1; }
+template <int N, int WPB = 1> constexpr int hex_epb() { return WPB * 64 / (N * N); }
 
 // Padded LDS layout of one cell's n^3 buffer: entry (x, y, z) at z*SZ + y*SY + x,
 // cells SE apart. The strides are chosen (by an offline search over the three
@@ -76,16 +81,16 @@ inline int64_t xcd_grid(int64_t nb) { return ((nb + kXcds - 1) / kXcds) * kXcds;
 
 // LDS (in units of T) one wavefront needs for degree n-1: three padded n^3 buffers
 // per cell (one without gradients) and 32 geometry values per cell.
-template <int N, bool GRAD> constexpr int hex_lds_size() {
-  return hex_epb<N>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32);
+template <int N, bool GRAD, int WPB = 1> constexpr int hex_lds_size() {
+  return hex_epb<N, WPB>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32);
 }
 
 // Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
 // on the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
-template <typename T, int N, int KIND, bool ATOMIC>
+template <typename T, int N, int KIND, bool ATOMIC, int WPB = 1>
 __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, const int comp, T *lds) {
   using TB = TabT<T, N>;
-  constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N>();
+  constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N, WPB>();
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
@@ -117,7 +122,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 #pragma unroll
     for (int l = 0; l < N; l++) idx_cur[l] = ok ? cm[pa + N * pb + NN * l] : -1;
   }
-  for (int i = t; i < EPB * 32; i += 64) {
+  for (int i = t; i < EPB * 32; i += 64 * WPB) {
     const int e = i >> 5, j = i & 31;
     const int64_t c = A.c0 + b * EPB + e;
     T v = T(0);
@@ -361,11 +366,12 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 // consecutive items, so they run on the same XCD at about the same time and share
 // the cache lines of their interleaved values.
 template <typename T, int N, int KIND, bool ATOMIC>
-__global__ void __launch_bounds__(64) hex_apply_kernel(const HexArgs<T> A) {
-  __shared__ T lds[hex_lds_size<N, KIND != K_MASS>()];
-  const int64_t nb = (A.c1 - A.c0 + hex_epb<N>() - 1) / hex_epb<N>();  // cell batches
+__global__ void __launch_bounds__(64 * hex_wpb<N>()) hex_apply_kernel(const HexArgs<T> A) {
+  constexpr int WPB = hex_wpb<N>(), EPB = hex_epb<N, WPB>();
+  __shared__ T lds[hex_lds_size<N, KIND != K_MASS, WPB>()];
+  const int64_t nb = (A.c1 - A.c0 + EPB - 1) / EPB;  // cell batches
   const int64_t vb = xcd_batch(blockIdx.x, nb * A.ncomp);
-  if (vb < nb * A.ncomp) hex_cells<T, N, KIND, ATOMIC>(A, vb / A.ncomp, (int)(vb % A.ncomp), lds);
+  if (vb < nb * A.ncomp) hex_cells<T, N, KIND, ATOMIC, WPB>(A, vb / A.ncomp, (int)(vb % A.ncomp), lds);
 }
 
 // ---------------------------------------------------------------------------------- batched apply
@@ -540,7 +546,7 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A) {
 // ---------------------------------------------------------------------------------- launchers
 template <typename T, int N, bool AT>
 static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
-  constexpr int EPB = hex_epb<N>();
+  constexpr int WPB = hex_wpb<N>(), EPB = hex_epb<N, WPB>();
   const int64_t nc = a.c1 - a.c0;
   if (nc <= 0) return MF_OK;
   const int64_t nb = (nc + EPB - 1) / EPB;
@@ -553,7 +559,7 @@ static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
     default: return fail(MF_EUNSUPPORTED, "hex kernel: operator kind");
   }
   (void)fn;
-  dim3 grid((unsigned)xcd_grid(nb * a.ncomp)), block(64);  // one (cell batch, component) per wavefront
+  dim3 grid((unsigned)xcd_grid(nb * a.ncomp)), block(64 * WPB);  // one (cell batch, component) per workgroup
   switch (kind) {
     case K_MASS: hex_apply_kernel<T, N, K_MASS, AT><<<grid, block, 0, s>>>(a); break;
     case K_HELM: hex_apply_kernel<T, N, K_HELM, AT><<<grid, block, 0, s>>>(a); break;

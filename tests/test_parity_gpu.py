@@ -39,7 +39,9 @@ def _relerr(y, ref):
     return np.abs(y - ref).max() / np.abs(ref).max()
 
 
-HEX_M = 6  # 216 cells: ragged for every per-degree tile (64, 28, 16, 10, 7, 5 cells)
+# cells per workgroup of the hex kernel for k = 1..6: 16, 7, 4, 2, 3, 5; the mesh
+# sizes below leave a ragged last workgroup for every degree (216 or 343 cells)
+HEX_M = {1: 6, 2: 6, 3: 7, 4: 7, 5: 7, 6: 7}
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -48,7 +50,7 @@ HEX_M = 6  # 216 cells: ragged for every per-degree tile (64, 28, 16, 10, 7, 5 c
                          ids=["helmholtz", "laplacian1", "laplacian3", "mass", "poisson"])
 def test_hex_action(mf, k, prec, kind, ncomp):
     print(f"hex kind={kind} ncomp={ncomp} k={k} prec={prec}", flush=True)
-    mesh = mg.hex_mesh(HEX_M, 0.15, config=1, seed_k=k)
+    mesh = mg.hex_mesh(HEX_M[k], 0.15, config=1, seed_k=k)
     space = mg.hex_space(mesh, k, ncomp=ncomp, config=1)
     coef = None
     if kind in (0, 3):
