@@ -103,6 +103,11 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 
   const int t = threadIdx.x;
   const bool mirror = t >= EPB * NN;
+  // A mirror lane duplicates the pencil of lane t - EPB n^2. In a one-wavefront
+  // workgroup it runs in lockstep with that lane, so its identical LDS stores are
+  // harmless; across wavefronts its in-place read-then-write could interleave with
+  // the original's, so there it stores nothing (and never scatters).
+  const bool STORE = WPB == 1 || !mirror;
   const int tt = mirror ? t - EPB * NN : t;
   const int le = tt / NN, p = tt - le * NN;
   const int pa = p % N, pb = p / N;
@@ -185,7 +190,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
         T s = T(0);
   #pragma unroll
         for (int l = 0; l < N; l++) s += TB::B(c, l) * r[l];
-        u0[IX(pa, pb, c)] = s;
+        if (STORE) u0[IX(pa, pb, c)] = s;
       }
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): contract y with B
@@ -196,7 +201,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
         T s = T(0);
   #pragma unroll
         for (int yy = 0; yy < N; yy++) s += TB::B(b, yy) * r[yy];
-        u0[IX(pa, b, pb)] = s;
+        if (STORE) u0[IX(pa, b, pb)] = s;
       }
       __syncthreads();
       // ---- x-pencil (y = pa, z = pb): contract x with B -> u at points; x-derivative
@@ -210,14 +215,14 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
         v[a] = s;
       }
   #pragma unroll
-      for (int a = 0; a < N; a++) u0[IX(a, pa, pb)] = v[a];
+      for (int a = 0; a < N; a++) if (STORE) u0[IX(a, pa, pb)] = v[a];
       if constexpr (GRAD) {
   #pragma unroll
         for (int a = 0; a < N; a++) {
           T s = T(0);
   #pragma unroll
           for (int b = 0; b < N; b++) s += TB::D(a, b) * v[b];
-          u1[IX(a, pa, pb)] = s;
+          if (STORE) u1[IX(a, pa, pb)] = s;
         }
         __syncthreads();
         // ---- y-pencil (x = pa, z = pb): y-derivative of u
@@ -228,7 +233,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
           T s = T(0);
   #pragma unroll
           for (int yy = 0; yy < N; yy++) s += TB::D(b, yy) * r[yy];
-          u2[IX(pa, b, pb)] = s;
+          if (STORE) u2[IX(pa, b, pb)] = s;
         }
       }
       __syncthreads();
@@ -275,8 +280,8 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
             const T f0 = sc * (r0[0] * gx + r0[1] * gy + r0[2] * gz);
             const T f1 = sc * (r1[0] * gx + r1[1] * gy + r1[2] * gz);
             f2[c] = sc * (r2[0] * gx + r2[1] * gy + r2[2] * gz);
-            u1[IX(pa, pb, c)] = f0;
-            u2[IX(pa, pb, c)] = f1;
+            if (STORE) u1[IX(pa, pb, c)] = f0;
+            if (STORE) u2[IX(pa, pb, c)] = f1;
           }
           v[c] = mterm;
         }
@@ -291,7 +296,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
           }
         }
   #pragma unroll
-        for (int c = 0; c < N; c++) u0[IX(pa, pb, c)] = v[c];
+        for (int c = 0; c < N; c++) if (STORE) u0[IX(pa, pb, c)] = v[c];
       }
       __syncthreads();
       if constexpr (GRAD) {
@@ -303,7 +308,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
           T s = u0[IX(pa, b, pb)];
   #pragma unroll
           for (int yy = 0; yy < N; yy++) s += TB::D(yy, b) * r[yy];
-          u0[IX(pa, b, pb)] = s;
+          if (STORE) u0[IX(pa, b, pb)] = s;
         }
         __syncthreads();
       }
@@ -326,7 +331,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
         T s = T(0);
   #pragma unroll
         for (int a = 0; a < N; a++) s += TB::B(a, i) * v[a];
-        u0[IX(i, pa, pb)] = s;
+        if (STORE) u0[IX(i, pa, pb)] = s;
       }
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): B^T along y
@@ -337,7 +342,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
         T s = T(0);
   #pragma unroll
         for (int b = 0; b < N; b++) s += TB::B(b, j) * r[b];
-        u0[IX(pa, j, pb)] = s;
+        if (STORE) u0[IX(pa, j, pb)] = s;
       }
       __syncthreads();
       // ---- z-pencil (i, j) = (pa, pb): B^T along z, scatter-add
