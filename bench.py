@@ -264,7 +264,7 @@ def bench_c4(mf, mg, nsys=64, seed=0):
     return out
 
 
-def bench_c5(mf, mg, m=64, k=3, channels=8, levels=6, steps=400, lr=1e-3, train_rhs=2, seed=0):
+def bench_c5(mf, mg, m=64, k=3, channels=8, levels=7, steps=800, lr=1e-3, train_rhs=2, seed=0):
     """Variable-coefficient Poisson, Q3 on 64^3 hex (193^3 = 7,189,057 dofs), kappa =
     exp(GRF), homogeneous Dirichlet, b = M f: time to 1e-10 with Jacobi-CG (FP64, and
     FP32-action refinement) against flexible CG with the learned preconditioner

@@ -550,6 +550,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
   if (!op->identity) {
     rc = upload(op->perm, sp->user_of_int.data(), sp->user_of_int.size() * sizeof(int32_t), s);
+    if (!rc) rc = upload(op->iperm, sp->int_of_user.data(), sp->int_of_user.size() * sizeof(int32_t), s);
     const size_t vb = (size_t)op->ndofs * (precision == MF_F64 ? 8 : 4);
     if (!rc) rc = op->wx.alloc(vb);
     if (!rc) rc = op->wy.alloc(vb);
@@ -587,14 +588,15 @@ static int user_apply(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y,
   const int32_t *uoi = op->perm.as<int32_t>();
   int rc = launch_to_internal<T>(uoi, op->nnodes, op->ncomp, x, wx, s);
   if (!rc) rc = op_apply_t<T>(op, c0, c1, wx, wy, false, bc, s);
-  if (!rc) rc = launch_from_internal<T>(uoi, op->nnodes, op->ncomp, wy, y, acc, s);
+  if (!rc) rc = launch_from_internal_gather<T>(op->iperm.as<int32_t>(), op->nnodes, op->ncomp, wy, y, acc, s);
   return rc;
 }
 
 template <typename T> static int user_diag(const mf_op *op, T *d, hipStream_t s) {
   if (op->identity) return op_diag_t<T>(op, d, s);
   int rc = op_diag_t<T>(op, op->wy.as<T>(), s);
-  if (!rc) rc = launch_from_internal<T>(op->perm.as<int32_t>(), op->nnodes, op->ncomp, op->wy.as<T>(), d, false, s);
+  if (!rc)
+    rc = launch_from_internal_gather<T>(op->iperm.as<int32_t>(), op->nnodes, op->ncomp, op->wy.as<T>(), d, false, s);
   return rc;
 }
 

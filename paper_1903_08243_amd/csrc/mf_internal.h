@@ -146,6 +146,10 @@ int launch_to_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *xu, 
 // y_user[uoi[i]*nc + c] (+)= y_int[i*nc + c]
 template <typename T>
 int launch_from_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *yi, T *yu, bool acc, hipStream_t s);
+// the same with the inverse permutation iou (user node -> internal node), as a gather
+template <typename T>
+int launch_from_internal_gather(const int32_t *iou, int64_t nnodes, int nc, const T *yi, T *yu, bool acc,
+                                hipStream_t s);
 
 }  // namespace mf
 
@@ -164,6 +168,7 @@ struct mf_op {
   bool has_coef = false;
   mf::DeviceBuffer map, geo, coef, tab, bc_dofs;  // map and bc_dofs in internal numbering
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
+  mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
   mf::DeviceBuffer cell_user;                     // internal cell -> user cell (int32)
   std::vector<int64_t> colour_ptr;                // colour ranges of the internal cell order
   mf::DeviceBuffer wx, wy;                        // user-numbering workspaces (ndofs, op precision)

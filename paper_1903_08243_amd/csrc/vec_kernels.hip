@@ -44,6 +44,20 @@ __global__ void from_internal_kernel(const int32_t *__restrict__ uoi, int64_t nn
   }
 }
 
+// The same permutation as a gather over user nodes: random reads, sequential writes
+// (random partial-line writes cost more than random reads).
+template <typename T>
+__global__ void from_internal_gather_kernel(const int32_t *__restrict__ iou, int64_t nnodes, int nc,
+                                            const T *__restrict__ yi, T *__restrict__ yu, bool acc) {
+  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (u >= nnodes) return;
+  const int64_t i = iou[u];
+  for (int c = 0; c < nc; c++) {
+    const T v = yi[i * nc + c];
+    yu[u * nc + c] = acc ? yu[u * nc + c] + v : v;
+  }
+}
+
 static unsigned grid_for(int64_t n, int block, int64_t cap) {
   int64_t g = (n + block - 1) / block;
   if (g > cap) g = cap;
@@ -83,6 +97,18 @@ int launch_from_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *yi
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
+template <typename T>
+int launch_from_internal_gather(const int32_t *iou, int64_t nnodes, int nc, const T *yi, T *yu, bool acc,
+                                hipStream_t s) {
+  if (nnodes <= 0) return MF_OK;
+  from_internal_gather_kernel<T><<<grid_for(nnodes, 256, 1ll << 30), 256, 0, s>>>(iou, nnodes, nc, yi, yu, acc);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_from_internal_gather<double>(const int32_t *, int64_t, int, const double *, double *, bool,
+                                                 hipStream_t);
+template int launch_from_internal_gather<float>(const int32_t *, int64_t, int, const float *, float *, bool,
+                                                hipStream_t);
 template int launch_to_internal<double>(const int32_t *, int64_t, int, const double *, double *, hipStream_t);
 template int launch_to_internal<float>(const int32_t *, int64_t, int, const float *, float *, hipStream_t);
 template int launch_from_internal<double>(const int32_t *, int64_t, int, const double *, double *, bool, hipStream_t);
