@@ -554,6 +554,18 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     const size_t vb = (size_t)op->ndofs * (precision == MF_F64 ? 8 : 4);
     if (!rc) rc = op->wx.alloc(vb);
     if (!rc) rc = op->wy.alloc(vb);
+    if (!rc) rc = op->wt.alloc(vb);
+    if (!rc) {
+      // user -> internal: x_int[i] = x_user[user_of_int[i]]; back: y_user[u] = y_int[int_of_user[u]]
+      std::vector<int32_t> p1, p2, q1, q2;
+      permute2_positions(sp->user_of_int.data(), sp->nnodes, p1, p2);
+      permute2_positions(sp->int_of_user.data(), sp->nnodes, q1, q2);
+      rc = upload(op->to1, p1.data(), p1.size() * 4, s);
+      if (!rc) rc = upload(op->to2, p2.data(), p2.size() * 4, s);
+      if (!rc) rc = upload(op->from1, q1.data(), q1.size() * 4, s);
+      if (!rc) rc = upload(op->from2, q2.data(), q2.size() * 4, s);
+      if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+    }
     if (rc) return rc;
   }
   if (ct == MF_CELL_HEX)
@@ -584,11 +596,13 @@ namespace mf {
 template <typename T>
 static int user_apply(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool acc, bool bc, hipStream_t s) {
   if (op->identity) return op_apply_t<T>(op, c0, c1, x, y, acc, bc, s);
-  T *wx = op->wx.as<T>(), *wy = op->wy.as<T>();
-  const int32_t *uoi = op->perm.as<int32_t>();
-  int rc = launch_to_internal<T>(uoi, op->nnodes, op->ncomp, x, wx, s);
+  T *wx = op->wx.as<T>(), *wy = op->wy.as<T>(), *wt = op->wt.as<T>();
+  int rc = launch_permute2<T>(op->to1.as<int32_t>(), op->to2.as<int32_t>(), op->nnodes, op->ncomp, x, wt, wx, false,
+                              s);
   if (!rc) rc = op_apply_t<T>(op, c0, c1, wx, wy, false, bc, s);
-  if (!rc) rc = launch_from_internal_gather<T>(op->iperm.as<int32_t>(), op->nnodes, op->ncomp, wy, y, acc, s);
+  if (!rc)
+    rc = launch_permute2<T>(op->from1.as<int32_t>(), op->from2.as<int32_t>(), op->nnodes, op->ncomp, wy, wt, y, acc,
+                            s);
   return rc;
 }
 

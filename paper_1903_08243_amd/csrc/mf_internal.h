@@ -146,6 +146,12 @@ int launch_to_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *xu, 
 // y_user[uoi[i]*nc + c] (+)= y_int[i*nc + c]
 template <typename T>
 int launch_from_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *yi, T *yu, bool acc, hipStream_t s);
+// out[i] = in[src[i]] (i < n nodes of nc values) in two stages through tmp, with the
+// positions from permute2_positions(src)
+template <typename T>
+int launch_permute2(const int32_t *pos1, const int32_t *pos2, int64_t n, int nc, const T *in, T *tmp, T *out,
+                    bool acc, hipStream_t s);
+void permute2_positions(const int32_t *src, int64_t n, std::vector<int32_t> &pos1, std::vector<int32_t> &pos2);
 // the same with the inverse permutation iou (user node -> internal node), as a gather
 template <typename T>
 int launch_from_internal_gather(const int32_t *iou, int64_t nnodes, int nc, const T *yi, T *yu, bool acc,
@@ -169,6 +175,7 @@ struct mf_op {
   mf::DeviceBuffer map, geo, coef, tab, bc_dofs;  // map and bc_dofs in internal numbering
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
   mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
+  mf::DeviceBuffer to1, to2, from1, from2, wt;    // two-stage permutations (positions) and their buffer
   mf::DeviceBuffer cell_user;                     // internal cell -> user cell (int32)
   std::vector<int64_t> colour_ptr;                // colour ranges of the internal cell order
   mf::DeviceBuffer wx, wy;                        // user-numbering workspaces (ndofs, op precision)

@@ -58,6 +58,44 @@ __global__ void from_internal_gather_kernel(const int32_t *__restrict__ iou, int
   }
 }
 
+// Two-stage permutation out[i] = in[src[i]] for a random src (the user <-> internal
+// node numbering): a single pass reads or writes at random, which touches a whole
+// cache line per element. Stage 1 reads `in` in order and streams each element into
+// the bucket of its destination (buckets of consecutive destinations, filled in
+// source order, so every bucket is written front to back); stage 2 writes `out` in
+// order, gathering from its own bucket, which is small enough to stay in the L2 of
+// the XCD that processes it. Blocks are mapped so that each XCD takes a contiguous
+// range of elements (workgroup w runs on XCD w % 8).
+__device__ __forceinline__ int64_t vec_xcd_block(int64_t w, int64_t nb) {
+  const int64_t per = (nb + 7) / 8;
+  return (w % 8) * per + w / 8;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) perm_stage1_kernel(const int32_t *__restrict__ pos1, int64_t n, int nc,
+                                                          const T *__restrict__ in, T *__restrict__ tmp,
+                                                          int64_t nblk) {
+  const int64_t b = vec_xcd_block(blockIdx.x, nblk);
+  const int64_t j = b * 256 + threadIdx.x;
+  if (b >= nblk || j >= n) return;
+  const int64_t q = pos1[j];
+  for (int c = 0; c < nc; c++) tmp[q * nc + c] = in[j * nc + c];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) perm_stage2_kernel(const int32_t *__restrict__ pos2, int64_t n, int nc,
+                                                          const T *__restrict__ tmp, T *__restrict__ out, bool acc,
+                                                          int64_t nblk) {
+  const int64_t b = vec_xcd_block(blockIdx.x, nblk);
+  const int64_t i = b * 256 + threadIdx.x;
+  if (b >= nblk || i >= n) return;
+  const int64_t q = pos2[i];
+  for (int c = 0; c < nc; c++) {
+    const T v = tmp[q * nc + c];
+    out[i * nc + c] = acc ? out[i * nc + c] + v : v;
+  }
+}
+
 static unsigned grid_for(int64_t n, int block, int64_t cap) {
   int64_t g = (n + block - 1) / block;
   if (g > cap) g = cap;
@@ -105,6 +143,37 @@ int launch_from_internal_gather(const int32_t *iou, int64_t nnodes, int nc, cons
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
+template <typename T>
+int launch_permute2(const int32_t *pos1, const int32_t *pos2, int64_t n, int nc, const T *in, T *tmp, T *out,
+                    bool acc, hipStream_t s) {
+  if (n <= 0) return MF_OK;
+  const int64_t nblk = (n + 255) / 256, grid = ((nblk + 7) / 8) * 8;
+  perm_stage1_kernel<T><<<(unsigned)grid, 256, 0, s>>>(pos1, n, nc, in, tmp, nblk);
+  MF_HIP(hipGetLastError());
+  perm_stage2_kernel<T><<<(unsigned)grid, 256, 0, s>>>(pos2, n, nc, tmp, out, acc, nblk);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_permute2<double>(const int32_t *, const int32_t *, int64_t, int, const double *, double *,
+                                     double *, bool, hipStream_t);
+template int launch_permute2<float>(const int32_t *, const int32_t *, int64_t, int, const float *, float *, float *,
+                                    bool, hipStream_t);
+
+void permute2_positions(const int32_t *src, int64_t n, std::vector<int32_t> &pos1, std::vector<int32_t> &pos2) {
+  // destination buckets of S consecutive elements; inside a bucket, source order
+  const int64_t nbk = 256, S = (n + nbk - 1) / nbk;
+  std::vector<int32_t> dst((size_t)n);
+  for (int64_t i = 0; i < n; i++) dst[src[i]] = (int32_t)i;
+  std::vector<int64_t> fill((size_t)nbk, 0);
+  pos1.assign((size_t)n, 0);
+  pos2.assign((size_t)n, 0);
+  for (int64_t j = 0; j < n; j++) {
+    const int64_t b = dst[j] / S;
+    pos1[j] = (int32_t)(b * S + fill[b]++);
+  }
+  for (int64_t i = 0; i < n; i++) pos2[i] = pos1[src[i]];
+}
+
 template int launch_from_internal_gather<double>(const int32_t *, int64_t, int, const double *, double *, bool,
                                                  hipStream_t);
 template int launch_from_internal_gather<float>(const int32_t *, int64_t, int, const float *, float *, bool,

@@ -95,8 +95,13 @@ def _perturb(ijk: np.ndarray, m: int, amp: float, g: np.random.Generator) -> np.
 
 def _lattice(m: int, gdim: int) -> np.ndarray:
     """(m+1)^gdim lattice indices, first coordinate fastest."""
-    axes = np.meshgrid(*([np.arange(m + 1)] * gdim), indexing="ij")
-    return np.stack([a.transpose(tuple(range(gdim))[::-1]).ravel() for a in axes], axis=1)
+    n = m + 1
+    idx = np.arange(n ** gdim, dtype=np.int64)
+    cols = []
+    for _ in range(gdim):
+        cols.append(idx % n)
+        idx = idx // n
+    return np.stack(cols, axis=1)
 
 
 def hex_mesh(m: int, perturb: float = 0.0, config: int = 1, seed_k: int = 0) -> Mesh:
