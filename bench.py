@@ -398,6 +398,7 @@ def main():
     ap.add_argument("--c5-only", action="store_true", help="only the learned-preconditioner comparison")
     ap.add_argument("--c5-m", type=int, default=64, help="cells per direction of that problem")
     ap.add_argument("--simplex-only", action="store_true", help="only the triangle mass and tet elasticity actions")
+    ap.add_argument("--c4-only", action="store_true", help="only the batched 64-system solves")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only run the dominant action kernel 10 times and a 256 MiB reference copy "
                          "(for hardware-counter runs)")
@@ -418,6 +419,9 @@ def main():
         return
     if args.c5_only:
         print(json.dumps(bench_c5(mf, mg, m=args.c5_m)))
+        return
+    if args.c4_only:
+        print(json.dumps(bench_c4(mf, mg)))
         return
     if args.simplex_only:
         print(json.dumps(bench_simplex(mf, mg)))
