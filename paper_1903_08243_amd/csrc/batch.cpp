@@ -26,7 +26,7 @@
 namespace mf {
 
 static constexpr int BCHUNK = 8;              // CG iterations per graph replay
-static constexpr int64_t VCH = 1 << 15;        // vector chunk length
+static constexpr int64_t VCH = 1 << 12;        // vector chunk length (16 elements per thread)
 
 template <typename T> struct HostBatchOp {  // mirrors HexBatchOp<T> in hex_kernels.hip
   HexArgs<T> a;

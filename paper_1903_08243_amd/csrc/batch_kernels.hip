@@ -120,17 +120,24 @@ __global__ void baxpy_kernel(double *__restrict__ x, const double *__restrict__ 
   for (int64_t i = (int64_t)blockIdx.x * BR + threadIdx.x; i < n; i += (int64_t)gridDim.x * BR) x[i] += d[i];
 }
 
-// One thread per system: sum the system's chunk partials in order, advance its state.
-__global__ void bfinalize_kernel(const double *__restrict__ part, int nch, const int32_t *__restrict__ cptr,
-                                 CgState *st, int nsys, int stage) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nsys) return;
+// One workgroup per system: its chunk partials are summed in a fixed order (a
+// strided pass per thread, then a fixed reduction tree), and thread 0 advances the
+// system's state.
+__global__ void __launch_bounds__(BR) bfinalize_kernel(const double *__restrict__ part, int nch,
+                                                       const int32_t *__restrict__ cptr, CgState *st, int nsys,
+                                                       int stage) {
+  __shared__ double sh[BR / 64];
+  const int s = blockIdx.x;
+  if (s >= nsys) return;  // uniform over the workgroup
   const bool two = stage == CG_STAGE_UPDATE || stage == CG_STAGE_INIT;
-  double t0 = 0.0, t1 = 0.0;
-  for (int c = cptr[s]; c < cptr[s + 1]; c++) {
-    t0 += part[c];
-    if (two) t1 += part[nch + c];
+  double a = 0.0, b = 0.0;
+  for (int c = cptr[s] + threadIdx.x; c < cptr[s + 1]; c += BR) {
+    a += part[c];
+    if (two) b += part[nch + c];
   }
+  const double t0 = bsum(a, sh);
+  const double t1 = two ? bsum(b, sh) : 0.0;
+  if (threadIdx.x != 0) return;
   CgState S = st[s];
   switch (stage) {
     case CG_STAGE_RESIDUAL:
@@ -194,7 +201,7 @@ template int batch_fill<double>(const BatchVec &, double *, const CgState *, hip
 template int batch_fill<float>(const BatchVec &, float *, const CgState *, hipStream_t);
 
 static int fin(const BatchVec &v, CgState *st, int stage, hipStream_t s) {
-  bfinalize_kernel<<<(v.nsys + 63) / 64, 64, 0, s>>>(v.part, v.nch, v.cptr, st, v.nsys, stage);
+  bfinalize_kernel<<<v.nsys, BR, 0, s>>>(v.part, v.nch, v.cptr, st, v.nsys, stage);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
