@@ -232,15 +232,15 @@ def bench_cg(mf, mg, k=3, m=32):
     return out
 
 
-def bench_c4(mf, mg, nsys=64, seed=0):
-    """64 Helmholtz systems on hex meshes m ~ U{8..40}^3, Q_k with k ~ U{2..5}, b ~ U[-1,1]:
-    FP32-action batched CG with FP64 refinement to 1e-10 (autotuned persistent launch)
+def bench_c4(mf, mg, nsys=64, seed=0, m_lo=8, m_hi=40):
+    """64 Helmholtz systems on hex meshes m ~ U{m_lo..m_hi}^3, Q_k with k ~ U{2..5},
+    b ~ U[-1,1]: FP32-action batched CG with FP64 refinement to 1e-10 (autotuned launch)
     vs the same batch in FP64 vs one FP64 Jacobi-CG solve after another."""
     import tempfile
 
     import torch
     r = np.random.default_rng([4, 9, seed])
-    ms, ks = r.integers(8, 41, size=nsys), r.integers(2, 6, size=nsys)
+    ms, ks = r.integers(m_lo, m_hi + 1, size=nsys), r.integers(2, 6, size=nsys)
     sy = []
     for i in range(nsys):
         mesh = mg.hex_mesh(int(ms[i]), 0.15, config=3, seed_k=100 + i)
@@ -421,7 +421,7 @@ def main():
         print(json.dumps(bench_c5(mf, mg, m=args.c5_m)))
         return
     if args.c4_only:
-        print(json.dumps(bench_c4(mf, mg)))
+        print(json.dumps({"c4": bench_c4(mf, mg), "c4_small": bench_c4(mf, mg, seed=1, m_lo=4, m_hi=12)}))
         return
     if args.simplex_only:
         print(json.dumps(bench_simplex(mf, mg)))
@@ -532,6 +532,12 @@ def main():
             log(f"  c4: {json.dumps({k: v for k, v in extra['c4_batched'].items() if k not in ('mesh_m', 'degree')})}")
         except Exception as ex:
             extra["c4_batched"] = {"error": repr(ex)}
+        try:
+            log("batched solves (64 small Helmholtz systems, 4^3..12^3 cells) ...")
+            extra["c4_batched_small"] = bench_c4(mf, mg, seed=1, m_lo=4, m_hi=12)
+            log(f"  c4 small: {json.dumps({k: v for k, v in extra['c4_batched_small'].items() if k not in ('mesh_m', 'degree')})}")
+        except Exception as ex:
+            extra["c4_batched_small"] = {"error": repr(ex)}
     if not args.quick and not args.no_c5:
         torch.cuda.empty_cache()
         try:
