@@ -147,7 +147,10 @@ int launch_to_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *xu, 
 template <typename T>
 int launch_from_internal(const int32_t *uoi, int64_t nnodes, int nc, const T *yi, T *yu, bool acc, hipStream_t s);
 // out[i] = in[src[i]] (i < n nodes of nc values) in two stages through tmp, with the
-// positions from permute2_positions(src)
+// positions from permute2_positions(src): pos1[j] is the slot of source node j in the
+// bucket of its destination, pos2[i] the slot holding destination i, which lies in
+// bucket i / kPermBucket. One bucket of nc values must fit in LDS.
+constexpr int kPermBucket = 2048;
 template <typename T>
 int launch_permute2(const int32_t *pos1, const int32_t *pos2, int64_t n, int nc, const T *in, T *tmp, T *out,
                     bool acc, hipStream_t s);

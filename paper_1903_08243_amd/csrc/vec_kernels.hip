@@ -59,40 +59,48 @@ __global__ void from_internal_gather_kernel(const int32_t *__restrict__ iou, int
 }
 
 // Two-stage permutation out[i] = in[src[i]] for a random src (the user <-> internal
-// node numbering): a single pass reads or writes at random, which touches a whole
-// cache line per element. Stage 1 reads `in` in order and streams each element into
-// the bucket of its destination (buckets of consecutive destinations, filled in
-// source order, so every bucket is written front to back); stage 2 writes `out` in
-// order, gathering from its own bucket, which is small enough to stay in the L2 of
-// the XCD that processes it. Blocks are mapped so that each XCD takes a contiguous
-// range of elements (workgroup w runs on XCD w % 8).
+// node numbering). A single pass reads or writes at random, one L2 request per
+// element. Stage 1 reads `in` in order and streams each element into the bucket of
+// its destination (buckets of kPermBucket consecutive destinations, filled in source
+// order, so every bucket is written front to back); stage 2 gives each bucket to one
+// workgroup, which loads it into LDS with coalesced reads, permutes it there and
+// writes its range of `out` in order. Work is one lane per value (node, component),
+// so the components of a node are moved by neighbouring lanes as one contiguous run.
+// Blocks are mapped so that each XCD takes a contiguous range (workgroup w runs on
+// XCD w % 8).
 __device__ __forceinline__ int64_t vec_xcd_block(int64_t w, int64_t nb) {
   const int64_t per = (nb + 7) / 8;
   return (w % 8) * per + w / 8;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) perm_stage1_kernel(const int32_t *__restrict__ pos1, int64_t n, int nc,
-                                                          const T *__restrict__ in, T *__restrict__ tmp,
-                                                          int64_t nblk) {
+template <typename T, int NC>
+__global__ void __launch_bounds__(256) perm_stage1_kernel(const int32_t *__restrict__ pos1, int64_t n,
+                                                          const T *__restrict__ in, T *__restrict__ tmp, int64_t nblk) {
   const int64_t b = vec_xcd_block(blockIdx.x, nblk);
-  const int64_t j = b * 256 + threadIdx.x;
-  if (b >= nblk || j >= n) return;
-  const int64_t q = pos1[j];
-  for (int c = 0; c < nc; c++) tmp[q * nc + c] = in[j * nc + c];
+  const int64_t v = b * 256 + threadIdx.x;
+  if (b >= nblk || v >= n * NC) return;
+  const int64_t j = v / NC;
+  const int c = (int)(v - j * NC);
+  tmp[(int64_t)pos1[j] * NC + c] = in[v];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) perm_stage2_kernel(const int32_t *__restrict__ pos2, int64_t n, int nc,
-                                                          const T *__restrict__ tmp, T *__restrict__ out, bool acc,
-                                                          int64_t nblk) {
-  const int64_t b = vec_xcd_block(blockIdx.x, nblk);
-  const int64_t i = b * 256 + threadIdx.x;
-  if (b >= nblk || i >= n) return;
-  const int64_t q = pos2[i];
-  for (int c = 0; c < nc; c++) {
-    const T v = tmp[q * nc + c];
-    out[i * nc + c] = acc ? out[i * nc + c] + v : v;
+constexpr int kPermThreads = 1024;
+template <typename T, int NC>
+__global__ void __launch_bounds__(kPermThreads) perm_stage2_kernel(const int32_t *__restrict__ pos2, int64_t n,
+                                                                   const T *__restrict__ tmp, T *__restrict__ out,
+                                                                   bool acc, int64_t nbk) {
+  __shared__ T buf[kPermBucket * NC];
+  const int64_t b = vec_xcd_block(blockIdx.x, nbk);
+  if (b >= nbk) return;
+  const int64_t lo = b * kPermBucket;
+  const int cnt = (int)((n - lo < kPermBucket ? n - lo : kPermBucket) * NC);
+  for (int v = threadIdx.x; v < cnt; v += kPermThreads) buf[v] = tmp[lo * NC + v];
+  __syncthreads();
+  for (int v = threadIdx.x; v < cnt; v += kPermThreads) {
+    const int j = v / NC, c = v - j * NC;
+    // the slot of a destination in this bucket lies in this bucket (see permute2_positions)
+    const T x = buf[(pos2[lo + j] - lo) * NC + c];
+    out[lo * NC + v] = acc ? out[lo * NC + v] + x : x;
   }
 }
 
@@ -143,14 +151,23 @@ int launch_from_internal_gather(const int32_t *iou, int64_t nnodes, int nc, cons
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
+template <typename T, int NC>
+static void permute2_nc(const int32_t *pos1, const int32_t *pos2, int64_t n, const T *in, T *tmp, T *out, bool acc,
+                        hipStream_t s) {
+  const int64_t nblk = (n * NC + 255) / 256, nbk = (n + kPermBucket - 1) / kPermBucket;
+  perm_stage1_kernel<T, NC><<<(unsigned)(((nblk + 7) / 8) * 8), 256, 0, s>>>(pos1, n, in, tmp, nblk);
+  perm_stage2_kernel<T, NC><<<(unsigned)(((nbk + 7) / 8) * 8), kPermThreads, 0, s>>>(pos2, n, tmp, out, acc, nbk);
+}
 template <typename T>
 int launch_permute2(const int32_t *pos1, const int32_t *pos2, int64_t n, int nc, const T *in, T *tmp, T *out,
                     bool acc, hipStream_t s) {
   if (n <= 0) return MF_OK;
-  const int64_t nblk = (n + 255) / 256, grid = ((nblk + 7) / 8) * 8;
-  perm_stage1_kernel<T><<<(unsigned)grid, 256, 0, s>>>(pos1, n, nc, in, tmp, nblk);
-  MF_HIP(hipGetLastError());
-  perm_stage2_kernel<T><<<(unsigned)grid, 256, 0, s>>>(pos2, n, nc, tmp, out, acc, nblk);
+  switch (nc) {
+    case 1: permute2_nc<T, 1>(pos1, pos2, n, in, tmp, out, acc, s); break;
+    case 2: permute2_nc<T, 2>(pos1, pos2, n, in, tmp, out, acc, s); break;
+    case 3: permute2_nc<T, 3>(pos1, pos2, n, in, tmp, out, acc, s); break;
+    default: return fail(MF_EINVAL, "launch_permute2: ncomp must be 1..3");
+  }
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
@@ -161,7 +178,7 @@ template int launch_permute2<float>(const int32_t *, const int32_t *, int64_t, i
 
 void permute2_positions(const int32_t *src, int64_t n, std::vector<int32_t> &pos1, std::vector<int32_t> &pos2) {
   // destination buckets of S consecutive elements; inside a bucket, source order
-  const int64_t nbk = 256, S = (n + nbk - 1) / nbk;
+  const int64_t S = kPermBucket, nbk = (n + S - 1) / S;
   std::vector<int32_t> dst((size_t)n);
   for (int64_t i = 0; i < n; i++) dst[src[i]] = (int32_t)i;
   std::vector<int64_t> fill((size_t)nbk, 0);
