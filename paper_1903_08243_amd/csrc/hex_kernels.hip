@@ -43,6 +43,61 @@ template <typename T, int N> struct TabT {
   static __device__ __forceinline__ constexpr T w(int a) { return T(HexC<N>::w[a]); }
 };
 
+// The 1D matrices as n x n accessors: B and the collocation derivative D, and their
+// transposes (for the test-function side).
+template <int N> struct MatB { static constexpr double at(int a, int i) { return HexC<N>::B[a][i]; } };
+template <int N> struct MatBt { static constexpr double at(int a, int i) { return HexC<N>::B[i][a]; } };
+template <int N> struct MatD { static constexpr double at(int a, int i) { return HexC<N>::D[a][i]; } };
+template <int N> struct MatDt { static constexpr double at(int a, int i) { return HexC<N>::D[i][a]; } };
+
+// out[a] = sum_i M(a, i) in[i] for a 1D matrix with the reflection symmetry of the
+// tensor bases: M(n-1-a, n-1-i) = SIGN M(a, i). The Gauss points and GLL nodes are
+// symmetric about the middle of the interval, so B (and its transpose) has SIGN = +1
+// and the derivative D has SIGN = -1. Splitting the input into its even part
+// in[i] + in[n-1-i] and odd part in[i] - in[n-1-i] gives each output pair
+// (a, n-1-a) from two half-size products: about n^2/2 + n multiply-adds instead of
+// n^2, and half as many distinct constants.
+template <int N, typename M, int SIGN> constexpr bool reflection_symmetric() {
+  for (int a = 0; a < N; a++)
+    for (int i = 0; i < N; i++) {
+      const double d = M::at(a, i) - SIGN * M::at(N - 1 - a, N - 1 - i);
+      const double m = M::at(a, i) < 0 ? -M::at(a, i) : M::at(a, i);
+      if ((d < 0 ? -d : d) > 1e-13 * (m > 1 ? m : 1)) return false;
+    }
+  return true;
+}
+
+template <typename T, int N, typename M, int SIGN>
+__device__ __forceinline__ void eo_contract(const T (&in)[N], T (&out)[N]) {
+  static_assert(reflection_symmetric<N, M, SIGN>(), "1D table lacks the reflection symmetry");
+  constexpr int H = N / 2;
+  T e[H], o[H];
+#pragma unroll
+  for (int i = 0; i < H; i++) {
+    e[i] = in[i] + in[N - 1 - i];
+    o[i] = in[i] - in[N - 1 - i];
+  }
+#pragma unroll
+  for (int a = 0; a < H; a++) {
+    T pe = T(0), po = T(0);
+#pragma unroll
+    for (int i = 0; i < H; i++) {
+      pe += T(0.5 * (M::at(a, i) + M::at(a, N - 1 - i))) * e[i];
+      po += T(0.5 * (M::at(a, i) - M::at(a, N - 1 - i))) * o[i];
+    }
+    if constexpr (N % 2 == 1) pe += T(M::at(a, H)) * in[H];
+    out[a] = pe + po;
+    out[N - 1 - a] = SIGN > 0 ? pe - po : po - pe;
+  }
+  if constexpr (N % 2 == 1) {
+    T m = T(0);
+#pragma unroll
+    for (int i = 0; i < H; i++) m += T(M::at(H, i)) * (SIGN > 0 ? e[i] : o[i]);
+    if constexpr (SIGN > 0) m += T(M::at(H, H)) * in[H];
+    out[H] = m;
+  }
+}
+
 __device__ __forceinline__ void atomic_add_f(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f(float *p, float v) { unsafeAtomicAdd(p, v); }
 
@@ -185,63 +240,42 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       // ---- z-pencil (i, j) = (pa, pb) gathered one item earlier; contract z with B
   #pragma unroll
       for (int l = 0; l < N; l++) r[l] = r_cur[l];
+      eo_contract<T, N, MatB<N>, 1>(r, v);
   #pragma unroll
-      for (int c = 0; c < N; c++) {
-        T s = T(0);
-  #pragma unroll
-        for (int l = 0; l < N; l++) s += TB::B(c, l) * r[l];
-        if (STORE) u0[IX(pa, pb, c)] = s;
-      }
+      for (int c = 0; c < N; c++) if (STORE) u0[IX(pa, pb, c)] = v[c];
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): contract y with B
   #pragma unroll
       for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
+      eo_contract<T, N, MatB<N>, 1>(r, v);
   #pragma unroll
-      for (int b = 0; b < N; b++) {
-        T s = T(0);
-  #pragma unroll
-        for (int yy = 0; yy < N; yy++) s += TB::B(b, yy) * r[yy];
-        if (STORE) u0[IX(pa, b, pb)] = s;
-      }
+      for (int b = 0; b < N; b++) if (STORE) u0[IX(pa, b, pb)] = v[b];
       __syncthreads();
       // ---- x-pencil (y = pa, z = pb): contract x with B -> u at points; x-derivative
   #pragma unroll
       for (int xx = 0; xx < N; xx++) r[xx] = u0[IX(xx, pa, pb)];
-  #pragma unroll
-      for (int a = 0; a < N; a++) {
-        T s = T(0);
-  #pragma unroll
-        for (int xx = 0; xx < N; xx++) s += TB::B(a, xx) * r[xx];
-        v[a] = s;
-      }
+      eo_contract<T, N, MatB<N>, 1>(r, v);
   #pragma unroll
       for (int a = 0; a < N; a++) if (STORE) u0[IX(a, pa, pb)] = v[a];
       if constexpr (GRAD) {
+        eo_contract<T, N, MatD<N>, -1>(v, r);
   #pragma unroll
-        for (int a = 0; a < N; a++) {
-          T s = T(0);
-  #pragma unroll
-          for (int b = 0; b < N; b++) s += TB::D(a, b) * v[b];
-          if (STORE) u1[IX(a, pa, pb)] = s;
-        }
+        for (int a = 0; a < N; a++) if (STORE) u1[IX(a, pa, pb)] = r[a];
         __syncthreads();
         // ---- y-pencil (x = pa, z = pb): y-derivative of u
   #pragma unroll
         for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
+        eo_contract<T, N, MatD<N>, -1>(r, v);
   #pragma unroll
-        for (int b = 0; b < N; b++) {
-          T s = T(0);
-  #pragma unroll
-          for (int yy = 0; yy < N; yy++) s += TB::D(b, yy) * r[yy];
-          if (STORE) u2[IX(pa, b, pb)] = s;
-        }
+        for (int b = 0; b < N; b++) if (STORE) u2[IX(pa, b, pb)] = v[b];
       }
       __syncthreads();
       // ---- pointwise on z-pencil (a, b) = (pa, pb)
       {
-        T uz[N], f2[N];
+        T uz[N], f2[N], dzv[N];
   #pragma unroll
         for (int c = 0; c < N; c++) uz[c] = u0[IX(pa, pb, c)];
+        if constexpr (GRAD) eo_contract<T, N, MatD<N>, -1>(uz, dzv);
   #pragma unroll
         for (int c = 0; c < N; c++) {
           const T x3 = TB::g(c);
@@ -268,9 +302,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
                              j1[0] * j2[1] - j1[1] * j2[0]};
             const T sc = wq * kq / adet;
             // d(u)/d(ref x), d/d(ref y) from LDS, d/d(ref z) from the register pencil
-            T dz = T(0);
-  #pragma unroll
-            for (int cc = 0; cc < N; cc++) dz += TB::D(c, cc) * uz[cc];
+            const T dz = dzv[c];
             const T dx = u1[IX(pa, pb, c)];
             const T dy = u2[IX(pa, pb, c)];
             // physical gradient times |det| pieces: e_b = r_b . (adj^T d) ; F = sc * adj adj^T d
@@ -287,13 +319,9 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
         }
         if constexpr (GRAD) {
           // z-transpose of the derivative: v[c] += sum_c' D[c'][c] f2[c']
+          eo_contract<T, N, MatDt<N>, -1>(f2, dzv);
   #pragma unroll
-          for (int c = 0; c < N; c++) {
-            T s = v[c];
-  #pragma unroll
-            for (int cc = 0; cc < N; cc++) s += TB::D(cc, c) * f2[cc];
-            v[c] = s;
-          }
+          for (int c = 0; c < N; c++) v[c] += dzv[c];
         }
   #pragma unroll
         for (int c = 0; c < N; c++) if (STORE) u0[IX(pa, pb, c)] = v[c];
@@ -303,11 +331,10 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
         // ---- y-pencil (x = pa, z = pb): add D^T along y of f1
   #pragma unroll
         for (int yy = 0; yy < N; yy++) r[yy] = u2[IX(pa, yy, pb)];
+        eo_contract<T, N, MatDt<N>, -1>(r, v);
   #pragma unroll
         for (int b = 0; b < N; b++) {
-          T s = u0[IX(pa, b, pb)];
-  #pragma unroll
-          for (int yy = 0; yy < N; yy++) s += TB::D(yy, b) * r[yy];
+          const T s = u0[IX(pa, b, pb)] + v[b];
           if (STORE) u0[IX(pa, b, pb)] = s;
         }
         __syncthreads();
@@ -318,41 +345,29 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       if constexpr (GRAD) {
   #pragma unroll
         for (int a = 0; a < N; a++) r[a] = u1[IX(a, pa, pb)];
+        T dv[N];
+        eo_contract<T, N, MatDt<N>, -1>(r, dv);
   #pragma unroll
-        for (int a = 0; a < N; a++) {
-          T s = v[a];
-  #pragma unroll
-          for (int aa = 0; aa < N; aa++) s += TB::D(aa, a) * r[aa];
-          v[a] = s;
-        }
+        for (int a = 0; a < N; a++) v[a] += dv[a];
       }
+      eo_contract<T, N, MatBt<N>, 1>(v, r);
   #pragma unroll
-      for (int i = 0; i < N; i++) {
-        T s = T(0);
-  #pragma unroll
-        for (int a = 0; a < N; a++) s += TB::B(a, i) * v[a];
-        if (STORE) u0[IX(i, pa, pb)] = s;
-      }
+      for (int i = 0; i < N; i++) if (STORE) u0[IX(i, pa, pb)] = r[i];
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): B^T along y
   #pragma unroll
       for (int b = 0; b < N; b++) r[b] = u0[IX(pa, b, pb)];
+      eo_contract<T, N, MatBt<N>, 1>(r, v);
   #pragma unroll
-      for (int j = 0; j < N; j++) {
-        T s = T(0);
-  #pragma unroll
-        for (int b = 0; b < N; b++) s += TB::B(b, j) * r[b];
-        if (STORE) u0[IX(pa, j, pb)] = s;
-      }
+      for (int j = 0; j < N; j++) if (STORE) u0[IX(pa, j, pb)] = v[j];
       __syncthreads();
       // ---- z-pencil (i, j) = (pa, pb): B^T along z, scatter-add
   #pragma unroll
       for (int c = 0; c < N; c++) r[c] = u0[IX(pa, pb, c)];
+      eo_contract<T, N, MatBt<N>, 1>(r, v);
   #pragma unroll
       for (int l = 0; l < N; l++) {
-        T s = T(0);
-  #pragma unroll
-        for (int c = 0; c < N; c++) s += TB::B(c, l) * r[c];
+        const T s = v[l];
         const int idx = mirror ? -1 : idx_cur[l];
         if (idx >= 0) {
           if constexpr (ATOMIC) atomic_add_f(&A.y[(int64_t)idx * nc + comp], s);
