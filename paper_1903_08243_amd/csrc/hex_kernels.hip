@@ -391,7 +391,8 @@ __global__ void __launch_bounds__(64 * hex_wpb<N>()) hex_apply_kernel(const HexA
   __shared__ T lds[hex_lds_size<N, KIND != K_MASS, WPB>()];
   const int64_t nb = (A.c1 - A.c0 + EPB - 1) / EPB;  // cell batches
   const int64_t vb = xcd_batch(blockIdx.x, nb * A.ncomp);
-  if (vb < nb * A.ncomp) hex_cells<T, N, KIND, ATOMIC, WPB>(A, vb / A.ncomp, (int)(vb % A.ncomp), lds);
+  // the grid has fewer than 2^31 items, so the split uses 32-bit division
+  if (vb < nb * A.ncomp) hex_cells<T, N, KIND, ATOMIC, WPB>(A, (int)vb / A.ncomp, (int)vb % A.ncomp, lds);
 }
 
 // ---------------------------------------------------------------------------------- batched apply
@@ -563,6 +564,175 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A) {
   }
 }
 
+// ---------------------------------------------------------------------------------- Q1
+// Q1 (n = 2) with one cell per lane, for the coloured scatter. A Q1 cell has 8 nodes,
+// so the pencil kernel's LDS stages and barriers cost more than its arithmetic. Here a
+// wavefront owns an aligned block of 64 cells and every stage keeps its 8 values in
+// registers. The map, geometry and coefficient of degree-1 operators are stored a
+// second time in blocks of 64 cells, entry-major inside a block
+// ([cell / 64][entry][cell % 64]), so each per-entry load of a wavefront reads one
+// contiguous segment. Per point the gradient is the collocation derivative of the
+// point values, and the test side is accumulated straight into the 8 point values
+// before the transposed interpolation. The cells of one launch share no node, so the
+// result is added to y with plain loads and stores. (With atomics, the 64 lanes of
+// an atomic instruction would hit 64 different cells' cache lines; the atomic
+// scatter uses the pencil kernel, whose lanes of one cell hit neighbouring nodes.)
+template <typename T, int KIND>
+__global__ void __launch_bounds__(64) hex_q1_kernel(const HexArgs<T> A) {
+  constexpr int N = 2;
+  using TB = TabT<T, N>;
+  constexpr bool GRAD = KIND != K_MASS;
+  constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
+  constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
+
+  const int64_t b0 = A.c0 >> 6, nblk = ((A.c1 + 63) >> 6) - b0;
+  const int64_t vb = xcd_batch(blockIdx.x, nblk * A.ncomp);
+  if (vb >= nblk * A.ncomp) return;
+  const int64_t blk = b0 + (int)vb / A.ncomp;  // the grid has fewer than 2^31 items
+  const int comp = (int)vb % A.ncomp;
+  const int lane = threadIdx.x;
+  const int64_t c = blk * 64 + lane;  // the arrays are padded to whole blocks
+  bool ok = c >= A.c0 && c < A.c1;
+  if (ok && A.cell_user) {
+    const int64_t u = A.cell_user[c];
+    ok = u >= A.ulo && u < A.uhi;
+  }
+  const int nc = A.ncomp;
+  int idx[8];
+  T xv[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const int32_t m = A.map[(blk * 8 + i) * 64 + lane];
+    idx[i] = ok ? m : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++) xv[i] = idx[i] >= 0 ? A.x[(int64_t)idx[i] * nc + comp] : T(0);
+  T G[21];
+#pragma unroll
+  for (int j = 0; j < 21; j++) G[j] = A.geo[(blk * 24 + j) * 64 + lane];
+  T K[8];
+  if constexpr (COEF) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) K[j] = A.coef ? A.coef[(blk * 8 + j) * 64 + lane] : T(j == 0 ? 1 : 0);
+  }
+
+  // values at the points: u = (B x B x B) x, index a + 2 b + 4 c (x fastest)
+  T u[8], t[8];
+#pragma unroll
+  for (int l = 0; l < 4; l++) {  // along x
+    const T e0 = xv[2 * l], e1 = xv[2 * l + 1];
+    t[2 * l] = TB::B(0, 0) * e0 + TB::B(0, 1) * e1;
+    t[2 * l + 1] = TB::B(1, 0) * e0 + TB::B(1, 1) * e1;
+  }
+#pragma unroll
+  for (int l = 0; l < 2; l++)  // along y
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      const T e0 = t[a + 4 * l], e1 = t[a + 2 + 4 * l];
+      u[a + 4 * l] = TB::B(0, 0) * e0 + TB::B(0, 1) * e1;
+      u[a + 2 + 4 * l] = TB::B(1, 0) * e0 + TB::B(1, 1) * e1;
+    }
+#pragma unroll
+  for (int p = 0; p < 4; p++) {  // along z
+    const T e0 = u[p], e1 = u[p + 4];
+    t[p] = TB::B(0, 0) * e0 + TB::B(0, 1) * e1;
+    t[p + 4] = TB::B(1, 0) * e0 + TB::B(1, 1) * e1;
+  }
+#pragma unroll
+  for (int q = 0; q < 8; q++) u[q] = t[q];
+
+  // pointwise; the test side (mass term and transposed derivatives of the fluxes) is
+  // accumulated in t at the points
+#pragma unroll
+  for (int q = 0; q < 8; q++) t[q] = T(0);
+#pragma unroll
+  for (int q = 0; q < 8; q++) {
+    const int a = q & 1, b = (q >> 1) & 1, cc = q >> 2;
+    const T x1 = TB::g(a), x2 = TB::g(b), x3 = TB::g(cc);
+    T j1[3], j2[3], j3[3];
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      const T c1 = G[0 + d], c2 = G[3 + d], c3 = G[6 + d], c4 = G[9 + d], c5 = G[12 + d], c6 = G[15 + d],
+              c7 = G[18 + d];
+      j1[d] = c1 + c4 * x2 + (c5 + c7 * x2) * x3;
+      j2[d] = c2 + c4 * x1 + (c6 + c7 * x1) * x3;
+      j3[d] = c3 + c5 * x1 + (c6 + c7 * x1) * x2;
+    }
+    const T r0[3] = {j2[1] * j3[2] - j2[2] * j3[1], j2[2] * j3[0] - j2[0] * j3[2], j2[0] * j3[1] - j2[1] * j3[0]};
+    const T det = j1[0] * r0[0] + j1[1] * r0[1] + j1[2] * r0[2];
+    const T adet = det < T(0) ? -det : det;
+    const T wq = TB::w(a) * TB::w(b) * TB::w(cc);
+    T kq = T(1);
+    if constexpr (COEF)
+      kq = K[0] + K[1] * x1 + K[2] * x2 + K[4] * x1 * x2 + (K[3] + K[5] * x1 + K[6] * x2 + K[7] * x1 * x2) * x3;
+    if constexpr (MASS) t[q] += wq * adet * kq * u[q];
+    if constexpr (GRAD) {
+      const T r1[3] = {j3[1] * j1[2] - j3[2] * j1[1], j3[2] * j1[0] - j3[0] * j1[2], j3[0] * j1[1] - j3[1] * j1[0]};
+      const T r2[3] = {j1[1] * j2[2] - j1[2] * j2[1], j1[2] * j2[0] - j1[0] * j2[2], j1[0] * j2[1] - j1[1] * j2[0]};
+      const T sc = wq * kq / adet;
+      // reference gradient by collocation on the two points of each direction
+      const int qx = q ^ 1, qy = q ^ 2, qz = q ^ 4;
+      const T dx = TB::D(a, a) * u[q] + TB::D(a, 1 - a) * u[qx];
+      const T dy = TB::D(b, b) * u[q] + TB::D(b, 1 - b) * u[qy];
+      const T dz = TB::D(cc, cc) * u[q] + TB::D(cc, 1 - cc) * u[qz];
+      const T gx = r0[0] * dx + r1[0] * dy + r2[0] * dz;
+      const T gy = r0[1] * dx + r1[1] * dy + r2[1] * dz;
+      const T gz = r0[2] * dx + r1[2] * dy + r2[2] * dz;
+      const T f0 = sc * (r0[0] * gx + r0[1] * gy + r0[2] * gz);
+      const T f1 = sc * (r1[0] * gx + r1[1] * gy + r1[2] * gz);
+      const T f2 = sc * (r2[0] * gx + r2[1] * gy + r2[2] * gz);
+      // transposed collocation derivatives: point q's flux reaches q and its neighbour
+      t[q] += TB::D(a, a) * f0 + TB::D(b, b) * f1 + TB::D(cc, cc) * f2;
+      t[qx] += TB::D(a, 1 - a) * f0;
+      t[qy] += TB::D(b, 1 - b) * f1;
+      t[qz] += TB::D(cc, 1 - cc) * f2;
+    }
+  }
+
+  // transposed interpolation back to the nodes: (B^T x B^T x B^T) t
+  T yv[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) yv[i] = idx[i] >= 0 ? A.y[(int64_t)idx[i] * nc + comp] : T(0);
+#pragma unroll
+  for (int p = 0; p < 4; p++) {  // along z
+    const T e0 = t[p], e1 = t[p + 4];
+    u[p] = TB::B(0, 0) * e0 + TB::B(1, 0) * e1;
+    u[p + 4] = TB::B(0, 1) * e0 + TB::B(1, 1) * e1;
+  }
+#pragma unroll
+  for (int l = 0; l < 2; l++)  // along y
+#pragma unroll
+    for (int a = 0; a < 2; a++) {
+      const T e0 = u[a + 4 * l], e1 = u[a + 2 + 4 * l];
+      t[a + 4 * l] = TB::B(0, 0) * e0 + TB::B(1, 0) * e1;
+      t[a + 2 + 4 * l] = TB::B(0, 1) * e0 + TB::B(1, 1) * e1;
+    }
+#pragma unroll
+  for (int l = 0; l < 4; l++) {  // along x, then scatter
+    const T e0 = t[2 * l], e1 = t[2 * l + 1];
+    const T s0 = TB::B(0, 0) * e0 + TB::B(1, 0) * e1;
+    const T s1 = TB::B(0, 1) * e0 + TB::B(1, 1) * e1;
+    if (idx[2 * l] >= 0) A.y[(int64_t)idx[2 * l] * nc + comp] = yv[2 * l] + s0;
+    if (idx[2 * l + 1] >= 0) A.y[(int64_t)idx[2 * l + 1] * nc + comp] = yv[2 * l + 1] + s1;
+  }
+}
+
+template <typename T>
+static int launch_q1(int kind, const HexArgs<T> &a, hipStream_t s) {
+  if (a.c1 <= a.c0) return MF_OK;
+  const int64_t nblk = ((a.c1 + 63) >> 6) - (a.c0 >> 6);
+  const dim3 grid((unsigned)xcd_grid(nblk * a.ncomp)), block(64);
+  switch (kind) {
+    case K_MASS: hex_q1_kernel<T, K_MASS><<<grid, block, 0, s>>>(a); break;
+    case K_HELM: hex_q1_kernel<T, K_HELM><<<grid, block, 0, s>>>(a); break;
+    case K_LAP: hex_q1_kernel<T, K_LAP><<<grid, block, 0, s>>>(a); break;
+    case K_POIS: hex_q1_kernel<T, K_POIS><<<grid, block, 0, s>>>(a); break;
+    default: return fail(MF_EUNSUPPORTED, "hex kernel: operator kind");
+  }
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
 // ---------------------------------------------------------------------------------- launchers
 template <typename T, int N, bool AT>
 static int launch_apply_na(int kind, const HexArgs<T> &a, hipStream_t s) {
@@ -615,7 +785,7 @@ static int launch_diag_n(int kind, const HexArgs<T> &a, hipStream_t s) {
 template <typename T>
 int launch_hex_apply(int N, int kind, const HexArgs<T> &a, bool atomic, hipStream_t s) {
   switch (N) {
-    case 2: return launch_apply_n<T, 2>(kind, a, atomic, s);
+    case 2: return atomic ? launch_apply_n<T, 2>(kind, a, true, s) : launch_q1<T>(kind, a, s);
     case 3: return launch_apply_n<T, 3>(kind, a, atomic, s);
     case 4: return launch_apply_n<T, 4>(kind, a, atomic, s);
     case 5: return launch_apply_n<T, 5>(kind, a, atomic, s);

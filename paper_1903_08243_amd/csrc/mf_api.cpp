@@ -293,8 +293,9 @@ template <typename T> static int setup_hex(mf_op *op, const mf_space *sp, const 
   }
   int rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
   if (rc) return rc;
+  std::vector<T> cf;
   if (op->has_coef) {
-    std::vector<T> cf((size_t)nc * 8);
+    cf.resize((size_t)nc * 8);
     for (int64_t K = 0; K < nc; K++) {
       double X[8], c[8];
       for (int v = 0; v < 8; v++) X[v] = pr->vertex_coef[sp->cell2vert_int[K * 8 + v]];
@@ -302,6 +303,24 @@ template <typename T> static int setup_hex(mf_op *op, const mf_space *sp, const 
       for (int m = 0; m < 8; m++) cf[K * 8 + m] = (T)c[m];
     }
     rc = upload(op->coef, cf.data(), cf.size() * sizeof(T), s);
+    if (rc) return rc;
+  }
+  if (k == 1) {
+    // block-interleaved copies for the degree-1 kernel; cells past the end get the
+    // unit-cube map and coefficient 1
+    const int64_t nb = (nc + 63) / 64;
+    std::vector<T> g2((size_t)nb * 24 * 64, T(0)), k2;
+    for (int64_t K = 0; K < nb * 64; K++)
+      for (int j = 0; j < 24; j++)
+        g2[((K / 64) * 24 + j) * 64 + K % 64] = K < nc ? geo[K * 24 + j] : T(j == 0 || j == 4 || j == 8 ? 1 : 0);
+    rc = upload(op->q1geo, g2.data(), g2.size() * sizeof(T), s);
+    if (!rc && op->has_coef) {
+      k2.assign((size_t)nb * 8 * 64, T(0));
+      for (int64_t K = 0; K < nb * 64; K++)
+        for (int j = 0; j < 8; j++) k2[((K / 64) * 8 + j) * 64 + K % 64] = K < nc ? cf[K * 8 + j] : T(j == 0 ? 1 : 0);
+      rc = upload(op->q1coef, k2.data(), k2.size() * sizeof(T), s);
+    }
+    if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     if (rc) return rc;
   }
   return MF_OK;
@@ -407,8 +426,11 @@ template <typename T>
 static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool atomic, const int32_t *filt,
                        int64_t ulo, int64_t uhi, hipStream_t s) {
   if (op->cell_type == MF_CELL_HEX) {
-    HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, x, y, c0, c1,
-                 op->ncomp, filt, ulo, uhi};
+    // the coloured degree-1 kernel reads the block-interleaved copies
+    const bool q1 = op->degree == 1 && !atomic;
+    HexArgs<T> a{(q1 ? op->q1map : op->map).as<int32_t>(), (q1 ? op->q1geo : op->geo).as<T>(),
+                 op->has_coef ? (q1 ? op->q1coef : op->coef).as<T>() : nullptr, x, y, c0, c1, op->ncomp, filt, ulo,
+                 uhi};
     return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
@@ -446,13 +468,18 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
 // Coloured launches avoid device-scope float atomics but cost one launch per
 // colour with 1/ncolours of the cells each. Measured on MI355X: for 32^3 hex the
 // single atomic launch is faster for scalar operators and the coloured launches
-// win for 3-component operators from Q2 up (three atomics per node otherwise);
-// for P2/P3 tet elasticity on 48^3 x 6 cells (31 colours) the coloured launches
-// are 1.1x (FP64) to 3.4x (FP32) faster than the atomic scatter.
+// win for 3-component operators from Q2 up (three atomics per node otherwise). For
+// scalar operators they break even at about 64^3 cells (Q1: 51 against 55 us, Q2:
+// 142 against 127 us in FP64) and win above (Q1 at 128^3: 238 against 346 us, Q2 at
+// 96^3: 364 against 458 us). For P2/P3 tet elasticity on 48^3 x 6 cells (31
+// colours) the coloured launches are 1.1x (FP64) to 3.4x (FP32) faster.
 static bool default_coloured(const mf_op *op) {
-  if (op->ncells < 4096 || op->degree < 2) return false;
-  if (op->cell_type == MF_CELL_HEX) return op->ncomp == 3;
-  return op->cell_type == MF_CELL_TET;
+  if (op->ncells < 4096) return false;
+  if (op->cell_type == MF_CELL_HEX) {
+    if (op->ncomp == 3 && op->degree >= 2) return true;
+    return op->ncells >= (op->degree == 1 ? (1 << 19) : (1 << 18));
+  }
+  return op->cell_type == MF_CELL_TET && op->degree >= 2;
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
@@ -533,6 +560,15 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   }
   int rc = upload(op->map, m.data(), m.size() * sizeof(int32_t), s);
   if (rc) return rc;
+  std::vector<int32_t> m2;
+  if (ct == MF_CELL_HEX && op->degree == 1) {
+    const int64_t nb = (nc + 63) / 64;
+    m2.assign((size_t)nb * 8 * 64, -1);
+    for (int64_t K = 0; K < nc; K++)
+      for (int i = 0; i < 8; i++) m2[((K / 64) * 8 + i) * 64 + K % 64] = m[K * 8 + i];
+    rc = upload(op->q1map, m2.data(), m2.size() * sizeof(int32_t), s);
+    if (rc) return rc;
+  }
   if (pr->dirichlet) {
     std::vector<int32_t> bd;
     for (int64_t n = 0; n < sp->nnodes; n++)

@@ -72,6 +72,8 @@ namespace mf {
 
 // Launch parameters of the hex sum-factorised kernel, per precision.
 template <typename T> struct HexArgs {
+  // [cell][entry] arrays; the degree-1 apply kernel takes the block-interleaved
+  // copies ([cell/64][entry][cell%64], padded to whole blocks) instead
   const int32_t *map;  // ncells x N^3 node ids (negative: constrained, -1-node)
   const T *geo;        // ncells x 24: trilinear coefficient vectors c1..c7 (x3), pad
   const T *coef;       // ncells x 8 monomial coefficients of the vertex coefficient, or null
@@ -86,6 +88,8 @@ template <typename T> struct HexArgs {
 // Kernel launchers (hex_kernels.hip)
 // atomic: scatter with device-scope atomics (any cell set); otherwise plain
 // read-modify-write, valid only when no two cells of [c0, c1) share a node.
+// For N = 2 the non-atomic launch takes the block-interleaved arrays (q1map, q1geo,
+// q1coef) and the atomic one the [cell][entry] arrays.
 template <typename T>
 int launch_hex_apply(int N, int kind, const HexArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
@@ -176,6 +180,8 @@ struct mf_op {
   double lam = 1.0, mu = 0.5;
   bool has_coef = false;
   mf::DeviceBuffer map, geo, coef, tab, bc_dofs;  // map and bc_dofs in internal numbering
+  mf::DeviceBuffer q1map, q1geo, q1coef;          // degree-1 hex: map, geometry, coefficient in
+                                                  // blocks of 64 cells, [cell/64][entry][cell%64]
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
   mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
   mf::DeviceBuffer to1, to2, from1, from2, wt;    // two-stage permutations (positions) and their buffer

@@ -62,6 +62,25 @@ def test_hex_action(mf, k, prec, kind, ncomp):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
+@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("kind,ncomp", [(1, 1), (2, 3), (3, 1), (0, 1)],
+                         ids=["helmholtz", "laplacian3", "poisson", "mass"])
+def test_hex_scatter_modes(mf, k, scatter, prec, kind, ncomp):
+    """Both scatter forms against the oracle (the default picks one per operator)."""
+    import torch
+    print(f"hex scatter={scatter} kind={kind} ncomp={ncomp} k={k} prec={prec}", flush=True)
+    mesh = mg.hex_mesh(HEX_M[k], 0.15, config=1, seed_k=k)
+    space = mg.hex_space(mesh, k, ncomp=ncomp, config=1)
+    coef = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if kind in (0, 3) else None
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
+    ref = oracle.OracleOp(space, kind, coef=coef).apply(x)
+    op = mf.Operator(mf.Space.from_meshgen(space), kind, prec, vertex_coef=coef, scatter=scatter)
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_tet_elasticity_action(mf, k, prec):
     print(f"tet elasticity k={k} prec={prec}", flush=True)
@@ -115,13 +134,16 @@ def test_tri_mass_c1_full_size(mf):
     assert _relerr(y, ref) <= 1e-12
 
 
-@pytest.mark.parametrize("case", ["hex", "tet", "tri"])
+@pytest.mark.parametrize("case", ["hex", "hex1", "tet", "tri"])
 def test_apply_range_increments(mf, case):
     """The paper's [start, end) wrapper with INC access: partial sums add up."""
     import torch
     if case == "hex":
         mesh = mg.hex_mesh(5, 0.15)
         space, kind, kw = mg.hex_space(mesh, 3), 1, {}
+    elif case == "hex1":
+        mesh = mg.hex_mesh(5, 0.15)
+        space, kind, kw = mg.hex_space(mesh, 1), 1, {}
     elif case == "tet":
         mesh = mg.tet_mesh(3, 0.2)
         space, kind, kw = mg.tet_space(mesh, 2), 4, {}
