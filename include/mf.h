@@ -97,10 +97,18 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             share no node; a full apply is one launch per colour with plain
  *             read-modify-write stores -- deterministic, bit-reproducible.
  *   ATOMIC    one launch, device-scope floating-point atomics.
- *   AUTO      COLOURED for 3-component hex operators of degree >= 2 on meshes
- *             of at least 4096 cells (where it measured faster), else ATOMIC.
- * Range applies (mf_op_apply_range*) always use ATOMIC. */
-enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2 };
+ *   PATCH     hex Q1 only: cells are grouped into spatially compact patches (at
+ *             most 512 cells, 1024 free nodes); a workgroup gathers its patch's
+ *             nodes into on-chip memory, accumulates the cells there, and writes
+ *             each node once, with a device atomic only where another patch
+ *             shares the node. One launch; not bit-reproducible.
+ *   AUTO      COLOURED for 3-component hex operators of degree >= 2 on meshes of
+ *             at least 4096 cells and for scalar hex operators of degree >= 2 on
+ *             at least 2^18 cells; PATCH for hex Q1 on at least 2^15 cells; tets
+ *             of degree >= 2 COLOURED; else ATOMIC (the measured choices).
+ * Range applies (mf_op_apply_range*) always use ATOMIC. Errors at mf_op_create:
+ * MF_EUNSUPPORTED for PATCH on other cells or degrees. */
+enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2, MF_SCATTER_PATCH = 3 };
 
 typedef struct {
   const double *vertex_coef; /* host, nverts; MASS coefficient c or POISSON kappa; NULL -> 1 */

@@ -14,7 +14,7 @@ import numpy as np
 CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
 MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY = range(5)
 F64, F32 = 0, 1
-SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED = 0, 1, 2
+SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED, SCATTER_PATCH = 0, 1, 2, 3
 _ERR = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EMESH", -5: "ENOTCONV", -6: "EBREAKDOWN",
         -7: "EUNSUPPORTED"}
 

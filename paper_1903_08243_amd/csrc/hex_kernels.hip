@@ -565,58 +565,20 @@ __global__ void __launch_bounds__(512) hex_diag_kernel(const HexArgs<T> A) {
 }
 
 // ---------------------------------------------------------------------------------- Q1
-// Q1 (n = 2) with one cell per lane, for the coloured scatter. A Q1 cell has 8 nodes,
-// so the pencil kernel's LDS stages and barriers cost more than its arithmetic. Here a
-// wavefront owns an aligned block of 64 cells and every stage keeps its 8 values in
-// registers. The map, geometry and coefficient of degree-1 operators are stored a
-// second time in blocks of 64 cells, entry-major inside a block
-// ([cell / 64][entry][cell % 64]), so each per-entry load of a wavefront reads one
-// contiguous segment. Per point the gradient is the collocation derivative of the
-// point values, and the test side is accumulated straight into the 8 point values
-// before the transposed interpolation. The cells of one launch share no node, so the
-// result is added to y with plain loads and stores. (With atomics, the 64 lanes of
-// an atomic instruction would hit 64 different cells' cache lines; the atomic
-// scatter uses the pencil kernel, whose lanes of one cell hit neighbouring nodes.)
+// The Q1 (n = 2) cell action on one lane: geometry G (c1..c7, three components
+// each), the coefficient's monomial coefficients K (used when the kind has one), the
+// 8 nodal values xv (index i + 2 j + 4 l, x fastest) -> the 8 local results yv.
+// Per point the gradient is the collocation derivative of the point values, and the
+// test side is accumulated straight into the 8 point values before the transposed
+// interpolation.
 template <typename T, int KIND>
-__global__ void __launch_bounds__(64) hex_q1_kernel(const HexArgs<T> A) {
+__device__ __forceinline__ void q1_cell(const T (&G)[21], const T (&K)[8], const T (&xv)[8], T (&yv)[8]) {
   constexpr int N = 2;
   using TB = TabT<T, N>;
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
-
-  const int64_t b0 = A.c0 >> 6, nblk = ((A.c1 + 63) >> 6) - b0;
-  const int64_t vb = xcd_batch(blockIdx.x, nblk * A.ncomp);
-  if (vb >= nblk * A.ncomp) return;
-  const int64_t blk = b0 + (int)vb / A.ncomp;  // the grid has fewer than 2^31 items
-  const int comp = (int)vb % A.ncomp;
-  const int lane = threadIdx.x;
-  const int64_t c = blk * 64 + lane;  // the arrays are padded to whole blocks
-  bool ok = c >= A.c0 && c < A.c1;
-  if (ok && A.cell_user) {
-    const int64_t u = A.cell_user[c];
-    ok = u >= A.ulo && u < A.uhi;
-  }
-  const int nc = A.ncomp;
-  int idx[8];
-  T xv[8];
-#pragma unroll
-  for (int i = 0; i < 8; i++) {
-    const int32_t m = A.map[(blk * 8 + i) * 64 + lane];
-    idx[i] = ok ? m : -1;
-  }
-#pragma unroll
-  for (int i = 0; i < 8; i++) xv[i] = idx[i] >= 0 ? A.x[(int64_t)idx[i] * nc + comp] : T(0);
-  T G[21];
-#pragma unroll
-  for (int j = 0; j < 21; j++) G[j] = A.geo[(blk * 24 + j) * 64 + lane];
-  T K[8];
-  if constexpr (COEF) {
-#pragma unroll
-    for (int j = 0; j < 8; j++) K[j] = A.coef ? A.coef[(blk * 8 + j) * 64 + lane] : T(j == 0 ? 1 : 0);
-  }
-
-  // values at the points: u = (B x B x B) x, index a + 2 b + 4 c (x fastest)
+  // values at the points: u = (B x B x B) x
   T u[8], t[8];
 #pragma unroll
   for (int l = 0; l < 4; l++) {  // along x
@@ -641,7 +603,7 @@ __global__ void __launch_bounds__(64) hex_q1_kernel(const HexArgs<T> A) {
 #pragma unroll
   for (int q = 0; q < 8; q++) u[q] = t[q];
 
-  // pointwise; the test side (mass term and transposed derivatives of the fluxes) is
+  // pointwise; the mass term and the transposed derivatives of the fluxes are
   // accumulated in t at the points
 #pragma unroll
   for (int q = 0; q < 8; q++) t[q] = T(0);
@@ -690,9 +652,6 @@ __global__ void __launch_bounds__(64) hex_q1_kernel(const HexArgs<T> A) {
   }
 
   // transposed interpolation back to the nodes: (B^T x B^T x B^T) t
-  T yv[8];
-#pragma unroll
-  for (int i = 0; i < 8; i++) yv[i] = idx[i] >= 0 ? A.y[(int64_t)idx[i] * nc + comp] : T(0);
 #pragma unroll
   for (int p = 0; p < 4; p++) {  // along z
     const T e0 = t[p], e1 = t[p + 4];
@@ -708,14 +667,158 @@ __global__ void __launch_bounds__(64) hex_q1_kernel(const HexArgs<T> A) {
       t[a + 2 + 4 * l] = TB::B(0, 1) * e0 + TB::B(1, 1) * e1;
     }
 #pragma unroll
-  for (int l = 0; l < 4; l++) {  // along x, then scatter
+  for (int l = 0; l < 4; l++) {  // along x
     const T e0 = t[2 * l], e1 = t[2 * l + 1];
-    const T s0 = TB::B(0, 0) * e0 + TB::B(1, 0) * e1;
-    const T s1 = TB::B(0, 1) * e0 + TB::B(1, 1) * e1;
-    if (idx[2 * l] >= 0) A.y[(int64_t)idx[2 * l] * nc + comp] = yv[2 * l] + s0;
-    if (idx[2 * l + 1] >= 0) A.y[(int64_t)idx[2 * l + 1] * nc + comp] = yv[2 * l + 1] + s1;
+    yv[2 * l] = TB::B(0, 0) * e0 + TB::B(1, 0) * e1;
+    yv[2 * l + 1] = TB::B(0, 1) * e0 + TB::B(1, 1) * e1;
   }
 }
+
+// Q1 with one cell per lane, for the coloured scatter. A Q1 cell has 8 nodes, so the
+// pencil kernel's LDS stages and barriers cost more than its arithmetic. Here a
+// wavefront owns an aligned block of 64 cells and every stage keeps its 8 values in
+// registers. The map, geometry and coefficient of degree-1 operators are stored a
+// second time in blocks of 64 cells, entry-major inside a block
+// ([cell / 64][entry][cell % 64]), so each per-entry load of a wavefront reads one
+// contiguous segment. The cells of one launch share no node, so the result is added
+// to y with plain loads and stores. (With atomics, the 64 lanes of an atomic
+// instruction would hit 64 different cells' cache lines; the atomic scatter uses the
+// pencil kernel, whose lanes of one cell hit neighbouring nodes.)
+template <typename T, int KIND>
+__global__ void __launch_bounds__(64) hex_q1_kernel(const HexArgs<T> A) {
+  constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
+  const int64_t b0 = A.c0 >> 6, nblk = ((A.c1 + 63) >> 6) - b0;
+  const int64_t vb = xcd_batch(blockIdx.x, nblk * A.ncomp);
+  if (vb >= nblk * A.ncomp) return;
+  const int64_t blk = b0 + (int)vb / A.ncomp;  // the grid has fewer than 2^31 items
+  const int comp = (int)vb % A.ncomp;
+  const int lane = threadIdx.x;
+  const int64_t c = blk * 64 + lane;  // the arrays are padded to whole blocks
+  bool ok = c >= A.c0 && c < A.c1;
+  if (ok && A.cell_user) {
+    const int64_t u = A.cell_user[c];
+    ok = u >= A.ulo && u < A.uhi;
+  }
+  const int nc = A.ncomp;
+  int idx[8];
+  T xv[8], yv[8], G[21], K[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) {
+    const int32_t m = A.map[(blk * 8 + i) * 64 + lane];
+    idx[i] = ok ? m : -1;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; i++) xv[i] = idx[i] >= 0 ? A.x[(int64_t)idx[i] * nc + comp] : T(0);
+#pragma unroll
+  for (int j = 0; j < 21; j++) G[j] = A.geo[(blk * 24 + j) * 64 + lane];
+#pragma unroll
+  for (int j = 0; j < 8; j++) K[j] = (COEF && A.coef) ? A.coef[(blk * 8 + j) * 64 + lane] : T(j == 0 ? 1 : 0);
+  q1_cell<T, KIND>(G, K, xv, yv);
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+    if (idx[i] >= 0) {
+      T *dst = &A.y[(int64_t)idx[i] * nc + comp];
+      *dst += yv[i];
+    }
+}
+
+// Q1 over patches, for full applies: a workgroup takes one patch of up to
+// kPatchCells cells that are close in space (cells in Morton order of their
+// centroids), gathers the patch's nodes from x into LDS once, lets each lane compute
+// whole cells from LDS and add their results into a per-patch LDS accumulator, and
+// finally writes every patch node once: nodes no other patch touches with a plain
+// read-modify-write, the others (the patch surface) with one device atomic each.
+// Against the coloured launches (every colour reads and writes every node) this
+// moves x and y about once per apply, and against the atomic scatter it issues about
+// one device atomic per cell instead of eight.
+template <typename T, int KIND>
+__device__ __forceinline__ void q1_patch_slot_load(const HexPatchArgs<T> &P, int p, int s, uint16_t (&li)[8],
+                                                   T (&G)[21], T (&K)[8]) {
+  constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
+  // slot s of patch p: entry e at ((p * cap / 64 + s / 64) * E + e) * 64 + s % 64. A
+  // slot number past the capacity reads slot 0 (a branch here costs registers) and is
+  // marked empty.
+  const bool have = s < P.cap;
+  const int ss = have ? s : 0;
+  const int64_t blk = (int64_t)p * (P.cap / 64) + ss / 64;
+  const int lane = ss % 64;
+#pragma unroll
+  for (int i = 0; i < 8; i++) li[i] = have ? P.lmap[(blk * 8 + i) * 64 + lane] : kPatchEmpty;
+#pragma unroll
+  for (int j = 0; j < 21; j++) G[j] = P.geo[(blk * 24 + j) * 64 + lane];
+#pragma unroll
+  for (int j = 0; j < 8; j++) K[j] = (COEF && P.coef) ? P.coef[(blk * 8 + j) * 64 + lane] : T(j == 0 ? 1 : 0);
+}
+
+template <typename T, int KIND>
+__device__ __forceinline__ void q1_patch_slot(const uint16_t (&li)[8], const T (&G)[21], const T (&K)[8], const T *sx,
+                                              T *sy) {
+  bool any = false;  // slots past the patch's cells (and cells with only constrained nodes)
+#pragma unroll
+  for (int i = 0; i < 8; i++) any |= li[i] != kPatchEmpty;
+  if (!any) return;
+  T xv[8], yv[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) xv[i] = li[i] != kPatchEmpty ? sx[li[i]] : T(0);
+  q1_cell<T, KIND>(G, K, xv, yv);
+#pragma unroll
+  for (int i = 0; i < 8; i++)
+    if (li[i] != kPatchEmpty) atomic_add_f(&sy[li[i]], yv[i]);
+}
+
+// Three wavefronts per SIMD where the registers allow it without spilling much (the
+// coefficient kinds need more and keep two).
+template <int KIND> constexpr int q1_patch_waves() { return KIND == K_POIS ? 2 : 3; }
+
+template <typename T, int KIND>
+__global__ void __launch_bounds__(kPatchThreads, q1_patch_waves<KIND>()) hex_q1_patch_kernel(const HexPatchArgs<T> P) {
+  static_assert(kPatchCells == 2 * kPatchThreads, "two cell slots per thread");
+  extern __shared__ __align__(16) unsigned char patch_lds[];
+  T *sx = (T *)patch_lds, *sy = sx + P.max_nodes;
+  const int64_t item = xcd_batch(blockIdx.x, P.npatch * P.ncomp);
+  if (item >= P.npatch * P.ncomp) return;
+  const int p = (int)item / P.ncomp, comp = (int)item % P.ncomp, nc = P.ncomp;
+  const int t = threadIdx.x;
+  // the first slot's map and geometry are requested before the gather of x, so
+  // their latency overlaps it
+  uint16_t li[8];
+  T G[21], K[8];
+  q1_patch_slot_load<T, KIND>(P, p, t, li, G, K);
+  const int n0 = P.node_ptr[p], nn = P.node_ptr[p + 1] - n0;
+  for (int i = t; i < nn; i += kPatchThreads) {
+    const int32_t id = P.nodes[n0 + i];
+    sx[i] = P.x[(int64_t)(id < 0 ? -1 - id : id) * nc + comp];
+    sy[i] = T(0);
+  }
+  __syncthreads();
+  q1_patch_slot<T, KIND>(li, G, K, sx, sy);
+  q1_patch_slot_load<T, KIND>(P, p, t + kPatchThreads, li, G, K);
+  q1_patch_slot<T, KIND>(li, G, K, sx, sy);
+  __syncthreads();
+  for (int i = t; i < nn; i += kPatchThreads) {
+    const int32_t id = P.nodes[n0 + i];
+    if (id >= 0) P.y[(int64_t)id * nc + comp] += sy[i];
+    else atomic_add_f(&P.y[(int64_t)(-1 - id) * nc + comp], sy[i]);
+  }
+}
+
+template <typename T>
+int launch_hex_q1_patches(int kind, const HexPatchArgs<T> &a, hipStream_t s) {
+  if (a.npatch <= 0) return MF_OK;
+  const dim3 grid((unsigned)xcd_grid((int64_t)a.npatch * a.ncomp)), block(kPatchThreads);
+  const size_t lds = 2 * (size_t)a.max_nodes * sizeof(T);
+  switch (kind) {
+    case K_MASS: hex_q1_patch_kernel<T, K_MASS><<<grid, block, lds, s>>>(a); break;
+    case K_HELM: hex_q1_patch_kernel<T, K_HELM><<<grid, block, lds, s>>>(a); break;
+    case K_LAP: hex_q1_patch_kernel<T, K_LAP><<<grid, block, lds, s>>>(a); break;
+    case K_POIS: hex_q1_patch_kernel<T, K_POIS><<<grid, block, lds, s>>>(a); break;
+    default: return fail(MF_EUNSUPPORTED, "hex patch kernel: operator kind");
+  }
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_hex_q1_patches<double>(int, const HexPatchArgs<double> &, hipStream_t);
+template int launch_hex_q1_patches<float>(int, const HexPatchArgs<float> &, hipStream_t);
 
 template <typename T>
 static int launch_q1(int kind, const HexArgs<T> &a, hipStream_t s) {

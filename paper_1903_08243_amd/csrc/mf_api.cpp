@@ -278,7 +278,121 @@ void mf_space_destroy(mf_space *s) { delete s; }
 // ------------------------------------------------------------------ operator setup
 namespace mf {
 
-template <typename T> static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+// 3 x 10-bit Morton code (bit i of x, y, z at bits 3i, 3i + 1, 3i + 2)
+static uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint32_t v) {
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
+// Patches of the degree-1 patch kernel: cells in Morton order of their centroids,
+// cut greedily into runs of at most `cap` cells (<= kPatchCells) and kPatchNodes
+// distinct free nodes. cap shrinks on small meshes so that there are about 1024
+// patches (several per compute unit). m: the flagged map ([cell][8], negative =
+// constrained); geo, cf: the [cell][entry] geometry and coefficient.
+template <typename T>
+static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<int32_t> &m, const std::vector<T> &geo,
+                             const std::vector<T> &cf, hipStream_t s) {
+  const int64_t nc = sp->ncells;
+  std::vector<double> cen((size_t)nc * 3);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t K = 0; K < nc; K++)
+    for (int a = 0; a < 3; a++) {
+      double c = 0.0;
+      for (int v = 0; v < 8; v++) c += sp->coords[(int64_t)sp->cell2vert_int[K * 8 + v] * 3 + a];
+      c *= 0.125;
+      cen[K * 3 + a] = c;
+      lo[a] = std::min(lo[a], c);
+      hi[a] = std::max(hi[a], c);
+    }
+  std::vector<std::pair<uint32_t, int64_t>> key((size_t)nc);
+  for (int64_t K = 0; K < nc; K++) {
+    uint32_t q[3];
+    for (int a = 0; a < 3; a++) {
+      const double w = hi[a] - lo[a];
+      const double f = w > 0.0 ? (cen[K * 3 + a] - lo[a]) / w * 1024.0 : 0.0;
+      q[a] = (uint32_t)std::min(1023.0, std::max(0.0, f));
+    }
+    key[K] = {morton3(q[0], q[1], q[2]), K};
+  }
+  std::sort(key.begin(), key.end());
+
+  const int cap = (int)std::min<int64_t>(kPatchCells, std::max<int64_t>(64, (nc / 1024) / 64 * 64));
+  const int SB = cap / 64;  // 64-slot blocks per patch
+  std::vector<int32_t> stamp((size_t)sp->nnodes, -1), loc((size_t)sp->nnodes, 0);
+  std::vector<int32_t> nptr{0}, nodes;
+  std::vector<uint16_t> lmap;
+  std::vector<T> pgeo, pcoef;
+  int pid = -1, ncell = 0, nnode = 0;
+  auto open_patch = [&]() {
+    pid++;
+    ncell = nnode = 0;
+    lmap.resize((size_t)(pid + 1) * cap * 8, kPatchEmpty);
+    pgeo.resize((size_t)(pid + 1) * cap * 24, T(0));
+    for (int sl = 0; sl < cap; sl++)  // empty slots: the unit-cube map
+      for (int j : {0, 4, 8}) pgeo[(((size_t)pid * SB + sl / 64) * 24 + j) * 64 + sl % 64] = T(1);
+    if (op->has_coef) pcoef.resize((size_t)(pid + 1) * cap * 8, T(0));
+  };
+  for (int64_t r = 0; r < nc; r++) {
+    const int64_t K = key[r].second;
+    int fresh = 0;
+    for (int i = 0; i < 8; i++) {
+      const int32_t id = m[K * 8 + i];
+      if (id >= 0 && stamp[id] != pid) fresh++;
+    }
+    if (pid < 0 || ncell == cap || nnode + fresh > kPatchNodes) {
+      if (pid >= 0) nptr.push_back((int32_t)nodes.size());
+      open_patch();
+    }
+    const int sl = ncell++;
+    const size_t b = (size_t)pid * SB + sl / 64, l = sl % 64;
+    for (int i = 0; i < 8; i++) {
+      const int32_t id = m[K * 8 + i];
+      uint16_t li = kPatchEmpty;
+      if (id >= 0) {
+        if (stamp[id] != pid) {
+          stamp[id] = pid;
+          loc[id] = nnode++;
+          nodes.push_back(id);
+        }
+        li = (uint16_t)loc[id];
+      }
+      lmap[(b * 8 + i) * 64 + l] = li;
+    }
+    for (int j = 0; j < 24; j++) pgeo[(b * 24 + j) * 64 + l] = geo[K * 24 + j];
+    if (op->has_coef)
+      for (int j = 0; j < 8; j++) pcoef[(b * 8 + j) * 64 + l] = cf[K * 8 + j];
+  }
+  if (pid >= 0) nptr.push_back((int32_t)nodes.size());
+  const int np = pid + 1;
+  // nodes that more than one patch touches are written with atomics (stored as -1-id)
+  std::vector<uint8_t> cnt((size_t)sp->nnodes, 0);
+  for (int32_t id : nodes) cnt[id] = (uint8_t)std::min(2, cnt[id] + 1);
+  int max_nodes = 0;
+  for (int p = 0; p < np; p++) max_nodes = std::max(max_nodes, nptr[p + 1] - nptr[p]);
+  for (int32_t &id : nodes)
+    if (cnt[id] > 1) id = -1 - id;
+  op->npatch = np;
+  op->pt_max_nodes = max_nodes;
+  op->pt_cap = cap;
+  int rc = upload(op->pt_nptr, nptr.data(), nptr.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->pt_nodes, nodes.data(), nodes.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->pt_lmap, lmap.data(), lmap.size() * sizeof(uint16_t), s);
+  if (!rc) rc = upload(op->pt_geo, pgeo.data(), pgeo.size() * sizeof(T), s);
+  if (!rc && op->has_coef) rc = upload(op->pt_coef, pcoef.data(), pcoef.size() * sizeof(T), s);
+  if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  return rc;
+}
+
+template <typename T>
+static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
+                     hipStream_t s) {
   const int k = sp->degree, N = k + 1;
   if (op->nq1d != N) return fail(MF_EUNSUPPORTED, "hex operators support nq1d = k+1 only");
   const int64_t nc = sp->ncells;
@@ -323,6 +437,7 @@ template <typename T> static int setup_hex(mf_op *op, const mf_space *sp, const 
     if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     if (rc) return rc;
   }
+  if (op->patched) return setup_hex_patches<T>(op, sp, m, geo, cf, s);
   return MF_OK;
 }
 
@@ -450,7 +565,12 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
     if (rc) return rc;
   }
   if (c0 == 0 && c1 == op->ncells) {
-    if (op->coloured) {
+    if (op->patched) {
+      HexPatchArgs<T> a{op->pt_nptr.as<int32_t>(), op->pt_nodes.as<int32_t>(), op->pt_lmap.as<uint16_t>(),
+                        op->pt_geo.as<T>(), op->has_coef ? op->pt_coef.as<T>() : nullptr, x, y, op->npatch,
+                        op->pt_max_nodes, op->ncomp, op->pt_cap};
+      rc = launch_hex_q1_patches<T>(op->kind, a, s);
+    } else if (op->coloured) {
       // one launch per colour: cells of a colour share no node, so no atomics
       for (size_t c = 0; c + 1 < op->colour_ptr.size() && !rc; c++)
         rc = cell_launch<T>(op, op->colour_ptr[c], op->colour_ptr[c + 1], x, y, false, nullptr, 0, 0, s);
@@ -525,6 +645,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     ok = kind == MF_OP_MASS && sp->ncomp == 1;
   if (!ok) return fail(MF_EUNSUPPORTED, "mf_op_create: operator / cell / ncomp combination not built");
   if (kind == MF_OP_POISSON && !pr->vertex_coef) return fail(MF_EINVAL, "POISSON needs vertex_coef (kappa)");
+  if (pr->scatter < MF_SCATTER_AUTO || pr->scatter > MF_SCATTER_PATCH)
+    return fail(MF_EINVAL, "mf_op_create: unknown scatter mode");
   std::unique_ptr<mf_op> op(new (std::nothrow) mf_op);
   if (!op) return fail(MF_ENOMEM, "mf_op_create: host allocation");
   op->cell_type = ct;
@@ -584,6 +706,14 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
+  if (pr->scatter == MF_SCATTER_PATCH) {
+    if (ct != MF_CELL_HEX || op->degree != 1)
+      return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for hex Q1 only");
+    op->patched = true;
+  } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15)) {
+    op->patched = true;
+  }
+  if (op->patched) op->coloured = false;
   if (!op->identity) {
     rc = upload(op->perm, sp->user_of_int.data(), sp->user_of_int.size() * sizeof(int32_t), s);
     if (!rc) rc = upload(op->iperm, sp->int_of_user.data(), sp->int_of_user.size() * sizeof(int32_t), s);
@@ -605,7 +735,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     if (rc) return rc;
   }
   if (ct == MF_CELL_HEX)
-    rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, s) : setup_hex<float>(op.get(), sp, pr, s);
+    rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, s) : setup_hex<float>(op.get(), sp, pr, m, s);
   else if (ct == MF_CELL_TET)
     rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, s) : setup_tet<float>(op.get(), sp, s);
   else

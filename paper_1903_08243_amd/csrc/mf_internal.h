@@ -85,6 +85,26 @@ template <typename T> struct HexArgs {
   int64_t ulo, uhi;
 };
 
+// Q1 patch decomposition (full applies of degree-1 hex operators): patches of up to
+// cap <= kPatchCells cells (a multiple of 64, the same for all patches of an
+// operator) with at most kPatchNodes distinct free nodes. Per-slot arrays are
+// block-interleaved with cap slots per patch: entry e of slot s of patch p at
+// ((p * cap / 64 + s / 64) * E + e) * 64 + s % 64; empty slots and constrained
+// nodes have local index kPatchEmpty.
+constexpr int kPatchCells = 512, kPatchNodes = 1024, kPatchThreads = 256;
+constexpr uint16_t kPatchEmpty = 0xFFFF;
+template <typename T> struct HexPatchArgs {
+  const int32_t *node_ptr;  // npatch + 1 offsets into nodes
+  const int32_t *nodes;     // internal node ids; -1-id for nodes other patches also touch
+  const uint16_t *lmap;     // per slot, 8 local node indices
+  const T *geo;             // per slot, 24 geometry entries (c1..c7 x3, pad)
+  const T *coef;            // per slot, 8 coefficient entries, or null
+  const T *x;
+  T *y;
+  int npatch, max_nodes, ncomp, cap;
+};
+template <typename T> int launch_hex_q1_patches(int kind, const HexPatchArgs<T> &a, hipStream_t s);
+
 // Kernel launchers (hex_kernels.hip)
 // atomic: scatter with device-scope atomics (any cell set); otherwise plain
 // read-modify-write, valid only when no two cells of [c0, c1) share a node.
@@ -182,6 +202,9 @@ struct mf_op {
   mf::DeviceBuffer map, geo, coef, tab, bc_dofs;  // map and bc_dofs in internal numbering
   mf::DeviceBuffer q1map, q1geo, q1coef;          // degree-1 hex: map, geometry, coefficient in
                                                   // blocks of 64 cells, [cell/64][entry][cell%64]
+  mf::DeviceBuffer pt_nptr, pt_nodes, pt_lmap, pt_geo, pt_coef;  // degree-1 hex patches
+  int npatch = 0, pt_max_nodes = 0, pt_cap = 0;
+  bool patched = false;  // full applies use the patch kernel
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
   mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
   mf::DeviceBuffer to1, to2, from1, from2, wt;    // two-stage permutations (positions) and their buffer

@@ -81,6 +81,44 @@ def test_hex_scatter_modes(mf, k, scatter, prec, kind, ncomp):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("m", [6, 20])
+@pytest.mark.parametrize("kind,ncomp", [(1, 1), (2, 3), (3, 1), (0, 1)],
+                         ids=["helmholtz", "laplacian3", "poisson", "mass"])
+def test_hex_q1_patch_scatter(mf, m, prec, kind, ncomp):
+    """Q1 through the patch kernel (216 cells: four patches, the last ragged; 8000
+    cells: 125 patches) against the oracle, with and without constrained nodes."""
+    import torch
+    print(f"hex patch m={m} kind={kind} ncomp={ncomp} prec={prec}", flush=True)
+    mesh = mg.hex_mesh(m, 0.15, config=1, seed_k=1)
+    space = mg.hex_space(mesh, 1, ncomp=ncomp, config=1)
+    coef = np.exp(np.random.default_rng(1).normal(size=mesh.nverts)) if kind in (0, 3) else None
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, 1)
+    orc = oracle.OracleOp(space, kind, coef=coef)
+    sp = mf.Space.from_meshgen(space)
+    op = mf.Operator(sp, kind, prec, vertex_coef=coef, scatter=mf.SCATTER_PATCH)
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    assert _relerr(y, orc.apply(x)) <= TOL[prec], _relerr(y, orc.apply(x))
+    # constrained boundary nodes: identity rows, zero columns
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    xm = x.reshape(-1, ncomp).copy()
+    xm[bnd] = 0.0
+    ref = orc.apply(xm.ravel()).reshape(-1, ncomp)
+    ref[bnd] = x.reshape(-1, ncomp)[bnd]
+    opd = mf.Operator(sp, kind, prec, vertex_coef=coef, dirichlet=mask, scatter=mf.SCATTER_PATCH)
+    yd = opd.apply(torch.tensor(x, device="cuda", dtype=opd.torch_dtype)).double().cpu().numpy()
+    assert _relerr(yd, ref.ravel()) <= TOL[prec], _relerr(yd, ref.ravel())
+
+
+def test_hex_patch_scatter_other_degrees_rejected(mf):
+    mesh = mg.hex_mesh(3, 0.15)
+    sp = mf.Space.from_meshgen(mg.hex_space(mesh, 2))
+    with pytest.raises(mf.MFError, match="patch"):
+        mf.Operator(sp, 1, 0, scatter=mf.SCATTER_PATCH)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_tet_elasticity_action(mf, k, prec):
     print(f"tet elasticity k={k} prec={prec}", flush=True)
