@@ -108,13 +108,13 @@ def measured_traffic():
         return None
 
 
-def cpu_baseline(mg, cases, budget_s=20.0):
+def cpu_baseline(mg, cases, budget_s=30.0):
     """The oracle (dense, FP64, all host cores) on a bounded sample: a contiguous
     slice of cells of every headline operator, scaled to GDoF/s by the slice fraction."""
     import oracle
     nthreads = oracle.default_threads()
     tot_dofs, tot_t = 0.0, 0.0
-    frac = 1.0 / 8.0
+    frac = 1.0 / 2.0
     samples = []
     for ent in cases:
         sp = ent["space"]
@@ -131,7 +131,7 @@ def cpu_baseline(mg, cases, budget_s=20.0):
         if tot_t > budget_s:
             break
     return {"value": tot_dofs / tot_t / 1e9, "unit": "GDoF/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"cells [0, ncells/8) of each of {len(samples)} headline operators "
+            "sample": f"cells [0, ncells/{round(1 / frac)}) of each of {len(samples)} headline operators "
                       f"({samples[0]}..{samples[-1]}), dofs scaled by the cell fraction; "
                       f"{tot_t:.1f} s of CPU work"}
 

@@ -170,7 +170,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 
   // One batch of EPB cells per call: map, geometry and the first component's
   // gathers are issued together, then each component is processed in turn.
-  int idx_cur[N];
+  int idx_cur[N], gidx[N];  // scatter (internal node) and gather positions
   {
     const int64_t c = A.c0 + b * EPB + le;
     bool ok = c < A.c1;
@@ -178,9 +178,11 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       const int64_t u = A.cell_user[c];
       ok = u >= A.ulo && u < A.uhi;
     }
-    const int32_t *cm = A.map + (ok ? c : A.c0) * N3;
+    const int64_t off = (ok ? c : A.c0) * N3 + pa + N * pb;
 #pragma unroll
-    for (int l = 0; l < N; l++) idx_cur[l] = ok ? cm[pa + N * pb + NN * l] : -1;
+    for (int l = 0; l < N; l++) idx_cur[l] = ok ? A.map[off + NN * l] : -1;
+#pragma unroll
+    for (int l = 0; l < N; l++) gidx[l] = A.gmap ? (ok ? A.gmap[off + NN * l] : -1) : idx_cur[l];
   }
   for (int i = t; i < EPB * 32; i += 64 * WPB) {
     const int e = i >> 5, j = i & 31;
@@ -229,7 +231,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       // them live across iterations (which doubled the register count).
       T yv[N], r_cur[N];
 #pragma unroll
-      for (int l = 0; l < N; l++) r_cur[l] = idx_cur[l] >= 0 ? A.x[(int64_t)idx_cur[l] * nc + comp] : T(0);
+      for (int l = 0; l < N; l++) r_cur[l] = gidx[l] >= 0 ? A.x[(int64_t)gidx[l] * nc + comp] : T(0);
       if constexpr (!ATOMIC) {
         // no other cell of this launch touches these nodes: read y now, write it at the end
 #pragma unroll
@@ -787,7 +789,8 @@ __global__ void __launch_bounds__(kPatchThreads, q1_patch_waves<KIND>()) hex_q1_
   const int n0 = P.node_ptr[p], nn = P.node_ptr[p + 1] - n0;
   for (int i = t; i < nn; i += kPatchThreads) {
     const int32_t id = P.nodes[n0 + i];
-    sx[i] = P.x[(int64_t)(id < 0 ? -1 - id : id) * nc + comp];
+    const int64_t g = P.gnodes ? P.gnodes[n0 + i] : (id < 0 ? -1 - id : id);
+    sx[i] = P.x[g * nc + comp];
     sy[i] = T(0);
   }
   __syncthreads();

@@ -297,8 +297,9 @@ static uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 // patches (several per compute unit). m: the flagged map ([cell][8], negative =
 // constrained); geo, cf: the [cell][entry] geometry and coefficient.
 template <typename T>
-static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<int32_t> &m, const std::vector<T> &geo,
-                             const std::vector<T> &cf, hipStream_t s) {
+static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<int32_t> &m,
+                             const std::vector<int32_t> &to_pos2, const std::vector<T> &geo, const std::vector<T> &cf,
+                             hipStream_t s) {
   const int64_t nc = sp->ncells;
   std::vector<double> cen((size_t)nc * 3);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
@@ -386,13 +387,19 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
   if (!rc) rc = upload(op->pt_lmap, lmap.data(), lmap.size() * sizeof(uint16_t), s);
   if (!rc) rc = upload(op->pt_geo, pgeo.data(), pgeo.size() * sizeof(T), s);
   if (!rc && op->has_coef) rc = upload(op->pt_coef, pcoef.data(), pcoef.size() * sizeof(T), s);
+  std::vector<int32_t> gn;
+  if (!rc && !to_pos2.empty()) {  // gather positions after the first permutation stage
+    gn.resize(nodes.size());
+    for (size_t i = 0; i < nodes.size(); i++) gn[i] = to_pos2[nodes[i] < 0 ? -1 - nodes[i] : nodes[i]];
+    rc = upload(op->pt_gnodes, gn.data(), gn.size() * sizeof(int32_t), s);
+  }
   if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
   return rc;
 }
 
 template <typename T>
 static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
-                     hipStream_t s) {
+                     const std::vector<int32_t> &to_pos2, hipStream_t s) {
   const int k = sp->degree, N = k + 1;
   if (op->nq1d != N) return fail(MF_EUNSUPPORTED, "hex operators support nq1d = k+1 only");
   const int64_t nc = sp->ncells;
@@ -437,7 +444,7 @@ static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     if (rc) return rc;
   }
-  if (op->patched) return setup_hex_patches<T>(op, sp, m, geo, cf, s);
+  if (op->patched) return setup_hex_patches<T>(op, sp, m, to_pos2, geo, cf, s);
   return MF_OK;
 }
 
@@ -537,15 +544,18 @@ static void count_work(mf_op *op) {
 // One launch of the cell kernel over internal cells [c0, c1). atomic: scatter with
 // atomics (optionally only cells whose user index is in [ulo, uhi)); otherwise
 // plain read-modify-write, which requires [c0, c1) to lie inside one colour.
+// fused: x is the first-stage output of the user -> internal permutation, gathered
+// through gmap (hex pencil kernel only).
 template <typename T>
 static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool atomic, const int32_t *filt,
-                       int64_t ulo, int64_t uhi, hipStream_t s) {
+                       int64_t ulo, int64_t uhi, hipStream_t s, bool fused = false) {
   if (op->cell_type == MF_CELL_HEX) {
     // the coloured degree-1 kernel reads the block-interleaved copies
     const bool q1 = op->degree == 1 && !atomic;
+    if (fused && q1) return fail(MF_EINVAL, "internal: fused gather with the coloured Q1 kernel");
     HexArgs<T> a{(q1 ? op->q1map : op->map).as<int32_t>(), (q1 ? op->q1geo : op->geo).as<T>(),
                  op->has_coef ? (q1 ? op->q1coef : op->coef).as<T>() : nullptr, x, y, c0, c1, op->ncomp, filt, ulo,
-                 uhi};
+                 uhi, fused ? op->gmap.as<int32_t>() : nullptr};
     return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
@@ -558,7 +568,7 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
 
 // y (+)= A_[c0,c1) x in internal numbering; [c0, c1) is a range of user cells.
 template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool acc,
-                                            bool bc, hipStream_t s) {
+                                            bool bc, hipStream_t s, bool fused = false) {
   int rc = MF_OK;
   if (!acc) {
     rc = launch_fill<T>(y, T(0), op->ndofs, s);
@@ -566,19 +576,20 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
   }
   if (c0 == 0 && c1 == op->ncells) {
     if (op->patched) {
-      HexPatchArgs<T> a{op->pt_nptr.as<int32_t>(), op->pt_nodes.as<int32_t>(), op->pt_lmap.as<uint16_t>(),
+      HexPatchArgs<T> a{op->pt_nptr.as<int32_t>(), op->pt_nodes.as<int32_t>(),
+                        fused ? op->pt_gnodes.as<int32_t>() : nullptr, op->pt_lmap.as<uint16_t>(),
                         op->pt_geo.as<T>(), op->has_coef ? op->pt_coef.as<T>() : nullptr, x, y, op->npatch,
                         op->pt_max_nodes, op->ncomp, op->pt_cap};
       rc = launch_hex_q1_patches<T>(op->kind, a, s);
     } else if (op->coloured) {
       // one launch per colour: cells of a colour share no node, so no atomics
       for (size_t c = 0; c + 1 < op->colour_ptr.size() && !rc; c++)
-        rc = cell_launch<T>(op, op->colour_ptr[c], op->colour_ptr[c + 1], x, y, false, nullptr, 0, 0, s);
+        rc = cell_launch<T>(op, op->colour_ptr[c], op->colour_ptr[c + 1], x, y, false, nullptr, 0, 0, s, fused);
     } else {
-      rc = cell_launch<T>(op, 0, op->ncells, x, y, true, nullptr, 0, 0, s);
+      rc = cell_launch<T>(op, 0, op->ncells, x, y, true, nullptr, 0, 0, s, fused);
     }
   } else if (c1 > c0) {
-    rc = cell_launch<T>(op, 0, op->ncells, x, y, true, op->cell_user.as<int32_t>(), c0, c1, s);
+    rc = cell_launch<T>(op, 0, op->ncells, x, y, true, op->cell_user.as<int32_t>(), c0, c1, s, fused);
   }
   if (rc) return rc;
   if (bc && op->n_bc_dofs) rc = launch_copy_constrained<T>(op->bc_dofs.as<int32_t>(), op->n_bc_dofs, x, y, s);
@@ -714,6 +725,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     op->patched = true;
   }
   if (op->patched) op->coloured = false;
+  std::vector<int32_t> to_pos2, gm;  // second-stage positions of the user -> internal permutation
   if (!op->identity) {
     rc = upload(op->perm, sp->user_of_int.data(), sp->user_of_int.size() * sizeof(int32_t), s);
     if (!rc) rc = upload(op->iperm, sp->int_of_user.data(), sp->int_of_user.size() * sizeof(int32_t), s);
@@ -723,19 +735,27 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     if (!rc) rc = op->wt.alloc(vb);
     if (!rc) {
       // user -> internal: x_int[i] = x_user[user_of_int[i]]; back: y_user[u] = y_int[int_of_user[u]]
-      std::vector<int32_t> p1, p2, q1, q2;
-      permute2_positions(sp->user_of_int.data(), sp->nnodes, p1, p2);
+      std::vector<int32_t> p1, q1, q2;
+      permute2_positions(sp->user_of_int.data(), sp->nnodes, p1, to_pos2);
       permute2_positions(sp->int_of_user.data(), sp->nnodes, q1, q2);
       rc = upload(op->to1, p1.data(), p1.size() * 4, s);
-      if (!rc) rc = upload(op->to2, p2.data(), p2.size() * 4, s);
+      if (!rc) rc = upload(op->to2, to_pos2.data(), to_pos2.size() * 4, s);
       if (!rc) rc = upload(op->from1, q1.data(), q1.size() * 4, s);
       if (!rc) rc = upload(op->from2, q2.data(), q2.size() * 4, s);
+      if (!rc && ct == MF_CELL_HEX) {
+        // x_int[i] sits at to_pos2[i] after the first stage: the map composed with it
+        gm.resize(m.size());
+        for (size_t i = 0; i < m.size(); i++) gm[i] = m[i] >= 0 ? to_pos2[m[i]] : m[i];
+        rc = upload(op->gmap, gm.data(), gm.size() * 4, s);
+        op->fused_gather = true;
+      }
       if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     }
     if (rc) return rc;
   }
   if (ct == MF_CELL_HEX)
-    rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, s) : setup_hex<float>(op.get(), sp, pr, m, s);
+    rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, to_pos2, s)
+                             : setup_hex<float>(op.get(), sp, pr, m, to_pos2, s);
   else if (ct == MF_CELL_TET)
     rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, s) : setup_tet<float>(op.get(), sp, s);
   else
@@ -763,9 +783,18 @@ template <typename T>
 static int user_apply(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool acc, bool bc, hipStream_t s) {
   if (op->identity) return op_apply_t<T>(op, c0, c1, x, y, acc, bc, s);
   T *wx = op->wx.as<T>(), *wy = op->wy.as<T>(), *wt = op->wt.as<T>();
-  int rc = launch_permute2<T>(op->to1.as<int32_t>(), op->to2.as<int32_t>(), op->nnodes, op->ncomp, x, wt, wx, false,
-                              s);
-  if (!rc) rc = op_apply_t<T>(op, c0, c1, wx, wy, false, bc, s);
+  int rc = MF_OK;
+  // The kernels can gather x straight from the first stage of the permutation (the
+  // composed map gmap), skipping its second stage, when no constrained rows need x in
+  // internal numbering and the kernel is one that takes gmap.
+  const bool fused = op->fused_gather && !(bc && op->n_bc_dofs) && !(op->degree == 1 && op->coloured);
+  if (fused) {
+    rc = launch_permute_stage1<T>(op->to1.as<int32_t>(), op->nnodes, op->ncomp, x, wt, s);
+    if (!rc) rc = op_apply_t<T>(op, c0, c1, wt, wy, false, bc, s, true);
+  } else {
+    rc = launch_permute2<T>(op->to1.as<int32_t>(), op->to2.as<int32_t>(), op->nnodes, op->ncomp, x, wt, wx, false, s);
+    if (!rc) rc = op_apply_t<T>(op, c0, c1, wx, wy, false, bc, s);
+  }
   if (!rc)
     rc = launch_permute2<T>(op->from1.as<int32_t>(), op->from2.as<int32_t>(), op->nnodes, op->ncomp, wy, wt, y, acc,
                             s);

@@ -83,6 +83,9 @@ template <typename T> struct HexArgs {
   int ncomp;
   const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
   int64_t ulo, uhi;
+  // if set (pencil kernel only): x is gathered at these positions instead of at map
+  // (same layout as map; negative = constrained), e.g. a half-permuted input
+  const int32_t *gmap;
 };
 
 // Q1 patch decomposition (full applies of degree-1 hex operators): patches of up to
@@ -96,6 +99,7 @@ constexpr uint16_t kPatchEmpty = 0xFFFF;
 template <typename T> struct HexPatchArgs {
   const int32_t *node_ptr;  // npatch + 1 offsets into nodes
   const int32_t *nodes;     // internal node ids; -1-id for nodes other patches also touch
+  const int32_t *gnodes;    // if set: gather positions of the nodes in x (else their ids)
   const uint16_t *lmap;     // per slot, 8 local node indices
   const T *geo;             // per slot, 24 geometry entries (c1..c7 x3, pad)
   const T *coef;            // per slot, 8 coefficient entries, or null
@@ -179,6 +183,9 @@ template <typename T>
 int launch_permute2(const int32_t *pos1, const int32_t *pos2, int64_t n, int nc, const T *in, T *tmp, T *out,
                     bool acc, hipStream_t s);
 void permute2_positions(const int32_t *src, int64_t n, std::vector<int32_t> &pos1, std::vector<int32_t> &pos2);
+// the first stage alone: tmp[pos1[j]] = in[j]
+template <typename T>
+int launch_permute_stage1(const int32_t *pos1, int64_t n, int nc, const T *in, T *tmp, hipStream_t s);
 // the same with the inverse permutation iou (user node -> internal node), as a gather
 template <typename T>
 int launch_from_internal_gather(const int32_t *iou, int64_t nnodes, int nc, const T *yi, T *yu, bool acc,
@@ -203,6 +210,10 @@ struct mf_op {
   mf::DeviceBuffer q1map, q1geo, q1coef;          // degree-1 hex: map, geometry, coefficient in
                                                   // blocks of 64 cells, [cell/64][entry][cell%64]
   mf::DeviceBuffer pt_nptr, pt_nodes, pt_lmap, pt_geo, pt_coef;  // degree-1 hex patches
+  // hex, user numbering: x is gathered straight from the first stage of the two-stage
+  // permutation (positions to2 of the map's nodes), which saves the second stage
+  mf::DeviceBuffer gmap, pt_gnodes;
+  bool fused_gather = false;
   int npatch = 0, pt_max_nodes = 0, pt_cap = 0;
   bool patched = false;  // full applies use the patch kernel
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)

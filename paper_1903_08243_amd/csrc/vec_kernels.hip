@@ -171,6 +171,22 @@ int launch_permute2(const int32_t *pos1, const int32_t *pos2, int64_t n, int nc,
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
+template <typename T>
+int launch_permute_stage1(const int32_t *pos1, int64_t n, int nc, const T *in, T *tmp, hipStream_t s) {
+  if (n <= 0) return MF_OK;
+  const int64_t nblk = (n * nc + 255) / 256;
+  const unsigned g = (unsigned)(((nblk + 7) / 8) * 8);
+  switch (nc) {
+    case 1: perm_stage1_kernel<T, 1><<<g, 256, 0, s>>>(pos1, n, in, tmp, nblk); break;
+    case 2: perm_stage1_kernel<T, 2><<<g, 256, 0, s>>>(pos1, n, in, tmp, nblk); break;
+    case 3: perm_stage1_kernel<T, 3><<<g, 256, 0, s>>>(pos1, n, in, tmp, nblk); break;
+    default: return fail(MF_EINVAL, "launch_permute_stage1: ncomp must be 1..3");
+  }
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_permute_stage1<double>(const int32_t *, int64_t, int, const double *, double *, hipStream_t);
+template int launch_permute_stage1<float>(const int32_t *, int64_t, int, const float *, float *, hipStream_t);
 template int launch_permute2<double>(const int32_t *, const int32_t *, int64_t, int, const double *, double *,
                                      double *, bool, hipStream_t);
 template int launch_permute2<float>(const int32_t *, const int32_t *, int64_t, int, const float *, float *, float *,
