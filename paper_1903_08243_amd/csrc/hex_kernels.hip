@@ -140,69 +140,20 @@ template <int N, bool GRAD, int WPB = 1> constexpr int hex_lds_size() {
   return hex_epb<N, WPB>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32);
 }
 
-// Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
-// on the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
-template <typename T, int N, int KIND, bool ATOMIC, int WPB = 1>
-__device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, const int comp, T *lds) {
+#define IX(x, y, z) ((z) * SZ + (y) * SY + (x))
+// The sum-factorised action of one cell on the calling thread's pencil (pa, pb, *):
+// on entry r holds the cell's nodal values on that z-pencil, on exit the local
+// result on the same pencil. Gc: the cell's 32 geometry and coefficient entries in
+// LDS; u0, u1, u2: its three padded n^3 LDS buffers (u0 alone without gradients).
+// Contains workgroup barriers, so every thread of the workgroup calls it.
+template <typename T, int N, int KIND, int WPB>
+__device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0, T *u1, T *u2, const int pa,
+                                                  const int pb, const bool STORE) {
   using TB = TabT<T, N>;
-  constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N, WPB>();
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
-  constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ, SE = HexLds<N>::SE;
-  T *s0 = lds;
-  T *s1 = lds + (GRAD ? EPB * SE : 0);
-  T *s2 = lds + (GRAD ? 2 * EPB * SE : 0);
-  T *sg = lds + (GRAD ? 3 : 1) * EPB * SE;
-#define IX(x, y, z) ((z) * SZ + (y) * SY + (x))
-
-  const int t = threadIdx.x;
-  const bool mirror = t >= EPB * NN;
-  // A mirror lane duplicates the pencil of lane t - EPB n^2. In a one-wavefront
-  // workgroup it runs in lockstep with that lane, so its identical LDS stores are
-  // harmless; across wavefronts its in-place read-then-write could interleave with
-  // the original's, so there it stores nothing (and never scatters).
-  const bool STORE = WPB == 1 || !mirror;
-  const int tt = mirror ? t - EPB * NN : t;
-  const int le = tt / NN, p = tt - le * NN;
-  const int pa = p % N, pb = p / N;
-  const int nc = A.ncomp;
-
-  // One batch of EPB cells per call: map, geometry and the first component's
-  // gathers are issued together, then each component is processed in turn.
-  int idx_cur[N], gidx[N];  // scatter (internal node) and gather positions
-  {
-    const int64_t c = A.c0 + b * EPB + le;
-    bool ok = c < A.c1;
-    if (ok && A.cell_user) {
-      const int64_t u = A.cell_user[c];
-      ok = u >= A.ulo && u < A.uhi;
-    }
-    const int64_t off = (ok ? c : A.c0) * N3 + pa + N * pb;
-#pragma unroll
-    for (int l = 0; l < N; l++) idx_cur[l] = ok ? A.map[off + NN * l] : -1;
-#pragma unroll
-    for (int l = 0; l < N; l++) gidx[l] = A.gmap ? (ok ? A.gmap[off + NN * l] : -1) : idx_cur[l];
-  }
-  for (int i = t; i < EPB * 32; i += 64 * WPB) {
-    const int e = i >> 5, j = i & 31;
-    const int64_t c = A.c0 + b * EPB + e;
-    T v = T(0);
-    if (c < A.c1) {
-      if (j < 24) v = A.geo[c * 24 + j];
-      else if (COEF && A.coef) v = A.coef[c * 8 + (j - 24)];
-      else if (j == 24) v = T(1);  // coefficient 1 when absent
-    } else if (j == 0 || j == 4 || j == 8) {
-      v = T(1);  // cells past the end: unit-cube geometry keeps the arithmetic finite
-    }
-    sg[i] = v;
-  }
-  __syncthreads();
-
-  T *u0 = s0 + le * SE;
-  T *u1 = s1 + (GRAD ? le * SE : 0);
-  T *u2 = s2 + (GRAD ? le * SE : 0);
-  const T *Gc = sg + le * 32;
+  constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ;
   const T x1 = TB::g(pa), x2 = TB::g(pb);
   const T wab = TB::w(pa) * TB::w(pb);
   {
@@ -226,22 +177,8 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
     }
 
     {
-      // One component per call: the body has no loop over components, so the
-      // compiler materialises the table constants at their uses instead of keeping
-      // them live across iterations (which doubled the register count).
-      T yv[N], r_cur[N];
-#pragma unroll
-      for (int l = 0; l < N; l++) r_cur[l] = gidx[l] >= 0 ? A.x[(int64_t)gidx[l] * nc + comp] : T(0);
-      if constexpr (!ATOMIC) {
-        // no other cell of this launch touches these nodes: read y now, write it at the end
-#pragma unroll
-        for (int l = 0; l < N; l++)
-          yv[l] = (!mirror && idx_cur[l] >= 0) ? A.y[(int64_t)idx_cur[l] * nc + comp] : T(0);
-      }
-      T r[N], v[N];
-      // ---- z-pencil (i, j) = (pa, pb) gathered one item earlier; contract z with B
-  #pragma unroll
-      for (int l = 0; l < N; l++) r[l] = r_cur[l];
+      T v[N];
+      // ---- z-pencil (i, j) = (pa, pb): contract z with B
       eo_contract<T, N, MatB<N>, 1>(r, v);
   #pragma unroll
       for (int c = 0; c < N; c++) if (STORE) u0[IX(pa, pb, c)] = v[c];
@@ -368,18 +305,94 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       for (int c = 0; c < N; c++) r[c] = u0[IX(pa, pb, c)];
       eo_contract<T, N, MatBt<N>, 1>(r, v);
   #pragma unroll
-      for (int l = 0; l < N; l++) {
-        const T s = v[l];
-        const int idx = mirror ? -1 : idx_cur[l];
-        if (idx >= 0) {
-          if constexpr (ATOMIC) atomic_add_f(&A.y[(int64_t)idx * nc + comp], s);
-          else A.y[(int64_t)idx * nc + comp] = yv[l] + s;
-        }
-      }
-
-      __syncthreads();
+      for (int l = 0; l < N; l++) r[l] = v[l];
     }
   }
+}
+
+// Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
+// on the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
+template <typename T, int N, int KIND, bool ATOMIC, int WPB = 1>
+__device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, const int comp, T *lds) {
+  using TB = TabT<T, N>;
+  constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N, WPB>();
+  constexpr bool GRAD = KIND != K_MASS;
+  constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
+  constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
+  constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ, SE = HexLds<N>::SE;
+  T *s0 = lds;
+  T *s1 = lds + (GRAD ? EPB * SE : 0);
+  T *s2 = lds + (GRAD ? 2 * EPB * SE : 0);
+  T *sg = lds + (GRAD ? 3 : 1) * EPB * SE;
+
+  const int t = threadIdx.x;
+  const bool mirror = t >= EPB * NN;
+  // A mirror lane duplicates the pencil of lane t - EPB n^2. In a one-wavefront
+  // workgroup it runs in lockstep with that lane, so its identical LDS stores are
+  // harmless; across wavefronts its in-place read-then-write could interleave with
+  // the original's, so there it stores nothing (and never scatters).
+  const bool STORE = WPB == 1 || !mirror;
+  const int tt = mirror ? t - EPB * NN : t;
+  const int le = tt / NN, p = tt - le * NN;
+  const int pa = p % N, pb = p / N;
+  const int nc = A.ncomp;
+
+  // One batch of EPB cells per call: map, geometry and the first component's
+  // gathers are issued together, then each component is processed in turn.
+  int idx_cur[N], gidx[N];  // scatter (internal node) and gather positions
+  {
+    const int64_t c = A.c0 + b * EPB + le;
+    bool ok = c < A.c1;
+    if (ok && A.cell_user) {
+      const int64_t u = A.cell_user[c];
+      ok = u >= A.ulo && u < A.uhi;
+    }
+    const int64_t off = (ok ? c : A.c0) * N3 + pa + N * pb;
+#pragma unroll
+    for (int l = 0; l < N; l++) idx_cur[l] = ok ? A.map[off + NN * l] : -1;
+#pragma unroll
+    for (int l = 0; l < N; l++) gidx[l] = A.gmap ? (ok ? A.gmap[off + NN * l] : -1) : idx_cur[l];
+  }
+  for (int i = t; i < EPB * 32; i += 64 * WPB) {
+    const int e = i >> 5, j = i & 31;
+    const int64_t c = A.c0 + b * EPB + e;
+    T v = T(0);
+    if (c < A.c1) {
+      if (j < 24) v = A.geo[c * 24 + j];
+      else if (COEF && A.coef) v = A.coef[c * 8 + (j - 24)];
+      else if (j == 24) v = T(1);  // coefficient 1 when absent
+    } else if (j == 0 || j == 4 || j == 8) {
+      v = T(1);  // cells past the end: unit-cube geometry keeps the arithmetic finite
+    }
+    sg[i] = v;
+  }
+  __syncthreads();
+
+  T *u0 = s0 + le * SE;
+  T *u1 = s1 + (GRAD ? le * SE : 0);
+  T *u2 = s2 + (GRAD ? le * SE : 0);
+  const T *Gc = sg + le * 32;
+  // One component per call: the body has no loop over components, so the compiler
+  // materialises the table constants at their uses instead of keeping them live
+  // across iterations (which doubled the register count).
+  T yv[N], r[N];
+#pragma unroll
+  for (int l = 0; l < N; l++) r[l] = gidx[l] >= 0 ? A.x[(int64_t)gidx[l] * nc + comp] : T(0);
+  if constexpr (!ATOMIC) {
+    // no other cell of this launch touches these nodes: read y now, write it at the end
+#pragma unroll
+    for (int l = 0; l < N; l++) yv[l] = (!mirror && idx_cur[l] >= 0) ? A.y[(int64_t)idx_cur[l] * nc + comp] : T(0);
+  }
+  hex_pencil_stages<T, N, KIND, WPB>(r, Gc, u0, u1, u2, pa, pb, STORE);
+#pragma unroll
+  for (int l = 0; l < N; l++) {
+    const int idx = mirror ? -1 : idx_cur[l];
+    if (idx >= 0) {
+      if constexpr (ATOMIC) atomic_add_f(&A.y[(int64_t)idx * nc + comp], r[l]);
+      else A.y[(int64_t)idx * nc + comp] = yv[l] + r[l];
+    }
+  }
+  __syncthreads();
 }
 
 #undef IX
@@ -806,8 +819,9 @@ __global__ void __launch_bounds__(kPatchThreads, q1_patch_waves<KIND>()) hex_q1_
 }
 
 template <typename T>
-int launch_hex_q1_patches(int kind, const HexPatchArgs<T> &a, hipStream_t s) {
+int launch_hex_patches(int N, int kind, const HexPatchArgs<T> &a, hipStream_t s) {
   if (a.npatch <= 0) return MF_OK;
+  if (N != 2) return fail(MF_EUNSUPPORTED, "hex patch kernel: degree");
   const dim3 grid((unsigned)xcd_grid((int64_t)a.npatch * a.ncomp)), block(kPatchThreads);
   const size_t lds = 2 * (size_t)a.max_nodes * sizeof(T);
   switch (kind) {
@@ -820,8 +834,8 @@ int launch_hex_q1_patches(int kind, const HexPatchArgs<T> &a, hipStream_t s) {
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
-template int launch_hex_q1_patches<double>(int, const HexPatchArgs<double> &, hipStream_t);
-template int launch_hex_q1_patches<float>(int, const HexPatchArgs<float> &, hipStream_t);
+template int launch_hex_patches<double>(int, int, const HexPatchArgs<double> &, hipStream_t);
+template int launch_hex_patches<float>(int, int, const HexPatchArgs<float> &, hipStream_t);
 
 template <typename T>
 static int launch_q1(int kind, const HexArgs<T> &a, hipStream_t s) {

@@ -291,16 +291,18 @@ static uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   return spread(x) | (spread(y) << 1) | (spread(z) << 2);
 }
 
-// Patches of the degree-1 patch kernel: cells in Morton order of their centroids,
-// cut greedily into runs of at most `cap` cells (<= kPatchCells) and kPatchNodes
-// distinct free nodes. cap shrinks on small meshes so that there are about 1024
-// patches (several per compute unit). m: the flagged map ([cell][8], negative =
-// constrained); geo, cf: the [cell][entry] geometry and coefficient.
+// Patches of the Q1 patch kernel: cells in Morton order of their centroids, cut
+// greedily into runs of at most `cap` cells and kPatchNodes distinct free nodes. cap
+// shrinks on small meshes so that there are about 1024 patches (several per compute
+// unit). m: the flagged map ([cell][D], negative = constrained); to_pos2: gather
+// positions after the first user -> internal permutation stage (empty when the
+// numbering is the identity); geo, cf: the [cell][entry] geometry and coefficient.
 template <typename T>
 static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<int32_t> &m,
                              const std::vector<int32_t> &to_pos2, const std::vector<T> &geo, const std::vector<T> &cf,
                              hipStream_t s) {
   const int64_t nc = sp->ncells;
+  constexpr int D = 8;
   std::vector<double> cen((size_t)nc * 3);
   double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
   for (int64_t K = 0; K < nc; K++)
@@ -324,8 +326,11 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
   }
   std::sort(key.begin(), key.end());
 
-  const int cap = (int)std::min<int64_t>(kPatchCells, std::max<int64_t>(64, (nc / 1024) / 64 * 64));
-  const int SB = cap / 64;  // 64-slot blocks per patch
+  // capacity: a multiple of 64 near ncells / 1024, at most kPatchCells
+  const int cap = 64 * (int)std::min<int64_t>(kPatchCells / 64, std::max<int64_t>(1, (nc / 1024) / 64));
+  auto at = [&](int64_t p, int sl, int E, int e) -> size_t {  // slot entry position
+    return (((size_t)p * (cap / 64) + sl / 64) * E + e) * 64 + sl % 64;
+  };
   std::vector<int32_t> stamp((size_t)sp->nnodes, -1), loc((size_t)sp->nnodes, 0);
   std::vector<int32_t> nptr{0}, nodes;
   std::vector<uint16_t> lmap;
@@ -334,17 +339,17 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
   auto open_patch = [&]() {
     pid++;
     ncell = nnode = 0;
-    lmap.resize((size_t)(pid + 1) * cap * 8, kPatchEmpty);
+    lmap.resize((size_t)(pid + 1) * cap * D, kPatchEmpty);
     pgeo.resize((size_t)(pid + 1) * cap * 24, T(0));
     for (int sl = 0; sl < cap; sl++)  // empty slots: the unit-cube map
-      for (int j : {0, 4, 8}) pgeo[(((size_t)pid * SB + sl / 64) * 24 + j) * 64 + sl % 64] = T(1);
+      for (int j : {0, 4, 8}) pgeo[at(pid, sl, 24, j)] = T(1);
     if (op->has_coef) pcoef.resize((size_t)(pid + 1) * cap * 8, T(0));
   };
   for (int64_t r = 0; r < nc; r++) {
     const int64_t K = key[r].second;
     int fresh = 0;
-    for (int i = 0; i < 8; i++) {
-      const int32_t id = m[K * 8 + i];
+    for (int i = 0; i < D; i++) {
+      const int32_t id = m[K * D + i];
       if (id >= 0 && stamp[id] != pid) fresh++;
     }
     if (pid < 0 || ncell == cap || nnode + fresh > kPatchNodes) {
@@ -352,9 +357,8 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
       open_patch();
     }
     const int sl = ncell++;
-    const size_t b = (size_t)pid * SB + sl / 64, l = sl % 64;
-    for (int i = 0; i < 8; i++) {
-      const int32_t id = m[K * 8 + i];
+    for (int i = 0; i < D; i++) {
+      const int32_t id = m[K * D + i];
       uint16_t li = kPatchEmpty;
       if (id >= 0) {
         if (stamp[id] != pid) {
@@ -364,11 +368,11 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
         }
         li = (uint16_t)loc[id];
       }
-      lmap[(b * 8 + i) * 64 + l] = li;
+      lmap[at(pid, sl, D, i)] = li;
     }
-    for (int j = 0; j < 24; j++) pgeo[(b * 24 + j) * 64 + l] = geo[K * 24 + j];
+    for (int j = 0; j < 24; j++) pgeo[at(pid, sl, 24, j)] = geo[K * 24 + j];
     if (op->has_coef)
-      for (int j = 0; j < 8; j++) pcoef[(b * 8 + j) * 64 + l] = cf[K * 8 + j];
+      for (int j = 0; j < 8; j++) pcoef[at(pid, sl, 8, j)] = cf[K * 8 + j];
   }
   if (pid >= 0) nptr.push_back((int32_t)nodes.size());
   const int np = pid + 1;
@@ -580,7 +584,7 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
                         fused ? op->pt_gnodes.as<int32_t>() : nullptr, op->pt_lmap.as<uint16_t>(),
                         op->pt_geo.as<T>(), op->has_coef ? op->pt_coef.as<T>() : nullptr, x, y, op->npatch,
                         op->pt_max_nodes, op->ncomp, op->pt_cap};
-      rc = launch_hex_q1_patches<T>(op->kind, a, s);
+      rc = launch_hex_patches<T>(op->degree + 1, op->kind, a, s);
     } else if (op->coloured) {
       // one launch per colour: cells of a colour share no node, so no atomics
       for (size_t c = 0; c + 1 < op->colour_ptr.size() && !rc; c++)

@@ -93,7 +93,8 @@ template <typename T> struct HexArgs {
 // operator) with at most kPatchNodes distinct free nodes. Per-slot arrays are
 // block-interleaved with cap slots per patch: entry e of slot s of patch p at
 // ((p * cap / 64 + s / 64) * E + e) * 64 + s % 64; empty slots and constrained
-// nodes have local index kPatchEmpty.
+// nodes have local index kPatchEmpty. (The same scheme around the pencil stages for
+// higher degrees measured slower than the atomic and coloured launches.)
 constexpr int kPatchCells = 512, kPatchNodes = 1024, kPatchThreads = 256;
 constexpr uint16_t kPatchEmpty = 0xFFFF;
 template <typename T> struct HexPatchArgs {
@@ -107,7 +108,8 @@ template <typename T> struct HexPatchArgs {
   T *y;
   int npatch, max_nodes, ncomp, cap;
 };
-template <typename T> int launch_hex_q1_patches(int kind, const HexPatchArgs<T> &a, hipStream_t s);
+// N = 2 only (the lane-per-cell Q1 kernel).
+template <typename T> int launch_hex_patches(int N, int kind, const HexPatchArgs<T> &a, hipStream_t s);
 
 // Kernel launchers (hex_kernels.hip)
 // atomic: scatter with device-scope atomics (any cell set); otherwise plain

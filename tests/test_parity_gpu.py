@@ -84,15 +84,16 @@ def test_hex_scatter_modes(mf, k, scatter, prec, kind, ncomp):
 @pytest.mark.parametrize("m", [6, 20])
 @pytest.mark.parametrize("kind,ncomp", [(1, 1), (2, 3), (3, 1), (0, 1)],
                          ids=["helmholtz", "laplacian3", "poisson", "mass"])
-def test_hex_q1_patch_scatter(mf, m, prec, kind, ncomp):
+def test_hex_patch_scatter(mf, m, prec, kind, ncomp):
     """Q1 through the patch kernel (216 cells: four patches, the last ragged; 8000
     cells: 125 patches) against the oracle, with and without constrained nodes."""
     import torch
-    print(f"hex patch m={m} kind={kind} ncomp={ncomp} prec={prec}", flush=True)
-    mesh = mg.hex_mesh(m, 0.15, config=1, seed_k=1)
-    space = mg.hex_space(mesh, 1, ncomp=ncomp, config=1)
-    coef = np.exp(np.random.default_rng(1).normal(size=mesh.nverts)) if kind in (0, 3) else None
-    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, 1)
+    k = 1
+    print(f"hex patch k={k} m={m} kind={kind} ncomp={ncomp} prec={prec}", flush=True)
+    mesh = mg.hex_mesh(m, 0.15, config=1, seed_k=k)
+    space = mg.hex_space(mesh, k, ncomp=ncomp, config=1)
+    coef = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if kind in (0, 3) else None
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
     orc = oracle.OracleOp(space, kind, coef=coef)
     sp = mf.Space.from_meshgen(space)
     op = mf.Operator(sp, kind, prec, vertex_coef=coef, scatter=mf.SCATTER_PATCH)
