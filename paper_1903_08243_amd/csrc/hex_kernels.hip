@@ -98,6 +98,21 @@ __device__ __forceinline__ void eo_contract(const T (&in)[N], T (&out)[N]) {
   }
 }
 
+// 1/a from the hardware reciprocal refined by Newton steps e = 1 - a r, r += r e
+// (two in FP64, one in FP32): about half the instructions of the IEEE division
+// sequence, within an ulp or two of the rounded quotient (a > 0, |det J| here).
+__device__ __forceinline__ double recip(double a) {
+  double r = __builtin_amdgcn_rcp(a);
+  double e = __builtin_fma(-a, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-a, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float a) {
+  const float r = __builtin_amdgcn_rcpf(a);
+  return __builtin_fmaf(r, __builtin_fmaf(-a, r, 1.0f), r);
+}
+
 __device__ __forceinline__ void atomic_add_f(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add_f(float *p, float v) { unsafeAtomicAdd(p, v); }
 
@@ -239,7 +254,7 @@ __device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0,
                              j3[0] * j1[1] - j3[1] * j1[0]};
             const T r2[3] = {j1[1] * j2[2] - j1[2] * j2[1], j1[2] * j2[0] - j1[0] * j2[2],
                              j1[0] * j2[1] - j1[1] * j2[0]};
-            const T sc = wq * kq / adet;
+            const T sc = wq * kq * recip(adet);
             // d(u)/d(ref x), d/d(ref y) from LDS, d/d(ref z) from the register pencil
             const T dz = dzv[c];
             const T dx = u1[IX(pa, pb, c)];
@@ -646,7 +661,7 @@ __device__ __forceinline__ void q1_cell(const T (&G)[21], const T (&K)[8], const
     if constexpr (GRAD) {
       const T r1[3] = {j3[1] * j1[2] - j3[2] * j1[1], j3[2] * j1[0] - j3[0] * j1[2], j3[0] * j1[1] - j3[1] * j1[0]};
       const T r2[3] = {j1[1] * j2[2] - j1[2] * j2[1], j1[2] * j2[0] - j1[0] * j2[2], j1[0] * j2[1] - j1[1] * j2[0]};
-      const T sc = wq * kq / adet;
+      const T sc = wq * kq * recip(adet);
       // reference gradient by collocation on the two points of each direction
       const int qx = q ^ 1, qy = q ^ 2, qz = q ^ 4;
       const T dx = TB::D(a, a) * u[q] + TB::D(a, 1 - a) * u[qx];
