@@ -386,6 +386,27 @@ def profile_kernel(mf, mg):
                       "cell_launches_per_apply": op.info["cell_launches"]}))
 
 
+def profile_q1(mf, mg):
+    """The low-order kernel of the weak-scaled figures (FP64 Helmholtz, Q1, 128^3, patch
+    scatter) launched 10 times, then the same 256 MiB calibration copy 10 times."""
+    import torch
+    mesh = mg.hex_mesh(128, 0.15, config=1, seed_k=1)
+    space = mg.hex_space(mesh, 1, ncomp=1, config=1)
+    op = mf.Operator(mf.Space.from_meshgen(space), mf.HELMHOLTZ, mf.F64)
+    x = torch.tensor(mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, 1), device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(10):
+        op.apply_internal(x, y)
+    a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profiled": "helmholtz-Q1 128^3 fp64 x10, copy 256MiB x10",
+                      "flops_per_apply": op.info["flops_per_apply"], "bytes_per_apply": op.info["bytes_per_apply"],
+                      "cell_launches_per_apply": op.info["cell_launches"]}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -402,6 +423,9 @@ def main():
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only run the dominant action kernel 10 times and a 256 MiB reference copy "
                          "(for hardware-counter runs)")
+    ap.add_argument("--profile-q1", action="store_true",
+                    help="only run the Q1 patch kernel on 128^3 10 times and the reference copy "
+                         "(for hardware-counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU design "
@@ -416,6 +440,9 @@ def main():
     mf.load_library()
     if args.profile_kernel:
         profile_kernel(mf, mg)
+        return
+    if args.profile_q1:
+        profile_q1(mf, mg)
         return
     if args.c5_only:
         print(json.dumps(bench_c5(mf, mg, m=args.c5_m)))
