@@ -112,6 +112,36 @@ def test_hex_patch_scatter(mf, m, prec, kind, ncomp):
     assert _relerr(yd, ref.ravel()) <= TOL[prec], _relerr(yd, ref.ravel())
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_hex_patch_scatter_accumulates(mf, prec):
+    """Full-range applies with accumulation go through the patch kernel (y not
+    cleared): two increments and one overwrite give 2 A x and A x, in user and in
+    internal numbering."""
+    import torch
+    mesh = mg.hex_mesh(20, 0.15, config=1, seed_k=1)
+    space = mg.hex_space(mesh, 1, config=1)
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, 1)
+    ref = oracle.OracleOp(space, oracle.OP_HELMHOLTZ).apply(x)
+    sp = mf.Space.from_meshgen(space)
+    op = mf.Operator(sp, 1, prec, scatter=mf.SCATTER_PATCH)
+    xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+    y = torch.zeros_like(xt)
+    nc = mesh.ncells
+    op.apply_range(0, nc, xt, y, accumulate=True)
+    op.apply_range(0, nc, xt, y, accumulate=True)
+    assert _relerr(y.double().cpu().numpy(), 2 * ref) <= TOL[prec]
+    op.apply_range(0, nc, xt, y, accumulate=False)
+    assert _relerr(y.double().cpu().numpy(), ref) <= TOL[prec]
+    # internal numbering (as inside CG): x_int[i] = x[i2u[i]], y[i2u[i]] = y_int[i]
+    i2u = sp.internal_to_user()
+    xi = torch.tensor(x[i2u], device="cuda", dtype=op.torch_dtype)
+    yi = torch.zeros_like(xi)
+    op.apply_range_internal(0, nc, xi, yi, accumulate=True)
+    yu = np.empty(space.ndofs)
+    yu[i2u] = yi.double().cpu().numpy()
+    assert _relerr(yu, ref) <= TOL[prec]
+
+
 def test_hex_patch_scatter_other_degrees_rejected(mf):
     mesh = mg.hex_mesh(3, 0.15)
     sp = mf.Space.from_meshgen(mg.hex_space(mesh, 2))
