@@ -520,11 +520,16 @@ static void count_work(mf_op *op) {
   const int comps = op->ncomp;
   double fl = 0.0, by = 2.0 * nd * s + 4.0 * op->D * nc;
   if (op->cell_type == MF_CELL_HEX) {
-    const double n = op->degree + 1, q3 = n * n * n;
+    const int ni = op->degree + 1;
+    const double n = ni, q3 = n * n * n;
     const bool grad = op->kind != MF_OP_MASS, mass = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ;
     // 1D contractions: 3 forward + 3 backward with B, plus 3 + 3 with the collocation
-    // derivative when gradients are needed; each costs 2 n^4 flops per component.
-    const double contr = (grad ? 12.0 : 6.0) * 2.0 * n * n * n * n * comps;
+    // derivative when gradients are needed, each over n^2 pencils of length n. A pencil
+    // costs 2 n^2 flops as a plain product (Q1) and, split into even and odd halves
+    // (n >= 3), n^2 + 2n flops for even n and n^2 + 2n - 1 for odd n (multiply-adds
+    // counted as two flops, as in the plain count).
+    const double pencil = ni >= 3 ? n * n + 2.0 * n - (ni % 2) : 2.0 * n * n;
+    const double contr = (grad ? 12.0 : 6.0) * n * n * pencil * comps;
     // per point: Jacobian 12, adjugate rows 18 (6 for the mass-only kernel), det 5,
     // weights/scale 4; per component: push-forward 18 + fluxes 21, mass term 4
     const double geo = grad ? 39.0 : 24.0;
