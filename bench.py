@@ -199,8 +199,12 @@ def bench_weak(mf, mg, reps=20):
             t = time_kernel(op, x, y, reps)
             r = roof(op, t, 0)
             tag = f"{name}-Q{k}_128cube"
+            # design-independent minimum: x and y once, the int32 cell map, FP64 vertex
+            # coordinates once (the kernels read 24 stored geometry values per cell instead)
+            bmin = 2.0 * space.ndofs * 8 + 4.0 * space.cell2node.shape[1] * mesh.ncells + 24.0 * mesh.nverts
             out[tag] = {"cells": mesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
-                        "bound": r["bound"], "frac": r["frac"], "gbs": r["gbs"], "tflops": r["tflops"]}
+                        "bound": r["bound"], "frac": r["frac"], "gbs": r["gbs"], "tflops": r["tflops"],
+                        "bmin_bytes": bmin, "frac_bmin": bmin / t / PEAK_HBM}
             log(f"  {tag}: {json.dumps(out[tag])}")
             del op
         del sp, space
