@@ -754,16 +754,23 @@ __global__ void __launch_bounds__(64) hex_q1_kernel(const HexArgs<T> A) {
 
 // Q1 over patches, for full applies: a workgroup takes one patch of up to
 // kPatchCells cells that are close in space (cells in Morton order of their
-// centroids), gathers the patch's nodes from x into LDS once, lets each lane compute
-// whole cells from LDS and add their results into a per-patch LDS accumulator, and
-// finally writes every patch node once: nodes no other patch touches with a plain
-// read-modify-write, the others (the patch surface) with one device atomic each.
-// Against the coloured launches (every colour reads and writes every node) this
-// moves x and y about once per apply, and against the atomic scatter it issues about
-// one device atomic per cell instead of eight.
+// centroids), gathers the patch's nodes from x and their vertex coordinates into LDS
+// once, lets each lane compute whole cells from LDS and add their results into a
+// per-patch LDS accumulator, and finally writes every patch node once: nodes no other
+// patch touches with a plain read-modify-write, the others (the patch surface) with
+// one device atomic each. Against the coloured launches (every colour reads and
+// writes every node) this moves x and y about once per apply, and against the atomic
+// scatter it issues about one device atomic per cell instead of eight. In FP64 the
+// cell geometry (the trilinear map's coefficients) is rebuilt from the 8 corner
+// coordinates gathered into LDS: 24 bytes per vertex, shared by its cells, instead of
+// 192 stored bytes per cell. In FP32 the 24 stored per-slot values (precomputed in
+// FP64, rounded once) are read instead: rebuilding them in FP32 would lose accuracy to
+// cancellation, and in FP64 it measured slower than the 96 stored bytes.
+template <typename T> constexpr bool q1_patch_coords() { return sizeof(T) == 8; }
+
 template <typename T, int KIND>
 __device__ __forceinline__ void q1_patch_slot_load(const HexPatchArgs<T> &P, int p, int s, uint16_t (&li)[8],
-                                                   T (&G)[21], T (&K)[8]) {
+                                                   T (&K)[8], T (&G)[21]) {
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
   // slot s of patch p: entry e at ((p * cap / 64 + s / 64) * E + e) * 64 + s % 64. A
   // slot number past the capacity reads slot 0 (a branch here costs registers) and is
@@ -775,25 +782,39 @@ __device__ __forceinline__ void q1_patch_slot_load(const HexPatchArgs<T> &P, int
 #pragma unroll
   for (int i = 0; i < 8; i++) li[i] = have ? P.lmap[(blk * 8 + i) * 64 + lane] : kPatchEmpty;
 #pragma unroll
-  for (int j = 0; j < 21; j++) G[j] = P.geo[(blk * 24 + j) * 64 + lane];
-#pragma unroll
   for (int j = 0; j < 8; j++) K[j] = (COEF && P.coef) ? P.coef[(blk * 8 + j) * 64 + lane] : T(j == 0 ? 1 : 0);
+  if constexpr (!q1_patch_coords<T>()) {
+#pragma unroll
+    for (int j = 0; j < 21; j++) G[j] = P.geo[(blk * 24 + j) * 64 + lane];
+  }
 }
 
 template <typename T, int KIND>
-__device__ __forceinline__ void q1_patch_slot(const uint16_t (&li)[8], const T (&G)[21], const T (&K)[8], const T *sx,
-                                              T *sy) {
-  bool any = false;  // slots past the patch's cells (and cells with only constrained nodes)
-#pragma unroll
-  for (int i = 0; i < 8; i++) any |= li[i] != kPatchEmpty;
-  if (!any) return;
+__device__ __forceinline__ void q1_patch_slot(const uint16_t (&li)[8], const T (&K)[8], T (&G)[21], const T *sx,
+                                              const double *sxyz, T *sy) {
+  if (li[0] == kPatchEmpty) return;  // a slot past the patch's cells (a real cell has all 8)
   T xv[8], yv[8];
 #pragma unroll
-  for (int i = 0; i < 8; i++) xv[i] = li[i] != kPatchEmpty ? sx[li[i]] : T(0);
+  for (int i = 0; i < 8; i++) xv[i] = sx[li[i]];
+  if constexpr (q1_patch_coords<T>()) {
+#pragma unroll
+    for (int d = 0; d < 3; d++) {
+      double X[8];
+#pragma unroll
+      for (int v = 0; v < 8; v++) X[v] = sxyz[3 * li[v] + d];
+      // monomial coefficients c1..c7 of the trilinear map (vertex v at (v&1, v>>1&1, v>>2&1))
+      G[0 + d] = T(X[1] - X[0]);
+      G[3 + d] = T(X[2] - X[0]);
+      G[6 + d] = T(X[4] - X[0]);
+      G[9 + d] = T(X[3] - X[1] - X[2] + X[0]);
+      G[12 + d] = T(X[5] - X[1] - X[4] + X[0]);
+      G[15 + d] = T(X[6] - X[2] - X[4] + X[0]);
+      G[18 + d] = T(X[7] - X[3] - X[5] - X[6] + X[1] + X[2] + X[4] - X[0]);
+    }
+  }
   q1_cell<T, KIND>(G, K, xv, yv);
 #pragma unroll
-  for (int i = 0; i < 8; i++)
-    if (li[i] != kPatchEmpty) atomic_add_f(&sy[li[i]], yv[i]);
+  for (int i = 0; i < 8; i++) atomic_add_f(&sy[li[i]], yv[i]);
 }
 
 // Three wavefronts per SIMD where the registers allow it without spilling much (the
@@ -803,33 +824,43 @@ template <int KIND> constexpr int q1_patch_waves() { return KIND == K_POIS ? 2 :
 template <typename T, int KIND>
 __global__ void __launch_bounds__(kPatchThreads, q1_patch_waves<KIND>()) hex_q1_patch_kernel(const HexPatchArgs<T> P) {
   static_assert(kPatchCells == 2 * kPatchThreads, "two cell slots per thread");
+  constexpr bool XYZ = q1_patch_coords<T>();
   extern __shared__ __align__(16) unsigned char patch_lds[];
-  T *sx = (T *)patch_lds, *sy = sx + P.max_nodes;
+  double *sxyz = (double *)patch_lds;
+  T *sx = (T *)(sxyz + (XYZ ? 3 * P.max_nodes : 0)), *sy = sx + P.max_nodes;
   const int64_t item = xcd_batch(blockIdx.x, P.npatch * P.ncomp);
   if (item >= P.npatch * P.ncomp) return;
   const int p = (int)item / P.ncomp, comp = (int)item % P.ncomp, nc = P.ncomp;
   const int t = threadIdx.x;
-  // the first slot's map and geometry are requested before the gather of x, so
-  // their latency overlaps it
+  // the first slot's map is requested before the gathers, so its latency overlaps them
   uint16_t li[8];
-  T G[21], K[8];
-  q1_patch_slot_load<T, KIND>(P, p, t, li, G, K);
+  T K[8], G[21];
+  q1_patch_slot_load<T, KIND>(P, p, t, li, K, G);
   const int n0 = P.node_ptr[p], nn = P.node_ptr[p + 1] - n0;
   for (int i = t; i < nn; i += kPatchThreads) {
-    const int32_t id = P.nodes[n0 + i];
-    const int64_t g = P.gnodes ? P.gnodes[n0 + i] : (id < 0 ? -1 - id : id);
-    sx[i] = P.x[g * nc + comp];
+    const int32_t e = P.nodes[n0 + i];
+    const int64_t id = e & kPatchIdMask;
+    const int64_t g = P.gnodes ? P.gnodes[n0 + i] : id;
+    const T xv = P.x[g * nc + comp];  // a constrained node's value is read, then replaced by 0
+    sx[i] = (e & kPatchFixed) ? T(0) : xv;
     sy[i] = T(0);
+    if constexpr (XYZ) {
+      sxyz[3 * i] = P.xyz[3 * id];
+      sxyz[3 * i + 1] = P.xyz[3 * id + 1];
+      sxyz[3 * i + 2] = P.xyz[3 * id + 2];
+    }
   }
   __syncthreads();
-  q1_patch_slot<T, KIND>(li, G, K, sx, sy);
-  q1_patch_slot_load<T, KIND>(P, p, t + kPatchThreads, li, G, K);
-  q1_patch_slot<T, KIND>(li, G, K, sx, sy);
+  q1_patch_slot<T, KIND>(li, K, G, sx, sxyz, sy);
+  q1_patch_slot_load<T, KIND>(P, p, t + kPatchThreads, li, K, G);
+  q1_patch_slot<T, KIND>(li, K, G, sx, sxyz, sy);
   __syncthreads();
   for (int i = t; i < nn; i += kPatchThreads) {
-    const int32_t id = P.nodes[n0 + i];
-    if (id >= 0) P.y[(int64_t)id * nc + comp] += sy[i];
-    else atomic_add_f(&P.y[(int64_t)(-1 - id) * nc + comp], sy[i]);
+    const int32_t e = P.nodes[n0 + i];
+    if (e & kPatchFixed) continue;
+    T *dst = &P.y[(int64_t)(e & kPatchIdMask) * nc + comp];
+    if (e & kPatchShared) atomic_add_f(dst, sy[i]);
+    else *dst += sy[i];
   }
 }
 
@@ -838,7 +869,7 @@ int launch_hex_patches(int N, int kind, const HexPatchArgs<T> &a, hipStream_t s)
   if (a.npatch <= 0) return MF_OK;
   if (N != 2) return fail(MF_EUNSUPPORTED, "hex patch kernel: degree");
   const dim3 grid((unsigned)xcd_grid((int64_t)a.npatch * a.ncomp)), block(kPatchThreads);
-  const size_t lds = 2 * (size_t)a.max_nodes * sizeof(T);
+  const size_t lds = (size_t)a.max_nodes * ((q1_patch_coords<T>() ? 3 * sizeof(double) : 0) + 2 * sizeof(T));
   switch (kind) {
     case K_MASS: hex_q1_patch_kernel<T, K_MASS><<<grid, block, lds, s>>>(a); break;
     case K_HELM: hex_q1_patch_kernel<T, K_HELM><<<grid, block, lds, s>>>(a); break;

@@ -278,6 +278,8 @@ void mf_space_destroy(mf_space *s) { delete s; }
 // ------------------------------------------------------------------ operator setup
 namespace mf {
 
+static bool default_coloured(const mf_op *op);
+
 // 3 x 10-bit Morton code (bit i of x, y, z at bits 3i, 3i + 1, 3i + 2)
 static uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
   auto spread = [](uint32_t v) {
@@ -299,8 +301,16 @@ static uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
 // numbering is the identity); geo, cf: the [cell][entry] geometry and coefficient.
 template <typename T>
 static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<int32_t> &m,
-                             const std::vector<int32_t> &to_pos2, const std::vector<T> &geo, const std::vector<T> &cf,
-                             hipStream_t s) {
+                             const std::vector<int32_t> &to_pos2, const std::vector<T> &geo,
+                             const std::vector<T> &cf, bool required, hipStream_t s) {
+  constexpr bool XYZ = sizeof(T) == 8;  // FP64: vertex coordinates; FP32: stored per-slot geometry
+  auto not_patched = [&](const char *why) {
+    if (required) return fail(MF_EUNSUPPORTED, std::string("mf_op_create: patch scatter: ") + why);
+    op->patched = false;  // keep the default of the other scatters
+    op->coloured = default_coloured(op);
+    return (int)MF_OK;
+  };
+  if (sp->nnodes > kPatchIdMask) return not_patched("too many nodes for the patch node encoding");
   const int64_t nc = sp->ncells;
   constexpr int D = 8;
   std::vector<double> cen((size_t)nc * 3);
@@ -331,6 +341,22 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
   auto at = [&](int64_t p, int sl, int E, int e) -> size_t {  // slot entry position
     return (((size_t)p * (cap / 64) + sl / 64) * E + e) * 64 + sl % 64;
   };
+  // Vertex coordinates per internal node (a Q1 node is a vertex: local node v of a cell
+  // is its vertex v); every cell must agree, else the patch path is not used.
+  const std::vector<int32_t> &c2n = sp->cell2node_int;
+  std::vector<double> xyz((size_t)sp->nnodes * 3, 0.0);
+  std::vector<uint8_t> seen((size_t)sp->nnodes, 0);
+  for (int64_t K = 0; K < nc; K++)
+    for (int v = 0; v < D; v++) {
+      const int64_t n = c2n[K * D + v];
+      const double *X = &sp->coords[(int64_t)sp->cell2vert_int[K * 8 + v] * 3];
+      if (!seen[n]) {
+        seen[n] = 1;
+        for (int a = 0; a < 3; a++) xyz[n * 3 + a] = X[a];
+      } else if (xyz[n * 3] != X[0] || xyz[n * 3 + 1] != X[1] || xyz[n * 3 + 2] != X[2]) {
+        return not_patched("the nodes are not the cells' vertices");
+      }
+    }
   std::vector<int32_t> stamp((size_t)sp->nnodes, -1), loc((size_t)sp->nnodes, 0);
   std::vector<int32_t> nptr{0}, nodes;
   std::vector<uint16_t> lmap;
@@ -340,61 +366,59 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
     pid++;
     ncell = nnode = 0;
     lmap.resize((size_t)(pid + 1) * cap * D, kPatchEmpty);
-    pgeo.resize((size_t)(pid + 1) * cap * 24, T(0));
-    for (int sl = 0; sl < cap; sl++)  // empty slots: the unit-cube map
-      for (int j : {0, 4, 8}) pgeo[at(pid, sl, 24, j)] = T(1);
+    if (!XYZ) {
+      pgeo.resize((size_t)(pid + 1) * cap * 24, T(0));
+      for (int sl = 0; sl < cap; sl++)  // empty slots: the unit-cube map
+        for (int j : {0, 4, 8}) pgeo[at(pid, sl, 24, j)] = T(1);
+    }
     if (op->has_coef) pcoef.resize((size_t)(pid + 1) * cap * 8, T(0));
   };
   for (int64_t r = 0; r < nc; r++) {
     const int64_t K = key[r].second;
     int fresh = 0;
-    for (int i = 0; i < D; i++) {
-      const int32_t id = m[K * D + i];
-      if (id >= 0 && stamp[id] != pid) fresh++;
-    }
+    for (int i = 0; i < D; i++)
+      if (stamp[c2n[K * D + i]] != pid) fresh++;
     if (pid < 0 || ncell == cap || nnode + fresh > kPatchNodes) {
       if (pid >= 0) nptr.push_back((int32_t)nodes.size());
       open_patch();
     }
     const int sl = ncell++;
     for (int i = 0; i < D; i++) {
-      const int32_t id = m[K * D + i];
-      uint16_t li = kPatchEmpty;
-      if (id >= 0) {
-        if (stamp[id] != pid) {
-          stamp[id] = pid;
-          loc[id] = nnode++;
-          nodes.push_back(id);
-        }
-        li = (uint16_t)loc[id];
+      const int32_t id = c2n[K * D + i];
+      if (stamp[id] != pid) {
+        stamp[id] = pid;
+        loc[id] = nnode++;
+        nodes.push_back(m[K * D + i] >= 0 ? id : (id | kPatchFixed));  // constrained: coordinates only
       }
-      lmap[at(pid, sl, D, i)] = li;
+      lmap[at(pid, sl, D, i)] = (uint16_t)loc[id];
     }
-    for (int j = 0; j < 24; j++) pgeo[at(pid, sl, 24, j)] = geo[K * 24 + j];
+    if (!XYZ)
+      for (int j = 0; j < 24; j++) pgeo[at(pid, sl, 24, j)] = geo[K * 24 + j];
     if (op->has_coef)
       for (int j = 0; j < 8; j++) pcoef[at(pid, sl, 8, j)] = cf[K * 8 + j];
   }
   if (pid >= 0) nptr.push_back((int32_t)nodes.size());
   const int np = pid + 1;
-  // nodes that more than one patch touches are written with atomics (stored as -1-id)
+  // nodes that more than one patch touches are written with atomics
   std::vector<uint8_t> cnt((size_t)sp->nnodes, 0);
-  for (int32_t id : nodes) cnt[id] = (uint8_t)std::min(2, cnt[id] + 1);
+  for (int32_t e : nodes) cnt[e & kPatchIdMask] = (uint8_t)std::min(2, cnt[e & kPatchIdMask] + 1);
   int max_nodes = 0;
   for (int p = 0; p < np; p++) max_nodes = std::max(max_nodes, nptr[p + 1] - nptr[p]);
-  for (int32_t &id : nodes)
-    if (cnt[id] > 1) id = -1 - id;
+  for (int32_t &e : nodes)
+    if (cnt[e & kPatchIdMask] > 1) e |= kPatchShared;
   op->npatch = np;
   op->pt_max_nodes = max_nodes;
   op->pt_cap = cap;
   int rc = upload(op->pt_nptr, nptr.data(), nptr.size() * sizeof(int32_t), s);
   if (!rc) rc = upload(op->pt_nodes, nodes.data(), nodes.size() * sizeof(int32_t), s);
   if (!rc) rc = upload(op->pt_lmap, lmap.data(), lmap.size() * sizeof(uint16_t), s);
-  if (!rc) rc = upload(op->pt_geo, pgeo.data(), pgeo.size() * sizeof(T), s);
+  if (!rc && XYZ) rc = upload(op->pt_xyz, xyz.data(), xyz.size() * sizeof(double), s);
+  if (!rc && !XYZ) rc = upload(op->pt_geo, pgeo.data(), pgeo.size() * sizeof(T), s);
   if (!rc && op->has_coef) rc = upload(op->pt_coef, pcoef.data(), pcoef.size() * sizeof(T), s);
   std::vector<int32_t> gn;
   if (!rc && !to_pos2.empty()) {  // gather positions after the first permutation stage
     gn.resize(nodes.size());
-    for (size_t i = 0; i < nodes.size(); i++) gn[i] = to_pos2[nodes[i] < 0 ? -1 - nodes[i] : nodes[i]];
+    for (size_t i = 0; i < nodes.size(); i++) gn[i] = to_pos2[nodes[i] & kPatchIdMask];
     rc = upload(op->pt_gnodes, gn.data(), gn.size() * sizeof(int32_t), s);
   }
   if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
@@ -448,7 +472,7 @@ static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     if (rc) return rc;
   }
-  if (op->patched) return setup_hex_patches<T>(op, sp, m, to_pos2, geo, cf, s);
+  if (op->patched) return setup_hex_patches<T>(op, sp, m, to_pos2, geo, cf, pr->scatter == MF_SCATTER_PATCH, s);
   return MF_OK;
 }
 
@@ -535,7 +559,10 @@ static void count_work(mf_op *op) {
     const double geo = grad ? 39.0 : 24.0;
     const double pw = (grad ? 39.0 : 0.0) * comps + (mass ? 4.0 * comps : 0.0);
     fl = nc * (contr + q3 * (geo + pw));
-    by += nc * 24.0 * s + (op->has_coef ? nc * 8.0 * s : 0.0);
+    // geometry: 24 stored values per cell, or (Q1 patch kernel in FP64) the FP64
+    // coordinates of the vertices, once per vertex
+    const bool xyz = op->patched && op->precision == MF_F64;
+    by += (xyz ? 24.0 * (double)op->nnodes : nc * 24.0 * s) + (op->has_coef ? nc * 8.0 * s : 0.0);
   } else if (op->cell_type == MF_CELL_TET) {
     const double D = op->D, Q = op->nqp;
     // per point per component: reference gradient 6D, its push-forward 18, stress 8,
@@ -587,7 +614,8 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
     if (op->patched) {
       HexPatchArgs<T> a{op->pt_nptr.as<int32_t>(), op->pt_nodes.as<int32_t>(),
                         fused ? op->pt_gnodes.as<int32_t>() : nullptr, op->pt_lmap.as<uint16_t>(),
-                        op->pt_geo.as<T>(), op->has_coef ? op->pt_coef.as<T>() : nullptr, x, y, op->npatch,
+                        op->pt_xyz.as<double>(), op->pt_geo.as<T>(), op->has_coef ? op->pt_coef.as<T>() : nullptr,
+                        x, y, op->npatch,
                         op->pt_max_nodes, op->ncomp, op->pt_cap};
       rc = launch_hex_patches<T>(op->degree + 1, op->kind, a, s);
     } else if (op->coloured) {

@@ -90,19 +90,24 @@ template <typename T> struct HexArgs {
 
 // Q1 patch decomposition (full applies of degree-1 hex operators): patches of up to
 // cap <= kPatchCells cells (a multiple of 64, the same for all patches of an
-// operator) with at most kPatchNodes distinct free nodes. Per-slot arrays are
-// block-interleaved with cap slots per patch: entry e of slot s of patch p at
-// ((p * cap / 64 + s / 64) * E + e) * 64 + s % 64; empty slots and constrained
-// nodes have local index kPatchEmpty. (The same scheme around the pencil stages for
-// higher degrees measured slower than the atomic and coloured launches.)
+// operator) with at most kPatchNodes distinct nodes (the cells' vertices). Per-slot
+// arrays are block-interleaved with cap slots per patch: entry e of slot s of patch
+// p at ((p * cap / 64 + s / 64) * E + e) * 64 + s % 64; empty slots have local index
+// kPatchEmpty. A patch node entry is the internal node id with flags: kPatchShared
+// (another patch touches the node: written with a device atomic) and kPatchFixed
+// (constrained: gathered as 0, never written; its coordinates are still needed).
+// (The same scheme around the pencil stages for higher degrees measured slower than
+// the atomic and coloured launches.)
 constexpr int kPatchCells = 512, kPatchNodes = 1024, kPatchThreads = 256;
 constexpr uint16_t kPatchEmpty = 0xFFFF;
+constexpr int32_t kPatchShared = 1 << 30, kPatchFixed = 1 << 29, kPatchIdMask = kPatchFixed - 1;
 template <typename T> struct HexPatchArgs {
   const int32_t *node_ptr;  // npatch + 1 offsets into nodes
-  const int32_t *nodes;     // internal node ids; -1-id for nodes other patches also touch
+  const int32_t *nodes;     // internal node ids with the kPatchShared / kPatchFixed flags
   const int32_t *gnodes;    // if set: gather positions of the nodes in x (else their ids)
-  const uint16_t *lmap;     // per slot, 8 local node indices
-  const T *geo;             // per slot, 24 geometry entries (c1..c7 x3, pad)
+  const uint16_t *lmap;     // per slot, 8 local node indices (local node v = vertex v)
+  const double *xyz;        // FP64 operators: per internal node, 3 vertex coordinates
+  const T *geo;             // FP32 operators: per slot, 24 geometry entries (c1..c7 x3, pad)
   const T *coef;            // per slot, 8 coefficient entries, or null
   const T *x;
   T *y;
@@ -211,7 +216,7 @@ struct mf_op {
   mf::DeviceBuffer map, geo, coef, tab, bc_dofs;  // map and bc_dofs in internal numbering
   mf::DeviceBuffer q1map, q1geo, q1coef;          // degree-1 hex: map, geometry, coefficient in
                                                   // blocks of 64 cells, [cell/64][entry][cell%64]
-  mf::DeviceBuffer pt_nptr, pt_nodes, pt_lmap, pt_geo, pt_coef;  // degree-1 hex patches
+  mf::DeviceBuffer pt_nptr, pt_nodes, pt_lmap, pt_xyz, pt_geo, pt_coef;  // degree-1 hex patches
   // hex, user numbering: x is gathered straight from the first stage of the two-stage
   // permutation (positions to2 of the map's nodes), which saves the second stage
   mf::DeviceBuffer gmap, pt_gnodes;
