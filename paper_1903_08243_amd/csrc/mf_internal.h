@@ -115,6 +115,9 @@ template <typename T> struct HexPatchArgs {
 };
 // N = 2 only (the lane-per-cell Q1 kernel).
 template <typename T> int launch_hex_patches(int N, int kind, const HexPatchArgs<T> &a, hipStream_t s);
+// N = 2, one colour's cells (no two share a node): the lane-per-cell kernel over the
+// block-interleaved arrays (hex_q1_kernels.hip)
+template <typename T> int launch_hex_q1_coloured(int kind, const HexArgs<T> &a, hipStream_t s);
 
 // Kernel launchers (hex_kernels.hip)
 // atomic: scatter with device-scope atomics (any cell set); otherwise plain
