@@ -100,8 +100,11 @@ def measured_traffic():
             parts = line.strip().split(": ", 1)
             if len(parts) == 2:
                 kv[parts[0]] = parts[1]
-        src = os.path.join(ROOT, kv["kernel_source"])
-        if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv["kernel_source_sha256"]:
+        # the sources the kernel is built from, hashed as one concatenation in order
+        h = hashlib.sha256()
+        for src in kv["kernel_source"].split(","):
+            h.update(open(os.path.join(ROOT, src.strip()), "rb").read())
+        if h.hexdigest() != kv["kernel_source_sha256"]:
             return None
         return float(kv["traffic_bytes_per_launch"])
     except (OSError, KeyError, ValueError):
