@@ -65,6 +65,25 @@ def test_cg_matches_dense_solve(mf, refined, kind, dirichlet):
         assert info["outer_iterations"] >= 2
 
 
+@pytest.mark.parametrize("refined", [False, True])
+@pytest.mark.parametrize("kind,dirichlet", [(1, False), (3, True)], ids=["helmholtz", "poisson-dirichlet"])
+def test_cg_with_q1_patch_scatter(mf, refined, kind, dirichlet):
+    """CG on Q1 operators that use the patch scatter (accumulating internal applies inside
+    the captured iteration) against the dense solve."""
+    import torch
+    space, coef, mask, b, xs = _problem(kind=kind, k=1, m=8, dirichlet=dirichlet)
+    sp = mf.Space.from_meshgen(space)
+    P = mf.SCATTER_PATCH
+    A64 = mf.Operator(sp, kind, mf.F64, vertex_coef=coef, dirichlet=mask, scatter=P)
+    A32 = mf.Operator(sp, kind, mf.F32, vertex_coef=coef, dirichlet=mask, scatter=P) if refined else None
+    M = mf.JacobiPrecond(A64)
+    bt = torch.tensor(b, device="cuda")
+    x = torch.zeros_like(bt)
+    info = mf.cg_solve(A64, bt, x, A32=A32, precond=M, rtol=1e-10)
+    assert info["rc"] == 0 and info["rel_residual"] <= 1e-10
+    assert np.abs(x.cpu().numpy() - xs).max() <= 1e-8 * np.abs(xs).max()
+
+
 def test_cg_nonzero_initial_guess_and_restart(mf):
     import torch
     space, coef, mask, b, xs = _problem(kind=1, k=3, m=4)
