@@ -257,6 +257,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   // One batch of EPB cells per call: map, geometry and the first component's
   // gathers are issued together, then each component is processed in turn.
   int idx_cur[N], gidx[N];  // scatter (internal node) and gather positions
+  int first = 0x7fffffff;   // nodes from this id up are first touched by this cell
   {
     const int64_t c = A.c0 + b * EPB + le;
     bool ok = c < A.c1;
@@ -264,6 +265,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       const int64_t u = A.cell_user[c];
       ok = u >= A.ulo && u < A.uhi;
     }
+    if (!ATOMIC && ok && A.first) first = A.first[c];
     const int64_t off = (ok ? c : A.c0) * N3 + pa + N * pb;
 #pragma unroll
     for (int l = 0; l < N; l++) idx_cur[l] = ok ? A.map[off + NN * l] : -1;
@@ -297,8 +299,10 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   for (int l = 0; l < N; l++) r[l] = gidx[l] >= 0 ? A.x[(int64_t)gidx[l] * nc + comp] : T(0);
   if constexpr (!ATOMIC) {
     // no other cell of this launch touches these nodes: read y now, write it at the end
+    // (nodes this cell touches first are stored without reading)
 #pragma unroll
-    for (int l = 0; l < N; l++) yv[l] = (!mirror && idx_cur[l] >= 0) ? A.y[(int64_t)idx_cur[l] * nc + comp] : T(0);
+    for (int l = 0; l < N; l++)
+      yv[l] = (!mirror && idx_cur[l] >= 0 && idx_cur[l] < first) ? A.y[(int64_t)idx_cur[l] * nc + comp] : T(0);
   }
   hex_pencil_stages<T, N, KIND, WPB>(r, Gc, u0, u1, u2, pa, pb, STORE);
 #pragma unroll

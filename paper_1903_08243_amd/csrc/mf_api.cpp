@@ -584,14 +584,14 @@ static void count_work(mf_op *op) {
 // through gmap (hex pencil kernel only).
 template <typename T>
 static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool atomic, const int32_t *filt,
-                       int64_t ulo, int64_t uhi, hipStream_t s, bool fused = false) {
+                       int64_t ulo, int64_t uhi, hipStream_t s, bool fused = false, bool first = false) {
   if (op->cell_type == MF_CELL_HEX) {
     // the coloured degree-1 kernel reads the block-interleaved copies
     const bool q1 = op->degree == 1 && !atomic;
     if (fused && q1) return fail(MF_EINVAL, "internal: fused gather with the coloured Q1 kernel");
     HexArgs<T> a{(q1 ? op->q1map : op->map).as<int32_t>(), (q1 ? op->q1geo : op->geo).as<T>(),
                  op->has_coef ? (q1 ? op->q1coef : op->coef).as<T>() : nullptr, x, y, c0, c1, op->ncomp, filt, ulo,
-                 uhi, fused ? op->gmap.as<int32_t>() : nullptr};
+                 uhi, fused ? op->gmap.as<int32_t>() : nullptr, first ? op->first_lo.as<int32_t>() : nullptr};
     return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
@@ -606,7 +606,11 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
 template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool acc,
                                             bool bc, hipStream_t s, bool fused = false) {
   int rc = MF_OK;
-  if (!acc) {
+  // A full colour-by-colour overwrite apply with first-touch thresholds writes every
+  // free node and clears nothing; constrained rows are then written by the copy below.
+  const bool first = !acc && c0 == 0 && c1 == op->ncells && op->coloured && !op->patched && op->first_ok &&
+                     (op->n_bc_dofs == 0 || bc);
+  if (!acc && !first) {
     rc = launch_fill<T>(y, T(0), op->ndofs, s);
     if (rc) return rc;
   }
@@ -621,7 +625,8 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
     } else if (op->coloured) {
       // one launch per colour: cells of a colour share no node, so no atomics
       for (size_t c = 0; c + 1 < op->colour_ptr.size() && !rc; c++)
-        rc = cell_launch<T>(op, op->colour_ptr[c], op->colour_ptr[c + 1], x, y, false, nullptr, 0, 0, s, fused);
+        rc = cell_launch<T>(op, op->colour_ptr[c], op->colour_ptr[c + 1], x, y, false, nullptr, 0, 0, s, fused,
+                            first);
     } else {
       rc = cell_launch<T>(op, 0, op->ncells, x, y, true, nullptr, 0, 0, s, fused);
     }
@@ -762,6 +767,37 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     op->patched = true;
   }
   if (op->patched) op->coloured = false;
+  if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured) {
+    // First-touch thresholds for overwrite applies (HexArgs::first). Colours are
+    // launched in internal cell order, so a node's first toucher is the first cell in
+    // that order that lists it. The threshold form needs every later toucher to see the
+    // node below its cell's threshold, and every free node needs a first toucher.
+    std::vector<int32_t> lo((size_t)nc, INT32_MAX);
+    std::vector<uint8_t> seen((size_t)sp->nnodes, 0);
+    bool ok = true;
+    for (int64_t K = 0; K < nc && ok; K++) {
+      int32_t mn = INT32_MAX, old = -1;
+      for (int i = 0; i < D; i++) {
+        const int32_t n = m[K * D + i];
+        if (n < 0) continue;
+        if (!seen[n]) {
+          seen[n] = 1;
+          mn = std::min(mn, n);
+        } else {
+          old = std::max(old, n);
+        }
+      }
+      lo[K] = mn;
+      ok = old < mn;
+    }
+    for (int64_t n = 0; n < sp->nnodes && ok; n++) ok = seen[n] || flag((int32_t)n) < 0;
+    if (ok) {
+      rc = upload(op->first_lo, lo.data(), lo.size() * sizeof(int32_t), s);
+      if (rc) return rc;
+      MF_HIP(hipStreamSynchronize(s));
+      op->first_ok = true;
+    }
+  }
   std::vector<int32_t> to_pos2, gm;  // second-stage positions of the user -> internal permutation
   if (!op->identity) {
     rc = upload(op->perm, sp->user_of_int.data(), sp->user_of_int.size() * sizeof(int32_t), s);

@@ -86,6 +86,11 @@ template <typename T> struct HexArgs {
   // if set (pencil kernel only): x is gathered at these positions instead of at map
   // (same layout as map; negative = constrained), e.g. a half-permuted input
   const int32_t *gmap;
+  // if set (pencil kernel, colour-by-colour overwrite applies only): per internal cell
+  // the lowest node id that the cell touches first in launch order. Nodes are numbered
+  // by first touch, so the cell touches node n first exactly when n >= first[cell]:
+  // it then stores its contribution without reading y, which needs no prior clearing.
+  const int32_t *first;
 };
 
 // Q1 patch decomposition (full applies of degree-1 hex operators): patches of up to
@@ -224,6 +229,10 @@ struct mf_op {
   // permutation (positions to2 of the map's nodes), which saves the second stage
   mf::DeviceBuffer gmap, pt_gnodes;
   bool fused_gather = false;
+  // first-touch thresholds (HexArgs::first) of a coloured pencil-kernel operator, and
+  // whether every node without a constraint is first touched by some cell
+  mf::DeviceBuffer first_lo;
+  bool first_ok = false;
   int npatch = 0, pt_max_nodes = 0, pt_cap = 0;
   bool patched = false;  // full applies use the patch kernel
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)

@@ -80,6 +80,55 @@ def test_hex_scatter_modes(mf, k, scatter, prec, kind, ncomp):
     assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
 
 
+@pytest.mark.parametrize("dirichlet", [False, True])
+@pytest.mark.parametrize("k,kind,ncomp", [(2, 2, 3), (4, 1, 1), (3, 3, 1)], ids=["lap3-q2", "helm-q4", "pois-q3"])
+def test_hex_coloured_overwrite_writes_every_entry(mf, k, kind, ncomp, dirichlet):
+    """Coloured overwrite applies store each node's first contribution without reading y
+    and clear nothing: every entry of a NaN-filled output must be written, through the
+    user-numbered apply (constrained rows copied), the internal apply, the cell-range
+    apply (which clears) and the accumulating apply."""
+    import torch
+    print(f"hex first-touch k={k} kind={kind} ncomp={ncomp} dirichlet={dirichlet}", flush=True)
+    mesh = mg.hex_mesh(6, 0.15, config=1, seed_k=k)
+    space = mg.hex_space(mesh, k, ncomp=ncomp, config=1)
+    coef = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if kind in (0, 3) else None
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
+    orc = oracle.OracleOp(space, kind, coef=coef)
+    mask = None
+    bnd = np.zeros(0, np.int64)
+    if dirichlet:
+        bnd = space.boundary_nodes()
+        mask = np.zeros(space.nnodes, np.uint8)
+        mask[bnd] = 1
+    xm = x.reshape(-1, ncomp).copy()
+    xm[bnd] = 0.0
+    ref_free = orc.apply(xm.ravel()).reshape(-1, ncomp)
+    ref = ref_free.copy()
+    ref[bnd] = x.reshape(-1, ncomp)[bnd]  # identity rows
+    ref_range = ref_free.copy()
+    ref_range[bnd] = 0.0  # constrained rows are not written by the cell kernels
+    sp = mf.Space.from_meshgen(space)
+    op = mf.Operator(sp, kind, mf.F64, vertex_coef=coef, dirichlet=mask, scatter=mf.SCATTER_COLOURED)
+    xt = torch.tensor(x, device="cuda")
+    nan = lambda: torch.full_like(xt, float("nan"))
+    y = op.apply(xt, nan()).cpu().numpy()
+    assert np.isfinite(y).all() and _relerr(y, ref.ravel()) <= 1e-12
+    y = op.apply_range(0, op.info["ncells"], xt, nan()).cpu().numpy()
+    assert np.isfinite(y).all() and _relerr(y, ref_range.ravel()) <= 1e-12
+    # internal numbering: permute with the space's own maps
+    perm = torch.tensor(sp.internal_to_user(), device="cuda", dtype=torch.long)
+    xi = xt.view(-1, ncomp)[perm].reshape(-1).contiguous()
+    yi = op.apply_internal(xi, torch.full_like(xi, float("nan"))).view(-1, ncomp)
+    yu = torch.empty_like(yi)
+    yu[perm] = yi
+    yu = yu.reshape(-1).cpu().numpy()
+    assert np.isfinite(yu).all() and _relerr(yu, ref.ravel()) <= 1e-12
+    # accumulating: y0 + A x
+    y0 = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k + 100)
+    y = op.apply_range(0, op.info["ncells"], xt, torch.tensor(y0, device="cuda"), accumulate=True).cpu().numpy()
+    assert _relerr(y, y0 + ref_range.ravel()) <= 1e-12
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("m", [6, 20])
 @pytest.mark.parametrize("kind,ncomp", [(1, 1), (2, 3), (3, 1), (0, 1)],
