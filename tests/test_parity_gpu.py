@@ -230,6 +230,33 @@ def test_tet_elasticity_dirichlet_rows(mf, k, prec):
     assert _relerr(y, ref.ravel()) <= TOL[prec]
 
 
+@pytest.mark.parametrize("dirichlet", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [2, 3])
+def test_tet_coloured_overwrite_writes_every_entry(mf, k, prec, dirichlet):
+    """Coloured tet launches store first-touched nodes without reading y and clear
+    nothing: a NaN-filled output is fully written (constrained rows by the copy)."""
+    import torch
+    print(f"tet first-touch k={k} prec={prec} dirichlet={dirichlet}", flush=True)
+    mesh = mg.tet_mesh(3, 0.2, config=2)
+    space = mg.tet_space(mesh, k, ncomp=3, config=2)
+    bnd = space.boundary_nodes() if dirichlet else np.zeros(0, np.int64)
+    mask = None
+    if dirichlet:
+        mask = np.zeros(space.nnodes, np.uint8)
+        mask[bnd] = 1
+    x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+    xm = x.reshape(-1, 3).copy()
+    xm[bnd] = 0.0
+    ref = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=1.0, mu=0.5).apply(xm.ravel()).reshape(-1, 3)
+    ref[bnd] = x.reshape(-1, 3)[bnd]
+    op = mf.Operator(mf.Space.from_meshgen(space), 4, prec, lam=1.0, mu=0.5, dirichlet=mask,
+                     scatter=mf.SCATTER_COLOURED)
+    xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+    y = op.apply(xt, torch.full_like(xt, float("nan"))).double().cpu().numpy()
+    assert np.isfinite(y).all() and _relerr(y, ref.ravel()) <= TOL[prec]
+
+
 @pytest.mark.parametrize("prec", [0, 1])
 def test_tri_mass_action(mf, prec):
     mesh = mg.tri_mesh(20, 0.2, config=0)  # 800 cells
