@@ -175,6 +175,9 @@ typedef struct {
   double bytes_per_apply; /* algorithmic HBM bytes of one action (perfect caching) */
   int cell_launches;      /* cell-kernel launches per full action (colours, or 1) */
   int ncolours;           /* colours of the space's cell colouring */
+  int clears_output;      /* 1: an overwrite apply clears y in a pass of its own before the
+                             cell launches; 0: the launches write every entry themselves
+                             (coloured hex k >= 2: each node's first contribution is stored) */
 } mf_op_info;
 
 int mf_op_get_info(const mf_op *op, mf_op_info *info);

@@ -962,6 +962,7 @@ int mf_op_get_info(const mf_op *op, mf_op_info *info) {
   info->bytes_per_apply = op->bytes;
   info->ncolours = (int)op->colour_ptr.size() - 1;
   info->cell_launches = op->coloured ? info->ncolours : 1;
+  info->clears_output = op->first_ok ? 0 : 1;
   return MF_OK;
 }
 

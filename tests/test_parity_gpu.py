@@ -109,6 +109,8 @@ def test_hex_coloured_overwrite_writes_every_entry(mf, k, kind, ncomp, dirichlet
     ref_range[bnd] = 0.0  # constrained rows are not written by the cell kernels
     sp = mf.Space.from_meshgen(space)
     op = mf.Operator(sp, kind, mf.F64, vertex_coef=coef, dirichlet=mask, scatter=mf.SCATTER_COLOURED)
+    assert op.info["clears_output"] == 0
+    assert mf.Operator(sp, kind, mf.F64, vertex_coef=coef, scatter=mf.SCATTER_ATOMIC).info["clears_output"] == 1
     xt = torch.tensor(x, device="cuda")
     nan = lambda: torch.full_like(xt, float("nan"))
     y = op.apply(xt, nan()).cpu().numpy()
