@@ -128,18 +128,27 @@ template <> struct Mfma16<double> {
   }
 };
 
+// One wavefront per 16 cells (a quarter of a 64-cell layout block); a workgroup holds
+// blockDim.x / 64 consecutive quarters (1 or 4; the wavefronts share nothing but cache
+// lines). A colour of the 48^3 x 6 workload holds about 21,000 cells: 4-wavefront groups
+// give about 335 workgroups for 256 CUs, one-wavefront groups about 1,300, which spread
+// more evenly (P2: 362 -> 327 us in FP64); P3 in FP64 (two wavefronts per SIMD) runs
+// faster with the four quarters of a layout block on one CU (737 against 832 us).
 template <typename T, int K, int NQ, bool ATOMIC>
 __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<T> A) {
   using MF = Mfma16<T>;
   using V4 = typename MF::V;
   constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
   constexpr int NR = (NQ + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wpg = blockDim.x >> 6;
   const int j = lane & 15, g = lane >> 4;
-  const int64_t nbt = (A.c1 + 63) / 64 - A.c0 / 64, per = (nbt + 7) / 8;
-  const int64_t bl = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (bl >= nbt) return;  // uniform over the workgroup
-  const int64_t batch = A.c0 / 64 + bl;
+  // workgroup units of wpg quarters; contiguous ranges of units per XCD
+  const int64_t nqb = 4 * ((A.c1 + 63) / 64 - A.c0 / 64), nbu = (nqb + wpg - 1) / wpg, per = (nbu + 7) / 8;
+  const int64_t bu = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t qb = bu * wpg + (threadIdx.x >> 6);
+  if (bu >= nbu || qb >= nqb) return;  // no barriers: wavefronts may leave on their own
+  const int64_t batch = A.c0 / 64 + qb / 4;
+  const int w = (int)(qb % 4);
   const int cl = 16 * w + j;
   const int64_t cell = batch * 64 + cl;
   bool valid = cell >= A.c0 && cell < A.c1;
@@ -290,8 +299,11 @@ static int launch_tet_kq(const TetArgs<T> &a, hipStream_t s, bool diag, bool ato
   dim3 grid((unsigned)(diag ? b1 - b0 : ((b1 - b0 + 7) / 8) * 8)), block(192);
   if constexpr (K >= 2) {
     if (!diag) {
-      if (atomic) tet_elasticity_mfma_kernel<T, K, NQ, true><<<grid, dim3(256), 0, s>>>(a);
-      else tet_elasticity_mfma_kernel<T, K, NQ, false><<<grid, dim3(256), 0, s>>>(a);
+      const int wpg = (K == 3 && sizeof(T) == 8) ? 4 : 1;  // wavefronts (16 cells each) per group
+      const int64_t nbu = (4 * (b1 - b0) + wpg - 1) / wpg;
+      const dim3 gq((unsigned)(((nbu + 7) / 8) * 8)), bq(64 * wpg);
+      if (atomic) tet_elasticity_mfma_kernel<T, K, NQ, true><<<gq, bq, 0, s>>>(a);
+      else tet_elasticity_mfma_kernel<T, K, NQ, false><<<gq, bq, 0, s>>>(a);
       MF_HIP(hipGetLastError());
       return MF_OK;
     }
