@@ -175,9 +175,11 @@ typedef struct {
   double bytes_per_apply; /* algorithmic HBM bytes of one action (perfect caching) */
   int cell_launches;      /* cell-kernel launches per full action (colours, or 1) */
   int ncolours;           /* colours of the space's cell colouring */
-  int clears_output;      /* 1: an overwrite apply clears y in a pass of its own before the
-                             cell launches; 0: the launches write every entry themselves
-                             (coloured hex k >= 2: each node's first contribution is stored) */
+  int clears_output;      /* 1: mf_op_apply / mf_op_apply_internal clear y in a pass of their
+                             own before the cell launches; 0: the launches write every entry
+                             themselves (coloured hex k >= 2: each node's first contribution
+                             is stored). Overwriting range applies of an operator with
+                             constrained nodes always clear. */
 } mf_op_info;
 
 int mf_op_get_info(const mf_op *op, mf_op_info *info);
