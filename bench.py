@@ -122,7 +122,7 @@ def cpu_baseline(mg, cases, budget_s=30.0):
     import oracle
     nthreads = oracle.default_threads()
     tot_dofs, tot_t = 0.0, 0.0
-    frac = 0.75  # about 13 s of oracle work on 16 host threads
+    frac = 0.75  # about 11 s of oracle work on 16 host threads
     samples = []
     for ent in cases:
         sp = ent["space"]
