@@ -254,6 +254,8 @@ def bench_cg(mf, mg, k=3, m=32):
     M = mf.JacobiPrecond(A64)
     b = torch.tensor(mg.uniform(space.ndofs, -1, 1, 3, mg.PURPOSE_RHS, k), device="cuda")
     out = {"problem": f"Helmholtz Q{k}, {m}^3 perturbed renumbered hex, {space.ndofs} dofs, Jacobi"}
+    xref = torch.zeros_like(b)  # reference: FP64 Jacobi-CG to 1e-13 (untimed)
+    mf.cg_solve(A64, b, xref, precond=M, rtol=1e-13, maxit=20000, raise_on_error=False)
     for name, a32 in (("fp64", None), ("fp32_refined", A32)):
         x = torch.zeros_like(b)
         mf.cg_solve(A64, b, x, A32=a32, precond=M, rtol=1e-10)  # warm (graph capture, caches)
@@ -264,7 +266,8 @@ def bench_cg(mf, mg, k=3, m=32):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         out[name] = {"seconds": dt, "iterations": info["inner_iterations"], "outer": info["outer_iterations"],
-                     "rel_residual": info["rel_residual"]}
+                     "rel_residual": info["rel_residual"],
+                     "rel_error_vs_1e-13_solution": float((x - xref).norm() / xref.norm())}
     return out
 
 
@@ -384,6 +387,9 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, levels=7, steps=800, lr=1e-3, train_
     del R
     torch.cuda.empty_cache()
     b = rhs(0)
+    # reference solution: FP64 Jacobi-CG to 1e-13 (untimed)
+    xref = torch.zeros_like(b)
+    mf.cg_solve(A64, b, xref, precond=J, rtol=1e-13, maxit=200000, raise_on_error=False)
     for name, a32, prec in (("jacobi_fp64", None, J), ("jacobi_fp32_refined", A32, J),
                             ("learned_fp32_refined", A32, M), ("learned_fp64", None, M)):
         x = torch.zeros_like(b)
@@ -395,7 +401,8 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, levels=7, steps=800, lr=1e-3, train_
         torch.cuda.synchronize()
         out[name] = {"seconds": time.perf_counter() - t0, "iterations": info["inner_iterations"],
                      "outer": info["outer_iterations"], "fallbacks": info["fallbacks"],
-                     "rel_residual": info["rel_residual"]}
+                     "rel_residual": info["rel_residual"],
+                     "rel_error_vs_1e-13_solution": float((x - xref).norm() / xref.norm())}
         log(f"  c5 {name}: {json.dumps(out[name])}")
     return out
 
