@@ -292,6 +292,14 @@ def bench_c4(mf, mg, nsys=64, seed=0, m_lo=8, m_hi=40):
         sy.append((A64, A32, M, b))
     ndofs = sum(int(s[3].numel()) for s in sy)
     out = {"systems": nsys, "total_dofs": ndofs, "mesh_m": [int(v) for v in ms], "degree": [int(v) for v in ks]}
+    # reference solutions: FP64 Jacobi-CG to 1e-13 (untimed)
+    xref = [torch.zeros_like(s[3]) for s in sy]
+    for (A64, A32, M, b), x in zip(sy, xref):
+        mf.cg_solve(A64, b, x, precond=M, rtol=1e-13, maxit=20000, raise_on_error=False)
+
+    def max_err(xs):
+        return max(float((x - xr).norm() / xr.norm()) for x, xr in zip(xs, xref))
+
     cache = os.path.join(tempfile.gettempdir(), "mf_batch_tuning.txt")
     for name, refined in (("batched_fp32_refined", True), ("batched_fp64", False)):
         xs = [torch.zeros_like(s[3]) for s in sy]
@@ -311,6 +319,7 @@ def bench_c4(mf, mg, nsys=64, seed=0, m_lo=8, m_hi=40):
         out[name] = {"seconds": dt, "rc": rc, "max_rel_residual": max(i["rel_residual"] for i in infos),
                      "max_inner_iterations": max(i["inner_iterations"] for i in infos),
                      "max_outer": max(i["outer_iterations"] for i in infos),
+                     "max_rel_error_vs_1e-13_solution": max_err(xs),
                      "tuning_items_per_grid": list(tune), "autotune_seconds": t_tune}
         del B
     xs = [torch.zeros_like(s[3]) for s in sy]
@@ -324,7 +333,8 @@ def bench_c4(mf, mg, nsys=64, seed=0, m_lo=8, m_hi=40):
     torch.cuda.synchronize()
     out["sequential_fp64"] = {"seconds": time.perf_counter() - t0,
                               "max_rel_residual": max(i["rel_residual"] for i in res),
-                              "max_iterations": max(i["inner_iterations"] for i in res)}
+                              "max_iterations": max(i["inner_iterations"] for i in res),
+                              "max_rel_error_vs_1e-13_solution": max_err(xs)}
     return out
 
 
