@@ -142,12 +142,16 @@ def measured_traffic():
 
 def cpu_baseline(mg, cases, budget_s=30.0):
     """The oracle (dense, FP64, all host cores) on a bounded sample: a contiguous
-    slice of cells of every headline operator, scaled to GDoF/s by the slice fraction."""
+    slice of cells of every headline operator, scaled to GDoF/s by the slice fraction.
+    Outside the timed oracle calls, the GPU applies the same cell range to the same x
+    (both precisions); the largest relative max-norm difference is returned as well."""
     import oracle
+    import torch
     nthreads = oracle.default_threads()
     tot_dofs, tot_t = 0.0, 0.0
     frac = 0.75  # about 11 s of oracle work on 16 host threads
     samples = []
+    err = {0: 0.0, 1: 0.0}
     for ent in cases:
         sp = ent["space"]
         orc = oracle.OracleOp(sp, ent["kind"])
@@ -155,17 +159,24 @@ def cpu_baseline(mg, cases, budget_s=30.0):
         nc = orc.ncells
         c1 = max(1, int(nc * frac))
         t0 = time.perf_counter()
-        orc.apply(x, cells=(0, c1), nthreads=nthreads)
+        ref = orc.apply(x, cells=(0, c1), nthreads=nthreads)
         dt = time.perf_counter() - t0
+        for prec, (op, xt, yt) in ent["ops"].items():
+            y = op.apply_range(0, c1, xt, yt).double().cpu().numpy()
+            err[prec] = max(err[prec], float(np.abs(y - ref).max() / np.abs(ref).max()))
         tot_dofs += ent["ndofs"] * (c1 / nc)
         tot_t += dt
         samples.append(ent["name"])
         if tot_t > budget_s:
             break
-    return {"value": tot_dofs / tot_t / 1e9, "unit": "GDoF/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"cells [0, {frac:g} ncells) of each of {len(samples)} headline operators "
-                      f"({samples[0]}..{samples[-1]}), dofs scaled by the cell fraction; "
-                      f"{tot_t:.1f} s of CPU work"}
+    cpu = {"value": tot_dofs / tot_t / 1e9, "unit": "GDoF/s", "cores": nthreads, "kind": "oracle",
+           "sample": f"cells [0, {frac:g} ncells) of each of {len(samples)} headline operators "
+                     f"({samples[0]}..{samples[-1]}), dofs scaled by the cell fraction; "
+                     f"{tot_t:.1f} s of CPU work"}
+    parity = {"operators": len(samples), "cells": f"[0, {frac:g} ncells)",
+              "max_rel_error_fp64": err[0], "max_rel_error_fp32": err[1],
+              "tolerance_fp64": 1e-12, "tolerance_fp32": 1e-5}
+    return cpu, parity
 
 
 def bench_simplex(mf, mg, reps=20):
@@ -602,11 +613,12 @@ def main():
         log(f"  cg: {json.dumps(extra['cg'])}")
     except Exception as ex:  # reported, never silently replaced
         extra["cg"] = {"error": repr(ex)}
-    cpu = None
+    cpu, parity = None, None
     if not args.no_cpu:
         log("timing the CPU oracle on a bounded sample ...")
-        cpu = cpu_baseline(mg, cases)
-        log(f"  cpu oracle: {cpu['value']:.4f} GDoF/s on {cpu['cores']} threads")
+        cpu, parity = cpu_baseline(mg, cases)
+        log(f"  cpu oracle: {cpu['value']:.4f} GDoF/s on {cpu['cores']} threads; GPU against it: "
+            f"{parity['max_rel_error_fp64']:.2e} (fp64), {parity['max_rel_error_fp32']:.2e} (fp32)")
     n_ops = len(cases)
     if not args.quick and not args.no_c4:
         del cases  # free the headline operators before the batched workload
@@ -639,7 +651,7 @@ def main():
                                "32^3 hex of the unit cube perturbed +-0.15h, random node renumbering",
                    "cells": 32768, "degrees": degrees, "operators_per_step": n_ops,
                    "dofs_per_step": dofs_per_step},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "parity_vs_oracle": parity,
         "internal_numbering": {"value": value_int, "unit": "GDoF/s", "ms_per_step": t_int * 1e3,
                                "note": "same step with vectors in the library's cell-order node numbering "
                                        "(no boundary permutation), as used inside CG"},
