@@ -7,10 +7,13 @@ renumbered, Q_k on GLL nodes for k = 1..6 with (k+1)^3 Gauss points. One step
 applies all 18 operators once (y = A x, inputs resident in HBM); `value` is
 total DoFs processed per second (GDoF/s).
 
-Also reported (outside the timed steps): per-operator GDoF/s and roofline
-fractions in FP64 and FP32, the P1 triangle mass and tet elasticity actions,
-CG time to 1e-10 (FP64 Jacobi-CG vs FP32-action iterative refinement), and
-the CPU oracle timed on a bounded sample of the same workload.
+Also reported (outside the timed steps): per-operator kernel time (mean, min and
+median of 5 runs of 20 applies; FP64 also with cold caches), GDoF/s and roofline
+fractions in FP64 and FP32, the P1 triangle mass and tet elasticity actions, CG time
+to 1e-10 (FP64 Jacobi-CG vs FP32-action iterative refinement, with the error against
+a 1e-13 solution), the batched and learned-preconditioner solves, the CPU oracle timed
+on a bounded sample of the same workload, and the GPU's difference from the oracle on
+that sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 """
@@ -564,9 +567,11 @@ def main():
         row = {"name": ent["name"], "ndofs": ent["ndofs"]}
         for prec, tag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
             op, x, y = ent["ops"][prec]
-            t = time_kernel(op, x, y, reps=20)
+            runs = [time_kernel(op, x, y, reps=20) for _ in range(5)]  # 5 runs of 20 applies
+            t = float(np.mean(runs))
             r = roof(op, t, prec)
-            row[tag] = {"us": t * 1e6, "gdofs": ent["ndofs"] / t / 1e9, "frac": r["frac"], "bound": r["bound"],
+            row[tag] = {"us": t * 1e6, "us_min": min(runs) * 1e6, "us_median": float(np.median(runs)) * 1e6,
+                        "gdofs": ent["ndofs"] / t / 1e9, "frac": r["frac"], "bound": r["bound"],
                         "tflops": r["tflops"], "gbs": r["gbs"]}
             if prec == mf.F64:
                 row[tag]["us_cold"] = time_kernel_cold(op, x, y, flush) * 1e6
