@@ -30,6 +30,9 @@ import numpy as np
 from . import tables
 
 OP_MASS, OP_HELMHOLTZ, OP_LAPLACIAN, OP_POISSON, OP_ELASTICITY = range(5)
+# St-Venant-Kirchhoff: tangent at a field u0 (bilinear in the trial field) and the
+# nonlinear residual form itself (supplementary operator list, "hyperelasticity")
+OP_HYPERELASTIC, OP_HYPER_RESIDUAL = 5, 6
 CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -54,7 +57,7 @@ def _load():
         common = [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                   ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
-                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p]
+                  ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
         _lib.oracle_apply.argtypes = common + [ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
         _lib.oracle_diagonal.argtypes = common + [ctypes.c_long, ctypes.c_long, ctypes.c_void_p,
@@ -79,6 +82,9 @@ def simplex_quad_degree(kind: int, k: int, has_coef: bool) -> int:
     """Polynomial degree of the integrand on an affine simplex (so that the
     collapsed rule integrates it exactly and the result is rule-independent)."""
     c = 1 if has_coef else 0
+    if kind in (OP_HYPERELASTIC, OP_HYPER_RESIDUAL):
+        # grad u0 has degree k-1, S degree 2(k-1), dF S and F dS degree 3(k-1), times grad v
+        return 4 * (k - 1)
     if kind == OP_MASS:
         return 2 * k + c
     if kind == OP_HELMHOLTZ:
@@ -95,9 +101,13 @@ class OracleOp:
     a collapsed Gauss rule exact for the integrand.
     """
 
-    def __init__(self, space, kind, lam=1.0, mu=0.5, coef=None, nq1d=None):
+    def __init__(self, space, kind, lam=1.0, mu=0.5, coef=None, nq1d=None, u0=None):
         mesh = space.mesh
         self.space, self.kind = space, kind
+        if kind in (OP_HYPERELASTIC, OP_HYPER_RESIDUAL):
+            assert mesh.cell_type == CELL_TET and space.ncomp == 3, "hyperelasticity: vector tets"
+        if kind == OP_HYPERELASTIC:
+            assert u0 is not None, "the tangent needs its linearisation point u0"
         self.lam, self.mu = float(lam), float(mu)
         k = space.degree
         if mesh.cell_type == CELL_HEX:
@@ -112,6 +122,7 @@ class OracleOp:
         self.c2v = c(mesh.cell2vert, np.int32)
         self.c2n = c(space.cell2node, np.int32)
         self.coef = None if coef is None else c(coef)
+        self.u0 = None if u0 is None else c(u0)
         self.gdim, self.nvc = mesh.gdim, mesh.cell2vert.shape[1]
         self.D, self.ncomp = self.c2n.shape[1], space.ncomp
         self.nq = self.qw.shape[0]
@@ -121,10 +132,11 @@ class OracleOp:
     def _common(self):
         return (self.gdim, self.nvc, _ptr(self.coords), _ptr(self.c2v), self.D, _ptr(self.c2n),
                 self.ncomp, self.nq, _ptr(self.qw), _ptr(self.vN), _ptr(self.vdN), _ptr(self.phi),
-                _ptr(self.dphi), self.kind, self.lam, self.mu, _ptr(self.coef))
+                _ptr(self.dphi), self.kind, self.lam, self.mu, _ptr(self.coef), _ptr(self.u0))
 
     def apply(self, x, cells=None, nthreads=None):
-        """y = A x (overwrites), optionally over the cell range [start, end) only."""
+        """y = A x (overwrites), optionally over the cell range [start, end) only. For
+        OP_HYPER_RESIDUAL, y is the residual vector r(x; phi_i) (nonlinear in x)."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         assert x.shape == (self.ndofs,)
         y = np.empty(self.ndofs)

@@ -23,6 +23,13 @@
  *   LAPLACIAN   f1_c = grad u_c  for each component            (int grad u : grad v)
  *   POISSON     f1 = coef * grad u                             (int kappa grad u . grad v)
  *   ELASTICITY  f1 = lambda tr(G) I + mu (G + G^T)             (int sigma(u) : grad v)
+ *   HYPERELASTIC  the St-Venant-Kirchhoff model of the supplementary operator list
+ *               (F = I + grad u0, E = (F^T F - I)/2, Psi = lambda/2 tr(E)^2 + mu tr(E^2),
+ *               S = dPsi/dE = lambda tr(E) I + 2 mu E, P = F S) linearised at a given
+ *               field u0: the directional derivative of P in the direction of the
+ *               trial field, f1 = dF S + F dS with dF = G, dE = (dF^T F + F^T dF)/2,
+ *               dS = lambda tr(dE) I + 2 mu dE
+ *   HYPER_RESIDUAL  the nonlinear form itself at u = x: f1 = P(I + G)   (int P : grad v)
  * The coefficient is a per-vertex field interpolated with the coordinate map's
  * vertex basis (linear on simplices, trilinear on hexahedra).
  *
@@ -37,7 +44,8 @@
 #include <omp.h>
 #endif
 
-enum { OP_MASS = 0, OP_HELMHOLTZ = 1, OP_LAPLACIAN = 2, OP_POISSON = 3, OP_ELASTICITY = 4 };
+enum { OP_MASS = 0, OP_HELMHOLTZ = 1, OP_LAPLACIAN = 2, OP_POISSON = 3, OP_ELASTICITY = 4,
+       OP_HYPERELASTIC = 5, OP_HYPER_RESIDUAL = 6 };
 enum { MODE_ACTION = 0, MODE_DIAG = 1 };
 
 #define MAXV 8
@@ -48,6 +56,7 @@ typedef struct {
   double lam, mu;
   const double *coords, *qw, *vN, *vdN, *phi, *dphi, *vcoef;
   const int *c2v, *c2n;
+  const double *u0; /* linearisation point of HYPERELASTIC (node-interleaved like x) */
 } problem;
 
 /* Jacobian J[a][b] = d x_a / d xi_b at quadrature point q; returns det J and
@@ -86,9 +95,17 @@ static double jacobian(const problem *P, const double *X, int q, double J[3][3],
   return det;
 }
 
-/* Pointwise fluxes (f0, f1) of the bilinear form for trial value u and gradient G. */
+/* Second Piola-Kirchhoff stress of the St-Venant-Kirchhoff model for a strain E. */
+static void svk_stress(const problem *P, double E[3][3], double S[3][3]) {
+  const double tr = E[0][0] + E[1][1] + E[2][2];
+  for (int i = 0; i < 3; i++)
+    for (int j = 0; j < 3; j++) S[i][j] = 2.0 * P->mu * E[i][j] + (i == j ? P->lam * tr : 0.0);
+}
+
+/* Pointwise fluxes (f0, f1) of the bilinear form for trial value u and gradient G;
+ * G0 is the gradient of the linearisation point u0 (HYPERELASTIC only). */
 static void pointwise(const problem *P, double coef, const double *u, double G[MAXC][3],
-                      double *f0, double f1[MAXC][3]) {
+                      double G0[MAXC][3], double *f0, double f1[MAXC][3]) {
   const int g = P->gdim, nc = P->ncomp;
   for (int c = 0; c < nc; c++) {
     f0[c] = 0.0;
@@ -120,6 +137,65 @@ static void pointwise(const problem *P, double coef, const double *u, double G[M
           f1[c][a] = P->mu * (G[c][a] + G[a][c]) + (c == a ? P->lam * tr : 0.0);
       break;
     }
+    case OP_HYPERELASTIC: {
+      /* F = I + grad u0; E = (F^T F - I)/2; S(E); dF = G; dE = (dF^T F + F^T dF)/2; dS(dE);
+       * f1 = dF S + F dS */
+      double F[3][3], E[3][3], S[3][3], dE[3][3], dS[3][3];
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) F[i][j] = (i == j ? 1.0 : 0.0) + G0[i][j];
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          double c = 0.0, d = 0.0;
+          for (int k = 0; k < 3; k++) {
+            c += F[k][i] * F[k][j];
+            d += G[k][i] * F[k][j] + F[k][i] * G[k][j];
+          }
+          E[i][j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
+          dE[i][j] = 0.5 * d;
+        }
+      svk_stress(P, E, S);
+      svk_stress(P, dE, dS);
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          double s = 0.0;
+          for (int k = 0; k < 3; k++) s += G[i][k] * S[k][j] + F[i][k] * dS[k][j];
+          f1[i][j] = s;
+        }
+      break;
+    }
+    case OP_HYPER_RESIDUAL: {
+      /* P = F S(E) with F = I + grad u, u = the trial field itself */
+      double F[3][3], E[3][3], S[3][3];
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) F[i][j] = (i == j ? 1.0 : 0.0) + G[i][j];
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          double c = 0.0;
+          for (int k = 0; k < 3; k++) c += F[k][i] * F[k][j];
+          E[i][j] = 0.5 * (c - (i == j ? 1.0 : 0.0));
+        }
+      svk_stress(P, E, S);
+      for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+          double s = 0.0;
+          for (int k = 0; k < 3; k++) s += F[i][k] * S[k][j];
+          f1[i][j] = s;
+        }
+      break;
+    }
+  }
+}
+
+/* Gradient of the linearisation point u0 at one point (zero when there is none). */
+static void grad_u0(const problem *P, long cell, const double *gphi, double G0[MAXC][3]) {
+  for (int c = 0; c < MAXC; c++)
+    for (int a = 0; a < 3; a++) G0[c][a] = 0.0;
+  if (!P->u0) return;
+  const int D = P->D, nc = P->ncomp;
+  for (int i = 0; i < D; i++) {
+    const long n = P->c2n[cell * D + i];
+    for (int c = 0; c < nc; c++)
+      for (int a = 0; a < P->gdim; a++) G0[c][a] += gphi[i * 3 + a] * P->u0[n * nc + c];
   }
 }
 
@@ -152,6 +228,8 @@ static void cell_kernel(const problem *P, long cell, const double *x, double *ou
         gphi[i * 3 + a] = s;
       }
     const double *ph = P->phi + (long)q * D;
+    double G0[MAXC][3];
+    grad_u0(P, cell, gphi, G0);
     if (mode == MODE_ACTION) {
       double u[MAXC] = {0}, G[MAXC][3] = {{0}}, f0[MAXC], f1[MAXC][3];
       for (int i = 0; i < D; i++)
@@ -159,7 +237,7 @@ static void cell_kernel(const problem *P, long cell, const double *x, double *ou
           u[c] += ph[i] * xe[i * nc + c];
           for (int a = 0; a < g; a++) G[c][a] += gphi[i * 3 + a] * xe[i * nc + c];
         }
-      pointwise(P, coef, u, G, f0, f1);
+      pointwise(P, coef, u, G, G0, f0, f1);
       for (int i = 0; i < D; i++)
         for (int c = 0; c < nc; c++) {
           double s = f0[c] * ph[i];
@@ -173,7 +251,7 @@ static void cell_kernel(const problem *P, long cell, const double *x, double *ou
           double u[MAXC] = {0}, G[MAXC][3] = {{0}}, f0[MAXC], f1[MAXC][3];
           u[c] = ph[i];
           for (int a = 0; a < g; a++) G[c][a] = gphi[i * 3 + a];
-          pointwise(P, coef, u, G, f0, f1);
+          pointwise(P, coef, u, G, G0, f0, f1);
           double s = f0[c] * ph[i];
           for (int a = 0; a < g; a++) s += f1[c][a] * gphi[i * 3 + a];
           ye[i * nc + c] += wdet * s;
@@ -218,11 +296,11 @@ static int run(const problem *P, long c0, long c1, long ndofs, const double *x, 
 #define PROBLEM_ARGS                                                                         \
   int gdim, int nvc, const double *coords, const int *c2v, int D, const int *c2n, int ncomp, \
       int nq, const double *qw, const double *vN, const double *vdN, const double *phi,     \
-      const double *dphi, int op, double lam, double mu, const double *vcoef
+      const double *dphi, int op, double lam, double mu, const double *vcoef, const double *u0
 
 #define FILL_PROBLEM                                                                        \
   problem P = {gdim, nvc, D, ncomp, nq, op, lam, mu, coords, qw, vN, vdN, phi, dphi, vcoef, \
-               c2v, c2n}
+               c2v, c2n, u0}
 
 /* y = A x over cells [c0, c1); y (ndofs) is overwritten. */
 int oracle_apply(PROBLEM_ARGS, long c0, long c1, long ndofs, const double *x, double *y,
@@ -264,12 +342,14 @@ int oracle_element_matrices(PROBLEM_ARGS, long ncells, double *out) {
           gphi[i * 3 + a] = s;
         }
       const double *ph = phi + (long)q * D;
+      double G0[MAXC][3];
+      grad_u0(&P, cell, gphi, G0);
       for (int j = 0; j < D; j++)
         for (int d = 0; d < nc; d++) {
           double u[MAXC] = {0}, G[MAXC][3] = {{0}}, f0[MAXC], f1[MAXC][3];
           u[d] = ph[j];
           for (int a = 0; a < g; a++) G[d][a] = gphi[j * 3 + a];
-          pointwise(&P, coef, u, G, f0, f1);
+          pointwise(&P, coef, u, G, G0, f0, f1);
           for (int i = 0; i < D; i++)
             for (int c = 0; c < nc; c++) {
               double s = f0[c] * ph[i];
