@@ -63,9 +63,16 @@ enum { MF_CELL_TRI = 0, MF_CELL_TET = 1, MF_CELL_HEX = 2 };
  *   LAPLACIAN   int grad u : grad v, ncomp 1 or 3 (paper: vector-valued)
  *   POISSON     int kappa grad u . grad v  (kappa: vertex coefficient)
  *   ELASTICITY  int sigma(u) : eps(v), sigma = 2 mu eps(u) + lambda tr(eps(u)) I;
- *               the paper's int eps(u):eps(v) is lambda = 0, mu = 1/2. */
+ *               the paper's int eps(u):eps(v) is lambda = 0, mu = 1/2.
+ *   HYPERELASTIC  the paper's hyperelasticity operator: the St-Venant-Kirchhoff
+ *               residual int P(u0) : grad v, P = F S, F = I + grad u0,
+ *               E = (F^T F - I)/2, S = lambda tr(E) I + 2 mu E, linearised at a given
+ *               displacement u0 (mf_op_params.u0): int (dF S + F dS) : grad v with
+ *               dF = grad u, dE = (dF^T F + F^T dF)/2, dS = lambda tr(dE) I + 2 mu dE.
+ *               Vector P1 and P2 tets (quadrature exact for the degree 4(k-1)
+ *               integrand). */
 enum { MF_OP_MASS = 0, MF_OP_HELMHOLTZ = 1, MF_OP_LAPLACIAN = 2, MF_OP_POISSON = 3,
-       MF_OP_ELASTICITY = 4 };
+       MF_OP_ELASTICITY = 4, MF_OP_HYPERELASTIC = 5 };
 
 enum { MF_F64 = 0, MF_F32 = 1 };
 
@@ -112,11 +119,14 @@ enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2, MF_S
 
 typedef struct {
   const double *vertex_coef; /* host, nverts; MASS coefficient c or POISSON kappa; NULL -> 1 */
-  double lambda, mu;         /* ELASTICITY Lame parameters */
+  double lambda, mu;         /* ELASTICITY and HYPERELASTIC Lame parameters */
   const uint8_t *dirichlet;  /* host, nnodes; nonzero marks a node whose every component is
                                 constrained: (A x)_b = x_b there, and constrained values are
                                 excluded from every other row. NULL -> no constraint. */
   int scatter;               /* MF_SCATTER_* */
+  const double *u0;          /* HYPERELASTIC: host, ndofs, user numbering (node-interleaved
+                                like x): the displacement the residual is linearised at,
+                                copied at create (constrained nodes included). Else ignored. */
 } mf_op_params;
 
 /* Create an operator. precision MF_F64 or MF_F32 (FP32 arithmetic with FP32
@@ -141,7 +151,7 @@ int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x
                       int accumulate, void *stream);
 
 /* d = diag(A) (ndofs, op precision); constrained dofs get 1. Used as the Jacobi
- * preconditioner. */
+ * preconditioner. MF_EUNSUPPORTED for HYPERELASTIC. */
 int mf_op_diagonal(const mf_op *op, void *d, void *stream);
 
 /* Internal cell order and numbering. Every space colours its cells greedily

@@ -12,7 +12,7 @@ import os
 import numpy as np
 
 CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
-MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY = range(5)
+MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY, HYPERELASTIC = range(6)
 F64, F32 = 0, 1
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED, SCATTER_PATCH = 0, 1, 2, 3
 _ERR = {-1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EMESH", -5: "ENOTCONV", -6: "EBREAKDOWN",
@@ -44,7 +44,7 @@ class _OpInfo(ctypes.Structure):
 
 class _OpParams(ctypes.Structure):
     _fields_ = [("vertex_coef", ctypes.c_void_p), ("lam", ctypes.c_double), ("mu", ctypes.c_double),
-                ("dirichlet", ctypes.c_void_p), ("scatter", ctypes.c_int)]
+                ("dirichlet", ctypes.c_void_p), ("scatter", ctypes.c_int), ("u0", ctypes.c_void_p)]
 
 
 class CGInfo(ctypes.Structure):
@@ -205,12 +205,14 @@ class Operator:
     """A matrix-free operator; apply() runs the HIP kernels on the current torch stream."""
 
     def __init__(self, space: Space, kind, precision=F64, nq1d=0, vertex_coef=None, lam=1.0, mu=0.5,
-                 dirichlet=None, scatter=SCATTER_AUTO, stream=None):
+                 dirichlet=None, scatter=SCATTER_AUTO, stream=None, u0=None):
         L = load_library()
         self._coef = None if vertex_coef is None else _np(vertex_coef, np.float64)
         self._bc = None if dirichlet is None else _np(dirichlet, np.uint8)
+        self._u0 = None if u0 is None else _np(u0, np.float64)
         pr = _OpParams(None if self._coef is None else self._coef.ctypes.data, lam, mu,
-                       None if self._bc is None else self._bc.ctypes.data, scatter)
+                       None if self._bc is None else self._bc.ctypes.data, scatter,
+                       None if self._u0 is None else self._u0.ctypes.data)
         h = ctypes.c_void_p()
         _check(L.mf_op_create(space.handle, kind, precision, nq1d, ctypes.byref(pr), _stream(stream),
                               ctypes.byref(h)))

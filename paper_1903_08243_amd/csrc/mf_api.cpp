@@ -476,10 +476,14 @@ static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   return MF_OK;
 }
 
-template <typename T> static int setup_tet(mf_op *op, const mf_space *sp, hipStream_t s) {
+template <typename T>
+static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
   const int k = sp->degree, D = sp->D;
   std::vector<double> pts, w, phi, dphi;
-  const int deg = 2 * k - 2;  // grad u . grad v on affine cells
+  const bool hyper = op->kind == MF_OP_HYPERELASTIC;
+  // integrand degree on affine cells: grad u . grad v; the hyperelastic tangent adds
+  // grad u0 three times (S is quadratic in it, then F S and F dS)
+  const int deg = hyper ? 4 * (k - 1) : 2 * k - 2;
   if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree");
   const int nq = (int)w.size();
   op->nqp = nq;
@@ -487,8 +491,9 @@ template <typename T> static int setup_tet(mf_op *op, const mf_space *sp, hipStr
   std::vector<T> tab;
   for (double v : dphi) tab.push_back((T)v);
   for (double v : w) tab.push_back((T)v);
-  if (k >= 2) {
-    // per-lane operands of the MFMA contractions, appended after the weights
+  if (k >= 2 || hyper) {
+    // per-lane operands of the MFMA contractions, appended after the weights (the
+    // hyperelastic tangent runs the MFMA kernel at every degree)
     std::vector<double> mt((size_t)tet_mfma_table_floats(k, nq));
     tet_mfma_tables(k, nq, dphi.data(), mt.data(), sizeof(T) == 8);
     for (double v : mt) tab.push_back((T)v);
@@ -496,6 +501,22 @@ template <typename T> static int setup_tet(mf_op *op, const mf_space *sp, hipStr
   int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
   if (rc) return rc;
   const int64_t nc = sp->ncells, nb = (nc + 63) / 64;
+  if (hyper) {
+    // linearisation point in internal numbering (every node, constrained ones included)
+    std::vector<T> u0((size_t)sp->nnodes * 3);
+    for (int64_t n = 0; n < sp->nnodes; n++)
+      for (int c = 0; c < 3; c++) u0[n * 3 + c] = (T)pr->u0[(int64_t)sp->user_of_int[n] * 3 + c];
+    rc = upload(op->u0, u0.data(), u0.size() * sizeof(T), s);
+    if (!rc && pr->dirichlet) {
+      // the map flags constrained nodes; u0 is gathered through an unflagged copy
+      std::vector<int32_t> um((size_t)nb * D * 64, -1);
+      for (int64_t K = 0; K < nc; K++)
+        for (int i = 0; i < D; i++) um[((K / 64) * D + i) * 64 + K % 64] = sp->cell2node_int[K * D + i];
+      rc = upload(op->u0map, um.data(), um.size() * sizeof(int32_t), s);
+    }
+    if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+    if (rc) return rc;
+  }
   std::vector<T> geo((size_t)nb * 10 * 64, T(0));
   for (int64_t K = 0; K < nc; K++) {
     const int32_t *cv = sp->cell2vert_int.data() + K * 4;
@@ -569,6 +590,12 @@ static void count_work(mf_op *op) {
     // P 20, test contraction 6D
     fl = nc * Q * 3.0 * (12.0 * D + 46.0);
     by += nc * 10.0 * s;
+    if (op->kind == MF_OP_HYPERELASTIC) {
+      // per point: the gradient of u0 (6D + 18 per component), F^T F and F^T dF (108),
+      // E, S and dS (63), dF S + F dS (108), minus the linear stress it replaces (24)
+      fl += nc * Q * (3.0 * (6.0 * D + 18.0) + 255.0);
+      by += 3.0 * (double)op->nnodes * s;  // u0 read once
+    }
   } else {
     fl = nc * 30.0;
     by += nc * 3.0 * s;
@@ -595,7 +622,7 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
-                 filt, ulo, uhi};
+                 filt, ulo, uhi, op->u0.as<T>(), op->u0map.as<int32_t>()};
     return launch_tet_elasticity<T>(op->degree, op->nqp, a, atomic, s);
   }
   TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), x, y, c0, c1, filt, ulo, uhi};
@@ -656,6 +683,7 @@ static bool default_coloured(const mf_op *op) {
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
+  if (op->kind == MF_OP_HYPERELASTIC) return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
   if (rc) return rc;
   if (op->cell_type == MF_CELL_HEX) {
@@ -683,20 +711,21 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
                  mf_op **out) {
   if (!sp || !out) return fail(MF_EINVAL, "mf_op_create: null argument");
   if (precision != MF_F64 && precision != MF_F32) return fail(MF_EINVAL, "mf_op_create: precision");
-  if (kind < MF_OP_MASS || kind > MF_OP_ELASTICITY) return fail(MF_EINVAL, "mf_op_create: operator kind");
-  mf_op_params defaults{nullptr, 1.0, 0.5, nullptr, MF_SCATTER_AUTO};
+  if (kind < MF_OP_MASS || kind > MF_OP_HYPERELASTIC) return fail(MF_EINVAL, "mf_op_create: operator kind");
+  mf_op_params defaults{nullptr, 1.0, 0.5, nullptr, MF_SCATTER_AUTO, nullptr};
   const mf_op_params *pr = params ? params : &defaults;
   hipStream_t s = (hipStream_t)stream;
   const int ct = sp->cell_type;
   // supported combinations
   bool ok = false;
   if (ct == MF_CELL_HEX)
-    ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3) : (kind != MF_OP_ELASTICITY && sp->ncomp == 1);
+    ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3) : (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else if (ct == MF_CELL_TET)
-    ok = kind == MF_OP_ELASTICITY && sp->ncomp == 3;
+    ok = (kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3;
   else
     ok = kind == MF_OP_MASS && sp->ncomp == 1;
   if (!ok) return fail(MF_EUNSUPPORTED, "mf_op_create: operator / cell / ncomp combination not built");
+  if (kind == MF_OP_HYPERELASTIC && !pr->u0) return fail(MF_EINVAL, "HYPERELASTIC needs u0 (linearisation point)");
   if (kind == MF_OP_POISSON && !pr->vertex_coef) return fail(MF_EINVAL, "POISSON needs vertex_coef (kappa)");
   if (pr->scatter < MF_SCATTER_AUTO || pr->scatter > MF_SCATTER_PATCH)
     return fail(MF_EINVAL, "mf_op_create: unknown scatter mode");
@@ -830,7 +859,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, to_pos2, s)
                              : setup_hex<float>(op.get(), sp, pr, m, to_pos2, s);
   else if (ct == MF_CELL_TET)
-    rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, s) : setup_tet<float>(op.get(), sp, s);
+    rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, pr, s) : setup_tet<float>(op.get(), sp, pr, s);
   else
     rc = precision == MF_F64 ? setup_tri<double>(op.get(), sp, pr, s) : setup_tri<float>(op.get(), sp, pr, s);
   if (rc) return rc;

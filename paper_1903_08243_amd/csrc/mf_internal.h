@@ -154,7 +154,12 @@ template <typename T> struct TetArgs {
   T lam, mu;
   const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
   int64_t ulo, uhi;
+  // HYPERELASTIC (else null): the linearisation point (internal numbering, like x) and
+  // the map it is gathered through (null: map; set when map flags constrained nodes)
+  const T *u0;
+  const int32_t *u0map;
 };
+// ELASTICITY, or HYPERELASTIC when a.u0 is set (k = 1, nq = 1 and k = 2, nq = 14)
 template <typename T>
 int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
@@ -238,6 +243,7 @@ struct mf_op {
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
   mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
   mf::DeviceBuffer to1, to2, from1, from2, wt;    // two-stage permutations (positions) and their buffer
+  mf::DeviceBuffer u0, u0map;                    // HYPERELASTIC linearisation point and its gather map
   mf::DeviceBuffer cell_user;                     // internal cell -> user cell (int32)
   std::vector<int64_t> colour_ptr;                // colour ranges of the internal cell order
   mf::DeviceBuffer wx, wy;                        // user-numbering workspaces (ndofs, op precision)

@@ -134,7 +134,11 @@ template <> struct Mfma16<double> {
 // give about 335 workgroups for 256 CUs, one-wavefront groups about 1,300, which spread
 // more evenly (P2: 362 -> 327 us in FP64); P3 in FP64 (two wavefronts per SIMD) runs
 // faster with the four quarters of a layout block on one CU (737 against 832 us).
-template <typename T, int K, int NQ, bool ATOMIC>
+// HYPER: the St-Venant-Kirchhoff tangent at A.u0 instead of linear elasticity: the
+// gradient of u0 at each point comes from the same forward contraction, and the flux
+// is dF S + F dS (F = I + grad u0, E = (F^T F - I)/2, S = lambda tr(E) I + 2 mu E,
+// dF = grad u, dE = (dF^T F + F^T dF)/2, dS = lambda tr(dE) I + 2 mu dE).
+template <typename T, int K, int NQ, bool ATOMIC, bool HYPER = false>
 __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<T> A) {
   using MF = Mfma16<T>;
   using V4 = typename MF::V;
@@ -174,6 +178,18 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
 #pragma unroll
     for (int c = 0; c < 3; c++) xv[s][c] = idx >= 0 ? A.x[3 * (int64_t)idx + c] : T(0);
   }
+  // the linearisation point at the same nodes (through the unflagged map if constrained)
+  T u0v[HYPER ? NS : 1][3];
+  if constexpr (HYPER) {
+    const int32_t *mq = (A.u0map ? A.u0map : A.map) + batch * (D * 64) + cl;
+#pragma unroll
+    for (int s = 0; s < NS; s++) {
+      const int i = 4 * s + g;
+      const int idx = (valid && i < D) ? mq[i * 64] : -1;
+#pragma unroll
+      for (int c = 0; c < 3; c++) u0v[s][c] = idx >= 0 ? A.u0[3 * (int64_t)idx + c] : T(0);
+    }
+  }
   V4 yacc[NT][3];
 #pragma unroll
   for (int t = 0; t < NT; t++)
@@ -181,14 +197,20 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
     for (int c = 0; c < 3; c++) yacc[t][c] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
   for (int r = 0; r < NR; r++) {
-    V4 gacc[3];
+    V4 gacc[3], g0acc[HYPER ? 3 : 1];
 #pragma unroll
     for (int c = 0; c < 3; c++) gacc[c] = V4{T(0), T(0), T(0), T(0)};
+    if constexpr (HYPER)
+#pragma unroll
+      for (int c = 0; c < 3; c++) g0acc[c] = V4{T(0), T(0), T(0), T(0)};
 #pragma unroll
     for (int s = 0; s < NS; s++) {
       const T av = fwd[(r * NS + s) * 64 + lane];
 #pragma unroll
       for (int c = 0; c < 3; c++) gacc[c] = MF::fma(av, xv[s][c], gacc[c]);
+      if constexpr (HYPER)
+#pragma unroll
+        for (int c = 0; c < 3; c++) g0acc[c] = MF::fma(av, u0v[s][c], g0acc[c]);
     }
     // point q = 4 r + g of this lane's cell: reference gradients gacc[c][a]
     const int q = 4 * r + g;
@@ -198,16 +220,59 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
     for (int c = 0; c < 3; c++)
 #pragma unroll
       for (int a = 0; a < 3; a++) gr[c][a] = gacc[c][0] * Ki[a] + gacc[c][1] * Ki[3 + a] + gacc[c][2] * Ki[6 + a];
-    const T tr = gr[0][0] + gr[1][1] + gr[2][2];
+    // flux f[c][a] against d v_c / d x_a
+    T f[3][3];
+    if constexpr (HYPER) {
+      T F[3][3], S[3][3], M[3][3];
+#pragma unroll
+      for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int a = 0; a < 3; a++)
+          F[c][a] = (c == a ? T(1) : T(0)) + g0acc[c][0] * Ki[a] + g0acc[c][1] * Ki[3 + a] + g0acc[c][2] * Ki[6 + a];
+      // S from E = (F^T F - I)/2; M = F^T dF, so dE = (M + M^T)/2
+      T trE = T(0);
+#pragma unroll
+      for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int jj = 0; jj < 3; jj++) {
+          T cc = T(0), mm = T(0);
+#pragma unroll
+          for (int k = 0; k < 3; k++) {
+            cc += F[k][i] * F[k][jj];
+            mm += F[k][i] * gr[k][jj];
+          }
+          const T e = T(0.5) * (cc - (i == jj ? T(1) : T(0)));
+          if (i == jj) trE += e;
+          S[i][jj] = T(2) * A.mu * e;
+          M[i][jj] = mm;
+        }
+      const T trM = M[0][0] + M[1][1] + M[2][2];
+#pragma unroll
+      for (int i = 0; i < 3; i++) S[i][i] += A.lam * trE;
+#pragma unroll
+      for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+          T v = T(0);
+#pragma unroll
+          for (int k = 0; k < 3; k++) {
+            const T dS = A.mu * (M[k][a] + M[a][k]) + (k == a ? A.lam * trM : T(0));
+            v += gr[i][k] * S[k][a] + F[i][k] * dS;
+          }
+          f[i][a] = v;
+        }
+    } else {
+      const T tr = gr[0][0] + gr[1][1] + gr[2][2];
+#pragma unroll
+      for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int a = 0; a < 3; a++) f[c][a] = A.mu * (gr[c][a] + gr[a][c]) + (a == c ? A.lam * tr : T(0));
+    }
     T P[3][3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      T sig[3];
+    for (int c = 0; c < 3; c++)
 #pragma unroll
-      for (int a = 0; a < 3; a++) sig[a] = A.mu * (gr[c][a] + gr[a][c]) + (a == c ? A.lam * tr : T(0));
-#pragma unroll
-      for (int d = 0; d < 3; d++) P[c][d] = wd * (sig[0] * Ki[3 * d + 0] + sig[1] * Ki[3 * d + 1] + sig[2] * Ki[3 * d + 2]);
-    }
+      for (int d = 0; d < 3; d++) P[c][d] = wd * (f[c][0] * Ki[3 * d + 0] + f[c][1] * Ki[3 * d + 1] + f[c][2] * Ki[3 * d + 2]);
 #pragma unroll
     for (int t = 0; t < NT; t++)
 #pragma unroll
@@ -323,7 +388,25 @@ static int launch_tet(int k, int nq, const TetArgs<T> &a, hipStream_t s, bool di
   return fail(MF_EUNSUPPORTED, "tet elasticity: degree / rule");
 }
 
+// St-Venant-Kirchhoff tangent: the MFMA kernel with HYPER for P1 (one point) and P2
+// (14 points, exact for the degree 4 integrand); one wavefront per workgroup.
+template <typename T, int K, int NQ>
+static int launch_tet_hyper_kq(const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  const int64_t b0 = a.c0 / 64, b1 = (a.c1 + 63) / 64;
+  if (a.c1 <= a.c0) return MF_OK;
+  const dim3 gq((unsigned)(((4 * (b1 - b0) + 7) / 8) * 8)), bq(64);
+  if (atomic) tet_elasticity_mfma_kernel<T, K, NQ, true, true><<<gq, bq, 0, s>>>(a);
+  else tet_elasticity_mfma_kernel<T, K, NQ, false, true><<<gq, bq, 0, s>>>(a);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
 template <typename T> int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  if (a.u0) {
+    if (k == 1 && nq == 1) return launch_tet_hyper_kq<T, 1, 1>(a, atomic, s);
+    if (k == 2 && nq == 14) return launch_tet_hyper_kq<T, 2, 14>(a, atomic, s);
+    return fail(MF_EUNSUPPORTED, "tet hyperelasticity: degree / rule");
+  }
   return launch_tet<T>(k, nq, a, s, false, atomic);
 }
 template <typename T> int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s) {
