@@ -225,6 +225,28 @@ def bench_simplex(mf, mg, reps=20):
             log(f"  {tag}: {json.dumps(out[tag])}")
             del op, xt, yt
         del sp, space
+    # the paper's hyperelasticity operator: the St-Venant-Kirchhoff tangent at a
+    # displacement u0 = 0.3 U[-1,1], P1 and P2 on the same mesh
+    for k in (1, 2):
+        space = mg.tet_space(mesh, k, config=2)
+        sp = mf.Space.from_meshgen(space)
+        x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+        u0 = 0.3 * mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_COEF, k)
+        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
+            op = mf.Operator(sp, mf.HYPERELASTIC, prec, lam=1.0, mu=0.5, u0=u0)
+            xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+            yt = torch.empty_like(xt)
+            t = time_kernel(op, xt, yt, reps)
+            F, B = op.info["flops_per_apply"], op.info["bytes_per_apply"]
+            P = PEAK_FP64 if prec == mf.F64 else PEAK_FP32
+            tag = f"tet_hyperelastic_p{k}_{ptag}"
+            out[tag] = {"cells": mesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
+                        "launches": op.info["cell_launches"], "qp": op.info["nqp"],
+                        "bound": "mfma", "tflops": F / t / 1e12,
+                        "frac": max(F / P, B / PEAK_HBM) / t, "gbs": B / t / 1e9}
+            log(f"  {tag}: {json.dumps(out[tag])}")
+            del op, xt, yt
+        del sp, space
     return out
 
 
