@@ -481,17 +481,35 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipS
   const int k = sp->degree, D = sp->D;
   std::vector<double> pts, w, phi, dphi;
   const bool hyper = op->kind == MF_OP_HYPERELASTIC;
-  // integrand degree on affine cells: grad u . grad v; the hyperelastic tangent adds
-  // grad u0 three times (S is quadratic in it, then F S and F dS)
-  const int deg = hyper ? 4 * (k - 1) : 2 * k - 2;
-  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree");
+  const bool scalar = sp->ncomp == 1;  // MASS, HELMHOLTZ, LAPLACIAN, POISSON
+  // integrand degree on affine cells: grad u . grad v (the hyperelastic tangent adds
+  // grad u0 three times: S is quadratic in it, then F S and F dS); u v for the value
+  // terms; one more with a (linearly interpolated) vertex coefficient
+  int deg = hyper ? 4 * (k - 1) : 2 * k - 2;
+  if (scalar) {
+    deg = (op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ) ? 2 * k : 2 * k - 2;
+    if (op->has_coef) deg += 1;
+  }
+  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rule table ends at 5)");
   const int nq = (int)w.size();
   op->nqp = nq;
   tet_lagrange(k, pts, phi, dphi);
   std::vector<T> tab;
-  for (double v : dphi) tab.push_back((T)v);
-  for (double v : w) tab.push_back((T)v);
-  if (k >= 2 || hyper) {
+  if (scalar) {
+    // phi [nq][D], reference gradients [nq][D][3], weights [nq], vertex basis [nq][4]
+    for (double v : phi) tab.push_back((T)v);
+    for (double v : dphi) tab.push_back((T)v);
+    for (double v : w) tab.push_back((T)v);
+    for (int q = 0; q < nq; q++) {
+      const double *x = &pts[3 * q];
+      tab.push_back((T)(1.0 - x[0] - x[1] - x[2]));
+      for (int a = 0; a < 3; a++) tab.push_back((T)x[a]);
+    }
+  } else {
+    for (double v : dphi) tab.push_back((T)v);
+    for (double v : w) tab.push_back((T)v);
+  }
+  if (!scalar && (k >= 2 || hyper)) {
     // per-lane operands of the MFMA contractions, appended after the weights (the
     // hyperelastic tangent runs the MFMA kernel at every degree)
     std::vector<double> mt((size_t)tet_mfma_table_floats(k, nq));
@@ -501,6 +519,16 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipS
   int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
   if (rc) return rc;
   const int64_t nc = sp->ncells, nb = (nc + 63) / 64;
+  if (scalar && op->has_coef) {
+    // vertex coefficients per cell, AoSoA [cell/64][4][64]
+    std::vector<T> cf((size_t)nb * 4 * 64, T(1));
+    for (int64_t K = 0; K < nc; K++)
+      for (int v = 0; v < 4; v++)
+        cf[((K / 64) * 4 + v) * 64 + K % 64] = (T)pr->vertex_coef[sp->cell2vert_int[K * 4 + v]];
+    rc = upload(op->coef, cf.data(), cf.size() * sizeof(T), s);
+    if (!rc) MF_HIP(hipStreamSynchronize(s));
+    if (rc) return rc;
+  }
   if (hyper) {
     // linearisation point in internal numbering (every node, constrained ones included)
     std::vector<T> u0((size_t)sp->nnodes * 3);
@@ -584,6 +612,14 @@ static void count_work(mf_op *op) {
     // coordinates of the vertices, once per vertex
     const bool xyz = op->patched && op->precision == MF_F64;
     by += (xyz ? 24.0 * (double)op->nnodes : nc * 24.0 * s) + (op->has_coef ? nc * 8.0 * s : 0.0);
+  } else if (op->cell_type == MF_CELL_TET && op->ncomp == 1) {
+    // scalar operators, dense tabulation, per point: value 2D and its test sum 2D;
+    // reference gradient 6D, push-forward 18, the reference-direction flux 18 (and a
+    // scale), test sum 6D; coefficient 8
+    const double D = op->D, Q = op->nqp;
+    const bool val = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ, grad = op->kind != MF_OP_MASS;
+    fl = nc * Q * ((val ? 4.0 * D + 3.0 : 0.0) + (grad ? 12.0 * D + 39.0 : 0.0) + (op->has_coef ? 8.0 : 0.0));
+    by += nc * 10.0 * s + (op->has_coef ? nc * 4.0 * s : 0.0);
   } else if (op->cell_type == MF_CELL_TET) {
     const double D = op->D, Q = op->nqp;
     // per point per component: reference gradient 6D, its push-forward 18, stress 8,
@@ -622,7 +658,9 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
-                 filt, ulo, uhi, op->u0.as<T>(), op->u0map.as<int32_t>()};
+                 filt, ulo, uhi, op->u0.as<T>(), op->u0map.as<int32_t>(),
+                 op->has_coef ? op->coef.as<T>() : nullptr};
+    if (op->ncomp == 1) return launch_tet_scalar<T>(op->degree, op->nqp, op->kind, a, atomic, s);
     return launch_tet_elasticity<T>(op->degree, op->nqp, a, atomic, s);
   }
   TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), x, y, c0, c1, filt, ulo, uhi};
@@ -683,7 +721,8 @@ static bool default_coloured(const mf_op *op) {
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
-  if (op->kind == MF_OP_HYPERELASTIC) return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC");
+  if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_TET && op->ncomp == 1))
+    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC or scalar tet operators");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
   if (rc) return rc;
   if (op->cell_type == MF_CELL_HEX) {
@@ -721,7 +760,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (ct == MF_CELL_HEX)
     ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3) : (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else if (ct == MF_CELL_TET)
-    ok = (kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3;
+    ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3) ||
+         (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else
     ok = kind == MF_OP_MASS && sp->ncomp == 1;
   if (!ok) return fail(MF_EUNSUPPORTED, "mf_op_create: operator / cell / ncomp combination not built");

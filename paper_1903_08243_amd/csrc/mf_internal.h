@@ -158,10 +158,17 @@ template <typename T> struct TetArgs {
   // the map it is gathered through (null: map; set when map flags constrained nodes)
   const T *u0;
   const int32_t *u0map;
+  // scalar operators (MASS, POISSON): AoSoA [ncells/64][4][64] vertex coefficients, or null
+  const T *coef;
 };
 // ELASTICITY, or HYPERELASTIC when a.u0 is set (k = 1, nq = 1 and k = 2, nq = 14)
 template <typename T>
 int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s);
+// one-component MASS, HELMHOLTZ, LAPLACIAN, POISSON on P1..P3 tets; tab holds phi
+// [nq][D], the reference gradients [nq][D][3], the weights [nq] and the vertex
+// basis [nq][4] at the points
+template <typename T>
+int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s);
 // Degree >= 2: the action runs on MFMA and needs these per-lane operands of the

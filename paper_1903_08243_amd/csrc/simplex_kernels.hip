@@ -95,6 +95,137 @@ __global__ void __launch_bounds__(192) tet_elasticity_kernel(const TetArgs<T> A)
   }
 }
 
+// ----------------------------------------------------------------- scalar tet operators
+// MASS int c u v, HELMHOLTZ int grad u . grad v + u v, LAPLACIAN int grad u . grad v,
+// POISSON int kappa grad u . grad v on affine tets (supplementary operator list), with
+// the vertex coefficient interpolated by the vertex basis. One lane per cell, one
+// wavefront per workgroup (64 cells of the AoSoA layout); the basis tables are the
+// same for every lane (scalar loads). Dense tabulation: simplices are not
+// sum-factorised.
+template <typename T, int K, int NQ, int KIND, bool ATOMIC>
+__global__ void __launch_bounds__(64) tet_scalar_kernel(const TetArgs<T> A) {
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
+  constexpr bool GRAD = KIND != MF_OP_MASS;
+  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
+  const int lane = threadIdx.x;
+  const int64_t nbt = (A.c1 + 63) / 64 - A.c0 / 64, per = (nbt + 7) / 8;
+  const int64_t bl = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (bl >= nbt) return;
+  const int64_t batch = A.c0 / 64 + bl;
+  const int64_t cell = batch * 64 + lane;
+  bool valid = cell >= A.c0 && cell < A.c1;
+  if (valid && A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    valid = u >= A.ulo && u < A.uhi;
+  }
+  const int32_t *mp = A.map + batch * (D * 64) + lane;
+  const T *gp = A.geo + batch * (10 * 64) + lane;
+  T Ki[9];
+#pragma unroll
+  for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
+  const T adet = gp[9 * 64];
+  T cv[4] = {T(1), T(1), T(1), T(1)};
+  if (COEF && A.coef)
+#pragma unroll
+    for (int v = 0; v < 4; v++) cv[v] = A.coef[(batch * 4 + v) * 64 + lane];
+  T xe[D], ye[D];
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int idx = valid ? mp[i * 64] : -1;
+    xe[i] = idx >= 0 ? A.x[idx] : T(0);
+    ye[i] = T(0);
+  }
+  const T *__restrict__ phi = A.tab;
+  const T *__restrict__ dphi = phi + NQ * D;
+  const T *__restrict__ qw = dphi + NQ * D * 3;
+  const T *__restrict__ vb = qw + NQ;
+  // kept rolled: unrolled, the table loads of every point are hoisted and spill
+#pragma unroll 1
+  for (int q = 0; q < NQ; q++) {
+    const T *pq = phi + q * D, *tq = dphi + q * D * 3;
+    const T wd = qw[q] * adet;
+    T cq = T(1);
+    if (COEF) cq = vb[4 * q] * cv[0] + vb[4 * q + 1] * cv[1] + vb[4 * q + 2] * cv[2] + vb[4 * q + 3] * cv[3];
+    T f0 = T(0), P0 = T(0), P1 = T(0), P2 = T(0);
+    if constexpr (VAL) {
+      T u = T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) u += xe[i] * pq[i];
+      f0 = wd * (KIND == MF_OP_MASS ? cq : T(1)) * u;
+    }
+    if constexpr (GRAD) {
+      T g0 = T(0), g1 = T(0), g2 = T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        g0 += xe[i] * tq[3 * i + 0];
+        g1 += xe[i] * tq[3 * i + 1];
+        g2 += xe[i] * tq[3 * i + 2];
+      }
+      // physical gradient G_a = sum_b g_b dxi_b/dx_a, flux f1 = (kappa) G, and its
+      // reference-direction form P_b = w |det| sum_a dxi_b/dx_a f1_a
+      const T s = wd * (KIND == MF_OP_POISSON ? cq : T(1));
+      T G[3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) G[a] = s * (g0 * Ki[a] + g1 * Ki[3 + a] + g2 * Ki[6 + a]);
+      P0 = G[0] * Ki[0] + G[1] * Ki[1] + G[2] * Ki[2];
+      P1 = G[0] * Ki[3] + G[1] * Ki[4] + G[2] * Ki[5];
+      P2 = G[0] * Ki[6] + G[1] * Ki[7] + G[2] * Ki[8];
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      T v = T(0);
+      if constexpr (VAL) v += f0 * pq[i];
+      if constexpr (GRAD) v += P0 * tq[3 * i + 0] + P1 * tq[3 * i + 1] + P2 * tq[3 * i + 2];
+      ye[i] += v;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int idx = valid ? mp[i * 64] : -1;
+    if (idx >= 0) {
+      if constexpr (ATOMIC) atomic_add_s(&A.y[idx], ye[i]);
+      else A.y[idx] += ye[i];  // cells of one launch share no node
+    }
+  }
+}
+
+template <typename T, int K, int NQ, int KIND>
+static int launch_tet_scalar_kq(const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  const int64_t nbt = (a.c1 + 63) / 64 - a.c0 / 64;
+  if (a.c1 <= a.c0) return MF_OK;
+  const dim3 g((unsigned)(((nbt + 7) / 8) * 8)), b(64);
+  if (atomic) tet_scalar_kernel<T, K, NQ, KIND, true><<<g, b, 0, s>>>(a);
+  else tet_scalar_kernel<T, K, NQ, KIND, false><<<g, b, 0, s>>>(a);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T, int K, int NQ>
+static int launch_tet_scalar_k(int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  switch (kind) {
+    case MF_OP_MASS: return launch_tet_scalar_kq<T, K, NQ, MF_OP_MASS>(a, atomic, s);
+    case MF_OP_HELMHOLTZ: return launch_tet_scalar_kq<T, K, NQ, MF_OP_HELMHOLTZ>(a, atomic, s);
+    case MF_OP_LAPLACIAN: return launch_tet_scalar_kq<T, K, NQ, MF_OP_LAPLACIAN>(a, atomic, s);
+    case MF_OP_POISSON: return launch_tet_scalar_kq<T, K, NQ, MF_OP_POISSON>(a, atomic, s);
+  }
+  return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
+}
+
+// rules of the tet quadrature table: 1 point (degree 1), 4 (degree 2), 14 (degree 5)
+template <typename T>
+int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  if (k == 1 && nq == 1) return launch_tet_scalar_k<T, 1, 1>(kind, a, atomic, s);
+  if (k == 1 && nq == 4) return launch_tet_scalar_k<T, 1, 4>(kind, a, atomic, s);
+  if (k == 1 && nq == 14) return launch_tet_scalar_k<T, 1, 14>(kind, a, atomic, s);
+  if (k == 2 && nq == 4) return launch_tet_scalar_k<T, 2, 4>(kind, a, atomic, s);
+  if (k == 2 && nq == 14) return launch_tet_scalar_k<T, 2, 14>(kind, a, atomic, s);
+  if (k == 3 && nq == 14) return launch_tet_scalar_k<T, 3, 14>(kind, a, atomic, s);
+  return fail(MF_EUNSUPPORTED, "tet scalar operator: degree / rule");
+}
+template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);
+template int launch_tet_scalar<float>(int, int, int, const TetArgs<float> &, bool, hipStream_t);
+
 // ----------------------------------------------------------------- tet elasticity on MFMA
 // Both contractions of the action are GEMMs over a batch of cells (the
 // tabulation of the reference gradients is shared by all cells):

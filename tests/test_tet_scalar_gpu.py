@@ -1,0 +1,108 @@
+"""GPU parity of the one-component operators on tetrahedra (mass with and without a
+vertex coefficient, Helmholtz, Laplacian, Poisson; P1..P3 wherever the tet rule table
+reaches the integrand degree) against the oracle, through the C-ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_08243_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+TOL = {0: 1e-12, 1: 1e-5}
+MASS, HELM, LAP, POIS = 0, 1, 2, 3
+# (kind, with a vertex coefficient): P3 mass and Helmholtz need a degree-6 rule
+CASES = [(k, kind, coef) for k in (1, 2, 3) for kind, coef in
+         ((MASS, False), (MASS, True), (HELM, False), (LAP, False), (POIS, True))
+         if not (k == 3 and kind in (MASS, HELM))]
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1903_08243_amd as m
+    m.load_library()
+    return m
+
+
+def _relerr(y, ref):
+    return np.abs(y - ref).max() / np.abs(ref).max()
+
+
+def _case(k, m=3):
+    mesh = mg.tet_mesh(m, 0.2, config=2, seed_k=k)  # 162 cells: a ragged 64-cell batch
+    space = mg.tet_space(mesh, k, ncomp=1, config=2, seed_k=k)
+    x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+    c = np.exp(np.random.default_rng(k).normal(size=mesh.nverts))
+    return mesh, space, x, c
+
+
+@pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k,kind,coef", CASES)
+def test_tet_scalar_action(mf, k, kind, coef, prec, scatter):
+    import torch
+    print(f"tet scalar k={k} kind={kind} coef={coef} prec={prec} scatter={scatter}", flush=True)
+    mesh, space, x, c = _case(k)
+    c = c if coef else None
+    ref = oracle.OracleOp(space, kind, coef=c).apply(x)
+    op = mf.Operator(mf.Space.from_meshgen(space), kind, prec, vertex_coef=c, scatter=scatter)
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_tet_scalar_dirichlet_and_range(mf, k):
+    """Poisson with constrained boundary nodes (identity rows, zero columns), and range
+    applies that add up to the full action."""
+    import torch
+    mesh, space, x, c = _case(k)
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    xm = x.copy()
+    xm[bnd] = 0.0
+    ref = oracle.OracleOp(space, POIS, coef=c).apply(xm)
+    ref[bnd] = x[bnd]
+    sp = mf.Space.from_meshgen(space)
+    op = mf.Operator(sp, POIS, mf.F64, vertex_coef=c, dirichlet=mask)
+    xt = torch.tensor(x, device="cuda")
+    assert _relerr(op.apply(xt).cpu().numpy(), ref) <= 1e-12
+    op2 = mf.Operator(sp, LAP, mf.F64)
+    nc = mesh.ncells
+    y = torch.zeros_like(xt)
+    for a, b in ((0, nc // 3), (nc // 3, nc)):
+        op2.apply_range(a, b, xt, y, accumulate=True)
+    full = oracle.OracleOp(space, LAP).apply(x)
+    assert _relerr(y.cpu().numpy(), full) <= 1e-12
+
+
+def test_tet_scalar_errors(mf):
+    mesh, space, x, c = _case(3, m=2)
+    sp = mf.Space.from_meshgen(space)
+    with pytest.raises(mf.MFError):
+        mf.Operator(sp, MASS, mf.F64)  # P3 mass: no degree-6 rule
+    with pytest.raises(mf.MFError):
+        mf.Operator(sp, LAP, mf.F64).diagonal()
+
+
+def test_tet_scalar_full_size_sampled(mf):
+    """48^3 x 6 tets, P2 Helmholtz, sampled outputs against the oracle on the cells
+    that touch them."""
+    import torch
+    mesh = mg.tet_mesh(48, 0.2, config=2)
+    space = mg.tet_space(mesh, 2, ncomp=1, config=2)
+    x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, 2)
+    rng = np.random.default_rng(0)
+    nodes = rng.choice(space.nnodes, size=100, replace=False)
+    touch = np.isin(space.cell2node, nodes).any(axis=1)
+    sub = mg.Space(mg.Mesh(mesh.cell_type, mesh.coords, mesh.cell2vert[touch], mesh.lattice_m, mesh.vert_ijk),
+                   2, 1, space.cell2node[touch], space.nnodes)
+    ref = oracle.OracleOp(sub, HELM).apply(x)
+    sp = mf.Space.from_meshgen(space)
+    for prec in (0, 1):
+        op = mf.Operator(sp, HELM, prec)
+        y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+        err = np.abs(y[nodes] - ref[nodes]).max() / np.abs(ref[nodes]).max()
+        assert err <= TOL[prec], (prec, err)
