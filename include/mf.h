@@ -135,6 +135,10 @@ typedef struct {
  * simplices ignore it and use a rule exact for the integrand. params may be
  * NULL (coefficient 1, lambda 1, mu 0.5, no constraints). stream: device
  * uploads are ordered on it; the call returns after they complete.
+ * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1) and LAPLACIAN
+ * (ncomp 1 or 3); tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
+ * HELMHOLTZ P1-P2, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules are exact to
+ * degree 5, which P3 mass and Helmholtz exceed); tri MASS P1.
  * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
 int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,
                  const mf_op_params *params, void *stream, mf_op **out);
