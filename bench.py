@@ -225,6 +225,26 @@ def bench_simplex(mf, mg, reps=20):
             log(f"  {tag}: {json.dumps(out[tag])}")
             del op, xt, yt
         del sp, space
+    # P2 / P3 triangles (lane per cell), 1024 x 1024 x 2 cells
+    tmesh = mg.tri_mesh(1024, 0.2, config=0)
+    for k, kind, name in ((2, mf.HELMHOLTZ, "helmholtz"), (3, mf.LAPLACIAN, "laplacian")):
+        space = mg.tri_space(tmesh, k)
+        sp = mf.Space.from_meshgen(space)
+        x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
+            op = mf.Operator(sp, kind, prec)
+            xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+            yt = torch.empty_like(xt)
+            t = time_kernel(op, xt, yt, reps)
+            r = roof(op, t, prec)
+            tag = f"tri_{name}_p{k}_{ptag}"
+            out[tag] = {"cells": tmesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
+                        "launches": op.info["cell_launches"], "qp": op.info["nqp"], "bound": r["bound"],
+                        "frac": r["frac"], "gbs": r["gbs"], "tflops": r["tflops"]}
+            log(f"  {tag}: {json.dumps(out[tag])}")
+            del op, xt, yt
+        del sp, space
+    del tmesh
     # one-component operators on the same tets (dense tabulation, lane per cell)
     for k, kind, name in ((1, mf.LAPLACIAN, "laplacian"), (2, mf.HELMHOLTZ, "helmholtz"),
                           (2, mf.LAPLACIAN, "laplacian"), (3, mf.LAPLACIAN, "laplacian")):

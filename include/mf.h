@@ -32,7 +32,8 @@
  *          Gauss-Lobatto-Legendre points, local id i + n*j + n*n*l, n = k+1;
  *     tet  vertices (0,0,0),(1,0,0),(0,1,0),(0,0,1); P_k nodes at the
  *          equispaced lattice points alpha/k, a1 fastest, then a2, then a3;
- *     tri  vertices (0,0),(1,0),(0,1); P1 nodes at the vertices.
+ *     tri  vertices (0,0),(1,0),(0,1); P_k nodes at the equispaced lattice points
+ *          alpha/k, a1 fastest.
  *   Vector fields are node-interleaved: dof = ncomp*node + component.
  */
 #ifndef MF_H
@@ -91,8 +92,8 @@ int mf_mesh_create(int cell_type, int64_t nverts, const double *coords, int64_t 
                    const int32_t *cell2vert, mf_mesh **out);
 
 /* Create a Lagrange space of the given degree (hex: Q_k on GLL nodes, k = 1..6;
- * tet: P_k equispaced, k = 1..3; tri: P1) with ncomp components.
- * cell2node: host, ncells x D (D = (k+1)^3 hex, (k+1)(k+2)(k+3)/6 tet, 3 tri),
+ * tet and tri: P_k equispaced, k = 1..3) with ncomp components.
+ * cell2node: host, ncells x D (D = (k+1)^3 hex, (k+1)(k+2)(k+3)/6 tet, (k+1)(k+2)/2 tri),
  * entries in [0, nnodes) -- the paper's cell2dof map (Section 2.2). The caller's
  * node numbering is kept at this boundary. Errors: MF_EINVAL, MF_EUNSUPPORTED. */
 int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *cell2node,
@@ -138,7 +139,8 @@ typedef struct {
  * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1) and LAPLACIAN
  * (ncomp 1 or 3); tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
  * HELMHOLTZ P1-P2, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules are exact to
- * degree 5, which P3 mass and Helmholtz exceed); tri MASS P1.
+ * degree 5, which P3 mass and Helmholtz exceed); tri MASS, HELMHOLTZ, LAPLACIAN and
+ * POISSON P1-P3 (ncomp 1).
  * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
 int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,
                  const mf_op_params *params, void *stream, mf_op **out);

@@ -163,8 +163,8 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
     if (degree < 1 || degree > 3) return fail(MF_EUNSUPPORTED, "tet spaces support degree 1..3");
     D = tet_ndofs(degree);
   } else {
-    if (degree != 1) return fail(MF_EUNSUPPORTED, "tri spaces support degree 1");
-    D = 3;
+    if (degree < 1 || degree > 3) return fail(MF_EUNSUPPORTED, "tri spaces support degree 1..3");
+    D = (degree + 1) * (degree + 2) / 2;
   }
   for (int64_t i = 0; i < mesh->ncells * D; i++)
     if (cell2node[i] < 0 || cell2node[i] >= nnodes)
@@ -573,7 +573,54 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipS
   return upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
 }
 
+// Triangles other than the closed-form P1 mass: tables (phi, reference gradients,
+// weights, vertex basis at the points of a collapsed rule exact for the integrand),
+// geometry [cell/64][5][64] (d xi_b / d x_a, |det J|), coefficients [cell/64][3][64].
+template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+  const int k = sp->degree;
+  int deg = (op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ) ? 2 * k : 2 * k - 2;
+  if (op->has_coef) deg += 1;
+  std::vector<double> pts, w, phi, dphi;
+  tri_rule(deg, pts, w);
+  tri_lagrange(k, pts, phi, dphi);
+  const int nq = (int)w.size();
+  op->nqp = nq;
+  std::vector<T> tab;
+  for (double v : phi) tab.push_back((T)v);
+  for (double v : dphi) tab.push_back((T)v);
+  for (double v : w) tab.push_back((T)v);
+  for (int q = 0; q < nq; q++) {
+    tab.push_back((T)(1.0 - pts[2 * q] - pts[2 * q + 1]));
+    tab.push_back((T)pts[2 * q]);
+    tab.push_back((T)pts[2 * q + 1]);
+  }
+  int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
+  if (rc) return rc;
+  const int64_t nc = sp->ncells, nb = (nc + 63) / 64;
+  std::vector<T> geo((size_t)nb * 5 * 64, T(0)), cf;
+  if (op->has_coef) cf.assign((size_t)nb * 3 * 64, T(1));
+  for (int64_t K = 0; K < nc; K++) {
+    const int32_t *cv = sp->cell2vert_int.data() + K * 3;
+    const double *p0 = &sp->coords[(int64_t)cv[0] * 2], *p1 = &sp->coords[(int64_t)cv[1] * 2],
+                 *p2 = &sp->coords[(int64_t)cv[2] * 2];
+    // J = [p1 - p0, p2 - p0] (columns); J^{-1}[b][a] = d xi_b / d x_a
+    const double j00 = p1[0] - p0[0], j01 = p2[0] - p0[0], j10 = p1[1] - p0[1], j11 = p2[1] - p0[1];
+    const double det = j00 * j11 - j01 * j10;
+    const double inv[4] = {j11 / det, -j01 / det, -j10 / det, j00 / det};
+    const int64_t b = K / 64, l = K % 64;
+    for (int m = 0; m < 4; m++) geo[(b * 5 + m) * 64 + l] = (T)inv[m];
+    geo[(b * 5 + 4) * 64 + l] = (T)std::fabs(det);
+    if (op->has_coef)
+      for (int v = 0; v < 3; v++) cf[(b * 3 + v) * 64 + l] = (T)pr->vertex_coef[cv[v]];
+  }
+  rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+  if (!rc && op->has_coef) rc = upload(op->coef, cf.data(), cf.size() * sizeof(T), s);
+  if (!rc) MF_HIP(hipStreamSynchronize(s));
+  return rc;
+}
+
 template <typename T> static int setup_tri(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+  if (!(op->kind == MF_OP_MASS && sp->degree == 1)) return setup_tri_pk<T>(op, sp, pr, s);
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 4, T(0));
   for (int64_t K = 0; K < nc; K++) {
@@ -632,6 +679,12 @@ static void count_work(mf_op *op) {
       fl += nc * Q * (3.0 * (6.0 * D + 18.0) + 255.0);
       by += 3.0 * (double)op->nnodes * s;  // u0 read once
     }
+  } else if (!(op->kind == MF_OP_MASS && op->degree == 1)) {
+    // triangles of degree k: per point value 4D + 3, gradient 8D + 17, coefficient 6
+    const double D = op->D, Q = op->nqp;
+    const bool val = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ, grad = op->kind != MF_OP_MASS;
+    fl = nc * Q * ((val ? 4.0 * D + 3.0 : 0.0) + (grad ? 8.0 * D + 17.0 : 0.0) + (op->has_coef ? 6.0 : 0.0));
+    by += nc * 5.0 * s + (op->has_coef ? nc * 3.0 * s : 0.0);
   } else {
     fl = nc * 30.0;
     by += nc * 3.0 * s;
@@ -662,6 +715,11 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
                  op->has_coef ? op->coef.as<T>() : nullptr};
     if (op->ncomp == 1) return launch_tet_scalar<T>(op->degree, op->nqp, op->kind, a, atomic, s);
     return launch_tet_elasticity<T>(op->degree, op->nqp, a, atomic, s);
+  }
+  if (!(op->kind == MF_OP_MASS && op->degree == 1)) {
+    TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, T(0), T(0),
+                 filt, ulo, uhi, nullptr, nullptr, op->has_coef ? op->coef.as<T>() : nullptr};
+    return launch_tri_scalar<T>(op->degree, op->nqp, op->kind, a, atomic, s);
   }
   TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), x, y, c0, c1, filt, ulo, uhi};
   return launch_tri_mass<T>(a, atomic, s);
@@ -721,8 +779,9 @@ static bool default_coloured(const mf_op *op) {
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
-  if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_TET && op->ncomp == 1))
-    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC or scalar tet operators");
+  if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_TET && op->ncomp == 1) ||
+      (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)))
+    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC or scalar tet / P2+ triangle operators");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
   if (rc) return rc;
   if (op->cell_type == MF_CELL_HEX) {
@@ -763,7 +822,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3) ||
          (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else
-    ok = kind == MF_OP_MASS && sp->ncomp == 1;
+    ok = kind <= MF_OP_POISSON && sp->ncomp == 1;
   if (!ok) return fail(MF_EUNSUPPORTED, "mf_op_create: operator / cell / ncomp combination not built");
   if (kind == MF_OP_HYPERELASTIC && !pr->u0) return fail(MF_EINVAL, "HYPERELASTIC needs u0 (linearisation point)");
   if (kind == MF_OP_POISSON && !pr->vertex_coef) return fail(MF_EINVAL, "POISSON needs vertex_coef (kappa)");
@@ -793,7 +852,9 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   // (internal node ids; the Dirichlet mask is given per user node)
   auto flag = [&](int32_t inode) { return (pr->dirichlet && pr->dirichlet[sp->user_of_int[inode]]) ? -1 : inode; };
   const std::vector<int32_t> &c2n = sp->cell2node_int;
-  if (ct == MF_CELL_TET) {
+  // the lane-per-cell simplex kernels read AoSoA maps (all but the closed-form P1
+  // triangle mass)
+  if (ct == MF_CELL_TET || (ct == MF_CELL_TRI && !(kind == MF_OP_MASS && sp->degree == 1))) {
     const int64_t nb = (nc + 63) / 64;
     m.assign((size_t)nb * D * 64, -1);
     for (int64_t K = 0; K < nc; K++)

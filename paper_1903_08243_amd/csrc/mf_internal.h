@@ -169,6 +169,11 @@ int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipSt
 // basis [nq][4] at the points
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s);
+// the same forms on P1..P3 triangles (TetArgs as a generic simplex argument block:
+// geo [cell/64][5][64], coef [cell/64][3][64], tab phi, gradients [nq][D][2], weights,
+// vertex basis [nq][3])
+template <typename T>
+int launch_tri_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s);
 // Degree >= 2: the action runs on MFMA and needs these per-lane operands of the

@@ -238,6 +238,126 @@ int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic,
 template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);
 template int launch_tet_scalar<float>(int, int, int, const TetArgs<float> &, bool, hipStream_t);
 
+// ----------------------------------------------------------------- scalar triangle operators
+// The same four one-component forms on affine triangles of degree K (the 2D version of
+// tet_scalar_kernel): geometry [cell/64][5][64] = d xi_b / d x_a (row-major, 4) and
+// |det J|; coefficients [cell/64][3][64]; tables phi [nq][D], reference gradients
+// [nq][D][2], weights [nq], vertex basis [nq][3]; nq is a run-time bound.
+template <typename T, int K, int KIND, bool ATOMIC>
+__global__ void __launch_bounds__(64) tri_scalar_kernel(const TetArgs<T> A, const int NQ) {
+  constexpr int D = (K + 1) * (K + 2) / 2;
+  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
+  constexpr bool GRAD = KIND != MF_OP_MASS;
+  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
+  const int lane = threadIdx.x;
+  const int64_t nbt = (A.c1 + 63) / 64 - A.c0 / 64, per = (nbt + 7) / 8;
+  const int64_t bl = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (bl >= nbt) return;
+  const int64_t batch = A.c0 / 64 + bl;
+  const int64_t cell = batch * 64 + lane;
+  bool valid = cell >= A.c0 && cell < A.c1;
+  if (valid && A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    valid = u >= A.ulo && u < A.uhi;
+  }
+  const int32_t *mp = A.map + batch * (D * 64) + lane;
+  const T *gp = A.geo + batch * (5 * 64) + lane;
+  T Ki[4];
+#pragma unroll
+  for (int m = 0; m < 4; m++) Ki[m] = gp[m * 64];
+  const T adet = gp[4 * 64];
+  T cv[3] = {T(1), T(1), T(1)};
+  if (COEF && A.coef)
+#pragma unroll
+    for (int v = 0; v < 3; v++) cv[v] = A.coef[(batch * 3 + v) * 64 + lane];
+  T xe[D], ye[D];
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int idx = valid ? mp[i * 64] : -1;
+    xe[i] = idx >= 0 ? A.x[idx] : T(0);
+    ye[i] = T(0);
+  }
+  const T *__restrict__ phi = A.tab;
+  const T *__restrict__ dphi = phi + NQ * D;
+  const T *__restrict__ qw = dphi + NQ * D * 2;
+  const T *__restrict__ vb = qw + NQ;
+#pragma unroll 1
+  for (int q = 0; q < NQ; q++) {
+    const T *pq = phi + q * D, *tq = dphi + q * D * 2;
+    const T wd = qw[q] * adet;
+    T cq = T(1);
+    if (COEF) cq = vb[3 * q] * cv[0] + vb[3 * q + 1] * cv[1] + vb[3 * q + 2] * cv[2];
+    T f0 = T(0), P0 = T(0), P1 = T(0);
+    if constexpr (VAL) {
+      T u = T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) u += xe[i] * pq[i];
+      f0 = wd * (KIND == MF_OP_MASS ? cq : T(1)) * u;
+    }
+    if constexpr (GRAD) {
+      T g0 = T(0), g1 = T(0);
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        g0 += xe[i] * tq[2 * i + 0];
+        g1 += xe[i] * tq[2 * i + 1];
+      }
+      const T s = wd * (KIND == MF_OP_POISSON ? cq : T(1));
+      const T G0 = s * (g0 * Ki[0] + g1 * Ki[2]), G1 = s * (g0 * Ki[1] + g1 * Ki[3]);
+      P0 = G0 * Ki[0] + G1 * Ki[1];
+      P1 = G0 * Ki[2] + G1 * Ki[3];
+    }
+#pragma unroll
+    for (int i = 0; i < D; i++) {
+      T v = T(0);
+      if constexpr (VAL) v += f0 * pq[i];
+      if constexpr (GRAD) v += P0 * tq[2 * i + 0] + P1 * tq[2 * i + 1];
+      ye[i] += v;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < D; i++) {
+    const int idx = valid ? mp[i * 64] : -1;
+    if (idx >= 0) {
+      if constexpr (ATOMIC) atomic_add_s(&A.y[idx], ye[i]);
+      else A.y[idx] += ye[i];  // cells of one launch share no node
+    }
+  }
+}
+
+template <typename T, int K, int KIND>
+static int launch_tri_scalar_kk(int nq, const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  const int64_t nbt = (a.c1 + 63) / 64 - a.c0 / 64;
+  if (a.c1 <= a.c0) return MF_OK;
+  const dim3 g((unsigned)(((nbt + 7) / 8) * 8)), b(64);
+  if (atomic) tri_scalar_kernel<T, K, KIND, true><<<g, b, 0, s>>>(a, nq);
+  else tri_scalar_kernel<T, K, KIND, false><<<g, b, 0, s>>>(a, nq);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T, int K>
+static int launch_tri_scalar_k(int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  switch (kind) {
+    case MF_OP_MASS: return launch_tri_scalar_kk<T, K, MF_OP_MASS>(nq, a, atomic, s);
+    case MF_OP_HELMHOLTZ: return launch_tri_scalar_kk<T, K, MF_OP_HELMHOLTZ>(nq, a, atomic, s);
+    case MF_OP_LAPLACIAN: return launch_tri_scalar_kk<T, K, MF_OP_LAPLACIAN>(nq, a, atomic, s);
+    case MF_OP_POISSON: return launch_tri_scalar_kk<T, K, MF_OP_POISSON>(nq, a, atomic, s);
+  }
+  return fail(MF_EUNSUPPORTED, "triangle scalar operator: kind");
+}
+
+template <typename T>
+int launch_tri_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  switch (k) {
+    case 1: return launch_tri_scalar_k<T, 1>(nq, kind, a, atomic, s);
+    case 2: return launch_tri_scalar_k<T, 2>(nq, kind, a, atomic, s);
+    case 3: return launch_tri_scalar_k<T, 3>(nq, kind, a, atomic, s);
+  }
+  return fail(MF_EUNSUPPORTED, "triangle scalar operator: degree");
+}
+template int launch_tri_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);
+template int launch_tri_scalar<float>(int, int, int, const TetArgs<float> &, bool, hipStream_t);
+
 // ----------------------------------------------------------------- tet elasticity on MFMA
 // Both contractions of the action are GEMMs over a batch of cells (the
 // tabulation of the reference gradients is shared by all cells):

@@ -220,4 +220,73 @@ void tet_lagrange(int k, const std::vector<double> &pts, std::vector<double> &ph
   }
 }
 
+// Triangle rule exact to the given degree: the Gauss product rule on the square mapped
+// by the collapse x = u, y = v (1 - u) (Jacobian 1 - u), n = ceil((degree + 2) / 2)
+// points per direction (the u-integrand gains one degree from the Jacobian).
+void tri_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
+  const int n = (degree + 3) / 2;
+  std::vector<double> x, wx;
+  gauss_legendre(n, x, wx);
+  pts.clear();
+  w.clear();
+  for (int i = 0; i < n; i++)
+    for (int j = 0; j < n; j++) {
+      pts.push_back(x[i]);
+      pts.push_back(x[j] * (1.0 - x[i]));
+      w.push_back(wx[i] * wx[j] * (1.0 - x[i]));
+    }
+}
+
+// P_k Lagrange basis on the reference triangle (equispaced lattice, a1 fastest) by
+// inverting the monomial Vandermonde matrix, as tet_lagrange in two dimensions.
+void tri_lagrange(int k, const std::vector<double> &pts, std::vector<double> &phi, std::vector<double> &dphi) {
+  const int D = (k + 1) * (k + 2) / 2;
+  std::vector<int> ex;  // monomial exponents (p, q)
+  for (int p = 0; p <= k; p++)
+    for (int q = 0; q + p <= k; q++) { ex.push_back(p); ex.push_back(q); }
+  std::vector<double> nodes;
+  for (int a2 = 0; a2 <= k; a2++)
+    for (int a1 = 0; a1 + a2 <= k; a1++) {
+      nodes.push_back((double)a1 / k);
+      nodes.push_back((double)a2 / k);
+    }
+  auto pw = [](double b, int e) { return e <= 0 ? 1.0 : std::pow(b, e); };
+  std::vector<double> A((size_t)D * 2 * D, 0.0);
+  for (int n = 0; n < D; n++) {
+    for (int m = 0; m < D; m++) A[n * 2 * D + m] = pw(nodes[2 * n], ex[2 * m]) * pw(nodes[2 * n + 1], ex[2 * m + 1]);
+    A[n * 2 * D + D + n] = 1.0;
+  }
+  for (int c = 0; c < D; c++) {  // Gauss-Jordan with partial pivoting
+    int piv = c;
+    for (int r = c + 1; r < D; r++)
+      if (std::fabs(A[r * 2 * D + c]) > std::fabs(A[piv * 2 * D + c])) piv = r;
+    for (int j = 0; j < 2 * D; j++) std::swap(A[c * 2 * D + j], A[piv * 2 * D + j]);
+    const double d = A[c * 2 * D + c];
+    for (int j = 0; j < 2 * D; j++) A[c * 2 * D + j] /= d;
+    for (int r = 0; r < D; r++)
+      if (r != c) {
+        const double f = A[r * 2 * D + c];
+        for (int j = 0; j < 2 * D; j++) A[r * 2 * D + j] -= f * A[c * 2 * D + j];
+      }
+  }
+  const int nq = (int)pts.size() / 2;
+  phi.assign((size_t)nq * D, 0.0);
+  dphi.assign((size_t)nq * D * 2, 0.0);
+  for (int q = 0; q < nq; q++) {
+    const double x = pts[2 * q], y = pts[2 * q + 1];
+    for (int m = 0; m < D; m++) {
+      const int p = ex[2 * m], r = ex[2 * m + 1];
+      const double val = pw(x, p) * pw(y, r);
+      const double dx = p ? p * pw(x, p - 1) * pw(y, r) : 0.0;
+      const double dy = r ? r * pw(x, p) * pw(y, r - 1) : 0.0;
+      for (int i = 0; i < D; i++) {
+        const double c = A[m * 2 * D + D + i];
+        phi[q * D + i] += c * val;
+        dphi[(q * D + i) * 2 + 0] += c * dx;
+        dphi[(q * D + i) * 2 + 1] += c * dy;
+      }
+    }
+  }
+}
+
 }  // namespace mf

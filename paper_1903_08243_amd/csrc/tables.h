@@ -15,6 +15,10 @@ void lagrange_eval(const std::vector<double> &nodes, const std::vector<double> &
 // Simplex quadrature of the given exact degree on the reference tet: points (x,y,z) and
 // weights (summing to 1/6). Returns false if no rule of that degree is built in.
 bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w);
+// triangle: collapsed Gauss rule exact to `degree` (pts as (x, y) pairs) and the P_k
+// equispaced Lagrange basis (a1 fastest) with reference gradients at given points
+void tri_rule(int degree, std::vector<double> &pts, std::vector<double> &w);
+void tri_lagrange(int k, const std::vector<double> &pts, std::vector<double> &phi, std::vector<double> &dphi);
 // P_k Lagrange basis on the reference tet at pts: phi[q*D+i], dphi[(q*D+i)*3+d].
 void tet_lagrange(int k, const std::vector<double> &pts, std::vector<double> &phi,
                   std::vector<double> &dphi);

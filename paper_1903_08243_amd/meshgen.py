@@ -227,6 +227,24 @@ def tri_p1_space(mesh: Mesh, renumber: bool = False, config: int = 0) -> Space:
     return Space(mesh, 1, 1, perm[mesh.cell2vert].astype(np.int32), nn, node_ijk, perm)
 
 
+def tri_space(mesh: Mesh, k: int, renumber: bool = True, config: int = 0, seed_k: int | None = None) -> Space:
+    """P_k nodes of the split squares are exactly the points of the k-refined lattice
+    (one component)."""
+    m = mesh.lattice_m
+    G = m * k + 1
+    vij = mesh.vert_ijk[mesh.cell2vert]  # (ncells, 3, 2)
+    alpha = simplex_lattice(k, 2)  # (D, 2)
+    v0 = vij[:, 0, :]
+    pos = k * v0[:, None, :] + np.einsum("da,cae->cde", alpha, vij[:, 1:, :] - v0[:, None, :])
+    lat = pos[..., 0] + G * pos[..., 1]
+    nn = G ** 2
+    perm = _permutation(nn, renumber, config, k if seed_k is None else seed_k)
+    lat_ij = _lattice(m * k, 2)
+    node_ijk = np.empty_like(lat_ij)
+    node_ijk[perm] = lat_ij
+    return Space(mesh, k, 1, perm[lat].astype(np.int32), nn, node_ijk, perm)
+
+
 def uniform(n: int, lo: float, hi: float, config: int, purpose: int, k: int = 0) -> np.ndarray:
     return rng(config, purpose, k).uniform(lo, hi, size=n)
 
