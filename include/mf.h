@@ -56,7 +56,9 @@ enum {
   MF_EUNSUPPORTED = -7  /* valid request this build does not implement */
 };
 
-enum { MF_CELL_TRI = 0, MF_CELL_TET = 1, MF_CELL_HEX = 2 };
+/* QUAD: bilinear quadrilateral, vertex v at reference (v & 1, v >> 1) -- the 2D
+ * tensor-product cell of the paper's sweep (Section 4.1) next to TRI, TET and HEX. */
+enum { MF_CELL_TRI = 0, MF_CELL_TET = 1, MF_CELL_HEX = 2, MF_CELL_QUAD = 3 };
 
 /* Bilinear forms (paper, supplementary material "operators"):
  *   MASS        int c u v            (c: optional vertex coefficient, else 1)
@@ -81,19 +83,21 @@ typedef struct mf_mesh mf_mesh;
 typedef struct mf_space mf_space;
 typedef struct mf_op mf_op;
 
-/* Create a mesh. coords: host, nverts x gdim (gdim 2 for TRI, 3 otherwise),
+/* Create a mesh. coords: host, nverts x gdim (gdim 2 for TRI and QUAD, 3 otherwise),
  * components interleaved per vertex (the paper's coordinate dat accessed as
- * coords[gdim*vertex + i], Listing 3). cell2vert: host, ncells x (3|4|8).
- * Every cell's Jacobian determinant is checked at its vertices (hex: at the
- * 8 corners, which must share one sign); a zero or sign-changing determinant
+ * coords[gdim*vertex + i], Listing 3). cell2vert: host, ncells x (3|4|8; 4 for TET
+ * and QUAD). Every cell's Jacobian determinant is checked at its vertices (hex and
+ * quad: at every corner, which must share one sign); a zero or sign-changing determinant
  * gives MF_EMESH. |det J| is used afterwards (Listing 2 takes fabs of the
  * determinant). Errors: MF_EINVAL (bad type/sizes/index), MF_EMESH. */
 int mf_mesh_create(int cell_type, int64_t nverts, const double *coords, int64_t ncells,
                    const int32_t *cell2vert, mf_mesh **out);
 
-/* Create a Lagrange space of the given degree (hex: Q_k on GLL nodes, k = 1..6;
+/* Create a Lagrange space of the given degree (hex and quad: Q_k on GLL nodes,
+ * k = 1..6, local node i + (k+1)(j + (k+1) l) at the GLL point (i, j, l), i fastest;
  * tet and tri: P_k equispaced, k = 1..3) with ncomp components.
- * cell2node: host, ncells x D (D = (k+1)^3 hex, (k+1)(k+2)(k+3)/6 tet, (k+1)(k+2)/2 tri),
+ * cell2node: host, ncells x D (D = (k+1)^3 hex, (k+1)^2 quad, (k+1)(k+2)(k+3)/6 tet,
+ * (k+1)(k+2)/2 tri),
  * entries in [0, nnodes) -- the paper's cell2dof map (Section 2.2). The caller's
  * node numbering is kept at this boundary. Errors: MF_EINVAL, MF_EUNSUPPORTED. */
 int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *cell2node,
@@ -132,15 +136,16 @@ typedef struct {
 
 /* Create an operator. precision MF_F64 or MF_F32 (FP32 arithmetic with FP32
  * accumulation; cell geometry is precomputed in FP64 and rounded once).
- * nq1d: hex quadrature points per direction, 0 -> k+1 (tensor Gauss-Legendre);
- * simplices ignore it and use a rule exact for the integrand. params may be
+ * nq1d: hex and quad quadrature points per direction, 0 -> k+1 (tensor
+ * Gauss-Legendre; quad: k+1..8, the paper's k+2 included); simplices ignore it and
+ * use a rule exact for the integrand. params may be
  * NULL (coefficient 1, lambda 1, mu 0.5, no constraints). stream: device
  * uploads are ordered on it; the call returns after they complete.
  * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1) and LAPLACIAN
  * (ncomp 1 or 3); tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
- * HELMHOLTZ P1-P2, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules are exact to
- * degree 5, which P3 mass and Helmholtz exceed); tri MASS, HELMHOLTZ, LAPLACIAN and
- * POISSON P1-P3 (ncomp 1).
+ * HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules reach degree 7);
+ * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1); quad MASS, HELMHOLTZ,
+ * LAPLACIAN and POISSON Q1-Q6 (ncomp 1).
  * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
 int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,
                  const mf_op_params *params, void *stream, mf_op **out);

@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(64) tet_scalar_kernel(const TetArgs<T> A) {
   // P3 in FP64: one point's 80 table values do not fit the scalar registers, so the
   // tables are staged in LDS once per workgroup and read as same-address broadcasts
   // (1237 -> 954 us at 48^3 x 6 cells; FP32 spills half as much and ran slower staged)
-  constexpr bool STAGE = K == 3 && sizeof(T) == 8;
+  constexpr bool STAGE = K == 3 && sizeof(T) == 8 && NQ <= 14;  // larger rules exceed LDS
   constexpr int NTAB = NQ * D * 4 + NQ * 5;
   __shared__ T stab[STAGE ? NTAB : 1];
   const T *tab = A.tab;
@@ -224,7 +224,8 @@ static int launch_tet_scalar_k(int kind, const TetArgs<T> &a, bool atomic, hipSt
   return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
 }
 
-// rules of the tet quadrature table: 1 point (degree 1), 4 (degree 2), 14 (degree 5)
+// rules of the tet quadrature table: 1 point (degree 1), 4 (degree 2), 14 (degree 5),
+// 125 (collapsed product rule, degree 7)
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
   if (k == 1 && nq == 1) return launch_tet_scalar_k<T, 1, 1>(kind, a, atomic, s);
@@ -233,6 +234,7 @@ int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic,
   if (k == 2 && nq == 4) return launch_tet_scalar_k<T, 2, 4>(kind, a, atomic, s);
   if (k == 2 && nq == 14) return launch_tet_scalar_k<T, 2, 14>(kind, a, atomic, s);
   if (k == 3 && nq == 14) return launch_tet_scalar_k<T, 3, 14>(kind, a, atomic, s);
+  if (k == 3 && nq == 125) return launch_tet_scalar_k<T, 3, 125>(kind, a, atomic, s);  // degree 6-7
   return fail(MF_EUNSUPPORTED, "tet scalar operator: degree / rule");
 }
 template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);

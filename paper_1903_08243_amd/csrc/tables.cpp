@@ -152,6 +152,22 @@ bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
     s31(0.0927352503108912, 0.0734930431163619 / 6.0);
     s31(0.3108859192633006, 0.1126879257180159 / 6.0);
     s22(0.0455037041256496, 0.0425460207770812 / 6.0);
+  } else if (degree <= 7) {
+    // collapsed Gauss product rule: x = u, y = v (1 - u), z = w (1 - u)(1 - v), Jacobian
+    // (1 - u)^2 (1 - v); a degree-p monomial becomes degree p + 2 in u, p + 1 in v and p
+    // in w, so n = ceil((p + 3) / 2) points per direction integrate it exactly
+    const int n = (degree + 4) / 2;
+    std::vector<double> x, wx;
+    gauss_legendre(n, x, wx);
+    for (int i = 0; i < n; i++)
+      for (int j = 0; j < n; j++)
+        for (int l = 0; l < n; l++) {
+          const double u = x[i], v = x[j], t = x[l];
+          pts.push_back(u);
+          pts.push_back(v * (1.0 - u));
+          pts.push_back(t * (1.0 - u) * (1.0 - v));
+          w.push_back(wx[i] * wx[j] * wx[l] * (1.0 - u) * (1.0 - u) * (1.0 - v));
+        }
   } else {
     return false;
   }

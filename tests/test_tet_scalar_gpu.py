@@ -10,10 +10,10 @@ from paper_1903_08243_amd import meshgen as mg
 pytestmark = pytest.mark.gpu
 TOL = {0: 1e-12, 1: 1e-5}
 MASS, HELM, LAP, POIS = 0, 1, 2, 3
-# (kind, with a vertex coefficient): P3 mass and Helmholtz need a degree-6 rule
+# (kind, with a vertex coefficient); P3 mass and Helmholtz use the 125-point collapsed
+# rule (degree 6 and 7)
 CASES = [(k, kind, coef) for k in (1, 2, 3) for kind, coef in
-         ((MASS, False), (MASS, True), (HELM, False), (LAP, False), (POIS, True))
-         if not (k == 3 and kind in (MASS, HELM))]
+         ((MASS, False), (MASS, True), (HELM, False), (LAP, False), (POIS, True))]
 
 
 @pytest.fixture(scope="module")
@@ -81,8 +81,7 @@ def test_tet_scalar_dirichlet_and_range(mf, k):
 def test_tet_scalar_errors(mf):
     mesh, space, x, c = _case(3, m=2)
     sp = mf.Space.from_meshgen(space)
-    with pytest.raises(mf.MFError):
-        mf.Operator(sp, MASS, mf.F64)  # P3 mass: no degree-6 rule
+    assert mf.Operator(sp, MASS, mf.F64, vertex_coef=c).info["nqp"] == 125
     with pytest.raises(mf.MFError):
         mf.Operator(sp, LAP, mf.F64).diagonal()
 
