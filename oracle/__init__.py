@@ -33,7 +33,7 @@ OP_MASS, OP_HELMHOLTZ, OP_LAPLACIAN, OP_POISSON, OP_ELASTICITY = range(5)
 # St-Venant-Kirchhoff: tangent at a field u0 (bilinear in the trial field) and the
 # nonlinear residual form itself (supplementary operator list, "hyperelasticity")
 OP_HYPERELASTIC, OP_HYPER_RESIDUAL = 5, 6
-CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
+CELL_TRI, CELL_TET, CELL_HEX, CELL_QUAD = 0, 1, 2, 3
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
@@ -112,6 +112,8 @@ class OracleOp:
         k = space.degree
         if mesh.cell_type == CELL_HEX:
             qw, phi, dphi, vN, vdN = tables.hex_tables(k, nq1d or (k + 1))
+        elif mesh.cell_type == CELL_QUAD:
+            qw, phi, dphi, vN, vdN = tables.quad_tables(k, nq1d or (k + 1))
         else:
             dim = 2 if mesh.cell_type == CELL_TRI else 3
             qw, phi, dphi, vN, vdN = tables.simplex_tables(

@@ -102,6 +102,42 @@ def hex_tables(k: int, nq1d: int):
     return qw, phi, dphi, vN, vdN
 
 
+def quad_tables(k: int, nq1d: int):
+    """The 2D counterpart of hex_tables: Q_k (GLL) basis and the bilinear vertex basis.
+
+    Returns (qw[nq], phi[nq, D], dphi[nq, D, 2], vN[nq, 4], vdN[nq, 4, 2]) with
+    points (a, b) ordered a fastest, basis (i, j) i fastest, vertex v at (v & 1, v >> 1).
+    """
+    g, w = gauss_legendre01(nq1d)
+    V, dV = lagrange1d(gll_nodes01(k), g)
+    n = k + 1
+    nq, D = nq1d ** 2, n ** 2
+    qw = np.zeros(nq)
+    phi = np.zeros((nq, D))
+    dphi = np.zeros((nq, D, 2))
+    vN = np.zeros((nq, 4))
+    vdN = np.zeros((nq, 4, 2))
+    for b in range(nq1d):
+        for a in range(nq1d):
+            q = a + nq1d * b
+            qw[q] = w[a] * w[b]
+            xi = (g[a], g[b])
+            for j in range(n):
+                for i in range(n):
+                    d = i + n * j
+                    phi[q, d] = V[a, i] * V[b, j]
+                    dphi[q, d, 0] = dV[a, i] * V[b, j]
+                    dphi[q, d, 1] = V[a, i] * dV[b, j]
+            for v in range(4):
+                o = (v & 1, v >> 1)
+                f = [xi[dd] if o[dd] else 1.0 - xi[dd] for dd in range(2)]
+                df = [1.0 if o[dd] else -1.0 for dd in range(2)]
+                vN[q, v] = f[0] * f[1]
+                vdN[q, v, 0] = df[0] * f[1]
+                vdN[q, v, 1] = f[0] * df[1]
+    return qw, phi, dphi, vN, vdN
+
+
 def simplex_lattice(k: int, dim: int) -> np.ndarray:
     out = []
     if dim == 2:

@@ -29,7 +29,7 @@ from itertools import permutations
 
 import numpy as np
 
-CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
+CELL_TRI, CELL_TET, CELL_HEX, CELL_QUAD = 0, 1, 2, 3
 PURPOSE_PERTURB, PURPOSE_PERM, PURPOSE_X, PURPOSE_COEF, PURPOSE_RHS, PURPOSE_GRF = range(6)
 
 
@@ -137,6 +137,38 @@ def hex_space(mesh: Mesh, k: int, ncomp: int = 1, renumber: bool = True,
     node_ijk = np.empty_like(lat_ijk)
     node_ijk[perm] = lat_ijk
     return Space(mesh, k, ncomp, c2n.astype(np.int32), nn, node_ijk, perm)
+
+
+def quad_mesh(m: int, perturb: float = 0.0, config: int = 0, seed_k: int = 0) -> Mesh:
+    """Unit square, m x m bilinear quadrilaterals; vertex v of a cell at (v & 1, v >> 1)."""
+    ij = _lattice(m, 2)
+    coords = _perturb(ij, m, perturb, rng(config, PURPOSE_PERTURB, seed_k))
+    c = np.arange(m)
+    cy, cx = np.meshgrid(c, c, indexing="ij")
+    cx, cy = cx.ravel(), cy.ravel()
+    M = m + 1
+    c2v = np.empty((m * m, 4), dtype=np.int32)
+    for v in range(4):
+        c2v[:, v] = (cx + (v & 1)) + M * (cy + (v >> 1))
+    return Mesh(CELL_QUAD, coords, c2v, m, ij)
+
+
+def quad_space(mesh: Mesh, k: int, renumber: bool = True, config: int = 0,
+               seed_k: int | None = None) -> Space:
+    """Q_k nodes (one component): the k-refined lattice; local node (i, j), i fastest."""
+    m = mesh.lattice_m
+    G = m * k + 1
+    c = np.arange(m)
+    cy, cx = np.meshgrid(c, c, indexing="ij")
+    base = cx.ravel() * k + G * (cy.ravel() * k)
+    loc = _lattice(k, 2)
+    c2n = base[:, None] + (loc[:, 0] + G * loc[:, 1])[None, :]
+    nn = G * G
+    perm = _permutation(nn, renumber, config, k if seed_k is None else seed_k)
+    lat_ij = _lattice(m * k, 2)
+    node_ij = np.empty_like(lat_ij)
+    node_ij[perm] = lat_ij
+    return Space(mesh, k, 1, perm[c2n].astype(np.int32), nn, node_ij, perm)
 
 
 def _permutation(nn: int, renumber: bool, config: int, k: int) -> np.ndarray:
