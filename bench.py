@@ -245,9 +245,30 @@ def bench_simplex(mf, mg, reps=20):
             del op, xt, yt
         del sp, space
     del tmesh
+    # Q_k quadrilaterals (2D sum factorisation, lane per point), 1024 x 1024 cells
+    qmesh = mg.quad_mesh(1024, 0.25, config=0)
+    for k, kind, name in ((2, mf.HELMHOLTZ, "helmholtz"), (6, mf.LAPLACIAN, "laplacian")):
+        space = mg.quad_space(qmesh, k)
+        sp = mf.Space.from_meshgen(space)
+        x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
+            op = mf.Operator(sp, kind, prec)
+            xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+            yt = torch.empty_like(xt)
+            t = time_kernel(op, xt, yt, reps)
+            r = roof(op, t, prec)
+            tag = f"quad_{name}_q{k}_{ptag}"
+            out[tag] = {"cells": qmesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
+                        "launches": op.info["cell_launches"], "qp": op.info["nqp"], "bound": r["bound"],
+                        "frac": r["frac"], "gbs": r["gbs"], "tflops": r["tflops"]}
+            log(f"  {tag}: {json.dumps(out[tag])}")
+            del op, xt, yt
+        del sp, space
+    del qmesh
     # one-component operators on the same tets (dense tabulation, lane per cell)
     for k, kind, name in ((1, mf.LAPLACIAN, "laplacian"), (2, mf.HELMHOLTZ, "helmholtz"),
-                          (2, mf.LAPLACIAN, "laplacian"), (3, mf.LAPLACIAN, "laplacian")):
+                          (2, mf.LAPLACIAN, "laplacian"), (3, mf.LAPLACIAN, "laplacian"),
+                          (3, mf.HELMHOLTZ, "helmholtz")):
         space = mg.tet_space(mesh, k, ncomp=1, config=2)
         sp = mf.Space.from_meshgen(space)
         x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)

@@ -11,7 +11,7 @@ import os
 
 import numpy as np
 
-CELL_TRI, CELL_TET, CELL_HEX = 0, 1, 2
+CELL_TRI, CELL_TET, CELL_HEX, CELL_QUAD = 0, 1, 2, 3
 MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY, HYPERELASTIC = range(6)
 F64, F32 = 0, 1
 SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED, SCATTER_PATCH = 0, 1, 2, 3

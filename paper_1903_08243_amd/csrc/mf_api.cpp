@@ -48,7 +48,8 @@ template <typename T> static std::vector<T> cast_vec(const std::vector<double> &
 }
 
 static int nvc_of(int cell_type) {
-  return cell_type == MF_CELL_TRI ? 3 : cell_type == MF_CELL_TET ? 4 : cell_type == MF_CELL_HEX ? 8 : 0;
+  return cell_type == MF_CELL_TRI ? 3 : cell_type == MF_CELL_TET ? 4 : cell_type == MF_CELL_HEX ? 8
+         : cell_type == MF_CELL_QUAD ? 4 : 0;
 }
 
 // Trilinear map x(xi) = c0 + c1 xi1 + c2 xi2 + c3 xi3 + c4 xi1 xi2 + c5 xi1 xi3 + c6 xi2 xi3
@@ -81,7 +82,7 @@ int mf_mesh_create(int cell_type, int64_t nverts, const double *coords, int64_t 
   if (nverts <= 0 || ncells < 0 || !coords || (ncells > 0 && !cell2vert))
     return fail(MF_EINVAL, "mf_mesh_create: bad sizes or null arrays");
   if (nverts > INT32_MAX || ncells > INT32_MAX) return fail(MF_EINVAL, "mf_mesh_create: sizes exceed int32");
-  const int g = cell_type == MF_CELL_TRI ? 2 : 3;
+  const int g = (cell_type == MF_CELL_TRI || cell_type == MF_CELL_QUAD) ? 2 : 3;
   for (int64_t i = 0; i < ncells * nvc; i++)
     if (cell2vert[i] < 0 || cell2vert[i] >= nverts)
       return fail(MF_EINVAL, "mf_mesh_create: cell2vert entry " + std::to_string(i) + " out of range");
@@ -110,6 +111,25 @@ int mf_mesh_create(int cell_type, int64_t nverts, const double *coords, int64_t 
                          J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
                          J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
       if (!(std::fabs(det) > tol)) return fail(MF_EMESH, "degenerate tetrahedron " + std::to_string(K));
+    } else if (cell_type == MF_CELL_QUAD) {
+      // det J of a bilinear map is affine in (xi, eta) (the xi eta terms cancel), so
+      // one sign at the 4 corners holds over the cell
+      int sign = 0;
+      for (int corner = 0; corner < 4; corner++) {
+        const double xi = corner & 1, eta = corner >> 1;
+        double j[2][2];
+        for (int a = 0; a < 2; a++) {
+          const double X0 = coords[(int64_t)cv[0] * 2 + a], X1 = coords[(int64_t)cv[1] * 2 + a],
+                       X2 = coords[(int64_t)cv[2] * 2 + a], X3 = coords[(int64_t)cv[3] * 2 + a];
+          j[a][0] = (X1 - X0) + (X3 - X1 - X2 + X0) * eta;
+          j[a][1] = (X2 - X0) + (X3 - X1 - X2 + X0) * xi;
+        }
+        const double det = j[0][0] * j[1][1] - j[0][1] * j[1][0];
+        const int sg = det > tol ? 1 : det < -tol ? -1 : 0;
+        if (sg == 0 || (sign != 0 && sg != sign))
+          return fail(MF_EMESH, "degenerate or tangled quadrilateral " + std::to_string(K));
+        sign = sg;
+      }
     } else {
       double c[3][8];
       for (int a = 0; a < 3; a++) {
@@ -159,6 +179,9 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
   if (mesh->cell_type == MF_CELL_HEX) {
     if (degree < 1 || degree > 6) return fail(MF_EUNSUPPORTED, "hex spaces support degree 1..6");
     D = (degree + 1) * (degree + 1) * (degree + 1);
+  } else if (mesh->cell_type == MF_CELL_QUAD) {
+    if (degree < 1 || degree > 6) return fail(MF_EUNSUPPORTED, "quad spaces support degree 1..6");
+    D = (degree + 1) * (degree + 1);
   } else if (mesh->cell_type == MF_CELL_TET) {
     if (degree < 1 || degree > 3) return fail(MF_EUNSUPPORTED, "tet spaces support degree 1..3");
     D = tet_ndofs(degree);
@@ -490,7 +513,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipS
     deg = (op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ) ? 2 * k : 2 * k - 2;
     if (op->has_coef) deg += 1;
   }
-  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rule table ends at 5)");
+  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rule table ends at 7)");
   const int nq = (int)w.size();
   op->nqp = nq;
   tet_lagrange(k, pts, phi, dphi);
@@ -634,6 +657,42 @@ template <typename T> static int setup_tri(mf_op *op, const mf_space *sp, const 
   return upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
 }
 
+// Quads: 1D tables (GLL Lagrange basis and its derivative at the Gauss points, the
+// weights and the points), the bilinear map coefficients per cell [cell][6] and the
+// vertex coefficients [cell][4], in internal cell order.
+template <typename T> static int setup_quad(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+  const int k = sp->degree, nq = op->nq1d;
+  std::vector<double> g, w, V, dV;
+  gauss_legendre(nq, g, w);
+  lagrange_eval(gll_points(k), g, V, dV);
+  std::vector<T> tab;
+  for (double v : V) tab.push_back((T)v);
+  for (double v : dV) tab.push_back((T)v);
+  for (double v : w) tab.push_back((T)v);
+  for (double v : g) tab.push_back((T)v);
+  int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
+  if (rc) return rc;
+  const int64_t nc = sp->ncells;
+  std::vector<T> geo((size_t)nc * 6), cf;
+  if (op->has_coef) cf.resize((size_t)nc * 4);
+  for (int64_t K = 0; K < nc; K++) {
+    const int32_t *cv = sp->cell2vert_int.data() + K * 4;
+    for (int a = 0; a < 2; a++) {
+      const double X0 = sp->coords[(int64_t)cv[0] * 2 + a], X1 = sp->coords[(int64_t)cv[1] * 2 + a],
+                   X2 = sp->coords[(int64_t)cv[2] * 2 + a], X3 = sp->coords[(int64_t)cv[3] * 2 + a];
+      geo[K * 6 + 0 + a] = (T)(X1 - X0);
+      geo[K * 6 + 2 + a] = (T)(X2 - X0);
+      geo[K * 6 + 4 + a] = (T)(X3 - X1 - X2 + X0);
+    }
+    if (op->has_coef)
+      for (int v = 0; v < 4; v++) cf[K * 4 + v] = (T)pr->vertex_coef[cv[v]];
+  }
+  rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+  if (!rc && op->has_coef) rc = upload(op->coef, cf.data(), cf.size() * sizeof(T), s);
+  if (!rc) MF_HIP(hipStreamSynchronize(s));
+  return rc;
+}
+
 static void count_work(mf_op *op) {
   const double s = op->precision == MF_F64 ? 8.0 : 4.0;
   const double nc = (double)op->ncells, nd = (double)op->ndofs;
@@ -659,6 +718,19 @@ static void count_work(mf_op *op) {
     // coordinates of the vertices, once per vertex
     const bool xyz = op->patched && op->precision == MF_F64;
     by += (xyz ? 24.0 * (double)op->nnodes : nc * 24.0 * s) + (op->has_coef ? nc * 8.0 * s : 0.0);
+  } else if (op->cell_type == MF_CELL_QUAD) {
+    // sum factorisation in 2D, n = k+1 nodes and q points per direction; multiply-adds
+    // per cell (two flops each): forward x pass q n^2 (twice with gradients), forward y
+    // pass q^2 n per value or gradient component, backward passes the same in reverse;
+    // per point: Jacobian and |det| w 14, coefficient 13, value 2, gradient push-forward
+    // and flux 17
+    const double n = op->degree + 1, q = op->nq1d;
+    const bool val = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ, grad = op->kind != MF_OP_MASS;
+    const double g = grad ? 1.0 : 0.0, v = val ? 1.0 : 0.0;
+    const double fma = q * n * n * (1 + g) + q * q * n * (v + 2 * g) + q * q * n * (v + 2 * g) + q * n * n * (1 + g);
+    const double pt = 14.0 + (op->has_coef ? 13.0 : 0.0) + 2.0 * v + 17.0 * g;
+    fl = nc * (2.0 * fma + q * q * pt);
+    by += nc * 6.0 * s + (op->has_coef ? nc * 4.0 * s : 0.0);
   } else if (op->cell_type == MF_CELL_TET && op->ncomp == 1) {
     // scalar operators, dense tabulation, per point: value 2D and its test sum 2D;
     // reference gradient 6D, push-forward 18, the reference-direction flux 18 (and a
@@ -709,6 +781,10 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
                  op->has_coef ? (q1 ? op->q1coef : op->coef).as<T>() : nullptr, x, y, c0, c1, op->ncomp, filt, ulo,
                  uhi, fused ? op->gmap.as<int32_t>() : nullptr, first ? op->first_lo.as<int32_t>() : nullptr};
     return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
+  } else if (op->cell_type == MF_CELL_QUAD) {
+    QuadArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
+                  op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi};
+    return launch_quad<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
                  filt, ulo, uhi, op->u0.as<T>(), op->u0map.as<int32_t>(),
@@ -780,8 +856,10 @@ static bool default_coloured(const mf_op *op) {
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
   if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_TET && op->ncomp == 1) ||
-      (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)))
-    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC or scalar tet / P2+ triangle operators");
+      (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)) ||
+      op->cell_type == MF_CELL_QUAD)
+    return fail(MF_EUNSUPPORTED,
+                "diagonal: not built for HYPERELASTIC, scalar tet, P2+ triangle or quad operators");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
   if (rc) return rc;
   if (op->cell_type == MF_CELL_HEX) {
@@ -818,6 +896,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   bool ok = false;
   if (ct == MF_CELL_HEX)
     ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3) : (kind <= MF_OP_POISSON && sp->ncomp == 1);
+  else if (ct == MF_CELL_QUAD)
+    ok = kind <= MF_OP_POISSON && sp->ncomp == 1;
   else if (ct == MF_CELL_TET)
     ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3) ||
          (kind <= MF_OP_POISSON && sp->ncomp == 1);
@@ -842,8 +922,15 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   op->lam = pr->lambda;
   op->mu = pr->mu;
   op->has_coef = pr->vertex_coef != nullptr && (kind == MF_OP_MASS || kind == MF_OP_POISSON);
-  op->nq1d = ct == MF_CELL_HEX ? (nq1d > 0 ? nq1d : sp->degree + 1) : 0;
+  const bool tensor = ct == MF_CELL_HEX || ct == MF_CELL_QUAD;
+  op->nq1d = tensor ? (nq1d > 0 ? nq1d : sp->degree + 1) : 0;
   if (ct == MF_CELL_HEX) op->nqp = op->nq1d * op->nq1d * op->nq1d;
+  if (ct == MF_CELL_QUAD) {
+    // one lane per point, and every dof needs a lane
+    if (op->nq1d != sp->degree + 1 && op->nq1d != sp->degree + 2)
+      return fail(MF_EUNSUPPORTED, "quad: nq1d must be k+1 or k+2");
+    op->nqp = op->nq1d * op->nq1d;
+  }
 
   // maps: constrained nodes are stored as -1 (gathered as 0, never scattered)
   const int64_t nc = sp->ncells;
@@ -959,6 +1046,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (ct == MF_CELL_HEX)
     rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, to_pos2, s)
                              : setup_hex<float>(op.get(), sp, pr, m, to_pos2, s);
+  else if (ct == MF_CELL_QUAD)
+    rc = precision == MF_F64 ? setup_quad<double>(op.get(), sp, pr, s) : setup_quad<float>(op.get(), sp, pr, s);
   else if (ct == MF_CELL_TET)
     rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, pr, s) : setup_tet<float>(op.get(), sp, pr, s);
   else

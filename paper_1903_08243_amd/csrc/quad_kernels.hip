@@ -1,0 +1,208 @@
+// Operator action on bilinear quadrilaterals, Q_k (k = 1..6) on GLL nodes.
+//
+// Quads are the 2D tensor-product cells of the paper's sweep (Section 4.1): the
+// coordinate map is bilinear, so the Jacobian is evaluated at every quadrature point
+// (Section 2.1), and the basis is a tensor product, so the interpolation to the points
+// and the integration against the test functions factorise into 1D contractions
+// (sum factorisation, Sections 3 and 4.2.4): two passes each way instead of a dense
+// D x Q tabulation.
+//
+// GPU mapping: a workgroup is one 64-lane wavefront; lane p of a cell is quadrature
+// point (a, b) = (p % nq, p / nq) of the nq x nq grid (nq <= 8), and 64 / nq^2 cells sit
+// side by side in the wavefront (16 for Q1 with 2 x 2 points, one for Q6). Between the
+// 1D passes the half-interpolated fields (lane (a, j): point a in x, node j in y) go
+// through LDS. The gathered and scattered dof (i, j) of a cell is lane i + (k+1) j.
+#include "mf_internal.h"
+
+namespace mf {
+
+namespace {
+__device__ __forceinline__ void quad_atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void quad_atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+}  // namespace
+
+// N = k + 1 nodes and NQ Gauss points per direction. tab: B[a][i] = l_i(g_a) [NQ][N],
+// B'[a][i] [NQ][N], weights [NQ], points [NQ]. atomic: device atomics for the scatter,
+// else plain read-modify-write (the cells of one launch share no node).
+template <typename T, int N, int NQ, int KIND>
+__global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const bool atomic) {
+  constexpr int P = NQ * NQ, CPW = 64 / P, D = N * N, H = NQ * N;
+  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
+  constexpr bool GRAD = KIND != MF_OP_MASS;
+  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
+  static_assert(NQ >= N && P <= 64, "one lane per point, and every dof has a lane");
+  __shared__ T sB[H], sD[H], sw[NQ], sg[NQ];
+  __shared__ T U[CPW][D];             // gathered dof values
+  __shared__ T X0[CPW][H], X1[CPW][H];  // (a, j) fields, forward, then backward
+  __shared__ T F0[CPW][P], F1[CPW][P], F2[CPW][P];  // value flux, reference-gradient fluxes
+  const int lane = threadIdx.x;
+  const int slot = lane / P, p = lane - slot * P;
+  const bool act = slot < CPW;  // the last 64 mod P lanes idle
+  // consecutive workgroup ids land on different XCDs: give each XCD a contiguous run of
+  // cell groups (its L2 then holds the nodes its neighbouring cells share)
+  const int64_t ngrp = (A.c1 - A.c0 + CPW - 1) / CPW, per = (ngrp + 7) / 8;
+  const int64_t grp = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (grp >= ngrp) return;  // uniform over the workgroup
+  const int64_t cell = A.c0 + grp * CPW + slot;
+  bool valid = act && cell < A.c1;
+  if (valid && A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    valid = u >= A.ulo && u < A.uhi;
+  }
+  if (lane < H) {
+    sB[lane] = A.tab[lane];
+    sD[lane] = A.tab[H + lane];
+  }
+  if (lane < NQ) {
+    sw[lane] = A.tab[2 * H + lane];
+    sg[lane] = A.tab[2 * H + NQ + lane];
+  }
+  int idx = -1;  // node of dof p (negative: constrained or no cell)
+  if (valid && p < D) idx = A.map[cell * D + p];
+  if (act && p < D) U[slot][p] = idx >= 0 ? A.x[idx] : T(0);
+  __syncthreads();
+  // forward x pass, lane (a, j): sum over nodes i in x
+  if (act && p < H) {
+    const int a = p % NQ, j = p / NQ;
+    T s0 = T(0), s1 = T(0);
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+      const T u = U[slot][i + N * j];
+      s0 += sB[a * N + i] * u;
+      if constexpr (GRAD) s1 += sD[a * N + i] * u;
+    }
+    X0[slot][p] = s0;
+    if constexpr (GRAD) X1[slot][p] = s1;
+  }
+  __syncthreads();
+  // forward y pass and the pointwise fluxes, lane (a, b)
+  if (act) {
+    const int a = p % NQ, b = p / NQ;
+    T u = T(0), gx = T(0), gy = T(0);  // value and reference gradient at the point
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+      const T x0 = X0[slot][a + NQ * j];
+      if constexpr (VAL) u += sB[b * N + j] * x0;
+      if constexpr (GRAD) {
+        gx += sB[b * N + j] * X1[slot][a + NQ * j];
+        gy += sD[b * N + j] * x0;
+      }
+    }
+    // x(xi, eta) = x0 + c1 xi + c2 eta + c3 xi eta per coordinate; a lane without a
+    // cell takes the unit square so that its (discarded) arithmetic stays finite
+    T c1x = T(1), c1y = T(0), c2x = T(0), c2y = T(1), c3x = T(0), c3y = T(0);
+    if (valid) {
+      const T *g = A.geo + cell * 6;
+      c1x = g[0];
+      c1y = g[1];
+      c2x = g[2];
+      c2y = g[3];
+      c3x = g[4];
+      c3y = g[5];
+    }
+    const T xi = sg[a], eta = sg[b];
+    // J[r][c] = d x_r / d xi_c
+    const T J00 = c1x + c3x * eta, J01 = c2x + c3x * xi;
+    const T J10 = c1y + c3y * eta, J11 = c2y + c3y * xi;
+    const T det = J00 * J11 - J01 * J10;
+    const T wdet = sw[a] * sw[b] * (det < T(0) ? -det : det);
+    T cq = T(1);
+    if (COEF && A.coef && valid) {
+      const T *cv = A.coef + cell * 4;
+      cq = (T(1) - xi) * (T(1) - eta) * cv[0] + xi * (T(1) - eta) * cv[1] + (T(1) - xi) * eta * cv[2] +
+           xi * eta * cv[3];
+    }
+    T f0 = T(0), P0 = T(0), P1 = T(0);
+    if constexpr (VAL) f0 = wdet * (KIND == MF_OP_MASS ? cq : T(1)) * u;
+    if constexpr (GRAD) {
+      // J^{-1} = [[J11, -J01], [-J10, J00]] / det; physical gradient G_a = sum_b
+      // (J^{-1})[b][a] g_b, then the reference-direction flux P_b = s sum_a (J^{-1})[b][a] G_a
+      const T r = T(1) / det;
+      const T G0 = (J11 * gx - J10 * gy) * r, G1 = (J00 * gy - J01 * gx) * r;
+      const T s = wdet * (KIND == MF_OP_POISSON ? cq : T(1)) * r;
+      P0 = s * (J11 * G0 - J01 * G1);
+      P1 = s * (J00 * G1 - J10 * G0);
+    }
+    F0[slot][p] = f0;
+    F1[slot][p] = P0;
+    F2[slot][p] = P1;
+  }
+  __syncthreads();
+  // backward y pass, lane (a, j): integrate against the test functions in y
+  if (act && p < H) {
+    const int a = p % NQ, j = p / NQ;
+    T y0 = T(0), y1 = T(0);
+#pragma unroll
+    for (int b = 0; b < NQ; b++) {
+      const int q = a + NQ * b;
+      if constexpr (VAL) y0 += sB[b * N + j] * F0[slot][q];
+      if constexpr (GRAD) {
+        y0 += sD[b * N + j] * F2[slot][q];
+        y1 += sB[b * N + j] * F1[slot][q];
+      }
+    }
+    X0[slot][p] = y0;
+    if constexpr (GRAD) X1[slot][p] = y1;
+  }
+  __syncthreads();
+  // backward x pass, lane (i, j), and the scatter
+  if (act && p < D && idx >= 0) {
+    const int i = p % N, j = p / N;
+    T v = T(0);
+#pragma unroll
+    for (int a = 0; a < NQ; a++) {
+      v += sB[a * N + i] * X0[slot][a + NQ * j];
+      if constexpr (GRAD) v += sD[a * N + i] * X1[slot][a + NQ * j];
+    }
+    if (atomic) quad_atomic_add(&A.y[idx], v);
+    else A.y[idx] += v;
+  }
+}
+
+template <typename T, int N, int NQ, int KIND>
+static int launch_quad_nk(const QuadArgs<T> &a, bool atomic, hipStream_t s) {
+  constexpr int CPW = 64 / (NQ * NQ);
+  const int64_t ngrp = (a.c1 - a.c0 + CPW - 1) / CPW;
+  const dim3 g((unsigned)(((ngrp + 7) / 8) * 8)), b(64);
+  quad_kernel<T, N, NQ, KIND><<<g, b, 0, s>>>(a, atomic);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T, int N, int NQ>
+static int launch_quad_nq(int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s) {
+  switch (kind) {
+    case MF_OP_MASS: return launch_quad_nk<T, N, NQ, MF_OP_MASS>(a, atomic, s);
+    case MF_OP_HELMHOLTZ: return launch_quad_nk<T, N, NQ, MF_OP_HELMHOLTZ>(a, atomic, s);
+    case MF_OP_LAPLACIAN: return launch_quad_nk<T, N, NQ, MF_OP_LAPLACIAN>(a, atomic, s);
+    case MF_OP_POISSON: return launch_quad_nk<T, N, NQ, MF_OP_POISSON>(a, atomic, s);
+  }
+  return fail(MF_EUNSUPPORTED, "quad operator kind");
+}
+
+template <typename T, int N>
+static int launch_quad_n(int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s) {
+  if (nq == N) return launch_quad_nq<T, N, N>(kind, a, atomic, s);
+  if constexpr (N < 8)
+    if (nq == N + 1) return launch_quad_nq<T, N, N + 1>(kind, a, atomic, s);
+  return fail(MF_EUNSUPPORTED, "quad: nq1d must be k+1 or k+2 (at most 8)");
+}
+
+template <typename T>
+int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s) {
+  if (a.c1 <= a.c0) return MF_OK;
+  switch (k) {
+    case 1: return launch_quad_n<T, 2>(nq, kind, a, atomic, s);
+    case 2: return launch_quad_n<T, 3>(nq, kind, a, atomic, s);
+    case 3: return launch_quad_n<T, 4>(nq, kind, a, atomic, s);
+    case 4: return launch_quad_n<T, 5>(nq, kind, a, atomic, s);
+    case 5: return launch_quad_n<T, 6>(nq, kind, a, atomic, s);
+    case 6: return launch_quad_n<T, 7>(nq, kind, a, atomic, s);
+  }
+  return fail(MF_EUNSUPPORTED, "quad degree (1..6)");
+}
+
+template int launch_quad<double>(int, int, int, const QuadArgs<double> &, bool, hipStream_t);
+template int launch_quad<float>(int, int, int, const QuadArgs<float> &, bool, hipStream_t);
+
+}  // namespace mf

@@ -1,0 +1,137 @@
+"""GPU parity of the one-component operators on Q1..Q6 quadrilaterals (mass with and
+without a vertex coefficient, Helmholtz, Laplacian, Poisson) against the oracle, through
+the C-ABI: both scatter modes, both precisions, k+1 and k+2 Gauss points per direction,
+Dirichlet rows, range applies, a ragged cell count and sampled outputs at 1024^2 cells."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1903_08243_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+TOL = {0: 1e-12, 1: 1e-5}
+MASS, HELM, LAP, POIS = 0, 1, 2, 3
+
+
+@pytest.fixture(scope="module")
+def mf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    import paper_1903_08243_amd as m
+    m.load_library()
+    return m
+
+
+def _relerr(y, ref):
+    return np.abs(y - ref).max() / np.abs(ref).max()
+
+
+def _case(k, m=11):
+    # 121 cells: not a multiple of the 16 / 7 / 4 / 2 cells a workgroup holds
+    mesh = mg.quad_mesh(m, 0.25, config=0)
+    space = mg.quad_space(mesh, k, seed_k=k)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+    c = np.exp(np.random.default_rng(k).normal(size=mesh.nverts))
+    return mesh, space, x, c
+
+
+@pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind,coef", [(MASS, False), (MASS, True), (HELM, False), (LAP, False), (POIS, True)],
+                         ids=["mass", "mass-coef", "helmholtz", "laplacian", "poisson"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_quad_action(mf, k, kind, coef, prec, scatter):
+    import torch
+    print(f"quad k={k} kind={kind} coef={coef} prec={prec} scatter={scatter}", flush=True)
+    mesh, space, x, c = _case(k)
+    c = c if coef else None
+    ref = oracle.OracleOp(space, kind, coef=c).apply(x)
+    op = mf.Operator(mf.Space.from_meshgen(space), kind, prec, vertex_coef=c, scatter=scatter)
+    assert op.info["nqp"] == (k + 1) ** 2
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_quad_paper_quadrature(mf, k):
+    """The paper's k+2 Gauss points per direction (Q6: 8 x 8, every lane a point)."""
+    import torch
+    print(f"quad nq1d=k+2 k={k}", flush=True)
+    mesh, space, x, c = _case(k)
+    sp = mf.Space.from_meshgen(space)
+    for kind, cf in ((HELM, None), (POIS, c)):
+        ref = oracle.OracleOp(space, kind, coef=cf, nq1d=k + 2).apply(x)
+        op = mf.Operator(sp, kind, mf.F64, nq1d=k + 2, vertex_coef=cf)
+        assert op.info["nqp"] == (k + 2) ** 2
+        y = op.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+        assert _relerr(y, ref) <= 1e-12, _relerr(y, ref)
+
+
+@pytest.mark.parametrize("k", [2, 5])
+def test_quad_dirichlet_range_errors(mf, k):
+    import torch
+    print(f"quad dirichlet/range k={k}", flush=True)
+    mesh, space, x, c = _case(k)
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    xm = x.copy()
+    xm[bnd] = 0.0
+    ref = oracle.OracleOp(space, HELM).apply(xm)
+    ref[bnd] = x[bnd]
+    sp = mf.Space.from_meshgen(space)
+    xt = torch.tensor(x, device="cuda")
+    for sc in (mf.SCATTER_ATOMIC, mf.SCATTER_COLOURED):
+        op = mf.Operator(sp, HELM, mf.F64, dirichlet=mask, scatter=sc)
+        assert _relerr(op.apply(xt).cpu().numpy(), ref) <= 1e-12
+    lap = mf.Operator(sp, LAP, mf.F64)
+    y = torch.zeros_like(xt)
+    for a, b in ((0, 37), (37, 38), (38, mesh.ncells)):
+        lap.apply_range(a, b, xt, y, accumulate=True)
+    assert _relerr(y.cpu().numpy(), oracle.OracleOp(space, LAP).apply(x)) <= 1e-12
+    with pytest.raises(mf.MFError):
+        lap.diagonal()
+    for bad in (k, k + 3):
+        with pytest.raises(mf.MFError):
+            mf.Operator(sp, LAP, mf.F64, nq1d=bad)
+    with pytest.raises(mf.MFError):
+        mf.Operator(sp, mf.ELASTICITY, mf.F64)
+
+
+def test_quad_single_cell_and_tangled(mf):
+    """One cell (a workgroup mostly idle) and the mesh check of a tangled cell."""
+    import torch
+    mesh = mg.quad_mesh(1)
+    space = mg.quad_space(mesh, 3, renumber=False)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, 3)
+    ref = oracle.OracleOp(space, HELM).apply(x)
+    op = mf.Operator(mf.Space.from_meshgen(space), HELM, mf.F64)
+    assert _relerr(op.apply(torch.tensor(x, device="cuda")).cpu().numpy(), ref) <= 1e-12
+    bad = mesh.cell2vert.copy()
+    bad[0, [2, 3]] = bad[0, [3, 2]]  # bow-tie: det J changes sign inside the cell
+    with pytest.raises(mf.MFError):
+        mf.Mesh(mg.CELL_QUAD, mesh.coords, bad)
+
+
+@pytest.mark.parametrize("k", [2, 6])
+def test_quad_large_sampled(mf, k):
+    """1024 x 1024 cells (Q6: 37.8 M dofs), Poisson, sampled outputs, both precisions."""
+    import torch
+    print(f"quad large k={k}", flush=True)
+    mesh = mg.quad_mesh(1024, 0.25, config=0)
+    space = mg.quad_space(mesh, k)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+    c = np.exp(np.random.default_rng(k).normal(size=mesh.nverts))
+    rng = np.random.default_rng(0)
+    nodes = rng.choice(space.nnodes, size=100, replace=False)
+    touch = np.isin(space.cell2node, nodes).any(axis=1)
+    sub = mg.Space(mg.Mesh(mesh.cell_type, mesh.coords, mesh.cell2vert[touch], mesh.lattice_m, mesh.vert_ijk),
+                   k, 1, space.cell2node[touch], space.nnodes)
+    ref = oracle.OracleOp(sub, POIS, coef=c).apply(x)
+    sp = mf.Space.from_meshgen(space)
+    for prec in (0, 1):
+        op = mf.Operator(sp, POIS, prec, vertex_coef=c)
+        y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+        assert np.abs(y[nodes] - ref[nodes]).max() / np.abs(ref[nodes]).max() <= TOL[prec]
+        del op
