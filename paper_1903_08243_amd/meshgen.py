@@ -154,8 +154,8 @@ def quad_mesh(m: int, perturb: float = 0.0, config: int = 0, seed_k: int = 0) ->
 
 
 def quad_space(mesh: Mesh, k: int, renumber: bool = True, config: int = 0,
-               seed_k: int | None = None) -> Space:
-    """Q_k nodes (one component): the k-refined lattice; local node (i, j), i fastest."""
+               seed_k: int | None = None, ncomp: int = 1) -> Space:
+    """Q_k nodes: the k-refined lattice; local node (i, j), i fastest."""
     m = mesh.lattice_m
     G = m * k + 1
     c = np.arange(m)
@@ -168,7 +168,7 @@ def quad_space(mesh: Mesh, k: int, renumber: bool = True, config: int = 0,
     lat_ij = _lattice(m * k, 2)
     node_ij = np.empty_like(lat_ij)
     node_ij[perm] = lat_ij
-    return Space(mesh, k, 1, perm[c2n].astype(np.int32), nn, node_ij, perm)
+    return Space(mesh, k, ncomp, perm[c2n].astype(np.int32), nn, node_ij, perm)
 
 
 def _permutation(nn: int, renumber: bool, config: int, k: int) -> np.ndarray:

@@ -124,3 +124,70 @@ def test_quad_detj_orientation():
     d = op.detj()
     assert d.min() > 0
     assert abs((d * op.qw[None, :]).sum() - 1.0) <= 1e-13
+
+
+def _1d_cross(k):
+    """A1[i, m] = int l_i' l_m over [0, 1] (first index differentiated)."""
+    x = _gll01(k)
+    t, w = L.leggauss(k + 3)
+    t, w = (t + 1) / 2, w / 2
+    n = k + 1
+    V = np.ones((t.size, n))
+    dV = np.zeros((t.size, n))
+    for i in range(n):
+        for m in range(n):
+            if m == i:
+                continue
+            V[:, i] *= (t - x[m]) / (x[i] - x[m])
+            term = np.full(t.size, 1.0 / (x[i] - x[m]))
+            for r in range(n):
+                if r != i and r != m:
+                    term *= (t - x[r]) / (x[i] - x[r])
+            dV[:, i] += term
+    return dV.T @ (w[:, None] * V)
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 6])
+def test_quad_elasticity_tensor_structure(k):
+    """Undistorted cell: block (c, c') of int sigma(u) : grad v is
+    mu delta_cc' (T00 + T11) + mu T_c'c + lam T_cc', T_pq[d, d'] = int d_p phi_d d_q phi_d'."""
+    lam, mu = 0.7, 0.4
+    mesh = mg.quad_mesh(1)
+    space = mg.quad_space(mesh, k, renumber=False, ncomp=2)
+    Ae = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=lam, mu=mu).element_matrices()[0]
+    M1, K1 = _1d_matrices(k)
+    A1 = _1d_cross(k)
+    T = {(0, 0): np.kron(M1, K1), (1, 1): np.kron(K1, M1), (0, 1): np.kron(A1.T, A1)}
+    T[(1, 0)] = T[(0, 1)].T
+    D = (k + 1) ** 2
+    ref = np.zeros((2 * D, 2 * D))
+    for c in range(2):
+        for cp in range(2):
+            blk = mu * T[(cp, c)] + lam * T[(c, cp)]
+            if c == cp:
+                blk = blk + mu * (T[(0, 0)] + T[(1, 1)])
+            ref[c::2, cp::2] = blk  # dof = 2 node + component
+    assert np.abs(Ae - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_quad_elasticity_invariants(k):
+    """Perturbed mesh: rigid motions in the null space, the linear-field patch test
+    and its energy area * (lam tr(eps)^2 + 2 mu eps:eps)."""
+    lam, mu = 1.0, 0.5
+    mesh = mg.quad_mesh(4, 0.25, config=0)
+    space = mg.quad_space(mesh, k, ncomp=2)
+    op = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=lam, mu=mu)
+    xy = _node_xy(mesh, space)
+    X, Y = xy[:, 0], xy[:, 1]
+    for ux, uy in ((np.ones_like(X), 0 * X), (0 * X, np.ones_like(X)), (-Y, X)):
+        u = np.stack([ux, uy], axis=1).ravel()
+        assert np.abs(op.apply(u)).max() <= 1e-12
+    G = np.array([[0.3, -1.1], [0.7, 0.9]])  # u = G (x, y) + const
+    u = np.stack([G[0, 0] * X + G[0, 1] * Y + 0.2, G[1, 0] * X + G[1, 1] * Y - 0.4], axis=1).ravel()
+    y = op.apply(u).reshape(-1, 2)
+    interior = np.setdiff1d(np.arange(space.nnodes), space.boundary_nodes())
+    assert np.abs(y[interior]).max() <= 1e-12
+    eps = (G + G.T) / 2
+    energy = lam * np.trace(eps) ** 2 + 2 * mu * (eps * eps).sum()
+    assert abs(u @ y.ravel() - energy) <= 1e-12
