@@ -724,11 +724,14 @@ static void count_work(mf_op *op) {
     // pass q^2 n per value or gradient component, backward passes the same in reverse;
     // per point: Jacobian and |det| w 14, coefficient 13, value 2, gradient push-forward
     // and flux 17
-    const double n = op->degree + 1, q = op->nq1d;
+    // (per component; elasticity: two components, and its stress 10 flops per point)
+    const double n = op->degree + 1, q = op->nq1d, C = comps;
     const bool val = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ, grad = op->kind != MF_OP_MASS;
     const double g = grad ? 1.0 : 0.0, v = val ? 1.0 : 0.0;
-    const double fma = q * n * n * (1 + g) + q * q * n * (v + 2 * g) + q * q * n * (v + 2 * g) + q * n * n * (1 + g);
-    const double pt = 14.0 + (op->has_coef ? 13.0 : 0.0) + 2.0 * v + 17.0 * g;
+    const double fma =
+        C * (q * n * n * (1 + g) + q * q * n * (v + 2 * g) + q * q * n * (v + 2 * g) + q * n * n * (1 + g));
+    const double pt = 14.0 + (op->has_coef ? 13.0 : 0.0) + 2.0 * v + 5.0 * g + 12.0 * g * C +
+                      (op->kind == MF_OP_ELASTICITY ? 10.0 : 0.0);
     fl = nc * (2.0 * fma + q * q * pt);
     by += nc * 6.0 * s + (op->has_coef ? nc * 4.0 * s : 0.0);
   } else if (op->cell_type == MF_CELL_TET && op->ncomp == 1) {
@@ -783,7 +786,7 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     return launch_hex_apply<T>(op->degree + 1, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_QUAD) {
     QuadArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
-                  op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi};
+                  op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, (T)op->lam, (T)op->mu};
     return launch_quad<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
@@ -897,7 +900,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (ct == MF_CELL_HEX)
     ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3) : (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else if (ct == MF_CELL_QUAD)
-    ok = kind <= MF_OP_POISSON && sp->ncomp == 1;
+    ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);
   else if (ct == MF_CELL_TET)
     ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3) ||
          (kind <= MF_OP_POISSON && sp->ncomp == 1);

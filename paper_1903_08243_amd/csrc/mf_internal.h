@@ -182,17 +182,19 @@ int tet_mfma_table_floats(int k, int nq);
 void tet_mfma_tables(int k, int nq, const double *dphi, double *out, bool f64);
 
 // Q1..Q6 on bilinear quadrilaterals (quad_kernels.hip): one-component MASS, HELMHOLTZ,
-// LAPLACIAN, POISSON, sum-factorised, nq = k+1 or k+2 Gauss points per direction
+// LAPLACIAN, POISSON and two-component ELASTICITY, sum-factorised, nq = k+1 or k+2
+// Gauss points per direction
 template <typename T> struct QuadArgs {
   const int32_t *map;  // [ncells][(k+1)^2] node ids, dof i + (k+1) j (negative: constrained)
   const T *geo;        // [ncells][6]: bilinear map coefficients c1, c2, c3 as (x, y) pairs
   const T *coef;       // [ncells][4] vertex coefficients (MASS c, POISSON kappa), or null
   const T *tab;        // B [nq][k+1], B' [nq][k+1], weights [nq], points [nq]
-  const T *x;
+  const T *x;          // ELASTICITY: two components per node, interleaved
   T *y;
   int64_t c0, c1;
   const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
   int64_t ulo, uhi;
+  T lam, mu;  // ELASTICITY Lame parameters
 };
 template <typename T>
 int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s);

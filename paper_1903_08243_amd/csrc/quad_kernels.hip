@@ -1,4 +1,5 @@
-// Operator action on bilinear quadrilaterals, Q_k (k = 1..6) on GLL nodes.
+// Operator action on bilinear quadrilaterals, Q_k (k = 1..6) on GLL nodes: the
+// one-component forms and 2D linear elasticity.
 //
 // Quads are the 2D tensor-product cells of the paper's sweep (Section 4.1): the
 // coordinate map is bilinear, so the Jacobian is evaluated at every quadrature point
@@ -23,18 +24,21 @@ __device__ __forceinline__ void quad_atomic_add(float *p, float v) { unsafeAtomi
 
 // N = k + 1 nodes and NQ Gauss points per direction. tab: B[a][i] = l_i(g_a) [NQ][N],
 // B'[a][i] [NQ][N], weights [NQ], points [NQ]. atomic: device atomics for the scatter,
-// else plain read-modify-write (the cells of one launch share no node).
+// else plain read-modify-write (the cells of one launch share no node). ELASTICITY has
+// two components (node-interleaved dofs), the others one.
 template <typename T, int N, int NQ, int KIND>
 __global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const bool atomic) {
   constexpr int P = NQ * NQ, CPW = 64 / P, D = N * N, H = NQ * N;
+  constexpr bool ELAS = KIND == MF_OP_ELASTICITY;
+  constexpr int NC = ELAS ? 2 : 1;
   constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
   constexpr bool GRAD = KIND != MF_OP_MASS;
   constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
   static_assert(NQ >= N && P <= 64, "one lane per point, and every dof has a lane");
   __shared__ T sB[H], sD[H], sw[NQ], sg[NQ];
-  __shared__ T U[CPW][D];             // gathered dof values
-  __shared__ T X0[CPW][H], X1[CPW][H];  // (a, j) fields, forward, then backward
-  __shared__ T F0[CPW][P], F1[CPW][P], F2[CPW][P];  // value flux, reference-gradient fluxes
+  __shared__ T U[CPW][NC][D];                 // gathered dof values
+  __shared__ T X0[CPW][NC][H], X1[CPW][NC][H];  // (a, j) fields, forward, then backward
+  __shared__ T F0[CPW][P], F1[CPW][NC][P], F2[CPW][NC][P];  // value flux, reference fluxes
   const int lane = threadIdx.x;
   const int slot = lane / P, p = lane - slot * P;
   const bool act = slot < CPW;  // the last 64 mod P lanes idle
@@ -59,33 +63,43 @@ __global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const boo
   }
   int idx = -1;  // node of dof p (negative: constrained or no cell)
   if (valid && p < D) idx = A.map[cell * D + p];
-  if (act && p < D) U[slot][p] = idx >= 0 ? A.x[idx] : T(0);
+  if (act && p < D)
+#pragma unroll
+    for (int c = 0; c < NC; c++) U[slot][c][p] = idx >= 0 ? A.x[(int64_t)idx * NC + c] : T(0);
   __syncthreads();
   // forward x pass, lane (a, j): sum over nodes i in x
   if (act && p < H) {
     const int a = p % NQ, j = p / NQ;
-    T s0 = T(0), s1 = T(0);
 #pragma unroll
-    for (int i = 0; i < N; i++) {
-      const T u = U[slot][i + N * j];
-      s0 += sB[a * N + i] * u;
-      if constexpr (GRAD) s1 += sD[a * N + i] * u;
+    for (int c = 0; c < NC; c++) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int i = 0; i < N; i++) {
+        const T u = U[slot][c][i + N * j];
+        s0 += sB[a * N + i] * u;
+        if constexpr (GRAD) s1 += sD[a * N + i] * u;
+      }
+      X0[slot][c][p] = s0;
+      if constexpr (GRAD) X1[slot][c][p] = s1;
     }
-    X0[slot][p] = s0;
-    if constexpr (GRAD) X1[slot][p] = s1;
   }
   __syncthreads();
   // forward y pass and the pointwise fluxes, lane (a, b)
   if (act) {
     const int a = p % NQ, b = p / NQ;
-    T u = T(0), gx = T(0), gy = T(0);  // value and reference gradient at the point
+    T u = T(0), gx[NC], gy[NC];  // value and reference gradients at the point
+#pragma unroll
+    for (int c = 0; c < NC; c++) gx[c] = gy[c] = T(0);
 #pragma unroll
     for (int j = 0; j < N; j++) {
-      const T x0 = X0[slot][a + NQ * j];
-      if constexpr (VAL) u += sB[b * N + j] * x0;
-      if constexpr (GRAD) {
-        gx += sB[b * N + j] * X1[slot][a + NQ * j];
-        gy += sD[b * N + j] * x0;
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        const T x0 = X0[slot][c][a + NQ * j];
+        if constexpr (VAL) u += sB[b * N + j] * x0;
+        if constexpr (GRAD) {
+          gx[c] += sB[b * N + j] * X1[slot][c][a + NQ * j];
+          gy[c] += sD[b * N + j] * x0;
+        }
       }
     }
     // x(xi, eta) = x0 + c1 xi + c2 eta + c3 xi eta per coordinate; a lane without a
@@ -112,50 +126,82 @@ __global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const boo
       cq = (T(1) - xi) * (T(1) - eta) * cv[0] + xi * (T(1) - eta) * cv[1] + (T(1) - xi) * eta * cv[2] +
            xi * eta * cv[3];
     }
-    T f0 = T(0), P0 = T(0), P1 = T(0);
+    T f0 = T(0), P0[NC], P1[NC];
     if constexpr (VAL) f0 = wdet * (KIND == MF_OP_MASS ? cq : T(1)) * u;
     if constexpr (GRAD) {
       // J^{-1} = [[J11, -J01], [-J10, J00]] / det; physical gradient G_a = sum_b
-      // (J^{-1})[b][a] g_b, then the reference-direction flux P_b = s sum_a (J^{-1})[b][a] G_a
+      // (J^{-1})[b][a] g_b, then the reference-direction flux P_b = s sum_a (J^{-1})[b][a] S_a
+      // of the physical flux S (the gradient itself, kappa times it, or the stress)
       const T r = T(1) / det;
-      const T G0 = (J11 * gx - J10 * gy) * r, G1 = (J00 * gy - J01 * gx) * r;
-      const T s = wdet * (KIND == MF_OP_POISSON ? cq : T(1)) * r;
-      P0 = s * (J11 * G0 - J01 * G1);
-      P1 = s * (J00 * G1 - J10 * G0);
+      T G[NC][2];
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        G[c][0] = (J11 * gx[c] - J10 * gy[c]) * r;
+        G[c][1] = (J00 * gy[c] - J01 * gx[c]) * r;
+      }
+      T S[NC][2];
+      if constexpr (ELAS) {
+        // sigma = lambda tr(grad u) I + mu (grad u + grad u^T)
+        const T tr = A.lam * (G[0][0] + G[1][1]), od = A.mu * (G[0][1] + G[1][0]);
+        S[0][0] = tr + T(2) * A.mu * G[0][0];
+        S[1][1] = tr + T(2) * A.mu * G[1][1];
+        S[0][1] = od;
+        S[1][0] = od;
+      } else {
+        S[0][0] = G[0][0];
+        S[0][1] = G[0][1];
+      }
+      const T sc = wdet * (KIND == MF_OP_POISSON ? cq : T(1)) * r;
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        P0[c] = sc * (J11 * S[c][0] - J01 * S[c][1]);
+        P1[c] = sc * (J00 * S[c][1] - J10 * S[c][0]);
+      }
     }
     F0[slot][p] = f0;
-    F1[slot][p] = P0;
-    F2[slot][p] = P1;
+    if constexpr (GRAD)
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        F1[slot][c][p] = P0[c];
+        F2[slot][c][p] = P1[c];
+      }
   }
   __syncthreads();
   // backward y pass, lane (a, j): integrate against the test functions in y
   if (act && p < H) {
     const int a = p % NQ, j = p / NQ;
-    T y0 = T(0), y1 = T(0);
 #pragma unroll
-    for (int b = 0; b < NQ; b++) {
-      const int q = a + NQ * b;
-      if constexpr (VAL) y0 += sB[b * N + j] * F0[slot][q];
-      if constexpr (GRAD) {
-        y0 += sD[b * N + j] * F2[slot][q];
-        y1 += sB[b * N + j] * F1[slot][q];
+    for (int c = 0; c < NC; c++) {
+      T y0 = T(0), y1 = T(0);
+#pragma unroll
+      for (int b = 0; b < NQ; b++) {
+        const int q = a + NQ * b;
+        if constexpr (VAL) y0 += sB[b * N + j] * F0[slot][q];
+        if constexpr (GRAD) {
+          y0 += sD[b * N + j] * F2[slot][c][q];
+          y1 += sB[b * N + j] * F1[slot][c][q];
+        }
       }
+      X0[slot][c][p] = y0;
+      if constexpr (GRAD) X1[slot][c][p] = y1;
     }
-    X0[slot][p] = y0;
-    if constexpr (GRAD) X1[slot][p] = y1;
   }
   __syncthreads();
   // backward x pass, lane (i, j), and the scatter
   if (act && p < D && idx >= 0) {
     const int i = p % N, j = p / N;
-    T v = T(0);
 #pragma unroll
-    for (int a = 0; a < NQ; a++) {
-      v += sB[a * N + i] * X0[slot][a + NQ * j];
-      if constexpr (GRAD) v += sD[a * N + i] * X1[slot][a + NQ * j];
+    for (int c = 0; c < NC; c++) {
+      T v = T(0);
+#pragma unroll
+      for (int a = 0; a < NQ; a++) {
+        v += sB[a * N + i] * X0[slot][c][a + NQ * j];
+        if constexpr (GRAD) v += sD[a * N + i] * X1[slot][c][a + NQ * j];
+      }
+      T *yp = A.y + (int64_t)idx * NC + c;
+      if (atomic) quad_atomic_add(yp, v);
+      else *yp += v;
     }
-    if (atomic) quad_atomic_add(&A.y[idx], v);
-    else A.y[idx] += v;
   }
 }
 
@@ -176,6 +222,7 @@ static int launch_quad_nq(int kind, const QuadArgs<T> &a, bool atomic, hipStream
     case MF_OP_HELMHOLTZ: return launch_quad_nk<T, N, NQ, MF_OP_HELMHOLTZ>(a, atomic, s);
     case MF_OP_LAPLACIAN: return launch_quad_nk<T, N, NQ, MF_OP_LAPLACIAN>(a, atomic, s);
     case MF_OP_POISSON: return launch_quad_nk<T, N, NQ, MF_OP_POISSON>(a, atomic, s);
+    case MF_OP_ELASTICITY: return launch_quad_nk<T, N, NQ, MF_OP_ELASTICITY>(a, atomic, s);
   }
   return fail(MF_EUNSUPPORTED, "quad operator kind");
 }

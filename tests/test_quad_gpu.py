@@ -1,5 +1,5 @@
-"""GPU parity of the one-component operators on Q1..Q6 quadrilaterals (mass with and
-without a vertex coefficient, Helmholtz, Laplacian, Poisson) against the oracle, through
+"""GPU parity of the operators on Q1..Q6 quadrilaterals (mass with and without a vertex
+coefficient, Helmholtz, Laplacian, Poisson, 2D elasticity) against the oracle, through
 the C-ABI: both scatter modes, both precisions, k+1 and k+2 Gauss points per direction,
 Dirichlet rows, range applies, a ragged cell count and sampled outputs at 1024^2 cells."""
 import numpy as np
@@ -96,7 +96,7 @@ def test_quad_dirichlet_range_errors(mf, k):
         with pytest.raises(mf.MFError):
             mf.Operator(sp, LAP, mf.F64, nq1d=bad)
     with pytest.raises(mf.MFError):
-        mf.Operator(sp, mf.ELASTICITY, mf.F64)
+        mf.Operator(sp, mf.ELASTICITY, mf.F64)  # one component
 
 
 def test_quad_single_cell_and_tangled(mf):
@@ -135,3 +135,46 @@ def test_quad_large_sampled(mf, k):
         y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
         assert np.abs(y[nodes] - ref[nodes]).max() / np.abs(ref[nodes]).max() <= TOL[prec]
         del op
+
+
+@pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
+def test_quad_elasticity(mf, k, prec, scatter):
+    """2D linear elasticity (two node-interleaved components), lambda 0.7, mu 0.4."""
+    import torch
+    print(f"quad elasticity k={k} prec={prec} scatter={scatter}", flush=True)
+    mesh = mg.quad_mesh(11, 0.25, config=0)
+    space = mg.quad_space(mesh, k, seed_k=k, ncomp=2)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+    ref = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=0.7, mu=0.4).apply(x)
+    op = mf.Operator(mf.Space.from_meshgen(space), mf.ELASTICITY, prec, lam=0.7, mu=0.4, scatter=scatter)
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+
+
+@pytest.mark.parametrize("k", [2, 6])
+def test_quad_elasticity_dirichlet_paper_rule(mf, k):
+    """Clamped boundary (both components) with the paper's k+2 points, and a range apply."""
+    import torch
+    print(f"quad elasticity dirichlet k={k}", flush=True)
+    mesh = mg.quad_mesh(11, 0.25, config=0)
+    space = mg.quad_space(mesh, k, seed_k=k, ncomp=2)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    bd = np.stack([2 * bnd, 2 * bnd + 1], axis=1).ravel()
+    xm = x.copy()
+    xm[bd] = 0.0
+    ref = oracle.OracleOp(space, oracle.OP_ELASTICITY, nq1d=k + 2).apply(xm)
+    ref[bd] = x[bd]
+    sp = mf.Space.from_meshgen(space)
+    xt = torch.tensor(x, device="cuda")
+    op = mf.Operator(sp, mf.ELASTICITY, mf.F64, nq1d=k + 2, dirichlet=mask)
+    assert _relerr(op.apply(xt).cpu().numpy(), ref) <= 1e-12
+    op = mf.Operator(sp, mf.ELASTICITY, mf.F64)
+    y = torch.zeros_like(xt)
+    for a, b in ((0, 60), (60, mesh.ncells)):
+        op.apply_range(a, b, xt, y, accumulate=True)
+    assert _relerr(y.cpu().numpy(), oracle.OracleOp(space, oracle.OP_ELASTICITY).apply(x)) <= 1e-12
