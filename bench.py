@@ -247,8 +247,9 @@ def bench_simplex(mf, mg, reps=20):
     del tmesh
     # Q_k quadrilaterals (2D sum factorisation, lane per point), 1024 x 1024 cells
     qmesh = mg.quad_mesh(1024, 0.25, config=0)
-    for k, kind, name in ((2, mf.HELMHOLTZ, "helmholtz"), (6, mf.LAPLACIAN, "laplacian")):
-        space = mg.quad_space(qmesh, k)
+    for k, kind, name, nc in ((2, mf.HELMHOLTZ, "helmholtz", 1), (6, mf.LAPLACIAN, "laplacian", 1),
+                              (2, mf.ELASTICITY, "elasticity", 2)):
+        space = mg.quad_space(qmesh, k, ncomp=nc)
         sp = mf.Space.from_meshgen(space)
         x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
         for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):

@@ -847,9 +847,13 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
 // scalar operators they break even at about 64^3 cells (Q1: 51 against 55 us, Q2:
 // 142 against 127 us in FP64) and win above (Q1 at 128^3: 238 against 346 us, Q2 at
 // 96^3: 364 against 458 us). For P2/P3 tet elasticity on 48^3 x 6 cells (31
-// colours) the coloured launches are 1.1x (FP64) to 3.4x (FP32) faster.
+// colours) the coloured launches are 1.1x (FP64) to 3.4x (FP32) faster. Quads (4
+// colours): the two scatters are within a few percent for the one-component operators
+// (atomic ahead at 256^2 cells), and the coloured launches win for elasticity (Q2 at
+// 1024^2 cells: 390 against 527 us in FP64, 251 against 379 us in FP32).
 static bool default_coloured(const mf_op *op) {
   if (op->ncells < 4096) return false;
+  if (op->cell_type == MF_CELL_QUAD) return op->ncomp == 2;
   if (op->cell_type == MF_CELL_HEX) {
     if (op->ncomp == 3 && op->degree >= 2) return true;
     return op->ncells >= (op->degree == 1 ? (1 << 19) : (1 << 18));

@@ -225,7 +225,7 @@ static int launch_tet_scalar_k(int kind, const TetArgs<T> &a, bool atomic, hipSt
 }
 
 // rules of the tet quadrature table: 1 point (degree 1), 4 (degree 2), 14 (degree 5),
-// 125 (collapsed product rule, degree 7)
+// 64 (conical Gauss-Jacobi product rule, degree 7)
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
   if (k == 1 && nq == 1) return launch_tet_scalar_k<T, 1, 1>(kind, a, atomic, s);
@@ -234,7 +234,7 @@ int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic,
   if (k == 2 && nq == 4) return launch_tet_scalar_k<T, 2, 4>(kind, a, atomic, s);
   if (k == 2 && nq == 14) return launch_tet_scalar_k<T, 2, 14>(kind, a, atomic, s);
   if (k == 3 && nq == 14) return launch_tet_scalar_k<T, 3, 14>(kind, a, atomic, s);
-  if (k == 3 && nq == 125) return launch_tet_scalar_k<T, 3, 125>(kind, a, atomic, s);  // degree 6-7
+  if (k == 3 && nq == 64) return launch_tet_scalar_k<T, 3, 64>(kind, a, atomic, s);  // degree 6-7
   return fail(MF_EUNSUPPORTED, "tet scalar operator: degree / rule");
 }
 template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);

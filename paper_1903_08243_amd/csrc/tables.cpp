@@ -120,6 +120,58 @@ int tet_ndofs(int k) { return (k + 1) * (k + 2) * (k + 3) / 6; }
 //   degree 1: centroid;  degree 2: 4 points (a,a,a,1-3a) with a = (5 - sqrt 5)/20;
 //   degree 5: 14 points -- two (a,a,a,1-3a) orbits and one (a,a,1/2-a,1/2-a) orbit
 //   (the positive-weight 14-point rule of Walkington / Keast).
+// Gauss-Jacobi rule on [0, 1] for the weight (1 - u)^alpha: the n nodes are the roots
+// of the Jacobi polynomial P_n^(alpha, 0)(2u - 1), found by Newton's method with
+// deflation against the roots already found; with s = 2u - 1 the weights on [-1, 1],
+// 2^(alpha+1) / ((1 - s^2) P_n'(s)^2), shrink by 2^-(alpha+1) on [0, 1]. The three-term
+// recurrence and the derivative identity
+//   (2n + alpha)(1 - s^2) P_n' = n (alpha - (2n + alpha) s) P_n + 2 n (n + alpha) P_(n-1)
+// are the standard ones for beta = 0.
+static void gauss_jacobi01(int n, int alpha, std::vector<double> &x, std::vector<double> &w) {
+  const double a = alpha;
+  auto eval = [&](double s, double &pn, double &dpn) {
+    double p0 = 1.0, p1 = 0.5 * ((a + 2.0) * s + a);
+    if (n == 1) {
+      pn = p1;
+      p1 = p0;
+    } else {
+      for (int k = 2; k <= n; k++) {
+        const double c = 2.0 * k + a;
+        const double p2 = ((c - 1.0) * (c * (c - 2.0) * s + a * a) * p1 - 2.0 * (k + a - 1.0) * (k - 1.0) * c * p0) /
+                          (2.0 * k * (k + a) * (c - 2.0));
+        p0 = p1;
+        p1 = p2;
+      }
+      pn = p1;
+      p1 = p0;  // P_(n-1)
+    }
+    dpn = (n * (a - (2.0 * n + a) * s) * pn + 2.0 * n * (n + a) * p1) / ((2.0 * n + a) * (1.0 - s * s));
+  };
+  std::vector<double> r;
+  for (int i = 0; i < n; i++) {
+    double s = -std::cos((2.0 * i + 1.0) * M_PI / (2.0 * n));  // ascending start values
+    for (int it = 0; it < 100; it++) {
+      double p, dp;
+      eval(s, p, dp);
+      double defl = 0.0;
+      for (double q : r) defl += 1.0 / (s - q);
+      const double ds = p / (dp - p * defl);
+      s -= ds;
+      if (std::fabs(ds) < 1e-16) break;
+    }
+    r.push_back(s);
+  }
+  std::sort(r.begin(), r.end());
+  x.resize(n);
+  w.resize(n);
+  for (int i = 0; i < n; i++) {
+    double p, dp;
+    eval(r[i], p, dp);
+    x[i] = 0.5 * (r[i] + 1.0);
+    w[i] = 1.0 / ((1.0 - r[i] * r[i]) * dp * dp);
+  }
+}
+
 bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
   pts.clear();
   w.clear();
@@ -153,20 +205,24 @@ bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
     s31(0.3108859192633006, 0.1126879257180159 / 6.0);
     s22(0.0455037041256496, 0.0425460207770812 / 6.0);
   } else if (degree <= 7) {
-    // collapsed Gauss product rule: x = u, y = v (1 - u), z = w (1 - u)(1 - v), Jacobian
-    // (1 - u)^2 (1 - v); a degree-p monomial becomes degree p + 2 in u, p + 1 in v and p
-    // in w, so n = ceil((p + 3) / 2) points per direction integrate it exactly
-    const int n = (degree + 4) / 2;
-    std::vector<double> x, wx;
-    gauss_legendre(n, x, wx);
+    // conical product rule: x = u, y = v (1 - u), z = t (1 - u)(1 - v), Jacobian
+    // (1 - u)^2 (1 - v). A degree-p monomial has degree at most p in each of u, v, t, so
+    // Gauss-Jacobi rules for the weights (1 - u)^2 and (1 - v), which absorb the
+    // Jacobian, and Gauss-Legendre in t, each with n = 4 points (exact to degree 7),
+    // integrate it exactly: 64 points
+    const int n = 4;
+    std::vector<double> xu, wu, xv, wv, xt, wt;
+    gauss_jacobi01(n, 2, xu, wu);
+    gauss_jacobi01(n, 1, xv, wv);
+    gauss_legendre(n, xt, wt);
     for (int i = 0; i < n; i++)
       for (int j = 0; j < n; j++)
         for (int l = 0; l < n; l++) {
-          const double u = x[i], v = x[j], t = x[l];
+          const double u = xu[i], v = xv[j], t = xt[l];
           pts.push_back(u);
           pts.push_back(v * (1.0 - u));
           pts.push_back(t * (1.0 - u) * (1.0 - v));
-          w.push_back(wx[i] * wx[j] * wx[l] * (1.0 - u) * (1.0 - u) * (1.0 - v));
+          w.push_back(wu[i] * wv[j] * wt[l]);
         }
   } else {
     return false;
