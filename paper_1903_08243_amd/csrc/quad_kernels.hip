@@ -22,10 +22,18 @@ __device__ __forceinline__ void quad_atomic_add(double *p, double v) { unsafeAto
 __device__ __forceinline__ void quad_atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
 }  // namespace
 
+// Cell groups (64 / nq^2 cells side by side) per workgroup, run as a software pipeline.
+constexpr int kQuadGroups = 8;
+
 // N = k + 1 nodes and NQ Gauss points per direction. tab: B[a][i] = l_i(g_a) [NQ][N],
 // B'[a][i] [NQ][N], weights [NQ], points [NQ]. atomic: device atomics for the scatter,
 // else plain read-modify-write (the cells of one launch share no node). ELASTICITY has
 // two components (node-interleaved dofs), the others one.
+//
+// A workgroup takes kQuadGroups consecutive cell groups. While group t is computed, the
+// x values, geometry and coefficients of group t+1 and the map entries of group t+2
+// are in flight, so the two dependent global loads of a group (map, then x) are hidden
+// behind the arithmetic and LDS passes of the groups before it.
 template <typename T, int N, int NQ, int KIND>
 __global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const bool atomic) {
   constexpr int P = NQ * NQ, CPW = 64 / P, D = N * N, H = NQ * N;
@@ -44,15 +52,12 @@ __global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const boo
   const bool act = slot < CPW;  // the last 64 mod P lanes idle
   // consecutive workgroup ids land on different XCDs: give each XCD a contiguous run of
   // cell groups (its L2 then holds the nodes its neighbouring cells share)
-  const int64_t ngrp = (A.c1 - A.c0 + CPW - 1) / CPW, per = (ngrp + 7) / 8;
-  const int64_t grp = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (grp >= ngrp) return;  // uniform over the workgroup
-  const int64_t cell = A.c0 + grp * CPW + slot;
-  bool valid = act && cell < A.c1;
-  if (valid && A.cell_user) {
-    const int64_t u = A.cell_user[cell];
-    valid = u >= A.ulo && u < A.uhi;
-  }
+  const int64_t ngrp = (A.c1 - A.c0 + CPW - 1) / CPW, nwg = (ngrp + kQuadGroups - 1) / kQuadGroups;
+  const int64_t per = (nwg + 7) / 8;
+  const int64_t wg = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (wg >= nwg) return;  // uniform over the workgroup
+  const int64_t gbase = wg * kQuadGroups;
+  const int ng = (int)(ngrp - gbase < kQuadGroups ? ngrp - gbase : kQuadGroups);  // uniform
   if (lane < H) {
     sB[lane] = A.tab[lane];
     sD[lane] = A.tab[H + lane];
@@ -61,155 +66,201 @@ __global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const boo
     sw[lane] = A.tab[2 * H + lane];
     sg[lane] = A.tab[2 * H + NQ + lane];
   }
-  int idx = -1;  // node of dof p (negative: constrained or no cell)
-  if (valid && p < D) idx = A.map[cell * D + p];
-  if (act && p < D)
-#pragma unroll
-    for (int c = 0; c < NC; c++) U[slot][c][p] = idx >= 0 ? A.x[(int64_t)idx * NC + c] : T(0);
-  __syncthreads();
-  // forward x pass, lane (a, j): sum over nodes i in x
-  if (act && p < H) {
-    const int a = p % NQ, j = p / NQ;
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-      T s0 = T(0), s1 = T(0);
-#pragma unroll
-      for (int i = 0; i < N; i++) {
-        const T u = U[slot][c][i + N * j];
-        s0 += sB[a * N + i] * u;
-        if constexpr (GRAD) s1 += sD[a * N + i] * u;
+  // stage 1 of group t: is this lane's cell in the launch, and the node of its dof p
+  auto load_map = [&](int t, bool &v, int &idx) {
+    v = false;
+    idx = -1;
+    if (t < ng && act) {
+      const int64_t cell = A.c0 + (gbase + t) * CPW + slot;
+      v = cell < A.c1;
+      if (v && A.cell_user) {
+        const int64_t u = A.cell_user[cell];
+        v = u >= A.ulo && u < A.uhi;
       }
-      X0[slot][c][p] = s0;
-      if constexpr (GRAD) X1[slot][c][p] = s1;
+      if (v && p < D) idx = A.map[cell * D + p];
     }
-  }
-  __syncthreads();
-  // forward y pass and the pointwise fluxes, lane (a, b)
-  if (act) {
-    const int a = p % NQ, b = p / NQ;
-    T u = T(0), gx[NC], gy[NC];  // value and reference gradients at the point
+  };
+  // stage 2: the dof values, the bilinear map x(xi, eta) = x0 + c1 xi + c2 eta + c3 xi eta
+  // (c1, c2, c3 as (x, y) pairs) and the vertex coefficients; a lane without a cell takes
+  // the unit square so that its discarded arithmetic stays finite
+  auto load_data = [&](int t, bool v, int idx, T *xv, T *gm, T *cf) {
 #pragma unroll
-    for (int c = 0; c < NC; c++) gx[c] = gy[c] = T(0);
+    for (int c = 0; c < NC; c++) xv[c] = idx >= 0 ? A.x[(int64_t)idx * NC + c] : T(0);
+    gm[0] = T(1);
+    gm[1] = T(0);
+    gm[2] = T(0);
+    gm[3] = T(1);
+    gm[4] = T(0);
+    gm[5] = T(0);
 #pragma unroll
-    for (int j = 0; j < N; j++) {
+    for (int m = 0; m < 4; m++) cf[m] = T(1);
+    if (v) {
+      const int64_t cell = A.c0 + (gbase + t) * CPW + slot;
+#pragma unroll
+      for (int m = 0; m < 6; m++) gm[m] = A.geo[cell * 6 + m];
+      if (COEF && A.coef)
+#pragma unroll
+        for (int m = 0; m < 4; m++) cf[m] = A.coef[cell * 4 + m];
+    }
+  };
+  bool v0, v1;
+  int i0, i1;
+  T xv0[NC], gm0[6], cf0[4];
+  load_map(0, v0, i0);
+  load_data(0, v0, i0, xv0, gm0, cf0);
+  load_map(1, v1, i1);
+  for (int t = 0; t < ng; t++) {
+    T xv1[NC], gm1[6], cf1[4];
+    bool v2;
+    int i2;
+    load_data(t + 1, v1, i1, xv1, gm1, cf1);
+    load_map(t + 2, v2, i2);
+    __syncthreads();  // the previous group's last LDS reads are done
+    if (act && p < D)
+#pragma unroll
+      for (int c = 0; c < NC; c++) U[slot][c][p] = xv0[c];
+    __syncthreads();
+    // forward x pass, lane (a, j): sum over nodes i in x
+    if (act && p < H) {
+      const int a = p % NQ, j = p / NQ;
 #pragma unroll
       for (int c = 0; c < NC; c++) {
-        const T x0 = X0[slot][c][a + NQ * j];
-        if constexpr (VAL) u += sB[b * N + j] * x0;
-        if constexpr (GRAD) {
-          gx[c] += sB[b * N + j] * X1[slot][c][a + NQ * j];
-          gy[c] += sD[b * N + j] * x0;
+        T s0 = T(0), s1 = T(0);
+#pragma unroll
+        for (int i = 0; i < N; i++) {
+          const T u = U[slot][c][i + N * j];
+          s0 += sB[a * N + i] * u;
+          if constexpr (GRAD) s1 += sD[a * N + i] * u;
+        }
+        X0[slot][c][p] = s0;
+        if constexpr (GRAD) X1[slot][c][p] = s1;
+      }
+    }
+    __syncthreads();
+    // forward y pass and the pointwise fluxes, lane (a, b)
+    if (act) {
+      const int a = p % NQ, b = p / NQ;
+      T u = T(0), gx[NC], gy[NC];  // value and reference gradients at the point
+#pragma unroll
+      for (int c = 0; c < NC; c++) gx[c] = gy[c] = T(0);
+#pragma unroll
+      for (int j = 0; j < N; j++) {
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+          const T x0 = X0[slot][c][a + NQ * j];
+          if constexpr (VAL) u += sB[b * N + j] * x0;
+          if constexpr (GRAD) {
+            gx[c] += sB[b * N + j] * X1[slot][c][a + NQ * j];
+            gy[c] += sD[b * N + j] * x0;
+          }
         }
       }
-    }
-    // x(xi, eta) = x0 + c1 xi + c2 eta + c3 xi eta per coordinate; a lane without a
-    // cell takes the unit square so that its (discarded) arithmetic stays finite
-    T c1x = T(1), c1y = T(0), c2x = T(0), c2y = T(1), c3x = T(0), c3y = T(0);
-    if (valid) {
-      const T *g = A.geo + cell * 6;
-      c1x = g[0];
-      c1y = g[1];
-      c2x = g[2];
-      c2y = g[3];
-      c3x = g[4];
-      c3y = g[5];
-    }
-    const T xi = sg[a], eta = sg[b];
-    // J[r][c] = d x_r / d xi_c
-    const T J00 = c1x + c3x * eta, J01 = c2x + c3x * xi;
-    const T J10 = c1y + c3y * eta, J11 = c2y + c3y * xi;
-    const T det = J00 * J11 - J01 * J10;
-    const T wdet = sw[a] * sw[b] * (det < T(0) ? -det : det);
-    T cq = T(1);
-    if (COEF && A.coef && valid) {
-      const T *cv = A.coef + cell * 4;
-      cq = (T(1) - xi) * (T(1) - eta) * cv[0] + xi * (T(1) - eta) * cv[1] + (T(1) - xi) * eta * cv[2] +
-           xi * eta * cv[3];
-    }
-    T f0 = T(0), P0[NC], P1[NC];
-    if constexpr (VAL) f0 = wdet * (KIND == MF_OP_MASS ? cq : T(1)) * u;
-    if constexpr (GRAD) {
-      // J^{-1} = [[J11, -J01], [-J10, J00]] / det; physical gradient G_a = sum_b
-      // (J^{-1})[b][a] g_b, then the reference-direction flux P_b = s sum_a (J^{-1})[b][a] S_a
-      // of the physical flux S (the gradient itself, kappa times it, or the stress)
-      const T r = T(1) / det;
-      T G[NC][2];
+      const T xi = sg[a], eta = sg[b];
+      // J[r][c] = d x_r / d xi_c
+      const T J00 = gm0[0] + gm0[4] * eta, J01 = gm0[2] + gm0[4] * xi;
+      const T J10 = gm0[1] + gm0[5] * eta, J11 = gm0[3] + gm0[5] * xi;
+      const T det = J00 * J11 - J01 * J10;
+      const T wdet = sw[a] * sw[b] * (det < T(0) ? -det : det);
+      T cq = T(1);
+      if (COEF && A.coef)
+        cq = (T(1) - xi) * (T(1) - eta) * cf0[0] + xi * (T(1) - eta) * cf0[1] + (T(1) - xi) * eta * cf0[2] +
+             xi * eta * cf0[3];
+      T f0 = T(0), P0[NC], P1[NC];
+      if constexpr (VAL) f0 = wdet * (KIND == MF_OP_MASS ? cq : T(1)) * u;
+      if constexpr (GRAD) {
+        // J^{-1} = [[J11, -J01], [-J10, J00]] / det; physical gradient G_a = sum_b
+        // (J^{-1})[b][a] g_b, then the reference-direction flux P_b = s sum_a
+        // (J^{-1})[b][a] S_a of the physical flux S (the gradient, kappa times it, or
+        // the stress)
+        const T r = T(1) / det;
+        T G[NC][2];
 #pragma unroll
-      for (int c = 0; c < NC; c++) {
-        G[c][0] = (J11 * gx[c] - J10 * gy[c]) * r;
-        G[c][1] = (J00 * gy[c] - J01 * gx[c]) * r;
-      }
-      T S[NC][2];
-      if constexpr (ELAS) {
-        // sigma = lambda tr(grad u) I + mu (grad u + grad u^T)
-        const T tr = A.lam * (G[0][0] + G[1][1]), od = A.mu * (G[0][1] + G[1][0]);
-        S[0][0] = tr + T(2) * A.mu * G[0][0];
-        S[1][1] = tr + T(2) * A.mu * G[1][1];
-        S[0][1] = od;
-        S[1][0] = od;
-      } else {
-        S[0][0] = G[0][0];
-        S[0][1] = G[0][1];
-      }
-      const T sc = wdet * (KIND == MF_OP_POISSON ? cq : T(1)) * r;
+        for (int c = 0; c < NC; c++) {
+          G[c][0] = (J11 * gx[c] - J10 * gy[c]) * r;
+          G[c][1] = (J00 * gy[c] - J01 * gx[c]) * r;
+        }
+        T S[NC][2];
+        if constexpr (ELAS) {
+          // sigma = lambda tr(grad u) I + mu (grad u + grad u^T)
+          const T tr = A.lam * (G[0][0] + G[1][1]), od = A.mu * (G[0][1] + G[1][0]);
+          S[0][0] = tr + T(2) * A.mu * G[0][0];
+          S[1][1] = tr + T(2) * A.mu * G[1][1];
+          S[0][1] = od;
+          S[1][0] = od;
+        } else {
+          S[0][0] = G[0][0];
+          S[0][1] = G[0][1];
+        }
+        const T sc = wdet * (KIND == MF_OP_POISSON ? cq : T(1)) * r;
 #pragma unroll
-      for (int c = 0; c < NC; c++) {
-        P0[c] = sc * (J11 * S[c][0] - J01 * S[c][1]);
-        P1[c] = sc * (J00 * S[c][1] - J10 * S[c][0]);
-      }
-    }
-    F0[slot][p] = f0;
-    if constexpr (GRAD)
-#pragma unroll
-      for (int c = 0; c < NC; c++) {
-        F1[slot][c][p] = P0[c];
-        F2[slot][c][p] = P1[c];
-      }
-  }
-  __syncthreads();
-  // backward y pass, lane (a, j): integrate against the test functions in y
-  if (act && p < H) {
-    const int a = p % NQ, j = p / NQ;
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-      T y0 = T(0), y1 = T(0);
-#pragma unroll
-      for (int b = 0; b < NQ; b++) {
-        const int q = a + NQ * b;
-        if constexpr (VAL) y0 += sB[b * N + j] * F0[slot][q];
-        if constexpr (GRAD) {
-          y0 += sD[b * N + j] * F2[slot][c][q];
-          y1 += sB[b * N + j] * F1[slot][c][q];
+        for (int c = 0; c < NC; c++) {
+          P0[c] = sc * (J11 * S[c][0] - J01 * S[c][1]);
+          P1[c] = sc * (J00 * S[c][1] - J10 * S[c][0]);
         }
       }
-      X0[slot][c][p] = y0;
-      if constexpr (GRAD) X1[slot][c][p] = y1;
+      F0[slot][p] = f0;
+      if constexpr (GRAD)
+#pragma unroll
+        for (int c = 0; c < NC; c++) {
+          F1[slot][c][p] = P0[c];
+          F2[slot][c][p] = P1[c];
+        }
     }
-  }
-  __syncthreads();
-  // backward x pass, lane (i, j), and the scatter
-  if (act && p < D && idx >= 0) {
-    const int i = p % N, j = p / N;
+    __syncthreads();
+    // backward y pass, lane (a, j): integrate against the test functions in y
+    if (act && p < H) {
+      const int a = p % NQ, j = p / NQ;
 #pragma unroll
-    for (int c = 0; c < NC; c++) {
-      T v = T(0);
+      for (int c = 0; c < NC; c++) {
+        T y0 = T(0), y1 = T(0);
 #pragma unroll
-      for (int a = 0; a < NQ; a++) {
-        v += sB[a * N + i] * X0[slot][c][a + NQ * j];
-        if constexpr (GRAD) v += sD[a * N + i] * X1[slot][c][a + NQ * j];
+        for (int b = 0; b < NQ; b++) {
+          const int q = a + NQ * b;
+          if constexpr (VAL) y0 += sB[b * N + j] * F0[slot][q];
+          if constexpr (GRAD) {
+            y0 += sD[b * N + j] * F2[slot][c][q];
+            y1 += sB[b * N + j] * F1[slot][c][q];
+          }
+        }
+        X0[slot][c][p] = y0;
+        if constexpr (GRAD) X1[slot][c][p] = y1;
       }
-      T *yp = A.y + (int64_t)idx * NC + c;
-      if (atomic) quad_atomic_add(yp, v);
-      else *yp += v;
     }
+    __syncthreads();
+    // backward x pass, lane (i, j), and the scatter
+    if (act && p < D && i0 >= 0) {
+      const int i = p % N, j = p / N;
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        T v = T(0);
+#pragma unroll
+        for (int a = 0; a < NQ; a++) {
+          v += sB[a * N + i] * X0[slot][c][a + NQ * j];
+          if constexpr (GRAD) v += sD[a * N + i] * X1[slot][c][a + NQ * j];
+        }
+        T *yp = A.y + (int64_t)i0 * NC + c;
+        if (atomic) quad_atomic_add(yp, v);
+        else *yp += v;
+      }
+    }
+    v0 = v1;
+    i0 = i1;
+#pragma unroll
+    for (int c = 0; c < NC; c++) xv0[c] = xv1[c];
+#pragma unroll
+    for (int m = 0; m < 6; m++) gm0[m] = gm1[m];
+#pragma unroll
+    for (int m = 0; m < 4; m++) cf0[m] = cf1[m];
+    v1 = v2;
+    i1 = i2;
   }
 }
 
 template <typename T, int N, int NQ, int KIND>
 static int launch_quad_nk(const QuadArgs<T> &a, bool atomic, hipStream_t s) {
   constexpr int CPW = 64 / (NQ * NQ);
-  const int64_t ngrp = (a.c1 - a.c0 + CPW - 1) / CPW;
-  const dim3 g((unsigned)(((ngrp + 7) / 8) * 8)), b(64);
+  const int64_t ngrp = (a.c1 - a.c0 + CPW - 1) / CPW, nwg = (ngrp + kQuadGroups - 1) / kQuadGroups;
+  const dim3 g((unsigned)(((nwg + 7) / 8) * 8)), b(64);
   quad_kernel<T, N, NQ, KIND><<<g, b, 0, s>>>(a, atomic);
   MF_HIP(hipGetLastError());
   return MF_OK;
