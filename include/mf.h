@@ -163,7 +163,8 @@ int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x
                       int accumulate, void *stream);
 
 /* d = diag(A) (ndofs, op precision); constrained dofs get 1. Used as the Jacobi
- * preconditioner. MF_EUNSUPPORTED for HYPERELASTIC. */
+ * preconditioner. MF_EUNSUPPORTED for HYPERELASTIC, the one-component tet operators
+ * and triangles other than the P1 mass. */
 int mf_op_diagonal(const mf_op *op, void *d, void *stream);
 
 /* Internal cell order and numbering. Every space colours its cells greedily

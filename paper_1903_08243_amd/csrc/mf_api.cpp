@@ -863,16 +863,18 @@ static bool default_coloured(const mf_op *op) {
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
   if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_TET && op->ncomp == 1) ||
-      (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)) ||
-      op->cell_type == MF_CELL_QUAD)
-    return fail(MF_EUNSUPPORTED,
-                "diagonal: not built for HYPERELASTIC, scalar tet, P2+ triangle or quad operators");
+      (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)))
+    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC, scalar tet or P2+ triangle operators");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
   if (rc) return rc;
   if (op->cell_type == MF_CELL_HEX) {
     HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, nullptr, d, 0,
                  op->ncells, op->ncomp, nullptr, 0, 0};
     rc = launch_hex_diag<T>(op->degree + 1, op->kind, a, s);
+  } else if (op->cell_type == MF_CELL_QUAD) {
+    QuadArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
+                  op->tab.as<T>(), nullptr, d, 0, op->ncells, nullptr, 0, 0, (T)op->lam, (T)op->mu};
+    rc = launch_quad<T>(op->degree, op->nq1d, op->kind, a, true, s, true);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), nullptr, d, 0, op->ncells, (T)op->lam,
                  (T)op->mu, nullptr, 0, 0};

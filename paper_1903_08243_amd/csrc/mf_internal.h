@@ -196,8 +196,9 @@ template <typename T> struct QuadArgs {
   int64_t ulo, uhi;
   T lam, mu;  // ELASTICITY Lame parameters
 };
+// diag: accumulate diag(A) into a.y (a.x unused; always atomic)
 template <typename T>
-int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s);
+int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s, bool diag = false);
 
 // Tri P1 mass with vertex coefficient (simplex_kernels.hip)
 template <typename T> struct TriArgs {

@@ -256,6 +256,143 @@ __global__ void __launch_bounds__(64) quad_kernel(const QuadArgs<T> A, const boo
   }
 }
 
+// diag(A) on quads: a(phi_d e_c, phi_d e_c) for every dof, sum-factorised. At point
+// (a, b) the form restricted to one basis function is m phi^2 + g^T C g with g the
+// reference gradient (B'_ai B_bj, B_ai B'_bj) of phi = B_ai B_bj: m = w |det| (c), and
+// C = w |det| s J^{-1} J^{-T} (s = kappa or 1), or for elasticity component c
+// w |det| (mu J^{-1} J^{-T} + (mu + lambda) k k^T) with k the column c of J^{-1}. The
+// sum over b is taken per (a, j), then over a per node (i, j). One workgroup per group
+// of 64 / nq^2 cells, lane = point, atomics for the shared nodes.
+template <typename T, int N, int NQ, int KIND>
+__global__ void __launch_bounds__(64) quad_diag_kernel(const QuadArgs<T> A) {
+  constexpr int P = NQ * NQ, CPW = 64 / P, D = N * N, H = NQ * N;
+  constexpr bool ELAS = KIND == MF_OP_ELASTICITY;
+  constexpr int NC = ELAS ? 2 : 1;
+  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
+  constexpr bool GRAD = KIND != MF_OP_MASS;
+  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
+  __shared__ T sB[H], sD[H], sw[NQ], sg[NQ];
+  __shared__ T Cq[CPW][NC][4][P];  // m, C00, C01, C11 per point
+  __shared__ T Tq[CPW][NC][4][H];  // their sums over b against the y factors, per (a, j)
+  const int lane = threadIdx.x;
+  const int slot = lane / P, p = lane - slot * P;
+  const bool act = slot < CPW;
+  const int64_t ngrp = (A.c1 - A.c0 + CPW - 1) / CPW, per = (ngrp + 7) / 8;
+  const int64_t grp = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (grp >= ngrp) return;  // uniform over the workgroup
+  const int64_t cell = A.c0 + grp * CPW + slot;
+  const bool valid = act && cell < A.c1;
+  if (lane < H) {
+    sB[lane] = A.tab[lane];
+    sD[lane] = A.tab[H + lane];
+  }
+  if (lane < NQ) {
+    sw[lane] = A.tab[2 * H + lane];
+    sg[lane] = A.tab[2 * H + NQ + lane];
+  }
+  T gm[6] = {T(1), T(0), T(0), T(1), T(0), T(0)}, cf[4] = {T(1), T(1), T(1), T(1)};
+  if (valid) {
+#pragma unroll
+    for (int m = 0; m < 6; m++) gm[m] = A.geo[cell * 6 + m];
+    if (COEF && A.coef)
+#pragma unroll
+      for (int m = 0; m < 4; m++) cf[m] = A.coef[cell * 4 + m];
+  }
+  __syncthreads();
+  if (act) {
+    const int a = p % NQ, b = p / NQ;
+    const T xi = sg[a], eta = sg[b];
+    const T J00 = gm[0] + gm[4] * eta, J01 = gm[2] + gm[4] * xi;
+    const T J10 = gm[1] + gm[5] * eta, J11 = gm[3] + gm[5] * xi;
+    const T det = J00 * J11 - J01 * J10;
+    const T wdet = sw[a] * sw[b] * (det < T(0) ? -det : det);
+    T cq = T(1);
+    if (COEF && A.coef)
+      cq = (T(1) - xi) * (T(1) - eta) * cf[0] + xi * (T(1) - eta) * cf[1] + (T(1) - xi) * eta * cf[2] +
+           xi * eta * cf[3];
+    const T rd = T(1) / det;
+    // rows of J^{-1}: k0 = (J11, -J01) / det, k1 = (-J10, J00) / det
+    const T k00 = J11 * rd, k01 = -J01 * rd, k10 = -J10 * rd, k11 = J00 * rd;
+    const T G00 = k00 * k00 + k01 * k01, G01 = k00 * k10 + k01 * k11, G11 = k10 * k10 + k11 * k11;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      T m = T(0), c00 = T(0), c01 = T(0), c11 = T(0);
+      if constexpr (VAL) m = wdet * (KIND == MF_OP_MASS ? cq : T(1));
+      if constexpr (GRAD) {
+        if constexpr (ELAS) {
+          const T q0 = c == 0 ? k00 : k01, q1 = c == 0 ? k10 : k11;  // column c of J^{-1}
+          const T e = A.mu + A.lam;
+          c00 = wdet * (A.mu * G00 + e * q0 * q0);
+          c01 = wdet * (A.mu * G01 + e * q0 * q1);
+          c11 = wdet * (A.mu * G11 + e * q1 * q1);
+        } else {
+          const T sc = wdet * (KIND == MF_OP_POISSON ? cq : T(1));
+          c00 = sc * G00;
+          c01 = sc * G01;
+          c11 = sc * G11;
+        }
+      }
+      Cq[slot][c][0][p] = m;
+      Cq[slot][c][1][p] = c00;
+      Cq[slot][c][2][p] = c01;
+      Cq[slot][c][3][p] = c11;
+    }
+  }
+  __syncthreads();
+  // lane (a, j): T0 = sum_b (m + C00 ...) split by which factor carries the derivative
+  // in y: B_bj^2 multiplies m and C00, B_bj B'_bj multiplies C01, B'_bj^2 multiplies C11
+  if (act && p < H) {
+    const int a = p % NQ, j = p / NQ;
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      T t0 = T(0), t1 = T(0), t2 = T(0), t3 = T(0);
+#pragma unroll
+      for (int b = 0; b < NQ; b++) {
+        const int q = a + NQ * b;
+        const T bb = sB[b * N + j], db = sD[b * N + j];
+        t0 += bb * bb * Cq[slot][c][0][q];
+        t1 += bb * bb * Cq[slot][c][1][q];
+        t2 += bb * db * Cq[slot][c][2][q];
+        t3 += db * db * Cq[slot][c][3][q];
+      }
+      Tq[slot][c][0][p] = t0;
+      Tq[slot][c][1][p] = t1;
+      Tq[slot][c][2][p] = t2;
+      Tq[slot][c][3][p] = t3;
+    }
+  }
+  __syncthreads();
+  // lane (i, j): sum over a with B_ai^2 (value and C11), B'_ai^2 (C00), 2 B_ai B'_ai (C01)
+  if (valid && p < D) {
+    const int idx = A.map[cell * D + p];
+    if (idx >= 0) {
+      const int i = p % N, j = p / N;
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        T v = T(0);
+#pragma unroll
+        for (int a = 0; a < NQ; a++) {
+          const T ba = sB[a * N + i], da = sD[a * N + i];
+          const int h = a + NQ * j;
+          v += ba * ba * (Tq[slot][c][0][h] + Tq[slot][c][3][h]) + da * da * Tq[slot][c][1][h] +
+               T(2) * ba * da * Tq[slot][c][2][h];
+        }
+        quad_atomic_add(A.y + (int64_t)idx * NC + c, v);
+      }
+    }
+  }
+}
+
+template <typename T, int N, int NQ, int KIND>
+static int launch_quad_diag_nk(const QuadArgs<T> &a, hipStream_t s) {
+  constexpr int CPW = 64 / (NQ * NQ);
+  const int64_t ngrp = (a.c1 - a.c0 + CPW - 1) / CPW;
+  const dim3 g((unsigned)(((ngrp + 7) / 8) * 8)), b(64);
+  quad_diag_kernel<T, N, NQ, KIND><<<g, b, 0, s>>>(a);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
 template <typename T, int N, int NQ, int KIND>
 static int launch_quad_nk(const QuadArgs<T> &a, bool atomic, hipStream_t s) {
   constexpr int CPW = 64 / (NQ * NQ);
@@ -267,7 +404,17 @@ static int launch_quad_nk(const QuadArgs<T> &a, bool atomic, hipStream_t s) {
 }
 
 template <typename T, int N, int NQ>
-static int launch_quad_nq(int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s) {
+static int launch_quad_nq(int kind, const QuadArgs<T> &a, bool atomic, bool diag, hipStream_t s) {
+  if (diag) {
+    switch (kind) {
+      case MF_OP_MASS: return launch_quad_diag_nk<T, N, NQ, MF_OP_MASS>(a, s);
+      case MF_OP_HELMHOLTZ: return launch_quad_diag_nk<T, N, NQ, MF_OP_HELMHOLTZ>(a, s);
+      case MF_OP_LAPLACIAN: return launch_quad_diag_nk<T, N, NQ, MF_OP_LAPLACIAN>(a, s);
+      case MF_OP_POISSON: return launch_quad_diag_nk<T, N, NQ, MF_OP_POISSON>(a, s);
+      case MF_OP_ELASTICITY: return launch_quad_diag_nk<T, N, NQ, MF_OP_ELASTICITY>(a, s);
+    }
+    return fail(MF_EUNSUPPORTED, "quad operator kind");
+  }
   switch (kind) {
     case MF_OP_MASS: return launch_quad_nk<T, N, NQ, MF_OP_MASS>(a, atomic, s);
     case MF_OP_HELMHOLTZ: return launch_quad_nk<T, N, NQ, MF_OP_HELMHOLTZ>(a, atomic, s);
@@ -279,28 +426,28 @@ static int launch_quad_nq(int kind, const QuadArgs<T> &a, bool atomic, hipStream
 }
 
 template <typename T, int N>
-static int launch_quad_n(int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s) {
-  if (nq == N) return launch_quad_nq<T, N, N>(kind, a, atomic, s);
+static int launch_quad_n(int nq, int kind, const QuadArgs<T> &a, bool atomic, bool diag, hipStream_t s) {
+  if (nq == N) return launch_quad_nq<T, N, N>(kind, a, atomic, diag, s);
   if constexpr (N < 8)
-    if (nq == N + 1) return launch_quad_nq<T, N, N + 1>(kind, a, atomic, s);
+    if (nq == N + 1) return launch_quad_nq<T, N, N + 1>(kind, a, atomic, diag, s);
   return fail(MF_EUNSUPPORTED, "quad: nq1d must be k+1 or k+2 (at most 8)");
 }
 
 template <typename T>
-int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s) {
+int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s, bool diag) {
   if (a.c1 <= a.c0) return MF_OK;
   switch (k) {
-    case 1: return launch_quad_n<T, 2>(nq, kind, a, atomic, s);
-    case 2: return launch_quad_n<T, 3>(nq, kind, a, atomic, s);
-    case 3: return launch_quad_n<T, 4>(nq, kind, a, atomic, s);
-    case 4: return launch_quad_n<T, 5>(nq, kind, a, atomic, s);
-    case 5: return launch_quad_n<T, 6>(nq, kind, a, atomic, s);
-    case 6: return launch_quad_n<T, 7>(nq, kind, a, atomic, s);
+    case 1: return launch_quad_n<T, 2>(nq, kind, a, atomic, diag, s);
+    case 2: return launch_quad_n<T, 3>(nq, kind, a, atomic, diag, s);
+    case 3: return launch_quad_n<T, 4>(nq, kind, a, atomic, diag, s);
+    case 4: return launch_quad_n<T, 5>(nq, kind, a, atomic, diag, s);
+    case 5: return launch_quad_n<T, 6>(nq, kind, a, atomic, diag, s);
+    case 6: return launch_quad_n<T, 7>(nq, kind, a, atomic, diag, s);
   }
   return fail(MF_EUNSUPPORTED, "quad degree (1..6)");
 }
 
-template int launch_quad<double>(int, int, int, const QuadArgs<double> &, bool, hipStream_t);
-template int launch_quad<float>(int, int, int, const QuadArgs<float> &, bool, hipStream_t);
+template int launch_quad<double>(int, int, int, const QuadArgs<double> &, bool, hipStream_t, bool);
+template int launch_quad<float>(int, int, int, const QuadArgs<float> &, bool, hipStream_t, bool);
 
 }  // namespace mf

@@ -90,8 +90,11 @@ def test_quad_dirichlet_range_errors(mf, k):
     for a, b in ((0, 37), (37, 38), (38, mesh.ncells)):
         lap.apply_range(a, b, xt, y, accumulate=True)
     assert _relerr(y.cpu().numpy(), oracle.OracleOp(space, LAP).apply(x)) <= 1e-12
-    with pytest.raises(mf.MFError):
-        lap.diagonal()
+    # diagonal with constrained rows: 1 there
+    d = mf.Operator(sp, HELM, mf.F64, dirichlet=mask).diagonal().cpu().numpy()
+    dref = oracle.OracleOp(space, HELM).diagonal()
+    dref[bnd] = 1.0
+    assert _relerr(d, dref) <= 1e-12
     for bad in (k, k + 3):
         with pytest.raises(mf.MFError):
             mf.Operator(sp, LAP, mf.F64, nq1d=bad)
@@ -178,3 +181,22 @@ def test_quad_elasticity_dirichlet_paper_rule(mf, k):
     for a, b in ((0, 60), (60, mesh.ncells)):
         op.apply_range(a, b, xt, y, accumulate=True)
     assert _relerr(y.cpu().numpy(), oracle.OracleOp(space, oracle.OP_ELASTICITY).apply(x)) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind", [MASS, HELM, LAP, POIS, 4], ids=["mass", "helmholtz", "laplacian", "poisson",
+                                                               "elasticity"])
+@pytest.mark.parametrize("k", [1, 3, 6])
+def test_quad_diagonal(mf, k, kind, prec):
+    """diag(A) (the Jacobi preconditioner) against the oracle's, k+1 and k+2 points."""
+    print(f"quad diagonal k={k} kind={kind} prec={prec}", flush=True)
+    mesh = mg.quad_mesh(11, 0.25, config=0)
+    nc = 2 if kind == 4 else 1
+    space = mg.quad_space(mesh, k, seed_k=k, ncomp=nc)
+    c = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if kind in (MASS, POIS) else None
+    sp = mf.Space.from_meshgen(space)
+    for nq in (k + 1, k + 2):
+        ref = oracle.OracleOp(space, kind, coef=c, nq1d=nq, lam=0.7, mu=0.4).diagonal()
+        op = mf.Operator(sp, kind, prec, nq1d=nq, vertex_coef=c, lam=0.7, mu=0.4)
+        d = op.diagonal().double().cpu().numpy()
+        assert _relerr(d, ref) <= TOL[prec], _relerr(d, ref)
