@@ -259,9 +259,9 @@ def tri_p1_space(mesh: Mesh, renumber: bool = False, config: int = 0) -> Space:
     return Space(mesh, 1, 1, perm[mesh.cell2vert].astype(np.int32), nn, node_ijk, perm)
 
 
-def tri_space(mesh: Mesh, k: int, renumber: bool = True, config: int = 0, seed_k: int | None = None) -> Space:
-    """P_k nodes of the split squares are exactly the points of the k-refined lattice
-    (one component)."""
+def tri_space(mesh: Mesh, k: int, renumber: bool = True, config: int = 0, seed_k: int | None = None,
+              ncomp: int = 1) -> Space:
+    """P_k nodes of the split squares are exactly the points of the k-refined lattice."""
     m = mesh.lattice_m
     G = m * k + 1
     vij = mesh.vert_ijk[mesh.cell2vert]  # (ncells, 3, 2)
@@ -274,7 +274,7 @@ def tri_space(mesh: Mesh, k: int, renumber: bool = True, config: int = 0, seed_k
     lat_ij = _lattice(m * k, 2)
     node_ijk = np.empty_like(lat_ij)
     node_ijk[perm] = lat_ij
-    return Space(mesh, k, 1, perm[lat].astype(np.int32), nn, node_ijk, perm)
+    return Space(mesh, k, ncomp, perm[lat].astype(np.int32), nn, node_ijk, perm)
 
 
 def uniform(n: int, lo: float, hi: float, config: int, purpose: int, k: int = 0) -> np.ndarray:

@@ -39,3 +39,27 @@ def test_tri_invariants(k):
     H = oracle.OracleOp(space, oracle.OP_HELMHOLTZ)
     a, b = np.random.default_rng(1).uniform(-1, 1, (2, space.ndofs))
     assert abs(H.apply(a) @ b - a @ H.apply(b)) <= 1e-13 * abs(H.apply(a) @ b)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_tri_elasticity_invariants(k):
+    """2D elasticity on perturbed triangles: rigid motions in the null space, the
+    linear-field patch test (interior rows vanish) and its exact energy
+    area * (lam tr(eps)^2 + 2 mu eps:eps), symmetry."""
+    lam, mu = 0.7, 0.4
+    mesh = mg.tri_mesh(5, 0.2, config=0)
+    space = mg.tri_space(mesh, k, ncomp=2)
+    op = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=lam, mu=mu)
+    xy = _node_xy(mesh, space)
+    X, Y = xy[:, 0], xy[:, 1]
+    for ux, uy in ((np.ones_like(X), 0 * X), (0 * X, np.ones_like(X)), (-Y, X)):
+        assert np.abs(op.apply(np.stack([ux, uy], axis=1).ravel())).max() <= 1e-12
+    G = np.array([[0.3, -1.1], [0.7, 0.9]])
+    u = np.stack([G[0, 0] * X + G[0, 1] * Y + 0.2, G[1, 0] * X + G[1, 1] * Y - 0.4], axis=1).ravel()
+    y = op.apply(u).reshape(-1, 2)
+    interior = np.setdiff1d(np.arange(space.nnodes), space.boundary_nodes())
+    assert np.abs(y[interior]).max() <= 1e-12
+    eps = (G + G.T) / 2
+    assert abs(u @ y.ravel() - (lam * np.trace(eps) ** 2 + 2 * mu * (eps * eps).sum())) <= 1e-12
+    a, b = np.random.default_rng(1).uniform(-1, 1, (2, space.ndofs))
+    assert abs(op.apply(a) @ b - a @ op.apply(b)) <= 1e-13 * abs(op.apply(a) @ b)
