@@ -145,7 +145,8 @@ typedef struct {
  * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1) and LAPLACIAN
  * (ncomp 1 or 3); tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
  * HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules reach degree 7);
- * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1); quad MASS, HELMHOLTZ,
+ * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1) and ELASTICITY P1-P3
+ * (ncomp 2, the 2D stress); quad MASS, HELMHOLTZ,
  * LAPLACIAN and POISSON Q1-Q6 (ncomp 1) and ELASTICITY Q1-Q6 (ncomp 2, the 2D stress).
  * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
 int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,

@@ -755,10 +755,15 @@ static void count_work(mf_op *op) {
       by += 3.0 * (double)op->nnodes * s;  // u0 read once
     }
   } else if (!(op->kind == MF_OP_MASS && op->degree == 1)) {
-    // triangles of degree k: per point value 4D + 3, gradient 8D + 17, coefficient 6
+    // triangles of degree k: per point value 4D + 3, gradient 8D + 17, coefficient 6;
+    // elasticity per component reference gradient 4D, push-forward and pull-back 12,
+    // test sum 4D, plus the stress 9 and the weight
     const double D = op->D, Q = op->nqp;
     const bool val = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ, grad = op->kind != MF_OP_MASS;
-    fl = nc * Q * ((val ? 4.0 * D + 3.0 : 0.0) + (grad ? 8.0 * D + 17.0 : 0.0) + (op->has_coef ? 6.0 : 0.0));
+    if (op->kind == MF_OP_ELASTICITY)
+      fl = nc * Q * (2.0 * (8.0 * D + 12.0) + 10.0);
+    else
+      fl = nc * Q * ((val ? 4.0 * D + 3.0 : 0.0) + (grad ? 8.0 * D + 17.0 : 0.0) + (op->has_coef ? 6.0 : 0.0));
     by += nc * 5.0 * s + (op->has_coef ? nc * 3.0 * s : 0.0);
   } else {
     fl = nc * 30.0;
@@ -796,7 +801,7 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     return launch_tet_elasticity<T>(op->degree, op->nqp, a, atomic, s);
   }
   if (!(op->kind == MF_OP_MASS && op->degree == 1)) {
-    TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, T(0), T(0),
+    TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
                  filt, ulo, uhi, nullptr, nullptr, op->has_coef ? op->coef.as<T>() : nullptr};
     return launch_tri_scalar<T>(op->degree, op->nqp, op->kind, a, atomic, s);
   }
@@ -911,7 +916,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3) ||
          (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else
-    ok = kind <= MF_OP_POISSON && sp->ncomp == 1;
+    ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);
   if (!ok) return fail(MF_EUNSUPPORTED, "mf_op_create: operator / cell / ncomp combination not built");
   if (kind == MF_OP_HYPERELASTIC && !pr->u0) return fail(MF_EINVAL, "HYPERELASTIC needs u0 (linearisation point)");
   if (kind == MF_OP_POISSON && !pr->vertex_coef) return fail(MF_EINVAL, "POISSON needs vertex_coef (kappa)");

@@ -241,13 +241,16 @@ template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, b
 template int launch_tet_scalar<float>(int, int, int, const TetArgs<float> &, bool, hipStream_t);
 
 // ----------------------------------------------------------------- scalar triangle operators
-// The same four one-component forms on affine triangles of degree K (the 2D version of
+// The same four one-component forms, and 2D linear elasticity (two node-interleaved
+// components, TetArgs lam and mu), on affine triangles of degree K (the 2D version of
 // tet_scalar_kernel): geometry [cell/64][5][64] = d xi_b / d x_a (row-major, 4) and
 // |det J|; coefficients [cell/64][3][64]; tables phi [nq][D], reference gradients
 // [nq][D][2], weights [nq], vertex basis [nq][3]; nq is a run-time bound.
 template <typename T, int K, int KIND, bool ATOMIC>
 __global__ void __launch_bounds__(64) tri_scalar_kernel(const TetArgs<T> A, const int NQ) {
   constexpr int D = (K + 1) * (K + 2) / 2;
+  constexpr bool ELAS = KIND == MF_OP_ELASTICITY;  // two node-interleaved components
+  constexpr int NC = ELAS ? 2 : 1;
   constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
   constexpr bool GRAD = KIND != MF_OP_MASS;
   constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
@@ -272,12 +275,15 @@ __global__ void __launch_bounds__(64) tri_scalar_kernel(const TetArgs<T> A, cons
   if (COEF && A.coef)
 #pragma unroll
     for (int v = 0; v < 3; v++) cv[v] = A.coef[(batch * 3 + v) * 64 + lane];
-  T xe[D], ye[D];
+  T xe[NC][D], ye[NC][D];
 #pragma unroll
   for (int i = 0; i < D; i++) {
     const int idx = valid ? mp[i * 64] : -1;
-    xe[i] = idx >= 0 ? A.x[idx] : T(0);
-    ye[i] = T(0);
+#pragma unroll
+    for (int c = 0; c < NC; c++) {
+      xe[c][i] = idx >= 0 ? A.x[(int64_t)idx * NC + c] : T(0);
+      ye[c][i] = T(0);
+    }
   }
   const T *__restrict__ phi = A.tab;
   const T *__restrict__ dphi = phi + NQ * D;
@@ -289,40 +295,67 @@ __global__ void __launch_bounds__(64) tri_scalar_kernel(const TetArgs<T> A, cons
     const T wd = qw[q] * adet;
     T cq = T(1);
     if (COEF) cq = vb[3 * q] * cv[0] + vb[3 * q + 1] * cv[1] + vb[3 * q + 2] * cv[2];
-    T f0 = T(0), P0 = T(0), P1 = T(0);
+    T f0 = T(0), P0[NC], P1[NC];
     if constexpr (VAL) {
       T u = T(0);
 #pragma unroll
-      for (int i = 0; i < D; i++) u += xe[i] * pq[i];
+      for (int i = 0; i < D; i++) u += xe[0][i] * pq[i];
       f0 = wd * (KIND == MF_OP_MASS ? cq : T(1)) * u;
     }
     if constexpr (GRAD) {
-      T g0 = T(0), g1 = T(0);
+      // physical gradient G_a = sum_b g_b Ki[b][a], Ki[b][a] = d xi_b / d x_a
+      T G[NC][2];
 #pragma unroll
-      for (int i = 0; i < D; i++) {
-        g0 += xe[i] * tq[2 * i + 0];
-        g1 += xe[i] * tq[2 * i + 1];
+      for (int c = 0; c < NC; c++) {
+        T g0 = T(0), g1 = T(0);
+#pragma unroll
+        for (int i = 0; i < D; i++) {
+          g0 += xe[c][i] * tq[2 * i + 0];
+          g1 += xe[c][i] * tq[2 * i + 1];
+        }
+        G[c][0] = g0 * Ki[0] + g1 * Ki[2];
+        G[c][1] = g0 * Ki[1] + g1 * Ki[3];
+      }
+      // physical flux S (the gradient, kappa times it, or the stress
+      // lambda tr(grad u) I + mu (grad u + grad u^T)), then P_b = w |det| sum_a Ki[b][a] S_a
+      T S[NC][2];
+      if constexpr (ELAS) {
+        const T tr = A.lam * (G[0][0] + G[1][1]), od = A.mu * (G[0][1] + G[1][0]);
+        S[0][0] = tr + T(2) * A.mu * G[0][0];
+        S[1][1] = tr + T(2) * A.mu * G[1][1];
+        S[0][1] = od;
+        S[1][0] = od;
+      } else {
+        S[0][0] = G[0][0];
+        S[0][1] = G[0][1];
       }
       const T s = wd * (KIND == MF_OP_POISSON ? cq : T(1));
-      const T G0 = s * (g0 * Ki[0] + g1 * Ki[2]), G1 = s * (g0 * Ki[1] + g1 * Ki[3]);
-      P0 = G0 * Ki[0] + G1 * Ki[1];
-      P1 = G0 * Ki[2] + G1 * Ki[3];
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        P0[c] = s * (S[c][0] * Ki[0] + S[c][1] * Ki[1]);
+        P1[c] = s * (S[c][0] * Ki[2] + S[c][1] * Ki[3]);
+      }
     }
 #pragma unroll
-    for (int i = 0; i < D; i++) {
-      T v = T(0);
-      if constexpr (VAL) v += f0 * pq[i];
-      if constexpr (GRAD) v += P0 * tq[2 * i + 0] + P1 * tq[2 * i + 1];
-      ye[i] += v;
-    }
+    for (int c = 0; c < NC; c++)
+#pragma unroll
+      for (int i = 0; i < D; i++) {
+        T v = T(0);
+        if constexpr (VAL) v += f0 * pq[i];
+        if constexpr (GRAD) v += P0[c] * tq[2 * i + 0] + P1[c] * tq[2 * i + 1];
+        ye[c][i] += v;
+      }
   }
 #pragma unroll
   for (int i = 0; i < D; i++) {
     const int idx = valid ? mp[i * 64] : -1;
-    if (idx >= 0) {
-      if constexpr (ATOMIC) atomic_add_s(&A.y[idx], ye[i]);
-      else A.y[idx] += ye[i];  // cells of one launch share no node
-    }
+    if (idx >= 0)
+#pragma unroll
+      for (int c = 0; c < NC; c++) {
+        T *yp = A.y + (int64_t)idx * NC + c;
+        if constexpr (ATOMIC) atomic_add_s(yp, ye[c][i]);
+        else *yp += ye[c][i];  // cells of one launch share no node
+      }
   }
 }
 
@@ -344,6 +377,7 @@ static int launch_tri_scalar_k(int nq, int kind, const TetArgs<T> &a, bool atomi
     case MF_OP_HELMHOLTZ: return launch_tri_scalar_kk<T, K, MF_OP_HELMHOLTZ>(nq, a, atomic, s);
     case MF_OP_LAPLACIAN: return launch_tri_scalar_kk<T, K, MF_OP_LAPLACIAN>(nq, a, atomic, s);
     case MF_OP_POISSON: return launch_tri_scalar_kk<T, K, MF_OP_POISSON>(nq, a, atomic, s);
+    case MF_OP_ELASTICITY: return launch_tri_scalar_kk<T, K, MF_OP_ELASTICITY>(nq, a, atomic, s);
   }
   return fail(MF_EUNSUPPORTED, "triangle scalar operator: kind");
 }

@@ -93,3 +93,49 @@ def test_tri_scalar_large_sampled(mf):
         op = mf.Operator(sp, POIS, prec, vertex_coef=c)
         y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
         assert np.abs(y[nodes] - ref[nodes]).max() / np.abs(ref[nodes]).max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_tri_elasticity(mf, k, prec, scatter):
+    """2D linear elasticity (two node-interleaved components), lambda 0.7, mu 0.4."""
+    import torch
+    print(f"tri elasticity k={k} prec={prec} scatter={scatter}", flush=True)
+    mesh = mg.tri_mesh(9, 0.2, config=0)
+    space = mg.tri_space(mesh, k, seed_k=k, ncomp=2)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+    ref = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=0.7, mu=0.4).apply(x)
+    op = mf.Operator(mf.Space.from_meshgen(space), mf.ELASTICITY, prec, lam=0.7, mu=0.4, scatter=scatter)
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_tri_elasticity_dirichlet_range(mf, k):
+    """Clamped boundary (both components) and a split range apply; one component is
+    rejected."""
+    import torch
+    print(f"tri elasticity dirichlet k={k}", flush=True)
+    mesh = mg.tri_mesh(9, 0.2, config=0)
+    space = mg.tri_space(mesh, k, seed_k=k, ncomp=2)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    bd = np.stack([2 * bnd, 2 * bnd + 1], axis=1).ravel()
+    xm = x.copy()
+    xm[bd] = 0.0
+    ref = oracle.OracleOp(space, oracle.OP_ELASTICITY).apply(xm)
+    ref[bd] = x[bd]
+    sp = mf.Space.from_meshgen(space)
+    xt = torch.tensor(x, device="cuda")
+    op = mf.Operator(sp, mf.ELASTICITY, mf.F64, dirichlet=mask)
+    assert _relerr(op.apply(xt).cpu().numpy(), ref) <= 1e-12
+    op = mf.Operator(sp, mf.ELASTICITY, mf.F64)
+    y = torch.zeros_like(xt)
+    for a, b in ((0, 77), (77, mesh.ncells)):
+        op.apply_range(a, b, xt, y, accumulate=True)
+    assert _relerr(y.cpu().numpy(), oracle.OracleOp(space, oracle.OP_ELASTICITY).apply(x)) <= 1e-12
+    with pytest.raises(mf.MFError):
+        mf.Operator(mf.Space.from_meshgen(mg.tri_space(mesh, k)), mf.ELASTICITY, mf.F64)
