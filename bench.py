@@ -227,8 +227,9 @@ def bench_simplex(mf, mg, reps=20):
         del sp, space
     # P2 / P3 triangles (lane per cell), 1024 x 1024 x 2 cells
     tmesh = mg.tri_mesh(1024, 0.2, config=0)
-    for k, kind, name in ((2, mf.HELMHOLTZ, "helmholtz"), (3, mf.LAPLACIAN, "laplacian")):
-        space = mg.tri_space(tmesh, k)
+    for k, kind, name, nc in ((2, mf.HELMHOLTZ, "helmholtz", 1), (3, mf.LAPLACIAN, "laplacian", 1),
+                              (2, mf.ELASTICITY, "elasticity", 2)):
+        space = mg.tri_space(tmesh, k, ncomp=nc)
         sp = mf.Space.from_meshgen(space)
         x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
         for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
