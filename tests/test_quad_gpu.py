@@ -200,3 +200,31 @@ def test_quad_diagonal(mf, k, kind, prec):
         op = mf.Operator(sp, kind, prec, nq1d=nq, vertex_coef=c, lam=0.7, mu=0.4)
         d = op.diagonal().double().cpu().numpy()
         assert _relerr(d, ref) <= TOL[prec], _relerr(d, ref)
+
+
+@pytest.mark.parametrize("kind", [HELM, 4], ids=["helmholtz", "elasticity"])
+def test_quad_jacobi_cg(mf, kind):
+    """Jacobi-preconditioned CG through the C-ABI on Q3 quads (Dirichlet boundary):
+    the solution matches a dense solve of the oracle's assembled matrix."""
+    import torch
+    print(f"quad jacobi cg kind={kind}", flush=True)
+    mesh = mg.quad_mesh(6, 0.25, config=0)
+    nc = 2 if kind == 4 else 1
+    space = mg.quad_space(mesh, 3, seed_k=3, ncomp=nc)
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    bd = (bnd[:, None] * nc + np.arange(nc)).ravel()
+    b = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_RHS, 3)
+    A = oracle.OracleOp(space, kind).assemble_dense()
+    free = np.setdiff1d(np.arange(space.ndofs), bd)
+    # constrained rows are the identity and constrained values leave the free rows
+    xref = b.copy()
+    xref[free] = np.linalg.solve(A[np.ix_(free, free)], b[free])
+    sp = mf.Space.from_meshgen(space)
+    op = mf.Operator(sp, kind, mf.F64, dirichlet=mask)
+    x = torch.zeros(space.ndofs, dtype=torch.float64, device="cuda")
+    bt = torch.tensor(b, device="cuda")
+    info = mf.cg_solve(op, bt, x, precond=mf.JacobiPrecond(op), rtol=1e-12)
+    assert info["rc"] == 0, info
+    assert np.abs(x.cpu().numpy() - xref).max() <= 1e-8 * np.abs(xref).max()
