@@ -392,6 +392,31 @@ def test_hex_laplacian_of_linear_field_vanishes_inside(k):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3])
+def test_hex_elasticity_invariants(k):
+    """Elasticity on perturbed trilinear hexes: the six rigid motions are in the null
+    space, the linear-field patch test holds at interior nodes, and the energy of a
+    linear field is lam tr(eps)^2 + 2 mu eps:eps (unit volume)."""
+    lam, mu = 0.7, 0.4
+    mesh = mg.hex_mesh(3, 0.15, config=1, seed_k=k)
+    sp_ = mg.hex_space(mesh, k, ncomp=3)
+    op = oracle.OracleOp(sp_, oracle.OP_ELASTICITY, lam=lam, mu=mu)
+    xn = _hex_node_coords(mesh, sp_)
+    X, Y, Z = xn[:, 0], xn[:, 1], xn[:, 2]
+    one, zero = np.ones_like(X), np.zeros_like(X)
+    scale = np.abs(op.apply(np.random.default_rng(0).uniform(-1, 1, sp_.ndofs))).max()
+    for m in ((one, zero, zero), (zero, one, zero), (zero, zero, one), (-Y, X, zero), (zero, -Z, Y), (Z, zero, -X)):
+        assert np.abs(op.apply(np.stack(m, axis=1).ravel())).max() < 1e-13 * scale
+    G = np.array([[0.3, -1.1, 0.2], [0.7, 0.9, -0.4], [-0.5, 0.1, 0.6]])
+    u = (xn @ G.T + np.array([0.2, -0.4, 0.1])).ravel()
+    y = op.apply(u).reshape(-1, 3)
+    interior = np.ones(sp_.nnodes, bool)
+    interior[sp_.boundary_nodes()] = False
+    assert np.abs(y[interior]).max() < 1e-13 * scale
+    eps = (G + G.T) / 2
+    assert abs(u @ y.ravel() - (lam * np.trace(eps) ** 2 + 2 * mu * (eps * eps).sum())) < 1e-12
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_tet_elasticity_patch_test(k):
     mesh = mg.tet_mesh(2, 0.2, config=2)
     sp_ = mg.tet_space(mesh, k, ncomp=3)
