@@ -1,0 +1,243 @@
+// Linear elasticity on trilinear hexahedra, Q1..Q6 on GLL nodes, three node-interleaved
+// components: int sigma(u) : grad v with sigma = lambda tr(grad u) I + mu (grad u +
+// grad u^T) (the paper's vector operator on the tensor-product cell, Section 4.1).
+//
+// The basis is a tensor product, so the action factorises into 1D contractions
+// (Sections 3 and 4.2.4): three passes forward (values and reference gradients of each
+// component at the points), the pointwise stress with the Jacobian of the trilinear map
+// evaluated at every point (Section 2.1), and three passes back. One workgroup per
+// cell, one thread per quadrature point (rounded up to whole wavefronts); between the
+// passes the partial contractions sit in two ping-pong LDS buffers.
+#include "mf_internal.h"
+
+namespace mf {
+
+namespace {
+__device__ __forceinline__ void hex_el_atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void hex_el_atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+}  // namespace
+
+// N = k + 1 nodes and NQ Gauss points per direction. tab: B[a][i] = l_i(g_a) [NQ][N],
+// B'[a][i], weights [NQ], points [NQ]. geo: [cell][24], coefficient m = 1..7 of the
+// trilinear map x = c0 + c1 xi1 + c2 xi2 + c3 xi3 + c4 xi1 xi2 + c5 xi1 xi3 + c6 xi2 xi3
+// + c7 xi1 xi2 xi3 at 3 (m - 1) + coordinate.
+template <typename T, int N, int NQ>
+__global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T> A, const bool atomic) {
+  constexpr int D = N * N * N, SX = NQ * N * N, SY = NQ * NQ * N, P = NQ * NQ * NQ, H = NQ * N;
+  static_assert(NQ >= N, "every node needs a thread");
+  __shared__ T sB[H], sD[H], sw[NQ], sg[NQ];
+  __shared__ T bufA[9 * SY];  // dofs, then the y-pass fields, then the backward z fields
+  __shared__ T bufB[9 * P];   // x-pass fields, then the point fluxes, then the backward y fields
+  const int t = threadIdx.x;
+  // consecutive workgroup ids land on different XCDs: each XCD takes a contiguous run
+  const int64_t n = A.c1 - A.c0, per = (n + 7) / 8;
+  const int64_t ci = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (ci >= n) return;  // uniform over the workgroup
+  const int64_t cell = A.c0 + ci;
+  if (A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    if (u < A.ulo || u >= A.uhi) return;  // uniform: one cell per workgroup
+  }
+  if (t < H) {
+    sB[t] = A.tab[t];
+    sD[t] = A.tab[H + t];
+  }
+  if (t < NQ) {
+    sw[t] = A.tab[2 * H + t];
+    sg[t] = A.tab[2 * H + NQ + t];
+  }
+  int idx = -1;  // node of dof t in y (internal numbering)
+  if (t < D) {
+    idx = A.map[cell * D + t];
+    const int gi = A.gmap ? A.gmap[cell * D + t] : idx;  // its position in x
+#pragma unroll
+    for (int c = 0; c < 3; c++) bufA[c * D + t] = gi >= 0 ? A.x[(int64_t)gi * 3 + c] : T(0);
+  }
+  __syncthreads();
+  // x pass, thread (a, j, l): X0 = sum_i B[a][i] U[i, j, l], X1 with B'
+  if (t < SX) {
+    const int a = t % NQ, j = (t / NQ) % N, l = t / (NQ * N);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int i = 0; i < N; i++) {
+        const T u = bufA[c * D + i + N * (j + N * l)];
+        s0 += sB[a * N + i] * u;
+        s1 += sD[a * N + i] * u;
+      }
+      bufB[c * SX + t] = s0;
+      bufB[(3 + c) * SX + t] = s1;
+    }
+  }
+  __syncthreads();
+  // y pass, thread (a, b, l): Y00 = B_y X0, Y01 = B'_y X0, Y10 = B_y X1
+  if (t < SY) {
+    const int a = t % NQ, b = (t / NQ) % NQ, l = t / (NQ * NQ);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T y00 = T(0), y01 = T(0), y10 = T(0);
+#pragma unroll
+      for (int j = 0; j < N; j++) {
+        const T x0 = bufB[c * SX + a + NQ * (j + N * l)], x1 = bufB[(3 + c) * SX + a + NQ * (j + N * l)];
+        y00 += sB[b * N + j] * x0;
+        y01 += sD[b * N + j] * x0;
+        y10 += sB[b * N + j] * x1;
+      }
+      bufA[c * SY + t] = y00;
+      bufA[(3 + c) * SY + t] = y01;
+      bufA[(6 + c) * SY + t] = y10;
+    }
+  }
+  __syncthreads();
+  // z pass and the stress, thread = point (a, b, e)
+  if (t < P) {
+    const int a = t % NQ, b = (t / NQ) % NQ, e = t / (NQ * NQ);
+    T g[3][3];  // g[c][d]: reference derivative d of component c
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+      for (int l = 0; l < N; l++) {
+        const int h = a + NQ * (b + NQ * l);
+        gx += sB[e * N + l] * bufA[(6 + c) * SY + h];
+        gy += sB[e * N + l] * bufA[(3 + c) * SY + h];
+        gz += sD[e * N + l] * bufA[c * SY + h];
+      }
+      g[c][0] = gx;
+      g[c][1] = gy;
+      g[c][2] = gz;
+    }
+    const T x1 = sg[a], x2 = sg[b], x3 = sg[e];
+    const T *gc = A.geo + cell * 24;
+    T J[3][3];  // J[r][d] = d x_r / d xi_d
+#pragma unroll
+    for (int r = 0; r < 3; r++) {
+      const T c1 = gc[r], c2 = gc[3 + r], c3 = gc[6 + r], c4 = gc[9 + r], c5 = gc[12 + r], c6 = gc[15 + r],
+              c7 = gc[18 + r];
+      J[r][0] = c1 + c4 * x2 + c5 * x3 + c7 * x2 * x3;
+      J[r][1] = c2 + c4 * x1 + c6 * x3 + c7 * x1 * x3;
+      J[r][2] = c3 + c5 * x1 + c6 * x2 + c7 * x1 * x2;
+    }
+    // inverse by cofactors: K[d][r] = d xi_d / d x_r = C[r][d] / det
+    T C[3][3];
+    C[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    C[0][1] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    C[0][2] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    C[1][0] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    C[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    C[1][2] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    C[2][0] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    C[2][1] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    C[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const T det = J[0][0] * C[0][0] + J[0][1] * C[0][1] + J[0][2] * C[0][2];
+    const T rd = T(1) / det;
+    // physical gradient G[c][r] = sum_d K[d][r] g[c][d]
+    T G[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+      for (int r = 0; r < 3; r++) G[c][r] = (C[r][0] * g[c][0] + C[r][1] * g[c][1] + C[r][2] * g[c][2]) * rd;
+    const T tr = A.lam * (G[0][0] + G[1][1] + G[2][2]);
+    const T wdet = sw[a] * sw[b] * sw[e] * (det < T(0) ? -det : det) * rd;
+    // stress S[c][r], then the reference flux F[c][d] = w |det| sum_r K[d][r] S[c][r]
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T S[3];
+#pragma unroll
+      for (int r = 0; r < 3; r++) S[r] = A.mu * (G[c][r] + G[r][c]) + (r == c ? tr : T(0));
+#pragma unroll
+      for (int d = 0; d < 3; d++) bufB[(3 * d + c) * P + t] = wdet * (C[0][d] * S[0] + C[1][d] * S[1] + C[2][d] * S[2]);
+    }
+  }
+  __syncthreads();
+  // backward z, thread (a, b, l): Zx = B_z Fx, Zy = B_z Fy, Zz = B'_z Fz
+  if (t < SY) {
+    const int a = t % NQ, b = (t / NQ) % NQ, l = t / (NQ * NQ);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T zx = T(0), zy = T(0), zz = T(0);
+#pragma unroll
+      for (int e = 0; e < NQ; e++) {
+        const int q = a + NQ * (b + NQ * e);
+        zx += sB[e * N + l] * bufB[c * P + q];
+        zy += sB[e * N + l] * bufB[(3 + c) * P + q];
+        zz += sD[e * N + l] * bufB[(6 + c) * P + q];
+      }
+      bufA[c * SY + t] = zx;
+      bufA[(3 + c) * SY + t] = zy;
+      bufA[(6 + c) * SY + t] = zz;
+    }
+  }
+  __syncthreads();
+  // backward y, thread (a, j, l): Vx = B_y Zx, Vb = B'_y Zy + B_y Zz
+  if (t < SX) {
+    const int a = t % NQ, j = (t / NQ) % N, l = t / (NQ * N);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T vx = T(0), vb = T(0);
+#pragma unroll
+      for (int b = 0; b < NQ; b++) {
+        const int h = a + NQ * (b + NQ * l);
+        vx += sB[b * N + j] * bufA[c * SY + h];
+        vb += sD[b * N + j] * bufA[(3 + c) * SY + h] + sB[b * N + j] * bufA[(6 + c) * SY + h];
+      }
+      bufB[c * SX + t] = vx;
+      bufB[(3 + c) * SX + t] = vb;
+    }
+  }
+  __syncthreads();
+  // backward x, thread (i, j, l), and the scatter
+  if (t < D && idx >= 0) {
+    const int i = t % N, j = (t / N) % N, l = t / (N * N);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T v = T(0);
+#pragma unroll
+      for (int a = 0; a < NQ; a++) {
+        const int h = a + NQ * (j + N * l);
+        v += sD[a * N + i] * bufB[c * SX + h] + sB[a * N + i] * bufB[(3 + c) * SX + h];
+      }
+      T *yp = A.y + (int64_t)idx * 3 + c;
+      if (atomic) hex_el_atomic_add(yp, v);
+      else *yp += v;
+    }
+  }
+}
+
+template <typename T, int N, int NQ>
+static int launch_hex_el_nq(const HexElasArgs<T> &a, bool atomic, hipStream_t s) {
+  constexpr int P = NQ * NQ * NQ;
+  const int64_t n = a.c1 - a.c0;
+  const dim3 g((unsigned)(((n + 7) / 8) * 8)), b((unsigned)((P + 63) / 64 * 64));
+  hex_elasticity_kernel<T, N, NQ><<<g, b, 0, s>>>(a, atomic);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T, int N>
+static int launch_hex_el_n(int nq, const HexElasArgs<T> &a, bool atomic, hipStream_t s) {
+  if (nq == N) return launch_hex_el_nq<T, N, N>(a, atomic, s);
+  if constexpr (N < 7)
+    if (nq == N + 1) return launch_hex_el_nq<T, N, N + 1>(a, atomic, s);
+  return fail(MF_EUNSUPPORTED, "hex elasticity: nq1d must be k+1 or k+2 (at most 7)");
+}
+
+template <typename T>
+int launch_hex_elasticity(int k, int nq, const HexElasArgs<T> &a, bool atomic, hipStream_t s) {
+  if (a.c1 <= a.c0) return MF_OK;
+  switch (k) {
+    case 1: return launch_hex_el_n<T, 2>(nq, a, atomic, s);
+    case 2: return launch_hex_el_n<T, 3>(nq, a, atomic, s);
+    case 3: return launch_hex_el_n<T, 4>(nq, a, atomic, s);
+    case 4: return launch_hex_el_n<T, 5>(nq, a, atomic, s);
+    case 5: return launch_hex_el_n<T, 6>(nq, a, atomic, s);
+    case 6: return launch_hex_el_n<T, 7>(nq, a, atomic, s);
+  }
+  return fail(MF_EUNSUPPORTED, "hex elasticity degree (1..6)");
+}
+
+template int launch_hex_elasticity<double>(int, int, const HexElasArgs<double> &, bool, hipStream_t);
+template int launch_hex_elasticity<float>(int, int, const HexElasArgs<float> &, bool, hipStream_t);
+
+}  // namespace mf

@@ -452,7 +452,8 @@ template <typename T>
 static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
                      const std::vector<int32_t> &to_pos2, hipStream_t s) {
   const int k = sp->degree, N = k + 1;
-  if (op->nq1d != N) return fail(MF_EUNSUPPORTED, "hex operators support nq1d = k+1 only");
+  if (op->nq1d != N && op->kind != MF_OP_ELASTICITY)
+    return fail(MF_EUNSUPPORTED, "hex operators support nq1d = k+1 only (elasticity: k+1 or k+2)");
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 24, T(0));
   for (int64_t K = 0; K < nc; K++) {
@@ -660,17 +661,24 @@ template <typename T> static int setup_tri(mf_op *op, const mf_space *sp, const 
 // Quads: 1D tables (GLL Lagrange basis and its derivative at the Gauss points, the
 // weights and the points), the bilinear map coefficients per cell [cell][6] and the
 // vertex coefficients [cell][4], in internal cell order.
-template <typename T> static int setup_quad(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
-  const int k = sp->degree, nq = op->nq1d;
+// 1D tables of the tensor-product kernels (quads, hex elasticity): the GLL Lagrange
+// basis B[a][i] and its derivative at the nq1d Gauss points, the weights, the points
+template <typename T> static int upload_tensor_tables(mf_op *op, hipStream_t s) {
   std::vector<double> g, w, V, dV;
-  gauss_legendre(nq, g, w);
-  lagrange_eval(gll_points(k), g, V, dV);
+  gauss_legendre(op->nq1d, g, w);
+  lagrange_eval(gll_points(op->degree), g, V, dV);
   std::vector<T> tab;
   for (double v : V) tab.push_back((T)v);
   for (double v : dV) tab.push_back((T)v);
   for (double v : w) tab.push_back((T)v);
   for (double v : g) tab.push_back((T)v);
   int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
+  if (!rc) MF_HIP(hipStreamSynchronize(s));
+  return rc;
+}
+
+template <typename T> static int setup_quad(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+  int rc = upload_tensor_tables<T>(op, s);
   if (rc) return rc;
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 6), cf;
@@ -698,7 +706,15 @@ static void count_work(mf_op *op) {
   const double nc = (double)op->ncells, nd = (double)op->ndofs;
   const int comps = op->ncomp;
   double fl = 0.0, by = 2.0 * nd * s + 4.0 * op->D * nc;
-  if (op->cell_type == MF_CELL_HEX) {
+  if (op->cell_type == MF_CELL_HEX && op->kind == MF_OP_ELASTICITY) {
+    // per component, multiply-adds: x pass 2 q n^3, y pass 3 q^2 n^2, z pass 3 q^3 n and
+    // the same backward (n = k+1, q points per direction); per point the Jacobian 36,
+    // cofactors and det 50, gradients 54, stress 15, fluxes 54 and the weight 5 flops
+    const double n = op->degree + 1, q = op->nq1d;
+    const double fma = 3.0 * 2.0 * (2.0 * q * n * n * n + 3.0 * q * q * n * n + 3.0 * q * q * q * n);
+    fl = nc * (2.0 * fma + q * q * q * 214.0);
+    by += nc * 24.0 * s;
+  } else if (op->cell_type == MF_CELL_HEX) {
     const int ni = op->degree + 1;
     const double n = ni, q3 = n * n * n;
     const bool grad = op->kind != MF_OP_MASS, mass = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ;
@@ -781,7 +797,11 @@ static void count_work(mf_op *op) {
 template <typename T>
 static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool atomic, const int32_t *filt,
                        int64_t ulo, int64_t uhi, hipStream_t s, bool fused = false, bool first = false) {
-  if (op->cell_type == MF_CELL_HEX) {
+  if (op->cell_type == MF_CELL_HEX && op->kind == MF_OP_ELASTICITY) {
+    HexElasArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi,
+                     (T)op->lam, (T)op->mu, fused ? op->gmap.as<int32_t>() : nullptr};
+    return launch_hex_elasticity<T>(op->degree, op->nq1d, a, atomic, s);
+  } else if (op->cell_type == MF_CELL_HEX) {
     // the coloured degree-1 kernel reads the block-interleaved copies
     const bool q1 = op->degree == 1 && !atomic;
     if (fused && q1) return fail(MF_EINVAL, "internal: fused gather with the coloured Q1 kernel");
@@ -867,7 +887,8 @@ static bool default_coloured(const mf_op *op) {
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
-  if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_TET && op->ncomp == 1) ||
+  if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_HEX && op->kind == MF_OP_ELASTICITY) ||
+      (op->cell_type == MF_CELL_TET && op->ncomp == 1) ||
       (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)))
     return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC, scalar tet or P2+ triangle operators");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
@@ -909,7 +930,9 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   // supported combinations
   bool ok = false;
   if (ct == MF_CELL_HEX)
-    ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3) : (kind <= MF_OP_POISSON && sp->ncomp == 1);
+    ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3)
+         : kind == MF_OP_ELASTICITY ? sp->ncomp == 3
+                                    : (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else if (ct == MF_CELL_QUAD)
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);
   else if (ct == MF_CELL_TET)
@@ -939,6 +962,9 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   const bool tensor = ct == MF_CELL_HEX || ct == MF_CELL_QUAD;
   op->nq1d = tensor ? (nq1d > 0 ? nq1d : sp->degree + 1) : 0;
   if (ct == MF_CELL_HEX) op->nqp = op->nq1d * op->nq1d * op->nq1d;
+  if (ct == MF_CELL_HEX && kind == MF_OP_ELASTICITY &&
+      ((op->nq1d != sp->degree + 1 && op->nq1d != sp->degree + 2) || op->nq1d > 7))
+    return fail(MF_EUNSUPPORTED, "hex elasticity: nq1d must be k+1 or k+2 (at most 7)");
   if (ct == MF_CELL_QUAD) {
     // one lane per point, and every dof needs a lane
     if (op->nq1d != sp->degree + 1 && op->nq1d != sp->degree + 2)
@@ -991,14 +1017,15 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
   if (pr->scatter == MF_SCATTER_PATCH) {
-    if (ct != MF_CELL_HEX || op->degree != 1)
+    if (ct != MF_CELL_HEX || op->degree != 1 || kind == MF_OP_ELASTICITY)
       return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for hex Q1 only");
     op->patched = true;
-  } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15)) {
+  } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
+             kind != MF_OP_ELASTICITY) {
     op->patched = true;
   }
   if (op->patched) op->coloured = false;
-  if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured) {
+  if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured && kind != MF_OP_ELASTICITY) {
     // First-touch thresholds for overwrite applies (HexArgs::first). Colours are
     // launched in internal cell order, so a node's first toucher is the first cell in
     // that order that lists it. The threshold form needs every later toucher to see the
@@ -1057,9 +1084,12 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     }
     if (rc) return rc;
   }
-  if (ct == MF_CELL_HEX)
+  if (ct == MF_CELL_HEX) {
     rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, to_pos2, s)
                              : setup_hex<float>(op.get(), sp, pr, m, to_pos2, s);
+    if (!rc && kind == MF_OP_ELASTICITY)
+      rc = precision == MF_F64 ? upload_tensor_tables<double>(op.get(), s) : upload_tensor_tables<float>(op.get(), s);
+  }
   else if (ct == MF_CELL_QUAD)
     rc = precision == MF_F64 ? setup_quad<double>(op.get(), sp, pr, s) : setup_quad<float>(op.get(), sp, pr, s);
   else if (ct == MF_CELL_TET)

@@ -200,6 +200,23 @@ template <typename T> struct QuadArgs {
 template <typename T>
 int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s, bool diag = false);
 
+// ELASTICITY on Q1..Q6 hexahedra (hex_elas_kernels.hip): three node-interleaved
+// components, sum-factorised, nq = k+1 or k+2 Gauss points per direction (at most 7)
+template <typename T> struct HexElasArgs {
+  const int32_t *map;  // [ncells][(k+1)^3] node ids, internal numbering (negative: constrained)
+  const T *geo;        // [ncells][24] trilinear coefficients c1..c7 per coordinate
+  const T *tab;        // B [nq][k+1], B' [nq][k+1], weights [nq], points [nq]
+  const T *x;
+  T *y;
+  int64_t c0, c1;
+  const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
+  int64_t ulo, uhi;
+  T lam, mu;
+  const int32_t *gmap;  // if set: x is gathered through it (fused permutation), y through map
+};
+template <typename T>
+int launch_hex_elasticity(int k, int nq, const HexElasArgs<T> &a, bool atomic, hipStream_t s);
+
 // Tri P1 mass with vertex coefficient (simplex_kernels.hip)
 template <typename T> struct TriArgs {
   const int32_t *map;  // ncells x 3 (negative: constrained)
