@@ -246,6 +246,26 @@ def bench_simplex(mf, mg, reps=20):
             del op, xt, yt
         del sp, space
     del tmesh
+    # elasticity on Q2 / Q4 hexahedra (32^3 cells, one workgroup per cell)
+    hmesh = mg.hex_mesh(32, 0.15, config=1)
+    for k in (2, 4):
+        space = mg.hex_space(hmesh, k, ncomp=3)
+        sp = mf.Space.from_meshgen(space)
+        x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
+        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
+            op = mf.Operator(sp, mf.ELASTICITY, prec)
+            xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+            yt = torch.empty_like(xt)
+            t = time_kernel(op, xt, yt, reps)
+            r = roof(op, t, prec)
+            tag = f"hex_elasticity_q{k}_{ptag}"
+            out[tag] = {"cells": hmesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
+                        "launches": op.info["cell_launches"], "qp": op.info["nqp"], "bound": r["bound"],
+                        "frac": r["frac"], "gbs": r["gbs"], "tflops": r["tflops"]}
+            log(f"  {tag}: {json.dumps(out[tag])}")
+            del op, xt, yt
+        del sp, space
+    del hmesh
     # Q_k quadrilaterals (2D sum factorisation, lane per point), 1024 x 1024 cells
     qmesh = mg.quad_mesh(1024, 0.25, config=0)
     for k, kind, name, nc in ((2, mf.HELMHOLTZ, "helmholtz", 1), (6, mf.LAPLACIAN, "laplacian", 1),

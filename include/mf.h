@@ -142,8 +142,8 @@ typedef struct {
  * use a rule exact for the integrand. params may be
  * NULL (coefficient 1, lambda 1, mu 0.5, no constraints). stream: device
  * uploads are ordered on it; the call returns after they complete.
- * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1) and LAPLACIAN
- * (ncomp 1 or 3); tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
+ * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1), LAPLACIAN
+ * (ncomp 1 or 3) and ELASTICITY (ncomp 3; nq1d k+1 or k+2, at most 7); tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
  * HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules reach degree 7);
  * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1) and ELASTICITY P1-P3
  * (ncomp 2, the 2D stress); quad MASS, HELMHOLTZ,
@@ -164,8 +164,8 @@ int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x
                       int accumulate, void *stream);
 
 /* d = diag(A) (ndofs, op precision); constrained dofs get 1. Used as the Jacobi
- * preconditioner. MF_EUNSUPPORTED for HYPERELASTIC, the one-component tet operators
- * and triangles other than the P1 mass. */
+ * preconditioner. MF_EUNSUPPORTED for HYPERELASTIC, hex ELASTICITY, the one-component
+ * tet operators and triangles other than the P1 mass. */
 int mf_op_diagonal(const mf_op *op, void *d, void *stream);
 
 /* Internal cell order and numbering. Every space colours its cells greedily
