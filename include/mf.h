@@ -117,8 +117,9 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *   AUTO      COLOURED for 3-component hex operators of degree >= 2 on meshes of
  *             at least 4096 cells and for scalar hex operators of degree >= 2 on
  *             at least 2^18 cells; PATCH for hex Q1 on at least 2^15 cells; tets
- *             of degree >= 2 and quad ELASTICITY COLOURED (at least 4096 cells);
- *             else ATOMIC (the measured choices).
+ *             of degree >= 2, quad and triangle ELASTICITY (at least 4096 cells)
+ *             and the other triangle operators but the P1 mass on at least 2^20
+ *             cells COLOURED; else ATOMIC (the measured choices).
  * Range applies (mf_op_apply_range*) always use ATOMIC. Errors at mf_op_create:
  * MF_EUNSUPPORTED for PATCH on other cells or degrees. */
 enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2, MF_SCATTER_PATCH = 3 };

@@ -876,9 +876,18 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
 // colours): the two scatters are within a few percent for the one-component operators
 // (atomic ahead at 256^2 cells), and the coloured launches win for elasticity (Q2 at
 // 1024^2 cells: 390 against 527 us in FP64, 251 against 379 us in FP32).
+// Triangles (lane-per-cell kernel): elasticity P1-P3 at 1024^2 x 2 cells 2.2-5x faster
+// coloured (P2 FP64 943 -> 323 us), and mostly faster at 256^2 x 2; the one-component
+// operators lose coloured at 256^2 x 2 cells (P2 Helmholtz 29 against 51 us) and win at
+// 1024^2 x 2 (366 -> 173 us), so they switch at 2^20 cells (between the two measured
+// sizes). The closed-form P1 mass keeps atomics (not measured).
 static bool default_coloured(const mf_op *op) {
   if (op->ncells < 4096) return false;
   if (op->cell_type == MF_CELL_QUAD) return op->ncomp == 2;
+  if (op->cell_type == MF_CELL_TRI) {
+    if (op->kind == MF_OP_MASS && op->degree == 1) return false;
+    return op->ncomp == 2 || op->ncells >= (1 << 20);
+  }
   if (op->cell_type == MF_CELL_HEX) {
     if (op->ncomp == 3 && op->degree >= 2) return true;
     return op->ncells >= (op->degree == 1 ? (1 << 19) : (1 << 18));
