@@ -5,9 +5,10 @@
 // The basis is a tensor product, so the action factorises into 1D contractions
 // (Sections 3 and 4.2.4): three passes forward (values and reference gradients of each
 // component at the points), the pointwise stress with the Jacobian of the trilinear map
-// evaluated at every point (Section 2.1), and three passes back. One workgroup per
-// cell, one thread per quadrature point (rounded up to whole wavefronts); between the
-// passes the partial contractions sit in two ping-pong LDS buffers.
+// evaluated at every point (Section 2.1), and three passes back. A thread per quadrature
+// point; one cell per workgroup (rounded up to whole wavefronts), or 64 / nq^3 cells in
+// one wavefront when a cell has at most 32 points (Q1: 8, Q2: 2); between the passes the
+// partial contractions sit in two ping-pong LDS buffers per cell.
 #include "mf_internal.h"
 
 namespace mf {
@@ -24,74 +25,81 @@ __device__ __forceinline__ void hex_el_atomic_add(float *p, float v) { unsafeAto
 template <typename T, int N, int NQ>
 __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T> A, const bool atomic) {
   constexpr int D = N * N * N, SX = NQ * N * N, SY = NQ * NQ * N, P = NQ * NQ * NQ, H = NQ * N;
+  constexpr int CPB = P <= 32 ? 64 / P : 1;  // cells per workgroup (Q1: 8, Q2: 2)
   static_assert(NQ >= N, "every node needs a thread");
   __shared__ T sB[H], sD[H], sw[NQ], sg[NQ];
-  __shared__ T bufA[9 * SY];  // dofs, then the y-pass fields, then the backward z fields
-  __shared__ T bufB[9 * P];   // x-pass fields, then the point fluxes, then the backward y fields
-  const int t = threadIdx.x;
+  __shared__ T bufA[CPB][9 * SY];  // dofs, then the y-pass fields, then the backward z fields
+  __shared__ T bufB[CPB][9 * P];   // x-pass fields, then the point fluxes, then the backward y fields
+  const int tid = threadIdx.x;
+  const int slot = tid / P, t = tid - slot * P;  // cell of the workgroup, thread within it
+  const bool act = slot < CPB;
   // consecutive workgroup ids land on different XCDs: each XCD takes a contiguous run
-  const int64_t n = A.c1 - A.c0, per = (n + 7) / 8;
-  const int64_t ci = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (ci >= n) return;  // uniform over the workgroup
-  const int64_t cell = A.c0 + ci;
-  if (A.cell_user) {
+  const int64_t ngrp = (A.c1 - A.c0 + CPB - 1) / CPB, per = (ngrp + 7) / 8;
+  const int64_t gi0 = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (gi0 >= ngrp) return;  // uniform over the workgroup
+  const int64_t cell = A.c0 + gi0 * CPB + slot;
+  bool valid = act && cell < A.c1;
+  if (valid && A.cell_user) {
     const int64_t u = A.cell_user[cell];
-    if (u < A.ulo || u >= A.uhi) return;  // uniform: one cell per workgroup
+    valid = u >= A.ulo && u < A.uhi;
   }
-  if (t < H) {
-    sB[t] = A.tab[t];
-    sD[t] = A.tab[H + t];
+  if (tid < H) {
+    sB[tid] = A.tab[tid];
+    sD[tid] = A.tab[H + tid];
   }
-  if (t < NQ) {
-    sw[t] = A.tab[2 * H + t];
-    sg[t] = A.tab[2 * H + NQ + t];
+  if (tid < NQ) {
+    sw[tid] = A.tab[2 * H + tid];
+    sg[tid] = A.tab[2 * H + NQ + tid];
   }
   int idx = -1;  // node of dof t in y (internal numbering)
-  if (t < D) {
-    idx = A.map[cell * D + t];
-    const int gi = A.gmap ? A.gmap[cell * D + t] : idx;  // its position in x
+  if (act && t < D) {
+    int gi = -1;  // its position in x
+    if (valid) {
+      idx = A.map[cell * D + t];
+      gi = A.gmap ? A.gmap[cell * D + t] : idx;
+    }
 #pragma unroll
-    for (int c = 0; c < 3; c++) bufA[c * D + t] = gi >= 0 ? A.x[(int64_t)gi * 3 + c] : T(0);
+    for (int c = 0; c < 3; c++) bufA[slot][c * D + t] = gi >= 0 ? A.x[(int64_t)gi * 3 + c] : T(0);
   }
   __syncthreads();
   // x pass, thread (a, j, l): X0 = sum_i B[a][i] U[i, j, l], X1 with B'
-  if (t < SX) {
+  if (act && t < SX) {
     const int a = t % NQ, j = (t / NQ) % N, l = t / (NQ * N);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       T s0 = T(0), s1 = T(0);
 #pragma unroll
       for (int i = 0; i < N; i++) {
-        const T u = bufA[c * D + i + N * (j + N * l)];
+        const T u = bufA[slot][c * D + i + N * (j + N * l)];
         s0 += sB[a * N + i] * u;
         s1 += sD[a * N + i] * u;
       }
-      bufB[c * SX + t] = s0;
-      bufB[(3 + c) * SX + t] = s1;
+      bufB[slot][c * SX + t] = s0;
+      bufB[slot][(3 + c) * SX + t] = s1;
     }
   }
   __syncthreads();
   // y pass, thread (a, b, l): Y00 = B_y X0, Y01 = B'_y X0, Y10 = B_y X1
-  if (t < SY) {
+  if (act && t < SY) {
     const int a = t % NQ, b = (t / NQ) % NQ, l = t / (NQ * NQ);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
       T y00 = T(0), y01 = T(0), y10 = T(0);
 #pragma unroll
       for (int j = 0; j < N; j++) {
-        const T x0 = bufB[c * SX + a + NQ * (j + N * l)], x1 = bufB[(3 + c) * SX + a + NQ * (j + N * l)];
+        const T x0 = bufB[slot][c * SX + a + NQ * (j + N * l)], x1 = bufB[slot][(3 + c) * SX + a + NQ * (j + N * l)];
         y00 += sB[b * N + j] * x0;
         y01 += sD[b * N + j] * x0;
         y10 += sB[b * N + j] * x1;
       }
-      bufA[c * SY + t] = y00;
-      bufA[(3 + c) * SY + t] = y01;
-      bufA[(6 + c) * SY + t] = y10;
+      bufA[slot][c * SY + t] = y00;
+      bufA[slot][(3 + c) * SY + t] = y01;
+      bufA[slot][(6 + c) * SY + t] = y10;
     }
   }
   __syncthreads();
   // z pass and the stress, thread = point (a, b, e)
-  if (t < P) {
+  if (act && t < P) {
     const int a = t % NQ, b = (t / NQ) % NQ, e = t / (NQ * NQ);
     T g[3][3];  // g[c][d]: reference derivative d of component c
 #pragma unroll
@@ -100,21 +108,26 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
 #pragma unroll
       for (int l = 0; l < N; l++) {
         const int h = a + NQ * (b + NQ * l);
-        gx += sB[e * N + l] * bufA[(6 + c) * SY + h];
-        gy += sB[e * N + l] * bufA[(3 + c) * SY + h];
-        gz += sD[e * N + l] * bufA[c * SY + h];
+        gx += sB[e * N + l] * bufA[slot][(6 + c) * SY + h];
+        gy += sB[e * N + l] * bufA[slot][(3 + c) * SY + h];
+        gz += sD[e * N + l] * bufA[slot][c * SY + h];
       }
       g[c][0] = gx;
       g[c][1] = gy;
       g[c][2] = gz;
     }
     const T x1 = sg[a], x2 = sg[b], x3 = sg[e];
-    const T *gc = A.geo + cell * 24;
+    // with several cells per workgroup a thread without a cell takes the unit cube, so that
+    // its discarded arithmetic stays finite; with one, every active thread's cell index is
+    // in range (a cell left out of a range apply only skips its scatter)
+    const bool gv = CPB == 1 || valid;
     T J[3][3];  // J[r][d] = d x_r / d xi_d
 #pragma unroll
     for (int r = 0; r < 3; r++) {
-      const T c1 = gc[r], c2 = gc[3 + r], c3 = gc[6 + r], c4 = gc[9 + r], c5 = gc[12 + r], c6 = gc[15 + r],
-              c7 = gc[18 + r];
+      const T *gc = A.geo + cell * 24;
+      const T c1 = gv ? gc[r] : T(r == 0), c2 = gv ? gc[3 + r] : T(r == 1), c3 = gv ? gc[6 + r] : T(r == 2),
+              c4 = gv ? gc[9 + r] : T(0), c5 = gv ? gc[12 + r] : T(0), c6 = gv ? gc[15 + r] : T(0),
+              c7 = gv ? gc[18 + r] : T(0);
       J[r][0] = c1 + c4 * x2 + c5 * x3 + c7 * x2 * x3;
       J[r][1] = c2 + c4 * x1 + c6 * x3 + c7 * x1 * x3;
       J[r][2] = c3 + c5 * x1 + c6 * x2 + c7 * x1 * x2;
@@ -147,12 +160,12 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
 #pragma unroll
       for (int r = 0; r < 3; r++) S[r] = A.mu * (G[c][r] + G[r][c]) + (r == c ? tr : T(0));
 #pragma unroll
-      for (int d = 0; d < 3; d++) bufB[(3 * d + c) * P + t] = wdet * (C[0][d] * S[0] + C[1][d] * S[1] + C[2][d] * S[2]);
+      for (int d = 0; d < 3; d++) bufB[slot][(3 * d + c) * P + t] = wdet * (C[0][d] * S[0] + C[1][d] * S[1] + C[2][d] * S[2]);
     }
   }
   __syncthreads();
   // backward z, thread (a, b, l): Zx = B_z Fx, Zy = B_z Fy, Zz = B'_z Fz
-  if (t < SY) {
+  if (act && t < SY) {
     const int a = t % NQ, b = (t / NQ) % NQ, l = t / (NQ * NQ);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -160,18 +173,18 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
 #pragma unroll
       for (int e = 0; e < NQ; e++) {
         const int q = a + NQ * (b + NQ * e);
-        zx += sB[e * N + l] * bufB[c * P + q];
-        zy += sB[e * N + l] * bufB[(3 + c) * P + q];
-        zz += sD[e * N + l] * bufB[(6 + c) * P + q];
+        zx += sB[e * N + l] * bufB[slot][c * P + q];
+        zy += sB[e * N + l] * bufB[slot][(3 + c) * P + q];
+        zz += sD[e * N + l] * bufB[slot][(6 + c) * P + q];
       }
-      bufA[c * SY + t] = zx;
-      bufA[(3 + c) * SY + t] = zy;
-      bufA[(6 + c) * SY + t] = zz;
+      bufA[slot][c * SY + t] = zx;
+      bufA[slot][(3 + c) * SY + t] = zy;
+      bufA[slot][(6 + c) * SY + t] = zz;
     }
   }
   __syncthreads();
   // backward y, thread (a, j, l): Vx = B_y Zx, Vb = B'_y Zy + B_y Zz
-  if (t < SX) {
+  if (act && t < SX) {
     const int a = t % NQ, j = (t / NQ) % N, l = t / (NQ * N);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -179,16 +192,16 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
 #pragma unroll
       for (int b = 0; b < NQ; b++) {
         const int h = a + NQ * (b + NQ * l);
-        vx += sB[b * N + j] * bufA[c * SY + h];
-        vb += sD[b * N + j] * bufA[(3 + c) * SY + h] + sB[b * N + j] * bufA[(6 + c) * SY + h];
+        vx += sB[b * N + j] * bufA[slot][c * SY + h];
+        vb += sD[b * N + j] * bufA[slot][(3 + c) * SY + h] + sB[b * N + j] * bufA[slot][(6 + c) * SY + h];
       }
-      bufB[c * SX + t] = vx;
-      bufB[(3 + c) * SX + t] = vb;
+      bufB[slot][c * SX + t] = vx;
+      bufB[slot][(3 + c) * SX + t] = vb;
     }
   }
   __syncthreads();
   // backward x, thread (i, j, l), and the scatter
-  if (t < D && idx >= 0) {
+  if (act && t < D && idx >= 0) {
     const int i = t % N, j = (t / N) % N, l = t / (N * N);
 #pragma unroll
     for (int c = 0; c < 3; c++) {
@@ -196,7 +209,7 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
 #pragma unroll
       for (int a = 0; a < NQ; a++) {
         const int h = a + NQ * (j + N * l);
-        v += sD[a * N + i] * bufB[c * SX + h] + sB[a * N + i] * bufB[(3 + c) * SX + h];
+        v += sD[a * N + i] * bufB[slot][c * SX + h] + sB[a * N + i] * bufB[slot][(3 + c) * SX + h];
       }
       T *yp = A.y + (int64_t)idx * 3 + c;
       if (atomic) hex_el_atomic_add(yp, v);
@@ -207,9 +220,9 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
 
 template <typename T, int N, int NQ>
 static int launch_hex_el_nq(const HexElasArgs<T> &a, bool atomic, hipStream_t s) {
-  constexpr int P = NQ * NQ * NQ;
-  const int64_t n = a.c1 - a.c0;
-  const dim3 g((unsigned)(((n + 7) / 8) * 8)), b((unsigned)((P + 63) / 64 * 64));
+  constexpr int P = NQ * NQ * NQ, CPB = P <= 32 ? 64 / P : 1;
+  const int64_t ngrp = (a.c1 - a.c0 + CPB - 1) / CPB;
+  const dim3 g((unsigned)(((ngrp + 7) / 8) * 8)), b((unsigned)(CPB > 1 ? 64 : (P + 63) / 64 * 64));
   hex_elasticity_kernel<T, N, NQ><<<g, b, 0, s>>>(a, atomic);
   MF_HIP(hipGetLastError());
   return MF_OK;
