@@ -191,3 +191,16 @@ def test_quad_elasticity_invariants(k):
     eps = (G + G.T) / 2
     energy = lam * np.trace(eps) ** 2 + 2 * mu * (eps * eps).sum()
     assert abs(u @ y.ravel() - energy) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
+def test_quad_diagonal_is_assembled_diagonal(kind):
+    """The oracle's diagonal on perturbed quads equals the diagonal of the matrix
+    assembled from its element matrices (which the tensor-structure pins fix)."""
+    mesh = mg.quad_mesh(3, 0.25, config=0)
+    nc = 2 if kind == 4 else 1
+    space = mg.quad_space(mesh, 3, ncomp=nc)
+    c = np.exp(np.random.default_rng(3).normal(size=mesh.nverts)) if kind in (0, 3) else None
+    op = oracle.OracleOp(space, kind, coef=c, lam=0.7, mu=0.4)
+    d = np.diag(op.assemble_dense())
+    assert np.abs(op.diagonal() - d).max() <= 1e-14 * np.abs(d).max()
