@@ -1,0 +1,197 @@
+"""Pins of the oracle's coefficient paths and of the hex tensor form at Q5/Q6.
+
+The variable-coefficient operators (POISSON's kappa, the MASS coefficient c) read a
+per-vertex field interpolated with the coordinate map's vertex basis (supplementary
+operator list; Section 2.1: coefficients live in the same finite element machinery as
+the coordinates). Two exact identities pin that path on perturbed meshes of every
+cell type:
+
+* For a vertex field kappa_v = l(x_v) with l affine, the interpolant reproduces
+  l(x) exactly (the geometry is the same interpolation of the vertex coordinates),
+  and u = g.x is reproduced exactly by the isoparametric space, so
+  u^T K u = |g|^2 int_Omega l dx. The integrand kappa |det J| has degree <= 3 per
+  reference variable on hexahedra (<= 2 on quadrilaterals, 1 on simplices), which
+  the (k+1)-point Gauss rule and the simplex rules integrate exactly.
+* 1^T M(c) 1 = int_Omega c dx for the same affine c (partition of unity), and for
+  k >= 2 also u^T M(c) 1 = int c u dx with u = g.x + s.
+
+The domain is the unit cube/square (boundary vertices move tangentially), so the
+integrals of affine and quadratic functions are closed forms. A dropped coefficient,
+a coefficient interpolated with a mirrored or permuted vertex basis, or a wrong
+Jacobian factor changes these sums.
+
+Also the uniform-mesh Kronecker pin at Q5 and Q6, with the 1D matrices built from
+GLL nodes found as roots of P_k' (numpy) and integrated by a longer Gauss rule --
+code paths separate from the oracle's tables.
+"""
+import numpy as np
+import pytest
+from numpy.polynomial import legendre as L
+
+import oracle
+from oracle import tables as T
+from paper_1903_08243_amd import meshgen as mg
+
+A0, B = 2.0, np.array([1.0, -0.5, 0.3])  # kappa = A0 + B . x  (positive on the unit cube)
+
+
+def _unit_integrals(gdim):
+    """int over [0,1]^d of 1, x_i and x_i x_j."""
+    m1 = np.full(gdim, 0.5)
+    m2 = np.full((gdim, gdim), 0.25) + np.eye(gdim) * (1.0 / 3.0 - 0.25)
+    return m1, m2
+
+
+def _vertex_field(mesh, a, b):
+    return a + mesh.coords @ b[: mesh.gdim]
+
+
+def _hex_nodes(mesh, sp_):
+    k, n = sp_.degree, sp_.degree + 1
+    g = T.gll_nodes01(k)
+    X = mesh.coords[mesh.cell2vert]
+    out = np.zeros((sp_.nnodes, 3))
+    for l in range(n):
+        for j in range(n):
+            for i in range(n):
+                xi = (g[i], g[j], g[l])
+                p = np.zeros((mesh.ncells, 3))
+                for v in range(8):
+                    o = (v & 1, (v >> 1) & 1, (v >> 2) & 1)
+                    p += np.prod([xi[d] if o[d] else 1 - xi[d] for d in range(3)]) * X[:, v, :]
+                out[sp_.cell2node[:, i + n * (j + n * l)]] = p
+    return out
+
+
+def _quad_nodes(mesh, sp_):
+    k, n = sp_.degree, sp_.degree + 1
+    g = T.gll_nodes01(k)
+    X = mesh.coords[mesh.cell2vert]
+    out = np.zeros((sp_.nnodes, 2))
+    for j in range(n):
+        for i in range(n):
+            xi, eta = g[i], g[j]
+            N = np.array([(1 - xi) * (1 - eta), xi * (1 - eta), (1 - xi) * eta, xi * eta])
+            out[sp_.cell2node[:, i + n * j]] = np.einsum("v,cva->ca", N, X)
+    return out
+
+
+def _simplex_nodes(mesh, sp_):
+    dim = mesh.gdim
+    alpha = T.simplex_lattice(sp_.degree, dim) / sp_.degree
+    X = mesh.coords[mesh.cell2vert]
+    pos = X[:, None, 0, :] + np.einsum("da,cae->cde", alpha, X[:, 1:, :] - X[:, None, 0, :])
+    out = np.zeros((sp_.nnodes, dim))
+    out[sp_.cell2node.ravel()] = pos.reshape(-1, dim)
+    return out
+
+
+def _case(cell, k):
+    if cell == "hex":
+        mesh = mg.hex_mesh(3, 0.15, config=1, seed_k=k)
+        sp_ = mg.hex_space(mesh, k)
+        return mesh, sp_, _hex_nodes(mesh, sp_)
+    if cell == "quad":
+        mesh = mg.quad_mesh(4, 0.25, config=0, seed_k=k)
+        sp_ = mg.quad_space(mesh, k)
+        return mesh, sp_, _quad_nodes(mesh, sp_)
+    if cell == "tet":
+        mesh = mg.tet_mesh(2, 0.2, config=2, seed_k=k)
+        sp_ = mg.tet_space(mesh, k, ncomp=1)
+        return mesh, sp_, _simplex_nodes(mesh, sp_)
+    mesh = mg.tri_mesh(4, 0.2, config=0)
+    sp_ = mg.tri_space(mesh, k)
+    return mesh, sp_, _simplex_nodes(mesh, sp_)
+
+
+CASES = [("hex", k) for k in range(1, 7)] + [("quad", k) for k in range(1, 7)] + \
+        [("tet", k) for k in (1, 2, 3)] + [("tri", k) for k in (1, 2, 3)]
+
+
+@pytest.mark.parametrize("cell,k", CASES)
+def test_poisson_energy_of_linear_field_is_kappa_integral(cell, k):
+    mesh, sp_, xn = _case(cell, k)
+    d = mesh.gdim
+    m1, _ = _unit_integrals(d)
+    kint = A0 + B[:d] @ m1
+    op = oracle.OracleOp(sp_, oracle.OP_POISSON, coef=_vertex_field(mesh, A0, B))
+    g = np.array([0.3, -1.1, 0.7])[:d]
+    h = np.array([-0.8, 0.4, 1.3])[:d]
+    u, v = xn @ g, xn @ h
+    Ku = op.apply(u)
+    assert abs(u @ Ku - (g @ g) * kint) < 1e-12 * (g @ g) * kint
+    assert abs(v @ Ku - (g @ h) * kint) < 1e-12 * (g @ g + h @ h) * kint
+    # the same field without the coefficient gives |g|^2 |Omega|: kappa is not dropped
+    plain = oracle.OracleOp(sp_, oracle.OP_LAPLACIAN)
+    assert abs(u @ plain.apply(u) - g @ g) < 1e-12 * (g @ g)
+    assert abs(kint - 1.0) > 0.1
+
+
+@pytest.mark.parametrize("cell,k", CASES)
+def test_mass_coefficient_integrals(cell, k):
+    mesh, sp_, xn = _case(cell, k)
+    d = mesh.gdim
+    m1, m2 = _unit_integrals(d)
+    b = B[:d]
+    op = oracle.OracleOp(sp_, oracle.OP_MASS, coef=_vertex_field(mesh, A0, B))
+    one = np.ones(sp_.ndofs)
+    M1 = op.apply(one)
+    assert abs(one @ M1 - (A0 + b @ m1)) < 1e-13
+    # int (A0 + b.x)(s + g.x): degree 2 in x, exact for the rule when the integrand
+    # c u |det J| has per-variable degree <= 2k+1 (hex: 1 + 1 + 2 <= 2k+1 for k >= 2)
+    if cell in ("hex", "quad") and k < 2:
+        return
+    s, g = 0.4, np.array([0.3, -1.1, 0.7])[:d]
+    u = s + xn @ g
+    exact = A0 * s + (A0 * g + s * b) @ m1 + b @ m2 @ g
+    assert abs(u @ M1 - exact) < 1e-13 * max(1.0, abs(exact))
+
+
+def _gll01_numpy(k):
+    inner = L.legroots(L.legder([0] * k + [1])) if k >= 2 else np.zeros(0)
+    return np.concatenate([[0.0], (np.sort(inner) + 1) / 2, [1.0]])
+
+
+def _1d_matrices_numpy(k):
+    """1D GLL mass and stiffness on [0, 1] by a (k+3)-point Gauss rule (exact for the
+    degree-2k products), basis and derivative by the product formula."""
+    x = _gll01_numpy(k)
+    t, w = L.leggauss(k + 3)
+    t, w = (t + 1) / 2, w / 2
+    n = k + 1
+    V = np.ones((t.size, n))
+    dV = np.zeros((t.size, n))
+    for i in range(n):
+        for m in range(n):
+            if m == i:
+                continue
+            V[:, i] *= (t - x[m]) / (x[i] - x[m])
+            term = np.full(t.size, 1.0 / (x[i] - x[m]))
+            for r in range(n):
+                if r not in (i, m):
+                    term *= (t - x[r]) / (x[i] - x[r])
+            dV[:, i] += term
+    return V.T @ (w[:, None] * V), dV.T @ (w[:, None] * dV)
+
+
+@pytest.mark.parametrize("k", [5, 6])
+def test_uniform_hex_matches_kronecker_assembly_high_degree(k):
+    """On an undistorted mesh the (k+1)-point Gauss rule is exact for the mass and
+    stiffness integrands, so the operator is the Kronecker form of the 1D matrices."""
+    m, h = 2, 0.5
+    mesh = mg.hex_mesh(m, 0.0)
+    M1, K1 = _1d_matrices_numpy(k)
+    Me = h ** 3 * np.kron(np.kron(M1, M1), M1)
+    Ke = h * (np.kron(np.kron(M1, M1), K1) + np.kron(np.kron(M1, K1), M1) + np.kron(np.kron(K1, M1), M1))
+    for ncomp, kind, Eloc in [(1, oracle.OP_MASS, Me), (1, oracle.OP_HELMHOLTZ, Me + Ke),
+                              (3, oracle.OP_LAPLACIAN, Ke)]:
+        sp_ = mg.hex_space(mesh, k, ncomp=ncomp, renumber=True, config=9)
+        op = oracle.OracleOp(sp_, kind)
+        x = np.random.default_rng(k).uniform(-1, 1, op.ndofs)
+        Ax = np.zeros(op.ndofs)
+        for c2n in sp_.cell2node:
+            for comp in range(ncomp):
+                idx = c2n.astype(np.int64) * ncomp + comp
+                Ax[idx] += Eloc @ x[idx]
+        y = op.apply(x)
+        assert np.max(np.abs(y - Ax)) <= 1e-12 * np.max(np.abs(Ax))

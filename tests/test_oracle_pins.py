@@ -189,7 +189,7 @@ def test_q1_interior_stencils_golden():
 
 
 # ----------------------------------------------------------------- P5 volumes
-@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_hex_mass_volume_perturbed(k):
     mesh = mg.hex_mesh(3, 0.15, config=1, seed_k=k)
     sp_ = mg.hex_space(mesh, k)
@@ -375,7 +375,7 @@ def test_elasticity_kills_rigid_modes(k):
 
 
 # ----------------------------------------------------------------- P7 linear fields
-@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_hex_laplacian_of_linear_field_vanishes_inside(k):
     mesh = mg.hex_mesh(3, 0.15, config=1, seed_k=k)
     sp_ = mg.hex_space(mesh, k)
