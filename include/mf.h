@@ -347,6 +347,14 @@ int mf_batch_solve(mf_batch *batch, double rtol, double inner_rtol, int maxit, m
 /* One batched operator launch (inner = 1: the inner operators on the internal
  * search directions; 0: the FP64 operators on the iterates), for timing. */
 int mf_batch_apply(mf_batch *batch, int inner, void *stream);
+/* y[i] = A[i] x[i] for every system in ONE batched launch (the launch mf_batch_solve
+ * iterates with, at the current tuning): inner = 1 applies the inner operators (A32
+ * when the batch refines: x[i], y[i] FP32; else A64), inner = 0 the FP64 operators.
+ * x[i], y[i]: device vectors of system i in user numbering (nsys entries each, y[i]
+ * overwritten, no aliasing). The inputs pass through the batch's internal iteration
+ * buffers, which a later mf_batch_solve re-initialises from the bound vectors.
+ * Asynchronous on stream. Errors: MF_EINVAL (null batch, array or vector). */
+int mf_batch_apply_user(mf_batch *batch, int inner, const void *const *x, void *const *y, void *stream);
 /* Autotuner: times the batched launch with one wavefront per single-batch work
  * item (grid 0), and persistent grids of 1, 2, 4 x (CUs x 4) wavefronts with
  * work-list granularities of 1..32 cell batches per item, and keeps the fastest. With cache_path, a result for the same (kind, inner
@@ -356,6 +364,16 @@ int mf_batch_autotune(mf_batch *batch, const char *cache_path, void *stream);
 int mf_batch_get_tuning(const mf_batch *batch, int *items_per, int *grid);
 int mf_batch_set_tuning(mf_batch *batch, int items_per, int grid);
 void mf_batch_destroy(mf_batch *batch);
+
+/* ----------------------------------------------------------------- attainable peaks
+ * The device's attainable rates, measured as the paper measured its CPUs' (Section 4.1,
+ * Table 1: STREAM bandwidth and LINPACK beside the theoretical peaks): out[0] HBM GB/s
+ * of a 1 GiB streaming copy (bytes read + written), out[1] FP64 and out[2] FP32 vector
+ * multiply-add TFLOP/s (independent chains, no packed math), out[3] FP32 matrix TFLOP/s
+ * (v_mfma_f32_4x4x1_16b) and out[4] FP64 matrix TFLOP/s (v_mfma_f64_4x4x4_4b).
+ * out: host, 5 doubles. Allocates and frees 2 GiB of device memory. Synchronous.
+ * Errors: MF_EINVAL (out NULL), MF_ENOMEM, MF_EDEVICE. */
+int mf_probe_peaks(double *out, void *stream);
 
 /* ----------------------------------------------------------------- teardown / errors */
 void mf_mesh_destroy(mf_mesh *m);   /* NULL-safe */

@@ -8,5 +8,5 @@ first call raises -- there is no CPU fallback.
 from .api import (  # noqa: F401
     CELL_HEX, CELL_QUAD, CELL_TET, CELL_TRI, F32, F64, SCATTER_AUTO, SCATTER_ATOMIC, SCATTER_COLOURED, SCATTER_PATCH, MASS, HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY, HYPERELASTIC,
     MFError, Mesh, Space, Operator, JacobiPrecond, LearnedPrecond, CNN, Batch, cg_solve, cnn_nparams,
-    cnn_initial_weights, library_path, load_library,
+    cnn_initial_weights, library_path, load_library, probe_peaks,
 )

@@ -83,6 +83,7 @@ def load_library():
         "mf_batch_create": (I, [I, P, P, P, P, P, P, PP]),
         "mf_batch_solve": (I, [P, D, D, I, P, P]),
         "mf_batch_apply": (I, [P, I, P]),
+        "mf_batch_apply_user": (I, [P, I, P, P, P]),
         "mf_batch_autotune": (I, [P, ctypes.c_char_p, P]),
         "mf_batch_get_tuning": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "mf_batch_set_tuning": (I, [P, I, I]),
@@ -106,6 +107,7 @@ def load_library():
         "mf_precond_harvest": (I, [P, P, P, I, I, P, P, P, P]),
         "mf_cnn_energy_loss_grad": (I, [P, P, P, P, ctypes.POINTER(D), P, P]),
         "mf_cnn_train_energy": (I, [P, P, P, I, P, I, P, ctypes.c_float, P, P]),
+        "mf_probe_peaks": (I, [P, P]),
         "mf_last_error": (ctypes.c_char_p, []),
         "mf_version": (ctypes.c_char_p, []),
     }
@@ -141,6 +143,15 @@ def _dev(t, dtype=None):
     if dtype is not None and t.dtype != dtype:
         raise TypeError(f"expected {dtype}, got {t.dtype}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def probe_peaks(stream=None):
+    """Attainable device rates (mf_probe_peaks): HBM copy GB/s, FP64 / FP32 vector and
+    FP32 / FP64 matrix TFLOP/s."""
+    out = (ctypes.c_double * 5)()
+    _check(load_library().mf_probe_peaks(out, _stream(stream)))
+    keys = ("hbm_copy_gbs", "fp64_vector_tflops", "fp32_vector_tflops", "fp32_mfma_tflops", "fp64_mfma_tflops")
+    return dict(zip(keys, list(out)))
 
 
 class Mesh:
@@ -478,6 +489,7 @@ class Batch:
         h = ctypes.c_void_p()
         _check(L.mf_batch_create(n, a64, a32, mm, bb, xx, _stream(stream), ctypes.byref(h)))
         self.handle, self.n = h, n
+        self.refine = A32 is not None
 
     def solve(self, rtol=1e-10, inner_rtol=0.0, maxit=100000, stream=None, raise_on_error=True):
         infos = (CGInfo * self.n)()
@@ -488,6 +500,19 @@ class Batch:
 
     def apply(self, inner=True, stream=None):
         _check(load_library().mf_batch_apply(self.handle, int(inner), _stream(stream)))
+
+    def apply_user(self, xs, ys, inner=True, stream=None):
+        """ys[i] = A[i] xs[i] for all systems in one batched launch (user numbering)."""
+        if len(xs) != self.n or len(ys) != self.n:
+            raise ValueError("one x and one y per system")
+        import torch
+        dt = torch.float32 if (inner and self.refine) else torch.float64
+        for t in list(xs) + list(ys):
+            _dev(t, dt)
+        P = ctypes.c_void_p
+        xx = (P * self.n)(*[t.data_ptr() for t in xs])
+        yy = (P * self.n)(*[t.data_ptr() for t in ys])
+        _check(load_library().mf_batch_apply_user(self.handle, int(inner), xx, yy, _stream(stream)))
 
     def autotune(self, cache_path=None, stream=None):
         _check(load_library().mf_batch_autotune(self.handle, None if cache_path is None else cache_path.encode(),
