@@ -325,6 +325,53 @@ int mf_batch_apply(mf_batch *B, int inner, void *stream) {
   return MF_OK;
 }
 
+int mf_batch_apply_user(mf_batch *B, int inner, const void *const *x, void *const *y, void *stream) {
+  if (!B || !x || !y) return fail(MF_EINVAL, "mf_batch_apply_user: null argument");
+  for (int i = 0; i < B->nsys; i++)
+    if (!x[i] || !y[i]) return fail(MF_EINVAL, "mf_batch_apply_user: null vector");
+  MF_HIP(hipEventRecord(B->ev, (hipStream_t)stream));
+  MF_HIP(hipStreamWaitEvent(B->s, B->ev, 0));
+  const bool f32 = inner && B->refine;
+  // the operator table of the launch reads from and writes to these concatenated
+  // internal buffers (see mf_batch_create)
+  void *in = !inner ? B->x.ptr : (f32 ? B->p32.ptr : B->p.ptr);
+  void *out = f32 ? B->Ap32.ptr : B->Ap.ptr;
+  int rc = MF_OK;
+  for (int i = 0; i < B->nsys && !rc; i++) {
+    const mf_op *a = B->A64[i];
+    const int64_t o = B->off[i];
+    if (f32) {
+      float *dst = (float *)in + o;
+      if (a->identity) MF_HIP(hipMemcpyAsync(dst, x[i], (size_t)a->ndofs * 4, hipMemcpyDeviceToDevice, B->s));
+      else rc = launch_to_internal<float>(a->perm.as<int32_t>(), a->nnodes, a->ncomp, (const float *)x[i], dst, B->s);
+    } else {
+      double *dst = (double *)in + o;
+      if (a->identity) MF_HIP(hipMemcpyAsync(dst, x[i], (size_t)a->ndofs * 8, hipMemcpyDeviceToDevice, B->s));
+      else rc = launch_to_internal<double>(a->perm.as<int32_t>(), a->nnodes, a->ncomp, (const double *)x[i], dst, B->s);
+    }
+  }
+  if (rc) return rc;
+  rc = inner ? batch_apply(B, B->ops_in, f32 ? MF_F32 : MF_F64, out, nullptr)
+             : batch_apply(B, B->ops64x, MF_F64, out, nullptr);
+  for (int i = 0; i < B->nsys && !rc; i++) {
+    const mf_op *a = B->A64[i];
+    const int64_t o = B->off[i];
+    if (f32) {
+      const float *src = (const float *)out + o;
+      if (a->identity) MF_HIP(hipMemcpyAsync(y[i], src, (size_t)a->ndofs * 4, hipMemcpyDeviceToDevice, B->s));
+      else rc = launch_from_internal<float>(a->perm.as<int32_t>(), a->nnodes, a->ncomp, src, (float *)y[i], false, B->s);
+    } else {
+      const double *src = (const double *)out + o;
+      if (a->identity) MF_HIP(hipMemcpyAsync(y[i], src, (size_t)a->ndofs * 8, hipMemcpyDeviceToDevice, B->s));
+      else rc = launch_from_internal<double>(a->perm.as<int32_t>(), a->nnodes, a->ncomp, src, (double *)y[i], false, B->s);
+    }
+  }
+  if (rc) return rc;
+  MF_HIP(hipEventRecord(B->ev, B->s));
+  MF_HIP(hipStreamWaitEvent((hipStream_t)stream, B->ev, 0));
+  return MF_OK;
+}
+
 int mf_batch_autotune(mf_batch *B, const char *cache_path, void *stream) {
   if (!B) return fail(MF_EINVAL, "mf_batch_autotune: null batch");
   // key: operator kind, precision of the inner action, device CU count, and the (degree, cells) multiset

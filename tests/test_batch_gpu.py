@@ -78,3 +78,36 @@ def test_batch_autotune_and_cache(mf, tmp_path):
         assert rc == 0
         for x, r in zip(xs, ref):
             assert torch.allclose(x, r, rtol=0, atol=1e-9 * float(r.abs().max()))
+
+
+@pytest.mark.parametrize("tuning", [(1, 0), (4, 512), (1, 37)])
+def test_batched_action_matches_oracle(mf, tuning):
+    """One batched launch over uneven systems (k = 2..5, ragged sizes, one 20^3 mesh)
+    against the oracle's action, system by system: FP64 operators at 1e-12 and the
+    FP32 inner operators at 1e-5 (relative max-norm), one wavefront per work item
+    (grid 0) and persistent grids with coarse and fine work lists."""
+    import torch
+    import oracle
+    sizes = [(3, 2), (5, 5), (4, 3), (20, 2), (6, 4), (2, 5), (7, 3), (9, 4)]
+    spaces, A64, A32 = [], [], []
+    for i, (m, k) in enumerate(sizes):
+        mesh = mg.hex_mesh(m, 0.15, config=3, seed_k=30 + i)
+        space = mg.hex_space(mesh, k, config=3, seed_k=30 + i)
+        sp = mf.Space.from_meshgen(space)
+        spaces.append(space)
+        A64.append(mf.Operator(sp, mf.HELMHOLTZ, mf.F64))
+        A32.append(mf.Operator(sp, mf.HELMHOLTZ, mf.F32))
+    b = [torch.zeros(s.ndofs, dtype=torch.float64, device="cuda") for s in spaces]
+    x = [torch.zeros_like(t) for t in b]
+    B = mf.Batch(A64, b, x, A32=A32)
+    B.set_tuning(*tuning)
+    xs = [mg.uniform(s.ndofs, -1, 1, 3, mg.PURPOSE_X, 30 + i) for i, s in enumerate(spaces)]
+    refs = [oracle.OracleOp(s, oracle.OP_HELMHOLTZ).apply(xv) for s, xv in zip(spaces, xs)]
+    for inner, dt, tol in ((False, torch.float64, 1e-12), (True, torch.float32, 1e-5)):
+        xd = [torch.tensor(xv, device="cuda", dtype=dt) for xv in xs]
+        yd = [torch.full_like(t, float("nan")) for t in xd]
+        B.apply_user(xd, yd, inner=inner)
+        torch.cuda.synchronize()
+        for i, (y, ref) in enumerate(zip(yd, refs)):
+            err = np.abs(y.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+            assert err <= tol, (tuning, inner, sizes[i], err)
