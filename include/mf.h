@@ -243,6 +243,31 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
                 double *x, double rtol, double inner_rtol, int maxit, mf_cg_info *info,
                 void *stream);
 
+/* For callers that cannot allocate device memory (code under stream capture
+ * elsewhere in the program, tight serving loops, harnesses that forbid hipMalloc):
+ * mf_cg_solve with the same arguments and results, except that
+ *  - the solver's vectors live in one fixed device array of the library,
+ *    MF_NOALLOC_SCRATCH_BYTES per GPU, held from the first call on that GPU until
+ *    the process ends; a solve needs 8 n bytes for each of r, p and A p, plus
+ *    8 n + 4 n + 4 n with A32 (correction, FP32 search direction and its image),
+ *    plus 16 n when the space's internal numbering differs from the user's (b and x
+ *    moved inside), each vector rounded up to 256 bytes, plus 33 KB of reduction
+ *    partials and state (n = A64's DoF count);
+ *  - it runs on `stream` itself and creates no stream, event, graph or pinned
+ *    buffer (the iteration chunks are launched directly, not replayed from a graph);
+ *    the iteration state is read back through pageable host memory;
+ *  - M must be NULL or a Jacobi preconditioner.
+ * Every call on one GPU uses that GPU's array and leaves its contents behind (each
+ * solve initialises what it reads), so calls that overlap in time on one GPU, from
+ * several threads or streams, race and must be serialised by the caller.
+ * Errors: as mf_cg_solve; MF_EINVAL when the solve needs more than
+ * MF_NOALLOC_SCRATCH_BYTES (message states both sizes); MF_EUNSUPPORTED for a
+ * learned M; MF_EDEVICE if the array's device address cannot be obtained. */
+#define MF_NOALLOC_SCRATCH_BYTES (64u << 20)
+int mf_cg_solve_noalloc(const mf_op *A64, const mf_op *A32, const mf_precond *M, const double *b,
+                        double *x, double rtol, double inner_rtol, int maxit, mf_cg_info *info,
+                        void *stream);
+
 void mf_precond_destroy(mf_precond *p);
 
 /* z = M r for FP64 device vectors of the operator's space in user numbering

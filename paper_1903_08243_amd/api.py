@@ -80,6 +80,7 @@ def load_library():
         "mf_op_get_info": (I, [P, ctypes.POINTER(_OpInfo)]),
         "mf_precond_create_jacobi": (I, [P, P, PP]),
         "mf_cg_solve": (I, [P, P, P, P, P, D, D, I, ctypes.POINTER(CGInfo), P]),
+        "mf_cg_solve_noalloc": (I, [P, P, P, P, P, D, D, I, ctypes.POINTER(CGInfo), P]),
         "mf_batch_create": (I, [I, P, P, P, P, P, P, PP]),
         "mf_batch_solve": (I, [P, D, D, I, P, P]),
         "mf_batch_apply": (I, [P, I, P]),
@@ -451,11 +452,14 @@ class LearnedPrecond(_Precond):
 
 
 def cg_solve(A64: Operator, b, x, A32: Operator | None = None, precond=None, rtol=1e-10, inner_rtol=0.0,
-             maxit=10000, stream=None, raise_on_error=True):
-    """FP64 (optionally FP32-refined) preconditioned CG; x holds the initial guess."""
+             maxit=10000, stream=None, raise_on_error=True, noalloc=False):
+    """FP64 (optionally FP32-refined) preconditioned CG; x holds the initial guess.
+    noalloc: the variant that allocates nothing (vectors in the library's fixed
+    device array, MF_NOALLOC_SCRATCH_BYTES per GPU)."""
     import torch
     info = CGInfo()
-    rc = load_library().mf_cg_solve(A64.handle, None if A32 is None else A32.handle,
+    fn = load_library().mf_cg_solve_noalloc if noalloc else load_library().mf_cg_solve
+    rc = fn(A64.handle, None if A32 is None else A32.handle,
                                     None if precond is None else precond.handle, _dev(b, torch.float64),
                                     _dev(x, torch.float64), rtol, inner_rtol, maxit, ctypes.byref(info),
                                     _stream(stream))

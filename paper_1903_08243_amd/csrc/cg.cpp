@@ -24,20 +24,46 @@ static constexpr int CHUNK = 8;
 
 struct CgWork {
   int64_t n = 0;
-  DeviceBuffer r, p, Ap, part, st, p32, Ap32, d, bi, xi, z;
+  // device vectors of one solve: owned by `own` (mf_cg_solve) or carved from a
+  // caller-provided workspace (cg_solve_in); null when the solve does not need them
+  double *r = nullptr, *p = nullptr, *Ap = nullptr, *part = nullptr, *d = nullptr, *bi = nullptr, *xi = nullptr,
+         *z = nullptr;
+  float *p32 = nullptr, *Ap32 = nullptr;
+  CgState *st = nullptr;
+  DeviceBuffer own[11];
   const mf_precond *M = nullptr;  // learned preconditioner (flexible CG), or null
   hipStream_t s = nullptr;
+  bool own_stream = false;
+  bool graphs = true;  // replay captured chunks (false: launch each chunk directly)
   hipEvent_t ev = nullptr;
-  CgState *host_st = nullptr;  // pinned
+  CgState *host_st = nullptr;  // pinned (mf_cg_solve) or host_local
+  bool pinned = false;
+  CgState host_local{};
   hipGraphExec_t exec[2] = {nullptr, nullptr};  // [0] FP64 operator chunk, [1] FP32 operator chunk
   ~CgWork() {
     for (auto &e : exec)
       if (e) (void)hipGraphExecDestroy(e);
-    if (host_st) (void)hipHostFree(host_st);
+    if (pinned && host_st) (void)hipHostFree(host_st);
     if (ev) (void)hipEventDestroy(ev);
-    if (s) (void)hipStreamDestroy(s);
+    if (own_stream && s) (void)hipStreamDestroy(s);
   }
 };
+
+// The device vectors a solve of (A64, A32, M) needs, in a fixed order: one entry
+// per vector with its size in bytes (0 when unused).
+struct CgNeed {
+  void **slot[11];
+  size_t bytes[11];
+};
+static CgNeed cg_need(CgWork &w, const mf_op *A64, const mf_op *A32, const mf_precond *M) {
+  const size_t n = (size_t)A64->ndofs;
+  const bool learned = M && M->kind == 1, perm = !A64->identity;
+  return CgNeed{{(void **)&w.r, (void **)&w.p, (void **)&w.Ap, (void **)&w.part, (void **)&w.st, (void **)&w.z,
+                 (void **)&w.p32, (void **)&w.Ap32, (void **)&w.d, (void **)&w.bi, (void **)&w.xi},
+                {n * 8, n * 8, n * 8, (size_t)4 * CG_NPART * 8, sizeof(CgState), learned ? n * 8 : 0,
+                 A32 ? n * 4 : 0, A32 ? n * 4 : 0, A32 ? n * 8 : 0, perm ? n * 8 : 0, perm ? n * 8 : 0}};
+}
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // all solver vectors live in the operators' internal numbering; the output was
 // cleared by the preceding vector kernel, so the action accumulates
@@ -49,23 +75,23 @@ static int record_chunk(const mf_op *A, const double *dinv, double *x, CgWork &w
   if (w.M) {
     // flexible CG: z = M r from the learned preconditioner, Polak-Ribiere beta
     for (int j = 0; j < CHUNK; j++) {
-      void *Ap = a32 ? w.Ap32.ptr : w.Ap.ptr;
-      int rc = a32 ? apply_any(A, w.p32.ptr, Ap, w.s) : apply_any(A, w.p.ptr, Ap, w.s);
-      if (!rc) rc = fcg_update(x, w.r.as<double>(), w.p.as<double>(), Ap, a32, w.n, w.part.as<double>(),
-                               w.st.as<CgState>(), w.s);
-      if (!rc) rc = precond_cnn_apply_internal(w.M, w.r.as<double>(), w.z.as<double>(), w.s);
-      if (!rc) rc = fcg_direction(w.r.as<double>(), w.z.as<double>(), dinv, w.p.as<double>(),
-                                  a32 ? w.p32.as<float>() : nullptr, Ap, a32, w.n, w.part.as<double>(),
-                                  w.st.as<CgState>(), w.s);
+      void *Ap = a32 ? (void *)w.Ap32 : (void *)w.Ap;
+      int rc = a32 ? apply_any(A, w.p32, Ap, w.s) : apply_any(A, w.p, Ap, w.s);
+      if (!rc) rc = fcg_update(x, w.r, w.p, Ap, a32, w.n, w.part,
+                               w.st, w.s);
+      if (!rc) rc = precond_cnn_apply_internal(w.M, w.r, w.z, w.s);
+      if (!rc) rc = fcg_direction(w.r, w.z, dinv, w.p,
+                                  a32 ? w.p32 : nullptr, Ap, a32, w.n, w.part,
+                                  w.st, w.s);
       if (rc) return rc;
     }
     return MF_OK;
   }
   for (int j = 0; j < CHUNK; j++) {
-    int rc = a32 ? apply_any(A, w.p32.ptr, w.Ap32.ptr, w.s) : apply_any(A, w.p.ptr, w.Ap.ptr, w.s);
+    int rc = a32 ? apply_any(A, w.p32, w.Ap32, w.s) : apply_any(A, w.p, w.Ap, w.s);
     if (rc) return rc;
-    rc = cg_step_after_apply(x, w.r.as<double>(), w.p.as<double>(), a32 ? w.p32.as<float>() : nullptr,
-                             a32 ? w.Ap32.ptr : w.Ap.ptr, a32, dinv, w.n, w.part.as<double>(), w.st.as<CgState>(),
+    rc = cg_step_after_apply(x, w.r, w.p, a32 ? w.p32 : nullptr,
+                             a32 ? (void *)w.Ap32 : (void *)w.Ap, a32, dinv, w.n, w.part, w.st,
                              w.s);
     if (rc) return rc;
   }
@@ -93,7 +119,7 @@ static int chunk_graph(const mf_op *A, const double *dinv, double *x, CgWork &w,
 }
 
 static int read_state(CgWork &w, CgState &out) {
-  MF_HIP(hipMemcpyAsync(w.host_st, w.st.ptr, sizeof(CgState), hipMemcpyDeviceToHost, w.s));
+  MF_HIP(hipMemcpyAsync(w.host_st, w.st, sizeof(CgState), hipMemcpyDeviceToHost, w.s));
   MF_HIP(hipStreamSynchronize(w.s));
   out = *w.host_st;
   return MF_OK;
@@ -107,25 +133,32 @@ static int pcg_core(const mf_op *A, const double *dinv, double *x, double tol2, 
   init.tol2 = tol2;
   init.maxit = maxit;
   *w.host_st = init;
-  MF_HIP(hipMemcpyAsync(w.st.ptr, w.host_st, sizeof(CgState), hipMemcpyHostToDevice, w.s));
+  MF_HIP(hipMemcpyAsync(w.st, w.host_st, sizeof(CgState), hipMemcpyHostToDevice, w.s));
   int rc;
   if (w.M) {
-    rc = precond_cnn_apply_internal(w.M, w.r.as<double>(), w.z.as<double>(), w.s);
-    if (!rc) rc = fcg_init(w.r.as<double>(), w.z.as<double>(), dinv, w.p.as<double>(),
-                           a32 ? w.p32.as<float>() : nullptr, w.n, w.part.as<double>(), w.st.as<CgState>(), w.s,
-                           a32 ? w.Ap32.ptr : w.Ap.ptr);
+    rc = precond_cnn_apply_internal(w.M, w.r, w.z, w.s);
+    if (!rc) rc = fcg_init(w.r, w.z, dinv, w.p,
+                           a32 ? w.p32 : nullptr, w.n, w.part, w.st, w.s,
+                           a32 ? (void *)w.Ap32 : (void *)w.Ap);
   } else {
-    rc = cg_init(w.r.as<double>(), dinv, w.p.as<double>(), a32 ? w.p32.as<float>() : nullptr, w.n,
-                 w.part.as<double>(), w.st.as<CgState>(), w.s, a32 ? w.Ap32.ptr : w.Ap.ptr);
+    rc = cg_init(w.r, dinv, w.p, a32 ? w.p32 : nullptr, w.n,
+                 w.part, w.st, w.s, a32 ? (void *)w.Ap32 : (void *)w.Ap);
   }
   if (rc) return rc;
   rc = read_state(w, out);
   if (rc || out.stop || maxit <= 0) return rc;
   hipGraphExec_t &exec = w.exec[a32 ? 1 : 0];
-  rc = chunk_graph(A, dinv, x, w, exec);
-  if (rc) return rc;
+  if (w.graphs) {
+    rc = chunk_graph(A, dinv, x, w, exec);
+    if (rc) return rc;
+  }
   while (true) {
-    MF_HIP(hipGraphLaunch(exec, w.s));
+    if (w.graphs) {
+      MF_HIP(hipGraphLaunch(exec, w.s));
+    } else {
+      rc = record_chunk(A, dinv, x, w);
+      if (rc) return rc;
+    }
     rc = read_state(w, out);
     if (rc) return rc;
     if (out.stop) break;
@@ -134,9 +167,9 @@ static int pcg_core(const mf_op *A, const double *dinv, double *x, double tol2, 
 }
 
 static int residual(const mf_op *A64, const double *b, const double *x, CgWork &w, double &rr) {
-  int rc = op_apply_internal(A64, x, w.Ap.ptr, w.s);
+  int rc = op_apply_internal(A64, x, w.Ap, w.s);
   if (rc) return rc;
-  rc = cg_residual(b, w.Ap.ptr, false, w.r.as<double>(), w.n, w.part.as<double>(), w.st.as<CgState>(), w.s);
+  rc = cg_residual(b, w.Ap, false, w.r, w.n, w.part, w.st, w.s);
   if (rc) return rc;
   CgState st;
   rc = read_state(w, st);
@@ -182,59 +215,46 @@ void mf_precond_destroy(mf_precond *p) {
   delete p;
 }
 
-int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const double *b, double *x, double rtol,
-                double inner_rtol, int maxit, mf_cg_info *info, void *stream) {
-  if (!A64 || !b || !x) return fail(MF_EINVAL, "mf_cg_solve: null argument");
-  if (A64->precision != MF_F64) return fail(MF_EINVAL, "mf_cg_solve: A64 must be an FP64 operator");
+}  // extern "C"
+
+namespace mf {
+
+static int cg_check(const mf_op *A64, const mf_op *A32, const mf_precond *M, const double *b, double *x, double rtol,
+                    int maxit, const char *who) {
+  const std::string f(who);
+  if (!A64 || !b || !x) return fail(MF_EINVAL, f + ": null argument");
+  if (A64->precision != MF_F64) return fail(MF_EINVAL, f + ": A64 must be an FP64 operator");
   if (A32 && (A32->ndofs != A64->ndofs || A32->precision != MF_F32))
-    return fail(MF_EINVAL, "mf_cg_solve: A32 must be an FP32 operator of the same size");
+    return fail(MF_EINVAL, f + ": A32 must be an FP32 operator of the same size");
   if (A32 && A32->numbering_id != A64->numbering_id)
-    return fail(MF_EINVAL, "mf_cg_solve: A32 and A64 must be built on the same space");
+    return fail(MF_EINVAL, f + ": A32 and A64 must be built on the same space");
   if (M && (M->n != A64->ndofs || M->numbering_id != A64->numbering_id))
-    return fail(MF_EINVAL, "mf_cg_solve: preconditioner built for another space");
-  if (!(rtol > 0.0) || maxit < 0) return fail(MF_EINVAL, "mf_cg_solve: rtol / maxit");
+    return fail(MF_EINVAL, f + ": preconditioner built for another space");
+  if (!(rtol > 0.0) || maxit < 0) return fail(MF_EINVAL, f + ": rtol / maxit");
+  return MF_OK;
+}
+
+// The solve proper, on w.s with w's vectors bound: the outer loop, the inner PCG
+// chunks and the moves between the user and the internal numbering.
+static int cg_core(CgWork &w, const mf_op *A64, const mf_op *A32, const mf_precond *M, const double *b, double *x,
+                   double rtol, double inner_rtol, int maxit, mf_cg_info *info) {
   const int64_t n = A64->ndofs;
-  hipStream_t caller = (hipStream_t)stream;
-  CgWork w;
-  w.n = n;
-  MF_HIP(hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking));
-  MF_HIP(hipEventCreateWithFlags(&w.ev, hipEventDisableTiming));
-  MF_HIP(hipHostMalloc((void **)&w.host_st, sizeof(CgState), hipHostMallocDefault));
-  // order the solve after the caller's pending work on its stream
-  MF_HIP(hipEventRecord(w.ev, caller));
-  MF_HIP(hipStreamWaitEvent(w.s, w.ev, 0));
-  int rc = MF_OK;
-  for (DeviceBuffer *bptr : {&w.r, &w.p, &w.Ap})
-    if (!rc) rc = bptr->alloc((size_t)n * 8);
-  if (!rc) rc = w.part.alloc((size_t)4 * CG_NPART * 8);
-  if (M && M->kind == 1) {
-    w.M = M;
-    if (!rc) rc = w.z.alloc((size_t)n * 8);
-  }
-  if (!rc) rc = w.st.alloc(sizeof(CgState));
-  if (A32) {
-    if (!rc) rc = w.p32.alloc((size_t)n * 4);
-    if (!rc) rc = w.Ap32.alloc((size_t)n * 4);
-    if (!rc) rc = w.d.alloc((size_t)n * 8);
-  }
-  if (rc) return rc;
   const double *dinv = M ? M->dinv.as<double>() : nullptr;
   // move b and x into the internal numbering (once per solve)
   double *x_user = x;
+  int rc = MF_OK;
   if (!A64->identity) {
-    rc = w.bi.alloc((size_t)n * 8);
-    if (!rc) rc = w.xi.alloc((size_t)n * 8);
     const int32_t *uoi = A64->perm.as<int32_t>();
-    if (!rc) rc = launch_to_internal<double>(uoi, A64->nnodes, A64->ncomp, b, w.bi.as<double>(), w.s);
-    if (!rc) rc = launch_to_internal<double>(uoi, A64->nnodes, A64->ncomp, x, w.xi.as<double>(), w.s);
+    rc = launch_to_internal<double>(uoi, A64->nnodes, A64->ncomp, b, w.bi, w.s);
+    if (!rc) rc = launch_to_internal<double>(uoi, A64->nnodes, A64->ncomp, x, w.xi, w.s);
     if (rc) return rc;
-    b = w.bi.as<double>();
-    x = w.xi.as<double>();
+    b = w.bi;
+    x = w.xi;
   }
 
   // ||b||^2 via the residual kernel with Ax = 0 is avoided: r = b - A*0 costs an apply; use r = b - Ap with Ap = 0
-  rc = launch_fill<double>(w.Ap.as<double>(), 0.0, n, w.s);
-  if (!rc) rc = cg_residual(b, w.Ap.ptr, false, w.r.as<double>(), n, w.part.as<double>(), w.st.as<CgState>(), w.s);
+  rc = launch_fill<double>(w.Ap, 0.0, n, w.s);
+  if (!rc) rc = cg_residual(b, w.Ap, false, w.r, n, w.part, w.st, w.s);
   CgState st{};
   if (!rc) rc = read_state(w, st);
   if (rc) return rc;
@@ -282,9 +302,9 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
       if (rr <= tol2 || !(rr == rr) || inf.inner_iterations >= maxit) break;
       const double irt = std::max(floor_rt, std::sqrt(tol2 / rr));
       // inner: A32 d = r from d = 0, FP64 vectors
-      rc = launch_fill<double>(w.d.as<double>(), 0.0, n, w.s);
+      rc = launch_fill<double>(w.d, 0.0, n, w.s);
       if (rc) return rc;
-      rc = pcg_core(A32, dinv, w.d.as<double>(), irt * irt * rr, maxit - inf.inner_iterations, w, st);
+      rc = pcg_core(A32, dinv, w.d, irt * irt * rr, maxit - inf.inner_iterations, w, st);
       if (rc) return rc;
       inf.inner_iterations += st.iters;
       inf.fallbacks += st.nfallback;
@@ -292,7 +312,7 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
         status = fail(MF_EBREAKDOWN, "inner CG breakdown (non-finite value or p'Ap <= 0)");
         break;
       }
-      rc = cg_axpy(x, w.d.as<double>(), n, w.s);
+      rc = cg_axpy(x, w.d, n, w.s);
       if (rc) return rc;
     }
   }
@@ -307,6 +327,71 @@ int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const d
   MF_HIP(hipStreamSynchronize(w.s));
   if (info) *info = inf;
   return status;
+}
+
+size_t cg_workspace_bytes(const mf_op *A64, const mf_op *A32, const mf_precond *M) {
+  CgWork w;
+  const CgNeed need = cg_need(w, A64, A32, M);
+  size_t tot = 0;
+  for (int i = 0; i < 11; i++) tot += align256(need.bytes[i]);
+  return tot;
+}
+
+int cg_solve_in(void *ws, size_t ws_bytes, const mf_op *A64, const mf_op *A32, const mf_precond *M,
+                const double *b, double *x, double rtol, double inner_rtol, int maxit, mf_cg_info *info,
+                hipStream_t s) {
+  int rc = cg_check(A64, A32, M, b, x, rtol, maxit, "mf_cg_solve_noalloc");
+  if (rc) return rc;
+  if (M && M->kind != 0)
+    return fail(MF_EUNSUPPORTED, "mf_cg_solve_noalloc: only the Jacobi preconditioner (or none) is supported");
+  const size_t need_bytes = cg_workspace_bytes(A64, A32, M);
+  if (need_bytes > ws_bytes)
+    return fail(MF_EINVAL, "mf_cg_solve_noalloc: the solve needs " + std::to_string(need_bytes) +
+                               " bytes of workspace, more than the " + std::to_string(ws_bytes) + " available");
+  CgWork w;
+  w.n = A64->ndofs;
+  w.s = s;
+  w.graphs = false;  // graph instantiation allocates; the chunks are launched directly
+  w.host_st = &w.host_local;
+  const CgNeed need = cg_need(w, A64, A32, M);
+  char *base = (char *)ws;
+  for (int i = 0; i < 11; i++) {
+    *need.slot[i] = need.bytes[i] ? (void *)base : nullptr;
+    base += align256(need.bytes[i]);
+  }
+  return cg_core(w, A64, A32, M, b, x, rtol, inner_rtol, maxit, info);
+}
+
+}  // namespace mf
+
+using namespace mf;
+
+extern "C" {
+
+int mf_cg_solve(const mf_op *A64, const mf_op *A32, const mf_precond *M, const double *b, double *x, double rtol,
+                double inner_rtol, int maxit, mf_cg_info *info, void *stream) {
+  int rc = cg_check(A64, A32, M, b, x, rtol, maxit, "mf_cg_solve");
+  if (rc) return rc;
+  hipStream_t caller = (hipStream_t)stream;
+  CgWork w;
+  w.n = A64->ndofs;
+  MF_HIP(hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking));
+  w.own_stream = true;
+  MF_HIP(hipEventCreateWithFlags(&w.ev, hipEventDisableTiming));
+  MF_HIP(hipHostMalloc((void **)&w.host_st, sizeof(CgState), hipHostMallocDefault));
+  w.pinned = true;
+  // order the solve after the caller's pending work on its stream
+  MF_HIP(hipEventRecord(w.ev, caller));
+  MF_HIP(hipStreamWaitEvent(w.s, w.ev, 0));
+  if (M && M->kind == 1) w.M = M;
+  const CgNeed need = cg_need(w, A64, A32, M);
+  for (int i = 0; i < 11 && !rc; i++)
+    if (need.bytes[i]) {
+      rc = w.own[i].alloc(need.bytes[i]);
+      *need.slot[i] = w.own[i].ptr;
+    }
+  if (rc) return rc;
+  return cg_core(w, A64, A32, M, b, x, rtol, inner_rtol, maxit, info);
 }
 
 }  // extern "C"

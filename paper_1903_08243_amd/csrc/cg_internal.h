@@ -58,6 +58,17 @@ int fcg_direction(const double *r, double *z, const double *dinv, double *p, flo
                   int64_t n, double *part, CgState *st, hipStream_t s);
 int precond_cnn_apply_internal(const mf_precond *P, const double *r, double *z, hipStream_t s);
 
+// Device workspace (bytes) that a solve of (A64, A32, M) needs: every vector of the
+// solve, each rounded up to 256 bytes.
+size_t cg_workspace_bytes(const mf_op *A64, const mf_op *A32, const mf_precond *M);
+// mf_cg_solve on the caller's stream with its vectors carved from ws (ws_bytes
+// long): creates no stream, event, graph or pinned buffer and allocates no device
+// memory (learned preconditioners are rejected). MF_EINVAL when the solve needs more
+// than ws_bytes.
+int cg_solve_in(void *ws, size_t ws_bytes, const mf_op *A64, const mf_op *A32, const mf_precond *M,
+                const double *b, double *x, double rtol, double inner_rtol, int maxit, mf_cg_info *info,
+                hipStream_t s);
+
 }  // namespace mf
 
 struct mf_precond {
