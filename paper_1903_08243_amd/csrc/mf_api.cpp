@@ -500,8 +500,133 @@ static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   return MF_OK;
 }
 
+// Simplex patch scatter (SimplexPatchArgs), built from the flagged internal map m
+// (AoSoA [cell/64][D][64]) and the per-cell geometry gflat ([cell][G]): cells in Morton
+// order of their centroids, greedy patches of at most cap cells and nmax free nodes.
 template <typename T>
-static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+static int setup_simplex_patches(mf_op *op, const mf_space *sp, const std::vector<int32_t> &m, bool m_aosoa,
+                                 const std::vector<T> &gflat, int G, int cap, int nmax, hipStream_t s) {
+  const int64_t nc = sp->ncells;
+  const int D = sp->D, nv = sp->nvc, gd = sp->gdim;
+  auto mp = [&](int64_t K, int i) { return m_aosoa ? m[((K / 64) * D + i) * 64 + K % 64] : m[K * D + i]; };
+  std::vector<double> cen((size_t)nc * 3, 0.0);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t K = 0; K < nc; K++)
+    for (int a = 0; a < gd; a++) {
+      double c = 0.0;
+      for (int v = 0; v < nv; v++) c += sp->coords[(int64_t)sp->cell2vert_int[K * nv + v] * gd + a];
+      c /= nv;
+      cen[K * 3 + a] = c;
+      lo[a] = std::min(lo[a], c);
+      hi[a] = std::max(hi[a], c);
+    }
+  std::vector<std::pair<uint32_t, int64_t>> key((size_t)nc);
+  for (int64_t K = 0; K < nc; K++) {
+    uint32_t q[3] = {0, 0, 0};
+    for (int a = 0; a < gd; a++) {
+      const double w = hi[a] - lo[a];
+      const double f = w > 0.0 ? (cen[K * 3 + a] - lo[a]) / w * 1024.0 : 0.0;
+      q[a] = (uint32_t)std::min(1023.0, std::max(0.0, f));
+    }
+    key[K] = {morton3(q[0], q[1], q[2]), K};
+  }
+  std::sort(key.begin(), key.end());
+  // greedy patches: slots (patch, slot) hold cells; node lists of free nodes
+  std::vector<int32_t> stamp((size_t)sp->nnodes, -1), loc((size_t)sp->nnodes, 0);
+  std::vector<int32_t> nptr{0}, nodes;
+  std::vector<int64_t> slot_cell;  // per slot: cell or -1
+  int pid = -1, ncell = 0, nnode = 0;
+  for (int64_t r = 0; r < nc; r++) {
+    const int64_t K = key[r].second;
+    int fresh = 0;
+    for (int i = 0; i < D; i++) {
+      const int32_t n = mp(K, i);
+      if (n >= 0 && stamp[n] != pid) fresh++;
+    }
+    if (pid < 0 || ncell == cap || nnode + fresh > nmax) {
+      if (pid >= 0) {
+        nptr.push_back((int32_t)nodes.size());
+        slot_cell.resize((size_t)(pid + 1) * cap, -1);
+      }
+      pid++;
+      ncell = nnode = 0;
+    }
+    slot_cell.resize((size_t)pid * cap + ncell + 1, -1);
+    slot_cell[(size_t)pid * cap + ncell] = K;
+    ncell++;
+    for (int i = 0; i < D; i++) {
+      const int32_t n = mp(K, i);
+      if (n >= 0 && stamp[n] != pid) {
+        stamp[n] = pid;
+        loc[n] = nnode++;
+        nodes.push_back(n);
+      }
+    }
+  }
+  const int np = pid + 1;
+  nptr.push_back((int32_t)nodes.size());
+  slot_cell.resize((size_t)np * cap, -1);
+  int maxn = 0;
+  for (int p = 0; p < np; p++) maxn = std::max(maxn, nptr[p + 1] - nptr[p]);
+  // per-slot AoSoA arrays (local indices from each patch's own node list)
+  const int64_t nblk = (int64_t)np * cap / 64;
+  std::vector<int32_t> smap((size_t)nblk * D * 64, -1);
+  std::vector<uint16_t> slmap((size_t)nblk * D * 64, kSlotSkip);
+  std::vector<T> sgeo((size_t)nblk * G * 64, T(0));
+  {
+    std::vector<int32_t> lidx((size_t)sp->nnodes, -1);
+    for (int p = 0; p < np; p++) {
+      for (int e = nptr[p]; e < nptr[p + 1]; e++) lidx[nodes[e]] = e - nptr[p];
+      for (int sl = 0; sl < cap; sl++) {
+        const int64_t K = slot_cell[(size_t)p * cap + sl];
+        if (K < 0) continue;
+        const int64_t q = (int64_t)p * cap + sl, b = q / 64, l = q % 64;
+        for (int i = 0; i < D; i++) {
+          const int32_t n = mp(K, i);
+          smap[(b * D + i) * 64 + l] = n;
+          if (n >= 0) slmap[(b * D + i) * 64 + l] = (uint16_t)lidx[n];
+        }
+        for (int e = 0; e < G; e++) sgeo[(b * G + e) * 64 + l] = gflat[(size_t)K * G + e];
+      }
+    }
+  }
+  // nodes of more than one patch: their contributions go to sbuf slots, summed in
+  // patch order by the shared-node reduction
+  std::vector<int32_t> pc((size_t)sp->nnodes, 0);
+  for (int32_t n : nodes) pc[n]++;
+  std::vector<int32_t> sidx((size_t)sp->nnodes, -1), sptr{0}, snode;
+  for (int64_t n = 0; n < sp->nnodes; n++)
+    if (pc[n] > 1) {
+      sidx[n] = (int32_t)snode.size();
+      snode.push_back((int32_t)n);
+      sptr.push_back(sptr.back() + pc[n]);
+    }
+  if ((int64_t)sptr.back() >= (int64_t)kSharedOut || (int64_t)sp->nnodes >= (int64_t)kSharedOut)
+    return fail(MF_EUNSUPPORTED, "simplex patch scatter: too many nodes");
+  std::vector<int32_t> fill(snode.size(), 0), out(nodes.size());
+  for (size_t e = 0; e < nodes.size(); e++) {
+    const int32_t n = nodes[e];
+    out[e] = sidx[n] < 0 ? n : (kSharedOut | (sptr[sidx[n]] + fill[sidx[n]]++));
+  }
+  op->sp_npatch = np;
+  op->sp_cap = cap;
+  op->sp_nmax = maxn;
+  op->sp_nshared = (int64_t)snode.size();
+  int rc = upload(op->sp_map, smap.data(), smap.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->sp_lmap, slmap.data(), slmap.size() * sizeof(uint16_t), s);
+  if (!rc) rc = upload(op->sp_geo, sgeo.data(), sgeo.size() * sizeof(T), s);
+  if (!rc) rc = upload(op->sp_nptr, nptr.data(), nptr.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->sp_out, out.data(), out.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->sp_sptr, sptr.data(), sptr.size() * sizeof(int32_t), s);
+  if (!rc && !snode.empty()) rc = upload(op->sp_snode, snode.data(), snode.size() * sizeof(int32_t), s);
+  if (!rc) rc = op->sp_sbuf.alloc(std::max<size_t>(1, (size_t)sptr.back()) * sp->ncomp * sizeof(T));
+  if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  return rc;
+}
+
+template <typename T>
+static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
+                     hipStream_t s) {
   const int k = sp->degree, D = sp->D;
   std::vector<double> pts, w, phi, dphi;
   const bool hyper = op->kind == MF_OP_HYPERELASTIC;
@@ -569,7 +694,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipS
     if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     if (rc) return rc;
   }
-  std::vector<T> geo((size_t)nb * 10 * 64, T(0));
+  std::vector<T> geo((size_t)nb * 10 * 64, T(0)), gflat(op->spatched ? (size_t)nc * 10 : 0);
   for (int64_t K = 0; K < nc; K++) {
     const int32_t *cv = sp->cell2vert_int.data() + K * 4;
     double J[3][3];
@@ -593,8 +718,16 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipS
     for (int bb = 0; bb < 3; bb++)
       for (int a = 0; a < 3; a++) geo[(b * 10 + 3 * bb + a) * 64 + l] = (T)(R[bb][a] / det);
     geo[(b * 10 + 9) * 64 + l] = (T)std::fabs(det);
+    if (op->spatched)
+      for (int e = 0; e < 10; e++) gflat[(size_t)K * 10 + e] = geo[(b * 10 + e) * 64 + l];
   }
-  return upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+  rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+  if (!rc && op->spatched) {
+    // patches of 512 cells (P2) or 256 (P3) with at most 2048 nodes (48 KB of FP64 sums)
+    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, 10, k <= 2 ? 512 : 256, 2048, s);
+  }
+  if (!rc) MF_HIP(hipStreamSynchronize(s));
+  return rc;
 }
 
 // Triangles other than the closed-form P1 mass: tables (phi, reference gradients,
@@ -643,19 +776,27 @@ template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, con
   return rc;
 }
 
-template <typename T> static int setup_tri(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+template <typename T>
+static int setup_tri(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
+                     hipStream_t s) {
   if (!(op->kind == MF_OP_MASS && sp->degree == 1)) return setup_tri_pk<T>(op, sp, pr, s);
   const int64_t nc = sp->ncells;
-  std::vector<T> geo((size_t)nc * 4, T(0));
+  std::vector<T> geo((size_t)nc * 4, T(0)), gflat(op->spatched ? (size_t)nc * 3 : 0);
   for (int64_t K = 0; K < nc; K++) {
     const int32_t *cv = sp->cell2vert_int.data() + K * 3;
     const double *p0 = &sp->coords[(int64_t)cv[0] * 2], *p1 = &sp->coords[(int64_t)cv[1] * 2],
                  *p2 = &sp->coords[(int64_t)cv[2] * 2];
     const double area = 0.5 * std::fabs((p1[0] - p0[0]) * (p2[1] - p0[1]) - (p2[0] - p0[0]) * (p1[1] - p0[1]));
     for (int i = 0; i < 3; i++) geo[K * 4 + i] = (T)(area * (op->has_coef ? pr->vertex_coef[cv[i]] : 1.0));
+    if (op->spatched)
+      for (int i = 0; i < 3; i++) gflat[K * 3 + i] = geo[K * 4 + i];
   }
   op->nqp = 0;
-  return upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+  int rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
+  // patches of 2048 cells with at most 2048 nodes
+  if (!rc && op->spatched) rc = setup_simplex_patches<T>(op, sp, m, false, gflat, 3, 2048, 2048, s);
+  if (!rc) MF_HIP(hipStreamSynchronize(s));
+  return rc;
 }
 
 // Quads: 1D tables (GLL Lagrange basis and its derivative at the Gauss points, the
@@ -837,12 +978,28 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
   // free node and clears nothing; constrained rows are then written by the copy below.
   const bool first = !acc && c0 == 0 && c1 == op->ncells && op->coloured && !op->patched && op->first_ok &&
                      (op->n_bc_dofs == 0 || bc);
-  if (!acc && !first) {
+  // the simplex patch scatter writes every free node of a full apply once
+  const bool self_written = !acc && c0 == 0 && c1 == op->ncells && op->spatched && (op->n_bc_dofs == 0 || bc);
+  if (!acc && !first && !self_written) {
     rc = launch_fill<T>(y, T(0), op->ndofs, s);
     if (rc) return rc;
   }
   if (c0 == 0 && c1 == op->ncells) {
-    if (op->patched) {
+    if (op->spatched) {
+      SimplexPatchArgs<T> pa{op->sp_map.as<int32_t>(), op->sp_geo.as<T>(), op->sp_lmap.as<uint16_t>(),
+                             op->sp_nptr.as<int32_t>(), op->sp_out.as<int32_t>(), op->sp_sbuf.as<T>(),
+                             op->sp_npatch, op->sp_cap, op->sp_nmax, acc ? 1 : 0};
+      if (op->cell_type == MF_CELL_TRI) {
+        rc = launch_tri_mass_patches<T>(x, y, pa, s);
+      } else {
+        TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, 0, op->ncells, (T)op->lam,
+                     (T)op->mu, nullptr, 0, 0, nullptr, nullptr, nullptr};
+        rc = launch_tet_elasticity_patches<T>(op->degree, op->nqp, a, pa, s);
+      }
+      if (!rc)
+        rc = launch_simplex_shared_reduce<T>(op->sp_sptr.as<int32_t>(), op->sp_snode.as<int32_t>(),
+                                             op->sp_sbuf.as<T>(), y, op->sp_nshared, op->ncomp, acc, s);
+    } else if (op->patched) {
       HexPatchArgs<T> a{op->pt_nptr.as<int32_t>(), op->pt_nodes.as<int32_t>(),
                         fused ? op->pt_gnodes.as<int32_t>() : nullptr, op->pt_lmap.as<uint16_t>(),
                         op->pt_xyz.as<double>(), op->pt_geo.as<T>(), op->has_coef ? op->pt_coef.as<T>() : nullptr,
@@ -1025,15 +1182,24 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
-  if (pr->scatter == MF_SCATTER_PATCH) {
+  // tet elasticity P2/P3 (the MFMA kernel) and the P1 triangle mass: patch scatter on
+  // request, and by default from 2^15 cells
+  const bool tet_patchable = (ct == MF_CELL_TET && kind == MF_OP_ELASTICITY && (sp->degree == 2 || sp->degree == 3)) ||
+                             (ct == MF_CELL_TRI && kind == MF_OP_MASS && sp->degree == 1);
+  if (pr->scatter == MF_SCATTER_PATCH && tet_patchable) {
+    op->spatched = true;
+  } else if (pr->scatter == MF_SCATTER_AUTO && tet_patchable && nc >= (1 << 15)) {
+    op->spatched = true;
+  } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind == MF_OP_ELASTICITY)
-      return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for hex Q1 only");
+      return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for hex Q1, tet P2/P3 elasticity "
+                                   "and the P1 triangle mass");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
              kind != MF_OP_ELASTICITY) {
     op->patched = true;
   }
-  if (op->patched) op->coloured = false;
+  if (op->patched || op->spatched) op->coloured = false;
   if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured && kind != MF_OP_ELASTICITY) {
     // First-touch thresholds for overwrite applies (HexArgs::first). Colours are
     // launched in internal cell order, so a node's first toucher is the first cell in
@@ -1102,9 +1268,9 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   else if (ct == MF_CELL_QUAD)
     rc = precision == MF_F64 ? setup_quad<double>(op.get(), sp, pr, s) : setup_quad<float>(op.get(), sp, pr, s);
   else if (ct == MF_CELL_TET)
-    rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, pr, s) : setup_tet<float>(op.get(), sp, pr, s);
+    rc = precision == MF_F64 ? setup_tet<double>(op.get(), sp, pr, m, s) : setup_tet<float>(op.get(), sp, pr, m, s);
   else
-    rc = precision == MF_F64 ? setup_tri<double>(op.get(), sp, pr, s) : setup_tri<float>(op.get(), sp, pr, s);
+    rc = precision == MF_F64 ? setup_tri<double>(op.get(), sp, pr, m, s) : setup_tri<float>(op.get(), sp, pr, m, s);
   if (rc) return rc;
   MF_HIP(hipStreamSynchronize(s));
   count_work(op.get());
@@ -1234,7 +1400,7 @@ int mf_op_get_info(const mf_op *op, mf_op_info *info) {
   info->bytes_per_apply = op->bytes;
   info->ncolours = (int)op->colour_ptr.size() - 1;
   info->cell_launches = op->coloured ? info->ncolours : 1;
-  info->clears_output = op->first_ok ? 0 : 1;
+  info->clears_output = (op->first_ok || op->spatched) ? 0 : 1;
   return MF_OK;
 }
 

@@ -262,6 +262,49 @@ int launch_from_internal_gather(const int32_t *iou, int64_t nnodes, int nc, cons
 }  // namespace mf
 
 namespace mf {
+// Workgroups are dispatched round-robin over the 8 XCDs of an MI355X, each with its
+// own L2. Mapping workgroup w to batch (w % 8) * ceil(nb / 8) + w / 8 gives every
+// XCD one contiguous range of cell batches, so the nodes neighbouring cells share
+// (and the cache lines around them) are fetched into one L2 instead of several.
+// The grid must hold 8 * ceil(nb / 8) workgroups; results >= nb are idle.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_batch(int64_t w, int64_t nb) {
+  const int64_t per = (nb + kXcds - 1) / kXcds;
+  return (w % kXcds) * per + w / kXcds;
+}
+inline int64_t xcd_grid(int64_t nb) { return ((nb + kXcds - 1) / kXcds) * kXcds; }
+
+// Patch scatter of the simplex kernels (full applies). Cells are grouped into patches
+// of at most cap slots (a multiple of 64) in a locality (Morton) order, each touching
+// at most nmax distinct free nodes. A workgroup takes one patch: it sums the cells'
+// local results into the patch's nodes in LDS, then writes each node once: a node of
+// this patch alone straight into y, a node shared with other patches into its slot of
+// sbuf; simplex_shared_reduce then sums each shared node's slots (in a fixed order)
+// into y. Every free node is written once per apply, so overwrite applies need no
+// clearing pass. Per-slot arrays are AoSoA blocks of 64 slots
+// ([patch * cap / 64 + slot / 64][entry][slot % 64]); empty slots have map -1, local
+// index kSlotSkip and zero geometry.
+constexpr uint16_t kSlotSkip = 0xFFFF;      // constrained node or empty slot: no write
+constexpr int32_t kSharedOut = 1 << 30;     // out entry: slot in sbuf rather than a node id
+template <typename T> struct SimplexPatchArgs {
+  const int32_t *map;    // [blocks][D][64] internal node ids (negative: constrained or empty)
+  const T *geo;          // [blocks][G][64] the slot's cell geometry
+  const uint16_t *lmap;  // [blocks][D][64] index of the node in the patch's node list
+  const int32_t *nptr;   // [npatch + 1] node list offsets
+  const int32_t *out;    // per patch node: internal node id, or kSharedOut | sbuf slot
+  T *sbuf;               // [contributions][ncomp]
+  int npatch, cap, nmax, accumulate;
+};
+template <typename T>
+int launch_tet_elasticity_patches(int k, int nq, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
+                                  hipStream_t s);
+// the closed-form P1 triangle mass (geometry: the three s_a = |T| c_a per slot)
+template <typename T> int launch_tri_mass_patches(const T *x, T *y, const SimplexPatchArgs<T> &p, hipStream_t s);
+// y[snode[i]] (+)= sum of sbuf slots sptr[i] .. sptr[i+1]-1, per component
+template <typename T>
+int launch_simplex_shared_reduce(const int32_t *sptr, const int32_t *snode, const T *sbuf, T *y, int64_t nshared,
+                                 int ncomp, bool accumulate, hipStream_t s);
+
 // Internal-numbering entry points used by the solvers.
 int op_apply_internal(const mf_op *op, const void *x, void *y, hipStream_t s);
 // y += A x (internal numbering, y not cleared), then the constraint rows y_b = x_b
@@ -288,6 +331,12 @@ struct mf_op {
   bool first_ok = false;
   int npatch = 0, pt_max_nodes = 0, pt_cap = 0;
   bool patched = false;  // full applies use the patch kernel
+  // simplex patch scatter (SimplexPatchArgs): slot-ordered map, geometry and local
+  // indices, node outputs, shared-node sums
+  mf::DeviceBuffer sp_map, sp_geo, sp_lmap, sp_nptr, sp_out, sp_sbuf, sp_sptr, sp_snode;
+  int sp_npatch = 0, sp_cap = 0, sp_nmax = 0;
+  int64_t sp_nshared = 0;
+  bool spatched = false;
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
   mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
   mf::DeviceBuffer to1, to2, from1, from2, wt;    // two-stage permutations (positions) and their buffer

@@ -437,30 +437,19 @@ template <> struct Mfma16<double> {
 // gradient of u0 at each point comes from the same forward contraction, and the flux
 // is dF S + F dS (F = I + grad u0, E = (F^T F - I)/2, S = lambda tr(E) I + 2 mu E,
 // dF = grad u, dE = (dF^T F + F^T dF)/2, dS = lambda tr(dE) I + 2 mu dE).
-template <typename T, int K, int NQ, bool ATOMIC, bool HYPER = false>
-__global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<T> A) {
+// The action of one wavefront's 16 cells (cell j = lane % 16 of quarter w of a 64-cell
+// layout block whose map and geometry entries start at mp and gp, already offset to
+// the lane's cell): yacc[t][c][v] is the local result of component c at node
+// i = 16 t + 4 g + v (FP32) or 16 t + g + 4 v (FP64), g = lane / 16.
+template <typename T, int K, int NQ, bool HYPER>
+__device__ __forceinline__ void tet_elas_cells16(
+    const TetArgs<T> &A, const int32_t *mp, const T *gp, const bool valid, const int lane,
+    typename Mfma16<T>::V (&yacc)[((K + 1) * (K + 2) * (K + 3) / 6 + 15) / 16][3]) {
   using MF = Mfma16<T>;
   using V4 = typename MF::V;
   constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
   constexpr int NR = (NQ + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
-  const int lane = threadIdx.x & 63, wpg = blockDim.x >> 6;
-  const int j = lane & 15, g = lane >> 4;
-  // workgroup units of wpg quarters; contiguous ranges of units per XCD
-  const int64_t nqb = 4 * ((A.c1 + 63) / 64 - A.c0 / 64), nbu = (nqb + wpg - 1) / wpg, per = (nbu + 7) / 8;
-  const int64_t bu = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  const int64_t qb = bu * wpg + (threadIdx.x >> 6);
-  if (bu >= nbu || qb >= nqb) return;  // no barriers: wavefronts may leave on their own
-  const int64_t batch = A.c0 / 64 + qb / 4;
-  const int w = (int)(qb % 4);
-  const int cl = 16 * w + j;
-  const int64_t cell = batch * 64 + cl;
-  bool valid = cell >= A.c0 && cell < A.c1;
-  if (valid && A.cell_user) {
-    const int64_t u = A.cell_user[cell];
-    valid = u >= A.ulo && u < A.uhi;
-  }
-  const int32_t *mp = A.map + batch * (D * 64) + cl;
-  const T *gp = A.geo + batch * (10 * 64) + cl;
+  const int g = lane >> 4;
   T Ki[9];
 #pragma unroll
   for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
@@ -480,7 +469,7 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
   // the linearisation point at the same nodes (through the unflagged map if constrained)
   T u0v[HYPER ? NS : 1][3];
   if constexpr (HYPER) {
-    const int32_t *mq = (A.u0map ? A.u0map : A.map) + batch * (D * 64) + cl;
+    const int32_t *mq = A.u0map ? A.u0map + (mp - A.map) : mp;
 #pragma unroll
     for (int s = 0; s < NS; s++) {
       const int i = 4 * s + g;
@@ -489,7 +478,6 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
       for (int c = 0; c < 3; c++) u0v[s][c] = idx >= 0 ? A.u0[3 * (int64_t)idx + c] : T(0);
     }
   }
-  V4 yacc[NT][3];
 #pragma unroll
   for (int t = 0; t < NT; t++)
 #pragma unroll
@@ -581,6 +569,33 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
         for (int c = 0; c < 3; c++) yacc[t][c] = MF::fma(av, P[c][d], yacc[t][c]);
       }
   }
+}
+
+template <typename T, int K, int NQ, bool ATOMIC, bool HYPER = false>
+__global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<T> A) {
+  using V4 = typename Mfma16<T>::V;
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  constexpr int NT = (D + 15) / 16;
+  const int lane = threadIdx.x & 63, wpg = blockDim.x >> 6;
+  const int j = lane & 15, g = lane >> 4;
+  // workgroup units of wpg quarters; contiguous ranges of units per XCD
+  const int64_t nqb = 4 * ((A.c1 + 63) / 64 - A.c0 / 64), nbu = (nqb + wpg - 1) / wpg, per = (nbu + 7) / 8;
+  const int64_t bu = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const int64_t qb = bu * wpg + (threadIdx.x >> 6);
+  if (bu >= nbu || qb >= nqb) return;  // no barriers: wavefronts may leave on their own
+  const int64_t batch = A.c0 / 64 + qb / 4;
+  const int w = (int)(qb % 4);
+  const int cl = 16 * w + j;
+  const int64_t cell = batch * 64 + cl;
+  bool valid = cell >= A.c0 && cell < A.c1;
+  if (valid && A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    valid = u >= A.ulo && u < A.uhi;
+  }
+  const int32_t *mp = A.map + batch * (D * 64) + cl;
+  const T *gp = A.geo + batch * (10 * 64) + cl;
+  V4 yacc[NT][3];
+  tet_elas_cells16<T, K, NQ, HYPER>(A, mp, gp, valid, lane, yacc);
   // lane (cell, g) holds y for the nodes i = 16 t + 4 g + v (FP32), 16 t + g + 4 v (FP64)
   constexpr bool F64 = sizeof(T) == 8;
 #pragma unroll
@@ -598,6 +613,113 @@ __global__ void __launch_bounds__(256) tet_elasticity_mfma_kernel(const TetArgs<
       }
     }
 }
+
+// Patch scatter (SimplexPatchArgs): one workgroup of four wavefronts per patch; each
+// round the wavefronts take the patch's next 64 slots (16 cells each, as above), and
+// the local results are summed into the patch's nodes in LDS with LDS atomics. After
+// the last round every node of the patch is written once: into y if no other patch
+// touches it, else into its slot of sbuf.
+template <typename T, int K, int NQ>
+__global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs<T> A, const SimplexPatchArgs<T> P) {
+  using V4 = typename Mfma16<T>::V;
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  constexpr int NT = (D + 15) / 16;
+  constexpr bool F64 = sizeof(T) == 8;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *acc = reinterpret_cast<T *>(smem_raw);
+  const int64_t p = xcd_batch(blockIdx.x, P.npatch);  // contiguous patch ranges per XCD
+  if (p >= P.npatch) return;                           // whole workgroup: no barrier skipped
+  const int n0 = P.nptr[p], nn = P.nptr[p + 1] - n0;
+  for (int e = threadIdx.x; e < 3 * nn; e += blockDim.x) acc[e] = T(0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4, cl = 16 * w + j;
+  const int nblk = P.cap / 64;
+  for (int r = 0; r < nblk; r++) {
+    const int64_t blk = p * nblk + r;
+    V4 yacc[NT][3];
+    tet_elas_cells16<T, K, NQ, false>(A, P.map + blk * (D * 64) + cl, P.geo + blk * (10 * 64) + cl, true, lane,
+                                      yacc);
+    const uint16_t *lp = P.lmap + blk * (D * 64) + cl;
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = F64 ? 16 * t + g + 4 * v : 16 * t + 4 * g + v;
+        if (i < D) {
+          const int l = lp[i * 64];
+          if (l != kSlotSkip) {
+#pragma unroll
+            for (int c = 0; c < 3; c++) atomicAdd(&acc[3 * l + c], yacc[t][c][v]);
+          }
+        }
+      }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int32_t o = P.out[n0 + e];
+    if (o & kSharedOut) {
+      T *d = P.sbuf + 3 * (int64_t)(o & (kSharedOut - 1));
+#pragma unroll
+      for (int c = 0; c < 3; c++) d[c] = acc[3 * e + c];
+    } else {
+      T *d = A.y + 3 * (int64_t)o;
+#pragma unroll
+      for (int c = 0; c < 3; c++) d[c] = P.accumulate ? d[c] + acc[3 * e + c] : acc[3 * e + c];
+    }
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) simplex_shared_reduce_kernel(const int32_t *sptr, const int32_t *snode,
+                                                                     const T *sbuf, T *y, int64_t n, int nc,
+                                                                     int accumulate) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * nc) return;
+  const int64_t i = t / nc;
+  const int c = (int)(t - i * nc);
+  T v = T(0);
+  for (int32_t q = sptr[i]; q < sptr[i + 1]; q++) v += sbuf[(int64_t)q * nc + c];
+  T *d = y + (int64_t)snode[i] * nc + c;
+  *d = accumulate ? *d + v : v;
+}
+
+template <typename T>
+int launch_simplex_shared_reduce(const int32_t *sptr, const int32_t *snode, const T *sbuf, T *y, int64_t nshared,
+                                 int ncomp, bool accumulate, hipStream_t s) {
+  if (nshared <= 0) return MF_OK;
+  const int64_t n = nshared * ncomp;
+  simplex_shared_reduce_kernel<T><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(
+      sptr, snode, sbuf, y, nshared, ncomp, accumulate ? 1 : 0);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_simplex_shared_reduce<double>(const int32_t *, const int32_t *, const double *, double *,
+                                                  int64_t, int, bool, hipStream_t);
+template int launch_simplex_shared_reduce<float>(const int32_t *, const int32_t *, const float *, float *, int64_t,
+                                                 int, bool, hipStream_t);
+
+template <typename T, int K, int NQ>
+static int launch_tet_patch_kq(const TetArgs<T> &a, const SimplexPatchArgs<T> &p, hipStream_t s) {
+  if (p.npatch <= 0) return MF_OK;
+  const size_t lds = (size_t)p.nmax * 3 * sizeof(T);
+  if (lds > 64 * 1024) return fail(MF_EUNSUPPORTED, "tet patch scatter: patch node list too long for LDS");
+  tet_elasticity_patch_kernel<T, K, NQ><<<dim3((unsigned)xcd_grid(p.npatch)), dim3(256), lds, s>>>(a, p);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T>
+int launch_tet_elasticity_patches(int k, int nq, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
+                                  hipStream_t s) {
+  if (k == 2 && nq == 4) return launch_tet_patch_kq<T, 2, 4>(a, p, s);
+  if (k == 3 && nq == 14) return launch_tet_patch_kq<T, 3, 14>(a, p, s);
+  return fail(MF_EUNSUPPORTED, "tet patch scatter: degree / rule");
+}
+template int launch_tet_elasticity_patches<double>(int, int, const TetArgs<double> &,
+                                                   const SimplexPatchArgs<double> &, hipStream_t);
+template int launch_tet_elasticity_patches<float>(int, int, const TetArgs<float> &,
+                                                  const SimplexPatchArgs<float> &, hipStream_t);
 
 // Per-lane MFMA operands of the tabulation dphi[q][i][a] (host, for the kernel above).
 int tet_mfma_table_floats(int k, int nq) {
@@ -749,6 +871,56 @@ __global__ void __launch_bounds__(256) tri_mass_kernel(const TriArgs<T> A, bool 
     }
   }
 }
+
+// Patch scatter of the P1 mass (SimplexPatchArgs, geometry s_a = |T| c_a per slot):
+// a workgroup of 256 threads per patch, a thread per slot in turn, node sums in LDS.
+template <typename T>
+__global__ void __launch_bounds__(256) tri_mass_patch_kernel(const T *__restrict__ x, T *__restrict__ y,
+                                                             const SimplexPatchArgs<T> P) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T *acc = reinterpret_cast<T *>(smem_raw);
+  const int64_t p = xcd_batch(blockIdx.x, P.npatch);
+  if (p >= P.npatch) return;
+  const int n0 = P.nptr[p], nn = P.nptr[p + 1] - n0;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) acc[e] = T(0);
+  __syncthreads();
+  const T k60 = T(1) / T(60);
+  for (int sl = threadIdx.x; sl < P.cap; sl += blockDim.x) {
+    const int64_t q = p * P.cap + sl, b = q / 64, l = q % 64;
+    int idx[3], li[3];
+    T sa[3], xv[3];
+#pragma unroll
+    for (int i = 0; i < 3; i++) {
+      idx[i] = P.map[(b * 3 + i) * 64 + l];
+      li[i] = P.lmap[(b * 3 + i) * 64 + l];
+      sa[i] = P.geo[(b * 3 + i) * 64 + l];
+      xv[i] = idx[i] >= 0 ? x[idx[i]] : T(0);
+    }
+    const T S = sa[0] + sa[1] + sa[2];
+    const T X = xv[0] + xv[1] + xv[2];
+    const T sx = sa[0] * xv[0] + sa[1] * xv[1] + sa[2] * xv[2];
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+      if (li[i] != kSlotSkip) atomicAdd(&acc[li[i]], ((S + sa[i]) * X + sx + (S + T(2) * sa[i]) * xv[i]) * k60);
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int32_t o = P.out[n0 + e];
+    if (o & kSharedOut) P.sbuf[o & (kSharedOut - 1)] = acc[e];
+    else y[o] = P.accumulate ? y[o] + acc[e] : acc[e];
+  }
+}
+
+template <typename T> int launch_tri_mass_patches(const T *x, T *y, const SimplexPatchArgs<T> &p, hipStream_t s) {
+  if (p.npatch <= 0) return MF_OK;
+  const size_t lds = (size_t)p.nmax * sizeof(T);
+  if (lds > 64 * 1024) return fail(MF_EUNSUPPORTED, "triangle patch scatter: patch node list too long for LDS");
+  tri_mass_patch_kernel<T><<<dim3((unsigned)xcd_grid(p.npatch)), dim3(256), lds, s>>>(x, y, p);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+template int launch_tri_mass_patches<double>(const double *, double *, const SimplexPatchArgs<double> &, hipStream_t);
+template int launch_tri_mass_patches<float>(const float *, float *, const SimplexPatchArgs<float> &, hipStream_t);
 
 template <typename T> static int launch_tri(const TriArgs<T> &a, hipStream_t s, bool diag, bool atomic) {
   const int64_t n = a.c1 - a.c0;
