@@ -189,18 +189,21 @@ def cpu_baseline(mg, cases, budget_s=30.0):
 
 def bench_simplex(mf, mg, reps=20):
     """P1 triangle mass with a nodal coefficient (64x64x2 triangles, and a weak-scaled
-    2048x2048x2 mesh for the bandwidth figure) and vector P2/P3 tet elasticity
-    (48^3 x 6 Kuhn tets perturbed +-0.2h, renumbered, lambda 1, mu 0.5) in FP64 and
-    FP32 (MFMA contractions; coloured scatter by default, atomic scatter for
-    comparison). Per operator: kernel time, GDoF/s, roofline fraction."""
+    2048x2048x2 mesh for the bandwidth figure; patch scatter by default there, atomic
+    for comparison) and vector P2/P3 tet elasticity (48^3 x 6 Kuhn tets perturbed
+    +-0.2h, renumbered, lambda 1, mu 0.5) in FP64 and FP32 (MFMA contractions; patch
+    scatter by default, coloured launches for comparison). Per operator: kernel time
+    (every launch of one apply), GDoF/s, roofline fraction."""
     import torch
     out = {}
-    for m, tag in ((64, "tri_p1_mass_64"), (2048, "tri_p1_mass_2048_weak_scaled")):
+    for m, tag, sc in ((64, "tri_p1_mass_64", mf.SCATTER_AUTO),
+                       (2048, "tri_p1_mass_2048_weak_scaled", mf.SCATTER_AUTO),
+                       (2048, "tri_p1_mass_2048_weak_scaled_atomic_scatter", mf.SCATTER_ATOMIC)):
         mesh = mg.tri_mesh(m)
         space = mg.tri_p1_space(mesh)
         c = mg.uniform(mesh.nverts, 0.5, 1.5, 0, mg.PURPOSE_COEF)
         sp = mf.Space.from_meshgen(space)
-        op = mf.Operator(sp, mf.MASS, mf.F64, vertex_coef=c)
+        op = mf.Operator(sp, mf.MASS, mf.F64, vertex_coef=c, scatter=sc)
         x = torch.tensor(mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X), device="cuda")
         y = torch.empty_like(x)
         t = time_kernel(op, x, y, reps)
@@ -214,8 +217,8 @@ def bench_simplex(mf, mg, reps=20):
         sp = mf.Space.from_meshgen(space)
         x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
         for prec, ptag, sc in ((mf.F64, "fp64", mf.SCATTER_AUTO), (mf.F32, "fp32", mf.SCATTER_AUTO),
-                               (mf.F64, "fp64_atomic_scatter", mf.SCATTER_ATOMIC),
-                               (mf.F32, "fp32_atomic_scatter", mf.SCATTER_ATOMIC)):
+                               (mf.F64, "fp64_coloured_scatter", mf.SCATTER_COLOURED),
+                               (mf.F32, "fp32_coloured_scatter", mf.SCATTER_COLOURED)):
             op = mf.Operator(sp, mf.ELASTICITY, prec, lam=1.0, mu=0.5, scatter=sc)
             xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
             yt = torch.empty_like(xt)
@@ -494,13 +497,23 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, levels=7, steps=800, lr=1e-3, train_
                       "Dirichlet, kappa = exp(GRF, l=0.1)", "setup_seconds": time.perf_counter() - t_setup}
     net = mf.CNN(channels, levels, mf.cnn_initial_weights(channels, levels, seed=seed))
     M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
-    # training residuals: r_j = b - A x_j of Jacobi-CG iterates x_j of other right-hand sides
+    # training residuals: r_j = b - A x_j of Jacobi-CG iterates x_j for right-hand sides
+    # b = A e with e uniform noise on the free DoFs: the first residual (x_0 = 0) is the
+    # image of an error with every frequency, the later ones of smoother errors, so the
+    # residuals span the whole spectrum the preconditioner must handle
     g = np.random.default_rng([5, 7, seed])
     snaps = sorted(set(int(round(1.3 ** i)) for i in range(0, 30) if round(1.3 ** i) <= 1500))
+    free = torch.ones(space.ndofs, dtype=torch.float64, device="cuda")
+    free[torch.tensor(bnd, device="cuda").long()] = 0.0
+
+    def rhs_noise(i):
+        e = torch.tensor(np.random.default_rng([5, 8, seed, i]).uniform(-1, 1, space.ndofs), device="cuda")
+        return A64.apply(e * free)
+
     t0 = time.perf_counter()
     R = []
     for i in range(train_rhs):
-        b = rhs(1000 + i)
+        b = rhs_noise(i)
         R.append(b.clone())
         for j in snaps:
             xj = torch.zeros_like(b)
@@ -514,7 +527,8 @@ def bench_c5(mf, mg, m=64, k=3, channels=8, levels=7, steps=800, lr=1e-3, train_
     t0 = time.perf_counter()
     losses = net.train_energy(M, A64, R, g.integers(0, R.shape[0], size=steps), lr=lr)
     out["train_seconds"] = time.perf_counter() - t0
-    out["train"] = {"loss": "energy", "steps": steps, "lr": lr, "channels": channels, "levels": levels,
+    out["train"] = {"loss": "energy", "rhs": "A e, e ~ U[-1,1] on free dofs", "steps": steps, "lr": lr,
+                    "channels": channels, "levels": levels,
                     "loss_first": float(np.mean(losses[:10])), "loss_last": float(np.mean(losses[-50:]))}
     log(f"  c5 trained {steps} steps: energy loss {out['train']['loss_first']:.4f} -> {out['train']['loss_last']:.4f}")
     del R

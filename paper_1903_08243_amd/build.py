@@ -35,9 +35,16 @@ def _gen_tables() -> None:
         f.write(out)
 
 
+# Per-file flags. hex_kernels.hip: its FP32 contractions run on the matrix cores with
+# the accumulators in ordinary VGPRs; with the compiler's default choice of AGPRs the
+# degree-6 FP32 kernels gave wrong results (degrees 1-5 were right), so the VGPR form
+# is forced for that file.
+FILE_FLAGS = {"hex_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr[-6000:]}")
@@ -61,6 +68,47 @@ def build(verbose: bool = False) -> str:
     if verbose:
         print("built", LIB)
     return LIB
+
+
+SAN_LIB = os.path.join(BUILD, "libmf_hostsan.so")
+ASAN_RT = "libclang_rt.asan-x86_64.so"
+
+
+def build_host_sanitized(verbose: bool = False) -> str:
+    """A copy of the library whose host code of the set-up paths (mf_api.cpp: meshes,
+    spaces, colouring, numbering, patches, operator set-up; cnn.cpp: network
+    validation) is built with AddressSanitizer and UndefinedBehaviorSanitizer, for CPU
+    runs of those paths (load it with the ASan runtime preloaded; see asan_runtime()).
+    The other objects and all device code are the ordinary build's."""
+    if not os.path.exists(LIB):
+        build(verbose)
+    san = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-omit-frame-pointer"]
+    objs = []
+    for name in ("mf_api.cpp", "cnn.cpp"):
+        obj = os.path.join(BUILD, name + ".hostsan.o")
+        flags = [f for f in FLAGS if f != "-O3"]
+        r = subprocess.run([HIPCC, *flags, *san, "-c", os.path.join(CSRC, name), "-o", obj], capture_output=True,
+                           text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitized build of {name} failed:\n{r.stderr[-4000:]}")
+        objs.append(obj)
+    rest = [os.path.join(BUILD, f) for f in sorted(os.listdir(BUILD))
+            if f.endswith(".o") and not f.endswith(".hostsan.o") and f not in ("mf_api.cpp.o", "cnn.cpp.o")]
+    r = subprocess.run([HIPCC, "--offload-arch=" + ARCH, "-shared", "-fPIC", *rest, *objs, "-Xarch_host",
+                        "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined", "-o", SAN_LIB],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitized link failed:\n" + r.stderr[-4000:])
+    if verbose:
+        print("built", SAN_LIB)
+    return SAN_LIB
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's ASan runtime (to preload into an uninstrumented Python)."""
+    r = subprocess.run([HIPCC, "-print-file-name=" + ASAN_RT], capture_output=True, text=True, check=True)
+    return r.stdout.strip()
 
 
 if __name__ == "__main__":

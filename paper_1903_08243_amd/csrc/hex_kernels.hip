@@ -51,21 +51,27 @@ template <> struct HexLds<7> { static constexpr int SY = 7, SZ = 52, SE = 364; }
 
 // ---------------------------------------------------------------------------------- apply
 
-// LDS (in units of T) one wavefront needs for degree n-1: three padded n^3 buffers
-// per cell (one without gradients) and 32 geometry values per cell.
-template <int N, bool GRAD, int WPB = 1> constexpr int hex_lds_size() {
-  return hex_epb<N, WPB>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32);
+// LDS (in units of T) one workgroup needs for degree n-1: three padded n^3 buffers
+// per cell (one without gradients), 32 geometry values per cell and, with more than
+// one wavefront, one buffer that mirror lanes write into (never read); in FP32 the
+// 128 table entries of the matrix-core contractions at the end.
+template <typename T, int N, bool GRAD, int WPB = 1> constexpr int hex_lds_size() {
+  return hex_epb<N, WPB>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32) + (WPB > 1 ? HexLds<N>::SE : 0) +
+         (sizeof(T) == 4 ? 128 : 0);
 }
 
 #define IX(x, y, z) ((z) * SZ + (y) * SY + (x))
 // The sum-factorised action of one cell on the calling thread's pencil (pa, pb, *):
 // on entry r holds the cell's nodal values on that z-pencil, on exit the local
 // result on the same pencil. Gc: the cell's 32 geometry and coefficient entries in
-// LDS; u0, u1, u2: its three padded n^3 LDS buffers (u0 alone without gradients).
+// LDS; u0, u1, u2: its three padded n^3 LDS buffers (u0 alone without gradients),
+// read through u* and written through w* (the same buffers, or for a mirror lane a
+// discard area, so its stores need no branch).
 // Contains workgroup barriers, so every thread of the workgroup calls it.
 template <typename T, int N, int KIND, int WPB>
-__device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0, T *u1, T *u2, const int pa,
-                                                  const int pb, const bool STORE) {
+__device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r)[N], const T *Gc, const T *u0,
+                                                  const T *u1, const T *u2, T *w0, T *w1, T *w2, const int pa,
+                                                  const int pb) {
   using TB = TabT<T, N>;
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
@@ -96,34 +102,34 @@ __device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0,
     {
       T v[N];
       // ---- z-pencil (i, j) = (pa, pb): contract z with B
-      eo_contract<T, N, MatB<N>, 1>(r, v);
+      contract<T, N, 0>(L, r, v);
   #pragma unroll
-      for (int c = 0; c < N; c++) if (STORE) u0[IX(pa, pb, c)] = v[c];
+      for (int c = 0; c < N; c++) w0[IX(pa, pb, c)] = v[c];
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): contract y with B
   #pragma unroll
       for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
-      eo_contract<T, N, MatB<N>, 1>(r, v);
+      contract<T, N, 0>(L, r, v);
   #pragma unroll
-      for (int b = 0; b < N; b++) if (STORE) u0[IX(pa, b, pb)] = v[b];
+      for (int b = 0; b < N; b++) w0[IX(pa, b, pb)] = v[b];
       __syncthreads();
       // ---- x-pencil (y = pa, z = pb): contract x with B -> u at points; x-derivative
   #pragma unroll
       for (int xx = 0; xx < N; xx++) r[xx] = u0[IX(xx, pa, pb)];
-      eo_contract<T, N, MatB<N>, 1>(r, v);
+      contract<T, N, 0>(L, r, v);
   #pragma unroll
-      for (int a = 0; a < N; a++) if (STORE) u0[IX(a, pa, pb)] = v[a];
+      for (int a = 0; a < N; a++) w0[IX(a, pa, pb)] = v[a];
       if constexpr (GRAD) {
-        eo_contract<T, N, MatD<N>, -1>(v, r);
+        contract<T, N, 1>(L, v, r);
   #pragma unroll
-        for (int a = 0; a < N; a++) if (STORE) u1[IX(a, pa, pb)] = r[a];
+        for (int a = 0; a < N; a++) w1[IX(a, pa, pb)] = r[a];
         __syncthreads();
         // ---- y-pencil (x = pa, z = pb): y-derivative of u
   #pragma unroll
         for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
-        eo_contract<T, N, MatD<N>, -1>(r, v);
+        contract<T, N, 1>(L, r, v);
   #pragma unroll
-        for (int b = 0; b < N; b++) if (STORE) u2[IX(pa, b, pb)] = v[b];
+        for (int b = 0; b < N; b++) w2[IX(pa, b, pb)] = v[b];
       }
       __syncthreads();
       // ---- pointwise on z-pencil (a, b) = (pa, pb)
@@ -131,7 +137,7 @@ __device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0,
         T uz[N], f2[N], dzv[N];
   #pragma unroll
         for (int c = 0; c < N; c++) uz[c] = u0[IX(pa, pb, c)];
-        if constexpr (GRAD) eo_contract<T, N, MatD<N>, -1>(uz, dzv);
+        if constexpr (GRAD) contract<T, N, 1>(L, uz, dzv);
   #pragma unroll
         for (int c = 0; c < N; c++) {
           const T x3 = TB::g(c);
@@ -168,30 +174,30 @@ __device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0,
             const T f0 = sc * (r0[0] * gx + r0[1] * gy + r0[2] * gz);
             const T f1 = sc * (r1[0] * gx + r1[1] * gy + r1[2] * gz);
             f2[c] = sc * (r2[0] * gx + r2[1] * gy + r2[2] * gz);
-            if (STORE) u1[IX(pa, pb, c)] = f0;
-            if (STORE) u2[IX(pa, pb, c)] = f1;
+            w1[IX(pa, pb, c)] = f0;
+            w2[IX(pa, pb, c)] = f1;
           }
           v[c] = mterm;
         }
         if constexpr (GRAD) {
           // z-transpose of the derivative: v[c] += sum_c' D[c'][c] f2[c']
-          eo_contract<T, N, MatDt<N>, -1>(f2, dzv);
+          contract<T, N, 3>(L, f2, dzv);
   #pragma unroll
           for (int c = 0; c < N; c++) v[c] += dzv[c];
         }
   #pragma unroll
-        for (int c = 0; c < N; c++) if (STORE) u0[IX(pa, pb, c)] = v[c];
+        for (int c = 0; c < N; c++) w0[IX(pa, pb, c)] = v[c];
       }
       __syncthreads();
       if constexpr (GRAD) {
         // ---- y-pencil (x = pa, z = pb): add D^T along y of f1
   #pragma unroll
         for (int yy = 0; yy < N; yy++) r[yy] = u2[IX(pa, yy, pb)];
-        eo_contract<T, N, MatDt<N>, -1>(r, v);
+        contract<T, N, 3>(L, r, v);
   #pragma unroll
         for (int b = 0; b < N; b++) {
           const T s = u0[IX(pa, b, pb)] + v[b];
-          if (STORE) u0[IX(pa, b, pb)] = s;
+          w0[IX(pa, b, pb)] = s;
         }
         __syncthreads();
       }
@@ -202,25 +208,25 @@ __device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0,
   #pragma unroll
         for (int a = 0; a < N; a++) r[a] = u1[IX(a, pa, pb)];
         T dv[N];
-        eo_contract<T, N, MatDt<N>, -1>(r, dv);
+        contract<T, N, 3>(L, r, dv);
   #pragma unroll
         for (int a = 0; a < N; a++) v[a] += dv[a];
       }
-      eo_contract<T, N, MatBt<N>, 1>(v, r);
+      contract<T, N, 2>(L, v, r);
   #pragma unroll
-      for (int i = 0; i < N; i++) if (STORE) u0[IX(i, pa, pb)] = r[i];
+      for (int i = 0; i < N; i++) w0[IX(i, pa, pb)] = r[i];
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): B^T along y
   #pragma unroll
       for (int b = 0; b < N; b++) r[b] = u0[IX(pa, b, pb)];
-      eo_contract<T, N, MatBt<N>, 1>(r, v);
+      contract<T, N, 2>(L, r, v);
   #pragma unroll
-      for (int j = 0; j < N; j++) if (STORE) u0[IX(pa, j, pb)] = v[j];
+      for (int j = 0; j < N; j++) w0[IX(pa, j, pb)] = v[j];
       __syncthreads();
       // ---- z-pencil (i, j) = (pa, pb): B^T along z, scatter-add
   #pragma unroll
       for (int c = 0; c < N; c++) r[c] = u0[IX(pa, pb, c)];
-      eo_contract<T, N, MatBt<N>, 1>(r, v);
+      contract<T, N, 2>(L, r, v);
   #pragma unroll
       for (int l = 0; l < N; l++) r[l] = v[l];
     }
@@ -228,7 +234,7 @@ __device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, T *u0,
 }
 
 // Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
-// on the calling wavefront, using `lds` (hex_lds_size<N, GRAD>() values).
+// on the calling wavefront, using `lds` (hex_lds_size<T, N, GRAD>() values).
 template <typename T, int N, int KIND, bool ATOMIC, int WPB = 1>
 __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, const int comp, T *lds) {
   using TB = TabT<T, N>;
@@ -247,8 +253,8 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   // A mirror lane duplicates the pencil of lane t - EPB n^2. In a one-wavefront
   // workgroup it runs in lockstep with that lane, so its identical LDS stores are
   // harmless; across wavefronts its in-place read-then-write could interleave with
-  // the original's, so there it stores nothing (and never scatters).
-  const bool STORE = WPB == 1 || !mirror;
+  // the original's, so there it writes into a discard buffer instead. It never
+  // scatters.
   const int tt = mirror ? t - EPB * NN : t;
   const int le = tt / NN, p = tt - le * NN;
   const int pa = p % N, pb = p / N;
@@ -271,6 +277,11 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
     for (int l = 0; l < N; l++) idx_cur[l] = ok ? A.map[off + NN * l] : -1;
 #pragma unroll
     for (int l = 0; l < N; l++) gidx[l] = A.gmap ? (ok ? A.gmap[off + NN * l] : -1) : idx_cur[l];
+  }
+  float *mtab = nullptr;  // FP32: the contraction tables (last 128 entries of lds)
+  if constexpr (sizeof(T) == 4) {
+    mtab = reinterpret_cast<float *>(lds) + hex_lds_size<T, N, GRAD, WPB>() - 128;
+    fill_mfma_tables<N>(mtab, t, 64 * WPB);
   }
   for (int i = t; i < EPB * 32; i += 64 * WPB) {
     const int e = i >> 5, j = i & 31;
@@ -304,7 +315,12 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
     for (int l = 0; l < N; l++)
       yv[l] = (!mirror && idx_cur[l] >= 0 && idx_cur[l] < first) ? A.y[(int64_t)idx_cur[l] * nc + comp] : T(0);
   }
-  hex_pencil_stages<T, N, KIND, WPB>(r, Gc, u0, u1, u2, pa, pb, STORE);
+  T *dump = sg + EPB * 32;  // the discard buffer (WPB > 1)
+  const bool discard = WPB > 1 && mirror;
+  LaneTabs<T, N> L;
+  L.bind(reinterpret_cast<const T *>(mtab));
+  hex_pencil_stages<T, N, KIND, WPB>(L, r, Gc, u0, u1, u2, discard ? dump : u0, discard ? dump : u1,
+                                     discard ? dump : u2, pa, pb);
 #pragma unroll
   for (int l = 0; l < N; l++) {
     const int idx = mirror ? -1 : idx_cur[l];
@@ -324,7 +340,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 template <typename T, int N, int KIND, bool ATOMIC>
 __global__ void __launch_bounds__(64 * hex_wpb<N>()) hex_apply_kernel(const HexArgs<T> A) {
   constexpr int WPB = hex_wpb<N>(), EPB = hex_epb<N, WPB>();
-  __shared__ T lds[hex_lds_size<N, KIND != K_MASS, WPB>()];
+  __shared__ T lds[hex_lds_size<T, N, KIND != K_MASS, WPB>()];
   const int64_t nb = (A.c1 - A.c0 + EPB - 1) / EPB;  // cell batches
   const int64_t vb = xcd_batch(blockIdx.x, nb * A.ncomp);
   // the grid has fewer than 2^31 items, so the split uses 32-bit division
@@ -351,8 +367,8 @@ __global__ void __launch_bounds__(64) hex_batch_kernel(const HexBatchOp<T> *__re
                                                        const HexBatchItem *__restrict__ items, int nitems,
                                                        const int *__restrict__ stop, int stop_stride) {
   constexpr bool GRAD = KIND != K_MASS;
-  constexpr int L2 = hex_lds_size<2, GRAD>(), L3 = hex_lds_size<3, GRAD>(), L4 = hex_lds_size<4, GRAD>(),
-                L5 = hex_lds_size<5, GRAD>(), L6 = hex_lds_size<6, GRAD>();
+  constexpr int L2 = hex_lds_size<T, 2, GRAD>(), L3 = hex_lds_size<T, 3, GRAD>(), L4 = hex_lds_size<T, 4, GRAD>(),
+                L5 = hex_lds_size<T, 5, GRAD>(), L6 = hex_lds_size<T, 6, GRAD>();
   constexpr int LA = L2 > L3 ? L2 : L3, LB = L4 > L5 ? L4 : L5, LC = LA > LB ? LA : LB;
   constexpr int LM = LC > L6 ? LC : L6;
   __shared__ T lds[LM];

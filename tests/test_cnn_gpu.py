@@ -316,3 +316,58 @@ def test_energy_training_lowers_the_loss(mf):
     losses = net.train_energy(M, A64, Rt, g.integers(0, 6, size=200), lr=2e-3)
     assert np.all(np.isfinite(losses))
     assert losses[-20:].mean() < losses[:5].mean()
+
+
+def test_energy_training_cuts_iterations(mf):
+    """What training gains: on a 33^3 lattice (Q2, 16^3 cells, variable kappa), a
+    network trained on the energy loss over residuals of Jacobi-CG runs (right-hand
+    sides A e with uniform-noise errors e) solves a mass-weighted right-hand side in
+    fewer flexible-CG iterations than the untrained network (zero weights, which is
+    exactly the Jacobi preconditioner). Wall times of both solves are printed."""
+    import time
+    import torch
+    print("cnn energy training: iterations against the untrained network", flush=True)
+    C, L = 8, 6
+    space, kappa, bnd, node_grid, G, A64, _ = _poisson_problem(mf, 16, 2, 0)  # 33^3 lattice
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    Mass = mf.Operator(mf.Space.from_meshgen(space), mf.MASS, mf.F64, dirichlet=mask)
+    J = mf.JacobiPrecond(A64)
+    free = np.ones(space.ndofs)
+    free[bnd] = 0.0
+    snaps = sorted(set(int(round(1.4 ** i)) for i in range(0, 16)))
+    R = []
+    for s in range(2):
+        e = np.random.default_rng([9, s]).uniform(-1, 1, space.ndofs) * free
+        b = A64.apply(torch.tensor(e, device="cuda"))
+        R.append(b.clone())
+        for j in snaps:
+            xj = torch.zeros_like(b)
+            mf.cg_solve(A64, b, xj, precond=J, rtol=1e-14, maxit=j, raise_on_error=False)
+            R.append(b - A64.apply(xj))
+    R = torch.stack(R)
+    f = _rhs(space, bnd, 0)
+    bt = Mass.apply(torch.tensor(f, device="cuda"))
+
+    def solve(net):
+        M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
+        x = torch.zeros_like(bt)
+        mf.cg_solve(A64, bt, x, precond=M, rtol=1e-10)  # warm-up (graph capture)
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = mf.cg_solve(A64, bt, x, precond=M, rtol=1e-10)
+        torch.cuda.synchronize()
+        assert info["rel_residual"] <= 1e-10
+        return info["inner_iterations"], time.perf_counter() - t0
+
+    it0, t0 = solve(mf.CNN(C, L, np.zeros(mf.cnn_nparams(C, L), np.float32)))
+    net = mf.CNN(C, L, mf.cnn_initial_weights(C, L, seed=0))
+    M = mf.LearnedPrecond(A64, net, (G, G, G), node_grid)
+    order = np.random.default_rng(1).integers(0, R.shape[0], size=300)
+    losses = net.train_energy(M, A64, R, order, lr=1e-3)
+    assert np.all(np.isfinite(losses)) and losses[-30:].mean() < losses[:10].mean()
+    it1, t1 = solve(net)
+    print(f"  untrained: {it0} iterations, {t0 * 1e3:.1f} ms; trained: {it1} iterations, {t1 * 1e3:.1f} ms",
+          flush=True)
+    assert it1 <= 0.8 * it0
