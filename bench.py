@@ -340,6 +340,85 @@ def bench_simplex(mf, mg, reps=20):
     return out
 
 
+# The paper's Table 2 (operator characteristics on its CPUs): arithmetic intensity
+# (FLOP/byte under perfect caching), D (loop trip count over degrees of freedom; per
+# direction on quad/hex) and Q (over quadrature points; per direction on quad/hex) for
+# P1..P6, per operator and cell. Quoted for comparison with the same quantities of the
+# operators built here.
+TABLE2 = {
+    ("mass", "tri"): [(1.2, 3, 3), (1.7, 6, 6), (3.0, 10, 12), (5.6, 15, 25), (7.5, 21, 36), (9.7, 28, 49)],
+    ("mass", "quad"): [(4.7, 2, 3), (3.9, 3, 4), (3.9, 4, 5), (3.9, 5, 6), (3.9, 6, 7), (4.1, 7, 8)],
+    ("mass", "tet"): [(2.7, 4, 4), (5.9, 10, 14), (8.7, 20, 24), (39.2, 35, 125), (55.9, 56, 216), (81.2, 84, 343)],
+    ("mass", "hex"): [(16.9, 2, 3), (10.8, 3, 4), (8.5, 4, 5), (7.4, 5, 6), (7.0, 6, 7), (6.9, 7, 8)],
+    ("helmholtz", "tri"): [(1.8, 3, 3), (5.7, 6, 6), (9.6, 10, 12), (17.8, 15, 25), (23.3, 21, 36), (29.9, 28, 49)],
+    ("helmholtz", "quad"): [(10.7, 2, 3), (10.6, 3, 4), (10.5, 4, 5), (10.5, 5, 6), (10.4, 6, 7), (10.9, 7, 8)],
+    ("helmholtz", "tet"): [(3.9, 4, 4), (27.3, 10, 14), (37.5, 20, 24), (164.1, 35, 125), (230.1, 56, 216),
+                           (331.4, 84, 343)],
+    ("helmholtz", "hex"): [(45.5, 2, 3), (34.9, 3, 4), (27.9, 4, 5), (24.5, 5, 6), (23.1, 6, 7), (22.7, 7, 8)],
+    ("laplacian", "tri"): [(0.5, 3, 1), (2.7, 6, 3), (4.0, 10, 6), (6.9, 15, 12), (12.6, 21, 25), (16.8, 28, 36)],
+    ("laplacian", "quad"): [(7.9, 2, 3), (8.7, 3, 4), (8.4, 4, 5), (8.3, 5, 6), (8.2, 6, 7), (8.6, 7, 8)],
+    ("laplacian", "tet"): [(1.9, 4, 1), (10.4, 10, 4), (24.0, 20, 14), (31.5, 35, 24), (124.3, 56, 125),
+                           (189.3, 84, 216)],
+    ("laplacian", "hex"): [(37.8, 2, 3), (27.1, 3, 4), (21.6, 4, 5), (19.2, 5, 6), (18.4, 6, 7), (18.3, 7, 8)],
+    ("elasticity", "tri"): [(0.5, 3, 1), (3.0, 6, 3), (4.4, 10, 6), (7.3, 15, 12), (13.2, 21, 25), (17.4, 28, 36)],
+    ("elasticity", "quad"): [(10.2, 2, 3), (10.2, 3, 4), (9.5, 4, 5), (9.2, 5, 6), (9.0, 6, 7), (9.3, 7, 8)],
+    ("elasticity", "tet"): [(1.9, 4, 1), (11.6, 10, 4), (25.6, 20, 14), (32.7, 35, 24), (127.5, 56, 125),
+                            (192.6, 84, 216)],
+    ("elasticity", "hex"): [(48.0, 2, 3), (31.8, 3, 4), (24.4, 4, 5), (21.3, 5, 6), (20.1, 6, 7), (19.8, 7, 8)],
+    ("hyperelasticity", "tet"): [(1.7, 4, 1), (63.2, 10, 14), (313.8, 20, 125), (600.0, 35, 343),
+                                 (915.2, 56, 729), (1428.3, 84, 1331)],
+}
+
+
+def table2(mf, mg):
+    """D, Q and arithmetic intensity of every operator built here, beside the paper's
+    Table 2 row for the same operator, cell and degree. Ours: D = nodes per cell (per
+    direction on quad/hex), Q = quadrature points (per direction on quad/hex), AI =
+    the algorithmic flops / algorithmic HBM bytes of one FP64 action on a small mesh
+    (counted as in the roofline: x read and y written once, map, geometry); the paper
+    counts per element with its own caching model, so the AIs are not the same measure.
+    Hex and quad are built with k+1 and, where the kernels allow it, the paper's k+2
+    points per direction. Nothing is timed."""
+    meshes = {"tri": mg.tri_mesh(16, 0.2, config=0), "quad": mg.quad_mesh(16, 0.25, config=0),
+              "tet": mg.tet_mesh(6, 0.2, config=2), "hex": mg.hex_mesh(8, 0.15, config=1)}
+    kinds = {"mass": mf.MASS, "helmholtz": mf.HELMHOLTZ, "laplacian": mf.LAPLACIAN, "elasticity": mf.ELASTICITY,
+             "hyperelasticity": mf.HYPERELASTIC}
+    dim = {"tri": 2, "quad": 2, "tet": 3, "hex": 3}
+    rows = []
+    for (opname, cell), ref in TABLE2.items():
+        for k in range(1, 7):
+            ncomp = dim[cell] if opname in ("laplacian", "elasticity", "hyperelasticity") else 1
+            mesh = meshes[cell]
+            row = {"op": opname, "cell": cell, "k": k, "paper": {"AI": ref[k - 1][0], "D": ref[k - 1][1],
+                                                              "Q": ref[k - 1][2]}}
+            for q_extra in ((0, 1) if cell in ("quad", "hex") else (0,)):
+                tag = "ours" if q_extra == 0 else "ours_q_k+2"
+                try:
+                    if cell == "tri":
+                        space = mg.tri_space(mesh, k, ncomp=ncomp) if k > 1 or ncomp > 1 else mg.tri_p1_space(mesh)
+                    elif cell == "quad":
+                        space = mg.quad_space(mesh, k, ncomp=ncomp)
+                    elif cell == "tet":
+                        space = mg.tet_space(mesh, k, ncomp=ncomp, config=2)
+                    else:
+                        space = mg.hex_space(mesh, k, ncomp=ncomp, config=1)
+                    kw = {}
+                    if opname == "hyperelasticity":
+                        kw["u0"] = 0.3 * mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_COEF, k)
+                    op = mf.Operator(mf.Space.from_meshgen(space), kinds[opname], mf.F64,
+                                     nq1d=(k + 2 if q_extra else 0), **kw)
+                    inf = op.info
+                    tensor = cell in ("quad", "hex")
+                    row[tag] = {"AI": inf["flops_per_apply"] / inf["bytes_per_apply"],
+                                "D": k + 1 if tensor else inf["dofs_per_cell"],
+                                "Q": inf["nq1d"] if tensor else inf["nqp"]}
+                    del op
+                except Exception as ex:  # not built for this combination
+                    row[tag] = {"not_built": str(ex)[:80]}
+            rows.append(row)
+    return rows
+
+
 def bench_weak(mf, mg, reps=20):
     """The bandwidth-bound low-degree hex actions at a weak-scaled size (128^3 cells
     instead of 32^3, same perturbation and random renumbering): FP64 Helmholtz and
@@ -611,6 +690,8 @@ def main():
     ap.add_argument("--c5-m", type=int, default=64, help="cells per direction of that problem")
     ap.add_argument("--simplex-only", action="store_true", help="only the triangle mass and tet elasticity actions")
     ap.add_argument("--c4-only", action="store_true", help="only the batched 64-system solves")
+    ap.add_argument("--table2", action="store_true",
+                    help="only the D / Q / arithmetic-intensity table beside the paper's Table 2")
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only run the dominant action kernel 10 times and a 256 MiB reference copy "
                          "(for hardware-counter runs)")
@@ -643,6 +724,10 @@ def main():
         return
     if args.simplex_only:
         print(json.dumps(bench_simplex(mf, mg)))
+        return
+    if args.table2:
+        for row in table2(mf, mg):
+            log(json.dumps(row))
         return
     degrees = [1, 2, 3] if args.quick else [1, 2, 3, 4, 5, 6]
     kinds = [("helmholtz", mf.HELMHOLTZ, 1), ("laplacian3", mf.LAPLACIAN, 3), ("laplacian1", mf.LAPLACIAN, 1)]
@@ -711,19 +796,26 @@ def main():
     t_dom = per[dom_i]["fp64"]["us"] * 1e-6
     nl = op.info["cell_launches"]  # equal-size colour launches share the action's work evenly
     r = roof(op, t_dom, 0)
+    if op.info["scatter"] == mf.SCATTER_PATCH:
+        # one patch launch per apply plus the (small) sum over the nodes patches share;
+        # the roofline counts the apply's work over both launches' time
+        kname = (f"hex_patch_kernel<double,{dom['k'] + 1},{dom['kind']}> + simplex_shared_reduce_kernel<double> "
+                 f"({dom['name']})")
+    else:
+        kname = f"hex_apply_kernel<double,{dom['k'] + 1},{dom['kind']}> ({dom['name']})"
     traffic = measured_traffic() if (dom["k"], dom["kind"], dom["ncomp"]) == (6, mf.LAPLACIAN, 3) else None
     if r["bound"] == "alu":
         roofline = {"bound": "alu", "achieved": r["flops"] / t_dom / 1e12, "peak": PEAK_FP64 / 1e12,
                     "unit": "TFLOP/s", "frac": r["flops"] / t_dom / PEAK_FP64, "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                    "kernel": f"hex_apply_kernel<double,{dom['k'] + 1},{dom['kind']}> ({dom['name']})",
+                    "kernel": kname,
                     "flops_per_launch": r["flops"] / nl, "bytes_per_launch": r["bytes"] / nl,
                     "launch_us": t_dom * 1e6 / nl, "launches_per_apply": nl}
     else:
         roofline = {"bound": "hbm", "achieved": r["bytes"] / t_dom / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                     "frac": r["bytes"] / t_dom / PEAK_HBM, "traffic": traffic,
                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                    "kernel": f"hex_apply_kernel<double,{dom['k'] + 1},{dom['kind']}> ({dom['name']})",
+                    "kernel": kname,
                     "flops_per_launch": r["flops"] / nl, "bytes_per_launch": r["bytes"] / nl,
                     "launch_us": t_dom * 1e6 / nl, "launches_per_apply": nl}
 
@@ -737,6 +829,10 @@ def main():
             extra["hex_weak_scaled"] = bench_weak(mf, mg)
         except Exception as ex:
             extra["hex_weak_scaled"] = {"error": repr(ex)}
+    try:
+        extra["table2"] = table2(mf, mg)
+    except Exception as ex:  # reported, never silently replaced
+        extra["table2"] = {"error": repr(ex)}
     try:
         extra["cg"] = bench_cg(mf, mg)
         log(f"  cg: {json.dumps(extra['cg'])}")

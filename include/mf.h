@@ -203,8 +203,13 @@ typedef struct {
   int clears_output;      /* 1: mf_op_apply / mf_op_apply_internal clear y in a pass of their
                              own before the cell launches; 0: the launches write every entry
                              themselves (coloured hex k >= 2: each node's first contribution
-                             is stored). Overwriting range applies of an operator with
-                             constrained nodes always clear. */
+                             is stored; patch scatters: each node is written once).
+                             Overwriting range applies of an operator with constrained nodes
+                             always clear. */
+  int scatter;            /* the scatter full actions use: MF_SCATTER_ATOMIC, _COLOURED or
+                             _PATCH (patch: one patch launch, plus one launch summing the
+                             nodes shared between patches, except for the degree-1 hex
+                             patches, which use device atomics there) */
 } mf_op_info;
 
 int mf_op_get_info(const mf_op *op, mf_op_info *info);

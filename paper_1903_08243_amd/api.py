@@ -39,7 +39,8 @@ class _OpInfo(ctypes.Structure):
                 ("degree", ctypes.c_int), ("ncomp", ctypes.c_int), ("nq1d", ctypes.c_int),
                 ("nqp", ctypes.c_int), ("dofs_per_cell", ctypes.c_int),
                 ("flops_per_apply", ctypes.c_double), ("bytes_per_apply", ctypes.c_double),
-                ("cell_launches", ctypes.c_int), ("ncolours", ctypes.c_int), ("clears_output", ctypes.c_int)]
+                ("cell_launches", ctypes.c_int), ("ncolours", ctypes.c_int), ("clears_output", ctypes.c_int),
+                ("scatter", ctypes.c_int)]
 
 
 class _OpParams(ctypes.Structure):

@@ -35,11 +35,8 @@ def _gen_tables() -> None:
         f.write(out)
 
 
-# Per-file flags. hex_kernels.hip: its FP32 contractions run on the matrix cores with
-# the accumulators in ordinary VGPRs; with the compiler's default choice of AGPRs the
-# degree-6 FP32 kernels gave wrong results (degrees 1-5 were right), so the VGPR form
-# is forced for that file.
-FILE_FLAGS = {"hex_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-file compiler flags (none at present).
+FILE_FLAGS: dict = {}
 
 
 def _compile(src: str) -> str:

@@ -53,8 +53,7 @@ template <> struct HexLds<7> { static constexpr int SY = 7, SZ = 52, SE = 364; }
 
 // LDS (in units of T) one workgroup needs for degree n-1: three padded n^3 buffers
 // per cell (one without gradients), 32 geometry values per cell and, with more than
-// one wavefront, one buffer that mirror lanes write into (never read); in FP32 the
-// 128 table entries of the matrix-core contractions at the end.
+// one wavefront, one buffer that mirror lanes write into (never read).
 template <typename T, int N, bool GRAD, int WPB = 1> constexpr int hex_lds_size() {
   return hex_epb<N, WPB>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32) + (WPB > 1 ? HexLds<N>::SE : 0) +
          (sizeof(T) == 4 ? 128 : 0);
@@ -69,9 +68,8 @@ template <typename T, int N, bool GRAD, int WPB = 1> constexpr int hex_lds_size(
 // discard area, so its stores need no branch).
 // Contains workgroup barriers, so every thread of the workgroup calls it.
 template <typename T, int N, int KIND, int WPB>
-__device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r)[N], const T *Gc, const T *u0,
-                                                  const T *u1, const T *u2, T *w0, T *w1, T *w2, const int pa,
-                                                  const int pb) {
+__device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, const T *u0, const T *u1, const T *u2,
+                                                  T *w0, T *w1, T *w2, const int pa, const int pb) {
   using TB = TabT<T, N>;
   constexpr bool GRAD = KIND != K_MASS;
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
@@ -102,32 +100,32 @@ __device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r
     {
       T v[N];
       // ---- z-pencil (i, j) = (pa, pb): contract z with B
-      contract<T, N, 0>(L, r, v);
+      eo_contract<T, N, MatB<N>, 1>(r, v);
   #pragma unroll
       for (int c = 0; c < N; c++) w0[IX(pa, pb, c)] = v[c];
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): contract y with B
   #pragma unroll
       for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
-      contract<T, N, 0>(L, r, v);
+      eo_contract<T, N, MatB<N>, 1>(r, v);
   #pragma unroll
       for (int b = 0; b < N; b++) w0[IX(pa, b, pb)] = v[b];
       __syncthreads();
       // ---- x-pencil (y = pa, z = pb): contract x with B -> u at points; x-derivative
   #pragma unroll
       for (int xx = 0; xx < N; xx++) r[xx] = u0[IX(xx, pa, pb)];
-      contract<T, N, 0>(L, r, v);
+      eo_contract<T, N, MatB<N>, 1>(r, v);
   #pragma unroll
       for (int a = 0; a < N; a++) w0[IX(a, pa, pb)] = v[a];
       if constexpr (GRAD) {
-        contract<T, N, 1>(L, v, r);
+        eo_contract<T, N, MatD<N>, -1>(v, r);
   #pragma unroll
         for (int a = 0; a < N; a++) w1[IX(a, pa, pb)] = r[a];
         __syncthreads();
         // ---- y-pencil (x = pa, z = pb): y-derivative of u
   #pragma unroll
         for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
-        contract<T, N, 1>(L, r, v);
+        eo_contract<T, N, MatD<N>, -1>(r, v);
   #pragma unroll
         for (int b = 0; b < N; b++) w2[IX(pa, b, pb)] = v[b];
       }
@@ -137,7 +135,7 @@ __device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r
         T uz[N], f2[N], dzv[N];
   #pragma unroll
         for (int c = 0; c < N; c++) uz[c] = u0[IX(pa, pb, c)];
-        if constexpr (GRAD) contract<T, N, 1>(L, uz, dzv);
+        if constexpr (GRAD) eo_contract<T, N, MatD<N>, -1>(uz, dzv);
   #pragma unroll
         for (int c = 0; c < N; c++) {
           const T x3 = TB::g(c);
@@ -181,7 +179,7 @@ __device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r
         }
         if constexpr (GRAD) {
           // z-transpose of the derivative: v[c] += sum_c' D[c'][c] f2[c']
-          contract<T, N, 3>(L, f2, dzv);
+          eo_contract<T, N, MatDt<N>, -1>(f2, dzv);
   #pragma unroll
           for (int c = 0; c < N; c++) v[c] += dzv[c];
         }
@@ -193,7 +191,7 @@ __device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r
         // ---- y-pencil (x = pa, z = pb): add D^T along y of f1
   #pragma unroll
         for (int yy = 0; yy < N; yy++) r[yy] = u2[IX(pa, yy, pb)];
-        contract<T, N, 3>(L, r, v);
+        eo_contract<T, N, MatDt<N>, -1>(r, v);
   #pragma unroll
         for (int b = 0; b < N; b++) {
           const T s = u0[IX(pa, b, pb)] + v[b];
@@ -208,25 +206,25 @@ __device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r
   #pragma unroll
         for (int a = 0; a < N; a++) r[a] = u1[IX(a, pa, pb)];
         T dv[N];
-        contract<T, N, 3>(L, r, dv);
+        eo_contract<T, N, MatDt<N>, -1>(r, dv);
   #pragma unroll
         for (int a = 0; a < N; a++) v[a] += dv[a];
       }
-      contract<T, N, 2>(L, v, r);
+      eo_contract<T, N, MatBt<N>, 1>(v, r);
   #pragma unroll
       for (int i = 0; i < N; i++) w0[IX(i, pa, pb)] = r[i];
       __syncthreads();
       // ---- y-pencil (x = pa, z = pb): B^T along y
   #pragma unroll
       for (int b = 0; b < N; b++) r[b] = u0[IX(pa, b, pb)];
-      contract<T, N, 2>(L, r, v);
+      eo_contract<T, N, MatBt<N>, 1>(r, v);
   #pragma unroll
       for (int j = 0; j < N; j++) w0[IX(pa, j, pb)] = v[j];
       __syncthreads();
       // ---- z-pencil (i, j) = (pa, pb): B^T along z, scatter-add
   #pragma unroll
       for (int c = 0; c < N; c++) r[c] = u0[IX(pa, pb, c)];
-      contract<T, N, 2>(L, r, v);
+      eo_contract<T, N, MatBt<N>, 1>(r, v);
   #pragma unroll
       for (int l = 0; l < N; l++) r[l] = v[l];
     }
@@ -235,7 +233,10 @@ __device__ __forceinline__ void hex_pencil_stages(const LaneTabs<T, N> &L, T (&r
 
 // Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
 // on the calling wavefront, using `lds` (hex_lds_size<T, N, GRAD>() values).
-template <typename T, int N, int KIND, bool ATOMIC, int WPB = 1>
+// PATCH: b is a patch of EPB cell slots (cell arrays in slot order); the results are
+// summed into the patch's nodes in LDS and each node written once (HexArgs patch
+// fields), instead of the atomic or coloured scatter into y.
+template <typename T, int N, int KIND, bool ATOMIC, int WPB = 1, bool PATCH = false>
 __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, const int comp, T *lds) {
   using TB = TabT<T, N>;
   constexpr int NN = N * N, N3 = NN * N, EPB = hex_epb<N, WPB>();
@@ -243,10 +244,11 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
   constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ, SE = HexLds<N>::SE;
-  T *s0 = lds;
-  T *s1 = lds + (GRAD ? EPB * SE : 0);
-  T *s2 = lds + (GRAD ? 2 * EPB * SE : 0);
-  T *sg = lds + (GRAD ? 3 : 1) * EPB * SE;
+  T *const base = lds;
+  T *s0 = base;
+  T *s1 = base + (GRAD ? EPB * SE : 0);
+  T *s2 = base + (GRAD ? 2 * EPB * SE : 0);
+  T *sg = base + (GRAD ? 3 : 1) * EPB * SE;
 
   const int t = threadIdx.x;
   const bool mirror = t >= EPB * NN;
@@ -271,17 +273,12 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
       const int64_t u = A.cell_user[c];
       ok = u >= A.ulo && u < A.uhi;
     }
-    if (!ATOMIC && ok && A.first) first = A.first[c];
+    if (!ATOMIC && !PATCH && ok && A.first) first = A.first[c];
     const int64_t off = (ok ? c : A.c0) * N3 + pa + N * pb;
 #pragma unroll
     for (int l = 0; l < N; l++) idx_cur[l] = ok ? A.map[off + NN * l] : -1;
 #pragma unroll
     for (int l = 0; l < N; l++) gidx[l] = A.gmap ? (ok ? A.gmap[off + NN * l] : -1) : idx_cur[l];
-  }
-  float *mtab = nullptr;  // FP32: the contraction tables (last 128 entries of lds)
-  if constexpr (sizeof(T) == 4) {
-    mtab = reinterpret_cast<float *>(lds) + hex_lds_size<T, N, GRAD, WPB>() - 128;
-    fill_mfma_tables<N>(mtab, t, 64 * WPB);
   }
   for (int i = t; i < EPB * 32; i += 64 * WPB) {
     const int e = i >> 5, j = i & 31;
@@ -308,7 +305,7 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   T yv[N], r[N];
 #pragma unroll
   for (int l = 0; l < N; l++) r[l] = gidx[l] >= 0 ? A.x[(int64_t)gidx[l] * nc + comp] : T(0);
-  if constexpr (!ATOMIC) {
+  if constexpr (!ATOMIC && !PATCH) {
     // no other cell of this launch touches these nodes: read y now, write it at the end
     // (nodes this cell touches first are stored without reading)
 #pragma unroll
@@ -317,10 +314,35 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   }
   T *dump = sg + EPB * 32;  // the discard buffer (WPB > 1)
   const bool discard = WPB > 1 && mirror;
-  LaneTabs<T, N> L;
-  L.bind(reinterpret_cast<const T *>(mtab));
-  hex_pencil_stages<T, N, KIND, WPB>(L, r, Gc, u0, u1, u2, discard ? dump : u0, discard ? dump : u1,
+  hex_pencil_stages<T, N, KIND, WPB>(r, Gc, u0, u1, u2, discard ? dump : u0, discard ? dump : u1,
                                      discard ? dump : u2, pa, pb);
+  if constexpr (PATCH) {
+    __syncthreads();  // every lane has finished reading the stage buffers, reused below
+    const int n0 = A.pnptr[b], nn = A.pnptr[b + 1] - n0;
+    T *acc = base;  // nn <= EPB n^3 <= the stage buffers' size
+    for (int e = t; e < nn; e += 64 * WPB) acc[e] = T(0);
+    __syncthreads();
+    if (!mirror) {
+      const uint16_t *lp = A.plmap + (b * EPB + le) * N3 + pa + N * pb;
+#pragma unroll
+      for (int l = 0; l < N; l++) {
+        const int li = lp[NN * l];
+        if (li != kSlotSkip) atomicAdd(&acc[li], r[l]);
+      }
+    }
+    __syncthreads();
+    for (int e = t; e < nn; e += 64 * WPB) {
+      const int32_t o = A.pout[n0 + e];
+      if (o & kSharedOut) {
+        A.psbuf[(int64_t)(o & (kSharedOut - 1)) * nc + comp] = acc[e];
+      } else {
+        T *d = A.y + (int64_t)o * nc + comp;
+        *d = A.accumulate ? *d + acc[e] : acc[e];
+      }
+    }
+    __syncthreads();
+    return;
+  }
 #pragma unroll
   for (int l = 0; l < N; l++) {
     const int idx = mirror ? -1 : idx_cur[l];
@@ -340,11 +362,61 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 template <typename T, int N, int KIND, bool ATOMIC>
 __global__ void __launch_bounds__(64 * hex_wpb<N>()) hex_apply_kernel(const HexArgs<T> A) {
   constexpr int WPB = hex_wpb<N>(), EPB = hex_epb<N, WPB>();
-  __shared__ T lds[hex_lds_size<T, N, KIND != K_MASS, WPB>()];
+  __shared__ __align__(16) T lds[hex_lds_size<T, N, KIND != K_MASS, WPB>()];
   const int64_t nb = (A.c1 - A.c0 + EPB - 1) / EPB;  // cell batches
   const int64_t vb = xcd_batch(blockIdx.x, nb * A.ncomp);
   // the grid has fewer than 2^31 items, so the split uses 32-bit division
   if (vb < nb * A.ncomp) hex_cells<T, N, KIND, ATOMIC, WPB>(A, (int)vb / A.ncomp, (int)vb % A.ncomp, lds);
+}
+
+// Patch scatter: one workgroup per (patch of EPB cells, component).
+template <typename T, int N, int KIND>
+__global__ void __launch_bounds__(64 * hex_wpb<N>()) hex_patch_kernel(const HexArgs<T> A, const int npatch) {
+  constexpr int WPB = hex_wpb<N>();
+  __shared__ __align__(16) T lds[hex_lds_size<T, N, KIND != K_MASS, WPB>()];
+  const int64_t vb = xcd_batch(blockIdx.x, (int64_t)npatch * A.ncomp);
+  if (vb < (int64_t)npatch * A.ncomp)
+    hex_cells<T, N, KIND, false, WPB, true>(A, (int)vb / A.ncomp, (int)vb % A.ncomp, lds);
+}
+
+template <typename T, int N>
+static int launch_patch_n(int kind, const HexArgs<T> &a, int npatch, hipStream_t s) {
+  constexpr int WPB = hex_wpb<N>();
+  if (npatch <= 0) return MF_OK;
+  dim3 grid((unsigned)xcd_grid((int64_t)npatch * a.ncomp)), block(64 * WPB);
+  switch (kind) {
+    case K_MASS: hex_patch_kernel<T, N, K_MASS><<<grid, block, 0, s>>>(a, npatch); break;
+    case K_HELM: hex_patch_kernel<T, N, K_HELM><<<grid, block, 0, s>>>(a, npatch); break;
+    case K_LAP: hex_patch_kernel<T, N, K_LAP><<<grid, block, 0, s>>>(a, npatch); break;
+    case K_POIS: hex_patch_kernel<T, N, K_POIS><<<grid, block, 0, s>>>(a, npatch); break;
+    default: return fail(MF_EUNSUPPORTED, "hex patch kernel: operator kind");
+  }
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T>
+int launch_hex_cell_patches(int N, int kind, const HexArgs<T> &a, int npatch, hipStream_t s) {
+  switch (N) {
+    case 3: return launch_patch_n<T, 3>(kind, a, npatch, s);
+    case 4: return launch_patch_n<T, 4>(kind, a, npatch, s);
+    case 5: return launch_patch_n<T, 5>(kind, a, npatch, s);
+    case 6: return launch_patch_n<T, 6>(kind, a, npatch, s);
+    case 7: return launch_patch_n<T, 7>(kind, a, npatch, s);
+  }
+  return fail(MF_EUNSUPPORTED, "hex patch kernel: degree");
+}
+template int launch_hex_cell_patches<double>(int, int, const HexArgs<double> &, int, hipStream_t);
+template int launch_hex_cell_patches<float>(int, int, const HexArgs<float> &, int, hipStream_t);
+int hex_cells_per_patch(int N) {
+  switch (N) {
+    case 3: return hex_epb<3, hex_wpb<3>()>();
+    case 4: return hex_epb<4, hex_wpb<4>()>();
+    case 5: return hex_epb<5, hex_wpb<5>()>();
+    case 6: return hex_epb<6, hex_wpb<6>()>();
+    case 7: return hex_epb<7, hex_wpb<7>()>();
+  }
+  return 0;
 }
 
 // ---------------------------------------------------------------------------------- batched apply
@@ -371,7 +443,7 @@ __global__ void __launch_bounds__(64) hex_batch_kernel(const HexBatchOp<T> *__re
                 L5 = hex_lds_size<T, 5, GRAD>(), L6 = hex_lds_size<T, 6, GRAD>();
   constexpr int LA = L2 > L3 ? L2 : L3, LB = L4 > L5 ? L4 : L5, LC = LA > LB ? LA : LB;
   constexpr int LM = LC > L6 ? LC : L6;
-  __shared__ T lds[LM];
+  __shared__ __align__(16) T lds[LM];
   if constexpr (PERSIST) {
     // wavefronts stride over the work list and the batch ranges of their items
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {

@@ -448,6 +448,103 @@ static int setup_hex_patches(mf_op *op, const mf_space *sp, const std::vector<in
   return rc;
 }
 
+// Patch scatter of the hex pencil kernel: patches are runs of EPB consecutive cells in
+// the Morton order of the cell centroids (EPB: the kernel's cells per workgroup), the
+// cell arrays are copied into patch-slot order, and each patch lists its free nodes;
+// nodes of more than one patch get sbuf slots (as the simplex patches).
+template <typename T>
+static int setup_hex_cell_patches(mf_op *op, const mf_space *sp, const std::vector<int32_t> &m,
+                                  const std::vector<int32_t> &gm, const std::vector<T> &geo,
+                                  const std::vector<T> &cf, hipStream_t s) {
+  const int64_t nc = sp->ncells;
+  const int D = sp->D, N = sp->degree + 1, E = hex_cells_per_patch(N);
+  if (E <= 0) return fail(MF_EUNSUPPORTED, "hex patch scatter: degree");
+  std::vector<std::pair<uint32_t, int64_t>> key((size_t)nc);
+  {
+    std::vector<double> cen((size_t)nc * 3);
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int64_t K = 0; K < nc; K++)
+      for (int a = 0; a < 3; a++) {
+        double c = 0.0;
+        for (int v = 0; v < 8; v++) c += sp->coords[(int64_t)sp->cell2vert_int[K * 8 + v] * 3 + a];
+        cen[K * 3 + a] = c * 0.125;
+        lo[a] = std::min(lo[a], c * 0.125);
+        hi[a] = std::max(hi[a], c * 0.125);
+      }
+    for (int64_t K = 0; K < nc; K++) {
+      uint32_t q[3];
+      for (int a = 0; a < 3; a++) {
+        const double w = hi[a] - lo[a];
+        const double f = w > 0.0 ? (cen[K * 3 + a] - lo[a]) / w * 1024.0 : 0.0;
+        q[a] = (uint32_t)std::min(1023.0, std::max(0.0, f));
+      }
+      key[K] = {morton3(q[0], q[1], q[2]), K};
+    }
+    std::sort(key.begin(), key.end());
+  }
+  const int64_t np = (nc + E - 1) / E, ns = np * E;
+  std::vector<int32_t> pmap((size_t)ns * D, -1), pgmap(gm.empty() ? 0 : (size_t)ns * D, -1), nptr{0}, nodes;
+  std::vector<uint16_t> plmap((size_t)ns * D, kSlotSkip);
+  std::vector<T> pgeo((size_t)ns * 24, T(0)), pcf(op->has_coef ? (size_t)ns * 8 : 0, T(0));
+  std::vector<int32_t> stamp((size_t)sp->nnodes, -1), loc((size_t)sp->nnodes, 0);
+  for (int64_t q = 0; q < ns; q++) {
+    const int64_t p = q / E;
+    if (q >= nc) {  // empty slot: the unit cube, coefficient 1, no nodes
+      for (int j : {0, 4, 8}) pgeo[q * 24 + j] = T(1);
+      if (op->has_coef) pcf[q * 8] = T(1);
+      continue;
+    }
+    const int64_t K = key[q].second;
+    for (int i = 0; i < D; i++) {
+      const int32_t n = m[K * D + i];
+      pmap[q * D + i] = n;
+      if (!gm.empty()) pgmap[q * D + i] = gm[K * D + i];
+      if (n < 0) continue;
+      if (stamp[n] != (int32_t)p) {
+        stamp[n] = (int32_t)p;
+        loc[n] = (int32_t)nodes.size() - nptr[p];
+        nodes.push_back(n);
+      }
+      plmap[q * D + i] = (uint16_t)loc[n];
+    }
+    for (int j = 0; j < 24; j++) pgeo[q * 24 + j] = geo[K * 24 + j];
+    if (op->has_coef)
+      for (int j = 0; j < 8; j++) pcf[q * 8 + j] = cf[K * 8 + j];
+    if ((q + 1) % E == 0 || q + 1 == nc) nptr.push_back((int32_t)nodes.size());
+  }
+  while ((int64_t)nptr.size() < np + 1) nptr.push_back((int32_t)nodes.size());
+  std::vector<int32_t> pc((size_t)sp->nnodes, 0);
+  for (int32_t n : nodes) pc[n]++;
+  std::vector<int32_t> sidx((size_t)sp->nnodes, -1), sptr{0}, snode;
+  for (int64_t n = 0; n < sp->nnodes; n++)
+    if (pc[n] > 1) {
+      sidx[n] = (int32_t)snode.size();
+      snode.push_back((int32_t)n);
+      sptr.push_back(sptr.back() + pc[n]);
+    }
+  if ((int64_t)sptr.back() >= (int64_t)kSharedOut || (int64_t)sp->nnodes >= (int64_t)kSharedOut)
+    return fail(MF_EUNSUPPORTED, "hex patch scatter: too many nodes");
+  std::vector<int32_t> fill(snode.size(), 0), out(nodes.size());
+  for (size_t e = 0; e < nodes.size(); e++) {
+    const int32_t n = nodes[e];
+    out[e] = sidx[n] < 0 ? n : (kSharedOut | (sptr[sidx[n]] + fill[sidx[n]]++));
+  }
+  op->hp_npatch = (int)np;
+  op->sp_nshared = (int64_t)snode.size();
+  int rc = upload(op->hp_map, pmap.data(), pmap.size() * sizeof(int32_t), s);
+  if (!rc && !pgmap.empty()) rc = upload(op->hp_gmap, pgmap.data(), pgmap.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->hp_lmap, plmap.data(), plmap.size() * sizeof(uint16_t), s);
+  if (!rc) rc = upload(op->hp_geo, pgeo.data(), pgeo.size() * sizeof(T), s);
+  if (!rc && op->has_coef) rc = upload(op->hp_coef, pcf.data(), pcf.size() * sizeof(T), s);
+  if (!rc) rc = upload(op->hp_nptr, nptr.data(), nptr.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->hp_out, out.data(), out.size() * sizeof(int32_t), s);
+  if (!rc) rc = upload(op->sp_sptr, sptr.data(), sptr.size() * sizeof(int32_t), s);
+  if (!rc && !snode.empty()) rc = upload(op->sp_snode, snode.data(), snode.size() * sizeof(int32_t), s);
+  if (!rc) rc = op->sp_sbuf.alloc(std::max<size_t>(1, (size_t)sptr.back()) * sp->ncomp * sizeof(T));
+  if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
+  return rc;
+}
+
 template <typename T>
 static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
                      const std::vector<int32_t> &to_pos2, hipStream_t s) {
@@ -497,6 +594,14 @@ static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     if (rc) return rc;
   }
   if (op->patched) return setup_hex_patches<T>(op, sp, m, to_pos2, geo, cf, pr->scatter == MF_SCATTER_PATCH, s);
+  if (op->hpatched) {
+    std::vector<int32_t> gm;
+    if (op->fused_gather) {
+      gm.resize(m.size());
+      for (size_t i = 0; i < m.size(); i++) gm[i] = m[i] >= 0 ? to_pos2[m[i]] : m[i];
+    }
+    return setup_hex_cell_patches<T>(op, sp, m, gm, geo, cf, s);
+  }
   return MF_OK;
 }
 
@@ -979,13 +1084,23 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
   const bool first = !acc && c0 == 0 && c1 == op->ncells && op->coloured && !op->patched && op->first_ok &&
                      (op->n_bc_dofs == 0 || bc);
   // the simplex patch scatter writes every free node of a full apply once
-  const bool self_written = !acc && c0 == 0 && c1 == op->ncells && op->spatched && (op->n_bc_dofs == 0 || bc);
+  const bool self_written =
+      !acc && c0 == 0 && c1 == op->ncells && (op->spatched || op->hpatched) && (op->n_bc_dofs == 0 || bc);
   if (!acc && !first && !self_written) {
     rc = launch_fill<T>(y, T(0), op->ndofs, s);
     if (rc) return rc;
   }
   if (c0 == 0 && c1 == op->ncells) {
-    if (op->spatched) {
+    if (op->hpatched) {
+      HexArgs<T> a{op->hp_map.as<int32_t>(), op->hp_geo.as<T>(), op->has_coef ? op->hp_coef.as<T>() : nullptr, x, y,
+                   0, (int64_t)op->hp_npatch * hex_cells_per_patch(op->degree + 1), op->ncomp, nullptr, 0, 0,
+                   fused ? op->hp_gmap.as<int32_t>() : nullptr, nullptr, op->hp_lmap.as<uint16_t>(),
+                   op->hp_nptr.as<int32_t>(), op->hp_out.as<int32_t>(), op->sp_sbuf.as<T>(), acc ? 1 : 0};
+      rc = launch_hex_cell_patches<T>(op->degree + 1, op->kind, a, op->hp_npatch, s);
+      if (!rc)
+        rc = launch_simplex_shared_reduce<T>(op->sp_sptr.as<int32_t>(), op->sp_snode.as<int32_t>(),
+                                             op->sp_sbuf.as<T>(), y, op->sp_nshared, op->ncomp, acc, s);
+    } else if (op->spatched) {
       SimplexPatchArgs<T> pa{op->sp_map.as<int32_t>(), op->sp_geo.as<T>(), op->sp_lmap.as<uint16_t>(),
                              op->sp_nptr.as<int32_t>(), op->sp_out.as<int32_t>(), op->sp_sbuf.as<T>(),
                              op->sp_npatch, op->sp_cap, op->sp_nmax, acc ? 1 : 0};
@@ -1186,20 +1301,29 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   // request, and by default from 2^15 cells
   const bool tet_patchable = (ct == MF_CELL_TET && kind == MF_OP_ELASTICITY && (sp->degree == 2 || sp->degree == 3)) ||
                              (ct == MF_CELL_TRI && kind == MF_OP_MASS && sp->degree == 1);
+  // hex degrees 2-6 (the pencil kernel): patch scatter on request, and by default for
+  // degrees 2-4. A patch is one workgroup's cells (7, 4 and 2 cells for k = 2..4, 3 and
+  // 5 for k = 5, 6); at 32^3 it beat the coloured and atomic scatters for k <= 4 (FP64
+  // vector Laplacian Q2 63 -> 38 us, Q3 84 -> 65 us, Q4 157 -> 138 us) and lost for k = 5, 6
+  // (Q5 242 -> 309 us, Q6 390 -> 471 us), where most of a patch's nodes are shared.
+  const bool hex_patchable = ct == MF_CELL_HEX && kind != MF_OP_ELASTICITY && sp->degree >= 2 && sp->degree <= 6;
   if (pr->scatter == MF_SCATTER_PATCH && tet_patchable) {
     op->spatched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && tet_patchable && nc >= (1 << 15)) {
     op->spatched = true;
+  } else if (hex_patchable && (pr->scatter == MF_SCATTER_PATCH ||
+                               (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4))) {
+    op->hpatched = true;
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind == MF_OP_ELASTICITY)
-      return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for hex Q1, tet P2/P3 elasticity "
-                                   "and the P1 triangle mass");
+      return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, tet "
+                                   "P2/P3 elasticity and the P1 triangle mass");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
              kind != MF_OP_ELASTICITY) {
     op->patched = true;
   }
-  if (op->patched || op->spatched) op->coloured = false;
+  if (op->patched || op->spatched || op->hpatched) op->coloured = false;
   if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured && kind != MF_OP_ELASTICITY) {
     // First-touch thresholds for overwrite applies (HexArgs::first). Colours are
     // launched in internal cell order, so a node's first toucher is the first cell in
@@ -1400,7 +1524,10 @@ int mf_op_get_info(const mf_op *op, mf_op_info *info) {
   info->bytes_per_apply = op->bytes;
   info->ncolours = (int)op->colour_ptr.size() - 1;
   info->cell_launches = op->coloured ? info->ncolours : 1;
-  info->clears_output = (op->first_ok || op->spatched) ? 0 : 1;
+  info->clears_output = (op->first_ok || op->spatched || op->hpatched) ? 0 : 1;
+  info->scatter = (op->patched || op->spatched || op->hpatched) ? MF_SCATTER_PATCH
+                  : op->coloured                                  ? MF_SCATTER_COLOURED
+                                                                  : MF_SCATTER_ATOMIC;
   return MF_OK;
 }
 

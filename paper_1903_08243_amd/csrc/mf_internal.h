@@ -91,6 +91,15 @@ template <typename T> struct HexArgs {
   // by first touch, so the cell touches node n first exactly when n >= first[cell]:
   // it then stores its contribution without reading y, which needs no prior clearing.
   const int32_t *first;
+  // patch scatter (hex_patch_kernel; the cell arrays above are then in patch-slot
+  // order, EPB slots per patch): per slot and node the index in its patch's node list
+  // (kSlotSkip: constrained or empty), the node-list offsets and outputs, and the
+  // shared-node slots (as SimplexPatchArgs; sbuf is [slot][ncomp])
+  const uint16_t *plmap = nullptr;
+  const int32_t *pnptr = nullptr;
+  const int32_t *pout = nullptr;
+  T *psbuf = nullptr;
+  int accumulate = 0;
 };
 
 // Q1 patch decomposition (full applies of degree-1 hex operators): patches of up to
@@ -298,6 +307,10 @@ template <typename T> struct SimplexPatchArgs {
 template <typename T>
 int launch_tet_elasticity_patches(int k, int nq, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
                                   hipStream_t s);
+// hex pencil kernel with the patch scatter (degrees 2-6): a.map / gmap / geo / coef in
+// patch-slot order (hex_cells_per_patch(N) slots per patch) and the patch fields set
+template <typename T> int launch_hex_cell_patches(int N, int kind, const HexArgs<T> &a, int npatch, hipStream_t s);
+int hex_cells_per_patch(int N);
 // the closed-form P1 triangle mass (geometry: the three s_a = |T| c_a per slot)
 template <typename T> int launch_tri_mass_patches(const T *x, T *y, const SimplexPatchArgs<T> &p, hipStream_t s);
 // y[snode[i]] (+)= sum of sbuf slots sptr[i] .. sptr[i+1]-1, per component
@@ -337,6 +350,12 @@ struct mf_op {
   int sp_npatch = 0, sp_cap = 0, sp_nmax = 0;
   int64_t sp_nshared = 0;
   bool spatched = false;
+  // hex pencil-kernel patch scatter (degrees 2-6): patch-slot-ordered cell arrays
+  // (map, gather map, geometry, coefficient, local node indices) and node outputs; the
+  // shared-node slots reuse sp_sbuf, sp_sptr, sp_snode, sp_nshared
+  mf::DeviceBuffer hp_map, hp_gmap, hp_geo, hp_coef, hp_lmap, hp_nptr, hp_out;
+  int hp_npatch = 0;
+  bool hpatched = false;
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
   mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
   mf::DeviceBuffer to1, to2, from1, from2, wt;    // two-stage permutations (positions) and their buffer

@@ -193,11 +193,41 @@ def test_hex_patch_scatter_accumulates(mf, prec):
     assert _relerr(yu, ref) <= TOL[prec]
 
 
-def test_hex_patch_scatter_other_degrees_rejected(mf):
-    mesh = mg.hex_mesh(3, 0.15)
-    sp = mf.Space.from_meshgen(mg.hex_space(mesh, 2))
-    with pytest.raises(mf.MFError, match="patch"):
-        mf.Operator(sp, 1, 0, scatter=mf.SCATTER_PATCH)
+@pytest.mark.parametrize("dirichlet", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
+def test_hex_cell_patch_scatter(mf, k, prec, dirichlet):
+    """Degrees 2-6: the pencil kernel's patch scatter (runs of cells in Morton order,
+    node sums in LDS, shared nodes summed by a second kernel) writes every entry of a
+    NaN-filled output with no clearing pass, matches the oracle with constrained rows,
+    and its accumulating form (used inside CG) adds the same values."""
+    import torch
+    print(f"hex cell patches k={k} prec={prec} dirichlet={dirichlet}", flush=True)
+    mesh = mg.hex_mesh(HEX_M[k], 0.15, config=1, seed_k=k)
+    space = mg.hex_space(mesh, k, ncomp=3, config=1)
+    bnd = space.boundary_nodes() if dirichlet else np.zeros(0, np.int64)
+    mask = None
+    if dirichlet:
+        mask = np.zeros(space.nnodes, np.uint8)
+        mask[bnd] = 1
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
+    xm = x.reshape(-1, 3).copy()
+    xm[bnd] = 0.0
+    ref = oracle.OracleOp(space, 2).apply(xm.ravel()).reshape(-1, 3)
+    ref[bnd] = x.reshape(-1, 3)[bnd]
+    op = mf.Operator(mf.Space.from_meshgen(space), 2, prec, dirichlet=mask, scatter=mf.SCATTER_PATCH)
+    assert op.info["clears_output"] == 0 and op.info["cell_launches"] == 1
+    xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+    y = op.apply(xt, torch.full_like(xt, float("nan"))).double().cpu().numpy()
+    assert np.isfinite(y).all()
+    assert _relerr(y, ref.ravel()) <= TOL[prec], _relerr(y, ref.ravel())
+    if not dirichlet:
+        y0 = torch.tensor(mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_RHS, k), device="cuda", dtype=op.torch_dtype)
+        yi = op.apply_internal(xt).double().cpu().numpy()
+        yt = y0.clone()
+        op.apply_range_internal(0, op.info["ncells"], xt, yt, accumulate=True)
+        d = (yt.double() - y0.double()).cpu().numpy()
+        assert np.abs(d - yi).max() <= 4 * TOL[prec] * (np.abs(yi).max() + 1.0)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
