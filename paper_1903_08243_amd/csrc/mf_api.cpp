@@ -549,8 +549,8 @@ template <typename T>
 static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
                      const std::vector<int32_t> &to_pos2, hipStream_t s) {
   const int k = sp->degree, N = k + 1;
-  if (op->nq1d != N && op->kind != MF_OP_ELASTICITY)
-    return fail(MF_EUNSUPPORTED, "hex operators support nq1d = k+1 only (elasticity: k+1 or k+2)");
+  if (op->nq1d != N && (op->nq1d != N + 1 || op->nq1d > 7))
+    return fail(MF_EUNSUPPORTED, "hex operators: nq1d must be k+1 or k+2 (at most 7)");
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 24, T(0));
   for (int64_t K = 0; K < nc; K++) {
@@ -745,6 +745,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     if (op->has_coef) deg += 1;
   }
   if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rule table ends at 7)");
+  op->qdeg = deg;
   const int nq = (int)w.size();
   op->nqp = nq;
   tet_lagrange(k, pts, phi, dphi);
@@ -960,6 +961,18 @@ static void count_work(mf_op *op) {
     const double fma = 3.0 * 2.0 * (2.0 * q * n * n * n + 3.0 * q * q * n * n + 3.0 * q * q * q * n);
     fl = nc * (2.0 * fma + q * q * q * 214.0);
     by += nc * 24.0 * s;
+  } else if (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) {
+    // k+2 points (thread-per-point kernel), per component, multiply-adds: forward x
+    // (1 + g) q n^3, y (1 + 2g) q^2 n^2, z (m + 3g) q^3 n, and the same backward
+    // (n = k+1 nodes, q points, g / m: gradient / value terms); per point the Jacobian 36,
+    // cofactors and det 32, weight and coefficient 16; per component the push-forward 18,
+    // fluxes 21 and the mass term 4
+    const double n = op->degree + 1, q = op->nq1d;
+    const bool grad = op->kind != MF_OP_MASS, mass = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ;
+    const double g = grad ? 1.0 : 0.0, mm = mass ? 1.0 : 0.0;
+    const double fma = (1 + g) * q * n * n * n + (1 + 2 * g) * q * q * n * n + (mm + 3 * g) * q * q * q * n;
+    fl = nc * (comps * 2.0 * 2.0 * fma + q * q * q * (84.0 + comps * (39.0 * g + 4.0 * mm)));
+    by += nc * 24.0 * s + (op->has_coef ? nc * 8.0 * s : 0.0);
   } else if (op->cell_type == MF_CELL_HEX) {
     const int ni = op->degree + 1;
     const double n = ni, q3 = n * n * n;
@@ -1047,6 +1060,11 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     HexElasArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi,
                      (T)op->lam, (T)op->mu, fused ? op->gmap.as<int32_t>() : nullptr};
     return launch_hex_elasticity<T>(op->degree, op->nq1d, a, atomic, s);
+  } else if (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) {
+    HexQArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(),
+                  op->has_coef ? op->coef.as<T>() : nullptr, x, y, c0, c1, filt, ulo, uhi,
+                  fused ? op->gmap.as<int32_t>() : nullptr, op->ncomp};
+    return launch_hex_q<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_HEX) {
     // the coloured degree-1 kernel reads the block-interleaved copies
     const bool q1 = op->degree == 1 && !atomic;
@@ -1169,9 +1187,11 @@ static bool default_coloured(const mf_op *op) {
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
   if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_HEX && op->kind == MF_OP_ELASTICITY) ||
+      (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) ||
       (op->cell_type == MF_CELL_TET && op->ncomp == 1) ||
       (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)))
-    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC, scalar tet or P2+ triangle operators");
+    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC, hex with k+2 points, scalar tet or P2+ "
+                                 "triangle operators");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
   if (rc) return rc;
   if (op->cell_type == MF_CELL_HEX) {
@@ -1282,6 +1302,15 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     rc = upload(op->q1map, m2.data(), m2.size() * sizeof(int32_t), s);
     if (rc) return rc;
   }
+  // host data for matrix assembly (operators it is built for)
+  if ((ct == MF_CELL_TET && kind != MF_OP_HYPERELASTIC) || (ct == MF_CELL_TRI && kind == MF_OP_MASS && sp->degree == 1)) {
+    op->h_unode.resize((size_t)nc * D);
+    for (int64_t i = 0; i < nc * D; i++) op->h_unode[i] = sp->user_of_int[c2n[i]];
+    if (pr->dirichlet)
+      for (int64_t u = 0; u < sp->nnodes; u++)
+        if (pr->dirichlet[u])
+          for (int c = 0; c < sp->ncomp; c++) op->h_bc_user.push_back((int32_t)(u * sp->ncomp + c));
+  }
   if (pr->dirichlet) {
     std::vector<int32_t> bd;
     for (int64_t n = 0; n < sp->nnodes; n++)
@@ -1306,7 +1335,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   // 5 for k = 5, 6); at 32^3 it beat the coloured and atomic scatters for k <= 4 (FP64
   // vector Laplacian Q2 63 -> 38 us, Q3 84 -> 65 us, Q4 157 -> 138 us) and lost for k = 5, 6
   // (Q5 242 -> 309 us, Q6 390 -> 471 us), where most of a patch's nodes are shared.
-  const bool hex_patchable = ct == MF_CELL_HEX && kind != MF_OP_ELASTICITY && sp->degree >= 2 && sp->degree <= 6;
+  const bool hex_patchable = ct == MF_CELL_HEX && kind != MF_OP_ELASTICITY && sp->degree >= 2 && sp->degree <= 6 &&
+                             op->nq1d == sp->degree + 1;
   if (pr->scatter == MF_SCATTER_PATCH && tet_patchable) {
     op->spatched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && tet_patchable && nc >= (1 << 15)) {
@@ -1315,16 +1345,17 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
                                (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4))) {
     op->hpatched = true;
   } else if (pr->scatter == MF_SCATTER_PATCH) {
-    if (ct != MF_CELL_HEX || op->degree != 1 || kind == MF_OP_ELASTICITY)
+    if (ct != MF_CELL_HEX || op->degree != 1 || kind == MF_OP_ELASTICITY || op->nq1d != 2)
       return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, tet "
                                    "P2/P3 elasticity and the P1 triangle mass");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
-             kind != MF_OP_ELASTICITY) {
+             kind != MF_OP_ELASTICITY && op->nq1d == 2) {
     op->patched = true;
   }
   if (op->patched || op->spatched || op->hpatched) op->coloured = false;
-  if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured && kind != MF_OP_ELASTICITY) {
+  if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured && kind != MF_OP_ELASTICITY &&
+      op->nq1d == op->degree + 1) {
     // First-touch thresholds for overwrite applies (HexArgs::first). Colours are
     // launched in internal cell order, so a node's first toucher is the first cell in
     // that order that lists it. The threshold form needs every later toucher to see the
@@ -1386,7 +1417,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (ct == MF_CELL_HEX) {
     rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, to_pos2, s)
                              : setup_hex<float>(op.get(), sp, pr, m, to_pos2, s);
-    if (!rc && kind == MF_OP_ELASTICITY)
+    if (!rc && (kind == MF_OP_ELASTICITY || op->nq1d != sp->degree + 1))
       rc = precision == MF_F64 ? upload_tensor_tables<double>(op.get(), s) : upload_tensor_tables<float>(op.get(), s);
   }
   else if (ct == MF_CELL_QUAD)

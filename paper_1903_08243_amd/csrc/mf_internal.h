@@ -211,6 +211,25 @@ int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipS
 
 // ELASTICITY on Q1..Q6 hexahedra (hex_elas_kernels.hip): three node-interleaved
 // components, sum-factorised, nq = k+1 or k+2 Gauss points per direction (at most 7)
+// Scalar hex operators with k+2 Gauss points per direction (hex_q_kernels.hip): map,
+// geometry, tables as HexElasArgs; coef: 8 trilinear coefficients of the vertex
+// coefficient per cell (or null); ncomp 1 or 3 (node-interleaved).
+template <typename T> struct HexQArgs {
+  const int32_t *map;
+  const T *geo;
+  const T *tab;
+  const T *coef;
+  const T *x;
+  T *y;
+  int64_t c0, c1;
+  const int32_t *cell_user;
+  int64_t ulo, uhi;
+  const int32_t *gmap;
+  int ncomp;
+};
+template <typename T>
+int launch_hex_q(int k, int nq, int kind, const HexQArgs<T> &a, bool atomic, hipStream_t s);
+
 template <typename T> struct HexElasArgs {
   const int32_t *map;  // [ncells][(k+1)^3] node ids, internal numbering (negative: constrained)
   const T *geo;        // [ncells][24] trilinear coefficients c1..c7 per coordinate
@@ -318,6 +337,18 @@ template <typename T>
 int launch_simplex_shared_reduce(const int32_t *sptr, const int32_t *snode, const T *sbuf, T *y, int64_t nshared,
                                  int ncomp, bool accumulate, hipStream_t s);
 
+// Element matrices of tet operators (FP64 tables phi [nq][D], reference gradients
+// [nq][D][3], weights [nq], vertex basis [nq][4]) added into CSR values (user numbering
+// through unode [cell][D]); the closed-form P1 triangle mass likewise.
+template <typename T>
+int launch_tet_element_csr(const int32_t *fmap, const int32_t *unode, const T *geo, const T *coef,
+                           const double *tab, int64_t ncells, int D, int nq, int kind, int ncomp, double lam,
+                           double mu, const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
+template <typename T>
+int launch_tri_mass_element_csr(const int32_t *fmap, const int32_t *unode, const T *geo, int64_t ncells,
+                                const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
+template <typename T> int launch_set_at(const int64_t *pos, int64_t n, T v, T *vals, hipStream_t s);
+
 // Internal-numbering entry points used by the solvers.
 int op_apply_internal(const mf_op *op, const void *x, void *y, hipStream_t s);
 // y += A x (internal numbering, y not cleared), then the constraint rows y_b = x_b
@@ -356,6 +387,14 @@ struct mf_op {
   mf::DeviceBuffer hp_map, hp_gmap, hp_geo, hp_coef, hp_lmap, hp_nptr, hp_out;
   int hp_npatch = 0;
   bool hpatched = false;
+  // matrix assembly (tets P1-P3 and the P1 triangle mass): per internal cell the user
+  // node of each local node, the constrained user dofs, the quadrature degree of the
+  // tet rule, and the CSR pattern once built
+  std::vector<int32_t> h_unode, h_bc_user;
+  int qdeg = 0;
+  mutable std::vector<int64_t> csr_rowptr;
+  mutable std::vector<int32_t> csr_col;
+  mutable bool csr_built = false;
   mf::DeviceBuffer perm;                          // internal node -> user node (int32)
   mf::DeviceBuffer iperm;                         // user node -> internal node (int32)
   mf::DeviceBuffer to1, to2, from1, from2, wt;    // two-stage permutations (positions) and their buffer

@@ -136,8 +136,12 @@ def _gll_1d_matrices(k):
     return M, K
 
 
+@pytest.mark.parametrize("extra", [0, 1], ids=["q=k+1", "q=k+2"])
 @pytest.mark.parametrize("k", [1, 2, 3, 4])
-def test_uniform_hex_matches_kronecker_assembly(k):
+def test_uniform_hex_matches_kronecker_assembly(k, extra):
+    """On the uniform mesh the integrands are polynomials of degree <= 2k per variable,
+    so k+1 and k+2 Gauss points both integrate them exactly: the action equals the
+    Kronecker form of the exact 1D matrices for either rule."""
     m = 2
     h = 1.0 / m
     mesh = mg.hex_mesh(m, 0.0)
@@ -147,7 +151,7 @@ def test_uniform_hex_matches_kronecker_assembly(k):
     for ncomp, kind, Eloc in [(1, oracle.OP_MASS, Me), (1, oracle.OP_HELMHOLTZ, Me + Ke),
                               (3, oracle.OP_LAPLACIAN, Ke)]:
         sp_ = mg.hex_space(mesh, k, ncomp=ncomp, renumber=True, config=9)
-        op = oracle.OracleOp(sp_, kind)
+        op = oracle.OracleOp(sp_, kind, nq1d=k + 1 + extra)
         A = np.zeros((op.ndofs, op.ndofs))
         for c2n in sp_.cell2node:
             for comp in range(ncomp):

@@ -537,3 +537,38 @@ def test_coloured_scatter_is_bit_reproducible_and_matches_atomic(mf, prec):
     assert np.array_equal(y1, y2)
     ya = opa.apply(x).cpu().numpy()
     assert _relerr(ya, y1) <= (1e-14 if prec == 0 else 1e-6)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("kind,ncomp", [(1, 1), (2, 3), (0, 1), (3, 1)],
+                         ids=["helmholtz", "laplacian3", "mass", "poisson"])
+def test_hex_action_k_plus_2_points(mf, k, scatter, prec, kind, ncomp):
+    """The paper's hex quadrature (k+2 Gauss points per direction, Table 2's Q) on
+    perturbed meshes against the oracle with the same rule."""
+    import torch
+    print(f"hex k+2 points kind={kind} ncomp={ncomp} k={k} prec={prec} scatter={scatter}", flush=True)
+    mesh = mg.hex_mesh(5, 0.15, config=1, seed_k=k)  # 125 cells: ragged against 64 / q^3 cells per group
+    space = mg.hex_space(mesh, k, ncomp=ncomp, config=1)
+    coef = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if kind in (0, 3) else None
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
+    ref = oracle.OracleOp(space, kind, coef=coef, nq1d=k + 2).apply(x)
+    op = mf.Operator(mf.Space.from_meshgen(space), kind, prec, nq1d=k + 2, vertex_coef=coef, scatter=scatter)
+    assert op.info["nq1d"] == k + 2
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+
+
+def test_hex_k_plus_2_points_limits(mf):
+    """k+2 points are built up to 7 per direction; other rules and the diagonal are
+    rejected."""
+    mesh = mg.hex_mesh(2, 0.15, config=1)
+    sp = mf.Space.from_meshgen(mg.hex_space(mesh, 6, config=1))
+    with pytest.raises(mf.MFError, match="nq1d"):
+        mf.Operator(sp, 1, 0, nq1d=8)
+    sp2 = mf.Space.from_meshgen(mg.hex_space(mesh, 2, config=1))
+    with pytest.raises(mf.MFError, match="nq1d"):
+        mf.Operator(sp2, 1, 0, nq1d=5)
+    with pytest.raises(mf.MFError, match="diagonal"):
+        mf.Operator(sp2, 1, 0, nq1d=4).diagonal()
