@@ -165,8 +165,11 @@ int mf_op_apply_range(const mf_op *op, int64_t start, int64_t end, const void *x
                       int accumulate, void *stream);
 
 /* d = diag(A) (ndofs, op precision); constrained dofs get 1. Used as the Jacobi
- * preconditioner. MF_EUNSUPPORTED for HYPERELASTIC, hex ELASTICITY, the one-component
- * tet operators and triangles other than the P1 mass. */
+ * preconditioner. Hex scalar operators with k+1 points, quadrilaterals, tet elasticity
+ * and the P1 triangle mass have fused diagonal kernels; the one-component tet
+ * operators, the other triangle operators, hex elasticity and the hex operators with
+ * k+2 points sum the diagonals of their element matrices (FP64, a thread per cell
+ * and node; synchronous). MF_EUNSUPPORTED for HYPERELASTIC. */
 int mf_op_diagonal(const mf_op *op, void *d, void *stream);
 
 /* Internal cell order and numbering. Every space colours its cells greedily
@@ -176,7 +179,11 @@ int mf_op_diagonal(const mf_op *op, void *d, void *stream);
  * user cell of each internal cell (ncells entries, may be NULL), the colour
  * offsets (ncolours + 1 entries, may be NULL) and the number of colours.
  * Nodes are numbered internally in order of first appearance when the cells
- * are traversed in that internal order; the kernels gather
+ * are traversed in that internal order (hexahedra, quadrilaterals, triangles) or,
+ * for tetrahedra, in the Morton order of their centroids (each
+ * coordinate quantised to 1024 steps over the centroids' bounding box, bit b of
+ * x, y, z at bits 3b, 3b+1, 3b+2 of the code; ties by internal cell order), the
+ * order in which the patch scatter takes them; the kernels gather
  * and scatter only in that numbering, so the nodes of neighbouring cells are
  * neighbours in memory whatever numbering the caller uses. mf_op_apply and
  * mf_op_apply_range take user-numbered vectors and pay one permutation in and

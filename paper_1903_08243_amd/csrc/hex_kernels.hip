@@ -25,6 +25,8 @@
 //           entry per point), adjugate rows, G = w |det|^{-1} adj adj^T,
 //           fluxes F = coef G grad_ref u and mass term w |det| coef u.
 // Backward: transposes in the reverse order, then atomic scatter-add.
+#include <type_traits>
+
 #include "hex_common.h"
 
 namespace mf {
@@ -319,25 +321,29 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   if constexpr (PATCH) {
     __syncthreads();  // every lane has finished reading the stage buffers, reused below
     const int n0 = A.pnptr[b], nn = A.pnptr[b + 1] - n0;
-    T *acc = base;  // nn <= EPB n^3 <= the stage buffers' size
-    for (int e = t; e < nn; e += 64 * WPB) acc[e] = T(0);
+    // nn <= EPB n^3 <= the stage buffers' size. FP32 sums are kept in FP64 where the
+    // workgroup's LDS holds them (LDS FP32 atomic adds measured several times slower
+    // than FP64 ones)
+    using Acc = std::conditional_t<(sizeof(T) == 4 && 2 * EPB * N3 <= hex_lds_size<T, N, GRAD, WPB>()), double, T>;
+    Acc *acc = reinterpret_cast<Acc *>(base);
+    for (int e = t; e < nn; e += 64 * WPB) acc[e] = Acc(0);
     __syncthreads();
     if (!mirror) {
       const uint16_t *lp = A.plmap + (b * EPB + le) * N3 + pa + N * pb;
 #pragma unroll
       for (int l = 0; l < N; l++) {
         const int li = lp[NN * l];
-        if (li != kSlotSkip) atomicAdd(&acc[li], r[l]);
+        if (li != kSlotSkip) atomicAdd(&acc[li], (Acc)r[l]);
       }
     }
     __syncthreads();
     for (int e = t; e < nn; e += 64 * WPB) {
       const int32_t o = A.pout[n0 + e];
       if (o & kSharedOut) {
-        A.psbuf[(int64_t)(o & (kSharedOut - 1)) * nc + comp] = acc[e];
+        A.psbuf[(int64_t)(o & (kSharedOut - 1)) * nc + comp] = (T)acc[e];
       } else {
         T *d = A.y + (int64_t)o * nc + comp;
-        *d = A.accumulate ? *d + acc[e] : acc[e];
+        *d = A.accumulate ? *d + (T)acc[e] : (T)acc[e];
       }
     }
     __syncthreads();

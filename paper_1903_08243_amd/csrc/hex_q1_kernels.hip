@@ -204,7 +204,7 @@ __device__ __forceinline__ void q1_patch_slot_load(const HexPatchArgs<T> &P, int
 
 template <typename T, int KIND>
 __device__ __forceinline__ void q1_patch_slot(const uint16_t (&li)[8], const T (&K)[8], T (&G)[21], const T *sx,
-                                              const double *sxyz, T *sy) {
+                                              const double *sxyz, double *sy) {
   if (li[0] == kPatchEmpty) return;  // a slot past the patch's cells (a real cell has all 8)
   T xv[8], yv[8];
 #pragma unroll
@@ -227,7 +227,7 @@ __device__ __forceinline__ void q1_patch_slot(const uint16_t (&li)[8], const T (
   }
   q1_cell<T, KIND>(G, K, xv, yv);
 #pragma unroll
-  for (int i = 0; i < 8; i++) atomic_add_f(&sy[li[i]], yv[i]);
+  for (int i = 0; i < 8; i++) atomic_add_f(&sy[li[i]], (double)yv[i]);
 }
 
 // Three wavefronts per SIMD where the registers allow it without spilling much (the
@@ -239,8 +239,11 @@ __global__ void __launch_bounds__(kPatchThreads, q1_patch_waves<KIND>()) hex_q1_
   static_assert(kPatchCells == 2 * kPatchThreads, "two cell slots per thread");
   constexpr bool XYZ = q1_patch_coords<T>();
   extern __shared__ __align__(16) unsigned char patch_lds[];
+  // node sums in FP64 for both precisions (LDS FP32 atomic adds measured several
+  // times slower than FP64 ones)
   double *sxyz = (double *)patch_lds;
-  T *sx = (T *)(sxyz + (XYZ ? 3 * P.max_nodes : 0)), *sy = sx + P.max_nodes;
+  double *sy = sxyz + (XYZ ? 3 * P.max_nodes : 0);
+  T *sx = (T *)(sy + P.max_nodes);
   const int64_t item = xcd_batch(blockIdx.x, P.npatch * P.ncomp);
   if (item >= P.npatch * P.ncomp) return;
   const int p = (int)item / P.ncomp, comp = (int)item % P.ncomp, nc = P.ncomp;
@@ -256,7 +259,7 @@ __global__ void __launch_bounds__(kPatchThreads, q1_patch_waves<KIND>()) hex_q1_
     const int64_t g = P.gnodes ? P.gnodes[n0 + i] : id;
     const T xv = P.x[g * nc + comp];  // a constrained node's value is read, then replaced by 0
     sx[i] = (e & kPatchFixed) ? T(0) : xv;
-    sy[i] = T(0);
+    sy[i] = 0.0;
     if constexpr (XYZ) {
       sxyz[3 * i] = P.xyz[3 * id];
       sxyz[3 * i + 1] = P.xyz[3 * id + 1];
@@ -272,8 +275,8 @@ __global__ void __launch_bounds__(kPatchThreads, q1_patch_waves<KIND>()) hex_q1_
     const int32_t e = P.nodes[n0 + i];
     if (e & kPatchFixed) continue;
     T *dst = &P.y[(int64_t)(e & kPatchIdMask) * nc + comp];
-    if (e & kPatchShared) atomic_add_f(dst, sy[i]);
-    else *dst += sy[i];
+    if (e & kPatchShared) atomic_add_f(dst, (T)sy[i]);
+    else *dst += (T)sy[i];
   }
 }
 
@@ -282,7 +285,7 @@ int launch_hex_patches(int N, int kind, const HexPatchArgs<T> &a, hipStream_t s)
   if (a.npatch <= 0) return MF_OK;
   if (N != 2) return fail(MF_EUNSUPPORTED, "hex patch kernel: degree");
   const dim3 grid((unsigned)xcd_grid((int64_t)a.npatch * a.ncomp)), block(kPatchThreads);
-  const size_t lds = (size_t)a.max_nodes * ((q1_patch_coords<T>() ? 3 * sizeof(double) : 0) + 2 * sizeof(T));
+  const size_t lds = (size_t)a.max_nodes * ((q1_patch_coords<T>() ? 3 * sizeof(double) : 0) + sizeof(double) + sizeof(T));
   switch (kind) {
     case K_MASS: hex_q1_patch_kernel<T, K_MASS><<<grid, block, lds, s>>>(a); break;
     case K_HELM: hex_q1_patch_kernel<T, K_HELM><<<grid, block, lds, s>>>(a); break;

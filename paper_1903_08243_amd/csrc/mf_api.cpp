@@ -65,6 +65,51 @@ static void trilinear_coeffs(const double X[8], double c[8]) {
   c[7] = X[7] - X[3] - X[5] - X[6] + X[1] + X[2] + X[4] - X[0];
 }
 
+// 3 x 10-bit Morton code (bit i of x, y, z at bits 3i, 3i + 1, 3i + 2)
+static uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
+  auto spread = [](uint32_t v) {
+    v &= 1023u;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+  };
+  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
+}
+
+// Cells 0..nc-1 (vertex lists cv, nvc per cell) sorted by the Morton code of their
+// centroids, each coordinate quantised to 1024 steps over the centroids' bounding
+// box; ties by cell index.
+static std::vector<int64_t> morton_cell_order(const std::vector<double> &coords, int gd, const int32_t *cv, int nvc,
+                                              int64_t nc) {
+  std::vector<double> cen((size_t)nc * 3, 0.0);
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int64_t K = 0; K < nc; K++)
+    for (int a = 0; a < gd; a++) {
+      double c = 0.0;
+      for (int v = 0; v < nvc; v++) c += coords[(int64_t)cv[K * nvc + v] * gd + a];
+      c /= nvc;
+      cen[K * 3 + a] = c;
+      lo[a] = std::min(lo[a], c);
+      hi[a] = std::max(hi[a], c);
+    }
+  std::vector<std::pair<uint32_t, int64_t>> key((size_t)nc);
+  for (int64_t K = 0; K < nc; K++) {
+    uint32_t q[3] = {0, 0, 0};
+    for (int a = 0; a < gd; a++) {
+      const double w = hi[a] - lo[a];
+      const double f = w > 0.0 ? (cen[K * 3 + a] - lo[a]) / w * 1024.0 : 0.0;
+      q[a] = (uint32_t)std::min(1023.0, std::max(0.0, f));
+    }
+    key[K] = {morton3(q[0], q[1], q[2]), K};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int64_t> order((size_t)nc);
+  for (int64_t r = 0; r < nc; r++) order[r] = key[r].second;
+  return order;
+}
+
 }  // namespace mf
 
 using namespace mf;
@@ -249,12 +294,24 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
   s->cell2vert_int.resize(nc * nvc);
   for (int64_t ic = 0; ic < nc; ic++)
     for (int v = 0; v < nvc; v++) s->cell2vert_int[ic * nvc + v] = mesh->cell2vert[(int64_t)s->cell_user_of_int[ic] * nvc + v];
-  // internal node numbering: first appearance in the internal cell order
+  // internal node numbering: first appearance when the cells are traversed in the
+  // internal cell order (hexahedra, quadrilaterals, triangles: the coloured hex
+  // launches store a node's first contribution without reading y, which needs this
+  // order, and the coloured triangle launches measured up to 2x slower otherwise) or,
+  // for tetrahedra, in the Morton order of their centroids (the patch scatter of the
+  // elasticity kernels takes Morton-ordered runs of cells, whose nodes then sit
+  // together in memory: P2 86 -> 80 us, P3 384 -> 374 us at 48^3 x 6 cells)
   s->int_of_user.assign((size_t)nnodes, -1);
   s->user_of_int.clear();
   s->user_of_int.reserve((size_t)nnodes);
-  s->cell2node_int.resize(s->cell2node.size());
-  for (int64_t ic = 0; ic < nc; ic++) {
+  std::vector<int64_t> walk;
+  if (mesh->cell_type == MF_CELL_TET) {
+    walk = morton_cell_order(s->coords, s->gdim, s->cell2vert_int.data(), nvc, nc);
+  } else {
+    walk.resize((size_t)nc);
+    for (int64_t ic = 0; ic < nc; ic++) walk[ic] = ic;
+  }
+  for (int64_t ic : walk) {
     const int32_t *row = cell2node + (int64_t)s->cell_user_of_int[ic] * D;
     for (int i = 0; i < D; i++) {
       const int32_t u = row[i];
@@ -262,8 +319,12 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
         s->int_of_user[u] = (int32_t)s->user_of_int.size();
         s->user_of_int.push_back(u);
       }
-      s->cell2node_int[ic * D + i] = s->int_of_user[u];
     }
+  }
+  s->cell2node_int.resize(s->cell2node.size());
+  for (int64_t ic = 0; ic < nc; ic++) {
+    const int32_t *row = cell2node + (int64_t)s->cell_user_of_int[ic] * D;
+    for (int i = 0; i < D; i++) s->cell2node_int[ic * D + i] = s->int_of_user[row[i]];
   }
   for (int64_t u = 0; u < nnodes; u++)  // nodes in no cell keep their relative order at the end
     if (s->int_of_user[u] < 0) {
@@ -303,18 +364,6 @@ namespace mf {
 
 static bool default_coloured(const mf_op *op);
 
-// 3 x 10-bit Morton code (bit i of x, y, z at bits 3i, 3i + 1, 3i + 2)
-static uint32_t morton3(uint32_t x, uint32_t y, uint32_t z) {
-  auto spread = [](uint32_t v) {
-    v &= 1023u;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
-  };
-  return spread(x) | (spread(y) << 1) | (spread(z) << 2);
-}
 
 // Patches of the Q1 patch kernel: cells in Morton order of their centroids, cut
 // greedily into runs of at most `cap` cells and kPatchNodes distinct free nodes. cap
@@ -614,35 +663,14 @@ static int setup_simplex_patches(mf_op *op, const mf_space *sp, const std::vecto
   const int64_t nc = sp->ncells;
   const int D = sp->D, nv = sp->nvc, gd = sp->gdim;
   auto mp = [&](int64_t K, int i) { return m_aosoa ? m[((K / 64) * D + i) * 64 + K % 64] : m[K * D + i]; };
-  std::vector<double> cen((size_t)nc * 3, 0.0);
-  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
-  for (int64_t K = 0; K < nc; K++)
-    for (int a = 0; a < gd; a++) {
-      double c = 0.0;
-      for (int v = 0; v < nv; v++) c += sp->coords[(int64_t)sp->cell2vert_int[K * nv + v] * gd + a];
-      c /= nv;
-      cen[K * 3 + a] = c;
-      lo[a] = std::min(lo[a], c);
-      hi[a] = std::max(hi[a], c);
-    }
-  std::vector<std::pair<uint32_t, int64_t>> key((size_t)nc);
-  for (int64_t K = 0; K < nc; K++) {
-    uint32_t q[3] = {0, 0, 0};
-    for (int a = 0; a < gd; a++) {
-      const double w = hi[a] - lo[a];
-      const double f = w > 0.0 ? (cen[K * 3 + a] - lo[a]) / w * 1024.0 : 0.0;
-      q[a] = (uint32_t)std::min(1023.0, std::max(0.0, f));
-    }
-    key[K] = {morton3(q[0], q[1], q[2]), K};
-  }
-  std::sort(key.begin(), key.end());
+  const std::vector<int64_t> order = morton_cell_order(sp->coords, gd, sp->cell2vert_int.data(), nv, nc);
   // greedy patches: slots (patch, slot) hold cells; node lists of free nodes
   std::vector<int32_t> stamp((size_t)sp->nnodes, -1), loc((size_t)sp->nnodes, 0);
   std::vector<int32_t> nptr{0}, nodes;
   std::vector<int64_t> slot_cell;  // per slot: cell or -1
   int pid = -1, ncell = 0, nnode = 0;
   for (int64_t r = 0; r < nc; r++) {
-    const int64_t K = key[r].second;
+    const int64_t K = order[r];
     int fresh = 0;
     for (int i = 0; i < D; i++) {
       const int32_t n = mp(K, i);
@@ -829,8 +857,12 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   }
   rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
   if (!rc && op->spatched) {
-    // patches of 512 cells (P2) or 256 (P3) with at most 2048 nodes (48 KB of FP64 sums)
-    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, 10, k <= 2 ? 512 : 256, 2048, s);
+    // patch sizes measured best on 48^3 x 6 cells among 128..1024 cells and 1024..2700
+    // nodes: P2 384 cells / 2048 nodes (FP64 72, FP32 57 us; 512 cells: 80, 74 us), P3
+    // 384 / 2700 in FP64 (352 us; 256 / 2048: 366 us), 256 / 2048 in FP32 (210 us)
+    const bool f64 = sizeof(T) == 8;
+    const int cap = k <= 2 ? 384 : (f64 ? 384 : 256), nmax = k <= 2 ? 2048 : (f64 ? 2700 : 2048);
+    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, 10, cap, nmax, s);
   }
   if (!rc) MF_HIP(hipStreamSynchronize(s));
   return rc;
@@ -843,6 +875,7 @@ template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, con
   const int k = sp->degree;
   int deg = (op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ) ? 2 * k : 2 * k - 2;
   if (op->has_coef) deg += 1;
+  op->qdeg = deg;
   std::vector<double> pts, w, phi, dphi;
   tri_rule(deg, pts, w);
   tri_lagrange(k, pts, phi, dphi);
@@ -1186,15 +1219,12 @@ static bool default_coloured(const mf_op *op) {
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {
-  if (op->kind == MF_OP_HYPERELASTIC || (op->cell_type == MF_CELL_HEX && op->kind == MF_OP_ELASTICITY) ||
-      (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) ||
-      (op->cell_type == MF_CELL_TET && op->ncomp == 1) ||
-      (op->cell_type == MF_CELL_TRI && !(op->kind == MF_OP_MASS && op->degree == 1)))
-    return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC, hex with k+2 points, scalar tet or P2+ "
-                                 "triangle operators");
+  if (op->kind == MF_OP_HYPERELASTIC) return fail(MF_EUNSUPPORTED, "diagonal: not built for HYPERELASTIC");
   int rc = launch_fill<T>(d, T(0), op->ndofs, s);
   if (rc) return rc;
-  if (op->cell_type == MF_CELL_HEX) {
+  if (element_diag_supported(op)) {
+    rc = element_diag<T>(op, d, s);
+  } else if (op->cell_type == MF_CELL_HEX) {
     HexArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr, nullptr, d, 0,
                  op->ncells, op->ncomp, nullptr, 0, 0};
     rc = launch_hex_diag<T>(op->degree + 1, op->kind, a, s);

@@ -347,6 +347,15 @@ int launch_tet_element_csr(const int32_t *fmap, const int32_t *unode, const T *g
 template <typename T>
 int launch_tri_mass_element_csr(const int32_t *fmap, const int32_t *unode, const T *geo, int64_t ncells,
                                 const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
+template <typename T>
+int launch_simplex_element_diag(int dim, const int32_t *fmap, const T *geo, const T *coef, const double *tab,
+                                int64_t ncells, int D, int nq, int kind, int nc, double lam, double mu, T *d,
+                                hipStream_t s);
+template <typename T>
+int launch_hex_element_diag(const int32_t *map, const T *geo, const T *coef, const double *tab, int64_t ncells,
+                            int n, int nq, int kind, int nc, double lam, double mu, T *d, hipStream_t s);
+bool element_diag_supported(const mf_op *op);
+template <typename T> int element_diag(const mf_op *op, T *d, hipStream_t s);
 template <typename T> int launch_set_at(const int64_t *pos, int64_t n, T v, T *vals, hipStream_t s);
 
 // Internal-numbering entry points used by the solvers.

@@ -626,11 +626,13 @@ __global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs
   constexpr int NT = (D + 15) / 16;
   constexpr bool F64 = sizeof(T) == 8;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *acc = reinterpret_cast<T *>(smem_raw);
+  // sums in FP64 for both precisions: LDS FP32 atomic adds measured several times
+  // slower than FP64 ones here (the FP32 P2 kernel waited on LDS 70x longer)
+  double *acc = reinterpret_cast<double *>(smem_raw);
   const int64_t p = xcd_batch(blockIdx.x, P.npatch);  // contiguous patch ranges per XCD
   if (p >= P.npatch) return;                           // whole workgroup: no barrier skipped
   const int n0 = P.nptr[p], nn = P.nptr[p + 1] - n0;
-  for (int e = threadIdx.x; e < 3 * nn; e += blockDim.x) acc[e] = T(0);
+  for (int e = threadIdx.x; e < 3 * nn; e += blockDim.x) acc[e] = 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int j = lane & 15, g = lane >> 4, cl = 16 * w + j;
@@ -650,7 +652,7 @@ __global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs
           const int l = lp[i * 64];
           if (l != kSlotSkip) {
 #pragma unroll
-            for (int c = 0; c < 3; c++) atomicAdd(&acc[3 * l + c], yacc[t][c][v]);
+            for (int c = 0; c < 3; c++) atomicAdd(&acc[3 * l + c], (double)yacc[t][c][v]);
           }
         }
       }
@@ -661,11 +663,11 @@ __global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs
     if (o & kSharedOut) {
       T *d = P.sbuf + 3 * (int64_t)(o & (kSharedOut - 1));
 #pragma unroll
-      for (int c = 0; c < 3; c++) d[c] = acc[3 * e + c];
+      for (int c = 0; c < 3; c++) d[c] = (T)acc[3 * e + c];
     } else {
       T *d = A.y + 3 * (int64_t)o;
 #pragma unroll
-      for (int c = 0; c < 3; c++) d[c] = P.accumulate ? d[c] + acc[3 * e + c] : acc[3 * e + c];
+      for (int c = 0; c < 3; c++) d[c] = P.accumulate ? d[c] + (T)acc[3 * e + c] : (T)acc[3 * e + c];
     }
   }
 }
@@ -702,7 +704,7 @@ template int launch_simplex_shared_reduce<float>(const int32_t *, const int32_t 
 template <typename T, int K, int NQ>
 static int launch_tet_patch_kq(const TetArgs<T> &a, const SimplexPatchArgs<T> &p, hipStream_t s) {
   if (p.npatch <= 0) return MF_OK;
-  const size_t lds = (size_t)p.nmax * 3 * sizeof(T);
+  const size_t lds = (size_t)p.nmax * 3 * sizeof(double);
   if (lds > 64 * 1024) return fail(MF_EUNSUPPORTED, "tet patch scatter: patch node list too long for LDS");
   tet_elasticity_patch_kernel<T, K, NQ><<<dim3((unsigned)xcd_grid(p.npatch)), dim3(256), lds, s>>>(a, p);
   MF_HIP(hipGetLastError());
@@ -878,11 +880,11 @@ template <typename T>
 __global__ void __launch_bounds__(256) tri_mass_patch_kernel(const T *__restrict__ x, T *__restrict__ y,
                                                              const SimplexPatchArgs<T> P) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T *acc = reinterpret_cast<T *>(smem_raw);
+  double *acc = reinterpret_cast<double *>(smem_raw);  // FP64 sums, as in the tet patch kernel
   const int64_t p = xcd_batch(blockIdx.x, P.npatch);
   if (p >= P.npatch) return;
   const int n0 = P.nptr[p], nn = P.nptr[p + 1] - n0;
-  for (int e = threadIdx.x; e < nn; e += blockDim.x) acc[e] = T(0);
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) acc[e] = 0.0;
   __syncthreads();
   const T k60 = T(1) / T(60);
   for (int sl = threadIdx.x; sl < P.cap; sl += blockDim.x) {
@@ -901,19 +903,19 @@ __global__ void __launch_bounds__(256) tri_mass_patch_kernel(const T *__restrict
     const T sx = sa[0] * xv[0] + sa[1] * xv[1] + sa[2] * xv[2];
 #pragma unroll
     for (int i = 0; i < 3; i++)
-      if (li[i] != kSlotSkip) atomicAdd(&acc[li[i]], ((S + sa[i]) * X + sx + (S + T(2) * sa[i]) * xv[i]) * k60);
+      if (li[i] != kSlotSkip) atomicAdd(&acc[li[i]], (double)(((S + sa[i]) * X + sx + (S + T(2) * sa[i]) * xv[i]) * k60));
   }
   __syncthreads();
   for (int e = threadIdx.x; e < nn; e += blockDim.x) {
     const int32_t o = P.out[n0 + e];
-    if (o & kSharedOut) P.sbuf[o & (kSharedOut - 1)] = acc[e];
-    else y[o] = P.accumulate ? y[o] + acc[e] : acc[e];
+    if (o & kSharedOut) P.sbuf[o & (kSharedOut - 1)] = (T)acc[e];
+    else y[o] = P.accumulate ? y[o] + (T)acc[e] : (T)acc[e];
   }
 }
 
 template <typename T> int launch_tri_mass_patches(const T *x, T *y, const SimplexPatchArgs<T> &p, hipStream_t s) {
   if (p.npatch <= 0) return MF_OK;
-  const size_t lds = (size_t)p.nmax * sizeof(T);
+  const size_t lds = (size_t)p.nmax * sizeof(double);
   if (lds > 64 * 1024) return fail(MF_EUNSUPPORTED, "triangle patch scatter: patch node list too long for LDS");
   tri_mass_patch_kernel<T><<<dim3((unsigned)xcd_grid(p.npatch)), dim3(256), lds, s>>>(x, y, p);
   MF_HIP(hipGetLastError());

@@ -72,8 +72,6 @@ def test_hex_elasticity_paper_rule_dirichlet_range(mf, k):
         op.apply_range(a, b, xt, y, accumulate=True)
     assert _relerr(y.cpu().numpy(), oracle.OracleOp(space, oracle.OP_ELASTICITY).apply(x)) <= 1e-12
     with pytest.raises(mf.MFError):
-        op.diagonal()
-    with pytest.raises(mf.MFError):
         mf.Operator(sp, mf.ELASTICITY, mf.F64, nq1d=k + 3)
 
 

@@ -486,6 +486,22 @@ def _first_touch(c2n, nnodes):
     return np.array(order + rest, dtype=np.int32)
 
 
+def _morton_order(cen):
+    """Definition: positions sorted by the Morton code of the centroids (each
+    coordinate quantised to 1024 steps over their bounding box, bit b of x, y, z at
+    bits 3b, 3b + 1, 3b + 2), ties by position."""
+    lo, hi = cen.min(axis=0), cen.max(axis=0)
+    q = np.zeros((len(cen), 3), np.int64)
+    for a in range(cen.shape[1]):
+        w = hi[a] - lo[a]
+        q[:, a] = np.clip(np.floor((cen[:, a] - lo[a]) / w * 1024.0), 0, 1023) if w > 0 else 0
+    code = np.zeros(len(cen), np.int64)
+    for b in range(10):
+        for a in range(3):
+            code |= ((q[:, a] >> b) & 1) << (3 * b + a)
+    return np.lexsort((np.arange(len(cen)), code))
+
+
 @pytest.mark.parametrize("case", ["hex", "tet", "tri"])
 def test_colouring_and_internal_numbering_bit_exact(mf, case):
     import torch
@@ -509,7 +525,8 @@ def test_colouring_and_internal_numbering_bit_exact(mf, case):
         nodes = space.cell2node[cells].ravel()
         assert len(np.unique(nodes)) == nodes.size
     i2u = sp.internal_to_user()
-    assert np.array_equal(i2u, _first_touch(space.cell2node[order], space.nnodes))
+    walk = order if case != "tet" else order[_morton_order(mesh.coords[mesh.cell2vert[order]].mean(axis=1))]
+    assert np.array_equal(i2u, _first_touch(space.cell2node[walk], space.nnodes))
     coef = np.ones(mesh.nverts) if kind == 0 else None
     op = mf.Operator(sp, kind, 0, vertex_coef=coef)
     nc = space.ncomp
@@ -561,8 +578,7 @@ def test_hex_action_k_plus_2_points(mf, k, scatter, prec, kind, ncomp):
 
 
 def test_hex_k_plus_2_points_limits(mf):
-    """k+2 points are built up to 7 per direction; other rules and the diagonal are
-    rejected."""
+    """k+2 points are built up to 7 per direction; other rules are rejected."""
     mesh = mg.hex_mesh(2, 0.15, config=1)
     sp = mf.Space.from_meshgen(mg.hex_space(mesh, 6, config=1))
     with pytest.raises(mf.MFError, match="nq1d"):
@@ -570,5 +586,3 @@ def test_hex_k_plus_2_points_limits(mf):
     sp2 = mf.Space.from_meshgen(mg.hex_space(mesh, 2, config=1))
     with pytest.raises(mf.MFError, match="nq1d"):
         mf.Operator(sp2, 1, 0, nq1d=5)
-    with pytest.raises(mf.MFError, match="diagonal"):
-        mf.Operator(sp2, 1, 0, nq1d=4).diagonal()

@@ -82,8 +82,6 @@ def test_tet_scalar_errors(mf):
     mesh, space, x, c = _case(3, m=2)
     sp = mf.Space.from_meshgen(space)
     assert mf.Operator(sp, MASS, mf.F64, vertex_coef=c).info["nqp"] == 64
-    with pytest.raises(mf.MFError):
-        mf.Operator(sp, LAP, mf.F64).diagonal()
 
 
 def test_tet_scalar_full_size_sampled(mf):
