@@ -237,9 +237,10 @@ int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out);
 /* Global sparse matrix of the operator, CSR in user numbering (rows and columns are
  * the dofs node * ncomp + component): the paper's matrix assembly (Sun et al.,
  * Section 5: the local kernel's element matrices scattered into a sparse matrix)
- * beside the matrix-free action. Built for tet operators of degree 1-3 (MASS,
- * HELMHOLTZ, LAPLACIAN, POISSON, ELASTICITY; not HYPERELASTIC) and the P1 triangle
- * mass.
+ * beside the matrix-free action. Built for every operator kind but HYPERELASTIC on
+ * tets and triangles of degree 1-3, quadrilaterals of degree 1-6 and hexahedra of
+ * degree 1-4, with the operator's own quadrature rule. `space` must be the space the
+ * operator was created on (MF_EINVAL otherwise); the pattern comes from its cell map.
  * mf_op_csr_pattern: rowptr (host, ndofs + 1 int64, nullable), col (host, nnz int32,
  * nullable; columns sorted in each row) and nnz (nullable). Entry (r, c) is in the
  * pattern when the nodes of dofs r and c share a cell (for ncomp > 1, every component
@@ -248,9 +249,10 @@ int mf_precond_create_jacobi(const mf_op *A, void *stream, mf_precond **out);
  * pattern's order; overwritten) = the element matrices, computed on the device in
  * FP64 and added in the operator's precision; constrained dofs give identity rows and
  * zero columns, as in the action. Synchronous (temporary device buffers).
- * Errors: MF_EUNSUPPORTED for other operators, MF_EINVAL for null arguments. */
-int mf_op_csr_pattern(const mf_op *op, int64_t *rowptr, int32_t *col, int64_t *nnz);
-int mf_op_assemble_csr(const mf_op *op, void *vals, void *stream);
+ * Errors: MF_EUNSUPPORTED outside the built set, MF_EINVAL for null arguments or a
+ * different space. */
+int mf_op_csr_pattern(const mf_op *op, const mf_space *space, int64_t *rowptr, int32_t *col, int64_t *nnz);
+int mf_op_assemble_csr(const mf_op *op, const mf_space *space, void *vals, void *stream);
 
 /* Conjugate gradients for A64 x = b, all vectors FP64 on the device (Hestenes
  * and Stiefel; not in the paper -- the solver that consumes the action).

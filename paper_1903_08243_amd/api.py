@@ -79,8 +79,8 @@ def load_library():
         "mf_space_get_permutation": (I, [P, P]),
         "mf_space_get_colouring": (I, [P, P, P, ctypes.POINTER(ctypes.c_int)]),
         "mf_op_get_info": (I, [P, ctypes.POINTER(_OpInfo)]),
-        "mf_op_csr_pattern": (I, [P, P, P, ctypes.POINTER(I64)]),
-        "mf_op_assemble_csr": (I, [P, P, P]),
+        "mf_op_csr_pattern": (I, [P, P, P, P, ctypes.POINTER(I64)]),
+        "mf_op_assemble_csr": (I, [P, P, P, P]),
         "mf_precond_create_jacobi": (I, [P, P, PP]),
         "mf_cg_solve": (I, [P, P, P, P, P, D, D, I, ctypes.POINTER(CGInfo), P]),
         "mf_cg_solve_noalloc": (I, [P, P, P, P, P, D, D, I, ctypes.POINTER(CGInfo), P]),
@@ -281,12 +281,13 @@ class Operator:
         import torch
         L = load_library()
         nnz = ctypes.c_int64()
-        _check(L.mf_op_csr_pattern(self.handle, None, None, ctypes.byref(nnz)))
+        sh = self.space.handle
+        _check(L.mf_op_csr_pattern(self.handle, sh, None, None, ctypes.byref(nnz)))
         rowptr = np.empty(self.ndofs + 1, np.int64)
         col = np.empty(nnz.value, np.int32)
-        _check(L.mf_op_csr_pattern(self.handle, rowptr.ctypes.data, col.ctypes.data, None))
+        _check(L.mf_op_csr_pattern(self.handle, sh, rowptr.ctypes.data, col.ctypes.data, None))
         vals = torch.empty(max(1, nnz.value), dtype=self.torch_dtype, device="cuda")[:nnz.value]
-        _check(L.mf_op_assemble_csr(self.handle, _dev(vals, self.torch_dtype), _stream(stream)))
+        _check(L.mf_op_assemble_csr(self.handle, sh, _dev(vals, self.torch_dtype), _stream(stream)))
         return rowptr, col, vals
 
     def diagonal(self, stream=None):

@@ -1332,15 +1332,11 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     rc = upload(op->q1map, m2.data(), m2.size() * sizeof(int32_t), s);
     if (rc) return rc;
   }
-  // host data for matrix assembly (operators it is built for)
-  if ((ct == MF_CELL_TET && kind != MF_OP_HYPERELASTIC) || (ct == MF_CELL_TRI && kind == MF_OP_MASS && sp->degree == 1)) {
-    op->h_unode.resize((size_t)nc * D);
-    for (int64_t i = 0; i < nc * D; i++) op->h_unode[i] = sp->user_of_int[c2n[i]];
-    if (pr->dirichlet)
-      for (int64_t u = 0; u < sp->nnodes; u++)
-        if (pr->dirichlet[u])
-          for (int c = 0; c < sp->ncomp; c++) op->h_bc_user.push_back((int32_t)(u * sp->ncomp + c));
-  }
+  // constrained dofs in user numbering (identity rows of the assembled matrix)
+  if (pr->dirichlet)
+    for (int64_t u = 0; u < sp->nnodes; u++)
+      if (pr->dirichlet[u])
+        for (int c = 0; c < sp->ncomp; c++) op->h_bc_user.push_back((int32_t)(u * sp->ncomp + c));
   if (pr->dirichlet) {
     std::vector<int32_t> bd;
     for (int64_t n = 0; n < sp->nnodes; n++)

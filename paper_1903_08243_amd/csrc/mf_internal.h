@@ -341,9 +341,13 @@ int launch_simplex_shared_reduce(const int32_t *sptr, const int32_t *snode, cons
 // [nq][D][3], weights [nq], vertex basis [nq][4]) added into CSR values (user numbering
 // through unode [cell][D]); the closed-form P1 triangle mass likewise.
 template <typename T>
-int launch_tet_element_csr(const int32_t *fmap, const int32_t *unode, const T *geo, const T *coef,
-                           const double *tab, int64_t ncells, int D, int nq, int kind, int ncomp, double lam,
-                           double mu, const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
+int launch_simplex_element_csr(int dim, const int32_t *fmap, const int32_t *unode, const T *geo, const T *coef,
+                               const double *tab, int64_t ncells, int D, int nq, int kind, int ncomp, double lam,
+                               double mu, const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
+template <typename T>
+int launch_tensor_element_csr(int dim, const int32_t *map, const int32_t *unode, const T *geo, const T *coef,
+                              const double *tab, int64_t ncells, int n, int nq, int kind, int ncomp, double lam,
+                              double mu, const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
 template <typename T>
 int launch_tri_mass_element_csr(const int32_t *fmap, const int32_t *unode, const T *geo, int64_t ncells,
                                 const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
@@ -399,7 +403,7 @@ struct mf_op {
   // matrix assembly (tets P1-P3 and the P1 triangle mass): per internal cell the user
   // node of each local node, the constrained user dofs, the quadrature degree of the
   // tet rule, and the CSR pattern once built
-  std::vector<int32_t> h_unode, h_bc_user;
+  std::vector<int32_t> h_bc_user;  // constrained dofs, user numbering
   int qdeg = 0;
   mutable std::vector<int64_t> csr_rowptr;
   mutable std::vector<int32_t> csr_col;

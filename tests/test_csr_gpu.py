@@ -51,20 +51,34 @@ def _tet(k, nc, m=3):
     return mesh, space
 
 
-CASES = [("tet", k, kind, coef) for k in (1, 2, 3)
-         for kind, coef in ((MASS, False), (MASS, True), (HELM, False), (LAP, False), (POIS, True), (ELAS, False))]
+KINDS = ((MASS, False), (MASS, True), (HELM, False), (LAP, False), (POIS, True), (ELAS, False))
+CASES = ([("tet", k, kind, coef) for k in (1, 2, 3) for kind, coef in KINDS]
+         + [("tri", k, kind, coef) for k in (1, 2, 3) for kind, coef in KINDS]
+         + [("quad", k, kind, coef) for k in (1, 2, 4) for kind, coef in KINDS]
+         + [("hex", k, kind, coef) for k in (1, 2, 3) for kind, coef in KINDS])
+
+
+def _space(cell, k, kind):
+    if cell == "tet":
+        return _tet(k, 3 if kind == ELAS else 1)
+    if cell == "tri":
+        mesh = mg.tri_mesh(9, 0.2, config=0)  # 162 cells
+        if k == 1 and kind != ELAS:
+            return mesh, mg.tri_p1_space(mesh, renumber=True)
+        return mesh, mg.tri_space(mesh, k, seed_k=k, ncomp=2 if kind == ELAS else 1)
+    if cell == "quad":
+        mesh = mg.quad_mesh(5, 0.25, config=0)
+        return mesh, mg.quad_space(mesh, k, ncomp=2 if kind == ELAS else 1)
+    mesh = mg.hex_mesh(3, 0.15, config=1, seed_k=k)
+    return mesh, mg.hex_space(mesh, k, ncomp=3 if kind == ELAS else 1, config=1)
 
 
 @pytest.mark.parametrize("dirichlet", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("cell,k,kind,coef", CASES + [("tri", 1, MASS, True)])
+@pytest.mark.parametrize("cell,k,kind,coef", CASES)
 def test_csr_matches_oracle_assembly(mf, cell, k, kind, coef, prec, dirichlet):
     print(f"csr {cell} k={k} kind={kind} coef={coef} prec={prec} dirichlet={dirichlet}", flush=True)
-    if cell == "tet":
-        mesh, space = _tet(k, 3 if kind == ELAS else 1)
-    else:
-        mesh = mg.tri_mesh(12, 0.2, config=0)
-        space = mg.tri_p1_space(mesh, renumber=True)
+    mesh, space = _space(cell, k, kind)
     c = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if coef else None
     mask = None
     bnd = np.zeros(0, np.int64)
@@ -109,8 +123,42 @@ def test_csr_matvec_equals_action(mf, k, kind, nc, prec):
     assert np.abs(ax - y).max() <= 4 * TOL[prec] * np.abs(y).max()
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_csr_matvec_equals_action_hex(mf, prec):
+    """Q2 Helmholtz on 16^3 perturbed hexes with the paper's k+2 points: A x against the
+    matrix-free action (coloured scatter)."""
+    import torch
+    mesh = mg.hex_mesh(16, 0.15, config=1, seed_k=2)
+    space = mg.hex_space(mesh, 2, config=1)
+    op = mf.Operator(mf.Space.from_meshgen(space), HELM, prec, nq1d=4)
+    rowptr, col, vals = op.csr()
+    x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, 2)
+    y = op.apply(torch.tensor(x, device="cuda", dtype=op.torch_dtype)).double().cpu().numpy()
+    v = vals.double().cpu().numpy()
+    rows = np.repeat(np.arange(space.ndofs), np.diff(rowptr))
+    ax = np.bincount(rows, weights=v * x[col], minlength=space.ndofs)
+    assert np.abs(ax - y).max() <= 4 * TOL[prec] * np.abs(y).max()
+
+
 def test_csr_unsupported_operators(mf):
-    mesh = mg.hex_mesh(3, 0.1, config=3)
-    op = mf.Operator(mf.Space.from_meshgen(mg.hex_space(mesh, 2, config=3)), HELM, 0)
+    mesh = mg.hex_mesh(2, 0.1, config=3)
+    op = mf.Operator(mf.Space.from_meshgen(mg.hex_space(mesh, 5, config=3)), HELM, 0)
     with pytest.raises(mf.MFError, match="assembly"):
         op.csr()
+    tm = mg.tet_mesh(2, 0.2, config=2)
+    ts = mg.tet_space(tm, 1, ncomp=3, config=2)
+    u0 = 0.1 * mg.uniform(ts.ndofs, -1, 1, 2, mg.PURPOSE_COEF, 1)
+    with pytest.raises(mf.MFError, match="assembly"):
+        mf.Operator(mf.Space.from_meshgen(ts), mf.HYPERELASTIC, 0, u0=u0).csr()
+
+
+def test_csr_rejects_another_space(mf):
+    import ctypes
+    mesh = mg.tet_mesh(2, 0.2, config=2)
+    space = mg.tet_space(mesh, 1, ncomp=1, config=2)
+    op = mf.Operator(mf.Space.from_meshgen(space), HELM, 0)
+    other = mf.Space.from_meshgen(space)
+    nnz = ctypes.c_int64()
+    L = mf.load_library()
+    assert L.mf_op_csr_pattern(op.handle, other.handle, None, None, ctypes.byref(nnz)) != 0
+    assert "not created on this space" in L.mf_last_error().decode()
