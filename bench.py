@@ -25,6 +25,7 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
 from __future__ import annotations
 
 import argparse
+import itertools
 import json
 import os
 import sys
@@ -254,19 +255,23 @@ def bench_simplex(mf, mg, reps=20):
             del op, xt, yt
         del sp, space
     del tmesh
-    # elasticity on Q2 / Q4 hexahedra (32^3 cells, one workgroup per cell)
+    # elasticity and the hyperelastic tangent (u0 = 0.3 U[-1, 1]) on Q2 / Q4 hexahedra
+    # (32^3 cells, one workgroup per cell)
     hmesh = mg.hex_mesh(32, 0.15, config=1)
     for k in (2, 4):
         space = mg.hex_space(hmesh, k, ncomp=3)
         sp = mf.Space.from_meshgen(space)
         x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
-        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
-            op = mf.Operator(sp, mf.ELASTICITY, prec)
+        u0 = 0.3 * mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_COEF, k)
+        for (prec, ptag), (kind, kname) in itertools.product(((mf.F64, "fp64"), (mf.F32, "fp32")),
+                                                              ((mf.ELASTICITY, "elasticity"),
+                                                               (mf.HYPERELASTIC, "hyperelastic"))):
+            op = mf.Operator(sp, kind, prec, u0=u0 if kind == mf.HYPERELASTIC else None)
             xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
             yt = torch.empty_like(xt)
             t = time_kernel(op, xt, yt, reps)
             r = roof(op, t, prec)
-            tag = f"hex_elasticity_q{k}_{ptag}"
+            tag = f"hex_{kname}_q{k}_{ptag}"
             out[tag] = {"cells": hmesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
                         "launches": op.info["cell_launches"], "qp": op.info["nqp"], "bound": r["bound"],
                         "frac": r["frac"], "gbs": r["gbs"], "tflops": r["tflops"]}

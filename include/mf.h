@@ -73,7 +73,7 @@ enum { MF_CELL_TRI = 0, MF_CELL_TET = 1, MF_CELL_HEX = 2, MF_CELL_QUAD = 3 };
  *               displacement u0 (mf_op_params.u0): int (dF S + F dS) : grad v with
  *               dF = grad u, dE = (dF^T F + F^T dF)/2, dS = lambda tr(dE) I + 2 mu dE.
  *               Vector P1 and P2 tets (quadrature exact for the degree 4(k-1)
- *               integrand). */
+ *               integrand) and Q1-Q6 hexahedra (nq1d k+1 or k+2, at most 7). */
 enum { MF_OP_MASS = 0, MF_OP_HELMHOLTZ = 1, MF_OP_LAPLACIAN = 2, MF_OP_POISSON = 3,
        MF_OP_ELASTICITY = 4, MF_OP_HYPERELASTIC = 5 };
 
@@ -144,7 +144,8 @@ typedef struct {
  * NULL (coefficient 1, lambda 1, mu 0.5, no constraints). stream: device
  * uploads are ordered on it; the call returns after they complete.
  * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1), LAPLACIAN
- * (ncomp 1 or 3) and ELASTICITY (ncomp 3; nq1d k+1 or k+2, at most 7); tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
+ * (ncomp 1 or 3), ELASTICITY and HYPERELASTIC (ncomp 3; nq1d k+1 or k+2, at most 7);
+ * tet ELASTICITY P1-P3 and HYPERELASTIC P1-P2 (ncomp 3); tet MASS and
  * HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules reach degree 7);
  * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1) and ELASTICITY P1-P3
  * (ncomp 2, the 2D stress); quad MASS, HELMHOLTZ,

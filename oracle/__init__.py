@@ -105,7 +105,7 @@ class OracleOp:
         mesh = space.mesh
         self.space, self.kind = space, kind
         if kind in (OP_HYPERELASTIC, OP_HYPER_RESIDUAL):
-            assert mesh.cell_type == CELL_TET and space.ncomp == 3, "hyperelasticity: vector tets"
+            assert mesh.cell_type in (CELL_TET, CELL_HEX) and space.ncomp == 3, "hyperelasticity: vector tets, hexes"
         if kind == OP_HYPERELASTIC:
             assert u0 is not None, "the tangent needs its linearisation point u0"
         self.lam, self.mu = float(lam), float(mu)

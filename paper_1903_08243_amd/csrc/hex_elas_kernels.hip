@@ -1,6 +1,10 @@
 // Linear elasticity on trilinear hexahedra, Q1..Q6 on GLL nodes, three node-interleaved
 // components: int sigma(u) : grad v with sigma = lambda tr(grad u) I + mu (grad u +
-// grad u^T) (the paper's vector operator on the tensor-product cell, Section 4.1).
+// grad u^T) (the paper's vector operator on the tensor-product cell, Section 4.1), and
+// the St-Venant-Kirchhoff tangent at a displacement u0 (supplementary operator list:
+// F = I + grad u0, E = (F^T F - I)/2, S = lambda tr(E) I + 2 mu E; the Gateaux
+// derivative of int F S : grad v in the direction u is int (grad u S + F dS) : grad v
+// with dS = S(dE), dE = (grad u^T F + F^T grad u)/2).
 //
 // The basis is a tensor product, so the action factorises into 1D contractions
 // (Sections 3 and 4.2.4): three passes forward (values and reference gradients of each
@@ -16,13 +20,78 @@ namespace mf {
 namespace {
 __device__ __forceinline__ void hex_el_atomic_add(double *p, double v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void hex_el_atomic_add(float *p, float v) { unsafeAtomicAdd(p, v); }
+
+// Forward passes of one cell: the three components' nodal values in bA [3][n^3] give
+// their reference gradients g[c][d] at this thread's point (t < q^3; zeros elsewhere).
+// Contains workgroup barriers: every thread of the workgroup calls it.
+template <typename T, int N, int NQ>
+__device__ __forceinline__ void hex_el_forward(T *bA, T *bB, const T *sB, const T *sD, const bool act, const int t,
+                                               T (&g)[3][3]) {
+  constexpr int D = N * N * N, SX = NQ * N * N, SY = NQ * NQ * N, P = NQ * NQ * NQ;
+  // x pass, thread (a, j, l): X0 = sum_i B[a][i] U[i, j, l], X1 with B'
+  if (act && t < SX) {
+    const int a = t % NQ, j = (t / NQ) % N, l = t / (NQ * N);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T s0 = T(0), s1 = T(0);
+#pragma unroll
+      for (int i = 0; i < N; i++) {
+        const T u = bA[c * D + i + N * (j + N * l)];
+        s0 += sB[a * N + i] * u;
+        s1 += sD[a * N + i] * u;
+      }
+      bB[c * SX + t] = s0;
+      bB[(3 + c) * SX + t] = s1;
+    }
+  }
+  __syncthreads();
+  // y pass, thread (a, b, l): Y00 = B_y X0, Y01 = B'_y X0, Y10 = B_y X1
+  if (act && t < SY) {
+    const int a = t % NQ, b = (t / NQ) % NQ, l = t / (NQ * NQ);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T y00 = T(0), y01 = T(0), y10 = T(0);
+#pragma unroll
+      for (int j = 0; j < N; j++) {
+        const T x0 = bB[c * SX + a + NQ * (j + N * l)], x1 = bB[(3 + c) * SX + a + NQ * (j + N * l)];
+        y00 += sB[b * N + j] * x0;
+        y01 += sD[b * N + j] * x0;
+        y10 += sB[b * N + j] * x1;
+      }
+      bA[c * SY + t] = y00;
+      bA[(3 + c) * SY + t] = y01;
+      bA[(6 + c) * SY + t] = y10;
+    }
+  }
+  __syncthreads();
+  // z pass, thread = point (a, b, e): g[c][d], reference derivative d of component c
+#pragma unroll
+  for (int c = 0; c < 3; c++) g[c][0] = g[c][1] = g[c][2] = T(0);
+  if (act && t < P) {
+    const int a = t % NQ, b = (t / NQ) % NQ, e = t / (NQ * NQ);
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+      T gx = T(0), gy = T(0), gz = T(0);
+#pragma unroll
+      for (int l = 0; l < N; l++) {
+        const int h = a + NQ * (b + NQ * l);
+        gx += sB[e * N + l] * bA[(6 + c) * SY + h];
+        gy += sB[e * N + l] * bA[(3 + c) * SY + h];
+        gz += sD[e * N + l] * bA[c * SY + h];
+      }
+      g[c][0] = gx;
+      g[c][1] = gy;
+      g[c][2] = gz;
+    }
+  }
+}
 }  // namespace
 
 // N = k + 1 nodes and NQ Gauss points per direction. tab: B[a][i] = l_i(g_a) [NQ][N],
 // B'[a][i], weights [NQ], points [NQ]. geo: [cell][24], coefficient m = 1..7 of the
 // trilinear map x = c0 + c1 xi1 + c2 xi2 + c3 xi3 + c4 xi1 xi2 + c5 xi1 xi3 + c6 xi2 xi3
 // + c7 xi1 xi2 xi3 at 3 (m - 1) + coordinate.
-template <typename T, int N, int NQ>
+template <typename T, int N, int NQ, bool HYPER>
 __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T> A, const bool atomic) {
   constexpr int D = N * N * N, SX = NQ * N * N, SY = NQ * NQ * N, P = NQ * NQ * NQ, H = NQ * N;
   constexpr int CPB = P <= 32 ? 64 / P : 1;  // cells per workgroup (Q1: 8, Q2: 2)
@@ -51,71 +120,30 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
     sw[tid] = A.tab[2 * H + tid];
     sg[tid] = A.tab[2 * H + NQ + tid];
   }
-  int idx = -1;  // node of dof t in y (internal numbering)
-  if (act && t < D) {
-    int gi = -1;  // its position in x
-    if (valid) {
-      idx = A.map[cell * D + t];
-      gi = A.gmap ? A.gmap[cell * D + t] : idx;
-    }
+  int idx = -1, gi = -1, gu = -1;  // node of dof t in y (internal numbering), in x, in u0
+  if (act && t < D && valid) {
+    idx = A.map[cell * D + t];
+    gi = A.gmap ? A.gmap[cell * D + t] : idx;
+    if constexpr (HYPER) gu = A.u0map ? A.u0map[cell * D + t] : idx;
+  }
+  T g0[3][3];  // reference gradient of u0 at this thread's point (HYPER)
+  if constexpr (HYPER) {
+    if (act && t < D)
+#pragma unroll
+      for (int c = 0; c < 3; c++) bufA[slot][c * D + t] = gu >= 0 ? A.u0[(int64_t)gu * 3 + c] : T(0);
+    __syncthreads();
+    hex_el_forward<T, N, NQ>(bufA[slot], bufB[slot], sB, sD, act, t, g0);
+    __syncthreads();  // bufA is loaded again below
+  }
+  if (act && t < D)
 #pragma unroll
     for (int c = 0; c < 3; c++) bufA[slot][c * D + t] = gi >= 0 ? A.x[(int64_t)gi * 3 + c] : T(0);
-  }
   __syncthreads();
-  // x pass, thread (a, j, l): X0 = sum_i B[a][i] U[i, j, l], X1 with B'
-  if (act && t < SX) {
-    const int a = t % NQ, j = (t / NQ) % N, l = t / (NQ * N);
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      T s0 = T(0), s1 = T(0);
-#pragma unroll
-      for (int i = 0; i < N; i++) {
-        const T u = bufA[slot][c * D + i + N * (j + N * l)];
-        s0 += sB[a * N + i] * u;
-        s1 += sD[a * N + i] * u;
-      }
-      bufB[slot][c * SX + t] = s0;
-      bufB[slot][(3 + c) * SX + t] = s1;
-    }
-  }
-  __syncthreads();
-  // y pass, thread (a, b, l): Y00 = B_y X0, Y01 = B'_y X0, Y10 = B_y X1
-  if (act && t < SY) {
-    const int a = t % NQ, b = (t / NQ) % NQ, l = t / (NQ * NQ);
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      T y00 = T(0), y01 = T(0), y10 = T(0);
-#pragma unroll
-      for (int j = 0; j < N; j++) {
-        const T x0 = bufB[slot][c * SX + a + NQ * (j + N * l)], x1 = bufB[slot][(3 + c) * SX + a + NQ * (j + N * l)];
-        y00 += sB[b * N + j] * x0;
-        y01 += sD[b * N + j] * x0;
-        y10 += sB[b * N + j] * x1;
-      }
-      bufA[slot][c * SY + t] = y00;
-      bufA[slot][(3 + c) * SY + t] = y01;
-      bufA[slot][(6 + c) * SY + t] = y10;
-    }
-  }
-  __syncthreads();
-  // z pass and the stress, thread = point (a, b, e)
+  T g[3][3];  // g[c][d]: reference derivative d of component c
+  hex_el_forward<T, N, NQ>(bufA[slot], bufB[slot], sB, sD, act, t, g);
+  // the stress, thread = point (a, b, e)
   if (act && t < P) {
     const int a = t % NQ, b = (t / NQ) % NQ, e = t / (NQ * NQ);
-    T g[3][3];  // g[c][d]: reference derivative d of component c
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-      T gx = T(0), gy = T(0), gz = T(0);
-#pragma unroll
-      for (int l = 0; l < N; l++) {
-        const int h = a + NQ * (b + NQ * l);
-        gx += sB[e * N + l] * bufA[slot][(6 + c) * SY + h];
-        gy += sB[e * N + l] * bufA[slot][(3 + c) * SY + h];
-        gz += sD[e * N + l] * bufA[slot][c * SY + h];
-      }
-      g[c][0] = gx;
-      g[c][1] = gy;
-      g[c][2] = gz;
-    }
     const T x1 = sg[a], x2 = sg[b], x3 = sg[e];
     // with several cells per workgroup a thread without a cell takes the unit cube, so that
     // its discarded arithmetic stays finite; with one, every active thread's cell index is
@@ -151,17 +179,62 @@ __global__ void __launch_bounds__(512) hex_elasticity_kernel(const HexElasArgs<T
     for (int c = 0; c < 3; c++)
 #pragma unroll
       for (int r = 0; r < 3; r++) G[c][r] = (C[r][0] * g[c][0] + C[r][1] * g[c][1] + C[r][2] * g[c][2]) * rd;
-    const T tr = A.lam * (G[0][0] + G[1][1] + G[2][2]);
     const T wdet = sw[a] * sw[b] * sw[e] * (det < T(0) ? -det : det) * rd;
-    // stress S[c][r], then the reference flux F[c][d] = w |det| sum_r K[d][r] S[c][r]
+    // stress Sg[c][r] against d v_c / d x_r, then the reference flux
+    // F[c][d] = w |det| sum_r K[d][r] Sg[c][r]
+    T Sg[3][3];
+    if constexpr (HYPER) {
+      T F[3][3], S[3][3], dS[3][3];
 #pragma unroll
-    for (int c = 0; c < 3; c++) {
-      T S[3];
+      for (int c = 0; c < 3; c++)
 #pragma unroll
-      for (int r = 0; r < 3; r++) S[r] = A.mu * (G[c][r] + G[r][c]) + (r == c ? tr : T(0));
+        for (int r = 0; r < 3; r++)
+          F[c][r] = (c == r ? T(1) : T(0)) + (C[r][0] * g0[c][0] + C[r][1] * g0[c][1] + C[r][2] * g0[c][2]) * rd;
+      T trE = T(0), trdE = T(0);
 #pragma unroll
-      for (int d = 0; d < 3; d++) bufB[slot][(3 * d + c) * P + t] = wdet * (C[0][d] * S[0] + C[1][d] * S[1] + C[2][d] * S[2]);
+      for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+          T ff = T(0), gf = T(0);
+#pragma unroll
+          for (int k = 0; k < 3; k++) {
+            ff += F[k][i] * F[k][j];
+            gf += G[k][i] * F[k][j] + F[k][i] * G[k][j];
+          }
+          const T E = T(0.5) * (ff - (i == j ? T(1) : T(0))), dE = T(0.5) * gf;
+          if (i == j) {
+            trE += E;
+            trdE += dE;
+          }
+          S[i][j] = T(2) * A.mu * E;
+          dS[i][j] = T(2) * A.mu * dE;
+        }
+#pragma unroll
+      for (int i = 0; i < 3; i++) {
+        S[i][i] += A.lam * trE;
+        dS[i][i] += A.lam * trdE;
+      }
+#pragma unroll
+      for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int r = 0; r < 3; r++) {
+          T v = T(0);
+#pragma unroll
+          for (int k = 0; k < 3; k++) v += G[c][k] * S[k][r] + F[c][k] * dS[k][r];
+          Sg[c][r] = v;
+        }
+    } else {
+      const T tr = A.lam * (G[0][0] + G[1][1] + G[2][2]);
+#pragma unroll
+      for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int r = 0; r < 3; r++) Sg[c][r] = A.mu * (G[c][r] + G[r][c]) + (r == c ? tr : T(0));
     }
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+      for (int d = 0; d < 3; d++)
+        bufB[slot][(3 * d + c) * P + t] = wdet * (C[0][d] * Sg[c][0] + C[1][d] * Sg[c][1] + C[2][d] * Sg[c][2]);
   }
   __syncthreads();
   // backward z, thread (a, b, l): Zx = B_z Fx, Zy = B_z Fy, Zz = B'_z Fz
@@ -223,7 +296,10 @@ static int launch_hex_el_nq(const HexElasArgs<T> &a, bool atomic, hipStream_t s)
   constexpr int P = NQ * NQ * NQ, CPB = P <= 32 ? 64 / P : 1;
   const int64_t ngrp = (a.c1 - a.c0 + CPB - 1) / CPB;
   const dim3 g((unsigned)(((ngrp + 7) / 8) * 8)), b((unsigned)(CPB > 1 ? 64 : (P + 63) / 64 * 64));
-  hex_elasticity_kernel<T, N, NQ><<<g, b, 0, s>>>(a, atomic);
+  if (a.u0)
+    hex_elasticity_kernel<T, N, NQ, true><<<g, b, 0, s>>>(a, atomic);
+  else
+    hex_elasticity_kernel<T, N, NQ, false><<<g, b, 0, s>>>(a, atomic);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }

@@ -642,6 +642,17 @@ static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     if (rc) return rc;
   }
+  if (op->kind == MF_OP_HYPERELASTIC) {
+    // linearisation point in internal numbering (every node, constrained ones included);
+    // with constrained nodes the map flags them, so u0 is gathered through an unflagged copy
+    std::vector<T> u0((size_t)sp->nnodes * 3);
+    for (int64_t n = 0; n < sp->nnodes; n++)
+      for (int c = 0; c < 3; c++) u0[n * 3 + c] = (T)pr->u0[(int64_t)sp->user_of_int[n] * 3 + c];
+    rc = upload(op->u0, u0.data(), u0.size() * sizeof(T), s);
+    if (!rc && pr->dirichlet) rc = upload(op->u0map, sp->cell2node_int.data(), sp->cell2node_int.size() * 4, s);
+    if (!rc) MF_HIP(hipStreamSynchronize(s));
+    if (rc) return rc;
+  }
   if (op->patched) return setup_hex_patches<T>(op, sp, m, to_pos2, geo, cf, pr->scatter == MF_SCATTER_PATCH, s);
   if (op->hpatched) {
     std::vector<int32_t> gm;
@@ -986,7 +997,7 @@ static void count_work(mf_op *op) {
   const double nc = (double)op->ncells, nd = (double)op->ndofs;
   const int comps = op->ncomp;
   double fl = 0.0, by = 2.0 * nd * s + 4.0 * op->D * nc;
-  if (op->cell_type == MF_CELL_HEX && op->kind == MF_OP_ELASTICITY) {
+  if (op->cell_type == MF_CELL_HEX && (op->kind == MF_OP_ELASTICITY || op->kind == MF_OP_HYPERELASTIC)) {
     // per component, multiply-adds: x pass 2 q n^3, y pass 3 q^2 n^2, z pass 3 q^3 n and
     // the same backward (n = k+1, q points per direction); per point the Jacobian 36,
     // cofactors and det 50, gradients 54, stress 15, fluxes 54 and the weight 5 flops
@@ -994,6 +1005,13 @@ static void count_work(mf_op *op) {
     const double fma = 3.0 * 2.0 * (2.0 * q * n * n * n + 3.0 * q * q * n * n + 3.0 * q * q * q * n);
     fl = nc * (2.0 * fma + q * q * q * 214.0);
     by += nc * 24.0 * s;
+    if (op->kind == MF_OP_HYPERELASTIC) {
+      // the forward passes again for u0, its push-forward (54) and F = I + grad u0 (3),
+      // F^T F and dE (135), S and dS (30), grad u S + F dS (162) minus the linear stress
+      // (15) per point; u0 read once
+      fl += nc * (fma + q * q * q * 369.0);
+      by += 3.0 * (double)op->nnodes * s;
+    }
   } else if (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) {
     // k+2 points (thread-per-point kernel), per component, multiply-adds: forward x
     // (1 + g) q n^3, y (1 + 2g) q^2 n^2, z (m + 3g) q^3 n, and the same backward
@@ -1089,9 +1107,13 @@ static void count_work(mf_op *op) {
 template <typename T>
 static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y, bool atomic, const int32_t *filt,
                        int64_t ulo, int64_t uhi, hipStream_t s, bool fused = false, bool first = false) {
-  if (op->cell_type == MF_CELL_HEX && op->kind == MF_OP_ELASTICITY) {
+  if (op->cell_type == MF_CELL_HEX && (op->kind == MF_OP_ELASTICITY || op->kind == MF_OP_HYPERELASTIC)) {
     HexElasArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi,
                      (T)op->lam, (T)op->mu, fused ? op->gmap.as<int32_t>() : nullptr};
+    if (op->kind == MF_OP_HYPERELASTIC) {
+      a.u0 = op->u0.as<T>();
+      a.u0map = op->u0map.ptr ? op->u0map.as<int32_t>() : nullptr;
+    }
     return launch_hex_elasticity<T>(op->degree, op->nq1d, a, atomic, s);
   } else if (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) {
     HexQArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(),
@@ -1262,7 +1284,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   bool ok = false;
   if (ct == MF_CELL_HEX)
     ok = (kind == MF_OP_LAPLACIAN) ? (sp->ncomp == 1 || sp->ncomp == 3)
-         : kind == MF_OP_ELASTICITY ? sp->ncomp == 3
+         : (kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC) ? sp->ncomp == 3
                                     : (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else if (ct == MF_CELL_QUAD)
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);
@@ -1293,7 +1315,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   const bool tensor = ct == MF_CELL_HEX || ct == MF_CELL_QUAD;
   op->nq1d = tensor ? (nq1d > 0 ? nq1d : sp->degree + 1) : 0;
   if (ct == MF_CELL_HEX) op->nqp = op->nq1d * op->nq1d * op->nq1d;
-  if (ct == MF_CELL_HEX && kind == MF_OP_ELASTICITY &&
+  if (ct == MF_CELL_HEX && (kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC) &&
       ((op->nq1d != sp->degree + 1 && op->nq1d != sp->degree + 2) || op->nq1d > 7))
     return fail(MF_EUNSUPPORTED, "hex elasticity: nq1d must be k+1 or k+2 (at most 7)");
   if (ct == MF_CELL_QUAD) {
@@ -1361,7 +1383,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   // 5 for k = 5, 6); at 32^3 it beat the coloured and atomic scatters for k <= 4 (FP64
   // vector Laplacian Q2 63 -> 38 us, Q3 84 -> 65 us, Q4 157 -> 138 us) and lost for k = 5, 6
   // (Q5 242 -> 309 us, Q6 390 -> 471 us), where most of a patch's nodes are shared.
-  const bool hex_patchable = ct == MF_CELL_HEX && kind != MF_OP_ELASTICITY && sp->degree >= 2 && sp->degree <= 6 &&
+  const bool hex_patchable = ct == MF_CELL_HEX && kind <= MF_OP_POISSON && sp->degree >= 2 && sp->degree <= 6 &&
                              op->nq1d == sp->degree + 1;
   if (pr->scatter == MF_SCATTER_PATCH && tet_patchable) {
     op->spatched = true;
@@ -1371,16 +1393,16 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
                                (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4))) {
     op->hpatched = true;
   } else if (pr->scatter == MF_SCATTER_PATCH) {
-    if (ct != MF_CELL_HEX || op->degree != 1 || kind == MF_OP_ELASTICITY || op->nq1d != 2)
+    if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)
       return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, tet "
                                    "P2/P3 elasticity and the P1 triangle mass");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
-             kind != MF_OP_ELASTICITY && op->nq1d == 2) {
+             kind <= MF_OP_POISSON && op->nq1d == 2) {
     op->patched = true;
   }
   if (op->patched || op->spatched || op->hpatched) op->coloured = false;
-  if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured && kind != MF_OP_ELASTICITY &&
+  if (ct == MF_CELL_HEX && op->degree >= 2 && op->coloured && kind <= MF_OP_POISSON &&
       op->nq1d == op->degree + 1) {
     // First-touch thresholds for overwrite applies (HexArgs::first). Colours are
     // launched in internal cell order, so a node's first toucher is the first cell in
@@ -1443,7 +1465,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (ct == MF_CELL_HEX) {
     rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, to_pos2, s)
                              : setup_hex<float>(op.get(), sp, pr, m, to_pos2, s);
-    if (!rc && (kind == MF_OP_ELASTICITY || op->nq1d != sp->degree + 1))
+    if (!rc && (kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC || op->nq1d != sp->degree + 1))
       rc = precision == MF_F64 ? upload_tensor_tables<double>(op.get(), s) : upload_tensor_tables<float>(op.get(), s);
   }
   else if (ct == MF_CELL_QUAD)

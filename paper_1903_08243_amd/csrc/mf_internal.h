@@ -241,6 +241,8 @@ template <typename T> struct HexElasArgs {
   int64_t ulo, uhi;
   T lam, mu;
   const int32_t *gmap;  // if set: x is gathered through it (fused permutation), y through map
+  const T *u0 = nullptr;            // HYPERELASTIC: linearisation point, internal numbering
+  const int32_t *u0map = nullptr;   // its map when `map` flags constrained nodes
 };
 template <typename T>
 int launch_hex_elasticity(int k, int nq, const HexElasArgs<T> &a, bool atomic, hipStream_t s);

@@ -113,3 +113,59 @@ def test_tet_hyper_full_size_sampled(mf):
         y, _ = _apply(mf, space, prec, u0, x)
         err = np.abs(y[dofs] - ref[dofs]).max() / np.abs(ref[dofs]).max()
         assert err <= TOL[prec], (prec, err)
+
+
+def _hex_case(k, m=3):
+    mesh = mg.hex_mesh(m, 0.15, config=1, seed_k=k)  # 27 cells: ragged against 64 / q^3 cells per group
+    space = mg.hex_space(mesh, k, ncomp=3, config=1)  # renumbered nodes
+    u0 = 0.3 * mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_COEF, k)
+    x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+    return mesh, space, u0, x
+
+
+@pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k,extra", [(k, 0) for k in range(1, 7)] + [(k, 1) for k in range(1, 6)])
+def test_hex_hyper_action(mf, k, extra, prec, scatter):
+    print(f"hex hyper k={k} q=k+1+{extra} prec={prec} scatter={scatter}", flush=True)
+    mesh, space, u0, x = _hex_case(k)
+    nq = k + 1 + extra
+    ref = oracle.OracleOp(space, oracle.OP_HYPERELASTIC, lam=1.0, mu=0.5, u0=u0, nq1d=nq).apply(x)
+    y, op = _apply(mf, space, prec, u0, x, scatter=scatter, nq1d=nq)
+    assert op.info["nq1d"] == nq
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 3])
+def test_hex_hyper_dirichlet_rows_and_range(mf, k, prec):
+    """Constrained boundary nodes (u0 still enters there, through an unflagged map) and
+    range applies that add up to the full action."""
+    import torch
+    print(f"hex hyper dirichlet k={k} prec={prec}", flush=True)
+    mesh, space, u0, x = _hex_case(k)
+    bnd = space.boundary_nodes()
+    mask = np.zeros(space.nnodes, np.uint8)
+    mask[bnd] = 1
+    xm = x.reshape(-1, 3).copy()
+    xm[bnd] = 0.0
+    orc = oracle.OracleOp(space, oracle.OP_HYPERELASTIC, lam=1.0, mu=0.5, u0=u0)
+    ref = orc.apply(xm.ravel()).reshape(-1, 3)
+    ref[bnd] = x.reshape(-1, 3)[bnd]
+    y, _ = _apply(mf, space, prec, u0, x, dirichlet=mask)
+    assert _relerr(y, ref.ravel()) <= TOL[prec]
+    _, op = _apply(mf, space, prec, u0, x)
+    xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+    yr = torch.zeros_like(xt)
+    for a, b in ((0, 10), (10, mesh.ncells)):
+        op.apply_range(a, b, xt, yr, accumulate=True)
+    assert _relerr(yr.double().cpu().numpy(), orc.apply(x)) <= 4 * TOL[prec]
+
+
+def test_hex_hyper_at_zero_is_elasticity(mf):
+    import torch
+    mesh, space, _, x = _hex_case(2)
+    y, _ = _apply(mf, space, 0, np.zeros(space.ndofs), x)
+    lin = mf.Operator(mf.Space.from_meshgen(space), mf.ELASTICITY, mf.F64, lam=1.0, mu=0.5)
+    ref = lin.apply(torch.tensor(x, device="cuda")).cpu().numpy()
+    assert _relerr(y, ref) <= 1e-12

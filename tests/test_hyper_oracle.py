@@ -1,9 +1,10 @@
 """Pins of the oracle's St-Venant-Kirchhoff operators (supplementary operator list,
-"hyperelasticity"): the tangent at u0 = 0 is linear elasticity, the tangent is the
-derivative of the separately coded nonlinear residual (central differences, exact
-after one Richardson step because the residual is a cubic polynomial along a line),
-the tangent is symmetric (hyperelastic), and the residual vanishes for a rigid
-rotation (E = 0)."""
+"hyperelasticity") on P1/P2 tets and on Q1/Q2 trilinear hexes: the tangent at u0 = 0
+is linear elasticity, the tangent is the derivative of the separately coded nonlinear
+residual (central differences, exact after one Richardson step because the residual
+is a cubic polynomial along a line for any fixed quadrature rule), the tangent is
+symmetric (hyperelastic), and the residual vanishes for a rigid rotation (E = 0; the
+rotation's displacement is linear, hence in the isoparametric space)."""
 import numpy as np
 import pytest
 
@@ -13,17 +14,38 @@ from paper_1903_08243_amd import meshgen as mg
 LAM, MU = 1.0, 0.5
 
 
-def _space(k, m=2, pert=0.2):
+CASES = [("tet", 1), ("tet", 2), ("hex", 1), ("hex", 2)]
+
+
+def _space(cell, k, m=2, pert=0.2):
+    if cell == "hex":
+        mesh = mg.hex_mesh(m, 0.15, config=1, seed_k=k)
+        return mesh, mg.hex_space(mesh, k, ncomp=3, config=1)
     mesh = mg.tet_mesh(m, pert, config=2, seed_k=k)
     return mesh, mg.tet_space(mesh, k, ncomp=3, config=2, seed_k=k)
 
 
+def _gll01(k):
+    """GLL nodes on [0, 1]: the ends and the roots of P_k' (numpy Legendre series)."""
+    inner = np.polynomial.legendre.Legendre.basis(k).deriv().roots() if k > 1 else np.zeros(0)
+    return (np.concatenate([[-1.0], np.sort(inner.real), [1.0]]) + 1.0) / 2.0
+
+
 def _node_coords(mesh, space):
-    """Physical position of every node: the affine image of its reference position."""
+    """Physical position of every node: the image of its reference position under the
+    cell's affine (tet) or trilinear (hex, vertex v at (v&1, v>>1&1, v>>2&1)) map."""
     k = space.degree
-    alpha = mg.simplex_lattice(k, 3) / k  # (D, 3)
-    X = mesh.coords[mesh.cell2vert]  # (ncells, 4, 3)
-    pos = X[:, :1, :] + np.einsum("da,cae->cde", alpha, X[:, 1:, :] - X[:, :1, :])
+    if mesh.cell_type == oracle.CELL_HEX:
+        g = _gll01(k)
+        n = k + 1
+        ref = np.array([[g[i % n], g[(i // n) % n], g[i // (n * n)]] for i in range(n ** 3)])  # (D, 3)
+        bits = np.array([[(v >> d) & 1 for d in range(3)] for v in range(8)])  # (8, 3)
+        Nv = np.prod(np.where(bits[None, :, :] == 1, ref[:, None, :], 1.0 - ref[:, None, :]), axis=2)  # (D, 8)
+        pos = np.einsum("dv,cve->cde", Nv, mesh.coords[mesh.cell2vert])
+    else:
+        alpha = mg.simplex_lattice(k, 3) / k  # (D, 3)
+        X = mesh.coords[mesh.cell2vert]  # (ncells, 4, 3)
+        pos = X[:, :1, :] + np.einsum("da,cae->cde", alpha, X[:, 1:, :] - X[:, :1, :])
     out = np.zeros((space.nnodes, 3))
     out[space.cell2node.ravel()] = pos.reshape(-1, 3)
     return out
@@ -33,9 +55,9 @@ def _field(space, seed, amp):
     return amp * np.random.default_rng(seed).uniform(-1, 1, space.ndofs)
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_tangent_at_zero_is_linear_elasticity(k):
-    mesh, space = _space(k)
+@pytest.mark.parametrize("cell,k", CASES)
+def test_tangent_at_zero_is_linear_elasticity(cell, k):
+    mesh, space = _space(cell, k)
     x = _field(space, 1, 1.0)
     hyp = oracle.OracleOp(space, oracle.OP_HYPERELASTIC, lam=LAM, mu=MU, u0=np.zeros(space.ndofs))
     lin = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=LAM, mu=MU)
@@ -43,9 +65,9 @@ def test_tangent_at_zero_is_linear_elasticity(k):
     assert np.abs(y - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_tangent_is_derivative_of_residual(k):
-    mesh, space = _space(k)
+@pytest.mark.parametrize("cell,k", CASES)
+def test_tangent_is_derivative_of_residual(cell, k):
+    mesh, space = _space(cell, k)
     u0, w = _field(space, 2, 0.3), _field(space, 3, 1.0)
     K = oracle.OracleOp(space, oracle.OP_HYPERELASTIC, lam=LAM, mu=MU, u0=u0)
     R = oracle.OracleOp(space, oracle.OP_HYPER_RESIDUAL, lam=LAM, mu=MU)
@@ -60,9 +82,9 @@ def test_tangent_is_derivative_of_residual(k):
     assert np.abs(d1 - Kw).max() > 1e-8 * scale
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_tangent_is_symmetric(k):
-    mesh, space = _space(k)
+@pytest.mark.parametrize("cell,k", CASES)
+def test_tangent_is_symmetric(cell, k):
+    mesh, space = _space(cell, k)
     u0 = _field(space, 4, 0.3)
     K = oracle.OracleOp(space, oracle.OP_HYPERELASTIC, lam=LAM, mu=MU, u0=u0)
     a, b = _field(space, 5, 1.0), _field(space, 6, 1.0)
@@ -70,9 +92,9 @@ def test_tangent_is_symmetric(k):
     assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_residual_vanishes_for_rigid_rotation(k):
-    mesh, space = _space(k)
+@pytest.mark.parametrize("cell,k", CASES)
+def test_residual_vanishes_for_rigid_rotation(cell, k):
+    mesh, space = _space(cell, k)
     th = 0.7
     c, s = np.cos(th), np.sin(th)
     Rm = np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]]) @ np.array(
