@@ -321,8 +321,8 @@ def bench_simplex(mf, mg, reps=20):
             del op, xt, yt
         del sp, space
     # the paper's hyperelasticity operator: the St-Venant-Kirchhoff tangent at a
-    # displacement u0 = 0.3 U[-1,1], P1 and P2 on the same mesh
-    for k in (1, 2):
+    # displacement u0 = 0.3 U[-1,1], P1-P3 on the same mesh (P3: 125 points per cell)
+    for k in (1, 2, 3):
         space = mg.tet_space(mesh, k, config=2)
         sp = mf.Space.from_meshgen(space)
         x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)

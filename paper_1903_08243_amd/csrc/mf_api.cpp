@@ -783,7 +783,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     deg = (op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ) ? 2 * k : 2 * k - 2;
     if (op->has_coef) deg += 1;
   }
-  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rule table ends at 7)");
+  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rule table ends at 9)");
   op->qdeg = deg;
   const int nq = (int)w.size();
   op->nqp = nq;
@@ -1289,7 +1289,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   else if (ct == MF_CELL_QUAD)
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);
   else if (ct == MF_CELL_TET)
-    ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 2)) && sp->ncomp == 3) ||
+    ok = ((kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC) && sp->ncomp == 3) ||
          (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);

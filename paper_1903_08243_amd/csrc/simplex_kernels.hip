@@ -482,7 +482,9 @@ __device__ __forceinline__ void tet_elas_cells16(
   for (int t = 0; t < NT; t++)
 #pragma unroll
     for (int c = 0; c < 3; c++) yacc[t][c] = V4{T(0), T(0), T(0), T(0)};
-#pragma unroll
+  // point groups: unrolled up to the 14-point rule; the 125-point rule keeps the loop
+  constexpr int RU = NR <= 4 ? NR : 1;
+#pragma unroll RU
   for (int r = 0; r < NR; r++) {
     V4 gacc[3], g0acc[HYPER ? 3 : 1];
 #pragma unroll
@@ -811,8 +813,9 @@ static int launch_tet(int k, int nq, const TetArgs<T> &a, hipStream_t s, bool di
   return fail(MF_EUNSUPPORTED, "tet elasticity: degree / rule");
 }
 
-// St-Venant-Kirchhoff tangent: the MFMA kernel with HYPER for P1 (one point) and P2
-// (14 points, exact for the degree 4 integrand); one wavefront per workgroup.
+// St-Venant-Kirchhoff tangent: the MFMA kernel with HYPER for P1 (one point), P2
+// (14 points, exact for the degree 4 integrand) and P3 (the 125-point conical rule,
+// exact to degree 9, for the degree 8 integrand); one wavefront per workgroup.
 template <typename T, int K, int NQ>
 static int launch_tet_hyper_kq(const TetArgs<T> &a, bool atomic, hipStream_t s) {
   const int64_t b0 = a.c0 / 64, b1 = (a.c1 + 63) / 64;
@@ -828,6 +831,7 @@ template <typename T> int launch_tet_elasticity(int k, int nq, const TetArgs<T> 
   if (a.u0) {
     if (k == 1 && nq == 1) return launch_tet_hyper_kq<T, 1, 1>(a, atomic, s);
     if (k == 2 && nq == 14) return launch_tet_hyper_kq<T, 2, 14>(a, atomic, s);
+    if (k == 3 && nq == 125) return launch_tet_hyper_kq<T, 3, 125>(a, atomic, s);
     return fail(MF_EUNSUPPORTED, "tet hyperelasticity: degree / rule");
   }
   return launch_tet<T>(k, nq, a, s, false, atomic);

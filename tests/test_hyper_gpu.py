@@ -41,18 +41,18 @@ def _apply(mf, space, prec, u0, x, **kw):
 
 @pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_tet_hyper_action(mf, k, prec, scatter):
     print(f"tet hyper k={k} prec={prec} scatter={scatter}", flush=True)
     mesh, space, u0, x = _case(k)
     ref = oracle.OracleOp(space, oracle.OP_HYPERELASTIC, lam=1.0, mu=0.5, u0=u0).apply(x)
     y, op = _apply(mf, space, prec, u0, x, scatter=scatter)
-    assert op.info["nqp"] == (1 if k == 1 else 14)
+    assert op.info["nqp"] == {1: 1, 2: 14, 3: 125}[k]
     assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_tet_hyper_dirichlet_rows(mf, k, prec):
     """Constrained boundary nodes: identity rows, zero columns; u0 still enters at
     the constrained nodes (it is a coefficient, gathered through an unflagged map)."""
@@ -69,7 +69,7 @@ def test_tet_hyper_dirichlet_rows(mf, k, prec):
     assert _relerr(y, ref.ravel()) <= TOL[prec]
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_tet_hyper_at_zero_is_elasticity(mf, k):
     """At u0 = 0 the tangent is the linear elasticity operator (other quadrature rule,
     both exact)."""
@@ -90,9 +90,6 @@ def test_tet_hyper_errors(mf):
     op = mf.Operator(sp, mf.HYPERELASTIC, mf.F64, u0=u0)
     with pytest.raises(mf.MFError):
         op.diagonal()
-    space3 = mg.tet_space(mesh, 3, ncomp=3, config=2)
-    with pytest.raises(mf.MFError):
-        mf.Operator(mf.Space.from_meshgen(space3), mf.HYPERELASTIC, mf.F64, u0=np.zeros(space3.ndofs))
 
 
 def test_tet_hyper_full_size_sampled(mf):
