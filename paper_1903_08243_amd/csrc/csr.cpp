@@ -10,14 +10,14 @@
 namespace mf {
 
 static const char *kCsrScope =
-    "assembly is built for tet and triangle operators of degree 1-3, quadrilaterals of degree 1-6 and hexahedra of "
+    "assembly is built for tet and triangle operators of degree 1-6, quadrilaterals of degree 1-6 and hexahedra of "
     "degree 1-4 (not HYPERELASTIC)";
 
 static bool csr_supported(const mf_op *op) {
   if (op->kind == MF_OP_HYPERELASTIC) return false;
   switch (op->cell_type) {
     case MF_CELL_TET:
-    case MF_CELL_TRI: return op->degree <= 3;
+    case MF_CELL_TRI: return op->degree <= 6;
     case MF_CELL_QUAD: return op->degree <= 6;
     case MF_CELL_HEX: return op->degree <= 4;
   }

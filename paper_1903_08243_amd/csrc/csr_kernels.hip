@@ -62,7 +62,7 @@ __device__ __forceinline__ void add_block(int kind, int nc, int64_t ui, int64_t 
 }
 }  // namespace
 
-constexpr int kMaxD = 20;  // P3 tets
+constexpr int kMaxD = 84;  // P6 tets
 
 // Simplices: AoSoA map [cell/64][D][64], geometry [cell/64][DIM*DIM + 1][64] (d xi_b /
 // d x_a at b*DIM + a, then |det J|), vertex coefficients [cell/64][DIM+1][64]; tab
@@ -243,7 +243,7 @@ template <typename T>
 int launch_simplex_element_csr(int dim, const int32_t *fmap, const int32_t *unode, const T *geo, const T *coef,
                                const double *tab, int64_t ncells, int D, int nq, int kind, int ncomp, double lam,
                                double mu, const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s) {
-  if (D > kMaxD) return fail(MF_EUNSUPPORTED, "assembly: simplices up to P3");
+  if (D > kMaxD) return fail(MF_EUNSUPPORTED, "assembly: simplices up to P6");
   const int64_t n = ncells * D;
   if (n == 0) return MF_OK;
   const dim3 g((unsigned)((n + 255) / 256)), b(256);

@@ -9,7 +9,7 @@ namespace mf {
 
 bool element_diag_supported(const mf_op *op) {
   if (op->kind == MF_OP_HYPERELASTIC) return false;
-  if (op->cell_type == MF_CELL_TET) return op->ncomp == 1;
+  if (op->cell_type == MF_CELL_TET) return op->ncomp == 1 || op->degree >= 4;
   if (op->cell_type == MF_CELL_TRI) return !(op->kind == MF_OP_MASS && op->degree == 1);
   if (op->cell_type == MF_CELL_HEX) return op->kind == MF_OP_ELASTICITY || op->nq1d != op->degree + 1;
   return false;

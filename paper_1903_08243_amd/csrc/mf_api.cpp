@@ -228,10 +228,10 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
     if (degree < 1 || degree > 6) return fail(MF_EUNSUPPORTED, "quad spaces support degree 1..6");
     D = (degree + 1) * (degree + 1);
   } else if (mesh->cell_type == MF_CELL_TET) {
-    if (degree < 1 || degree > 3) return fail(MF_EUNSUPPORTED, "tet spaces support degree 1..3");
+    if (degree < 1 || degree > 6) return fail(MF_EUNSUPPORTED, "tet spaces support degree 1..6");
     D = tet_ndofs(degree);
   } else {
-    if (degree < 1 || degree > 3) return fail(MF_EUNSUPPORTED, "tri spaces support degree 1..3");
+    if (degree < 1 || degree > 6) return fail(MF_EUNSUPPORTED, "tri spaces support degree 1..6");
     D = (degree + 1) * (degree + 2) / 2;
   }
   for (int64_t i = 0; i < mesh->ncells * D; i++)
@@ -768,6 +768,36 @@ static int setup_simplex_patches(mf_op *op, const mf_space *sp, const std::vecto
   return rc;
 }
 
+// Tables of the dense simplex kernel (degrees 4-6), SimplexDenseArgs::tab: values and
+// reference gradients transposed ([node][point], [dim][node][point]) for the forward
+// contraction, then as [point][node], [point][dim][node] for the test side, the
+// weights and the vertex basis at the points
+template <typename T>
+static std::vector<T> dense_simplex_tables(int dim, const std::vector<double> &pts, const std::vector<double> &w,
+                                           const std::vector<double> &phi, const std::vector<double> &dphi) {
+  const int nq = (int)w.size(), D = (int)(phi.size() / w.size());
+  std::vector<T> tab;
+  tab.reserve((size_t)2 * nq * D * (1 + dim) + nq * (2 + dim));
+  for (int i = 0; i < D; i++)
+    for (int q = 0; q < nq; q++) tab.push_back((T)phi[(size_t)q * D + i]);
+  for (int d = 0; d < dim; d++)
+    for (int i = 0; i < D; i++)
+      for (int q = 0; q < nq; q++) tab.push_back((T)dphi[((size_t)q * D + i) * dim + d]);
+  for (int q = 0; q < nq; q++)
+    for (int i = 0; i < D; i++) tab.push_back((T)phi[(size_t)q * D + i]);
+  for (int q = 0; q < nq; q++)
+    for (int d = 0; d < dim; d++)
+      for (int i = 0; i < D; i++) tab.push_back((T)dphi[((size_t)q * D + i) * dim + d]);
+  for (int q = 0; q < nq; q++) tab.push_back((T)w[q]);
+  for (int q = 0; q < nq; q++) {
+    double s0 = 1.0;
+    for (int a = 0; a < dim; a++) s0 -= pts[(size_t)q * dim + a];
+    tab.push_back((T)s0);
+    for (int a = 0; a < dim; a++) tab.push_back((T)pts[(size_t)q * dim + a]);
+  }
+  return tab;
+}
+
 template <typename T>
 static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
                      hipStream_t s) {
@@ -789,7 +819,10 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   op->nqp = nq;
   tet_lagrange(k, pts, phi, dphi);
   std::vector<T> tab;
-  if (scalar) {
+  if (k >= 4) {
+    tab = dense_simplex_tables<T>(3, pts, w, phi, dphi);
+    op->dense_cb = simplex_dense_cells_per_block<T>(D, nq, sp->ncomp, 3);
+  } else if (scalar) {
     // phi [nq][D], reference gradients [nq][D][3], weights [nq], vertex basis [nq][4]
     for (double v : phi) tab.push_back((T)v);
     for (double v : dphi) tab.push_back((T)v);
@@ -803,7 +836,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     for (double v : dphi) tab.push_back((T)v);
     for (double v : w) tab.push_back((T)v);
   }
-  if (!scalar && (k >= 2 || hyper)) {
+  if (!scalar && k <= 3 && (k >= 2 || hyper)) {
     // per-lane operands of the MFMA contractions, appended after the weights (the
     // hyperelastic tangent runs the MFMA kernel at every degree)
     std::vector<double> mt((size_t)tet_mfma_table_floats(k, nq));
@@ -893,13 +926,18 @@ template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, con
   const int nq = (int)w.size();
   op->nqp = nq;
   std::vector<T> tab;
-  for (double v : phi) tab.push_back((T)v);
-  for (double v : dphi) tab.push_back((T)v);
-  for (double v : w) tab.push_back((T)v);
-  for (int q = 0; q < nq; q++) {
-    tab.push_back((T)(1.0 - pts[2 * q] - pts[2 * q + 1]));
-    tab.push_back((T)pts[2 * q]);
-    tab.push_back((T)pts[2 * q + 1]);
+  if (k >= 4) {
+    tab = dense_simplex_tables<T>(2, pts, w, phi, dphi);
+    op->dense_cb = simplex_dense_cells_per_block<T>(sp->D, nq, sp->ncomp, 2);
+  } else {
+    for (double v : phi) tab.push_back((T)v);
+    for (double v : dphi) tab.push_back((T)v);
+    for (double v : w) tab.push_back((T)v);
+    for (int q = 0; q < nq; q++) {
+      tab.push_back((T)(1.0 - pts[2 * q] - pts[2 * q + 1]));
+      tab.push_back((T)pts[2 * q]);
+      tab.push_back((T)pts[2 * q + 1]);
+    }
   }
   int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
   if (rc) return rc;
@@ -1060,6 +1098,13 @@ static void count_work(mf_op *op) {
                       (op->kind == MF_OP_ELASTICITY ? 10.0 : 0.0);
     fl = nc * (2.0 * fma + q * q * pt);
     by += nc * 6.0 * s + (op->has_coef ? nc * 4.0 * s : 0.0);
+  } else if ((op->cell_type == MF_CELL_TET || op->cell_type == MF_CELL_TRI) && op->degree >= 4) {
+    // dense kernel, per point and component: values and reference gradients 2 (1 + dim) D
+    // forward and the same backward, push-forward and pull-back 4 dim^2, the pointwise
+    // stress 4 dim (elasticity) and the weight; bytes: geometry dim^2 + 1 per cell
+    const double D = op->D, Q = op->nqp, dim = op->cell_type == MF_CELL_TET ? 3.0 : 2.0;
+    fl = nc * Q * comps * (4.0 * (1.0 + dim) * D + 4.0 * dim * dim + 4.0 * dim + 4.0);
+    by += nc * (dim * dim + 1.0) * s + (op->has_coef ? nc * (dim + 1.0) * s : 0.0);
   } else if (op->cell_type == MF_CELL_TET && op->ncomp == 1) {
     // scalar operators, dense tabulation, per point: value 2D and its test sum 2D;
     // reference gradient 6D, push-forward 18, the reference-direction flux 18 (and a
@@ -1132,6 +1177,11 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     QuadArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
                   op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, (T)op->lam, (T)op->mu};
     return launch_quad<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
+  } else if ((op->cell_type == MF_CELL_TET || op->cell_type == MF_CELL_TRI) && op->degree >= 4) {
+    SimplexDenseArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
+                          op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, op->D, op->nqp, op->ncomp, op->kind,
+                          op->dense_cb, (T)op->lam, (T)op->mu};
+    return launch_simplex_dense<T>(op->cell_type == MF_CELL_TET ? 3 : 2, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
                  filt, ulo, uhi, op->u0.as<T>(), op->u0map.as<int32_t>(),
@@ -1289,7 +1339,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   else if (ct == MF_CELL_QUAD)
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);
   else if (ct == MF_CELL_TET)
-    ok = ((kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC) && sp->ncomp == 3) ||
+    ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 3)) && sp->ncomp == 3) ||
          (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);

@@ -353,6 +353,22 @@ int launch_tensor_element_csr(int dim, const int32_t *map, const int32_t *unode,
 template <typename T>
 int launch_tri_mass_element_csr(const int32_t *fmap, const int32_t *unode, const T *geo, int64_t ncells,
                                 const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
+// simplices of degree 4-6 by dense tabulation (simplex_dense_kernels.hip)
+template <typename T> struct SimplexDenseArgs {
+  const int32_t *map;  // [cell/64][D][64] internal node ids (negative: constrained)
+  const T *geo;        // [cell/64][dim*dim + 1][64]: d xi_b / d x_a at b*dim + a, |det J|
+  const T *coef;       // [cell/64][dim + 1][64] vertex coefficients, or null
+  const T *tab;        // vT [D][nq], gT [dim][D][nq], v [nq][D], g [nq][dim][D], w [nq], vb [nq][dim+1]
+  const T *x;
+  T *y;
+  int64_t c0, c1;
+  const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
+  int64_t ulo, uhi;
+  int D, nq, ncomp, kind, cb;
+  T lam, mu;
+};
+template <typename T> int simplex_dense_cells_per_block(int D, int nq, int ncomp, int dim);
+template <typename T> int launch_simplex_dense(int dim, const SimplexDenseArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_simplex_element_diag(int dim, const int32_t *fmap, const T *geo, const T *coef, const double *tab,
                                 int64_t ncells, int D, int nq, int kind, int nc, double lam, double mu, T *d,
@@ -407,6 +423,7 @@ struct mf_op {
   // tet rule, and the CSR pattern once built
   std::vector<int32_t> h_bc_user;  // constrained dofs, user numbering
   int qdeg = 0;
+  int dense_cb = 0;  // cells per workgroup of the dense simplex kernel (degrees 4-6)
   mutable std::vector<int64_t> csr_rowptr;
   mutable std::vector<int32_t> csr_col;
   mutable bool csr_built = false;

@@ -204,14 +204,14 @@ bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
     s31(0.0927352503108912, 0.0734930431163619 / 6.0);
     s31(0.3108859192633006, 0.1126879257180159 / 6.0);
     s22(0.0455037041256496, 0.0425460207770812 / 6.0);
-  } else if (degree <= 9) {
+  } else if (degree <= 13) {
     // conical product rule: x = u, y = v (1 - u), z = t (1 - u)(1 - v), Jacobian
     // (1 - u)^2 (1 - v). A degree-p monomial has degree at most p in each of u, v, t, so
     // Gauss-Jacobi rules for the weights (1 - u)^2 and (1 - v), which absorb the
     // Jacobian, and Gauss-Legendre in t, each with n points (exact to degree 2n - 1),
-    // integrate it exactly: n = 4 (64 points) for degrees 6-7, n = 5 (125 points) for
-    // degrees 8-9
-    const int n = degree <= 7 ? 4 : 5;
+    // integrate it exactly: n = (degree + 2) / 2, 64 points for degrees 6-7 up to 343
+    // for degrees 12-13
+    const int n = (degree + 2) / 2;
     std::vector<double> xu, wu, xv, wv, xt, wt;
     gauss_jacobi01(n, 2, xu, wu);
     gauss_jacobi01(n, 1, xv, wv);
@@ -231,66 +231,67 @@ bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
   return true;
 }
 
-// P_k Lagrange basis on the reference tet by inverting the monomial
-// Vandermonde matrix at the equispaced lattice points.
-void tet_lagrange(int k, const std::vector<double> &pts, std::vector<double> &phi,
-                  std::vector<double> &dphi) {
-  const int D = tet_ndofs(k);
-  std::vector<int> ex;  // monomial exponents (p,q,r)
-  for (int p = 0; p <= k; p++)
-    for (int q = 0; q + p <= k; q++)
-      for (int r = 0; r + q + p <= k; r++) { ex.push_back(p); ex.push_back(q); ex.push_back(r); }
-  std::vector<double> nodes;  // lattice in the library's local order: a1 fastest, a3 slowest
-  for (int a3 = 0; a3 <= k; a3++)
-    for (int a2 = 0; a2 + a3 <= k; a2++)
-      for (int a1 = 0; a1 + a2 + a3 <= k; a1++) {
-        nodes.push_back((double)a1 / k);
-        nodes.push_back((double)a2 / k);
-        nodes.push_back((double)a3 / k);
-      }
-  // Vandermonde V[n][m] = monomial m at node n; coefficients C = V^{-1} (column i -> phi_i)
-  std::vector<double> A((size_t)D * 2 * D, 0.0);
-  for (int n = 0; n < D; n++) {
-    for (int m = 0; m < D; m++)
-      A[n * 2 * D + m] = std::pow(nodes[3 * n], ex[3 * m]) * std::pow(nodes[3 * n + 1], ex[3 * m + 1]) *
-                         std::pow(nodes[3 * n + 2], ex[3 * m + 2]);
-    A[n * 2 * D + D + n] = 1.0;
+// Equispaced P_k Lagrange basis on the reference simplex of dimension dim, in the
+// library's local node order (lattice a1 fastest), from the barycentric product form:
+// the node with lattice index a (alpha_0 = k - sum a, alpha_j = a_j) has
+//   phi_a(x) = prod_j P_{alpha_j}(lambda_j),  P_m(l) = prod_{r<m} (k l - r) / (r + 1),
+// with lambda_0 = 1 - sum x, lambda_j = x_j. It is 1 at its node and 0 at the others
+// (one factor vanishes there), and needs no linear solve. pts: [nq][dim].
+static void simplex_lagrange(int k, int dim, const std::vector<double> &pts, std::vector<double> &phi,
+                             std::vector<double> &dphi) {
+  std::vector<int> al;  // barycentric multi-indices, dim + 1 per node
+  if (dim == 3) {
+    for (int a3 = 0; a3 <= k; a3++)
+      for (int a2 = 0; a2 + a3 <= k; a2++)
+        for (int a1 = 0; a1 + a2 + a3 <= k; a1++) al.insert(al.end(), {k - a1 - a2 - a3, a1, a2, a3});
+  } else {
+    for (int a2 = 0; a2 <= k; a2++)
+      for (int a1 = 0; a1 + a2 <= k; a1++) al.insert(al.end(), {k - a1 - a2, a1, a2});
   }
-  for (int c = 0; c < D; c++) {  // Gauss-Jordan with partial pivoting
-    int piv = c;
-    for (int r = c + 1; r < D; r++)
-      if (std::fabs(A[r * 2 * D + c]) > std::fabs(A[piv * 2 * D + c])) piv = r;
-    for (int j = 0; j < 2 * D; j++) std::swap(A[c * 2 * D + j], A[piv * 2 * D + j]);
-    double d = A[c * 2 * D + c];
-    for (int j = 0; j < 2 * D; j++) A[c * 2 * D + j] /= d;
-    for (int r = 0; r < D; r++)
-      if (r != c) {
-        double f = A[r * 2 * D + c];
-        for (int j = 0; j < 2 * D; j++) A[r * 2 * D + j] -= f * A[c * 2 * D + j];
-      }
-  }
-  // inverse: Vinv[m][n] = A[m][D+n]; phi_i(x) = sum_m Vinv[m][i] mono_m(x)
-  const int nq = (int)pts.size() / 3;
+  const int nb = dim + 1, D = (int)al.size() / nb, nq = (int)pts.size() / dim;
+  // P_m(l) and its derivative for m = 0..k
+  auto pm = [k](int m, double l, double &v, double &dv) {
+    v = 1.0;
+    dv = 0.0;
+    for (int r = 0; r < m; r++) {
+      const double f = (k * l - r) / (r + 1.0), df = k / (r + 1.0);
+      dv = dv * f + v * df;
+      v *= f;
+    }
+  };
   phi.assign((size_t)nq * D, 0.0);
-  dphi.assign((size_t)nq * D * 3, 0.0);
-  auto pw = [](double b, int e) { return e <= 0 ? 1.0 : std::pow(b, e); };
+  dphi.assign((size_t)nq * D * dim, 0.0);
   for (int q = 0; q < nq; q++) {
-    const double x = pts[3 * q], y = pts[3 * q + 1], z = pts[3 * q + 2];
-    for (int m = 0; m < D; m++) {
-      const int p = ex[3 * m], r1 = ex[3 * m + 1], r2 = ex[3 * m + 2];
-      const double val = pw(x, p) * pw(y, r1) * pw(z, r2);
-      const double dx = p ? p * pw(x, p - 1) * pw(y, r1) * pw(z, r2) : 0.0;
-      const double dy = r1 ? r1 * pw(x, p) * pw(y, r1 - 1) * pw(z, r2) : 0.0;
-      const double dz = r2 ? r2 * pw(x, p) * pw(y, r1) * pw(z, r2 - 1) : 0.0;
-      for (int i = 0; i < D; i++) {
-        const double c = A[m * 2 * D + D + i];
-        phi[q * D + i] += c * val;
-        dphi[(q * D + i) * 3 + 0] += c * dx;
-        dphi[(q * D + i) * 3 + 1] += c * dy;
-        dphi[(q * D + i) * 3 + 2] += c * dz;
+    double lam[4];
+    lam[0] = 1.0;
+    for (int d = 0; d < dim; d++) {
+      lam[d + 1] = pts[q * dim + d];
+      lam[0] -= lam[d + 1];
+    }
+    for (int i = 0; i < D; i++) {
+      double v[4], dv[4];
+      for (int j = 0; j < nb; j++) pm(al[i * nb + j], lam[j], v[j], dv[j]);
+      double val = 1.0;
+      for (int j = 0; j < nb; j++) val *= v[j];
+      phi[(size_t)q * D + i] = val;
+      // d lambda_0 / d x_d = -1, d lambda_j / d x_d = [j = d + 1]
+      for (int d = 0; d < dim; d++) {
+        double g0 = dv[0], gd = dv[d + 1];
+        for (int j = 0; j < nb; j++) {
+          if (j != 0) g0 *= v[j];
+          if (j != d + 1) gd *= v[j];
+        }
+        dphi[((size_t)q * D + i) * dim + d] = gd - g0;
       }
     }
   }
+}
+
+// P_k Lagrange basis (equispaced nodes) on the reference tet at pts [nq][3]:
+// phi [nq][D], dphi [nq][D][3].
+void tet_lagrange(int k, const std::vector<double> &pts, std::vector<double> &phi,
+                  std::vector<double> &dphi) {
+  simplex_lagrange(k, 3, pts, phi, dphi);
 }
 
 // Triangle rule exact to the given degree: the Gauss product rule on the square mapped
@@ -310,56 +311,10 @@ void tri_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
     }
 }
 
-// P_k Lagrange basis on the reference triangle (equispaced lattice, a1 fastest) by
-// inverting the monomial Vandermonde matrix, as tet_lagrange in two dimensions.
+// P_k Lagrange basis (equispaced nodes, a1 fastest) on the reference triangle at pts
+// [nq][2]: phi [nq][D], dphi [nq][D][2] (the barycentric product form above).
 void tri_lagrange(int k, const std::vector<double> &pts, std::vector<double> &phi, std::vector<double> &dphi) {
-  const int D = (k + 1) * (k + 2) / 2;
-  std::vector<int> ex;  // monomial exponents (p, q)
-  for (int p = 0; p <= k; p++)
-    for (int q = 0; q + p <= k; q++) { ex.push_back(p); ex.push_back(q); }
-  std::vector<double> nodes;
-  for (int a2 = 0; a2 <= k; a2++)
-    for (int a1 = 0; a1 + a2 <= k; a1++) {
-      nodes.push_back((double)a1 / k);
-      nodes.push_back((double)a2 / k);
-    }
-  auto pw = [](double b, int e) { return e <= 0 ? 1.0 : std::pow(b, e); };
-  std::vector<double> A((size_t)D * 2 * D, 0.0);
-  for (int n = 0; n < D; n++) {
-    for (int m = 0; m < D; m++) A[n * 2 * D + m] = pw(nodes[2 * n], ex[2 * m]) * pw(nodes[2 * n + 1], ex[2 * m + 1]);
-    A[n * 2 * D + D + n] = 1.0;
-  }
-  for (int c = 0; c < D; c++) {  // Gauss-Jordan with partial pivoting
-    int piv = c;
-    for (int r = c + 1; r < D; r++)
-      if (std::fabs(A[r * 2 * D + c]) > std::fabs(A[piv * 2 * D + c])) piv = r;
-    for (int j = 0; j < 2 * D; j++) std::swap(A[c * 2 * D + j], A[piv * 2 * D + j]);
-    const double d = A[c * 2 * D + c];
-    for (int j = 0; j < 2 * D; j++) A[c * 2 * D + j] /= d;
-    for (int r = 0; r < D; r++)
-      if (r != c) {
-        const double f = A[r * 2 * D + c];
-        for (int j = 0; j < 2 * D; j++) A[r * 2 * D + j] -= f * A[c * 2 * D + j];
-      }
-  }
-  const int nq = (int)pts.size() / 2;
-  phi.assign((size_t)nq * D, 0.0);
-  dphi.assign((size_t)nq * D * 2, 0.0);
-  for (int q = 0; q < nq; q++) {
-    const double x = pts[2 * q], y = pts[2 * q + 1];
-    for (int m = 0; m < D; m++) {
-      const int p = ex[2 * m], r = ex[2 * m + 1];
-      const double val = pw(x, p) * pw(y, r);
-      const double dx = p ? p * pw(x, p - 1) * pw(y, r) : 0.0;
-      const double dy = r ? r * pw(x, p) * pw(y, r - 1) : 0.0;
-      for (int i = 0; i < D; i++) {
-        const double c = A[m * 2 * D + D + i];
-        phi[q * D + i] += c * val;
-        dphi[(q * D + i) * 2 + 0] += c * dx;
-        dphi[(q * D + i) * 2 + 1] += c * dy;
-      }
-    }
-  }
+  simplex_lagrange(k, 2, pts, phi, dphi);
 }
 
 }  // namespace mf

@@ -105,7 +105,7 @@ def _case(cell, k):
 
 
 CASES = [("hex", k) for k in range(1, 7)] + [("quad", k) for k in range(1, 7)] + \
-        [("tet", k) for k in (1, 2, 3)] + [("tri", k) for k in (1, 2, 3)]
+        [("tet", k) for k in range(1, 7)] + [("tri", k) for k in range(1, 7)]
 
 
 @pytest.mark.parametrize("cell,k", CASES)
