@@ -72,9 +72,10 @@ enum { MF_CELL_TRI = 0, MF_CELL_TET = 1, MF_CELL_HEX = 2, MF_CELL_QUAD = 3 };
  *               E = (F^T F - I)/2, S = lambda tr(E) I + 2 mu E, linearised at a given
  *               displacement u0 (mf_op_params.u0): int (dF S + F dS) : grad v with
  *               dF = grad u, dE = (dF^T F + F^T dF)/2, dS = lambda tr(dE) I + 2 mu dE.
- *               Vector P1-P3 tets (quadrature exact for the degree 4(k-1)
- *               integrand: 1, 14 and 125 points) and Q1-Q6 hexahedra (nq1d k+1 or
- *               k+2, at most 7). */
+ *               Vector P1-P6 tets (quadrature exact for the degree 4(k-1)
+ *               integrand: 1, 14 and 125 points for P1-P3, conical rules of up to
+ *               1331 points for P4-P6) and Q1-Q6 hexahedra (nq1d k+1 or k+2, at
+ *               most 7). */
 enum { MF_OP_MASS = 0, MF_OP_HELMHOLTZ = 1, MF_OP_LAPLACIAN = 2, MF_OP_POISSON = 3,
        MF_OP_ELASTICITY = 4, MF_OP_HYPERELASTIC = 5 };
 
@@ -146,10 +147,11 @@ typedef struct {
  * uploads are ordered on it; the call returns after they complete.
  * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1), LAPLACIAN
  * (ncomp 1 or 3), ELASTICITY and HYPERELASTIC (ncomp 3; nq1d k+1 or k+2, at most 7);
- * tet ELASTICITY and HYPERELASTIC P1-P3 (ncomp 3); tet MASS and
- * HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1; the tet rules reach degree 9);
- * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P3 (ncomp 1) and ELASTICITY P1-P3
- * (ncomp 2, the 2D stress); quad MASS, HELMHOLTZ,
+ * tet ELASTICITY and HYPERELASTIC P1-P6 (ncomp 3); tet MASS and
+ * HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1; the tet rules reach degree 21);
+ * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1) and ELASTICITY P1-P6
+ * (ncomp 2, the 2D stress); degrees 4-6 on simplices run a dense-tabulation kernel
+ * (a thread per point, then a thread per node); quad MASS, HELMHOLTZ,
  * LAPLACIAN and POISSON Q1-Q6 (ncomp 1) and ELASTICITY Q1-Q6 (ncomp 2, the 2D stress).
  * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
 int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,

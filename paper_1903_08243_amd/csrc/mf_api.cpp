@@ -813,7 +813,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     deg = (op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ) ? 2 * k : 2 * k - 2;
     if (op->has_coef) deg += 1;
   }
-  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rule table ends at 9)");
+  if (!tet_rule(deg, pts, w)) return fail(MF_EUNSUPPORTED, "tet quadrature degree (the rules end at 21)");
   op->qdeg = deg;
   const int nq = (int)w.size();
   op->nqp = nq;
@@ -821,7 +821,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   std::vector<T> tab;
   if (k >= 4) {
     tab = dense_simplex_tables<T>(3, pts, w, phi, dphi);
-    op->dense_cb = simplex_dense_cells_per_block<T>(D, nq, sp->ncomp, 3);
+    simplex_dense_shape<T>(D, nq, sp->ncomp, 3, hyper, op->dense_cb, op->dense_qc);
   } else if (scalar) {
     // phi [nq][D], reference gradients [nq][D][3], weights [nq], vertex basis [nq][4]
     for (double v : phi) tab.push_back((T)v);
@@ -928,7 +928,7 @@ template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, con
   std::vector<T> tab;
   if (k >= 4) {
     tab = dense_simplex_tables<T>(2, pts, w, phi, dphi);
-    op->dense_cb = simplex_dense_cells_per_block<T>(sp->D, nq, sp->ncomp, 2);
+    simplex_dense_shape<T>(sp->D, nq, sp->ncomp, 2, false, op->dense_cb, op->dense_qc);
   } else {
     for (double v : phi) tab.push_back((T)v);
     for (double v : dphi) tab.push_back((T)v);
@@ -1180,7 +1180,11 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
   } else if ((op->cell_type == MF_CELL_TET || op->cell_type == MF_CELL_TRI) && op->degree >= 4) {
     SimplexDenseArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
                           op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, op->D, op->nqp, op->ncomp, op->kind,
-                          op->dense_cb, (T)op->lam, (T)op->mu};
+                          op->dense_cb, op->dense_qc, (T)op->lam, (T)op->mu};
+    if (op->kind == MF_OP_HYPERELASTIC) {
+      a.u0 = op->u0.as<T>();
+      a.u0map = op->u0map.ptr ? op->u0map.as<int32_t>() : nullptr;
+    }
     return launch_simplex_dense<T>(op->cell_type == MF_CELL_TET ? 3 : 2, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
@@ -1339,7 +1343,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   else if (ct == MF_CELL_QUAD)
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);
   else if (ct == MF_CELL_TET)
-    ok = ((kind == MF_OP_ELASTICITY || (kind == MF_OP_HYPERELASTIC && sp->degree <= 3)) && sp->ncomp == 3) ||
+    ok = ((kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC) && sp->ncomp == 3) ||
          (kind <= MF_OP_POISSON && sp->ncomp == 1);
   else
     ok = (kind <= MF_OP_POISSON && sp->ncomp == 1) || (kind == MF_OP_ELASTICITY && sp->ncomp == 2);

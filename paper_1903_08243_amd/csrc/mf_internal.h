@@ -364,10 +364,12 @@ template <typename T> struct SimplexDenseArgs {
   int64_t c0, c1;
   const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
   int64_t ulo, uhi;
-  int D, nq, ncomp, kind, cb;
+  int D, nq, ncomp, kind, cb, qc;  // cb cells per workgroup (cb D <= 256), qc points per chunk
   T lam, mu;
+  const T *u0 = nullptr;           // HYPERELASTIC: linearisation point, internal numbering
+  const int32_t *u0map = nullptr;  // its AoSoA map when `map` flags constrained nodes
 };
-template <typename T> int simplex_dense_cells_per_block(int D, int nq, int ncomp, int dim);
+template <typename T> void simplex_dense_shape(int D, int nq, int ncomp, int dim, bool hyper, int &cb, int &qc);
 template <typename T> int launch_simplex_dense(int dim, const SimplexDenseArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_simplex_element_diag(int dim, const int32_t *fmap, const T *geo, const T *coef, const double *tab,
@@ -423,7 +425,7 @@ struct mf_op {
   // tet rule, and the CSR pattern once built
   std::vector<int32_t> h_bc_user;  // constrained dofs, user numbering
   int qdeg = 0;
-  int dense_cb = 0;  // cells per workgroup of the dense simplex kernel (degrees 4-6)
+  int dense_cb = 0, dense_qc = 0;  // dense simplex kernel (degrees 4-6): cells per workgroup, points per chunk
   mutable std::vector<int64_t> csr_rowptr;
   mutable std::vector<int32_t> csr_col;
   mutable bool csr_built = false;

@@ -204,13 +204,13 @@ bool tet_rule(int degree, std::vector<double> &pts, std::vector<double> &w) {
     s31(0.0927352503108912, 0.0734930431163619 / 6.0);
     s31(0.3108859192633006, 0.1126879257180159 / 6.0);
     s22(0.0455037041256496, 0.0425460207770812 / 6.0);
-  } else if (degree <= 13) {
+  } else if (degree <= 21) {
     // conical product rule: x = u, y = v (1 - u), z = t (1 - u)(1 - v), Jacobian
     // (1 - u)^2 (1 - v). A degree-p monomial has degree at most p in each of u, v, t, so
     // Gauss-Jacobi rules for the weights (1 - u)^2 and (1 - v), which absorb the
     // Jacobian, and Gauss-Legendre in t, each with n points (exact to degree 2n - 1),
-    // integrate it exactly: n = (degree + 2) / 2, 64 points for degrees 6-7 up to 343
-    // for degrees 12-13
+    // integrate it exactly: n = (degree + 2) / 2, 64 points for degrees 6-7 up to 1331
+    // for degrees 20-21
     const int n = (degree + 2) / 2;
     std::vector<double> xu, wu, xv, wv, xt, wt;
     gauss_jacobi01(n, 2, xu, wu);

@@ -24,8 +24,9 @@ def _relerr(y, ref):
     return np.abs(y - ref).max() / np.abs(ref).max()
 
 
-def _case(k, m=3):
-    mesh = mg.tet_mesh(m, 0.2, config=2, seed_k=k)  # 162 cells at m = 3: ragged batches
+def _case(k, m=None):
+    m = m or (3 if k <= 3 else 2)  # 162 cells at m = 3: ragged batches; 48 at m = 2
+    mesh = mg.tet_mesh(m, 0.2, config=2, seed_k=k)
     space = mg.tet_space(mesh, k, ncomp=3, config=2, seed_k=k)
     u0 = 0.3 * mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_COEF, k)
     x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
@@ -41,18 +42,18 @@ def _apply(mf, space, prec, u0, x, **kw):
 
 @pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_tet_hyper_action(mf, k, prec, scatter):
     print(f"tet hyper k={k} prec={prec} scatter={scatter}", flush=True)
     mesh, space, u0, x = _case(k)
     ref = oracle.OracleOp(space, oracle.OP_HYPERELASTIC, lam=1.0, mu=0.5, u0=u0).apply(x)
     y, op = _apply(mf, space, prec, u0, x, scatter=scatter)
-    assert op.info["nqp"] == {1: 1, 2: 14, 3: 125}[k]
+    assert op.info["nqp"] == {1: 1, 2: 14, 3: 125, 4: 343, 5: 729, 6: 1331}[k]
     assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
 def test_tet_hyper_dirichlet_rows(mf, k, prec):
     """Constrained boundary nodes: identity rows, zero columns; u0 still enters at
     the constrained nodes (it is a coefficient, gathered through an unflagged map)."""
@@ -69,7 +70,7 @@ def test_tet_hyper_dirichlet_rows(mf, k, prec):
     assert _relerr(y, ref.ravel()) <= TOL[prec]
 
 
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 6])
 def test_tet_hyper_at_zero_is_elasticity(mf, k):
     """At u0 = 0 the tangent is the linear elasticity operator (other quadrature rule,
     both exact)."""

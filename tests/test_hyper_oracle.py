@@ -14,7 +14,7 @@ from paper_1903_08243_amd import meshgen as mg
 LAM, MU = 1.0, 0.5
 
 
-CASES = [("tet", 1), ("tet", 2), ("tet", 3), ("hex", 1), ("hex", 2)]
+CASES = [("tet", k) for k in range(1, 7)] + [("hex", 1), ("hex", 2)]
 
 
 def _space(cell, k, m=2, pert=0.2):
