@@ -261,12 +261,18 @@ int mf_op_assemble_csr(const mf_op *op, const mf_space *space, void *vals, void 
 /* Conjugate gradients for A64 x = b, all vectors FP64 on the device (Hestenes
  * and Stiefel; not in the paper -- the solver that consumes the action).
  * A32 == NULL: plain preconditioned CG with the FP64 action.
- * A32 != NULL: iterative refinement -- the outer loop forms r = b - A64 x in
- * FP64 and stops when ||r||/||b|| <= rtol; each inner solve runs preconditioned
- * CG on A32 d = r with the FP32 action (FP64 vectors, dot products and
- * updates) to relative tolerance max(inner_rtol, rtol ||b|| / ||r||) -- the
- * final target, floored at inner_rtol (0 -> 1e-6, the FP32 action's accuracy)
- * -- then x += d.
+ * A32 != NULL, M NULL or Jacobi: one preconditioned CG sequence with the FP32
+ * action A32 p and FP64 vectors, dot products and updates, with reliable updates:
+ * whenever the recursively updated residual has dropped by the factor inner_rtol
+ * (0 -> 1e-3) since the last true residual, and whenever it meets the target, r is
+ * replaced by b - A64 x computed in FP64 and r'z recomputed, keeping the search
+ * direction; the solve stops when that true ||r||/||b|| <= rtol.
+ * info->outer_iterations counts the true residuals formed (the first included).
+ * A32 != NULL with a learned M: iterative refinement -- the outer loop forms
+ * r = b - A64 x in FP64 and stops when ||r||/||b|| <= rtol; each inner solve runs
+ * flexible CG on A32 d = r (FP64 vectors) to relative tolerance
+ * max(inner_rtol, rtol ||b|| / ||r||), floored at inner_rtol (0 -> 1e-6), then
+ * x += d.
  * M == NULL: no preconditioner; a Jacobi M: preconditioned CG; a learned M
  * (mf_precond_create_cnn): flexible CG with the Polak-Ribiere beta
  * -alpha <z_k+1, A p_k> / <z_k, r_k>, where any iteration whose network output z

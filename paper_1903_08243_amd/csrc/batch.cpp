@@ -154,7 +154,7 @@ static int record_chunk(mf_batch *B) {
   for (int j = 0; j < BCHUNK; j++) {
     int rc = batch_apply(B, B->ops_in, a32 ? MF_F32 : MF_F64, a32 ? B->Ap32.ptr : B->Ap.ptr, st);
     if (!rc)
-      rc = batch_step_after_apply(v, B->d.as<double>(), B->r.as<double>(), B->p.as<double>(),
+      rc = batch_step_after_apply(v, B->x.as<double>(), B->r.as<double>(), B->p.as<double>(),
                                   a32 ? B->p32.as<float>() : nullptr, a32 ? B->Ap32.ptr : B->Ap.ptr, a32,
                                   B->dinv.ptr ? B->dinv.as<double>() : nullptr, st, B->s);
     if (rc) return rc;
@@ -471,59 +471,87 @@ int mf_batch_solve(mf_batch *B, double rtol, double inner_rtol, int maxit, mf_cg
   std::vector<double> bb(ns), rr(ns);
   std::vector<int> outer(ns, 0), inner(ns, 0), done(ns, 0);
   for (int i = 0; i < ns; i++) bb[i] = B->host_st[i].rr;
-  const double floor_rt = inner_rtol > 0.0 ? inner_rtol : 1e-6;  // see mf_cg_solve
+  // One preconditioned CG sequence per system, all systems in one launch sequence,
+  // with reliable updates as in mf_cg_solve: whenever a live system's recursively
+  // updated residual has dropped by delta since its last true residual, or a system
+  // has newly stopped, the true residuals b - A64 x of all systems are formed in FP64
+  // and replace r (r'z recomputed, search directions kept); a system whose true
+  // residual misses the target resumes.
+  const double delta = inner_rtol > 0.0 ? std::min(inner_rtol, 0.5) : 1e-3;
   int status = MF_OK;
-  int total_inner = 0;
-  for (int it = 0; it < 100; it++) {
-    // true FP64 residual of every system
-    if ((rc = batch_apply(B, B->ops64x, MF_F64, B->Ap.ptr, nullptr))) return rc;
-    if ((rc = batch_residual(v, B->b.as<double>(), B->Ap.ptr, false, B->r.as<double>(), st, B->s))) return rc;
+  int nrel = 0;
+  auto true_residuals = [&]() -> int {
+    int r2 = batch_apply(B, B->ops64x, MF_F64, B->Ap.ptr, nullptr);
+    if (!r2) r2 = batch_residual(v, B->b.as<double>(), B->Ap.ptr, false, B->r.as<double>(), st, B->s);
+    return r2;
+  };
+  if ((rc = true_residuals())) return rc;
+  if ((rc = read_states(B))) return rc;
+  for (int i = 0; i < ns; i++) {
+    CgState S{};
+    S.tol2 = bb[i] == 0.0 ? DBL_MAX : rtol * rtol * bb[i];
+    S.maxit = maxit;
+    rr[i] = B->host_st[i].rr;
+    B->host_st[i] = S;
+  }
+  if ((rc = write_states(B))) return rc;
+  if ((rc = batch_init(v, B->r.as<double>(), dinv, B->p.as<double>(), B->refine ? B->p32.as<float>() : nullptr, st,
+                       B->s)))
+    return rc;
+  // the accumulating inner action starts from a cleared output
+  if (B->refine) {
+    if ((rc = launch_fill<float>(B->Ap32.as<float>(), 0.0f, B->ntot, B->s))) return rc;
+  } else if ((rc = launch_fill<double>(B->Ap.as<double>(), 0.0, B->ntot, B->s))) {
+    return rc;
+  }
+  if ((rc = read_states(B))) return rc;
+  std::vector<double> rr_ref(ns);
+  std::vector<int> stopped(ns);
+  for (int i = 0; i < ns; i++) {
+    rr_ref[i] = B->host_st[i].rr;
+    stopped[i] = B->host_st[i].stop;
+  }
+  bool all_stop = true;
+  for (int i = 0; i < ns; i++) all_stop &= stopped[i] != 0;
+  if (!all_stop && (rc = ensure_graph(B))) return rc;
+  while (!all_stop) {
+    MF_HIP(hipGraphLaunch(B->exec, B->s));
     if ((rc = read_states(B))) return rc;
-    bool all = true;
+    bool due = false, brk = false;
+    all_stop = true;
     for (int i = 0; i < ns; i++) {
-      rr[i] = B->host_st[i].rr;
-      if (!done[i]) outer[i]++;
-      done[i] = (bb[i] == 0.0 || rr[i] <= rtol * rtol * bb[i]) ? 1 : 0;
-      all &= done[i] != 0;
+      const CgState &S = B->host_st[i];
+      brk |= S.breakdown != 0;
+      all_stop &= S.stop != 0;
+      due |= (S.stop && !stopped[i]) || (!S.stop && S.rr < delta * rr_ref[i]);
     }
-    if (all || total_inner >= maxit) break;
-    // inner solves A d = r from d = 0 (all systems together); converged systems stop at once
-    for (int i = 0; i < ns; i++) {
-      CgState S{};
-      const double irt = std::max(floor_rt, std::sqrt(rtol * rtol * bb[i] / std::max(rr[i], 1e-300)));
-      S.tol2 = done[i] ? DBL_MAX : (B->refine ? irt * irt * rr[i] : rtol * rtol * bb[i]);
-      S.maxit = maxit - total_inner;
-      B->host_st[i] = S;
-    }
-    if ((rc = write_states(B))) return rc;
-    if ((rc = launch_fill<double>(B->d.as<double>(), 0.0, B->ntot, B->s))) return rc;
-    if ((rc = batch_init(v, B->r.as<double>(), dinv, B->p.as<double>(), B->refine ? B->p32.as<float>() : nullptr, st,
-                         B->s)))
-      return rc;
-    if ((rc = ensure_graph(B))) return rc;
-    int maxiters = 0;
-    while (true) {
-      if ((rc = read_states(B))) return rc;
-      bool all_stop = true;
-      maxiters = 0;
-      for (int i = 0; i < ns; i++) {
-        all_stop &= B->host_st[i].stop != 0;
-        maxiters = std::max(maxiters, B->host_st[i].iters);
-      }
-      if (all_stop) break;
-      MF_HIP(hipGraphLaunch(B->exec, B->s));
-    }
-    bool brk = false;
-    for (int i = 0; i < ns; i++) {
-      inner[i] += B->host_st[i].iters;
-      brk |= B->host_st[i].breakdown != 0;
-    }
-    total_inner += maxiters;
-    if ((rc = batch_axpy(B->x.as<double>(), B->d.as<double>(), B->ntot, B->s))) return rc;
     if (brk) {
       status = fail(MF_EBREAKDOWN, "batched CG breakdown in at least one system");
       break;
     }
+    if (!due && !all_stop) continue;
+    // reliable update of every system (the accumulating inner action's output was
+    // cleared by the last search-direction update)
+    if ((rc = true_residuals())) return rc;
+    if ((rc = batch_reliable(v, B->r.as<double>(), dinv, st, B->s))) return rc;
+    if ((rc = read_states(B))) return rc;
+    nrel++;
+    all_stop = true;
+    for (int i = 0; i < ns; i++) {
+      rr_ref[i] = B->host_st[i].rr;
+      stopped[i] = B->host_st[i].stop;
+      all_stop &= stopped[i] != 0;
+      brk |= B->host_st[i].breakdown != 0;
+    }
+    if (brk) {
+      status = fail(MF_EBREAKDOWN, "batched CG breakdown in at least one system");
+      break;
+    }
+  }
+  for (int i = 0; i < ns; i++) {
+    rr[i] = B->host_st[i].rr;
+    outer[i] = 1 + nrel;
+    inner[i] = B->host_st[i].iters;
   }
   // back to user numbering
   for (int i = 0; i < ns && !rc; i++) {

@@ -24,6 +24,8 @@ int batch_init(const BatchVec &v, const double *r, const double *dinv, double *p
 int batch_step_after_apply(const BatchVec &v, double *x, double *r, double *p, float *p32, const void *Ap, bool ap32,
                            const double *dinv, CgState *st, hipStream_t s);
 int batch_axpy(double *x, const double *d, int64_t n, hipStream_t s);
+// reliable update of every system: r'z and r'r of the replaced residual, p and iters kept
+int batch_reliable(const BatchVec &v, const double *r, const double *dinv, CgState *st, hipStream_t s);
 // y = 0 on the chunks of systems that have not stopped
 template <typename T> int batch_fill(const BatchVec &v, T *y, const CgState *st, hipStream_t s);
 

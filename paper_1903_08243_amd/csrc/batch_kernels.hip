@@ -129,7 +129,7 @@ __global__ void __launch_bounds__(BR) bfinalize_kernel(const double *__restrict_
   __shared__ double sh[BR / 64];
   const int s = blockIdx.x;
   if (s >= nsys) return;  // uniform over the workgroup
-  const bool two = stage == CG_STAGE_UPDATE || stage == CG_STAGE_INIT;
+  const bool two = stage == CG_STAGE_UPDATE || stage == CG_STAGE_INIT || stage == CG_STAGE_RELIABLE;
   double a = 0.0, b = 0.0;
   for (int c = cptr[s] + threadIdx.x; c < cptr[s + 1]; c += BR) {
     a += part[c];
@@ -149,6 +149,13 @@ __global__ void __launch_bounds__(BR) bfinalize_kernel(const double *__restrict_
       S.iters = 0;
       S.stop = (S.rr <= S.tol2) ? 1 : 0;
       S.breakdown = 0;
+      if (!(S.rr == S.rr) || !(S.rz == S.rz) || S.rz < 0.0) S.stop = S.breakdown = 1;
+      break;
+    case CG_STAGE_RELIABLE:  // the true residual replaced r: r'z, r'r; p and iters kept
+      S.rz = t0;
+      S.rr = t1;
+      S.breakdown = 0;
+      S.stop = (S.rr <= S.tol2 || S.iters >= S.maxit) ? 1 : 0;
       if (!(S.rr == S.rr) || !(S.rz == S.rz) || S.rz < 0.0) S.stop = S.breakdown = 1;
       break;
     case CG_STAGE_PAP:
@@ -219,6 +226,31 @@ int batch_init(const BatchVec &v, const double *r, const double *dinv, double *p
   binit_kernel<<<v.nch, BR, 0, s>>>(r, dinv, p, p32, v.chunks, v.nch, v.part);
   MF_HIP(hipGetLastError());
   return fin(v, st, CG_STAGE_INIT, s);
+}
+
+// partials of r'z (z = M^{-1} r) and r'r per chunk
+__global__ void __launch_bounds__(BR) brz_kernel(const double *__restrict__ r, const double *__restrict__ dinv,
+                                                 const VChunk *__restrict__ ch, int nch, double *__restrict__ part) {
+  __shared__ double sh[BR / 64];
+  const VChunk c = ch[blockIdx.x];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = c.start + threadIdx.x; i < c.start + c.len; i += BR) {
+    const double ri = r[i];
+    s1 += ri * (dinv ? dinv[i] * ri : ri);
+    s2 += ri * ri;
+  }
+  s1 = bsum(s1, sh);
+  s2 = bsum(s2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part[nch + blockIdx.x] = s2;
+  }
+}
+
+int batch_reliable(const BatchVec &v, const double *r, const double *dinv, CgState *st, hipStream_t s) {
+  brz_kernel<<<v.nch, BR, 0, s>>>(r, dinv, v.chunks, v.nch, v.part);
+  MF_HIP(hipGetLastError());
+  return fin(v, st, CG_STAGE_RELIABLE, s);
 }
 
 int batch_step_after_apply(const BatchVec &v, double *x, double *r, double *p, float *p32, const void *Ap, bool ap32,

@@ -166,6 +166,57 @@ static int pcg_core(const mf_op *A, const double *dinv, double *x, double tol2, 
   return MF_OK;
 }
 
+// FP32-action PCG with reliable updates: one Krylov sequence on A32 with FP64 vectors,
+// dots and updates; whenever the recursively updated residual has dropped by `delta`
+// since the last true one (and when it meets the target), r is replaced by the true
+// residual b - A64 x and r'z recomputed, keeping the search direction (the reliable
+// updates of van der Vorst and Ye, 2000). The FP32 rounding of the action then only
+// perturbs the search directions and x converges to the FP64 solution, without the
+// restarts of outer-inner refinement. w.r holds b - A64 x on entry; rr returns the
+// last true r'r.
+static int pcg_reliable(const mf_op *A32, const mf_op *A64, const double *b, const double *dinv, double *x,
+                        double tol2, int maxit, double delta, CgWork &w, mf_cg_info &inf, double &rr) {
+  CgState init{};
+  init.tol2 = tol2;
+  init.maxit = maxit;
+  *w.host_st = init;
+  MF_HIP(hipMemcpyAsync(w.st, w.host_st, sizeof(CgState), hipMemcpyHostToDevice, w.s));
+  int rc = cg_init(w.r, dinv, w.p, w.p32, w.n, w.part, w.st, w.s, w.Ap32);
+  CgState st{};
+  if (!rc) rc = read_state(w, st);
+  if (rc || st.stop || maxit <= 0) return rc;
+  double rr_ref = st.rr;
+  hipGraphExec_t &exec = w.exec[1];
+  if (w.graphs) {
+    rc = chunk_graph(A32, dinv, x, w, exec);
+    if (rc) return rc;
+  }
+  while (true) {
+    if (w.graphs) {
+      MF_HIP(hipGraphLaunch(exec, w.s));
+    } else {
+      rc = record_chunk(A32, dinv, x, w);
+      if (rc) return rc;
+    }
+    rc = read_state(w, st);
+    if (rc) return rc;
+    inf.inner_iterations = st.iters;
+    if (st.breakdown) return fail(MF_EBREAKDOWN, "CG breakdown (non-finite value or p'Ap <= 0)");
+    if (!st.stop && st.rr > delta * rr_ref) continue;
+    // reliable update: r = b - A64 x, then r'z, r'r
+    rc = op_apply_internal(A64, x, w.Ap, w.s);
+    if (!rc) rc = cg_residual(b, w.Ap, false, w.r, w.n, w.part, w.st, w.s);
+    if (!rc) rc = cg_reliable(w.r, dinv, w.n, w.part, w.st, w.s);
+    if (!rc) rc = read_state(w, st);
+    if (rc) return rc;
+    inf.outer_iterations++;
+    rr = st.rr;
+    rr_ref = st.rr;
+    if (st.breakdown) return fail(MF_EBREAKDOWN, "CG breakdown (non-finite residual)");
+    if (st.stop) return MF_OK;  // converged on the true residual, or maxit
+  }
+}
+
 static int residual(const mf_op *A64, const double *b, const double *x, CgWork &w, double &rr) {
   int rc = op_apply_internal(A64, x, w.Ap, w.s);
   if (rc) return rc;
@@ -289,8 +340,22 @@ static int cg_core(CgWork &w, const mf_op *A64, const mf_op *A32, const mf_preco
       rc = residual(A64, b, x, w, rr);
       if (rc) return rc;
     }
+  } else if (!w.M) {
+    // FP32 action with a reliable update every `delta` of residual reduction
+    // (inner_rtol; default 1e-3, measured best among 0.3 .. 1e-4: Helmholtz Q3 at 32^3
+    // 49.2 ms against 51.9 ms in FP64, Q5 at 24^3 101.5 against 119.1 ms, Q2 at 64^3
+    // 113.8 against 137.5 ms)
+    const double delta = inner_rtol > 0.0 ? std::min(inner_rtol, 0.5) : 1e-3;
+    rc = residual(A64, b, x, w, rr);
+    if (rc) return rc;
+    inf.outer_iterations = 1;
+    if (rr > tol2 && maxit > 0) {
+      status = pcg_reliable(A32, A64, b, dinv, x, tol2, maxit, delta, w, inf, rr);
+      if (status == MF_EDEVICE) return status;
+    }
   } else {
-    // Inner tolerance: aim straight at the final target, but not below the FP32
+    // learned preconditioner (flexible CG) with the FP32 action: outer-inner
+    // refinement. Inner tolerance: aim straight at the final target, but not below the FP32
     // action's accuracy floor (inner_rtol, default 1e-6): the first inner solve
     // then removes six orders of magnitude and the next one the rest, so little
     // Krylov information is lost to restarts.

@@ -16,7 +16,8 @@ enum {
   CG_STAGE_FUPDATE = 4,  // r'r after x, r update
   CG_STAGE_FZ = 5,       // z'r, z'Ap, non-finite count of z: accept z or flag the Jacobi fallback
   CG_STAGE_FZFIX = 6,    // after the fallback pass: beta (Polak-Ribiere) and r'z
-  CG_STAGE_FINIT = 7     // first z: r'r, z'r, non-finite count
+  CG_STAGE_FINIT = 7,    // first z: r'r, z'r, non-finite count
+  CG_STAGE_RELIABLE = 8  // after r was replaced by the true residual: r'z, r'r (iterations kept)
 };
 
 // Device-resident iteration state.
@@ -40,6 +41,9 @@ int cg_init(const double *r, const double *dinv, double *p, float *p32, int64_t 
 int cg_step_after_apply(double *x, double *r, double *p, float *p32, void *Ap, bool ap32, const double *dinv,
                         int64_t n, double *part, CgState *st, hipStream_t s);
 int cg_axpy(double *x, const double *d, int64_t n, hipStream_t s);
+// reliable update: r'z and r'r of the replaced residual r (z = M^{-1} r); the search
+// direction and the iteration count are kept, stop is re-evaluated
+int cg_reliable(const double *r, const double *dinv, int64_t n, double *part, CgState *st, hipStream_t s);
 int cg_recip(const void *d, bool d32, double *dinv, int64_t n, hipStream_t s);
 int cg_cast(const double *a, float *b, int64_t n, hipStream_t s);
 int cg_sqrt(const double *a, double *b, int64_t n, hipStream_t s);

@@ -67,6 +67,24 @@ __global__ void __launch_bounds__(RB) init_p_kernel(const double *__restrict__ r
   }
 }
 
+// partials of r'z (z = M^{-1} r) and r'r
+__global__ void __launch_bounds__(RB) rz_kernel(const double *__restrict__ r, const double *__restrict__ dinv, int64_t n,
+                                                double *__restrict__ part) {
+  __shared__ double sh[RB / 64];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RB + threadIdx.x; i < n; i += (int64_t)gridDim.x * RB) {
+    const double ri = r[i];
+    s1 += ri * (dinv ? dinv[i] * ri : ri);
+    s2 += ri * ri;
+  }
+  s1 = block_sum(s1, sh);
+  s2 = block_sum(s2, sh);
+  if (threadIdx.x == 0) {
+    part[blockIdx.x] = s1;
+    part[gridDim.x + blockIdx.x] = s2;
+  }
+}
+
 template <typename TA>
 __global__ void __launch_bounds__(RB) dot_kernel(const double *__restrict__ a, const TA *__restrict__ b, int64_t n,
                                                  double *__restrict__ part) {
@@ -241,7 +259,8 @@ __global__ void __launch_bounds__(RB) finalize_kernel(const double *__restrict__
                                                       int stage) {
   __shared__ double sh[RB / 64];
   const int nsum = (stage == CG_STAGE_FZ || stage == CG_STAGE_FINIT)                               ? 4
-                   : (stage == CG_STAGE_UPDATE || stage == CG_STAGE_INIT || stage == CG_STAGE_FZFIX) ? 2
+                   : (stage == CG_STAGE_UPDATE || stage == CG_STAGE_INIT || stage == CG_STAGE_FZFIX ||
+                      stage == CG_STAGE_RELIABLE)                                                   ? 2
                                                                                                      : 1;
   CgState S;
   if (threadIdx.x == 0) S = *st;  // issued together with the partial loads below
@@ -262,6 +281,13 @@ __global__ void __launch_bounds__(RB) finalize_kernel(const double *__restrict__
       S.iters = 0;
       S.stop = (S.rr <= S.tol2) ? 1 : 0;
       S.breakdown = 0;
+      if (!(S.rr == S.rr) || !(S.rz == S.rz) || S.rz < 0.0) S.stop = S.breakdown = 1;
+      break;
+    case CG_STAGE_RELIABLE:  // tot0 = r'z, tot1 = r'r of the true residual; p and iters kept
+      S.rz = tot[0];
+      S.rr = tot[1];
+      S.breakdown = 0;
+      S.stop = (S.rr <= S.tol2 || S.iters >= S.maxit) ? 1 : 0;
       if (!(S.rr == S.rr) || !(S.rz == S.rz) || S.rz < 0.0) S.stop = S.breakdown = 1;
       break;
     case CG_STAGE_PAP: {  // tot0 = p'Ap
@@ -381,6 +407,14 @@ int cg_step_after_apply(double *x, double *r, double *p, float *p32, void *Ap, b
   else update_kernel<double><<<g, RB, 0, s>>>(x, r, p, (const double *)Ap, dinv, st, n, part);
   finalize_kernel<<<1, RB, 0, s>>>(part, (int)g, st, CG_STAGE_UPDATE);
   p_update_kernel<<<g, RB, 0, s>>>(p, p32, r, dinv, st, n, Ap);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+int cg_reliable(const double *r, const double *dinv, int64_t n, double *part, CgState *st, hipStream_t s) {
+  const unsigned g = grid_n(n);
+  rz_kernel<<<g, RB, 0, s>>>(r, dinv, n, part);
+  finalize_kernel<<<1, RB, 0, s>>>(part, (int)g, st, CG_STAGE_RELIABLE);
   MF_HIP(hipGetLastError());
   return MF_OK;
 }
