@@ -394,13 +394,16 @@ int mf_precond_harvest(const mf_precond *M, const double *r, const double *e, in
 /* ----------------------------------------------------------------- batched solves
  * Many independent systems A64[i] x[i] = b[i] on uneven hex meshes and degrees,
  * solved together (not in the paper -- the batched form of the CG consumer of
- * the action). Every iteration applies all operators in ONE persistent launch
- * over a device work list of (operator, cell-batch range) items; vector stages
- * run over the concatenated vectors of all systems; chunks of iterations are
- * captured into a hipGraph and replayed. Requirements: scalar FP64 hex operators
- * of one kind, degree <= 5, without constraints; A32 (nullable) holds the FP32
- * operators on the same spaces (iterative refinement as in mf_cg_solve); M
- * (nullable, entries nullable) Jacobi preconditioners of the A64[i].
+ * the action). Every iteration applies all operators either in ONE persistent
+ * launch over a device work list of (operator, cell-batch range) items, or (launch
+ * form "per system", grid -1) with each live system's own operator kernels (its
+ * tile shape and scatter); vector stages run over the concatenated vectors of all
+ * systems; chunks of iterations are captured into a hipGraph and replayed (launched
+ * directly in the per-system form, whose set of live systems changes).
+ * Requirements: scalar FP64 hex operators of one kind, degree <= 5, without
+ * constraints; A32 (nullable) holds the FP32 operators on the same spaces (the FP32
+ * action with reliable updates, as in mf_cg_solve); M (nullable, entries nullable)
+ * Jacobi preconditioners of the A64[i].
  * The batch binds the device pointers b[i] (input) and x[i] (initial guess in,
  * solution out, user numbering); they must stay valid while the batch exists. */
 typedef struct mf_batch mf_batch;
@@ -422,11 +425,13 @@ int mf_batch_apply(mf_batch *batch, int inner, void *stream);
  * buffers, which a later mf_batch_solve re-initialises from the bound vectors.
  * Asynchronous on stream. Errors: MF_EINVAL (null batch, array or vector). */
 int mf_batch_apply_user(mf_batch *batch, int inner, const void *const *x, void *const *y, void *stream);
-/* Autotuner: times the batched launch with one wavefront per single-batch work
- * item (grid 0), and persistent grids of 1, 2, 4 x (CUs x 4) wavefronts with
- * work-list granularities of 1..32 cell batches per item, and keeps the fastest. With cache_path, a result for the same (kind, inner
- * precision, CU count, set of (degree, cells)) is read from / appended to that
- * text file. */
+/* Autotuner: times one application of all inner operators in each launch form --
+ * per-system kernels (grid -1), the work-list kernel with one wavefront per
+ * single-batch item (grid 0), and persistent grids of 1, 2, 4 x (CUs x 4)
+ * wavefronts with work-list granularities of 1..32 cell batches per item -- and
+ * keeps the fastest. With cache_path, a result for the same (kind, inner precision,
+ * CU count, set of (degree, cells)) is read from / appended to that text file.
+ * mf_batch_set_tuning: items_per >= 1, grid >= -1 (items_per 1 for grids 0, -1). */
 int mf_batch_autotune(mf_batch *batch, const char *cache_path, void *stream);
 int mf_batch_get_tuning(const mf_batch *batch, int *items_per, int *grid);
 int mf_batch_set_tuning(mf_batch *batch, int items_per, int grid);

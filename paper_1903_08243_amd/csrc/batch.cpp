@@ -8,9 +8,11 @@
 // systems have stopped; stopped systems cost no operator work (their items are
 // skipped) and their vector updates are no-ops.
 //
-// The work-list granularity (cell batches per item) and the persistent grid size
-// are tuning parameters; mf_batch_autotune times candidates on the device and
-// caches the winner in a text file.
+// The launch form is a tuning parameter: the work-list kernel with its granularity
+// (cell batches per item) and persistent grid size, or each live system's own
+// operator kernels (its tile shape and scatter, as in a single solve; chunks are then
+// launched directly, since the set of live systems changes); mf_batch_autotune times
+// the candidates on the device and caches the winner in a text file.
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -51,7 +53,8 @@ struct mf_batch {
   std::vector<double *> b_user, x_user;
   mf::DeviceBuffer b, x, r, p, Ap, p32, Ap32, d, dinv, part, st, chunks, cptr;
   mf::DeviceBuffer ops64x, ops_in, items;  // op tables: FP64 residual (x -> Ap), inner (p -> Ap / p32 -> Ap32)
-  int nch = 0, nitems = 0, grid = 0, items_per = 1;  // grid 0: one wavefront per item
+  int nch = 0, nitems = 0, grid = 0, items_per = 1;  // grid 0: one wavefront per item; -1: per-system kernels
+  std::vector<char> live;                            // per-system launches: systems not yet stopped
   int64_t resident = 0;
   hipStream_t s = nullptr;
   hipEvent_t ev = nullptr;
@@ -126,6 +129,24 @@ static int batch_apply(mf_batch *B, const mf::DeviceBuffer &ops, int precision, 
   const int stride = (int)(sizeof(CgState) / sizeof(int));
   const BatchVec v = vec_desc(B);
   int rc;
+  if (B->grid < 0) {
+    // each live system's own operator kernels, accumulating into its cleared output
+    const bool outer = &ops == &B->ops64x;
+    rc = st ? (precision == MF_F64 ? batch_fill(v, (double *)y, st, B->s) : batch_fill(v, (float *)y, st, B->s))
+            : (precision == MF_F64 ? launch_fill<double>((double *)y, 0.0, B->ntot, B->s)
+                                   : launch_fill<float>((float *)y, 0.0f, B->ntot, B->s));
+    for (int i = 0; i < B->nsys && !rc; i++) {
+      if (st && !B->live[i]) continue;
+      const int64_t o = B->off[i];
+      if (precision == MF_F32) {
+        rc = op_apply_internal_acc(B->A32[i], B->p32.as<float>() + o, (float *)y + o, B->s);
+      } else {
+        const double *in = (outer ? B->x.as<double>() : B->p.as<double>()) + o;
+        rc = op_apply_internal_acc(B->A64[i], in, (double *)y + o, B->s);
+      }
+    }
+    return rc;
+  }
   if (precision == MF_F64) {
     rc = st ? batch_fill(v, (double *)y, st, B->s) : launch_fill<double>((double *)y, 0.0, B->ntot, B->s);
     if (!rc) rc = launch_hex_batch<double>(B->kind, ops.ptr, B->items.ptr, B->nitems, B->grid, stop, stride, B->s);
@@ -303,8 +324,8 @@ int mf_batch_get_tuning(const mf_batch *B, int *items_per, int *grid) {
 }
 
 int mf_batch_set_tuning(mf_batch *B, int items_per, int grid) {
-  if (!B || items_per < 1 || grid < 0 || (grid == 0 && items_per != 1))
-    return fail(MF_EINVAL, "mf_batch_set_tuning: items_per >= 1, grid >= 0 (grid 0 needs items_per 1)");
+  if (!B || items_per < 1 || grid < -1 || (grid <= 0 && items_per != 1))
+    return fail(MF_EINVAL, "mf_batch_set_tuning: items_per >= 1, grid >= -1 (grid 0 and -1 need items_per 1)");
   if (B->exec) {
     (void)hipGraphExecDestroy(B->exec);
     B->exec = nullptr;
@@ -396,13 +417,13 @@ int mf_batch_autotune(mf_batch *B, const char *cache_path, void *stream) {
       if (line.rfind(key, 0) == 0) {
         std::istringstream is(line.substr(std::strlen(key)));
         int per = 0, grid = 0;
-        if (is >> per >> grid && per > 0 && grid >= 0) return mf_batch_set_tuning(B, per, grid);
+        if (is >> per >> grid && per > 0 && grid >= -1) return mf_batch_set_tuning(B, per, grid);
       }
     }
   }
   (void)stream;
   const int pers[] = {1, 2, 4, 8, 16, 32};
-  const int64_t grids[] = {0, B->resident, 2 * B->resident, 4 * B->resident};
+  const int64_t grids[] = {-1, 0, B->resident, 2 * B->resident, 4 * B->resident};
   hipEvent_t e0, e1;
   MF_HIP(hipEventCreate(&e0));
   MF_HIP(hipEventCreate(&e1));
@@ -411,7 +432,7 @@ int mf_batch_autotune(mf_batch *B, const char *cache_path, void *stream) {
   const bool a32 = B->refine;
   for (int per : pers) {
     for (int64_t g : grids) {
-      if (g == 0 && per != 1) continue;
+      if (g <= 0 && per != 1) continue;
       B->grid = (int)g;
       int rc = build_items(B, per);
       if (rc) return rc;
@@ -513,9 +534,16 @@ int mf_batch_solve(mf_batch *B, double rtol, double inner_rtol, int maxit, mf_cg
   }
   bool all_stop = true;
   for (int i = 0; i < ns; i++) all_stop &= stopped[i] != 0;
-  if (!all_stop && (rc = ensure_graph(B))) return rc;
+  const bool direct = B->grid < 0;  // per-system kernels: the live set changes, no graph
+  B->live.assign(ns, 1);
+  if (!all_stop && !direct && (rc = ensure_graph(B))) return rc;
   while (!all_stop) {
-    MF_HIP(hipGraphLaunch(B->exec, B->s));
+    if (direct) {
+      for (int i = 0; i < ns; i++) B->live[i] = B->host_st[i].stop ? 0 : 1;
+      if ((rc = record_chunk(B))) return rc;
+    } else {
+      MF_HIP(hipGraphLaunch(B->exec, B->s));
+    }
     if ((rc = read_states(B))) return rc;
     bool due = false, brk = false;
     all_stop = true;

@@ -70,7 +70,7 @@ def test_batch_autotune_and_cache(mf, tmp_path):
     assert rc == 0 and all(i["rel_residual"] <= 1e-10 for i in infos)
     # every work-list granularity gives the same batched solution
     ref = [x.clone() for x in xs]
-    for per, grid in [(1, 37), (32, 2048)]:
+    for per, grid in [(1, 37), (32, 2048), (1, -1)]:
         for x in xs:
             x.zero_()
         B.set_tuning(per, grid)
@@ -80,12 +80,13 @@ def test_batch_autotune_and_cache(mf, tmp_path):
             assert torch.allclose(x, r, rtol=0, atol=1e-9 * float(r.abs().max()))
 
 
-@pytest.mark.parametrize("tuning", [(1, 0), (4, 512), (1, 37)])
+@pytest.mark.parametrize("tuning", [(1, 0), (4, 512), (1, 37), (1, -1)])
 def test_batched_action_matches_oracle(mf, tuning):
     """One batched launch over uneven systems (k = 2..5, ragged sizes, one 20^3 mesh)
     against the oracle's action, system by system: FP64 operators at 1e-12 and the
     FP32 inner operators at 1e-5 (relative max-norm), one wavefront per work item
-    (grid 0) and persistent grids with coarse and fine work lists."""
+    (grid 0), persistent grids with coarse and fine work lists, and each system's own
+    kernels (grid -1)."""
     import torch
     import oracle
     sizes = [(3, 2), (5, 5), (4, 3), (20, 2), (6, 4), (2, 5), (7, 3), (9, 4)]
