@@ -193,8 +193,10 @@ def bench_simplex(mf, mg, reps=20):
     2048x2048x2 mesh for the bandwidth figure; patch scatter by default there, atomic
     for comparison) and vector P2/P3 tet elasticity (48^3 x 6 Kuhn tets perturbed
     +-0.2h, renumbered, lambda 1, mu 0.5) in FP64 and FP32 (MFMA contractions; patch
-    scatter by default, coloured launches for comparison). Per operator: kernel time
-    (every launch of one apply), GDoF/s, roofline fraction."""
+    scatter by default, coloured launches for comparison); the one-component tet
+    operators and the hyperelastic tangent on the same mesh; degrees 4-6 on smaller
+    meshes. Per operator: kernel time (every launch of one apply), GDoF/s, roofline
+    fraction."""
     import torch
     out = {}
     for m, tag, sc in ((64, "tri_p1_mass_64", mf.SCATTER_AUTO),
@@ -342,6 +344,32 @@ def bench_simplex(mf, mg, reps=20):
             log(f"  {tag}: {json.dumps(out[tag])}")
             del op, xt, yt
         del sp, space
+    del mesh
+    # degrees 4-6 (the dense kernel: a workgroup per block of cells, the points in
+    # chunks), 24^3 x 6 tets and 512^2 x 2 triangles, coloured scatter
+    for cell, k, kind, name, nc in (("tet", 4, mf.LAPLACIAN, "laplacian", 1), ("tet", 4, mf.ELASTICITY, "elasticity", 3),
+                                    ("tet", 6, mf.LAPLACIAN, "laplacian", 1), ("tri", 6, mf.HELMHOLTZ, "helmholtz", 1)):
+        if cell == "tet":
+            smesh = mg.tet_mesh(24, 0.2, config=2)
+            space = mg.tet_space(smesh, k, ncomp=nc, config=2)
+        else:
+            smesh = mg.tri_mesh(512, 0.2, config=0)
+            space = mg.tri_space(smesh, k, ncomp=nc)
+        sp = mf.Space.from_meshgen(space)
+        x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+        for prec, ptag in ((mf.F64, "fp64"), (mf.F32, "fp32")):
+            op = mf.Operator(sp, kind, prec, lam=1.0, mu=0.5)
+            xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+            yt = torch.empty_like(xt)
+            t = time_kernel(op, xt, yt, 5)
+            r = roof(op, t, prec)
+            tag = f"{cell}_{name}_p{k}_{ptag}"
+            out[tag] = {"cells": smesh.ncells, "ndofs": space.ndofs, "us": t * 1e6, "gdofs": space.ndofs / t / 1e9,
+                        "launches": op.info["cell_launches"], "qp": op.info["nqp"], "bound": r["bound"],
+                        "frac": r["frac"], "gbs": r["gbs"], "tflops": r["tflops"]}
+            log(f"  {tag}: {json.dumps(out[tag])}")
+            del op, xt, yt
+        del sp, space, smesh
     return out
 
 
@@ -718,7 +746,7 @@ def main():
     ap.add_argument("--c5-only", action="store_true", help="only the learned-preconditioner comparison")
     ap.add_argument("--detail-out", default=None, help="also write the detailed results (JSON) to this file")
     ap.add_argument("--c5-m", type=int, default=64, help="cells per direction of that problem")
-    ap.add_argument("--simplex-only", action="store_true", help="only the triangle mass and tet elasticity actions")
+    ap.add_argument("--simplex-only", action="store_true", help="only the simplex operator timings")
     ap.add_argument("--c4-only", action="store_true", help="only the batched 64-system solves")
     ap.add_argument("--table2", action="store_true",
                     help="only the D / Q / arithmetic-intensity table beside the paper's Table 2")

@@ -819,7 +819,12 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   op->nqp = nq;
   tet_lagrange(k, pts, phi, dphi);
   std::vector<T> tab;
-  if (k >= 4) {
+  // degrees 4-6 take the dense kernel (workgroup per cell block, points in chunks);
+  // so does the FP64 P3 Helmholtz operator, whose 64-point rule overflows the
+  // lane-per-cell kernel's registers (48^3 x 6 cells: 4.97 -> 3.86 ms; every other
+  // P2/P3 one-component operator measured slower there)
+  const bool dense = k >= 4 || (k == 3 && scalar && op->kind == MF_OP_HELMHOLTZ && sizeof(T) == 8);
+  if (dense) {
     tab = dense_simplex_tables<T>(3, pts, w, phi, dphi);
     simplex_dense_shape<T>(D, nq, sp->ncomp, 3, hyper, op->dense_cb, op->dense_qc);
   } else if (scalar) {
@@ -1098,7 +1103,7 @@ static void count_work(mf_op *op) {
                       (op->kind == MF_OP_ELASTICITY ? 10.0 : 0.0);
     fl = nc * (2.0 * fma + q * q * pt);
     by += nc * 6.0 * s + (op->has_coef ? nc * 4.0 * s : 0.0);
-  } else if ((op->cell_type == MF_CELL_TET || op->cell_type == MF_CELL_TRI) && op->degree >= 4) {
+  } else if (op->dense_cb > 0) {
     // dense kernel, per point and component: values and reference gradients 2 (1 + dim) D
     // forward and the same backward, push-forward and pull-back 4 dim^2, the pointwise
     // stress 4 dim (elasticity) and the weight; bytes: geometry dim^2 + 1 per cell
@@ -1177,7 +1182,7 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     QuadArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
                   op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, (T)op->lam, (T)op->mu};
     return launch_quad<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
-  } else if ((op->cell_type == MF_CELL_TET || op->cell_type == MF_CELL_TRI) && op->degree >= 4) {
+  } else if (op->dense_cb > 0) {  // simplices of degree 4-6, FP64 P3 tet Helmholtz
     SimplexDenseArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
                           op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, op->D, op->nqp, op->ncomp, op->kind,
                           op->dense_cb, op->dense_qc, (T)op->lam, (T)op->mu};
