@@ -111,19 +111,25 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             share no node; a full apply is one launch per colour with plain
  *             read-modify-write stores -- deterministic, bit-reproducible.
  *   ATOMIC    one launch, device-scope floating-point atomics.
- *   PATCH     hex Q1 only: cells are grouped into spatially compact patches (at
- *             most 512 cells, 1024 free nodes); a workgroup gathers its patch's
- *             nodes into on-chip memory, accumulates the cells there, and writes
- *             each node once, with a device atomic only where another patch
- *             shares the node. One launch; not bit-reproducible.
- *   AUTO      COLOURED for 3-component hex operators of degree >= 2 on meshes of
- *             at least 4096 cells and for scalar hex operators of degree >= 2 on
- *             at least 2^18 cells; PATCH for hex Q1 on at least 2^15 cells; tets
- *             of degree >= 2, quad and triangle ELASTICITY (at least 4096 cells)
- *             and the other triangle operators but the P1 mass on at least 2^20
- *             cells COLOURED; else ATOMIC (the measured choices).
+ *   PATCH     cells are grouped into spatially compact patches; a workgroup
+ *             accumulates its patch's cells in on-chip memory and writes each
+ *             node once: nodes of no other patch directly, shared nodes into
+ *             per-patch slots that a second launch sums in patch order
+ *             (deterministic), or for hex Q1 (patches of at most 512 cells, 1024
+ *             free nodes) with a device atomic (not bit-reproducible). Built for
+ *             the hex MASS, HELMHOLTZ, LAPLACIAN and POISSON operators of degree 1
+ *             (two points per direction) and 2-6 (k+1 points), P2 / P3 tet
+ *             ELASTICITY and one-component tet operators, and the P1 triangle mass.
+ *   AUTO      PATCH for hex Q1 on at least 2^15 cells, for those hex operators of
+ *             degree 2-4, and for the tet and triangle forms above on at least
+ *             2^15 cells; otherwise COLOURED for 3-component hex operators of
+ *             degree >= 2 on at least 4096 cells, scalar hex operators of degree
+ *             >= 2 on at least 2^18 cells, tets of degree >= 2, quad and triangle
+ *             ELASTICITY (at least 4096 cells) and the other triangle operators
+ *             but the P1 mass on at least 2^20 cells; else ATOMIC (the measured
+ *             choices).
  * Range applies (mf_op_apply_range*) always use ATOMIC. Errors at mf_op_create:
- * MF_EUNSUPPORTED for PATCH on other cells or degrees. */
+ * MF_EUNSUPPORTED for PATCH on other cells, kinds or degrees. */
 enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2, MF_SCATTER_PATCH = 3 };
 
 typedef struct {

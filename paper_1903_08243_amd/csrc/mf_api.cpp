@@ -819,12 +819,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   op->nqp = nq;
   tet_lagrange(k, pts, phi, dphi);
   std::vector<T> tab;
-  // degrees 4-6 take the dense kernel (workgroup per cell block, points in chunks);
-  // so does the FP64 P3 Helmholtz operator, whose 64-point rule overflows the
-  // lane-per-cell kernel's registers (48^3 x 6 cells: 4.97 -> 3.86 ms; every other
-  // P2/P3 one-component operator measured slower there)
-  const bool dense = k >= 4 || (k == 3 && scalar && op->kind == MF_OP_HELMHOLTZ && sizeof(T) == 8);
-  if (dense) {
+  if (k >= 4) {  // the dense kernel: a workgroup per cell block, the points in chunks
     tab = dense_simplex_tables<T>(3, pts, w, phi, dphi);
     simplex_dense_shape<T>(D, nq, sp->ncomp, 3, hyper, op->dense_cb, op->dense_qc);
   } else if (scalar) {
@@ -836,6 +831,11 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
       const double *x = &pts[3 * q];
       tab.push_back((T)(1.0 - x[0] - x[1] - x[2]));
       for (int a = 0; a < 3; a++) tab.push_back((T)x[a]);
+    }
+    if (k >= 2) {  // per-lane operands of the MFMA contractions
+      std::vector<double> mt((size_t)tet_mfma_scalar_table_floats(k, nq));
+      tet_mfma_scalar_tables(k, nq, phi.data(), dphi.data(), mt.data(), sizeof(T) == 8);
+      for (double v : mt) tab.push_back((T)v);
     }
   } else {
     for (double v : dphi) tab.push_back((T)v);
@@ -877,7 +877,11 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     if (!rc) MF_HIP(hipStreamSynchronize(s));  // the host vectors go out of scope
     if (rc) return rc;
   }
-  std::vector<T> geo((size_t)nb * 10 * 64, T(0)), gflat(op->spatched ? (size_t)nc * 10 : 0);
+  // patch slots carry the geometry and, for MASS and POISSON, the four vertex
+  // coefficients (1 without one)
+  const bool slot_coef = scalar && (op->kind == MF_OP_MASS || op->kind == MF_OP_POISSON);
+  const int G = slot_coef ? 14 : 10;
+  std::vector<T> geo((size_t)nb * 10 * 64, T(0)), gflat(op->spatched ? (size_t)nc * G : 0);
   for (int64_t K = 0; K < nc; K++) {
     const int32_t *cv = sp->cell2vert_int.data() + K * 4;
     double J[3][3];
@@ -901,8 +905,11 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     for (int bb = 0; bb < 3; bb++)
       for (int a = 0; a < 3; a++) geo[(b * 10 + 3 * bb + a) * 64 + l] = (T)(R[bb][a] / det);
     geo[(b * 10 + 9) * 64 + l] = (T)std::fabs(det);
-    if (op->spatched)
-      for (int e = 0; e < 10; e++) gflat[(size_t)K * 10 + e] = geo[(b * 10 + e) * 64 + l];
+    if (op->spatched) {
+      for (int e = 0; e < 10; e++) gflat[(size_t)K * G + e] = geo[(b * 10 + e) * 64 + l];
+      for (int v = 0; v < G - 10; v++)
+        gflat[(size_t)K * G + 10 + v] = op->has_coef ? (T)pr->vertex_coef[cv[v]] : T(1);
+    }
   }
   rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
   if (!rc && op->spatched) {
@@ -911,7 +918,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     // 384 / 2700 in FP64 (352 us; 256 / 2048: 366 us), 256 / 2048 in FP32 (210 us)
     const bool f64 = sizeof(T) == 8;
     const int cap = k <= 2 ? 384 : (f64 ? 384 : 256), nmax = k <= 2 ? 2048 : (f64 ? 2700 : 2048);
-    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, 10, cap, nmax, s);
+    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, G, cap, nmax, s);
   }
   if (!rc) MF_HIP(hipStreamSynchronize(s));
   return rc;
@@ -1182,7 +1189,7 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     QuadArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
                   op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, (T)op->lam, (T)op->mu};
     return launch_quad<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
-  } else if (op->dense_cb > 0) {  // simplices of degree 4-6, FP64 P3 tet Helmholtz
+  } else if (op->dense_cb > 0) {  // simplices of degree 4-6
     SimplexDenseArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
                           op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, op->D, op->nqp, op->ncomp, op->kind,
                           op->dense_cb, op->dense_qc, (T)op->lam, (T)op->mu};
@@ -1241,7 +1248,8 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
       } else {
         TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, 0, op->ncells, (T)op->lam,
                      (T)op->mu, nullptr, 0, 0, nullptr, nullptr, nullptr};
-        rc = launch_tet_elasticity_patches<T>(op->degree, op->nqp, a, pa, s);
+        rc = op->ncomp == 1 ? launch_tet_scalar_patches<T>(op->degree, op->nqp, op->kind, a, pa, s)
+                            : launch_tet_elasticity_patches<T>(op->degree, op->nqp, a, pa, s);
       }
       if (!rc)
         rc = launch_simplex_shared_reduce<T>(op->sp_sptr.as<int32_t>(), op->sp_snode.as<int32_t>(),
@@ -1433,9 +1441,10 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
-  // tet elasticity P2/P3 (the MFMA kernel) and the P1 triangle mass: patch scatter on
-  // request, and by default from 2^15 cells
-  const bool tet_patchable = (ct == MF_CELL_TET && kind == MF_OP_ELASTICITY && (sp->degree == 2 || sp->degree == 3)) ||
+  // P2/P3 tet elasticity and one-component tet operators (the MFMA kernels) and the P1
+  // triangle mass: patch scatter on request, and by default from 2^15 cells
+  const bool tet_patchable = (ct == MF_CELL_TET && (sp->degree == 2 || sp->degree == 3) &&
+                              (kind == MF_OP_ELASTICITY || (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
                              (ct == MF_CELL_TRI && kind == MF_OP_MASS && sp->degree == 1);
   // hex degrees 2-6 (the pencil kernel): patch scatter on request, and by default for
   // degrees 2-4. A patch is one workgroup's cells (7, 4 and 2 cells for k = 2..4, 3 and
@@ -1453,8 +1462,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     op->hpatched = true;
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)
-      return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, tet "
-                                   "P2/P3 elasticity and the P1 triangle mass");
+      return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, P2/P3 "
+                                   "tet elasticity and one-component tet operators, and the P1 triangle mass");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
              kind <= MF_OP_POISSON && op->nq1d == 2) {

@@ -175,9 +175,11 @@ template <typename T>
 int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s);
 // one-component MASS, HELMHOLTZ, LAPLACIAN, POISSON on P1..P3 tets; tab holds phi
 // [nq][D], the reference gradients [nq][D][3], the weights [nq] and the vertex
-// basis [nq][4] at the points
+// basis [nq][4] at the points, and for P2 / P3 (MFMA) then tet_mfma_scalar_tables
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s);
+int tet_mfma_scalar_table_floats(int k, int nq);
+void tet_mfma_scalar_tables(int k, int nq, const double *phi, const double *dphi, double *out, bool f64);
 // the same forms on P1..P3 triangles (TetArgs as a generic simplex argument block:
 // geo [cell/64][5][64], coef [cell/64][3][64], tab phi, gradients [nq][D][2], weights,
 // vertex basis [nq][3])
@@ -328,6 +330,11 @@ template <typename T> struct SimplexPatchArgs {
 template <typename T>
 int launch_tet_elasticity_patches(int k, int nq, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
                                   hipStream_t s);
+// the one-component P2 / P3 tet forms with the patch scatter (slot geometry: Kinv,
+// |det| and, for MASS and POISSON, the four vertex coefficients: 10 or 14 entries)
+template <typename T>
+int launch_tet_scalar_patches(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
+                              hipStream_t s);
 // hex pencil kernel with the patch scatter (degrees 2-6): a.map / gmap / geo / coef in
 // patch-slot order (hex_cells_per_patch(N) slots per patch) and the patch fields set
 template <typename T> int launch_hex_cell_patches(int N, int kind, const HexArgs<T> &a, int npatch, hipStream_t s);

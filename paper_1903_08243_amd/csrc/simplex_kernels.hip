@@ -224,17 +224,20 @@ static int launch_tet_scalar_k(int kind, const TetArgs<T> &a, bool atomic, hipSt
   return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
 }
 
+template <typename T>
+static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p,
+                                  bool atomic, hipStream_t s);
+
 // rules of the tet quadrature table: 1 point (degree 1), 4 (degree 2), 14 (degree 5),
-// 64 (conical Gauss-Jacobi product rule, degree 7)
+// 64 (conical Gauss-Jacobi product rule, degree 7). P1 runs the lane-per-cell kernel;
+// P2 and P3 run on MFMA (the tables then carry the per-lane operands after the vertex
+// basis)
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
   if (k == 1 && nq == 1) return launch_tet_scalar_k<T, 1, 1>(kind, a, atomic, s);
   if (k == 1 && nq == 4) return launch_tet_scalar_k<T, 1, 4>(kind, a, atomic, s);
   if (k == 1 && nq == 14) return launch_tet_scalar_k<T, 1, 14>(kind, a, atomic, s);
-  if (k == 2 && nq == 4) return launch_tet_scalar_k<T, 2, 4>(kind, a, atomic, s);
-  if (k == 2 && nq == 14) return launch_tet_scalar_k<T, 2, 14>(kind, a, atomic, s);
-  if (k == 3 && nq == 14) return launch_tet_scalar_k<T, 3, 14>(kind, a, atomic, s);
-  if (k == 3 && nq == 64) return launch_tet_scalar_k<T, 3, 64>(kind, a, atomic, s);  // degree 6-7
+  if (k == 2 || k == 3) return launch_tet_scalar_mfma<T>(k, nq, kind, a, nullptr, atomic, s);
   return fail(MF_EUNSUPPORTED, "tet scalar operator: degree / rule");
 }
 template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);
@@ -672,6 +675,258 @@ __global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs
       for (int c = 0; c < 3; c++) d[c] = P.accumulate ? d[c] + (T)acc[3 * e + c] : (T)acc[3 * e + c];
     }
   }
+}
+
+// ----------------------------------------------------------------- scalar tet operators on MFMA
+// The one-component forms of tet_scalar_kernel (degrees 2 and 3) in the GEMM form of the
+// elasticity kernel: a wavefront owns 16 cells and one accumulator. The forward rows
+// (q = 4 r + g, a) carry the reference gradient for a = 0..2 and the basis value in the
+// row a = 3 (padding in the elasticity tables), so one accumulator gives lane (cell, g)
+// the gradient and the value of u at point q. The backward K-steps are (r, a) with the
+// gradient rows and, for the kinds with a value term, (r, 3) with the basis values.
+// gp: the cell's geometry (Kinv, |det|), cp: its four vertex coefficients (null: 1),
+// both with entries 64 apart. Tables after the lane kernel's (phi, gradients, weights,
+// vertex basis): fwd[r][s][64], bwd[t][r][4][64] (tet_mfma_scalar_tables).
+template <typename T, int K, int NQ, int KIND>
+__device__ __forceinline__ void tet_scalar_cells16(const TetArgs<T> &A, const int32_t *mp, const T *gp,
+                                                   const T *cp, const bool valid, const int lane,
+                                                   typename Mfma16<T>::V (&yacc)[((K + 1) * (K + 2) * (K + 3) / 6 + 15) / 16]) {
+  using MF = Mfma16<T>;
+  using V4 = typename MF::V;
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  constexpr int NR = (NQ + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
+  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
+  constexpr bool GRAD = KIND != MF_OP_MASS;
+  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
+  const int g = lane >> 4;
+  T Ki[9];
+#pragma unroll
+  for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
+  const T adet = gp[9 * 64];
+  T cv[4] = {T(1), T(1), T(1), T(1)};
+  if (COEF && cp)
+#pragma unroll
+    for (int v = 0; v < 4; v++) cv[v] = cp[v * 64];
+  const T *qw = A.tab + NQ * D * 4;
+  const T *vb = qw + NQ;
+  const T *fwd = vb + NQ * 4;
+  const T *bwd = fwd + NR * NS * 64;
+  T xv[NS];
+#pragma unroll
+  for (int s = 0; s < NS; s++) {
+    const int i = 4 * s + g;
+    const int idx = (valid && i < D) ? mp[i * 64] : -1;
+    xv[s] = idx >= 0 ? A.x[idx] : T(0);
+  }
+#pragma unroll
+  for (int t = 0; t < NT; t++) yacc[t] = V4{T(0), T(0), T(0), T(0)};
+  constexpr int RU = NR <= 4 ? NR : 1;
+#pragma unroll RU
+  for (int r = 0; r < NR; r++) {
+    V4 acc = V4{T(0), T(0), T(0), T(0)};
+#pragma unroll
+    for (int s = 0; s < NS; s++) acc = MF::fma(fwd[(r * NS + s) * 64 + lane], xv[s], acc);
+    const int q = 4 * r + g, qq = q < NQ ? q : 0;
+    const T wd = q < NQ ? qw[qq] * adet : T(0);
+    T cq = T(1);
+    if constexpr (COEF) cq = vb[4 * qq] * cv[0] + vb[4 * qq + 1] * cv[1] + vb[4 * qq + 2] * cv[2] + vb[4 * qq + 3] * cv[3];
+    T P[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (GRAD) {
+      // physical gradient G_a = sum_b g_b dxi_b/dx_a scaled by w |det| (kappa), and its
+      // reference-direction form P_b = sum_a dxi_b/dx_a G_a
+      const T sc = wd * (KIND == MF_OP_POISSON ? cq : T(1));
+      T G[3];
+#pragma unroll
+      for (int a = 0; a < 3; a++) G[a] = sc * (acc[0] * Ki[a] + acc[1] * Ki[3 + a] + acc[2] * Ki[6 + a]);
+#pragma unroll
+      for (int d = 0; d < 3; d++) P[d] = G[0] * Ki[3 * d] + G[1] * Ki[3 * d + 1] + G[2] * Ki[3 * d + 2];
+    }
+    if constexpr (VAL) P[3] = wd * (KIND == MF_OP_MASS ? cq : T(1)) * acc[3];
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+      const T *bt = bwd + (t * NR + r) * 4 * 64 + lane;
+      if constexpr (GRAD)
+#pragma unroll
+        for (int d = 0; d < 3; d++) yacc[t] = MF::fma(bt[d * 64], P[d], yacc[t]);
+      if constexpr (VAL) yacc[t] = MF::fma(bt[3 * 64], P[3], yacc[t]);
+    }
+  }
+}
+
+template <typename T, int K, int NQ, int KIND, bool ATOMIC>
+__global__ void __launch_bounds__(64) tet_scalar_mfma_kernel(const TetArgs<T> A) {
+  using V4 = typename Mfma16<T>::V;
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  constexpr int NT = (D + 15) / 16;
+  const int lane = threadIdx.x;
+  const int j = lane & 15, g = lane >> 4;
+  // one wavefront per 16 cells; contiguous ranges of quarters per XCD
+  const int64_t nqb = 4 * ((A.c1 + 63) / 64 - A.c0 / 64), per = (nqb + 7) / 8;
+  const int64_t qb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (qb >= nqb) return;
+  const int64_t batch = A.c0 / 64 + qb / 4;
+  const int cl = 16 * (int)(qb % 4) + j;
+  const int64_t cell = batch * 64 + cl;
+  bool valid = cell >= A.c0 && cell < A.c1;
+  if (valid && A.cell_user) {
+    const int64_t u = A.cell_user[cell];
+    valid = u >= A.ulo && u < A.uhi;
+  }
+  const int32_t *mp = A.map + batch * (D * 64) + cl;
+  V4 yacc[NT];
+  tet_scalar_cells16<T, K, NQ, KIND>(A, mp, A.geo + batch * (10 * 64) + cl,
+                                     A.coef ? A.coef + batch * (4 * 64) + cl : nullptr, valid, lane, yacc);
+  constexpr bool F64 = sizeof(T) == 8;
+#pragma unroll
+  for (int t = 0; t < NT; t++)
+#pragma unroll
+    for (int v = 0; v < 4; v++) {
+      const int i = F64 ? 16 * t + g + 4 * v : 16 * t + 4 * g + v;
+      const int idx = (valid && i < D) ? mp[i * 64] : -1;
+      if (idx >= 0) {
+        if constexpr (ATOMIC) atomic_add_s(&A.y[idx], yacc[t][v]);
+        else A.y[idx] += yacc[t][v];  // cells of one launch share no node
+      }
+    }
+}
+
+// Patch scatter of the scalar forms (as tet_elasticity_patch_kernel, one component;
+// the slot geometry holds Kinv, |det| and, with a coefficient, the four vertex values).
+template <typename T, int K, int NQ, int KIND>
+__global__ void __launch_bounds__(256) tet_scalar_patch_kernel(const TetArgs<T> A, const SimplexPatchArgs<T> P) {
+  using V4 = typename Mfma16<T>::V;
+  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
+  constexpr int NT = (D + 15) / 16;
+  constexpr bool F64 = sizeof(T) == 8;
+  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
+  constexpr int G = COEF ? 14 : 10;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double *acc = reinterpret_cast<double *>(smem_raw);  // FP64 sums, as in the elasticity patch kernel
+  const int64_t p = xcd_batch(blockIdx.x, P.npatch);
+  if (p >= P.npatch) return;  // whole workgroup: no barrier skipped
+  const int n0 = P.nptr[p], nn = P.nptr[p + 1] - n0;
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) acc[e] = 0.0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int j = lane & 15, g = lane >> 4, cl = 16 * w + j;
+  const int nblk = P.cap / 64;
+  for (int r = 0; r < nblk; r++) {
+    const int64_t blk = p * nblk + r;
+    const T *gp = P.geo + blk * (G * 64) + cl;
+    V4 yacc[NT];
+    tet_scalar_cells16<T, K, NQ, KIND>(A, P.map + blk * (D * 64) + cl, gp, COEF ? gp + 10 * 64 : nullptr, true,
+                                       lane, yacc);
+    const uint16_t *lp = P.lmap + blk * (D * 64) + cl;
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+      for (int v = 0; v < 4; v++) {
+        const int i = F64 ? 16 * t + g + 4 * v : 16 * t + 4 * g + v;
+        if (i < D) {
+          const int l = lp[i * 64];
+          if (l != kSlotSkip) atomicAdd(&acc[l], (double)yacc[t][v]);
+        }
+      }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
+    const int32_t o = P.out[n0 + e];
+    if (o & kSharedOut) P.sbuf[o & (kSharedOut - 1)] = (T)acc[e];
+    else A.y[o] = P.accumulate ? A.y[o] + (T)acc[e] : (T)acc[e];
+  }
+}
+
+template <typename T, int K, int NQ, int KIND>
+static int launch_tet_scalar_mfma_kq(const TetArgs<T> &a, bool atomic, hipStream_t s) {
+  const int64_t nqb = 4 * ((a.c1 + 63) / 64 - a.c0 / 64);
+  if (a.c1 <= a.c0) return MF_OK;
+  const dim3 g((unsigned)(((nqb + 7) / 8) * 8)), b(64);
+  if (atomic) tet_scalar_mfma_kernel<T, K, NQ, KIND, true><<<g, b, 0, s>>>(a);
+  else tet_scalar_mfma_kernel<T, K, NQ, KIND, false><<<g, b, 0, s>>>(a);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+template <typename T, int K, int NQ, int KIND>
+static int launch_tet_scalar_patch_kq(const TetArgs<T> &a, const SimplexPatchArgs<T> &p, hipStream_t s) {
+  if (p.npatch <= 0) return MF_OK;
+  const size_t lds = (size_t)p.nmax * sizeof(double);
+  if (lds > 64 * 1024) return fail(MF_EUNSUPPORTED, "tet patch scatter: patch node list too long for LDS");
+  tet_scalar_patch_kernel<T, K, NQ, KIND><<<dim3((unsigned)xcd_grid(p.npatch)), dim3(256), lds, s>>>(a, p);
+  MF_HIP(hipGetLastError());
+  return MF_OK;
+}
+
+// kind dispatch for one (K, NQ): patch scatter when p is set, else atomic or coloured
+template <typename T, int K, int NQ>
+static int launch_tet_scalar_mfma_k(int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p, bool atomic,
+                                    hipStream_t s) {
+  switch (kind) {
+    case MF_OP_MASS:
+      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_MASS>(a, *p, s)
+               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_MASS>(a, atomic, s);
+    case MF_OP_HELMHOLTZ:
+      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_HELMHOLTZ>(a, *p, s)
+               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_HELMHOLTZ>(a, atomic, s);
+    case MF_OP_LAPLACIAN:
+      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_LAPLACIAN>(a, *p, s)
+               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_LAPLACIAN>(a, atomic, s);
+    case MF_OP_POISSON:
+      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_POISSON>(a, *p, s)
+               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_POISSON>(a, atomic, s);
+  }
+  return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
+}
+
+// P2 and P3 on the rules of the scalar kinds: 4 points (degree 2), 14 (degree 5), 64
+// (degree 7)
+template <typename T>
+static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p,
+                                  bool atomic, hipStream_t s) {
+  if (k == 2 && nq == 4) return launch_tet_scalar_mfma_k<T, 2, 4>(kind, a, p, atomic, s);
+  if (k == 2 && nq == 14) return launch_tet_scalar_mfma_k<T, 2, 14>(kind, a, p, atomic, s);
+  if (k == 3 && nq == 14) return launch_tet_scalar_mfma_k<T, 3, 14>(kind, a, p, atomic, s);
+  if (k == 3 && nq == 64) return launch_tet_scalar_mfma_k<T, 3, 64>(kind, a, p, atomic, s);
+  return fail(MF_EUNSUPPORTED, "tet scalar operator on MFMA: degree / rule");
+}
+
+template <typename T>
+int launch_tet_scalar_patches(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
+                              hipStream_t s) {
+  return launch_tet_scalar_mfma<T>(k, nq, kind, a, &p, false, s);
+}
+template int launch_tet_scalar_patches<double>(int, int, int, const TetArgs<double> &,
+                                               const SimplexPatchArgs<double> &, hipStream_t);
+template int launch_tet_scalar_patches<float>(int, int, int, const TetArgs<float> &,
+                                              const SimplexPatchArgs<float> &, hipStream_t);
+
+// Per-lane MFMA operands of the scalar forms: the forward rows of tet_mfma_tables with
+// the basis value phi[q][i] in the row a = 3, and backward K-steps for a = 0..3.
+int tet_mfma_scalar_table_floats(int k, int nq) {
+  const int D = (k + 1) * (k + 2) * (k + 3) / 6;
+  const int NR = (nq + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
+  return NR * NS * 64 + NT * NR * 4 * 64;
+}
+
+void tet_mfma_scalar_tables(int k, int nq, const double *phi, const double *dphi, double *out, bool f64) {
+  const int D = (k + 1) * (k + 2) * (k + 3) / 6;
+  const int NR = (nq + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
+  double *fwd = out, *bwd = out + NR * NS * 64;
+  auto entry = [&](int q, int i, int a) {
+    if (q >= nq || i >= D) return 0.0;
+    return a < 3 ? dphi[(q * D + i) * 3 + a] : phi[q * D + i];
+  };
+  for (int r = 0; r < NR; r++)
+    for (int s = 0; s < NS; s++)
+      for (int l = 0; l < 64; l++) {
+        const int m = l % 16, kk = l / 16;
+        const int q = 4 * r + (f64 ? m % 4 : m / 4), a = f64 ? m / 4 : m % 4;
+        fwd[(r * NS + s) * 64 + l] = entry(q, 4 * s + kk, a);
+      }
+  for (int t = 0; t < NT; t++)
+    for (int r = 0; r < NR; r++)
+      for (int d = 0; d < 4; d++)
+        for (int l = 0; l < 64; l++) bwd[((t * NR + r) * 4 + d) * 64 + l] = entry(4 * r + l / 16, 16 * t + l % 16, d);
 }
 
 template <typename T>

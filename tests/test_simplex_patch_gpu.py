@@ -1,5 +1,5 @@
-"""Patch scatter of the tet elasticity action (P2, P3) and of the P1 triangle mass
-against the oracle.
+"""Patch scatter of the tet elasticity action (P2, P3), of the one-component P2 / P3
+tet operators and of the P1 triangle mass against the oracle.
 
 A patch workgroup sums its cells' local results in LDS and writes each of its nodes
 once (straight into y, or into a slot that the shared-node reduction sums), so an
@@ -100,6 +100,56 @@ def test_tet_patch_matches_coloured_scatter(mf, k):
     b = mf.Operator(sp, mf.ELASTICITY, mf.F64, lam=1.0, mu=0.5, scatter=mf.SCATTER_COLOURED).apply(x)
     a, b = a.cpu().numpy(), b.cpu().numpy()
     assert _relerr(a, b) <= 1e-13
+
+
+# one-component forms on 7^3 x 6 = 2058 tets: several patches (384 or 256 cells), the
+# last one ragged; MASS and POISSON with a vertex coefficient, MASS also without
+SCALAR = [(0, True), (0, False), (1, False), (2, False), (3, True)]
+
+
+@pytest.mark.parametrize("dirichlet", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind,coef", SCALAR)
+@pytest.mark.parametrize("k", [2, 3])
+def test_tet_scalar_patch_action(mf, k, kind, coef, prec, dirichlet):
+    import torch
+    print(f"tet scalar patch k={k} kind={kind} coef={coef} prec={prec} dirichlet={dirichlet}", flush=True)
+    mesh = mg.tet_mesh(7, 0.2, config=2, seed_k=k)
+    space = mg.tet_space(mesh, k, ncomp=1, config=2, seed_k=k)
+    c = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if coef else None
+    x = mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k)
+    bnd = space.boundary_nodes() if dirichlet else np.zeros(0, np.int64)
+    mask = None
+    if dirichlet:
+        mask = np.zeros(space.nnodes, np.uint8)
+        mask[bnd] = 1
+    xm = x.copy()
+    xm[bnd] = 0.0
+    ref = oracle.OracleOp(space, kind, coef=c).apply(xm)
+    ref[bnd] = x[bnd]
+    op = mf.Operator(mf.Space.from_meshgen(space), kind, prec, vertex_coef=c, dirichlet=mask,
+                     scatter=mf.SCATTER_PATCH)
+    assert op.info["clears_output"] == 0 and op.info["scatter"] == mf.SCATTER_PATCH
+    xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+    y = op.apply(xt, torch.full_like(xt, float("nan"))).double().cpu().numpy()
+    assert np.isfinite(y).all()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+    if not dirichlet:
+        # accumulating form (internal numbering), as inside CG
+        y0 = torch.tensor(mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_RHS, k), device="cuda",
+                          dtype=op.torch_dtype)
+        yi = op.apply_internal(xt).double().cpu().numpy()
+        yt = y0.clone()
+        op.apply_range_internal(0, op.info["ncells"], xt, yt, accumulate=True)
+        d = (yt.double() - y0.double()).cpu().numpy()
+        assert np.abs(d - yi).max() <= 4 * TOL[prec] * (np.abs(yi).max() + 1.0)
+
+
+def test_tet_scalar_patch_rejected_for_p1(mf):
+    mesh = mg.tet_mesh(2, 0.2, config=2)
+    space = mg.tet_space(mesh, 1, ncomp=1, config=2)
+    with pytest.raises(mf.MFError, match="patch scatter"):
+        mf.Operator(mf.Space.from_meshgen(space), mf.LAPLACIAN, mf.F64, scatter=mf.SCATTER_PATCH)
 
 
 # 48 x 48 x 2 = 4608 triangles: three patches of 2048 cells, the last one ragged
