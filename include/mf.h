@@ -119,7 +119,8 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             free nodes) with a device atomic (not bit-reproducible). Built for
  *             the hex MASS, HELMHOLTZ, LAPLACIAN and POISSON operators of degree 1
  *             (two points per direction) and 2-6 (k+1 points), P2 / P3 tet
- *             ELASTICITY and one-component tet operators, and the P1 triangle mass.
+ *             ELASTICITY, P1-P3 one-component tet operators and the P1 triangle
+ *             mass.
  *   AUTO      PATCH for hex Q1 on at least 2^15 cells, for those hex operators of
  *             degree 2-4, and for the tet and triangle forms above on at least
  *             2^15 cells; otherwise COLOURED for 3-component hex operators of

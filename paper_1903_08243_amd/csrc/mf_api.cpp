@@ -832,11 +832,10 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
       tab.push_back((T)(1.0 - x[0] - x[1] - x[2]));
       for (int a = 0; a < 3; a++) tab.push_back((T)x[a]);
     }
-    if (k >= 2) {  // per-lane operands of the MFMA contractions
-      std::vector<double> mt((size_t)tet_mfma_scalar_table_floats(k, nq));
-      tet_mfma_scalar_tables(k, nq, phi.data(), dphi.data(), mt.data(), sizeof(T) == 8);
-      for (double v : mt) tab.push_back((T)v);
-    }
+    // per-lane operands of the MFMA contractions
+    std::vector<double> mt((size_t)tet_mfma_scalar_table_floats(k, nq));
+    tet_mfma_scalar_tables(k, nq, phi.data(), dphi.data(), mt.data(), sizeof(T) == 8);
+    for (double v : mt) tab.push_back((T)v);
   } else {
     for (double v : dphi) tab.push_back((T)v);
     for (double v : w) tab.push_back((T)v);
@@ -917,7 +916,8 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     // nodes: P2 384 cells / 2048 nodes (FP64 72, FP32 57 us; 512 cells: 80, 74 us), P3
     // 384 / 2700 in FP64 (352 us; 256 / 2048: 366 us), 256 / 2048 in FP32 (210 us)
     const bool f64 = sizeof(T) == 8;
-    const int cap = k <= 2 ? 384 : (f64 ? 384 : 256), nmax = k <= 2 ? 2048 : (f64 ? 2700 : 2048);
+    int cap = k <= 2 ? 384 : (f64 ? 384 : 256), nmax = k <= 2 ? 2048 : (f64 ? 2700 : 2048);
+    if (k == 1) cap = 1024;  // one-component P1: about 200 nodes per 1024 cells
     rc = setup_simplex_patches<T>(op, sp, m, true, gflat, G, cap, nmax, s);
   }
   if (!rc) MF_HIP(hipStreamSynchronize(s));
@@ -1441,10 +1441,11 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
-  // P2/P3 tet elasticity and one-component tet operators (the MFMA kernels) and the P1
-  // triangle mass: patch scatter on request, and by default from 2^15 cells
-  const bool tet_patchable = (ct == MF_CELL_TET && (sp->degree == 2 || sp->degree == 3) &&
-                              (kind == MF_OP_ELASTICITY || (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
+  // P2/P3 tet elasticity, P1-P3 one-component tet operators (the MFMA kernels) and the
+  // P1 triangle mass: patch scatter on request, and by default from 2^15 cells
+  const bool tet_patchable = (ct == MF_CELL_TET && sp->degree <= 3 &&
+                              ((kind == MF_OP_ELASTICITY && sp->degree >= 2) ||
+                               (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
                              (ct == MF_CELL_TRI && kind == MF_OP_MASS && sp->degree == 1);
   // hex degrees 2-6 (the pencil kernel): patch scatter on request, and by default for
   // degrees 2-4. A patch is one workgroup's cells (7, 4 and 2 cells for k = 2..4, 3 and
@@ -1463,7 +1464,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)
       return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, P2/P3 "
-                                   "tet elasticity and one-component tet operators, and the P1 triangle mass");
+                                   "tet elasticity, P1-P3 one-component tet operators and the P1 triangle mass");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
              kind <= MF_OP_POISSON && op->nq1d == 2) {

@@ -98,155 +98,24 @@ __global__ void __launch_bounds__(192) tet_elasticity_kernel(const TetArgs<T> A)
 // ----------------------------------------------------------------- scalar tet operators
 // MASS int c u v, HELMHOLTZ int grad u . grad v + u v, LAPLACIAN int grad u . grad v,
 // POISSON int kappa grad u . grad v on affine tets (supplementary operator list), with
-// the vertex coefficient interpolated by the vertex basis. One lane per cell, one
-// wavefront per workgroup (64 cells of the AoSoA layout); the basis tables are the
-// same for every lane (scalar loads). Dense tabulation: simplices are not
-// sum-factorised.
-template <typename T, int K, int NQ, int KIND, bool ATOMIC>
-__global__ void __launch_bounds__(64) tet_scalar_kernel(const TetArgs<T> A) {
-  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
-  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
-  constexpr bool GRAD = KIND != MF_OP_MASS;
-  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
-  const int lane = threadIdx.x;
-  const int64_t nbt = (A.c1 + 63) / 64 - A.c0 / 64, per = (nbt + 7) / 8;
-  const int64_t bl = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (bl >= nbt) return;
-  const int64_t batch = A.c0 / 64 + bl;
-  const int64_t cell = batch * 64 + lane;
-  bool valid = cell >= A.c0 && cell < A.c1;
-  if (valid && A.cell_user) {
-    const int64_t u = A.cell_user[cell];
-    valid = u >= A.ulo && u < A.uhi;
-  }
-  const int32_t *mp = A.map + batch * (D * 64) + lane;
-  const T *gp = A.geo + batch * (10 * 64) + lane;
-  T Ki[9];
-#pragma unroll
-  for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
-  const T adet = gp[9 * 64];
-  T cv[4] = {T(1), T(1), T(1), T(1)};
-  if (COEF && A.coef)
-#pragma unroll
-    for (int v = 0; v < 4; v++) cv[v] = A.coef[(batch * 4 + v) * 64 + lane];
-  T xe[D], ye[D];
-#pragma unroll
-  for (int i = 0; i < D; i++) {
-    const int idx = valid ? mp[i * 64] : -1;
-    xe[i] = idx >= 0 ? A.x[idx] : T(0);
-    ye[i] = T(0);
-  }
-  // P3 in FP64: one point's 80 table values do not fit the scalar registers, so the
-  // tables are staged in LDS once per workgroup and read as same-address broadcasts
-  // (1237 -> 954 us at 48^3 x 6 cells; FP32 spills half as much and ran slower staged)
-  constexpr bool STAGE = K == 3 && sizeof(T) == 8 && NQ <= 14;  // larger rules exceed LDS
-  constexpr int NTAB = NQ * D * 4 + NQ * 5;
-  __shared__ T stab[STAGE ? NTAB : 1];
-  const T *tab = A.tab;
-  if constexpr (STAGE) {
-    for (int i = lane; i < NTAB; i += 64) stab[i] = A.tab[i];
-    __syncthreads();
-    tab = stab;
-  }
-  const T *__restrict__ phi = tab;
-  const T *__restrict__ dphi = phi + NQ * D;
-  const T *__restrict__ qw = dphi + NQ * D * 3;
-  const T *__restrict__ vb = qw + NQ;
-  // kept rolled: unrolled, the table loads of every point are hoisted and spill
-#pragma unroll 1
-  for (int q = 0; q < NQ; q++) {
-    const T *pq = phi + q * D, *tq = dphi + q * D * 3;
-    const T wd = qw[q] * adet;
-    T cq = T(1);
-    if (COEF) cq = vb[4 * q] * cv[0] + vb[4 * q + 1] * cv[1] + vb[4 * q + 2] * cv[2] + vb[4 * q + 3] * cv[3];
-    T f0 = T(0), P0 = T(0), P1 = T(0), P2 = T(0);
-    if constexpr (VAL) {
-      T u = T(0);
-#pragma unroll
-      for (int i = 0; i < D; i++) u += xe[i] * pq[i];
-      f0 = wd * (KIND == MF_OP_MASS ? cq : T(1)) * u;
-    }
-    if constexpr (GRAD) {
-      T g0 = T(0), g1 = T(0), g2 = T(0);
-#pragma unroll
-      for (int i = 0; i < D; i++) {
-        g0 += xe[i] * tq[3 * i + 0];
-        g1 += xe[i] * tq[3 * i + 1];
-        g2 += xe[i] * tq[3 * i + 2];
-      }
-      // physical gradient G_a = sum_b g_b dxi_b/dx_a, flux f1 = (kappa) G, and its
-      // reference-direction form P_b = w |det| sum_a dxi_b/dx_a f1_a
-      const T s = wd * (KIND == MF_OP_POISSON ? cq : T(1));
-      T G[3];
-#pragma unroll
-      for (int a = 0; a < 3; a++) G[a] = s * (g0 * Ki[a] + g1 * Ki[3 + a] + g2 * Ki[6 + a]);
-      P0 = G[0] * Ki[0] + G[1] * Ki[1] + G[2] * Ki[2];
-      P1 = G[0] * Ki[3] + G[1] * Ki[4] + G[2] * Ki[5];
-      P2 = G[0] * Ki[6] + G[1] * Ki[7] + G[2] * Ki[8];
-    }
-#pragma unroll
-    for (int i = 0; i < D; i++) {
-      T v = T(0);
-      if constexpr (VAL) v += f0 * pq[i];
-      if constexpr (GRAD) v += P0 * tq[3 * i + 0] + P1 * tq[3 * i + 1] + P2 * tq[3 * i + 2];
-      ye[i] += v;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < D; i++) {
-    const int idx = valid ? mp[i * 64] : -1;
-    if (idx >= 0) {
-      if constexpr (ATOMIC) atomic_add_s(&A.y[idx], ye[i]);
-      else A.y[idx] += ye[i];  // cells of one launch share no node
-    }
-  }
-}
-
-template <typename T, int K, int NQ, int KIND>
-static int launch_tet_scalar_kq(const TetArgs<T> &a, bool atomic, hipStream_t s) {
-  const int64_t nbt = (a.c1 + 63) / 64 - a.c0 / 64;
-  if (a.c1 <= a.c0) return MF_OK;
-  const dim3 g((unsigned)(((nbt + 7) / 8) * 8)), b(64);
-  if (atomic) tet_scalar_kernel<T, K, NQ, KIND, true><<<g, b, 0, s>>>(a);
-  else tet_scalar_kernel<T, K, NQ, KIND, false><<<g, b, 0, s>>>(a);
-  MF_HIP(hipGetLastError());
-  return MF_OK;
-}
-
-template <typename T, int K, int NQ>
-static int launch_tet_scalar_k(int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
-  switch (kind) {
-    case MF_OP_MASS: return launch_tet_scalar_kq<T, K, NQ, MF_OP_MASS>(a, atomic, s);
-    case MF_OP_HELMHOLTZ: return launch_tet_scalar_kq<T, K, NQ, MF_OP_HELMHOLTZ>(a, atomic, s);
-    case MF_OP_LAPLACIAN: return launch_tet_scalar_kq<T, K, NQ, MF_OP_LAPLACIAN>(a, atomic, s);
-    case MF_OP_POISSON: return launch_tet_scalar_kq<T, K, NQ, MF_OP_POISSON>(a, atomic, s);
-  }
-  return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
-}
-
+// the vertex coefficient interpolated by the vertex basis; dense tabulation (simplices
+// are not sum-factorised), both contractions on MFMA (tet_scalar_cells16 below).
 template <typename T>
 static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p,
                                   bool atomic, hipStream_t s);
 
-// rules of the tet quadrature table: 1 point (degree 1), 4 (degree 2), 14 (degree 5),
-// 64 (conical Gauss-Jacobi product rule, degree 7). P1 runs the lane-per-cell kernel;
-// P2 and P3 run on MFMA (the tables then carry the per-lane operands after the vertex
-// basis)
+// P1-P3 run on MFMA (the tables carry the per-lane operands after the vertex basis)
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
-  if (k == 1 && nq == 1) return launch_tet_scalar_k<T, 1, 1>(kind, a, atomic, s);
-  if (k == 1 && nq == 4) return launch_tet_scalar_k<T, 1, 4>(kind, a, atomic, s);
-  if (k == 1 && nq == 14) return launch_tet_scalar_k<T, 1, 14>(kind, a, atomic, s);
-  if (k == 2 || k == 3) return launch_tet_scalar_mfma<T>(k, nq, kind, a, nullptr, atomic, s);
-  return fail(MF_EUNSUPPORTED, "tet scalar operator: degree / rule");
+  return launch_tet_scalar_mfma<T>(k, nq, kind, a, nullptr, atomic, s);
 }
 template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);
 template int launch_tet_scalar<float>(int, int, int, const TetArgs<float> &, bool, hipStream_t);
 
 // ----------------------------------------------------------------- scalar triangle operators
 // The same four one-component forms, and 2D linear elasticity (two node-interleaved
-// components, TetArgs lam and mu), on affine triangles of degree K (the 2D version of
-// tet_scalar_kernel): geometry [cell/64][5][64] = d xi_b / d x_a (row-major, 4) and
+// components, TetArgs lam and mu), on affine triangles of degree K, one lane per cell
+// and one wavefront per workgroup, the tables read with uniform loads: geometry [cell/64][5][64] = d xi_b / d x_a (row-major, 4) and
 // |det J|; coefficients [cell/64][3][64]; tables phi [nq][D], reference gradients
 // [nq][D][2], weights [nq], vertex basis [nq][3]; nq is a run-time bound.
 template <typename T, int K, int KIND, bool ATOMIC>
@@ -678,15 +547,15 @@ __global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs
 }
 
 // ----------------------------------------------------------------- scalar tet operators on MFMA
-// The one-component forms of tet_scalar_kernel (degrees 2 and 3) in the GEMM form of the
+// The one-component tet forms (degrees 1-3) in the GEMM form of the
 // elasticity kernel: a wavefront owns 16 cells and one accumulator. The forward rows
 // (q = 4 r + g, a) carry the reference gradient for a = 0..2 and the basis value in the
 // row a = 3 (padding in the elasticity tables), so one accumulator gives lane (cell, g)
 // the gradient and the value of u at point q. The backward K-steps are (r, a) with the
 // gradient rows and, for the kinds with a value term, (r, 3) with the basis values.
 // gp: the cell's geometry (Kinv, |det|), cp: its four vertex coefficients (null: 1),
-// both with entries 64 apart. Tables after the lane kernel's (phi, gradients, weights,
-// vertex basis): fwd[r][s][64], bwd[t][r][4][64] (tet_mfma_scalar_tables).
+// both with entries 64 apart. Tables: phi [nq][D], gradients [nq][D][3], weights [nq],
+// vertex basis [nq][4], then fwd[r][s][64], bwd[t][r][4][64] (tet_mfma_scalar_tables).
 template <typename T, int K, int NQ, int KIND>
 __device__ __forceinline__ void tet_scalar_cells16(const TetArgs<T> &A, const int32_t *mp, const T *gp,
                                                    const T *cp, const bool valid, const int lane,
@@ -878,11 +747,14 @@ static int launch_tet_scalar_mfma_k(int kind, const TetArgs<T> &a, const Simplex
   return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
 }
 
-// P2 and P3 on the rules of the scalar kinds: 4 points (degree 2), 14 (degree 5), 64
-// (degree 7)
+// P1-P3 on the rules of the tet quadrature table the scalar kinds take: 1 point
+// (degree 1), 4 (degree 2), 14 (degree 5), 64 (conical Gauss-Jacobi product, degree 7)
 template <typename T>
 static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p,
                                   bool atomic, hipStream_t s) {
+  if (k == 1 && nq == 1) return launch_tet_scalar_mfma_k<T, 1, 1>(kind, a, p, atomic, s);
+  if (k == 1 && nq == 4) return launch_tet_scalar_mfma_k<T, 1, 4>(kind, a, p, atomic, s);
+  if (k == 1 && nq == 14) return launch_tet_scalar_mfma_k<T, 1, 14>(kind, a, p, atomic, s);
   if (k == 2 && nq == 4) return launch_tet_scalar_mfma_k<T, 2, 4>(kind, a, p, atomic, s);
   if (k == 2 && nq == 14) return launch_tet_scalar_mfma_k<T, 2, 14>(kind, a, p, atomic, s);
   if (k == 3 && nq == 14) return launch_tet_scalar_mfma_k<T, 3, 14>(kind, a, p, atomic, s);

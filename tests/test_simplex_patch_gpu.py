@@ -1,4 +1,4 @@
-"""Patch scatter of the tet elasticity action (P2, P3), of the one-component P2 / P3
+"""Patch scatter of the tet elasticity action (P2, P3), of the one-component P1-P3
 tet operators and of the P1 triangle mass against the oracle.
 
 A patch workgroup sums its cells' local results in LDS and writes each of its nodes
@@ -102,15 +102,16 @@ def test_tet_patch_matches_coloured_scatter(mf, k):
     assert _relerr(a, b) <= 1e-13
 
 
-# one-component forms on 7^3 x 6 = 2058 tets: several patches (384 or 256 cells), the
-# last one ragged; MASS and POISSON with a vertex coefficient, MASS also without
+# one-component forms on 7^3 x 6 = 2058 tets: several patches (1024, 384 or 256
+# cells), the last one ragged; MASS and POISSON with a vertex coefficient, MASS also
+# without
 SCALAR = [(0, True), (0, False), (1, False), (2, False), (3, True)]
 
 
 @pytest.mark.parametrize("dirichlet", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("kind,coef", SCALAR)
-@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3])
 def test_tet_scalar_patch_action(mf, k, kind, coef, prec, dirichlet):
     import torch
     print(f"tet scalar patch k={k} kind={kind} coef={coef} prec={prec} dirichlet={dirichlet}", flush=True)
@@ -145,11 +146,11 @@ def test_tet_scalar_patch_action(mf, k, kind, coef, prec, dirichlet):
         assert np.abs(d - yi).max() <= 4 * TOL[prec] * (np.abs(yi).max() + 1.0)
 
 
-def test_tet_scalar_patch_rejected_for_p1(mf):
+def test_tet_patch_rejected_for_p1_elasticity(mf):
     mesh = mg.tet_mesh(2, 0.2, config=2)
-    space = mg.tet_space(mesh, 1, ncomp=1, config=2)
+    space = mg.tet_space(mesh, 1, ncomp=3, config=2)
     with pytest.raises(mf.MFError, match="patch scatter"):
-        mf.Operator(mf.Space.from_meshgen(space), mf.LAPLACIAN, mf.F64, scatter=mf.SCATTER_PATCH)
+        mf.Operator(mf.Space.from_meshgen(space), mf.ELASTICITY, mf.F64, lam=1.0, mu=0.5, scatter=mf.SCATTER_PATCH)
 
 
 # 48 x 48 x 2 = 4608 triangles: three patches of 2048 cells, the last one ragged
