@@ -125,7 +125,7 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             degree 2-4, and for the tet and triangle forms above on at least
  *             2^15 cells; otherwise COLOURED for 3-component hex operators of
  *             degree >= 2 on at least 4096 cells, scalar hex operators of degree
- *             >= 2 on at least 2^18 cells, tets of degree >= 2, quad and triangle
+ *             >= 2 on at least 2^18 cells, tets of degree 2 and 3, quad and triangle
  *             ELASTICITY (at least 4096 cells) and the other triangle operators
  *             but the P1 mass on at least 2^20 cells; else ATOMIC (the measured
  *             choices).
@@ -157,8 +157,9 @@ typedef struct {
  * tet ELASTICITY and HYPERELASTIC P1-P6 (ncomp 3); tet MASS and
  * HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1; the tet rules reach degree 21);
  * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1) and ELASTICITY P1-P6
- * (ncomp 2, the 2D stress); degrees 4-6 on simplices run a dense-tabulation kernel
- * (a thread per point, then a thread per node); quad MASS, HELMHOLTZ,
+ * (ncomp 2, the 2D stress); tets of degree >= 2 run on the matrix cores, triangles
+ * of degree 4-6 a dense-tabulation kernel (a thread per point, then a thread per
+ * node); quad MASS, HELMHOLTZ,
  * LAPLACIAN and POISSON Q1-Q6 (ncomp 1) and ELASTICITY Q1-Q6 (ncomp 2, the 2D stress).
  * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
 int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,

@@ -819,10 +819,7 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
   op->nqp = nq;
   tet_lagrange(k, pts, phi, dphi);
   std::vector<T> tab;
-  if (k >= 4) {  // the dense kernel: a workgroup per cell block, the points in chunks
-    tab = dense_simplex_tables<T>(3, pts, w, phi, dphi);
-    simplex_dense_shape<T>(D, nq, sp->ncomp, 3, hyper, op->dense_cb, op->dense_qc);
-  } else if (scalar) {
+  if (scalar) {
     // phi [nq][D], reference gradients [nq][D][3], weights [nq], vertex basis [nq][4]
     for (double v : phi) tab.push_back((T)v);
     for (double v : dphi) tab.push_back((T)v);
@@ -840,9 +837,10 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     for (double v : dphi) tab.push_back((T)v);
     for (double v : w) tab.push_back((T)v);
   }
-  if (!scalar && k <= 3 && (k >= 2 || hyper)) {
-    // per-lane operands of the MFMA contractions, appended after the weights (the
-    // hyperelastic tangent runs the MFMA kernel at every degree)
+  if (!scalar && (k >= 2 || hyper)) {
+    // per-lane operands of the MFMA contractions, appended after the weights (P1
+    // elasticity keeps a lane-per-cell kernel; the hyperelastic tangent runs the MFMA
+    // kernel at every degree)
     std::vector<double> mt((size_t)tet_mfma_table_floats(k, nq));
     tet_mfma_tables(k, nq, dphi.data(), mt.data(), sizeof(T) == 8);
     for (double v : mt) tab.push_back((T)v);
@@ -1304,7 +1302,10 @@ static bool default_coloured(const mf_op *op) {
     if (op->ncomp == 3 && op->degree >= 2) return true;
     return op->ncells >= (op->degree == 1 ? (1 << 19) : (1 << 18));
   }
-  return op->cell_type == MF_CELL_TET && op->degree >= 2;
+  // tets of degree >= 4 (MFMA, 64-1331 points per cell) keep atomics: at 24^3 x 6 a
+  // colour's 2,800 cells fill too little of the chip (FP64 P4 Laplacian 711 against
+  // 146 us, P6 3700 against 677 us; P6 elasticity 7385 against 3952 us)
+  return op->cell_type == MF_CELL_TET && op->degree >= 2 && op->degree <= 3;
 }
 
 template <typename T> static int op_diag_t(const mf_op *op, T *d, hipStream_t s) {

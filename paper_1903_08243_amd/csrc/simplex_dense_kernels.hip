@@ -1,5 +1,6 @@
-// Operators on simplices of degree 4-6 (triangles and tetrahedra; mass with a vertex
-// coefficient, Helmholtz, Laplacian with one or dim components, Poisson, elasticity):
+// Operators on simplices of degree 4-6 (mass with a vertex coefficient, Helmholtz,
+// Laplacian with one or dim components, Poisson, elasticity; the library runs
+// triangles here, tetrahedra on the matrix-core kernels):
 // the paper's local kernel by dense tabulation (Section 2.1: the basis and its
 // reference gradients tabulated at the quadrature points, the affine Jacobian per
 // cell; simplices are not sum-factorised, Section 4), for element sizes where a lane

@@ -104,7 +104,8 @@ template <typename T>
 static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p,
                                   bool atomic, hipStream_t s);
 
-// P1-P3 run on MFMA (the tables carry the per-lane operands after the vertex basis)
+// every degree runs on MFMA (the tables carry the per-lane operands after the vertex
+// basis)
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
   return launch_tet_scalar_mfma<T>(k, nq, kind, a, nullptr, atomic, s);
@@ -547,7 +548,7 @@ __global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs
 }
 
 // ----------------------------------------------------------------- scalar tet operators on MFMA
-// The one-component tet forms (degrees 1-3) in the GEMM form of the
+// The one-component tet forms (degrees 1-6) in the GEMM form of the
 // elasticity kernel: a wavefront owns 16 cells and one accumulator. The forward rows
 // (q = 4 r + g, a) carry the reference gradient for a = 0..2 and the basis value in the
 // row a = 3 (padding in the elasticity tables), so one accumulator gives lane (cell, g)
@@ -747,8 +748,9 @@ static int launch_tet_scalar_mfma_k(int kind, const TetArgs<T> &a, const Simplex
   return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
 }
 
-// P1-P3 on the rules of the tet quadrature table the scalar kinds take: 1 point
-// (degree 1), 4 (degree 2), 14 (degree 5), 64 (conical Gauss-Jacobi product, degree 7)
+// P1-P6 on the rules of the tet quadrature table the scalar kinds take: 1 point
+// (degree 1), 4 (degree 2), 14 (degree 5), and the conical Gauss-Jacobi products of n^3
+// points, exact to degree 2n - 1 (64, 125, 216, 343)
 template <typename T>
 static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p,
                                   bool atomic, hipStream_t s) {
@@ -759,6 +761,12 @@ static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, 
   if (k == 2 && nq == 14) return launch_tet_scalar_mfma_k<T, 2, 14>(kind, a, p, atomic, s);
   if (k == 3 && nq == 14) return launch_tet_scalar_mfma_k<T, 3, 14>(kind, a, p, atomic, s);
   if (k == 3 && nq == 64) return launch_tet_scalar_mfma_k<T, 3, 64>(kind, a, p, atomic, s);
+  if (k == 4 && nq == 64) return launch_tet_scalar_mfma_k<T, 4, 64>(kind, a, p, atomic, s);
+  if (k == 4 && nq == 125) return launch_tet_scalar_mfma_k<T, 4, 125>(kind, a, p, atomic, s);
+  if (k == 5 && nq == 125) return launch_tet_scalar_mfma_k<T, 5, 125>(kind, a, p, atomic, s);
+  if (k == 5 && nq == 216) return launch_tet_scalar_mfma_k<T, 5, 216>(kind, a, p, atomic, s);
+  if (k == 6 && nq == 216) return launch_tet_scalar_mfma_k<T, 6, 216>(kind, a, p, atomic, s);
+  if (k == 6 && nq == 343) return launch_tet_scalar_mfma_k<T, 6, 343>(kind, a, p, atomic, s);
   return fail(MF_EUNSUPPORTED, "tet scalar operator on MFMA: degree / rule");
 }
 
@@ -925,11 +933,14 @@ static int launch_tet_kq(const TetArgs<T> &a, hipStream_t s, bool diag, bool ato
       return MF_OK;
     }
   }
-  if (diag) tet_elasticity_diag_kernel<T, K, NQ><<<grid, block, 0, s>>>(a);
-  else if (atomic) tet_elasticity_kernel<T, K, NQ, true><<<grid, block, 0, s>>>(a);
-  else tet_elasticity_kernel<T, K, NQ, false><<<grid, block, 0, s>>>(a);
-  MF_HIP(hipGetLastError());
-  return MF_OK;
+  if constexpr (K <= 3) {
+    if (diag) tet_elasticity_diag_kernel<T, K, NQ><<<grid, block, 0, s>>>(a);
+    else if (atomic) tet_elasticity_kernel<T, K, NQ, true><<<grid, block, 0, s>>>(a);
+    else tet_elasticity_kernel<T, K, NQ, false><<<grid, block, 0, s>>>(a);
+    MF_HIP(hipGetLastError());
+    return MF_OK;
+  }
+  return fail(MF_EUNSUPPORTED, "tet elasticity: fused diagonal for degrees 1-3 only");
 }
 
 template <typename T>
@@ -937,6 +948,11 @@ static int launch_tet(int k, int nq, const TetArgs<T> &a, hipStream_t s, bool di
   if (k == 1 && nq == 1) return launch_tet_kq<T, 1, 1>(a, s, diag, atomic);
   if (k == 2 && nq == 4) return launch_tet_kq<T, 2, 4>(a, s, diag, atomic);
   if (k == 3 && nq == 14) return launch_tet_kq<T, 3, 14>(a, s, diag, atomic);
+  if (!diag) {  // degrees 4-6 (rules of degree 2k - 2): the MFMA kernel; their diagonal is element-wise
+    if (k == 4 && nq == 64) return launch_tet_kq<T, 4, 64>(a, s, false, atomic);
+    if (k == 5 && nq == 125) return launch_tet_kq<T, 5, 125>(a, s, false, atomic);
+    if (k == 6 && nq == 216) return launch_tet_kq<T, 6, 216>(a, s, false, atomic);
+  }
   return fail(MF_EUNSUPPORTED, "tet elasticity: degree / rule");
 }
 
@@ -959,6 +975,9 @@ template <typename T> int launch_tet_elasticity(int k, int nq, const TetArgs<T> 
     if (k == 1 && nq == 1) return launch_tet_hyper_kq<T, 1, 1>(a, atomic, s);
     if (k == 2 && nq == 14) return launch_tet_hyper_kq<T, 2, 14>(a, atomic, s);
     if (k == 3 && nq == 125) return launch_tet_hyper_kq<T, 3, 125>(a, atomic, s);
+    if (k == 4 && nq == 343) return launch_tet_hyper_kq<T, 4, 343>(a, atomic, s);
+    if (k == 5 && nq == 729) return launch_tet_hyper_kq<T, 5, 729>(a, atomic, s);
+    if (k == 6 && nq == 1331) return launch_tet_hyper_kq<T, 6, 1331>(a, atomic, s);
     return fail(MF_EUNSUPPORTED, "tet hyperelasticity: degree / rule");
   }
   return launch_tet<T>(k, nq, a, s, false, atomic);
