@@ -119,11 +119,11 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             free nodes) with a device atomic (not bit-reproducible). Built for
  *             the hex MASS, HELMHOLTZ, LAPLACIAN and POISSON operators of degree 1
  *             (two points per direction) and 2-6 (k+1 points), P2 / P3 tet
- *             ELASTICITY, P1-P3 one-component tet operators and the P1 triangle
- *             mass.
+ *             ELASTICITY, P1-P3 one-component tet operators and the one-component
+ *             triangle operators (the P1 mass included).
  *   AUTO      PATCH for hex Q1 on at least 2^15 cells, for those hex operators of
- *             degree 2-4, and for the tet and triangle forms above on at least
- *             2^15 cells; otherwise COLOURED for 3-component hex operators of
+ *             degree 2-4, and for the tet and triangle forms above (FP64
+ *             triangles only up to degree 4) on at least 2^15 cells; otherwise COLOURED for 3-component hex operators of
  *             degree >= 2 on at least 4096 cells, scalar hex operators of degree
  *             >= 2 on at least 2^18 cells, tets of degree 2 and 3, quad and triangle
  *             ELASTICITY (at least 4096 cells) and the other triangle operators

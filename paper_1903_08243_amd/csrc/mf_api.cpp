@@ -768,36 +768,6 @@ static int setup_simplex_patches(mf_op *op, const mf_space *sp, const std::vecto
   return rc;
 }
 
-// Tables of the dense simplex kernel (degrees 4-6), SimplexDenseArgs::tab: values and
-// reference gradients transposed ([node][point], [dim][node][point]) for the forward
-// contraction, then as [point][node], [point][dim][node] for the test side, the
-// weights and the vertex basis at the points
-template <typename T>
-static std::vector<T> dense_simplex_tables(int dim, const std::vector<double> &pts, const std::vector<double> &w,
-                                           const std::vector<double> &phi, const std::vector<double> &dphi) {
-  const int nq = (int)w.size(), D = (int)(phi.size() / w.size());
-  std::vector<T> tab;
-  tab.reserve((size_t)2 * nq * D * (1 + dim) + nq * (2 + dim));
-  for (int i = 0; i < D; i++)
-    for (int q = 0; q < nq; q++) tab.push_back((T)phi[(size_t)q * D + i]);
-  for (int d = 0; d < dim; d++)
-    for (int i = 0; i < D; i++)
-      for (int q = 0; q < nq; q++) tab.push_back((T)dphi[((size_t)q * D + i) * dim + d]);
-  for (int q = 0; q < nq; q++)
-    for (int i = 0; i < D; i++) tab.push_back((T)phi[(size_t)q * D + i]);
-  for (int q = 0; q < nq; q++)
-    for (int d = 0; d < dim; d++)
-      for (int i = 0; i < D; i++) tab.push_back((T)dphi[((size_t)q * D + i) * dim + d]);
-  for (int q = 0; q < nq; q++) tab.push_back((T)w[q]);
-  for (int q = 0; q < nq; q++) {
-    double s0 = 1.0;
-    for (int a = 0; a < dim; a++) s0 -= pts[(size_t)q * dim + a];
-    tab.push_back((T)s0);
-    for (int a = 0; a < dim; a++) tab.push_back((T)pts[(size_t)q * dim + a]);
-  }
-  return tab;
-}
-
 template <typename T>
 static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
                      hipStream_t s) {
@@ -830,8 +800,8 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
       for (int a = 0; a < 3; a++) tab.push_back((T)x[a]);
     }
     // per-lane operands of the MFMA contractions
-    std::vector<double> mt((size_t)tet_mfma_scalar_table_floats(k, nq));
-    tet_mfma_scalar_tables(k, nq, phi.data(), dphi.data(), mt.data(), sizeof(T) == 8);
+    std::vector<double> mt((size_t)simplex_mfma_scalar_table_floats(3, D, nq));
+    simplex_mfma_scalar_tables(3, D, nq, phi.data(), dphi.data(), mt.data(), sizeof(T) == 8);
     for (double v : mt) tab.push_back((T)v);
   } else {
     for (double v : dphi) tab.push_back((T)v);
@@ -925,7 +895,9 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
 // Triangles other than the closed-form P1 mass: tables (phi, reference gradients,
 // weights, vertex basis at the points of a collapsed rule exact for the integrand),
 // geometry [cell/64][5][64] (d xi_b / d x_a, |det J|), coefficients [cell/64][3][64].
-template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, const mf_op_params *pr, hipStream_t s) {
+template <typename T>
+static int setup_tri_pk(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
+                        hipStream_t s) {
   const int k = sp->degree;
   int deg = (op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ) ? 2 * k : 2 * k - 2;
   if (op->has_coef) deg += 1;
@@ -935,25 +907,31 @@ template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, con
   tri_lagrange(k, pts, phi, dphi);
   const int nq = (int)w.size();
   op->nqp = nq;
+  // phi [nq][D], reference gradients [nq][D][2], weights [nq], vertex basis [nq][3],
+  // then the per-lane operands of the matrix-core kernels
   std::vector<T> tab;
-  if (k >= 4) {
-    tab = dense_simplex_tables<T>(2, pts, w, phi, dphi);
-    simplex_dense_shape<T>(sp->D, nq, sp->ncomp, 2, false, op->dense_cb, op->dense_qc);
-  } else {
-    for (double v : phi) tab.push_back((T)v);
-    for (double v : dphi) tab.push_back((T)v);
-    for (double v : w) tab.push_back((T)v);
-    for (int q = 0; q < nq; q++) {
-      tab.push_back((T)(1.0 - pts[2 * q] - pts[2 * q + 1]));
-      tab.push_back((T)pts[2 * q]);
-      tab.push_back((T)pts[2 * q + 1]);
-    }
+  for (double v : phi) tab.push_back((T)v);
+  for (double v : dphi) tab.push_back((T)v);
+  for (double v : w) tab.push_back((T)v);
+  for (int q = 0; q < nq; q++) {
+    tab.push_back((T)(1.0 - pts[2 * q] - pts[2 * q + 1]));
+    tab.push_back((T)pts[2 * q]);
+    tab.push_back((T)pts[2 * q + 1]);
+  }
+  {
+    std::vector<double> mt((size_t)simplex_mfma_scalar_table_floats(2, sp->D, nq));
+    simplex_mfma_scalar_tables(2, sp->D, nq, phi.data(), dphi.data(), mt.data(), sizeof(T) == 8);
+    for (double v : mt) tab.push_back((T)v);
   }
   int rc = upload(op->tab, tab.data(), tab.size() * sizeof(T), s);
   if (rc) return rc;
   const int64_t nc = sp->ncells, nb = (nc + 63) / 64;
   std::vector<T> geo((size_t)nb * 5 * 64, T(0)), cf;
   if (op->has_coef) cf.assign((size_t)nb * 3 * 64, T(1));
+  // patch slots: the geometry and, for MASS and POISSON, the three vertex coefficients
+  const bool slot_coef = op->kind == MF_OP_MASS || op->kind == MF_OP_POISSON;
+  const int G = slot_coef ? 8 : 5;
+  std::vector<T> gflat(op->spatched ? (size_t)nc * G : 0);
   for (int64_t K = 0; K < nc; K++) {
     const int32_t *cv = sp->cell2vert_int.data() + K * 3;
     const double *p0 = &sp->coords[(int64_t)cv[0] * 2], *p1 = &sp->coords[(int64_t)cv[1] * 2],
@@ -967,9 +945,18 @@ template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, con
     geo[(b * 5 + 4) * 64 + l] = (T)std::fabs(det);
     if (op->has_coef)
       for (int v = 0; v < 3; v++) cf[(b * 3 + v) * 64 + l] = (T)pr->vertex_coef[cv[v]];
+    if (op->spatched) {
+      for (int e = 0; e < 5; e++) gflat[(size_t)K * G + e] = geo[(b * 5 + e) * 64 + l];
+      for (int v = 0; v < G - 5; v++) gflat[(size_t)K * G + 5 + v] = op->has_coef ? (T)pr->vertex_coef[cv[v]] : T(1);
+    }
   }
   rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
   if (!rc && op->has_coef) rc = upload(op->coef, cf.data(), cf.size() * sizeof(T), s);
+  if (!rc && op->spatched) {
+    // about k^2 / 2 nodes per cell: patches of at most 4096 nodes
+    const int cap = k <= 1 ? 2048 : k == 2 ? 1024 : k == 3 ? 512 : k == 4 ? 384 : 256;
+    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, G, cap, 4096, s);
+  }
   if (!rc) MF_HIP(hipStreamSynchronize(s));
   return rc;
 }
@@ -977,7 +964,7 @@ template <typename T> static int setup_tri_pk(mf_op *op, const mf_space *sp, con
 template <typename T>
 static int setup_tri(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
                      hipStream_t s) {
-  if (!(op->kind == MF_OP_MASS && sp->degree == 1)) return setup_tri_pk<T>(op, sp, pr, s);
+  if (!(op->kind == MF_OP_MASS && sp->degree == 1)) return setup_tri_pk<T>(op, sp, pr, m, s);
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 4, T(0)), gflat(op->spatched ? (size_t)nc * 3 : 0);
   for (int64_t K = 0; K < nc; K++) {
@@ -1108,13 +1095,6 @@ static void count_work(mf_op *op) {
                       (op->kind == MF_OP_ELASTICITY ? 10.0 : 0.0);
     fl = nc * (2.0 * fma + q * q * pt);
     by += nc * 6.0 * s + (op->has_coef ? nc * 4.0 * s : 0.0);
-  } else if (op->dense_cb > 0) {
-    // dense kernel, per point and component: values and reference gradients 2 (1 + dim) D
-    // forward and the same backward, push-forward and pull-back 4 dim^2, the pointwise
-    // stress 4 dim (elasticity) and the weight; bytes: geometry dim^2 + 1 per cell
-    const double D = op->D, Q = op->nqp, dim = op->cell_type == MF_CELL_TET ? 3.0 : 2.0;
-    fl = nc * Q * comps * (4.0 * (1.0 + dim) * D + 4.0 * dim * dim + 4.0 * dim + 4.0);
-    by += nc * (dim * dim + 1.0) * s + (op->has_coef ? nc * (dim + 1.0) * s : 0.0);
   } else if (op->cell_type == MF_CELL_TET && op->ncomp == 1) {
     // scalar operators, dense tabulation, per point: value 2D and its test sum 2D;
     // reference gradient 6D, push-forward 18, the reference-direction flux 18 (and a
@@ -1187,15 +1167,6 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     QuadArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
                   op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, (T)op->lam, (T)op->mu};
     return launch_quad<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
-  } else if (op->dense_cb > 0) {  // simplices of degree 4-6
-    SimplexDenseArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->has_coef ? op->coef.as<T>() : nullptr,
-                          op->tab.as<T>(), x, y, c0, c1, filt, ulo, uhi, op->D, op->nqp, op->ncomp, op->kind,
-                          op->dense_cb, op->dense_qc, (T)op->lam, (T)op->mu};
-    if (op->kind == MF_OP_HYPERELASTIC) {
-      a.u0 = op->u0.as<T>();
-      a.u0map = op->u0map.ptr ? op->u0map.as<int32_t>() : nullptr;
-    }
-    return launch_simplex_dense<T>(op->cell_type == MF_CELL_TET ? 3 : 2, a, atomic, s);
   } else if (op->cell_type == MF_CELL_TET) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
                  filt, ulo, uhi, op->u0.as<T>(), op->u0map.as<int32_t>(),
@@ -1206,7 +1177,8 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
   if (!(op->kind == MF_OP_MASS && op->degree == 1)) {
     TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, c0, c1, (T)op->lam, (T)op->mu,
                  filt, ulo, uhi, nullptr, nullptr, op->has_coef ? op->coef.as<T>() : nullptr};
-    return launch_tri_scalar<T>(op->degree, op->nqp, op->kind, a, atomic, s);
+    if (op->ncomp == 1) return launch_tri_scalar_mfma<T>(op->degree, op->nqp, op->kind, a, atomic, s);
+    return launch_tri_elasticity_mfma<T>(op->degree, op->nqp, a, atomic, s);
   }
   TriArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), x, y, c0, c1, filt, ulo, uhi};
   return launch_tri_mass<T>(a, atomic, s);
@@ -1241,8 +1213,12 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
       SimplexPatchArgs<T> pa{op->sp_map.as<int32_t>(), op->sp_geo.as<T>(), op->sp_lmap.as<uint16_t>(),
                              op->sp_nptr.as<int32_t>(), op->sp_out.as<int32_t>(), op->sp_sbuf.as<T>(),
                              op->sp_npatch, op->sp_cap, op->sp_nmax, acc ? 1 : 0};
-      if (op->cell_type == MF_CELL_TRI) {
+      if (op->cell_type == MF_CELL_TRI && op->kind == MF_OP_MASS && op->degree == 1) {
         rc = launch_tri_mass_patches<T>(x, y, pa, s);
+      } else if (op->cell_type == MF_CELL_TRI) {
+        TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, 0, op->ncells, (T)op->lam,
+                     (T)op->mu, nullptr, 0, 0, nullptr, nullptr, nullptr};
+        rc = launch_tri_scalar_patches<T>(op->degree, op->nqp, op->kind, a, pa, s);
       } else {
         TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, 0, op->ncells, (T)op->lam,
                      (T)op->mu, nullptr, 0, 0, nullptr, nullptr, nullptr};
@@ -1442,12 +1418,16 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
-  // P2/P3 tet elasticity, P1-P3 one-component tet operators (the MFMA kernels) and the
-  // P1 triangle mass: patch scatter on request, and by default from 2^15 cells
+  // P2/P3 tet elasticity, P1-P3 one-component tet operators and one-component triangle
+  // operators (the MFMA kernels), the P1 triangle mass: patch scatter on request, and by
+  // default from 2^15 cells (triangles up to degree 4: at 1024^2 x 2 cells, FP64, the
+  // patches took P2 Helmholtz from 174 (coloured) to 115 us and P3 Laplacian from 306 to
+  // 191 us; at degree 6 atomics ran faster in FP64, 395 against 447 us, and slower in
+  // FP32, 460 against 267 us)
   const bool tet_patchable = (ct == MF_CELL_TET && sp->degree <= 3 &&
                               ((kind == MF_OP_ELASTICITY && sp->degree >= 2) ||
                                (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
-                             (ct == MF_CELL_TRI && kind == MF_OP_MASS && sp->degree == 1);
+                             (ct == MF_CELL_TRI && kind <= MF_OP_POISSON && sp->ncomp == 1);
   // hex degrees 2-6 (the pencil kernel): patch scatter on request, and by default for
   // degrees 2-4. A patch is one workgroup's cells (7, 4 and 2 cells for k = 2..4, 3 and
   // 5 for k = 5, 6); at 32^3 it beat the coloured and atomic scatters for k <= 4 (FP64
@@ -1457,7 +1437,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
                              op->nq1d == sp->degree + 1;
   if (pr->scatter == MF_SCATTER_PATCH && tet_patchable) {
     op->spatched = true;
-  } else if (pr->scatter == MF_SCATTER_AUTO && tet_patchable && nc >= (1 << 15)) {
+  } else if (pr->scatter == MF_SCATTER_AUTO && tet_patchable &&
+             !(ct == MF_CELL_TRI && sp->degree >= 5 && precision == MF_F64) && nc >= (1 << 15)) {
     op->spatched = true;
   } else if (hex_patchable && (pr->scatter == MF_SCATTER_PATCH ||
                                (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4))) {
@@ -1465,7 +1446,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)
       return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, P2/P3 "
-                                   "tet elasticity, P1-P3 one-component tet operators and the P1 triangle mass");
+                                   "tet elasticity, P1-P3 one-component tet operators and one-component "
+                                   "triangle operators");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
              kind <= MF_OP_POISSON && op->nq1d == 2) {

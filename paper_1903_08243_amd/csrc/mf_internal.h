@@ -175,16 +175,24 @@ template <typename T>
 int launch_tet_elasticity(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s);
 // one-component MASS, HELMHOLTZ, LAPLACIAN, POISSON on P1..P3 tets; tab holds phi
 // [nq][D], the reference gradients [nq][D][3], the weights [nq] and the vertex
-// basis [nq][4] at the points, and for P2 / P3 (MFMA) then tet_mfma_scalar_tables
+// basis [nq][4] at the points, then simplex_mfma_scalar_tables (matrix-core kernels)
 template <typename T>
 int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s);
-int tet_mfma_scalar_table_floats(int k, int nq);
-void tet_mfma_scalar_tables(int k, int nq, const double *phi, const double *dphi, double *out, bool f64);
-// the same forms on P1..P3 triangles (TetArgs as a generic simplex argument block:
-// geo [cell/64][5][64], coef [cell/64][3][64], tab phi, gradients [nq][D][2], weights,
-// vertex basis [nq][3])
+// per-lane MFMA operands of the one-component simplex kernels (dim 2 or 3, D nodes)
+int simplex_mfma_scalar_table_floats(int dim, int D, int nq);
+void simplex_mfma_scalar_tables(int dim, int D, int nq, const double *phi, const double *dphi, double *out,
+                                bool f64);
+// the one-component forms on P1..P6 triangles on the matrix cores (TetArgs as a
+// generic simplex argument block: geo [cell/64][5][64], coef [cell/64][3][64], tab phi
+// [nq][D], gradients [nq][D][2], weights, vertex basis [nq][3], then
+// simplex_mfma_scalar_tables), atomic or coloured
 template <typename T>
-int launch_tri_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s);
+int launch_tri_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s);
+// 2D linear elasticity on P1..P6 triangles on the matrix cores (the same tables;
+// two node-interleaved components, TetArgs lam and mu)
+template <typename T>
+int launch_tri_elasticity_mfma(int k, int nq, const TetArgs<T> &a, bool atomic, hipStream_t s);
+
 template <typename T>
 int launch_tet_elasticity_diag(int k, int nq, const TetArgs<T> &a, hipStream_t s);
 // Degree >= 2: the action runs on MFMA and needs these per-lane operands of the
@@ -330,7 +338,12 @@ template <typename T> struct SimplexPatchArgs {
 template <typename T>
 int launch_tet_elasticity_patches(int k, int nq, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
                                   hipStream_t s);
-// the one-component P2 / P3 tet forms with the patch scatter (slot geometry: Kinv,
+// the one-component triangle forms with the patch scatter (slot geometry: d xi / d x,
+// |det| and, for MASS and POISSON, the three vertex coefficients: 5 or 8 entries)
+template <typename T>
+int launch_tri_scalar_patches(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
+                              hipStream_t s);
+// the one-component P1-P3 tet forms with the patch scatter (slot geometry: Kinv,
 // |det| and, for MASS and POISSON, the four vertex coefficients: 10 or 14 entries)
 template <typename T>
 int launch_tet_scalar_patches(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
@@ -360,24 +373,6 @@ int launch_tensor_element_csr(int dim, const int32_t *map, const int32_t *unode,
 template <typename T>
 int launch_tri_mass_element_csr(const int32_t *fmap, const int32_t *unode, const T *geo, int64_t ncells,
                                 const int64_t *rowptr, const int32_t *col, T *vals, hipStream_t s);
-// simplices of degree 4-6 by dense tabulation (simplex_dense_kernels.hip)
-template <typename T> struct SimplexDenseArgs {
-  const int32_t *map;  // [cell/64][D][64] internal node ids (negative: constrained)
-  const T *geo;        // [cell/64][dim*dim + 1][64]: d xi_b / d x_a at b*dim + a, |det J|
-  const T *coef;       // [cell/64][dim + 1][64] vertex coefficients, or null
-  const T *tab;        // vT [D][nq], gT [dim][D][nq], v [nq][D], g [nq][dim][D], w [nq], vb [nq][dim+1]
-  const T *x;
-  T *y;
-  int64_t c0, c1;
-  const int32_t *cell_user;  // if set: only cells whose user index is in [ulo, uhi)
-  int64_t ulo, uhi;
-  int D, nq, ncomp, kind, cb, qc;  // cb cells per workgroup (cb D <= 256), qc points per chunk
-  T lam, mu;
-  const T *u0 = nullptr;           // HYPERELASTIC: linearisation point, internal numbering
-  const int32_t *u0map = nullptr;  // its AoSoA map when `map` flags constrained nodes
-};
-template <typename T> void simplex_dense_shape(int D, int nq, int ncomp, int dim, bool hyper, int &cb, int &qc);
-template <typename T> int launch_simplex_dense(int dim, const SimplexDenseArgs<T> &a, bool atomic, hipStream_t s);
 template <typename T>
 int launch_simplex_element_diag(int dim, const int32_t *fmap, const T *geo, const T *coef, const double *tab,
                                 int64_t ncells, int D, int nq, int kind, int nc, double lam, double mu, T *d,
@@ -432,7 +427,6 @@ struct mf_op {
   // tet rule, and the CSR pattern once built
   std::vector<int32_t> h_bc_user;  // constrained dofs, user numbering
   int qdeg = 0;
-  int dense_cb = 0, dense_qc = 0;  // dense simplex kernel (degrees 4-6): cells per workgroup, points per chunk
   mutable std::vector<int64_t> csr_rowptr;
   mutable std::vector<int32_t> csr_col;
   mutable bool csr_built = false;

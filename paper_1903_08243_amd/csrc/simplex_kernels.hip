@@ -7,14 +7,17 @@
 // (Section 4.2.3): the kernels contract dense tabulations of the reference
 // basis gradients at quadrature points, the paper's constant tables.
 //
-// GPU mapping follows the paper's cross-element idea (Section 3.1: one SIMD
-// lane per element, element index fastest in every temporary) on a 64-wide
-// wavefront: lane = cell, and the AoSoA layouts [cell/64][entry][cell%64]
-// make every map / geometry load a unit-stride wavefront access. The tables
-// are uniform across the wavefront and are read through the scalar cache.
+// Layouts follow the paper's cross-element idea (Section 3.1: element index
+// fastest in every temporary): AoSoA [cell/64][entry][cell%64] maps, geometry and
+// coefficients, so a wavefront's loads of one entry are unit-stride. Over a batch
+// of cells both contractions are GEMMs with the tabulation shared by every cell,
+// so the tet kernels of degree >= 2 (and every one-component form) run them on the
+// matrix cores, 16 cells per wavefront (simplex_mfma.h); P1 elasticity keeps one
+// lane per cell. Here: tet elasticity and the hyperelastic tangent, the scalar tet
+// dispatch, the closed-form P1 triangle mass, the patch scatter's shared-node sum.
 #include <type_traits>
 
-#include "mf_internal.h"
+#include "simplex_mfma.h"
 
 namespace mf {
 
@@ -113,160 +116,6 @@ int launch_tet_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic,
 template int launch_tet_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);
 template int launch_tet_scalar<float>(int, int, int, const TetArgs<float> &, bool, hipStream_t);
 
-// ----------------------------------------------------------------- scalar triangle operators
-// The same four one-component forms, and 2D linear elasticity (two node-interleaved
-// components, TetArgs lam and mu), on affine triangles of degree K, one lane per cell
-// and one wavefront per workgroup, the tables read with uniform loads: geometry [cell/64][5][64] = d xi_b / d x_a (row-major, 4) and
-// |det J|; coefficients [cell/64][3][64]; tables phi [nq][D], reference gradients
-// [nq][D][2], weights [nq], vertex basis [nq][3]; nq is a run-time bound.
-template <typename T, int K, int KIND, bool ATOMIC>
-__global__ void __launch_bounds__(64) tri_scalar_kernel(const TetArgs<T> A, const int NQ) {
-  constexpr int D = (K + 1) * (K + 2) / 2;
-  constexpr bool ELAS = KIND == MF_OP_ELASTICITY;  // two node-interleaved components
-  constexpr int NC = ELAS ? 2 : 1;
-  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
-  constexpr bool GRAD = KIND != MF_OP_MASS;
-  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
-  const int lane = threadIdx.x;
-  const int64_t nbt = (A.c1 + 63) / 64 - A.c0 / 64, per = (nbt + 7) / 8;
-  const int64_t bl = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (bl >= nbt) return;
-  const int64_t batch = A.c0 / 64 + bl;
-  const int64_t cell = batch * 64 + lane;
-  bool valid = cell >= A.c0 && cell < A.c1;
-  if (valid && A.cell_user) {
-    const int64_t u = A.cell_user[cell];
-    valid = u >= A.ulo && u < A.uhi;
-  }
-  const int32_t *mp = A.map + batch * (D * 64) + lane;
-  const T *gp = A.geo + batch * (5 * 64) + lane;
-  T Ki[4];
-#pragma unroll
-  for (int m = 0; m < 4; m++) Ki[m] = gp[m * 64];
-  const T adet = gp[4 * 64];
-  T cv[3] = {T(1), T(1), T(1)};
-  if (COEF && A.coef)
-#pragma unroll
-    for (int v = 0; v < 3; v++) cv[v] = A.coef[(batch * 3 + v) * 64 + lane];
-  T xe[NC][D], ye[NC][D];
-#pragma unroll
-  for (int i = 0; i < D; i++) {
-    const int idx = valid ? mp[i * 64] : -1;
-#pragma unroll
-    for (int c = 0; c < NC; c++) {
-      xe[c][i] = idx >= 0 ? A.x[(int64_t)idx * NC + c] : T(0);
-      ye[c][i] = T(0);
-    }
-  }
-  const T *__restrict__ phi = A.tab;
-  const T *__restrict__ dphi = phi + NQ * D;
-  const T *__restrict__ qw = dphi + NQ * D * 2;
-  const T *__restrict__ vb = qw + NQ;
-#pragma unroll 1
-  for (int q = 0; q < NQ; q++) {
-    const T *pq = phi + q * D, *tq = dphi + q * D * 2;
-    const T wd = qw[q] * adet;
-    T cq = T(1);
-    if (COEF) cq = vb[3 * q] * cv[0] + vb[3 * q + 1] * cv[1] + vb[3 * q + 2] * cv[2];
-    T f0 = T(0), P0[NC], P1[NC];
-    if constexpr (VAL) {
-      T u = T(0);
-#pragma unroll
-      for (int i = 0; i < D; i++) u += xe[0][i] * pq[i];
-      f0 = wd * (KIND == MF_OP_MASS ? cq : T(1)) * u;
-    }
-    if constexpr (GRAD) {
-      // physical gradient G_a = sum_b g_b Ki[b][a], Ki[b][a] = d xi_b / d x_a
-      T G[NC][2];
-#pragma unroll
-      for (int c = 0; c < NC; c++) {
-        T g0 = T(0), g1 = T(0);
-#pragma unroll
-        for (int i = 0; i < D; i++) {
-          g0 += xe[c][i] * tq[2 * i + 0];
-          g1 += xe[c][i] * tq[2 * i + 1];
-        }
-        G[c][0] = g0 * Ki[0] + g1 * Ki[2];
-        G[c][1] = g0 * Ki[1] + g1 * Ki[3];
-      }
-      // physical flux S (the gradient, kappa times it, or the stress
-      // lambda tr(grad u) I + mu (grad u + grad u^T)), then P_b = w |det| sum_a Ki[b][a] S_a
-      T S[NC][2];
-      if constexpr (ELAS) {
-        const T tr = A.lam * (G[0][0] + G[1][1]), od = A.mu * (G[0][1] + G[1][0]);
-        S[0][0] = tr + T(2) * A.mu * G[0][0];
-        S[1][1] = tr + T(2) * A.mu * G[1][1];
-        S[0][1] = od;
-        S[1][0] = od;
-      } else {
-        S[0][0] = G[0][0];
-        S[0][1] = G[0][1];
-      }
-      const T s = wd * (KIND == MF_OP_POISSON ? cq : T(1));
-#pragma unroll
-      for (int c = 0; c < NC; c++) {
-        P0[c] = s * (S[c][0] * Ki[0] + S[c][1] * Ki[1]);
-        P1[c] = s * (S[c][0] * Ki[2] + S[c][1] * Ki[3]);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < NC; c++)
-#pragma unroll
-      for (int i = 0; i < D; i++) {
-        T v = T(0);
-        if constexpr (VAL) v += f0 * pq[i];
-        if constexpr (GRAD) v += P0[c] * tq[2 * i + 0] + P1[c] * tq[2 * i + 1];
-        ye[c][i] += v;
-      }
-  }
-#pragma unroll
-  for (int i = 0; i < D; i++) {
-    const int idx = valid ? mp[i * 64] : -1;
-    if (idx >= 0)
-#pragma unroll
-      for (int c = 0; c < NC; c++) {
-        T *yp = A.y + (int64_t)idx * NC + c;
-        if constexpr (ATOMIC) atomic_add_s(yp, ye[c][i]);
-        else *yp += ye[c][i];  // cells of one launch share no node
-      }
-  }
-}
-
-template <typename T, int K, int KIND>
-static int launch_tri_scalar_kk(int nq, const TetArgs<T> &a, bool atomic, hipStream_t s) {
-  const int64_t nbt = (a.c1 + 63) / 64 - a.c0 / 64;
-  if (a.c1 <= a.c0) return MF_OK;
-  const dim3 g((unsigned)(((nbt + 7) / 8) * 8)), b(64);
-  if (atomic) tri_scalar_kernel<T, K, KIND, true><<<g, b, 0, s>>>(a, nq);
-  else tri_scalar_kernel<T, K, KIND, false><<<g, b, 0, s>>>(a, nq);
-  MF_HIP(hipGetLastError());
-  return MF_OK;
-}
-
-template <typename T, int K>
-static int launch_tri_scalar_k(int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
-  switch (kind) {
-    case MF_OP_MASS: return launch_tri_scalar_kk<T, K, MF_OP_MASS>(nq, a, atomic, s);
-    case MF_OP_HELMHOLTZ: return launch_tri_scalar_kk<T, K, MF_OP_HELMHOLTZ>(nq, a, atomic, s);
-    case MF_OP_LAPLACIAN: return launch_tri_scalar_kk<T, K, MF_OP_LAPLACIAN>(nq, a, atomic, s);
-    case MF_OP_POISSON: return launch_tri_scalar_kk<T, K, MF_OP_POISSON>(nq, a, atomic, s);
-    case MF_OP_ELASTICITY: return launch_tri_scalar_kk<T, K, MF_OP_ELASTICITY>(nq, a, atomic, s);
-  }
-  return fail(MF_EUNSUPPORTED, "triangle scalar operator: kind");
-}
-
-template <typename T>
-int launch_tri_scalar(int k, int nq, int kind, const TetArgs<T> &a, bool atomic, hipStream_t s) {
-  switch (k) {
-    case 1: return launch_tri_scalar_k<T, 1>(nq, kind, a, atomic, s);
-    case 2: return launch_tri_scalar_k<T, 2>(nq, kind, a, atomic, s);
-    case 3: return launch_tri_scalar_k<T, 3>(nq, kind, a, atomic, s);
-  }
-  return fail(MF_EUNSUPPORTED, "triangle scalar operator: degree");
-}
-template int launch_tri_scalar<double>(int, int, int, const TetArgs<double> &, bool, hipStream_t);
-template int launch_tri_scalar<float>(int, int, int, const TetArgs<float> &, bool, hipStream_t);
-
 // ----------------------------------------------------------------- tet elasticity on MFMA
 // Both contractions of the action are GEMMs over a batch of cells (the
 // tabulation of the reference gradients is shared by all cells):
@@ -284,21 +133,7 @@ template int launch_tri_scalar<float>(int, int, int, const TetArgs<float> &, boo
 // K-steps (r, a) whose 4 entries are the points q = 4 r + 0..3. The per-lane
 // operands of the tabulation are precomputed on the host (mfma_tab layout:
 // fwd[r][s][64], bwd[t][r][a][64]).
-typedef float mf_floatx4 __attribute__((ext_vector_type(4)));
-typedef double mf_doublex4 __attribute__((ext_vector_type(4)));
-template <typename T> struct Mfma16;
-template <> struct Mfma16<float> {
-  typedef mf_floatx4 V;
-  static __device__ __forceinline__ V fma(float a, float b, V c) {
-    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-  }
-};
-template <> struct Mfma16<double> {
-  typedef mf_doublex4 V;
-  static __device__ __forceinline__ V fma(double a, double b, V c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-  }
-};
+// (Mfma16: the MFMA wrappers of simplex_mfma.h)
 
 // One wavefront per 16 cells (a quarter of a 64-cell layout block); a workgroup holds
 // blockDim.x / 64 consecutive quarters (1 or 4; the wavefronts share nothing but cache
@@ -548,225 +383,22 @@ __global__ void __launch_bounds__(256) tet_elasticity_patch_kernel(const TetArgs
 }
 
 // ----------------------------------------------------------------- scalar tet operators on MFMA
-// The one-component tet forms (degrees 1-6) in the GEMM form of the
-// elasticity kernel: a wavefront owns 16 cells and one accumulator. The forward rows
-// (q = 4 r + g, a) carry the reference gradient for a = 0..2 and the basis value in the
-// row a = 3 (padding in the elasticity tables), so one accumulator gives lane (cell, g)
-// the gradient and the value of u at point q. The backward K-steps are (r, a) with the
-// gradient rows and, for the kinds with a value term, (r, 3) with the basis values.
-// gp: the cell's geometry (Kinv, |det|), cp: its four vertex coefficients (null: 1),
-// both with entries 64 apart. Tables: phi [nq][D], gradients [nq][D][3], weights [nq],
-// vertex basis [nq][4], then fwd[r][s][64], bwd[t][r][4][64] (tet_mfma_scalar_tables).
-template <typename T, int K, int NQ, int KIND>
-__device__ __forceinline__ void tet_scalar_cells16(const TetArgs<T> &A, const int32_t *mp, const T *gp,
-                                                   const T *cp, const bool valid, const int lane,
-                                                   typename Mfma16<T>::V (&yacc)[((K + 1) * (K + 2) * (K + 3) / 6 + 15) / 16]) {
-  using MF = Mfma16<T>;
-  using V4 = typename MF::V;
-  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
-  constexpr int NR = (NQ + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
-  constexpr bool VAL = KIND == MF_OP_MASS || KIND == MF_OP_HELMHOLTZ;
-  constexpr bool GRAD = KIND != MF_OP_MASS;
-  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
-  const int g = lane >> 4;
-  T Ki[9];
-#pragma unroll
-  for (int m = 0; m < 9; m++) Ki[m] = gp[m * 64];
-  const T adet = gp[9 * 64];
-  T cv[4] = {T(1), T(1), T(1), T(1)};
-  if (COEF && cp)
-#pragma unroll
-    for (int v = 0; v < 4; v++) cv[v] = cp[v * 64];
-  const T *qw = A.tab + NQ * D * 4;
-  const T *vb = qw + NQ;
-  const T *fwd = vb + NQ * 4;
-  const T *bwd = fwd + NR * NS * 64;
-  T xv[NS];
-#pragma unroll
-  for (int s = 0; s < NS; s++) {
-    const int i = 4 * s + g;
-    const int idx = (valid && i < D) ? mp[i * 64] : -1;
-    xv[s] = idx >= 0 ? A.x[idx] : T(0);
-  }
-#pragma unroll
-  for (int t = 0; t < NT; t++) yacc[t] = V4{T(0), T(0), T(0), T(0)};
-  constexpr int RU = NR <= 4 ? NR : 1;
-#pragma unroll RU
-  for (int r = 0; r < NR; r++) {
-    V4 acc = V4{T(0), T(0), T(0), T(0)};
-#pragma unroll
-    for (int s = 0; s < NS; s++) acc = MF::fma(fwd[(r * NS + s) * 64 + lane], xv[s], acc);
-    const int q = 4 * r + g, qq = q < NQ ? q : 0;
-    const T wd = q < NQ ? qw[qq] * adet : T(0);
-    T cq = T(1);
-    if constexpr (COEF) cq = vb[4 * qq] * cv[0] + vb[4 * qq + 1] * cv[1] + vb[4 * qq + 2] * cv[2] + vb[4 * qq + 3] * cv[3];
-    T P[4] = {T(0), T(0), T(0), T(0)};
-    if constexpr (GRAD) {
-      // physical gradient G_a = sum_b g_b dxi_b/dx_a scaled by w |det| (kappa), and its
-      // reference-direction form P_b = sum_a dxi_b/dx_a G_a
-      const T sc = wd * (KIND == MF_OP_POISSON ? cq : T(1));
-      T G[3];
-#pragma unroll
-      for (int a = 0; a < 3; a++) G[a] = sc * (acc[0] * Ki[a] + acc[1] * Ki[3 + a] + acc[2] * Ki[6 + a]);
-#pragma unroll
-      for (int d = 0; d < 3; d++) P[d] = G[0] * Ki[3 * d] + G[1] * Ki[3 * d + 1] + G[2] * Ki[3 * d + 2];
-    }
-    if constexpr (VAL) P[3] = wd * (KIND == MF_OP_MASS ? cq : T(1)) * acc[3];
-#pragma unroll
-    for (int t = 0; t < NT; t++) {
-      const T *bt = bwd + (t * NR + r) * 4 * 64 + lane;
-      if constexpr (GRAD)
-#pragma unroll
-        for (int d = 0; d < 3; d++) yacc[t] = MF::fma(bt[d * 64], P[d], yacc[t]);
-      if constexpr (VAL) yacc[t] = MF::fma(bt[3 * 64], P[3], yacc[t]);
-    }
-  }
-}
-
-template <typename T, int K, int NQ, int KIND, bool ATOMIC>
-__global__ void __launch_bounds__(64) tet_scalar_mfma_kernel(const TetArgs<T> A) {
-  using V4 = typename Mfma16<T>::V;
-  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
-  constexpr int NT = (D + 15) / 16;
-  const int lane = threadIdx.x;
-  const int j = lane & 15, g = lane >> 4;
-  // one wavefront per 16 cells; contiguous ranges of quarters per XCD
-  const int64_t nqb = 4 * ((A.c1 + 63) / 64 - A.c0 / 64), per = (nqb + 7) / 8;
-  const int64_t qb = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (qb >= nqb) return;
-  const int64_t batch = A.c0 / 64 + qb / 4;
-  const int cl = 16 * (int)(qb % 4) + j;
-  const int64_t cell = batch * 64 + cl;
-  bool valid = cell >= A.c0 && cell < A.c1;
-  if (valid && A.cell_user) {
-    const int64_t u = A.cell_user[cell];
-    valid = u >= A.ulo && u < A.uhi;
-  }
-  const int32_t *mp = A.map + batch * (D * 64) + cl;
-  V4 yacc[NT];
-  tet_scalar_cells16<T, K, NQ, KIND>(A, mp, A.geo + batch * (10 * 64) + cl,
-                                     A.coef ? A.coef + batch * (4 * 64) + cl : nullptr, valid, lane, yacc);
-  constexpr bool F64 = sizeof(T) == 8;
-#pragma unroll
-  for (int t = 0; t < NT; t++)
-#pragma unroll
-    for (int v = 0; v < 4; v++) {
-      const int i = F64 ? 16 * t + g + 4 * v : 16 * t + 4 * g + v;
-      const int idx = (valid && i < D) ? mp[i * 64] : -1;
-      if (idx >= 0) {
-        if constexpr (ATOMIC) atomic_add_s(&A.y[idx], yacc[t][v]);
-        else A.y[idx] += yacc[t][v];  // cells of one launch share no node
-      }
-    }
-}
-
-// Patch scatter of the scalar forms (as tet_elasticity_patch_kernel, one component;
-// the slot geometry holds Kinv, |det| and, with a coefficient, the four vertex values).
-template <typename T, int K, int NQ, int KIND>
-__global__ void __launch_bounds__(256) tet_scalar_patch_kernel(const TetArgs<T> A, const SimplexPatchArgs<T> P) {
-  using V4 = typename Mfma16<T>::V;
-  constexpr int D = (K + 1) * (K + 2) * (K + 3) / 6;
-  constexpr int NT = (D + 15) / 16;
-  constexpr bool F64 = sizeof(T) == 8;
-  constexpr bool COEF = KIND == MF_OP_MASS || KIND == MF_OP_POISSON;
-  constexpr int G = COEF ? 14 : 10;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  double *acc = reinterpret_cast<double *>(smem_raw);  // FP64 sums, as in the elasticity patch kernel
-  const int64_t p = xcd_batch(blockIdx.x, P.npatch);
-  if (p >= P.npatch) return;  // whole workgroup: no barrier skipped
-  const int n0 = P.nptr[p], nn = P.nptr[p + 1] - n0;
-  for (int e = threadIdx.x; e < nn; e += blockDim.x) acc[e] = 0.0;
-  __syncthreads();
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int j = lane & 15, g = lane >> 4, cl = 16 * w + j;
-  const int nblk = P.cap / 64;
-  for (int r = 0; r < nblk; r++) {
-    const int64_t blk = p * nblk + r;
-    const T *gp = P.geo + blk * (G * 64) + cl;
-    V4 yacc[NT];
-    tet_scalar_cells16<T, K, NQ, KIND>(A, P.map + blk * (D * 64) + cl, gp, COEF ? gp + 10 * 64 : nullptr, true,
-                                       lane, yacc);
-    const uint16_t *lp = P.lmap + blk * (D * 64) + cl;
-#pragma unroll
-    for (int t = 0; t < NT; t++)
-#pragma unroll
-      for (int v = 0; v < 4; v++) {
-        const int i = F64 ? 16 * t + g + 4 * v : 16 * t + 4 * g + v;
-        if (i < D) {
-          const int l = lp[i * 64];
-          if (l != kSlotSkip) atomicAdd(&acc[l], (double)yacc[t][v]);
-        }
-      }
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < nn; e += blockDim.x) {
-    const int32_t o = P.out[n0 + e];
-    if (o & kSharedOut) P.sbuf[o & (kSharedOut - 1)] = (T)acc[e];
-    else A.y[o] = P.accumulate ? A.y[o] + (T)acc[e] : (T)acc[e];
-  }
-}
-
-template <typename T, int K, int NQ, int KIND>
-static int launch_tet_scalar_mfma_kq(const TetArgs<T> &a, bool atomic, hipStream_t s) {
-  const int64_t nqb = 4 * ((a.c1 + 63) / 64 - a.c0 / 64);
-  if (a.c1 <= a.c0) return MF_OK;
-  const dim3 g((unsigned)(((nqb + 7) / 8) * 8)), b(64);
-  if (atomic) tet_scalar_mfma_kernel<T, K, NQ, KIND, true><<<g, b, 0, s>>>(a);
-  else tet_scalar_mfma_kernel<T, K, NQ, KIND, false><<<g, b, 0, s>>>(a);
-  MF_HIP(hipGetLastError());
-  return MF_OK;
-}
-
-template <typename T, int K, int NQ, int KIND>
-static int launch_tet_scalar_patch_kq(const TetArgs<T> &a, const SimplexPatchArgs<T> &p, hipStream_t s) {
-  if (p.npatch <= 0) return MF_OK;
-  const size_t lds = (size_t)p.nmax * sizeof(double);
-  if (lds > 64 * 1024) return fail(MF_EUNSUPPORTED, "tet patch scatter: patch node list too long for LDS");
-  tet_scalar_patch_kernel<T, K, NQ, KIND><<<dim3((unsigned)xcd_grid(p.npatch)), dim3(256), lds, s>>>(a, p);
-  MF_HIP(hipGetLastError());
-  return MF_OK;
-}
-
-// kind dispatch for one (K, NQ): patch scatter when p is set, else atomic or coloured
-template <typename T, int K, int NQ>
-static int launch_tet_scalar_mfma_k(int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p, bool atomic,
-                                    hipStream_t s) {
-  switch (kind) {
-    case MF_OP_MASS:
-      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_MASS>(a, *p, s)
-               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_MASS>(a, atomic, s);
-    case MF_OP_HELMHOLTZ:
-      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_HELMHOLTZ>(a, *p, s)
-               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_HELMHOLTZ>(a, atomic, s);
-    case MF_OP_LAPLACIAN:
-      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_LAPLACIAN>(a, *p, s)
-               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_LAPLACIAN>(a, atomic, s);
-    case MF_OP_POISSON:
-      return p ? launch_tet_scalar_patch_kq<T, K, NQ, MF_OP_POISSON>(a, *p, s)
-               : launch_tet_scalar_mfma_kq<T, K, NQ, MF_OP_POISSON>(a, atomic, s);
-  }
-  return fail(MF_EUNSUPPORTED, "tet scalar operator: kind");
-}
-
-// P1-P6 on the rules of the tet quadrature table the scalar kinds take: 1 point
-// (degree 1), 4 (degree 2), 14 (degree 5), and the conical Gauss-Jacobi products of n^3
-// points, exact to degree 2n - 1 (64, 125, 216, 343)
+// simplex_scalar_* of simplex_mfma.h with DIM = 3, on the rules of the tet quadrature
+// table the scalar kinds take: 1 point (degree 1), 4 (degree 2), 14 (degree 5), and the
+// conical Gauss-Jacobi products of n^3 points, exact to degree 2n - 1 (64, 125, 216,
+// 343)
 template <typename T>
 static int launch_tet_scalar_mfma(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> *p,
                                   bool atomic, hipStream_t s) {
-  if (k == 1 && nq == 1) return launch_tet_scalar_mfma_k<T, 1, 1>(kind, a, p, atomic, s);
-  if (k == 1 && nq == 4) return launch_tet_scalar_mfma_k<T, 1, 4>(kind, a, p, atomic, s);
-  if (k == 1 && nq == 14) return launch_tet_scalar_mfma_k<T, 1, 14>(kind, a, p, atomic, s);
-  if (k == 2 && nq == 4) return launch_tet_scalar_mfma_k<T, 2, 4>(kind, a, p, atomic, s);
-  if (k == 2 && nq == 14) return launch_tet_scalar_mfma_k<T, 2, 14>(kind, a, p, atomic, s);
-  if (k == 3 && nq == 14) return launch_tet_scalar_mfma_k<T, 3, 14>(kind, a, p, atomic, s);
-  if (k == 3 && nq == 64) return launch_tet_scalar_mfma_k<T, 3, 64>(kind, a, p, atomic, s);
-  if (k == 4 && nq == 64) return launch_tet_scalar_mfma_k<T, 4, 64>(kind, a, p, atomic, s);
-  if (k == 4 && nq == 125) return launch_tet_scalar_mfma_k<T, 4, 125>(kind, a, p, atomic, s);
-  if (k == 5 && nq == 125) return launch_tet_scalar_mfma_k<T, 5, 125>(kind, a, p, atomic, s);
-  if (k == 5 && nq == 216) return launch_tet_scalar_mfma_k<T, 5, 216>(kind, a, p, atomic, s);
-  if (k == 6 && nq == 216) return launch_tet_scalar_mfma_k<T, 6, 216>(kind, a, p, atomic, s);
-  if (k == 6 && nq == 343) return launch_tet_scalar_mfma_k<T, 6, 343>(kind, a, p, atomic, s);
+#define MF_TET_KQ(K, NQ) \
+  if (k == K && nq == NQ) return launch_simplex_scalar_k<T, 3, K, NQ>(kind, a, p, atomic, s);
+  MF_TET_KQ(1, 1) MF_TET_KQ(1, 4) MF_TET_KQ(1, 14)
+  MF_TET_KQ(2, 4) MF_TET_KQ(2, 14)
+  MF_TET_KQ(3, 14) MF_TET_KQ(3, 64)
+  MF_TET_KQ(4, 64) MF_TET_KQ(4, 125)
+  MF_TET_KQ(5, 125) MF_TET_KQ(5, 216)
+  MF_TET_KQ(6, 216) MF_TET_KQ(6, 343)
+#undef MF_TET_KQ
   return fail(MF_EUNSUPPORTED, "tet scalar operator on MFMA: degree / rule");
 }
 
@@ -780,21 +412,21 @@ template int launch_tet_scalar_patches<double>(int, int, int, const TetArgs<doub
 template int launch_tet_scalar_patches<float>(int, int, int, const TetArgs<float> &,
                                               const SimplexPatchArgs<float> &, hipStream_t);
 
-// Per-lane MFMA operands of the scalar forms: the forward rows of tet_mfma_tables with
-// the basis value phi[q][i] in the row a = 3, and backward K-steps for a = 0..3.
-int tet_mfma_scalar_table_floats(int k, int nq) {
-  const int D = (k + 1) * (k + 2) * (k + 3) / 6;
+// Per-lane MFMA operands of the one-component forms (simplex_mfma.h): forward rows
+// (q, a) with the reference gradient for a < dim and the basis value phi[q][i] for
+// a = dim (a = 3 is padding on triangles), and backward K-steps for a = 0..dim.
+int simplex_mfma_scalar_table_floats(int dim, int D, int nq) {
   const int NR = (nq + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
-  return NR * NS * 64 + NT * NR * 4 * 64;
+  return NR * NS * 64 + NT * NR * (dim + 1) * 64;
 }
 
-void tet_mfma_scalar_tables(int k, int nq, const double *phi, const double *dphi, double *out, bool f64) {
-  const int D = (k + 1) * (k + 2) * (k + 3) / 6;
-  const int NR = (nq + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16;
+void simplex_mfma_scalar_tables(int dim, int D, int nq, const double *phi, const double *dphi, double *out,
+                                bool f64) {
+  const int NR = (nq + 3) / 4, NS = (D + 3) / 4, NT = (D + 15) / 16, NB = dim + 1;
   double *fwd = out, *bwd = out + NR * NS * 64;
   auto entry = [&](int q, int i, int a) {
-    if (q >= nq || i >= D) return 0.0;
-    return a < 3 ? dphi[(q * D + i) * 3 + a] : phi[q * D + i];
+    if (q >= nq || i >= D || a > dim) return 0.0;
+    return a < dim ? dphi[(q * D + i) * dim + a] : phi[q * D + i];
   };
   for (int r = 0; r < NR; r++)
     for (int s = 0; s < NS; s++)
@@ -805,8 +437,9 @@ void tet_mfma_scalar_tables(int k, int nq, const double *phi, const double *dphi
       }
   for (int t = 0; t < NT; t++)
     for (int r = 0; r < NR; r++)
-      for (int d = 0; d < 4; d++)
-        for (int l = 0; l < 64; l++) bwd[((t * NR + r) * 4 + d) * 64 + l] = entry(4 * r + l / 16, 16 * t + l % 16, d);
+      for (int d = 0; d < NB; d++)
+        for (int l = 0; l < 64; l++)
+          bwd[((t * NR + r) * NB + d) * 64 + l] = entry(4 * r + l / 16, 16 * t + l % 16, d);
 }
 
 template <typename T>

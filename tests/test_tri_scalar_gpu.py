@@ -1,7 +1,7 @@
 """GPU parity of the one-component operators on P1..P3 triangles (mass with and without
 a vertex coefficient, Helmholtz, Laplacian, Poisson) against the oracle, through the
-C-ABI. The P1 mass keeps its closed-form kernel; the other cases run the lane-per-cell
-triangle kernel."""
+C-ABI. The P1 mass keeps its closed-form kernel; the other cases run the matrix-core
+kernel (atomic, coloured and patch scatter); elasticity keeps the lane-per-cell kernel."""
 import numpy as np
 import pytest
 
@@ -71,6 +71,45 @@ def test_tri_scalar_dirichlet_range_errors(mf, k):
     for a, b in ((0, 50), (50, mesh.ncells)):
         lap.apply_range(a, b, xt, y, accumulate=True)
     assert _relerr(y.cpu().numpy(), oracle.OracleOp(space, LAP).apply(x)) <= 1e-12
+
+
+# 40 x 40 x 2 = 3200 triangles: several patches of 2048, 1024, 512 or 256 cells, the
+# last one ragged
+@pytest.mark.parametrize("dirichlet", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("kind,coef", [(MASS, True), (MASS, False), (HELM, False), (LAP, False), (POIS, True)],
+                         ids=["mass-coef", "mass", "helmholtz", "laplacian", "poisson"])
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_tri_scalar_patch(mf, k, kind, coef, prec, dirichlet):
+    import torch
+    if k == 1 and kind == MASS:
+        pytest.skip("the P1 mass has its own closed-form patch kernel (test_simplex_patch_gpu)")
+    print(f"tri scalar patch k={k} kind={kind} coef={coef} prec={prec} dirichlet={dirichlet}", flush=True)
+    mesh, space, x, c = _case(k, m=40)
+    c = c if coef else None
+    bnd = space.boundary_nodes() if dirichlet else np.zeros(0, np.int64)
+    mask = None
+    if dirichlet:
+        mask = np.zeros(space.nnodes, np.uint8)
+        mask[bnd] = 1
+    xm = x.copy()
+    xm[bnd] = 0.0
+    ref = oracle.OracleOp(space, kind, coef=c).apply(xm)
+    ref[bnd] = x[bnd]
+    op = mf.Operator(mf.Space.from_meshgen(space), kind, prec, vertex_coef=c, dirichlet=mask,
+                     scatter=mf.SCATTER_PATCH)
+    assert op.info["clears_output"] == 0 and op.info["scatter"] == mf.SCATTER_PATCH
+    xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+    y = op.apply(xt, torch.full_like(xt, float("nan"))).double().cpu().numpy()
+    assert np.isfinite(y).all()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+    if not dirichlet:
+        y0 = torch.tensor(mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_RHS, k), device="cuda", dtype=op.torch_dtype)
+        yi = op.apply_internal(xt).double().cpu().numpy()
+        yt = y0.clone()
+        op.apply_range_internal(0, op.info["ncells"], xt, yt, accumulate=True)
+        d = (yt.double() - y0.double()).cpu().numpy()
+        assert np.abs(d - yi).max() <= 4 * TOL[prec] * (np.abs(yi).max() + 1.0)
 
 
 def test_tri_scalar_large_sampled(mf):
