@@ -734,6 +734,32 @@ def profile_q1(mf, mg):
                       "cell_launches_per_apply": op.info["cell_launches"]}))
 
 
+def profile_simplex(mf, mg):
+    """The matrix-core simplex kernels for counter runs: vector P2 elasticity (48^3 x 6
+    tets, patch scatter) and scalar P3 Helmholtz on the same mesh, FP64, each applied 10
+    times on internally numbered vectors, then the 256 MiB calibration copy 10 times."""
+    import torch
+    mesh = mg.tet_mesh(48, 0.2, config=2)
+    info = {}
+    for k, nc, kind, name in ((2, 3, mf.ELASTICITY, "elasticity-P2"), (3, 1, mf.HELMHOLTZ, "helmholtz-P3")):
+        space = mg.tet_space(mesh, k, ncomp=nc, config=2)
+        op = mf.Operator(mf.Space.from_meshgen(space), kind, mf.F64, lam=1.0, mu=0.5)
+        x = torch.tensor(mg.uniform(space.ndofs, -1, 1, 2, mg.PURPOSE_X, k), device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(10):
+            op.apply_internal(x, y)
+        torch.cuda.synchronize()
+        info[name] = {"flops_per_apply": op.info["flops_per_apply"], "bytes_per_apply": op.info["bytes_per_apply"],
+                      "scatter": op.info["scatter"]}
+        del op, x, y
+    a = torch.ones(32 << 20, dtype=torch.float64, device="cuda")  # 256 MiB
+    b = torch.empty_like(a)
+    for _ in range(10):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"profiled": "tet elasticity P2 and Helmholtz P3 48^3x6 fp64 x10 each, copy 256MiB x10"} | info))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -753,6 +779,9 @@ def main():
     ap.add_argument("--profile-kernel", action="store_true",
                     help="only run the dominant action kernel 10 times and a 256 MiB reference copy "
                          "(for hardware-counter runs)")
+    ap.add_argument("--profile-simplex", action="store_true",
+                    help="only run the tet elasticity P2 and Helmholtz P3 matrix-core kernels 10 times each "
+                         "and the reference copy (for hardware-counter runs)")
     ap.add_argument("--profile-q1", action="store_true",
                     help="only run the Q1 patch kernel on 128^3 10 times and the reference copy "
                          "(for hardware-counter runs)")
@@ -773,6 +802,9 @@ def main():
         return
     if args.profile_q1:
         profile_q1(mf, mg)
+        return
+    if args.profile_simplex:
+        profile_simplex(mf, mg)
         return
     if args.c5_only:
         print(json.dumps(bench_c5(mf, mg, m=args.c5_m)))
