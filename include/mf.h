@@ -122,7 +122,7 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             ELASTICITY, P1-P3 one-component tet operators and the one-component
  *             triangle operators (the P1 mass included).
  *   AUTO      PATCH for hex Q1 on at least 2^15 cells, for those hex operators of
- *             degree 2-4, and for the tet and triangle forms above (FP64
+ *             degree 2-4 below 2^17 cells (degree 2: 2^20), and for the tet and triangle forms above (FP64
  *             triangles only up to degree 4) on at least 2^15 cells; otherwise COLOURED for 3-component hex operators of
  *             degree >= 2 on at least 4096 cells, scalar hex operators of degree
  *             >= 2 on at least 2^18 cells, tets of degree 2 and 3, quad and triangle

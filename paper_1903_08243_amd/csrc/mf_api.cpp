@@ -1429,10 +1429,13 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
                                (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
                              (ct == MF_CELL_TRI && kind <= MF_OP_POISSON && sp->ncomp == 1);
   // hex degrees 2-6 (the pencil kernel): patch scatter on request, and by default for
-  // degrees 2-4. A patch is one workgroup's cells (7, 4 and 2 cells for k = 2..4, 3 and
-  // 5 for k = 5, 6); at 32^3 it beat the coloured and atomic scatters for k <= 4 (FP64
-  // vector Laplacian Q2 63 -> 38 us, Q3 84 -> 65 us, Q4 157 -> 138 us) and lost for k = 5, 6
-  // (Q5 242 -> 309 us, Q6 390 -> 471 us), where most of a patch's nodes are shared.
+  // degrees 2-4 below 2^17 cells (Q2: 2^20). A patch is one workgroup's cells (7, 4 and
+  // 2 cells for k = 2..4, 3 and 5 for k = 5, 6); at 32^3 it beat the coloured and atomic
+  // scatters for k <= 4 (FP64 vector Laplacian Q2 63 -> 38 us, Q3 84 -> 65 us, Q4 157 ->
+  // 138 us) and lost for k = 5, 6 (Q5 242 -> 309 us, Q6 390 -> 471 us), where most of a
+  // patch's nodes are shared; on larger meshes the coloured launches win (FP64
+  // Helmholtz at 64^3: Q2 98 against 125 us still for the patches, Q3 228 against 188,
+  // Q4 496 against 421; at 128^3 Q2 874 against 773 us).
   const bool hex_patchable = ct == MF_CELL_HEX && kind <= MF_OP_POISSON && sp->degree >= 2 && sp->degree <= 6 &&
                              op->nq1d == sp->degree + 1;
   if (pr->scatter == MF_SCATTER_PATCH && tet_patchable) {
@@ -1441,7 +1444,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
              !(ct == MF_CELL_TRI && sp->degree >= 5 && precision == MF_F64) && nc >= (1 << 15)) {
     op->spatched = true;
   } else if (hex_patchable && (pr->scatter == MF_SCATTER_PATCH ||
-                               (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4))) {
+                               (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4 &&
+                                nc < (sp->degree == 2 ? (1 << 20) : (1 << 17))))) {
     op->hpatched = true;
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)
