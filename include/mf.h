@@ -119,16 +119,17 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             free nodes) with a device atomic (not bit-reproducible). Built for
  *             the hex MASS, HELMHOLTZ, LAPLACIAN and POISSON operators of degree 1
  *             (two points per direction) and 2-6 (k+1 points), P2 / P3 tet
- *             ELASTICITY, P1-P3 one-component tet operators and the one-component
- *             triangle operators (the P1 mass included).
+ *             ELASTICITY, P1-P3 one-component tet operators and the triangle
+ *             operators (the P1 mass and 2D ELASTICITY included).
  *   AUTO      PATCH for hex Q1 on at least 2^15 cells, for those hex operators of
- *             degree 2-4 below 2^17 cells (degree 2: 2^20), and for the tet and triangle forms above (FP64
- *             triangles only up to degree 4) on at least 2^15 cells; otherwise COLOURED for 3-component hex operators of
- *             degree >= 2 on at least 4096 cells, scalar hex operators of degree
- *             >= 2 on at least 2^18 cells, tets of degree 2 and 3, quad and triangle
- *             ELASTICITY (at least 4096 cells) and the other triangle operators
- *             but the P1 mass on at least 2^20 cells; else ATOMIC (the measured
- *             choices).
+ *             degree 2-4 below 2^17 cells (degree 2: 2^20), and for the tet and
+ *             triangle forms above on at least 2^15 cells (triangles of degree 5
+ *             and 6: only the FP32 one-component forms); otherwise COLOURED for
+ *             3-component hex operators of degree >= 2 on at least 4096 cells,
+ *             scalar hex operators of degree >= 2 on at least 2^18 cells, tets of
+ *             degree 2 and 3, quad and triangle ELASTICITY (at least 4096 cells)
+ *             and the other triangle operators but the P1 mass on at least 2^20
+ *             cells; else ATOMIC (the measured choices).
  * Range applies (mf_op_apply_range*) always use ATOMIC. Errors at mf_op_create:
  * MF_EUNSUPPORTED for PATCH on other cells, kinds or degrees. */
 enum { MF_SCATTER_AUTO = 0, MF_SCATTER_ATOMIC = 1, MF_SCATTER_COLOURED = 2, MF_SCATTER_PATCH = 3 };

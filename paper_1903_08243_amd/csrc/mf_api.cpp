@@ -930,6 +930,7 @@ static int setup_tri_pk(mf_op *op, const mf_space *sp, const mf_op_params *pr, c
   if (op->has_coef) cf.assign((size_t)nb * 3 * 64, T(1));
   // patch slots: the geometry and, for MASS and POISSON, the three vertex coefficients
   const bool slot_coef = op->kind == MF_OP_MASS || op->kind == MF_OP_POISSON;
+  const int nmax = op->kind == MF_OP_ELASTICITY ? 2048 : 4096;  // FP64 sums: 16 or 8 bytes per node
   const int G = slot_coef ? 8 : 5;
   std::vector<T> gflat(op->spatched ? (size_t)nc * G : 0);
   for (int64_t K = 0; K < nc; K++) {
@@ -953,9 +954,9 @@ static int setup_tri_pk(mf_op *op, const mf_space *sp, const mf_op_params *pr, c
   rc = upload(op->geo, geo.data(), geo.size() * sizeof(T), s);
   if (!rc && op->has_coef) rc = upload(op->coef, cf.data(), cf.size() * sizeof(T), s);
   if (!rc && op->spatched) {
-    // about k^2 / 2 nodes per cell: patches of at most 4096 nodes
+    // about k^2 / 2 nodes per cell: patches of at most 4096 nodes (elasticity 2048)
     const int cap = k <= 1 ? 2048 : k == 2 ? 1024 : k == 3 ? 512 : k == 4 ? 384 : 256;
-    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, G, cap, 4096, s);
+    rc = setup_simplex_patches<T>(op, sp, m, true, gflat, G, cap, nmax, s);
   }
   if (!rc) MF_HIP(hipStreamSynchronize(s));
   return rc;
@@ -1218,7 +1219,8 @@ template <typename T> static int op_apply_t(const mf_op *op, int64_t c0, int64_t
       } else if (op->cell_type == MF_CELL_TRI) {
         TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, 0, op->ncells, (T)op->lam,
                      (T)op->mu, nullptr, 0, 0, nullptr, nullptr, nullptr};
-        rc = launch_tri_scalar_patches<T>(op->degree, op->nqp, op->kind, a, pa, s);
+        rc = op->ncomp == 1 ? launch_tri_scalar_patches<T>(op->degree, op->nqp, op->kind, a, pa, s)
+                            : launch_tri_elasticity_patches<T>(op->degree, op->nqp, a, pa, s);
       } else {
         TetArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(), x, y, 0, op->ncells, (T)op->lam,
                      (T)op->mu, nullptr, 0, 0, nullptr, nullptr, nullptr};
@@ -1418,16 +1420,17 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
-  // P2/P3 tet elasticity, P1-P3 one-component tet operators and one-component triangle
-  // operators (the MFMA kernels), the P1 triangle mass: patch scatter on request, and by
-  // default from 2^15 cells (triangles up to degree 4: at 1024^2 x 2 cells, FP64, the
-  // patches took P2 Helmholtz from 174 (coloured) to 115 us and P3 Laplacian from 306 to
-  // 191 us; at degree 6 atomics ran faster in FP64, 395 against 447 us, and slower in
-  // FP32, 460 against 267 us)
+  // P2/P3 tet elasticity, P1-P3 one-component tet operators and the triangle operators
+  // (the MFMA kernels), the P1 triangle mass: patch scatter on request, and by default
+  // from 2^15 cells (triangles up to degree 4: at 1024^2 x 2 cells, FP64, the patches took
+  // P2 Helmholtz from 174 (coloured) to 115 us, P3 Laplacian from 306 to 191 us, P3
+  // elasticity from 527 to 329 us; at degree 6 atomics ran the Helmholtz operator faster
+  // in FP64, 395 against 447 us, and slower in FP32, 460 against 267 us, and the coloured
+  // launches ran elasticity faster, 611 / 322 against 788 / 518 us)
   const bool tet_patchable = (ct == MF_CELL_TET && sp->degree <= 3 &&
                               ((kind == MF_OP_ELASTICITY && sp->degree >= 2) ||
                                (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
-                             (ct == MF_CELL_TRI && kind <= MF_OP_POISSON && sp->ncomp == 1);
+                             (ct == MF_CELL_TRI && ((kind <= MF_OP_POISSON && sp->ncomp == 1) || kind == MF_OP_ELASTICITY));
   // hex degrees 2-6 (the pencil kernel): patch scatter on request, and by default for
   // degrees 2-4 below 2^17 cells (Q2: 2^20). A patch is one workgroup's cells (7, 4 and
   // 2 cells for k = 2..4, 3 and 5 for k = 5, 6); at 32^3 it beat the coloured and atomic
@@ -1441,7 +1444,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (pr->scatter == MF_SCATTER_PATCH && tet_patchable) {
     op->spatched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && tet_patchable &&
-             !(ct == MF_CELL_TRI && sp->degree >= 5 && precision == MF_F64) && nc >= (1 << 15)) {
+             !(ct == MF_CELL_TRI && sp->degree >= 5 && (precision == MF_F64 || kind == MF_OP_ELASTICITY)) &&
+             nc >= (1 << 15)) {
     op->spatched = true;
   } else if (hex_patchable && (pr->scatter == MF_SCATTER_PATCH ||
                                (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4 &&
@@ -1450,8 +1454,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)
       return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, P2/P3 "
-                                   "tet elasticity, P1-P3 one-component tet operators and one-component "
-                                   "triangle operators");
+                                   "tet elasticity, P1-P3 one-component tet operators and the triangle "
+                                   "operators");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
              kind <= MF_OP_POISSON && op->nq1d == 2) {

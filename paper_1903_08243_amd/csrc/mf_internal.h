@@ -343,6 +343,10 @@ int launch_tet_elasticity_patches(int k, int nq, const TetArgs<T> &a, const Simp
 template <typename T>
 int launch_tri_scalar_patches(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,
                               hipStream_t s);
+// 2D elasticity on triangles with the patch scatter (slot geometry as above, 5 entries;
+// two components per node)
+template <typename T>
+int launch_tri_elasticity_patches(int k, int nq, const TetArgs<T> &a, const SimplexPatchArgs<T> &p, hipStream_t s);
 // the one-component P1-P3 tet forms with the patch scatter (slot geometry: Kinv,
 // |det| and, for MASS and POISSON, the four vertex coefficients: 10 or 14 entries)
 template <typename T>

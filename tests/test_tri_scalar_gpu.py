@@ -148,6 +148,43 @@ def test_tri_elasticity(mf, k, prec, scatter):
     assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
 
 
+@pytest.mark.parametrize("dirichlet", [False, True])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("k", [1, 2, 3, 5])
+def test_tri_elasticity_patch(mf, k, prec, dirichlet):
+    """Patch scatter of 2D elasticity on 40 x 40 x 2 triangles (several patches, the last
+    ragged): every entry written, clamped rows, and the accumulating form."""
+    import torch
+    print(f"tri elasticity patch k={k} prec={prec} dirichlet={dirichlet}", flush=True)
+    mesh = mg.tri_mesh(40, 0.2, config=0)
+    space = mg.tri_space(mesh, k, seed_k=k, ncomp=2)
+    x = mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_X, k)
+    bnd = space.boundary_nodes() if dirichlet else np.zeros(0, np.int64)
+    mask = None
+    if dirichlet:
+        mask = np.zeros(space.nnodes, np.uint8)
+        mask[bnd] = 1
+    bd = np.stack([2 * bnd, 2 * bnd + 1], axis=1).ravel()
+    xm = x.copy()
+    xm[bd] = 0.0
+    ref = oracle.OracleOp(space, oracle.OP_ELASTICITY, lam=0.7, mu=0.4).apply(xm)
+    ref[bd] = x[bd]
+    op = mf.Operator(mf.Space.from_meshgen(space), mf.ELASTICITY, prec, lam=0.7, mu=0.4, dirichlet=mask,
+                     scatter=mf.SCATTER_PATCH)
+    assert op.info["clears_output"] == 0 and op.info["scatter"] == mf.SCATTER_PATCH
+    xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
+    y = op.apply(xt, torch.full_like(xt, float("nan"))).double().cpu().numpy()
+    assert np.isfinite(y).all()
+    assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
+    if not dirichlet:
+        y0 = torch.tensor(mg.uniform(space.ndofs, -1, 1, 0, mg.PURPOSE_RHS, k), device="cuda", dtype=op.torch_dtype)
+        yi = op.apply_internal(xt).double().cpu().numpy()
+        yt = y0.clone()
+        op.apply_range_internal(0, op.info["ncells"], xt, yt, accumulate=True)
+        d = (yt.double() - y0.double()).cpu().numpy()
+        assert np.abs(d - yi).max() <= 4 * TOL[prec] * (np.abs(yi).max() + 1.0)
+
+
 @pytest.mark.parametrize("k", [1, 3])
 def test_tri_elasticity_dirichlet_range(mf, k):
     """Clamped boundary (both components) and a split range apply; one component is
