@@ -119,12 +119,13 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             free nodes) with a device atomic (not bit-reproducible). Built for
  *             the hex MASS, HELMHOLTZ, LAPLACIAN and POISSON operators of degree 1
  *             (two points per direction) and 2-6 (k+1 points), P2 / P3 tet
- *             ELASTICITY, P1-P3 one-component tet operators and the triangle
- *             operators (the P1 mass and 2D ELASTICITY included).
+ *             ELASTICITY, one-component tet operators and the triangle operators
+ *             (the P1 mass and 2D ELASTICITY included).
  *   AUTO      PATCH for hex Q1 on at least 2^15 cells, for those hex operators of
  *             degree 2-4 below 2^17 cells (degree 2: 2^20), and for the tet and
- *             triangle forms above on at least 2^15 cells (triangles of degree 5
- *             and 6: only the FP32 one-component forms); otherwise COLOURED for
+ *             triangle forms above on at least 2^15 cells (one-component tets of
+ *             degree 4-6: only FP32 P4 and P5; triangles of degree 5 and 6: only
+ *             the FP32 one-component forms); otherwise COLOURED for
  *             3-component hex operators of degree >= 2 on at least 4096 cells,
  *             scalar hex operators of degree >= 2 on at least 2^18 cells, tets of
  *             degree 2 and 3, quad and triangle ELASTICITY (at least 4096 cells)

@@ -886,6 +886,12 @@ static int setup_tet(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
     const bool f64 = sizeof(T) == 8;
     int cap = k <= 2 ? 384 : (f64 ? 384 : 256), nmax = k <= 2 ? 2048 : (f64 ? 2700 : 2048);
     if (k == 1) cap = 1024;  // one-component P1: about 200 nodes per 1024 cells
+    if (k >= 4) {  // one-component P4-P6: about k^3 / 6 nodes per cell. At 24^3 x 6 the
+      // patches beat atomics in FP32 for P4 and P5 (Laplacian 147 -> 101 us, 291 -> 196 us)
+      // and lost in FP64 (140 -> 174 us, 311 -> 263 us for P5 but 699 -> 1834 us for P6)
+      cap = k == 4 ? 256 : 128;
+      nmax = 4096;
+    }
     rc = setup_simplex_patches<T>(op, sp, m, true, gflat, G, cap, nmax, s);
   }
   if (!rc) MF_HIP(hipStreamSynchronize(s));
@@ -1420,16 +1426,15 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   rc = upload(op->cell_user, sp->cell_user_of_int.data(), sp->cell_user_of_int.size() * sizeof(int32_t), s);
   if (rc) return rc;
   op->coloured = pr->scatter == MF_SCATTER_COLOURED || (pr->scatter == MF_SCATTER_AUTO && default_coloured(op.get()));
-  // P2/P3 tet elasticity, P1-P3 one-component tet operators and the triangle operators
+  // P2/P3 tet elasticity, one-component tet operators and the triangle operators
   // (the MFMA kernels), the P1 triangle mass: patch scatter on request, and by default
   // from 2^15 cells (triangles up to degree 4: at 1024^2 x 2 cells, FP64, the patches took
   // P2 Helmholtz from 174 (coloured) to 115 us, P3 Laplacian from 306 to 191 us, P3
   // elasticity from 527 to 329 us; at degree 6 atomics ran the Helmholtz operator faster
   // in FP64, 395 against 447 us, and slower in FP32, 460 against 267 us, and the coloured
   // launches ran elasticity faster, 611 / 322 against 788 / 518 us)
-  const bool tet_patchable = (ct == MF_CELL_TET && sp->degree <= 3 &&
-                              ((kind == MF_OP_ELASTICITY && sp->degree >= 2) ||
-                               (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
+  const bool tet_patchable = (ct == MF_CELL_TET && ((kind == MF_OP_ELASTICITY && sp->degree >= 2 && sp->degree <= 3) ||
+                                                    (kind <= MF_OP_POISSON && sp->ncomp == 1))) ||
                              (ct == MF_CELL_TRI && ((kind <= MF_OP_POISSON && sp->ncomp == 1) || kind == MF_OP_ELASTICITY));
   // hex degrees 2-6 (the pencil kernel): patch scatter on request, and by default for
   // degrees 2-4 below 2^17 cells (Q2: 2^20). A patch is one workgroup's cells (7, 4 and
@@ -1445,6 +1450,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
     op->spatched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && tet_patchable &&
              !(ct == MF_CELL_TRI && sp->degree >= 5 && (precision == MF_F64 || kind == MF_OP_ELASTICITY)) &&
+             !(ct == MF_CELL_TET && sp->degree >= 4 && (precision == MF_F64 || sp->degree == 6)) &&
              nc >= (1 << 15)) {
     op->spatched = true;
   } else if (hex_patchable && (pr->scatter == MF_SCATTER_PATCH ||
@@ -1454,8 +1460,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)
       return fail(MF_EUNSUPPORTED, "mf_op_create: the patch scatter is built for the hex scalar operators, P2/P3 "
-                                   "tet elasticity, P1-P3 one-component tet operators and the triangle "
-                                   "operators");
+                                   "tet elasticity, one-component tet operators and the triangle operators");
     op->patched = true;
   } else if (pr->scatter == MF_SCATTER_AUTO && ct == MF_CELL_HEX && op->degree == 1 && nc >= (1 << 15) &&
              kind <= MF_OP_POISSON && op->nq1d == 2) {

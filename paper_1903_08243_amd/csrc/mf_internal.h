@@ -347,7 +347,7 @@ int launch_tri_scalar_patches(int k, int nq, int kind, const TetArgs<T> &a, cons
 // two components per node)
 template <typename T>
 int launch_tri_elasticity_patches(int k, int nq, const TetArgs<T> &a, const SimplexPatchArgs<T> &p, hipStream_t s);
-// the one-component P1-P3 tet forms with the patch scatter (slot geometry: Kinv,
+// the one-component tet forms with the patch scatter (slot geometry: Kinv,
 // |det| and, for MASS and POISSON, the four vertex coefficients: 10 or 14 entries)
 template <typename T>
 int launch_tet_scalar_patches(int k, int nq, int kind, const TetArgs<T> &a, const SimplexPatchArgs<T> &p,

@@ -1,4 +1,4 @@
-"""Patch scatter of the tet elasticity action (P2, P3), of the one-component P1-P3
+"""Patch scatter of the tet elasticity action (P2, P3), of the one-component P1-P5
 tet operators and of the P1 triangle mass against the oracle.
 
 A patch workgroup sums its cells' local results in LDS and writes each of its nodes
@@ -102,7 +102,7 @@ def test_tet_patch_matches_coloured_scatter(mf, k):
     assert _relerr(a, b) <= 1e-13
 
 
-# one-component forms on 7^3 x 6 = 2058 tets: several patches (1024, 384 or 256
+# one-component forms on 7^3 x 6 = 2058 tets: several patches (1024, 384, 256 or 128
 # cells), the last one ragged; MASS and POISSON with a vertex coefficient, MASS also
 # without
 SCALAR = [(0, True), (0, False), (1, False), (2, False), (3, True)]
@@ -111,7 +111,7 @@ SCALAR = [(0, True), (0, False), (1, False), (2, False), (3, True)]
 @pytest.mark.parametrize("dirichlet", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("kind,coef", SCALAR)
-@pytest.mark.parametrize("k", [1, 2, 3])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
 def test_tet_scalar_patch_action(mf, k, kind, coef, prec, dirichlet):
     import torch
     print(f"tet scalar patch k={k} kind={kind} coef={coef} prec={prec} dirichlet={dirichlet}", flush=True)
