@@ -193,10 +193,11 @@ int mf_op_diagonal(const mf_op *op, void *d, void *stream);
  * user cell of each internal cell (ncells entries, may be NULL), the colour
  * offsets (ncolours + 1 entries, may be NULL) and the number of colours.
  * Nodes are numbered internally in order of first appearance when the cells
- * are traversed in that internal order (hexahedra, quadrilaterals, triangles) or,
- * for tetrahedra, in the Morton order of their centroids (each
+ * are traversed in that internal order (hexahedra, quadrilaterals) or, for
+ * tetrahedra and triangles, in the Morton order of their centroids (each
  * coordinate quantised to 1024 steps over the centroids' bounding box, bit b of
- * x, y, z at bits 3b, 3b+1, 3b+2 of the code; ties by internal cell order), the
+ * x, y, z at bits 3b, 3b+1, 3b+2 of the code, z = 0 on triangles; ties by
+ * internal cell order), the
  * order in which the patch scatter takes them; the kernels gather
  * and scatter only in that numbering, so the nodes of neighbouring cells are
  * neighbours in memory whatever numbering the caller uses. mf_op_apply and

@@ -295,17 +295,18 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
   for (int64_t ic = 0; ic < nc; ic++)
     for (int v = 0; v < nvc; v++) s->cell2vert_int[ic * nvc + v] = mesh->cell2vert[(int64_t)s->cell_user_of_int[ic] * nvc + v];
   // internal node numbering: first appearance when the cells are traversed in the
-  // internal cell order (hexahedra, quadrilaterals, triangles: the coloured hex
-  // launches store a node's first contribution without reading y, which needs this
-  // order, and the coloured triangle launches measured up to 2x slower otherwise) or,
-  // for tetrahedra, in the Morton order of their centroids (the patch scatter of the
-  // elasticity kernels takes Morton-ordered runs of cells, whose nodes then sit
-  // together in memory: P2 86 -> 80 us, P3 384 -> 374 us at 48^3 x 6 cells)
+  // internal cell order (hexahedra, quadrilaterals: the coloured hex launches store a
+  // node's first contribution without reading y, which needs this order) or, for
+  // simplices, in the Morton order of their centroids (the patch scatter takes
+  // Morton-ordered runs of cells, whose nodes then sit together in memory: tet P2
+  // elasticity 86 -> 80 us, P3 384 -> 374 us at 48^3 x 6 cells; triangles at 1024^2 x 2,
+  // P2 elasticity 175 -> 161 us, P3 Laplacian 191 -> 184 us, while the coloured and
+  // atomic launches of degree 6 lost 3-7 %)
   s->int_of_user.assign((size_t)nnodes, -1);
   s->user_of_int.clear();
   s->user_of_int.reserve((size_t)nnodes);
   std::vector<int64_t> walk;
-  if (mesh->cell_type == MF_CELL_TET) {
+  if (mesh->cell_type == MF_CELL_TET || mesh->cell_type == MF_CELL_TRI) {
     walk = morton_cell_order(s->coords, s->gdim, s->cell2vert_int.data(), nvc, nc);
   } else {
     walk.resize((size_t)nc);

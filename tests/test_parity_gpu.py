@@ -525,7 +525,7 @@ def test_colouring_and_internal_numbering_bit_exact(mf, case):
         nodes = space.cell2node[cells].ravel()
         assert len(np.unique(nodes)) == nodes.size
     i2u = sp.internal_to_user()
-    walk = order if case != "tet" else order[_morton_order(mesh.coords[mesh.cell2vert[order]].mean(axis=1))]
+    walk = order if case == "hex" else order[_morton_order(mesh.coords[mesh.cell2vert[order]].mean(axis=1))]
     assert np.array_equal(i2u, _first_touch(space.cell2node[walk], space.nnodes))
     coef = np.ones(mesh.nverts) if kind == 0 else None
     op = mf.Operator(sp, kind, 0, vertex_coef=coef)
