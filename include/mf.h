@@ -154,15 +154,15 @@ typedef struct {
  * use a rule exact for the integrand. params may be
  * NULL (coefficient 1, lambda 1, mu 0.5, no constraints). stream: device
  * uploads are ordered on it; the call returns after they complete.
- * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1), LAPLACIAN
- * (ncomp 1 or 3), ELASTICITY and HYPERELASTIC (ncomp 3; nq1d k+1 or k+2, at most 7);
- * tet ELASTICITY and HYPERELASTIC P1-P6 (ncomp 3); tet MASS and
- * HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1; the tet rules reach degree 21);
- * tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1) and ELASTICITY P1-P6
- * (ncomp 2, the 2D stress); tets of degree >= 2 run on the matrix cores, triangles
- * of degree 4-6 a dense-tabulation kernel (a thread per point, then a thread per
- * node); quad MASS, HELMHOLTZ,
- * LAPLACIAN and POISSON Q1-Q6 (ncomp 1) and ELASTICITY Q1-Q6 (ncomp 2, the 2D stress).
+ * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1) and LAPLACIAN
+ * (ncomp 1 or 3), nq1d k+1 or k+2; hex ELASTICITY and HYPERELASTIC (ncomp 3; nq1d
+ * k+1 or k+2, at most 7); tet ELASTICITY and HYPERELASTIC P1-P6 (ncomp 3); tet MASS
+ * and HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1; the tet rules reach degree
+ * 21); tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1) and ELASTICITY
+ * P1-P6 (ncomp 2, the 2D stress); the simplex operators run both contractions on the
+ * matrix cores (except P1 tet elasticity and the triangle P1 mass patch kernel, a
+ * lane per cell); quad MASS, HELMHOLTZ, LAPLACIAN and POISSON Q1-Q6 (ncomp 1) and
+ * ELASTICITY Q1-Q6 (ncomp 2, the 2D stress).
  * Errors: MF_EINVAL, MF_EUNSUPPORTED (op/cell/degree combination), MF_ENOMEM. */
 int mf_op_create(const mf_space *space, int kind, int precision, int nq1d,
                  const mf_op_params *params, void *stream, mf_op **out);

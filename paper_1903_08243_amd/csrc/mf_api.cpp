@@ -599,8 +599,8 @@ template <typename T>
 static int setup_hex(mf_op *op, const mf_space *sp, const mf_op_params *pr, const std::vector<int32_t> &m,
                      const std::vector<int32_t> &to_pos2, hipStream_t s) {
   const int k = sp->degree, N = k + 1;
-  if (op->nq1d != N && (op->nq1d != N + 1 || op->nq1d > 7))
-    return fail(MF_EUNSUPPORTED, "hex operators: nq1d must be k+1 or k+2 (at most 7)");
+  if (op->nq1d != N && op->nq1d != N + 1)
+    return fail(MF_EUNSUPPORTED, "hex operators: nq1d must be k+1 or k+2");
   const int64_t nc = sp->ncells;
   std::vector<T> geo((size_t)nc * 24, T(0));
   for (int64_t K = 0; K < nc; K++) {
@@ -995,8 +995,9 @@ static int setup_tri(mf_op *op, const mf_space *sp, const mf_op_params *pr, cons
 // Quads: 1D tables (GLL Lagrange basis and its derivative at the Gauss points, the
 // weights and the points), the bilinear map coefficients per cell [cell][6] and the
 // vertex coefficients [cell][4], in internal cell order.
-// 1D tables of the tensor-product kernels (quads, hex elasticity): the GLL Lagrange
-// basis B[a][i] and its derivative at the nq1d Gauss points, the weights, the points
+// 1D tables of the tensor-product kernels (quads, hex elasticity and hyperelasticity):
+// the GLL Lagrange basis B[a][i] and its derivative at the nq1d Gauss points, the
+// weights, the points
 template <typename T> static int upload_tensor_tables(mf_op *op, hipStream_t s) {
   std::vector<double> g, w, V, dV;
   gauss_legendre(op->nq1d, g, w);
@@ -1056,16 +1057,27 @@ static void count_work(mf_op *op) {
       by += 3.0 * (double)op->nnodes * s;
     }
   } else if (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) {
-    // k+2 points (thread-per-point kernel), per component, multiply-adds: forward x
-    // (1 + g) q n^3, y (1 + 2g) q^2 n^2, z (m + 3g) q^3 n, and the same backward
-    // (n = k+1 nodes, q points, g / m: gradient / value terms); per point the Jacobian 36,
-    // cofactors and det 32, weight and coefficient 16; per component the push-forward 18,
-    // fluxes 21 and the mass term 4
-    const double n = op->degree + 1, q = op->nq1d;
+    // k+2 points on pencils (n = k+1 nodes, q points per direction), per component: the
+    // rectangular even-odd passes n -> q over n^2, n q and q^2 pencils and back, plus,
+    // with gradients, three collocation derivatives and their transposes over q^2 pencils
+    // of length q (costed as in the k+1 count below); per point the k+1 kernel's
+    // geometry and flux terms
+    const int ni = op->degree + 1, nqi = op->nq1d;
+    const double n = ni, q = nqi;
     const bool grad = op->kind != MF_OP_MASS, mass = op->kind == MF_OP_MASS || op->kind == MF_OP_HELMHOLTZ;
-    const double g = grad ? 1.0 : 0.0, mm = mass ? 1.0 : 0.0;
-    const double fma = (1 + g) * q * n * n * n + (1 + 2 * g) * q * q * n * n + (mm + 3 * g) * q * q * q * n;
-    fl = nc * (comps * 2.0 * 2.0 * fma + q * q * q * (84.0 + comps * (39.0 * g + 4.0 * mm)));
+    // even-odd product of an no x nn matrix with reflection symmetry: the sums and
+    // differences of the input, two half-size products per output pair (one middle
+    // column when nn is odd), the pair itself, the middle row when no is odd
+    auto rect = [](int nn, int no) {
+      const int hi = nn / 2, ho = no / 2;
+      return 2.0 * hi + ho * (4.0 * hi + 2.0 * (nn % 2) + 2.0) + (no % 2) * (2.0 * hi + 2.0 * (nn % 2));
+    };
+    const double pencil = q * q + 2.0 * q - (nqi % 2);
+    const double contr = comps * ((n * n + n * q + q * q) * (rect(ni, nqi) + rect(nqi, ni)) +
+                                  (grad ? 6.0 : 0.0) * q * q * pencil);
+    const double geo = grad ? 39.0 : 24.0;
+    const double pw = (grad ? 39.0 : 0.0) * comps + (mass ? 4.0 * comps : 0.0);
+    fl = nc * (contr + q * q * q * (geo + pw));
     by += nc * 24.0 * s + (op->has_coef ? nc * 8.0 * s : 0.0);
   } else if (op->cell_type == MF_CELL_HEX) {
     const int ni = op->degree + 1;
@@ -1159,10 +1171,10 @@ static int cell_launch(const mf_op *op, int64_t c0, int64_t c1, const T *x, T *y
     }
     return launch_hex_elasticity<T>(op->degree, op->nq1d, a, atomic, s);
   } else if (op->cell_type == MF_CELL_HEX && op->nq1d != op->degree + 1) {
-    HexQArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(), op->tab.as<T>(),
+    HexQArgs<T> a{op->map.as<int32_t>(), op->geo.as<T>(),
                   op->has_coef ? op->coef.as<T>() : nullptr, x, y, c0, c1, filt, ulo, uhi,
                   fused ? op->gmap.as<int32_t>() : nullptr, op->ncomp};
-    return launch_hex_q<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
+    return launch_hex_kq<T>(op->degree, op->nq1d, op->kind, a, atomic, s);
   } else if (op->cell_type == MF_CELL_HEX) {
     // the coloured degree-1 kernel reads the block-interleaved copies
     const bool q1 = op->degree == 1 && !atomic;
@@ -1531,7 +1543,7 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   if (ct == MF_CELL_HEX) {
     rc = precision == MF_F64 ? setup_hex<double>(op.get(), sp, pr, m, to_pos2, s)
                              : setup_hex<float>(op.get(), sp, pr, m, to_pos2, s);
-    if (!rc && (kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC || op->nq1d != sp->degree + 1))
+    if (!rc && (kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC))
       rc = precision == MF_F64 ? upload_tensor_tables<double>(op.get(), s) : upload_tensor_tables<float>(op.get(), s);
   }
   else if (ct == MF_CELL_QUAD)

@@ -219,15 +219,14 @@ template <typename T> struct QuadArgs {
 template <typename T>
 int launch_quad(int k, int nq, int kind, const QuadArgs<T> &a, bool atomic, hipStream_t s, bool diag = false);
 
-// ELASTICITY on Q1..Q6 hexahedra (hex_elas_kernels.hip): three node-interleaved
-// components, sum-factorised, nq = k+1 or k+2 Gauss points per direction (at most 7)
-// Scalar hex operators with k+2 Gauss points per direction (hex_q_kernels.hip): map,
-// geometry, tables as HexElasArgs; coef: 8 trilinear coefficients of the vertex
-// coefficient per cell (or null); ncomp 1 or 3 (node-interleaved).
+// Scalar hex operators with k+2 Gauss points per direction on pencils
+// (hex_kq_kernels.hip): rectangular interpolation to the k+2 points, the k+1 kernel's
+// point stages, rectangular integration back. map and geo as HexElasArgs; coef: 8
+// trilinear coefficients of the vertex coefficient per cell (or null); ncomp 1 or 3
+// (node-interleaved). The 1D tables are compile-time constants.
 template <typename T> struct HexQArgs {
   const int32_t *map;
   const T *geo;
-  const T *tab;
   const T *coef;
   const T *x;
   T *y;
@@ -238,8 +237,10 @@ template <typename T> struct HexQArgs {
   int ncomp;
 };
 template <typename T>
-int launch_hex_q(int k, int nq, int kind, const HexQArgs<T> &a, bool atomic, hipStream_t s);
+int launch_hex_kq(int k, int nq, int kind, const HexQArgs<T> &a, bool atomic, hipStream_t s);
 
+// ELASTICITY on Q1..Q6 hexahedra (hex_elas_kernels.hip): three node-interleaved
+// components, sum-factorised, nq = k+1 or k+2 Gauss points per direction (at most 7)
 template <typename T> struct HexElasArgs {
   const int32_t *map;  // [ncells][(k+1)^3] node ids, internal numbering (negative: constrained)
   const T *geo;        // [ncells][24] trilinear coefficients c1..c7 per coordinate

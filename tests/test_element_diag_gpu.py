@@ -76,7 +76,7 @@ def test_hex_elasticity_diagonal(mf, k, extra, prec):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("kind,ncomp", [(HELM, 1), (LAP, 3), (MASS, 1), (POIS, 1)])
 def test_hex_k_plus_2_diagonal(mf, k, kind, ncomp, prec):
     print(f"hex k+2 diag k={k} kind={kind} prec={prec}", flush=True)

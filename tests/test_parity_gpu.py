@@ -558,7 +558,7 @@ def test_coloured_scatter_is_bit_reproducible_and_matches_atomic(mf, prec):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
-@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("kind,ncomp", [(1, 1), (2, 3), (0, 1), (3, 1)],
                          ids=["helmholtz", "laplacian3", "mass", "poisson"])
 def test_hex_action_k_plus_2_points(mf, k, scatter, prec, kind, ncomp):
@@ -578,11 +578,13 @@ def test_hex_action_k_plus_2_points(mf, k, scatter, prec, kind, ncomp):
 
 
 def test_hex_k_plus_2_points_limits(mf):
-    """k+2 points are built up to 7 per direction; other rules are rejected."""
+    """Scalar hex operators take k+1 or k+2 points per direction (8 at Q6); other
+    rules are rejected."""
     mesh = mg.hex_mesh(2, 0.15, config=1)
     sp = mf.Space.from_meshgen(mg.hex_space(mesh, 6, config=1))
+    assert mf.Operator(sp, 1, 0, nq1d=8).info["nq1d"] == 8
     with pytest.raises(mf.MFError, match="nq1d"):
-        mf.Operator(sp, 1, 0, nq1d=8)
+        mf.Operator(sp, 1, 0, nq1d=9)
     sp2 = mf.Space.from_meshgen(mg.hex_space(mesh, 2, config=1))
     with pytest.raises(mf.MFError, match="nq1d"):
         mf.Operator(sp2, 1, 0, nq1d=5)
