@@ -53,11 +53,17 @@ template <> struct HexLds<7> { static constexpr int SY = 7, SZ = 52, SE = 364; }
 
 // ---------------------------------------------------------------------------------- apply
 
-// LDS (in units of T) one workgroup needs for degree n-1: three padded n^3 buffers
-// per cell (one without gradients), 32 geometry values per cell and, with more than
-// one wavefront, one buffer that mirror lanes write into (never read).
+// Padded n^3 LDS buffers per cell: one without gradients; with gradients three, or
+// two from n = 6 on (the stage order of hex_pencil_stages2, which keeps the
+// x-derivative and the x-flux in registers: LDS, not registers, is what limits the
+// resident wavefronts of the Q5 and Q6 kernels).
+template <int N, bool GRAD> constexpr int hex_nbuf() { return GRAD ? (N >= 6 ? 2 : 3) : 1; }
+
+// LDS (in units of T) one workgroup needs for degree n-1: the stage buffers, 32
+// geometry values per cell and, with more than one wavefront, one buffer that mirror
+// lanes write into (never read).
 template <typename T, int N, bool GRAD, int WPB = 1> constexpr int hex_lds_size() {
-  return hex_epb<N, WPB>() * (HexLds<N>::SE * (GRAD ? 3 : 1) + 32) + (WPB > 1 ? HexLds<N>::SE : 0) +
+  return hex_epb<N, WPB>() * (HexLds<N>::SE * hex_nbuf<N, GRAD>() + 32) + (WPB > 1 ? HexLds<N>::SE : 0) +
          (sizeof(T) == 4 ? 128 : 0);
 }
 
@@ -233,6 +239,152 @@ __device__ __forceinline__ void hex_pencil_stages(T (&r)[N], const T *Gc, const 
   }
 }
 
+// The gradient kinds' action with two stage buffers U and V per cell (n >= 6): the
+// pointwise stage runs on x-pencils, whose lanes keep u from the x pass in registers
+// (its x-derivative is taken there); the z- and y-derivatives come through V and U (the y one in
+// place over u), the z- and y-fluxes go back through V and U and the x-flux stays in
+// registers. Same contract as hex_pencil_stages (on entry r holds the nodal z-pencil
+// (pa, pb, *), on exit the local result on it); one more barrier, a third less LDS.
+template <typename T, int N, int KIND, int WPB>
+__device__ __forceinline__ void hex_pencil_stages2(T (&r)[N], const T *Gc, const T *u0, const T *u1, T *w0, T *w1,
+                                                   const int pa, const int pb) {
+  using TB = TabT<T, N>;
+  constexpr bool MASS = KIND == K_HELM;
+  constexpr bool COEF = KIND == K_POIS;
+  constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ;
+  // this lane's x-pencil in the pointwise stage: y = g(pa), z = g(pb), x varies. Along
+  // it the Jacobian columns are j1 = P1, j2 = P2 + x Q2, j3 = P3 + x Q3 (trilinear map)
+  const T x2 = TB::g(pa), x3 = TB::g(pb);
+  const T wyz = TB::w(pa) * TB::w(pb);
+  T P1[3], P2[3], Q2[3], P3[3], Q3[3];
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const T c1 = Gc[0 + d], c2 = Gc[3 + d], c3 = Gc[6 + d], c4 = Gc[9 + d], c5 = Gc[12 + d], c6 = Gc[15 + d],
+            c7 = Gc[18 + d];
+    P1[d] = c1 + c4 * x2 + (c5 + c7 * x2) * x3;
+    P2[d] = c2 + c6 * x3;
+    Q2[d] = c4 + c7 * x3;
+    P3[d] = c3 + c6 * x2;
+    Q3[d] = c5 + c7 * x2;
+  }
+  T ka = T(1), kb = T(0);
+  if (COEF) {
+    const T *K = Gc + 24;
+    ka = K[0] + K[2] * x2 + (K[3] + K[6] * x2) * x3;
+    kb = K[1] + K[4] * x2 + (K[5] + K[7] * x2) * x3;
+  }
+  T v[N], ux[N], dxv[N];
+  // ---- z-pencil (x, y) = (pa, pb): B along z
+  eo_contract<T, N, MatB<N>, 1>(r, v);
+#pragma unroll
+  for (int c = 0; c < N; c++) w0[IX(pa, pb, c)] = v[c];
+  __syncthreads();
+  // ---- y-pencil (x = pa, z = pb): B along y
+#pragma unroll
+  for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
+  eo_contract<T, N, MatB<N>, 1>(r, v);
+#pragma unroll
+  for (int b = 0; b < N; b++) w0[IX(pa, b, pb)] = v[b];
+  __syncthreads();
+  // ---- x-pencil (y = pa, z = pb): B along x -> u at the points (kept in registers)
+#pragma unroll
+  for (int xx = 0; xx < N; xx++) r[xx] = u0[IX(xx, pa, pb)];
+  eo_contract<T, N, MatB<N>, 1>(r, ux);
+#pragma unroll
+  for (int a = 0; a < N; a++) w0[IX(a, pa, pb)] = ux[a];
+  __syncthreads();
+  // ---- z-pencil (x = pa, y = pb): z-derivative into V
+#pragma unroll
+  for (int c = 0; c < N; c++) r[c] = u0[IX(pa, pb, c)];
+  eo_contract<T, N, MatD<N>, -1>(r, v);
+#pragma unroll
+  for (int c = 0; c < N; c++) w1[IX(pa, pb, c)] = v[c];
+  __syncthreads();
+  // ---- y-pencil (x = pa, z = pb): y-derivative over u in U (each lane its own pencil)
+#pragma unroll
+  for (int yy = 0; yy < N; yy++) r[yy] = u0[IX(pa, yy, pb)];
+  eo_contract<T, N, MatD<N>, -1>(r, v);
+#pragma unroll
+  for (int b = 0; b < N; b++) w0[IX(pa, b, pb)] = v[b];
+  __syncthreads();
+  // ---- pointwise on the x-pencil (y = pa, z = pb); the x-derivative from the kept u
+  {
+    T f0[N];
+    eo_contract<T, N, MatD<N>, -1>(ux, dxv);
+#pragma unroll
+    for (int a = 0; a < N; a++) {
+      const T x1 = TB::g(a);
+      const T *j1 = P1;
+      T j2[3], j3[3];
+#pragma unroll
+      for (int d = 0; d < 3; d++) {
+        j2[d] = P2[d] + x1 * Q2[d];
+        j3[d] = P3[d] + x1 * Q3[d];
+      }
+      // adjugate rows: r0 = j2 x j3, r1 = j3 x j1, r2 = j1 x j2  (J^{-1} = rows / det)
+      const T r0[3] = {j2[1] * j3[2] - j2[2] * j3[1], j2[2] * j3[0] - j2[0] * j3[2], j2[0] * j3[1] - j2[1] * j3[0]};
+      const T r1[3] = {j3[1] * j1[2] - j3[2] * j1[1], j3[2] * j1[0] - j3[0] * j1[2], j3[0] * j1[1] - j3[1] * j1[0]};
+      const T r2[3] = {j1[1] * j2[2] - j1[2] * j2[1], j1[2] * j2[0] - j1[0] * j2[2], j1[0] * j2[1] - j1[1] * j2[0]};
+      const T det = j1[0] * r0[0] + j1[1] * r0[1] + j1[2] * r0[2];
+      const T adet = det < T(0) ? -det : det;
+      const T wq = wyz * TB::w(a);
+      const T kq = COEF ? ka + kb * x1 : T(1);
+      const T sc = wq * kq * recip(adet);
+      const T dx = dxv[a], dy = u0[IX(a, pa, pb)], dz = u1[IX(a, pa, pb)];
+      const T gx = r0[0] * dx + r1[0] * dy + r2[0] * dz;
+      const T gy = r0[1] * dx + r1[1] * dy + r2[1] * dz;
+      const T gz = r0[2] * dx + r1[2] * dy + r2[2] * dz;
+      f0[a] = sc * (r0[0] * gx + r0[1] * gy + r0[2] * gz);
+      w0[IX(a, pa, pb)] = sc * (r1[0] * gx + r1[1] * gy + r1[2] * gz);
+      w1[IX(a, pa, pb)] = sc * (r2[0] * gx + r2[1] * gy + r2[2] * gz);
+      if constexpr (MASS) ux[a] = wq * adet * ux[a];
+    }
+    // x-transpose of the derivative, in registers (plus the mass term)
+    eo_contract<T, N, MatDt<N>, -1>(f0, v);
+    if constexpr (MASS) {
+#pragma unroll
+      for (int a = 0; a < N; a++) v[a] += ux[a];
+    }
+  }
+  __syncthreads();
+  // ---- z-pencil (x = pa, y = pb): D^T along z of the z-flux in V; y-pencil (x = pa,
+  // z = pb): D^T along y of the y-flux in U (disjoint buffers, each lane its own pencils)
+  {
+    T t[N], q[N];
+#pragma unroll
+    for (int c = 0; c < N; c++) t[c] = u1[IX(pa, pb, c)];
+    eo_contract<T, N, MatDt<N>, -1>(t, q);
+#pragma unroll
+    for (int c = 0; c < N; c++) w1[IX(pa, pb, c)] = q[c];
+#pragma unroll
+    for (int yy = 0; yy < N; yy++) t[yy] = u0[IX(pa, yy, pb)];
+    eo_contract<T, N, MatDt<N>, -1>(t, q);
+#pragma unroll
+    for (int b = 0; b < N; b++) w0[IX(pa, b, pb)] = q[b];
+  }
+  __syncthreads();
+  // ---- x-pencil (y = pa, z = pb): sum the three terms, B^T along x
+#pragma unroll
+  for (int a = 0; a < N; a++) v[a] += u0[IX(a, pa, pb)] + u1[IX(a, pa, pb)];
+  eo_contract<T, N, MatBt<N>, 1>(v, r);
+#pragma unroll
+  for (int i = 0; i < N; i++) w0[IX(i, pa, pb)] = r[i];
+  __syncthreads();
+  // ---- y-pencil (x = pa, z = pb): B^T along y
+#pragma unroll
+  for (int b = 0; b < N; b++) r[b] = u0[IX(pa, b, pb)];
+  eo_contract<T, N, MatBt<N>, 1>(r, v);
+#pragma unroll
+  for (int j = 0; j < N; j++) w0[IX(pa, j, pb)] = v[j];
+  __syncthreads();
+  // ---- z-pencil (x, y) = (pa, pb): B^T along z
+#pragma unroll
+  for (int c = 0; c < N; c++) r[c] = u0[IX(pa, pb, c)];
+  eo_contract<T, N, MatBt<N>, 1>(r, v);
+#pragma unroll
+  for (int l = 0; l < N; l++) r[l] = v[l];
+}
+
 // Processes cell batch b (cells c0 + b*EPB ... c0 + b*EPB + EPB - 1) of one operator
 // on the calling wavefront, using `lds` (hex_lds_size<T, N, GRAD>() values).
 // PATCH: b is a patch of EPB cell slots (cell arrays in slot order); the results are
@@ -246,11 +398,12 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   constexpr bool MASS = KIND == K_MASS || KIND == K_HELM;
   constexpr bool COEF = KIND == K_MASS || KIND == K_POIS;
   constexpr int SY = HexLds<N>::SY, SZ = HexLds<N>::SZ, SE = HexLds<N>::SE;
+  constexpr int NBUF = hex_nbuf<N, GRAD>();
   T *const base = lds;
   T *s0 = base;
-  T *s1 = base + (GRAD ? EPB * SE : 0);
-  T *s2 = base + (GRAD ? 2 * EPB * SE : 0);
-  T *sg = base + (GRAD ? 3 : 1) * EPB * SE;
+  T *s1 = base + (NBUF > 1 ? EPB * SE : 0);
+  T *s2 = base + (NBUF > 2 ? 2 * EPB * SE : 0);
+  T *sg = base + NBUF * EPB * SE;
 
   const int t = threadIdx.x;
   const bool mirror = t >= EPB * NN;
@@ -298,8 +451,8 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   __syncthreads();
 
   T *u0 = s0 + le * SE;
-  T *u1 = s1 + (GRAD ? le * SE : 0);
-  T *u2 = s2 + (GRAD ? le * SE : 0);
+  T *u1 = s1 + (NBUF > 1 ? le * SE : 0);
+  T *u2 = s2 + (NBUF > 2 ? le * SE : 0);
   const T *Gc = sg + le * 32;
   // One component per call: the body has no loop over components, so the compiler
   // materialises the table constants at their uses instead of keeping them live
@@ -316,8 +469,11 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
   }
   T *dump = sg + EPB * 32;  // the discard buffer (WPB > 1)
   const bool discard = WPB > 1 && mirror;
-  hex_pencil_stages<T, N, KIND, WPB>(r, Gc, u0, u1, u2, discard ? dump : u0, discard ? dump : u1,
-                                     discard ? dump : u2, pa, pb);
+  if constexpr (NBUF == 2)
+    hex_pencil_stages2<T, N, KIND, WPB>(r, Gc, u0, u1, discard ? dump : u0, discard ? dump : u1, pa, pb);
+  else
+    hex_pencil_stages<T, N, KIND, WPB>(r, Gc, u0, u1, u2, discard ? dump : u0, discard ? dump : u1,
+                                       discard ? dump : u2, pa, pb);
   if constexpr (PATCH) {
     __syncthreads();  // every lane has finished reading the stage buffers, reused below
     const int n0 = A.pnptr[b], nn = A.pnptr[b + 1] - n0;
@@ -362,11 +518,19 @@ __device__ __forceinline__ void hex_cells(const HexArgs<T> &A, const int64_t b, 
 
 #undef IX
 
+// Resident wavefronts per SIMD the compiler must allow (register cap 512 / waves):
+// the FP64 gradient kernels from n = 6 on fit four wavefronts per SIMD in LDS, which
+// Helmholtz reaches only under the 128-register cap (a spill of under 64 bytes per
+// lane; measured 3 % faster than three wavefronts without it).
+template <typename T, int N, int KIND> constexpr int hex_min_waves() {
+  return (sizeof(T) == 8 && N >= 6 && KIND != K_MASS) ? 4 : 1;
+}
+
 // Work item = (cell batch, component): the ncomp components of a batch are
 // consecutive items, so they run on the same XCD at about the same time and share
 // the cache lines of their interleaved values.
 template <typename T, int N, int KIND, bool ATOMIC>
-__global__ void __launch_bounds__(64 * hex_wpb<N>()) hex_apply_kernel(const HexArgs<T> A) {
+__global__ void __launch_bounds__(64 * hex_wpb<N>(), (hex_min_waves<T, N, KIND>())) hex_apply_kernel(const HexArgs<T> A) {
   constexpr int WPB = hex_wpb<N>(), EPB = hex_epb<N, WPB>();
   __shared__ __align__(16) T lds[hex_lds_size<T, N, KIND != K_MASS, WPB>()];
   const int64_t nb = (A.c1 - A.c0 + EPB - 1) / EPB;  // cell batches
