@@ -126,7 +126,8 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             triangle forms above on at least 2^15 cells (one-component tets of
  *             degree 4-6: only FP32 P4 and P5; triangles of degree 5 and 6: only
  *             the FP32 one-component forms); otherwise COLOURED for
- *             3-component hex operators of degree >= 2 on at least 4096 cells,
+ *             3-component hex operators of degree >= 2 on at least 4096 cells
+ *             (the HYPERELASTIC tangent only up to degree 4),
  *             scalar hex operators of degree >= 2 on at least 2^18 cells, tets of
  *             degree 2 and 3, quad and triangle ELASTICITY (at least 4096 cells)
  *             and the other triangle operators but the P1 mass on at least 2^20
