@@ -127,7 +127,7 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             degree 4-6: only FP32 P4 and P5; triangles of degree 5 and 6: only
  *             the FP32 one-component forms); otherwise COLOURED for
  *             3-component hex operators of degree >= 2 on at least 4096 cells
- *             (the HYPERELASTIC tangent only up to degree 4),
+ *             (the HYPERELASTIC tangent only up to degree 4 in FP64, 5 in FP32),
  *             scalar hex operators of degree >= 2 on at least 2^18 cells, tets of
  *             degree 2 and 3, quad and triangle ELASTICITY (at least 4096 cells)
  *             and the other triangle operators but the P1 mass on at least 2^20

@@ -1296,9 +1296,10 @@ static bool default_coloured(const mf_op *op) {
     return op->ncomp == 2 || op->ncells >= (1 << 20);
   }
   if (op->cell_type == MF_CELL_HEX) {
-    // the hyperelastic tangent at Q5-Q6 spends long enough per cell that one atomic
-    // launch beats 8 colour launches (32^3, FP64 Q6 1405 against 1467 us)
-    if (op->kind == MF_OP_HYPERELASTIC && op->degree >= 5) return false;
+    // the hyperelastic tangent spends long enough per cell at Q6 (FP64 also Q5) that one
+    // atomic launch beats 8 colour launches (32^3: FP64 Q5 610 against 632 us, Q6 1405
+    // against 1467; FP32 Q6 665 against 704, but Q5 428 against 396)
+    if (op->kind == MF_OP_HYPERELASTIC && op->degree >= (op->precision == MF_F64 ? 5 : 6)) return false;
     if (op->ncomp == 3 && op->degree >= 2) return true;
     return op->ncells >= (op->degree == 1 ? (1 << 19) : (1 << 18));
   }
