@@ -74,8 +74,8 @@ enum { MF_CELL_TRI = 0, MF_CELL_TET = 1, MF_CELL_HEX = 2, MF_CELL_QUAD = 3 };
  *               dF = grad u, dE = (dF^T F + F^T dF)/2, dS = lambda tr(dE) I + 2 mu dE.
  *               Vector P1-P6 tets (quadrature exact for the degree 4(k-1)
  *               integrand: 1, 14 and 125 points for P1-P3, conical rules of up to
- *               1331 points for P4-P6) and Q1-Q6 hexahedra (nq1d k+1 or k+2, at
- *               most 7). */
+ *               1331 points for P4-P6) and Q1-Q6 hexahedra (nq1d k+1 or
+ *               k+2). */
 enum { MF_OP_MASS = 0, MF_OP_HELMHOLTZ = 1, MF_OP_LAPLACIAN = 2, MF_OP_POISSON = 3,
        MF_OP_ELASTICITY = 4, MF_OP_HYPERELASTIC = 5 };
 
@@ -157,7 +157,7 @@ typedef struct {
  * uploads are ordered on it; the call returns after they complete.
  * Built combinations: hex Q1-Q6 MASS, HELMHOLTZ, POISSON (ncomp 1) and LAPLACIAN
  * (ncomp 1 or 3), nq1d k+1 or k+2; hex ELASTICITY and HYPERELASTIC (ncomp 3; nq1d
- * k+1 or k+2, at most 7); tet ELASTICITY and HYPERELASTIC P1-P6 (ncomp 3); tet MASS
+ * k+1 or k+2); tet ELASTICITY and HYPERELASTIC P1-P6 (ncomp 3); tet MASS
  * and HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1; the tet rules reach degree
  * 21); tri MASS, HELMHOLTZ, LAPLACIAN and POISSON P1-P6 (ncomp 1) and ELASTICITY
  * P1-P6 (ncomp 2, the 2D stress); the simplex operators run both contractions on the

@@ -12,7 +12,8 @@
 // evaluated at every point (Section 2.1), and three passes back. A thread per quadrature
 // point; one cell per workgroup (rounded up to whole wavefronts), or 64 / nq^3 cells in
 // one wavefront when a cell has at most 32 points (Q1: 8, Q2: 2); between the passes the
-// partial contractions sit in two ping-pong LDS buffers per cell.
+// partial contractions sit in two ping-pong LDS buffers per cell (70 KB in FP64 for Q6
+// with 8 points: within gfx950's 160 KB per workgroup, two workgroups per CU).
 #include "mf_internal.h"
 
 namespace mf {
@@ -307,9 +308,8 @@ static int launch_hex_el_nq(const HexElasArgs<T> &a, bool atomic, hipStream_t s)
 template <typename T, int N>
 static int launch_hex_el_n(int nq, const HexElasArgs<T> &a, bool atomic, hipStream_t s) {
   if (nq == N) return launch_hex_el_nq<T, N, N>(a, atomic, s);
-  if constexpr (N < 7)
-    if (nq == N + 1) return launch_hex_el_nq<T, N, N + 1>(a, atomic, s);
-  return fail(MF_EUNSUPPORTED, "hex elasticity: nq1d must be k+1 or k+2 (at most 7)");
+  if (nq == N + 1) return launch_hex_el_nq<T, N, N + 1>(a, atomic, s);
+  return fail(MF_EUNSUPPORTED, "hex elasticity: nq1d must be k+1 or k+2");
 }
 
 template <typename T>

@@ -1385,8 +1385,8 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
   op->nq1d = tensor ? (nq1d > 0 ? nq1d : sp->degree + 1) : 0;
   if (ct == MF_CELL_HEX) op->nqp = op->nq1d * op->nq1d * op->nq1d;
   if (ct == MF_CELL_HEX && (kind == MF_OP_ELASTICITY || kind == MF_OP_HYPERELASTIC) &&
-      ((op->nq1d != sp->degree + 1 && op->nq1d != sp->degree + 2) || op->nq1d > 7))
-    return fail(MF_EUNSUPPORTED, "hex elasticity: nq1d must be k+1 or k+2 (at most 7)");
+      op->nq1d != sp->degree + 1 && op->nq1d != sp->degree + 2)
+    return fail(MF_EUNSUPPORTED, "hex elasticity: nq1d must be k+1 or k+2");
   if (ct == MF_CELL_QUAD) {
     // one lane per point, and every dof needs a lane
     if (op->nq1d != sp->degree + 1 && op->nq1d != sp->degree + 2)

@@ -45,7 +45,7 @@ def test_hex_elasticity_action(mf, k, prec, scatter):
     assert _relerr(y, ref) <= TOL[prec], _relerr(y, ref)
 
 
-@pytest.mark.parametrize("k", [1, 3, 5])
+@pytest.mark.parametrize("k", [1, 3, 5, 6])
 def test_hex_elasticity_paper_rule_dirichlet_range(mf, k):
     import torch
     print(f"hex elasticity k+2 / dirichlet / range k={k}", flush=True)
@@ -81,5 +81,5 @@ def test_hex_elasticity_errors(mf):
         mf.Operator(mf.Space.from_meshgen(mg.hex_space(mesh, 2)), mf.ELASTICITY, mf.F64)
     with pytest.raises(mf.MFError):  # the patch scatter is Q1 scalar/vector Laplacian-type only
         mf.Operator(mf.Space.from_meshgen(mg.hex_space(mesh, 1, ncomp=3)), mf.ELASTICITY, mf.F64, scatter=3)
-    with pytest.raises(mf.MFError):  # Q6 with 8 points: beyond the kernel's LDS budget
-        mf.Operator(mf.Space.from_meshgen(mg.hex_space(mesh, 6, ncomp=3)), mf.ELASTICITY, mf.F64, nq1d=8)
+    with pytest.raises(mf.MFError):  # k+3 points
+        mf.Operator(mf.Space.from_meshgen(mg.hex_space(mesh, 6, ncomp=3)), mf.ELASTICITY, mf.F64, nq1d=9)

@@ -123,7 +123,7 @@ def _hex_case(k, m=3):
 
 @pytest.mark.parametrize("scatter", [1, 2], ids=["atomic", "coloured"])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("k,extra", [(k, 0) for k in range(1, 7)] + [(k, 1) for k in range(1, 6)])
+@pytest.mark.parametrize("k,extra", [(k, 0) for k in range(1, 7)] + [(k, 1) for k in range(1, 7)])
 def test_hex_hyper_action(mf, k, extra, prec, scatter):
     print(f"hex hyper k={k} q=k+1+{extra} prec={prec} scatter={scatter}", flush=True)
     mesh, space, u0, x = _hex_case(k)
