@@ -122,7 +122,8 @@ int mf_space_create(const mf_mesh *mesh, int degree, int ncomp, const int32_t *c
  *             ELASTICITY, one-component tet operators and the triangle operators
  *             (the P1 mass and 2D ELASTICITY included).
  *   AUTO      PATCH for hex Q1 on at least 2^15 cells, for those hex operators of
- *             degree 2-4 below 2^17 cells (degree 2: 2^20), and for the tet and
+ *             degree 2-4 below 2^17 cells (degree 2: 2^20; in FP32 also the
+ *             one-component ones of degree 5 and 6), and for the tet and
  *             triangle forms above on at least 2^15 cells (one-component tets of
  *             degree 4-6: only FP32 P4 and P5; triangles of degree 5 and 6: only
  *             the FP32 one-component forms); otherwise COLOURED for

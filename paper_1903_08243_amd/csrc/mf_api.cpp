@@ -1470,9 +1470,13 @@ int mf_op_create(const mf_space *sp, int kind, int precision, int nq1d, const mf
              !(ct == MF_CELL_TET && sp->degree >= 4 && (precision == MF_F64 || sp->degree == 6)) &&
              nc >= (1 << 15)) {
     op->spatched = true;
-  } else if (hex_patchable && (pr->scatter == MF_SCATTER_PATCH ||
-                               (pr->scatter == MF_SCATTER_AUTO && sp->degree <= 4 &&
-                                nc < (sp->degree == 2 ? (1 << 20) : (1 << 17))))) {
+  } else if (hex_patchable &&
+             (pr->scatter == MF_SCATTER_PATCH ||
+              (pr->scatter == MF_SCATTER_AUTO && nc < (sp->degree == 2 ? (1 << 20) : (1 << 17)) &&
+               // measured at 32^3: patches win up to Q4 and, for one component, at Q5-Q6 in
+               // FP32 (10-30 % over atomics); FP64 Q5 gains warm (3-10 %) but loses with cold
+               // caches (125 against 96 us), FP64 Q6 does not gain
+               (sp->degree <= 4 || (sp->ncomp == 1 && precision == MF_F32))))) {
     op->hpatched = true;
   } else if (pr->scatter == MF_SCATTER_PATCH) {
     if (ct != MF_CELL_HEX || op->degree != 1 || kind > MF_OP_POISSON || op->nq1d != 2)

@@ -193,29 +193,32 @@ def test_hex_patch_scatter_accumulates(mf, prec):
     assert _relerr(yu, ref) <= TOL[prec]
 
 
+@pytest.mark.parametrize("kind,ncomp", [(2, 3), (1, 1), (3, 1)], ids=["laplacian3", "helmholtz", "poisson"])
 @pytest.mark.parametrize("dirichlet", [False, True])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
-def test_hex_cell_patch_scatter(mf, k, prec, dirichlet):
+def test_hex_cell_patch_scatter(mf, k, prec, dirichlet, kind, ncomp):
     """Degrees 2-6: the pencil kernel's patch scatter (runs of cells in Morton order,
     node sums in LDS, shared nodes summed by a second kernel) writes every entry of a
     NaN-filled output with no clearing pass, matches the oracle with constrained rows,
     and its accumulating form (used inside CG) adds the same values."""
     import torch
-    print(f"hex cell patches k={k} prec={prec} dirichlet={dirichlet}", flush=True)
+    print(f"hex cell patches k={k} prec={prec} dirichlet={dirichlet} kind={kind}", flush=True)
     mesh = mg.hex_mesh(HEX_M[k], 0.15, config=1, seed_k=k)
-    space = mg.hex_space(mesh, k, ncomp=3, config=1)
+    space = mg.hex_space(mesh, k, ncomp=ncomp, config=1)
+    coef = np.exp(np.random.default_rng(k).normal(size=mesh.nverts)) if kind == 3 else None
     bnd = space.boundary_nodes() if dirichlet else np.zeros(0, np.int64)
     mask = None
     if dirichlet:
         mask = np.zeros(space.nnodes, np.uint8)
         mask[bnd] = 1
     x = mg.uniform(space.ndofs, -1, 1, 1, mg.PURPOSE_X, k)
-    xm = x.reshape(-1, 3).copy()
+    xm = x.reshape(-1, ncomp).copy()
     xm[bnd] = 0.0
-    ref = oracle.OracleOp(space, 2).apply(xm.ravel()).reshape(-1, 3)
-    ref[bnd] = x.reshape(-1, 3)[bnd]
-    op = mf.Operator(mf.Space.from_meshgen(space), 2, prec, dirichlet=mask, scatter=mf.SCATTER_PATCH)
+    ref = oracle.OracleOp(space, kind, coef=coef).apply(xm.ravel()).reshape(-1, ncomp)
+    ref[bnd] = x.reshape(-1, ncomp)[bnd]
+    op = mf.Operator(mf.Space.from_meshgen(space), kind, prec, dirichlet=mask, scatter=mf.SCATTER_PATCH,
+                     vertex_coef=coef)
     assert op.info["clears_output"] == 0 and op.info["cell_launches"] == 1
     xt = torch.tensor(x, device="cuda", dtype=op.torch_dtype)
     y = op.apply(xt, torch.full_like(xt, float("nan"))).double().cpu().numpy()
